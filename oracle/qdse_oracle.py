@@ -1,0 +1,331 @@
+"""Plain FP64 CPU oracle for the vacuum quark gap equation with the Ball-Chiu
+vertex (Huang, Duan, Hu, Chen, arXiv:2012.03667).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this module; the product path never does. It shares no
+code with the HIP library.
+
+The map itself (one successive-approximation sweep, Sec. II eqs. dsesys and
+dsesys2, evaluated by direct radial x angular Gauss-Legendre sums as in Sec. III
+Listing 1/2) lives in ``qdse_oracle.cpp``; this module builds the grids, loads
+that library through ctypes and drives it:
+
+* ``picard``: successive approximation (Sec. I eq. jifen12) with the paper's
+  per-point convergence test (Sec. II eq. jifenab2) or the relative test on the
+  mass function M = B/A.
+* ``newton``: Newton's method on F(x) - x = 0 with Jacobian-vector products by
+  the complex step, for fixed points where successive approximation is not a
+  contraction; ``continuation`` walks the vertex homotopy lam from the bare
+  vertex (lam = 0) to Ball-Chiu (lam = 1).
+
+Grid (readings of Sec. II/III): u = ln p^2 on [ln s_min, ln s_max]; external
+nodes are the N-point Gauss-Legendre nodes in u, loop nodes the (N+1)-point ones
+on the same interval, so that the two sets interlace strictly (zeros of
+consecutive Legendre polynomials interlace), which is the ordering of eq.
+pqrelationship; angular nodes are M-point Gauss-Legendre nodes in z = cos(theta).
+Gauss-Legendre nodes come from ``numpy.polynomial.legendre.leggauss``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qdse_oracle.cpp")
+_LIB = os.path.join(_HERE, "libqdse_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (portable flags: no -march=native, no FMA
+    contraction, IEEE semantics)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("nq", ctypes.c_int), ("na", ctypes.c_int),
+                ("order", ctypes.c_int)] + [
+        (nm, ctypes.POINTER(ctypes.c_double))
+        for nm in ("s", "u", "t", "uq", "wq", "z", "wz")]
+
+
+class _Par(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("omega", ctypes.c_double),
+                ("m", ctypes.c_double), ("lam", ctypes.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        gp, pp = ctypes.POINTER(_Grid), ctypes.POINTER(_Par)
+        L.qo_vac_map.argtypes = [gp, pp, dp, dp, ctypes.c_int]
+        L.qo_vac_map_rows.argtypes = [gp, pp, dp, ip, ctypes.c_int, dp, ctypes.c_int]
+        L.qo_vac_jvp.argtypes = [gp, pp, dp, dp, dp, ctypes.c_int]
+        L.qo_vac_map_c.argtypes = [gp, pp, dp, dp, dp, dp, ctypes.c_int]
+        L.qo_interp.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp, ip]
+        L.qo_integrand.argtypes = [ctypes.c_double] * 8 + [dp, dp]
+        L.qo_integrand.restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+@dataclass
+class VacGrid:
+    """Discretisation of the vacuum problem (all float64 numpy arrays)."""
+    n: int
+    na: int
+    order: int
+    s: np.ndarray
+    u: np.ndarray
+    t: np.ndarray
+    uq: np.ndarray
+    wq: np.ndarray
+    z: np.ndarray
+    wz: np.ndarray
+
+    @property
+    def nq(self):
+        return len(self.t)
+
+    def _c(self):
+        g = _Grid(self.n, self.nq, self.na, self.order,
+                  *[_dp(a) for a in (self.s, self.u, self.t, self.uq, self.wq, self.z, self.wz)])
+        g._keep = self  # keep arrays alive
+        return g
+
+
+def gl_interval(n: int, a: float, b: float):
+    """n-point Gauss-Legendre nodes and weights mapped to [a, b]."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    return a + (b - a) * (x + 1.0) / 2.0, w * (b - a) / 2.0
+
+
+def vac_grid(n: int, na: int, s_min: float = 1e-4, s_max: float = 1e4,
+             order: int = 3, nq: int | None = None) -> VacGrid:
+    """External grid GL(n) in u = ln s, loop grid GL(n+1) in u on the same
+    interval (interleaved), angular grid GL(na) in z."""
+    a, b = np.log(s_min), np.log(s_max)
+    u, _ = gl_interval(n, a, b)
+    uq, wq = gl_interval(n + 1 if nq is None else nq, a, b)
+    z, wz = np.polynomial.legendre.leggauss(na)
+    return VacGrid(n, na, order, np.exp(u), u, np.exp(uq), uq, wq, z, wz)
+
+
+@dataclass
+class Params:
+    D: float
+    omega: float
+    m: float
+    lam: float = 1.0
+
+    def _c(self):
+        return _Par(self.D, self.omega, self.m, self.lam)
+
+    @staticmethod
+    def from_kappa(kappa: float, omega: float, m: float, lam: float = 1.0):
+        """D from the product D * omega = kappa^3."""
+        return Params(kappa ** 3 / omega, omega, m, lam)
+
+
+def _threads(nthreads):
+    return int(nthreads) if nthreads else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def F(g: VacGrid, p: Params, x: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """One sweep x' = F(x) of the successive approximation, x = [A | B]."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.shape == (2 * g.n,)
+    out = np.empty_like(x)
+    gc, pc = g._c(), p._c()
+    rc = lib().qo_vac_map(ctypes.byref(gc), ctypes.byref(pc), _dp(x), _dp(out), _threads(nthreads))
+    if rc:
+        raise ValueError("oracle: bad grid")
+    return out
+
+
+def F_rows(g: VacGrid, p: Params, x: np.ndarray, rows, nthreads: int | None = None):
+    """A'(rows), B'(rows) of one sweep, computed for the listed rows only."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.empty(2 * len(rows))
+    gc, pc = g._c(), p._c()
+    rc = lib().qo_vac_map_rows(ctypes.byref(gc), ctypes.byref(pc), _dp(x), _ip(rows),
+                               len(rows), _dp(out), _threads(nthreads))
+    if rc:
+        raise ValueError("oracle: bad grid or row index")
+    return out[:len(rows)], out[len(rows):]
+
+
+def F_complex(g: VacGrid, p: Params, x: np.ndarray, nthreads=None) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    xr, xi = np.ascontiguousarray(x.real), np.ascontiguousarray(x.imag)
+    orr, oi = np.empty_like(xr), np.empty_like(xr)
+    gc, pc = g._c(), p._c()
+    rc = lib().qo_vac_map_c(ctypes.byref(gc), ctypes.byref(pc), _dp(xr), _dp(xi), _dp(orr),
+                            _dp(oi), _threads(nthreads))
+    if rc:
+        raise ValueError("oracle: bad grid")
+    return orr + 1j * oi
+
+
+def jvp(g: VacGrid, p: Params, x: np.ndarray, v: np.ndarray, nthreads=None) -> np.ndarray:
+    """(dF/dx) v by the complex step."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty_like(x)
+    gc, pc = g._c(), p._c()
+    rc = lib().qo_vac_jvp(ctypes.byref(gc), ctypes.byref(pc), _dp(x), _dp(v), _dp(out),
+                          _threads(nthreads))
+    if rc:
+        raise ValueError("oracle: bad grid")
+    return out
+
+
+def jacobian(g: VacGrid, p: Params, x: np.ndarray, nthreads=None) -> np.ndarray:
+    """Dense dF/dx, one complex-step column at a time (small grids only)."""
+    n2 = 2 * g.n
+    J = np.empty((n2, n2))
+    e = np.zeros(n2)
+    for k in range(n2):
+        e[:] = 0.0
+        e[k] = 1.0
+        J[:, k] = jvp(g, p, x, e, nthreads)
+    return J
+
+
+def interp(u: np.ndarray, f: np.ndarray, x: np.ndarray, order: int):
+    """Interpolated values at x and the searched bracket of each point."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    fx = np.empty_like(x)
+    br = np.empty(len(x), dtype=np.int32)
+    rc = lib().qo_interp(len(u), _dp(u), _dp(f), len(x), _dp(x), order, _dp(fx), _ip(br))
+    if rc:
+        raise ValueError("oracle: bad interpolation request")
+    return fx, br
+
+
+def integrand(s, t, z, Ap, Bp, Aq, Bq, lam=1.0):
+    """(I_A, I_B) of eq. dsesys2 at one point (I_A includes its 1/p^2)."""
+    ia, ib = ctypes.c_double(), ctypes.c_double()
+    lib().qo_integrand(s, t, z, Ap, Bp, Aq, Bq, lam, ctypes.byref(ia), ctypes.byref(ib))
+    return ia.value, ib.value
+
+
+# --------------------------------------------------------------------------
+# Drivers
+# --------------------------------------------------------------------------
+
+def converged(x_old, x_new, n, tol, mode):
+    """Convergence test. mode 0: the paper's per-point absolute test on A and B
+    (Sec. II eq. jifenab2). mode 1: max |dM/M| < tol and max |dA| < tol."""
+    Ao, Bo, An, Bn = x_old[:n], x_old[n:], x_new[:n], x_new[n:]
+    if mode == 0:
+        r = max(np.max(np.abs(An - Ao)), np.max(np.abs(Bn - Bo)))
+    else:
+        Mo, Mn = Bo / Ao, Bn / An
+        r = max(np.max(np.abs(Mn - Mo) / np.abs(Mn)), np.max(np.abs(An - Ao)))
+    return r < tol, r
+
+
+def picard(g, p, x0, tol, max_iter=1000, mode=0, nthreads=None, history=False):
+    """Successive approximation x_{n+1} = F(x_n) (Sec. I eq. jifen12) until the
+    convergence test holds. Returns (x, iterations, last residual, hist)."""
+    x = np.array(x0, dtype=np.float64)
+    hist = []
+    r = np.inf
+    for it in range(1, max_iter + 1):
+        xn = F(g, p, x, nthreads)
+        ok, r = converged(x, xn, g.n, tol, mode)
+        if history:
+            hist.append(xn.copy())
+        x = xn
+        if not np.all(np.isfinite(x)):
+            return x, it, np.nan, hist
+        if ok:
+            return x, it, r, hist
+    return x, max_iter, r, hist
+
+
+def residual(g, p, x, nthreads=None):
+    return F(g, p, x, nthreads) - x
+
+
+def newton(g, p, x0, tol=1e-13, max_newton=40, dense_max=130, nthreads=None,
+           gmres_tol=1e-12):
+    """Newton's method on R(x) = F(x) - x: (I - J) dx = R, J = dF/dx. Dense
+    solve for small grids, GMRES (scipy) on complex-step products otherwise.
+    Returns (x, newton steps, max|R|)."""
+    x = np.array(x0, dtype=np.float64)
+    n2 = 2 * g.n
+    for it in range(max_newton):
+        R = residual(g, p, x, nthreads)
+        rn = np.max(np.abs(R))
+        if not np.isfinite(rn):
+            return x, it, np.inf
+        if rn < tol:
+            return x, it, rn
+        if g.n <= dense_max:
+            J = jacobian(g, p, x, nthreads)
+            dx = np.linalg.solve(np.eye(n2) - J, R)
+        else:
+            from scipy.sparse.linalg import LinearOperator, gmres
+            op = LinearOperator((n2, n2), matvec=lambda v: v - jvp(g, p, x, v, nthreads))
+            dx, info = gmres(op, R, rtol=gmres_tol, atol=0.0, restart=200, maxiter=20)
+        x = x + dx
+    R = residual(g, p, x, nthreads)
+    return x, max_newton, np.max(np.abs(R))
+
+
+def continuation(g, p, x0, steps=10, tol=1e-13, nthreads=None):
+    """Walk the vertex homotopy lam = 0 -> p.lam (bare -> Ball-Chiu): solve at
+    lam = 0 by Newton from x0, then Newton from the previous solution at each
+    of `steps` equally spaced lam values. Returns (x, max|R| at the end)."""
+    x = np.array(x0, dtype=np.float64)
+    rn = np.inf
+    for k in range(steps + 1):
+        pk = Params(p.D, p.omega, p.m, p.lam * k / steps)
+        x, _, rn = newton(g, pk, x, tol=tol, nthreads=nthreads)
+    return x, rn
+
+
+def certificate(g, p, x, nthreads=None):
+    """Physical-branch checks of a fixed point: residual, positivity of A and
+    absence of node-to-node sign alternation in the mass function."""
+    n = g.n
+    A, B = x[:n], x[n:]
+    R = residual(g, p, x, nthreads)
+    dM = np.diff(B / A)
+    flips = int(np.sum(dM[1:] * dM[:-1] < 0))
+    return {"resid": float(np.max(np.abs(R))), "A_pos": bool(np.all(A > 0)),
+            "slope_flips": flips}
+
+
+def spectral_radius(g, p, x, nthreads=None):
+    """Largest |eigenvalue| of dF/dx at x (dense; small grids), and the
+    eigenvalues themselves."""
+    ev = np.linalg.eigvals(jacobian(g, p, x, nthreads))
+    return float(np.max(np.abs(ev))), ev
