@@ -1,0 +1,169 @@
+/* qdse.h -- C ABI of the MI355X (gfx950) solver for the vacuum quark gap
+ * equation with the Ball-Chiu vertex (Huang, Duan, Hu, Chen, arXiv:2012.03667).
+ *
+ * The library evaluates, on one GPU, the successive-approximation map of the
+ * projected gap equations (Sec. II, eqs. dsesys, dsesys2; Sec. I, eq. jifen12)
+ *     A'(p^2) = 1 + C_F int d^4q/(2pi)^4 g(k^2) I_A / (q^2 A(q^2)^2 + B(q^2)^2)
+ *     B'(p^2) = m + C_F int d^4q/(2pi)^4 g(k^2) I_B / (q^2 A(q^2)^2 + B(q^2)^2)
+ * with g(k^2) = (8 pi^2 / omega^4) D exp(-k^2/omega^2) (eq. IRGsQC), C_F = 4/3,
+ * Gauss-Legendre quadrature in u = ln p^2 (radial) and in z = cos(theta)
+ * (angular), external nodes p^2 = s_i (N-point rule) interleaved with loop nodes
+ * q^2 = t_j ((N+1)-point rule on the same interval; Sec. III A, eq.
+ * pqrelationship), and Lagrange interpolation of A, B at the loop nodes with a
+ * bracket known in advance (Sec. III A, eq. chazhiresult; 2-point as in the
+ * paper or 4-point).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are DEVICE pointers (HIP device memory of the GPU that
+ *    was current at qdse_setup); all others are host pointers. The caller owns
+ *    every array it passes; the library never frees caller memory.
+ *  - The unknown vector of one instance is x = [A(s_0..s_{N-1}) | B(s_0..s_{N-1})],
+ *    FP64, N = n_radial. A batch is instance-major: x[inst * 2N + k].
+ *  - All device work is enqueued on the HIP stream given to qdse_setup.
+ *    qdse_iterate, qdse_jvp and qdse_vjp return without synchronising;
+ *    qdse_solve and qdse_grad synchronise the stream before they return
+ *    because they report convergence to the host.
+ *  - Return value: QDSE_OK (0), QDSE_NOT_CONVERGED (1, outputs hold the last
+ *    iterate), or a negative error code (outputs unspecified). Arguments are
+ *    validated before any HIP call. qdse_strerror names every code.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef QDSE_H
+#define QDSE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qdse_ctx qdse_ctx; /* opaque: grids, kernel matrices, workspaces */
+
+/* Discretisation shared by every instance of a context (Sec. IV: N external
+ * momenta, M Gauss-Legendre nodes). */
+typedef struct {
+  int n_radial;      /* N >= 4 external nodes p^2 = s_i                         */
+  int n_angle;       /* M >= 1 angular nodes in z = cos(theta)                   */
+  int interp_order;  /* 1: 2-point (eq. chazhiresult), 3: 4-point Lagrange in u  */
+  double s_min;      /* p^2 range in GeV^2, 0 < s_min < s_max                    */
+  double s_max;
+} qdse_grid;
+
+/* Per-instance physics parameters (Sec. II eq. IRGsQC; Sec. IV). */
+typedef struct {
+  double D;      /* interaction strength, GeV^2, D >= 0   */
+  double omega;  /* interaction range, GeV, omega > 0     */
+  double m;      /* current-quark mass, GeV                */
+} qdse_params;
+
+enum {
+  QDSE_OK = 0,
+  QDSE_NOT_CONVERGED = 1,
+  QDSE_EINVAL = -1,   /* bad argument (size, range, null pointer)            */
+  QDSE_ENOMEM = -2,   /* device or host allocation failed                    */
+  QDSE_EDEVICE = -3,  /* a HIP call failed (message via qdse_last_error)     */
+  QDSE_ENAN = -4,     /* an iterate became NaN or infinite                   */
+  QDSE_ENOTSUP = -5   /* option not available for this context             */
+};
+
+/* Arithmetic of the contraction over loop nodes, the only O(N^2) step. */
+enum {
+  QDSE_FP64 = 0,        /* FP64 throughout (direct difference form)          */
+  QDSE_FP32_REFINE = 1  /* FP32 MFMA contraction with FP32 accumulation for
+                           the sweeps, then FP64 sweeps until the test holds  */
+};
+
+/* Convergence test of qdse_solve. */
+enum {
+  QDSE_CONV_ABS = 0,  /* max_i |A'-A| < tol and max_i |B'-B| < tol (eq. jifenab2) */
+  QDSE_CONV_MASS = 1  /* max_i |M'-M|/|M'| < tol and max_i |A'-A| < tol, M = B/A  */
+};
+
+/* Builds the grids, the interpolation stencils and the angular-integrated
+ * kernel matrices for n_inst instances that share `grid` and have their own
+ * `params[inst]` (instances with equal omega share one set of matrices).
+ * precision: QDSE_FP64 or QDSE_FP32_REFINE (the latter also keeps FP32 copies).
+ * hip_stream: a hipStream_t (NULL = the null stream). On success *out owns all
+ * device memory of the context until qdse_destroy.
+ * Errors: QDSE_EINVAL (grid or params out of range, n_inst < 1, out == NULL),
+ * QDSE_ENOMEM, QDSE_EDEVICE. */
+int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst,
+               int precision, void* hip_stream, qdse_ctx** out);
+
+/* Releases every resource of ctx (NULL is allowed). */
+void qdse_destroy(qdse_ctx* ctx);
+
+/* Number of external nodes N, loop nodes N+1, angular nodes M, instances. */
+int qdse_dims(const qdse_ctx* ctx, int* n_radial, int* n_loop, int* n_angle, int* n_inst);
+
+/* Host copies of the grid: s[N] external p^2, t[N+1] loop q^2 (GeV^2). Either
+ * pointer may be NULL. */
+int qdse_nodes(const qdse_ctx* ctx, double* s, double* t);
+
+/* One sweep x_out = F(x_in) of the successive approximation (Sec. I eq.
+ * jifen12) for every instance, in FP64. d_x_in, d_x_out: [n_inst][2N] device,
+ * distinct buffers. Asynchronous. */
+int qdse_iterate(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
+
+/* Same sweep with the FP32 MFMA contraction (context set up with
+ * QDSE_FP32_REFINE, else QDSE_ENOTSUP). Asynchronous. */
+int qdse_iterate_fp32(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
+
+/* Successive approximation from the initial functions in d_x (Sec. II eq.
+ * jifenab1 gives A0 = B0 = 1; any start is accepted) until the test `conv_mode`
+ * holds with tolerance tol (Sec. II eq. jifenab2) or max_iter sweeps are done;
+ * each instance stops at its own first passing sweep. d_x is overwritten with
+ * the last iterate of every instance. iters[n_inst] (host, may be NULL):
+ * sweeps done; resid[n_inst] (host, may be NULL): the test statistic of the
+ * last sweep. Returns QDSE_OK if every instance passed, QDSE_NOT_CONVERGED if
+ * some hit max_iter, QDSE_ENAN if some iterate became non-finite.
+ * Synchronises the stream. */
+int qdse_solve(qdse_ctx* ctx, double* d_x, double tol, int max_iter, int conv_mode,
+               int* iters, double* resid);
+
+/* Jacobian-vector product d_jv = (dF/dx)(d_x) d_v for every instance (FP64,
+ * forward mode through interpolation, node functions and contraction).
+ * All [n_inst][2N] device. Asynchronous. */
+int qdse_jvp(qdse_ctx* ctx, const double* d_x, const double* d_v, double* d_jv);
+
+/* Transposed product d_out = (dF/dx)(d_x)^T d_w (reverse mode). Asynchronous. */
+int qdse_vjp(qdse_ctx* ctx, const double* d_x, const double* d_w, double* d_out);
+
+/* Gradient of a loss L(x*) through the fixed point x* = F(x*; theta), theta =
+ * (D, omega, m) per instance, by implicit differentiation: solves
+ * (I - J)^T lambda = d_g (J = dF/dx at d_xstar, d_g = dL/dx*) and returns
+ * theta_bar = lambda^T dF/dtheta in theta_bar[n_inst][3] (host). The linear
+ * solve (restarted GMRES) runs until ||residual||_2 < tol ||d_g||_2 for every
+ * instance or max_iter Krylov steps. Requires D > 0 for every instance
+ * (QDSE_EINVAL otherwise).
+ * Returns QDSE_NOT_CONVERGED if the adjoint solve did not reach tol.
+ * Synchronises the stream. */
+int qdse_grad(qdse_ctx* ctx, const double* d_xstar, const double* d_g, double tol,
+              int max_iter, double* theta_bar);
+
+/* Device copy of the three angular-integrated kernel matrices of instance inst,
+ * FP64 [3][N][N+1] into d_K (for inspection and tests). With E = exp(-k^2/omega^2),
+ * k^2 = p^2 + q^2 - 2 |p||q| z, the angular weight w_a sqrt(1 - z_a^2) (the
+ * d^4q measure), W_j = (radial weight in ln q^2) * t_j^2 and L = 1/(t_j - s_i):
+ *   K[0][i][j] = W_j t_j L sum_a w_a sqrt(1-z_a^2) E (1 - z_a^2)/k^2
+ *   K[1][i][j] = W_j/(2 s_i) sum_a w_a sqrt(1-z_a^2) E [3 r z (s_i+t_j) - 2 s_i t_j (1+2 z^2)]/k^2
+ *   K[2][i][j] = (3/2) W_j sum_a w_a sqrt(1-z_a^2) E,      r = sqrt(s_i t_j).
+ * These are the angular integrals of the bracketed factors of eq. dsesys2
+ * after the transverse-projector algebra (see the kernel source). */
+int qdse_kernel_matrices(qdse_ctx* ctx, int inst, double* d_K);
+
+/* Diagnostics: average device duration in milliseconds of the contraction
+ * kernel of one FP64 sweep (the O(N^2) step) at d_x, over `reps` launches on
+ * the context's stream, each bracketed by its own pair of HIP events. d_out
+ * [n_inst][2N] receives F(d_x). Synchronises the stream. */
+int qdse_time_contraction(qdse_ctx* ctx, const double* d_x, double* d_out, int reps,
+                          double* avg_ms);
+
+/* Human-readable name of a status code. */
+const char* qdse_strerror(int code);
+
+/* Text of the last HIP failure seen by this thread (empty if none). */
+const char* qdse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QDSE_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) solver for the vacuum quark gap equation with the Ball-Chiu
+vertex (Huang, Duan, Hu, Chen, arXiv:2012.03667).
+
+The compute path is the HIP library ``libqdse.so`` (C ABI in include/qdse.h);
+this package only marshals arguments: PyTorch supplies device memory and the
+stream. If the library is missing every entry point raises.
+"""
+from ._lib import (QDSE_CONV_ABS, QDSE_CONV_MASS, QDSE_ENAN, QDSE_FP32_REFINE, QDSE_FP64,
+                   QDSE_NOT_CONVERGED, QDSE_OK, QdseError, Solver, library_path, load)
+
+__all__ = ["Solver", "QdseError", "load", "library_path", "QDSE_OK", "QDSE_NOT_CONVERGED",
+           "QDSE_ENAN", "QDSE_FP64", "QDSE_FP32_REFINE", "QDSE_CONV_ABS", "QDSE_CONV_MASS"]

@@ -1,0 +1,204 @@
+"""ctypes binding of libqdse.so: argument marshalling only (see include/qdse.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libqdse.so")
+
+QDSE_OK, QDSE_NOT_CONVERGED = 0, 1
+QDSE_EINVAL, QDSE_ENOMEM, QDSE_EDEVICE, QDSE_ENAN, QDSE_ENOTSUP = -1, -2, -3, -4, -5
+QDSE_FP64, QDSE_FP32_REFINE = 0, 1
+QDSE_CONV_ABS, QDSE_CONV_MASS = 0, 1
+
+
+class QdseError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {code} ({_strerror(code)}) {_last_error()}")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n_radial", ctypes.c_int), ("n_angle", ctypes.c_int),
+                ("interp_order", ctypes.c_int), ("s_min", ctypes.c_double),
+                ("s_max", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("omega", ctypes.c_double), ("m", ctypes.c_double)]
+
+
+_lib = None
+_vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+def load():
+    """Loads libqdse.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise RuntimeError(f"{_LIBPATH} is missing: build it with paper_2012_03667_amd/build.py")
+    L = ctypes.CDLL(_LIBPATH)
+    L.qdse_setup.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.c_int,
+                             ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+    L.qdse_destroy.argtypes = [_vp]
+    L.qdse_destroy.restype = None
+    L.qdse_dims.argtypes = [_vp, _ip, _ip, _ip, _ip]
+    L.qdse_nodes.argtypes = [_vp, _dp, _dp]
+    L.qdse_iterate.argtypes = [_vp, _vp, _vp]
+    L.qdse_iterate_fp32.argtypes = [_vp, _vp, _vp]
+    L.qdse_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp]
+    L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
+    L.qdse_vjp.argtypes = [_vp, _vp, _vp, _vp]
+    L.qdse_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _dp]
+    L.qdse_kernel_matrices.argtypes = [_vp, ctypes.c_int, _vp]
+    L.qdse_time_contraction.argtypes = [_vp, _vp, _vp, ctypes.c_int, _dp]
+    L.qdse_strerror.argtypes = [ctypes.c_int]
+    L.qdse_strerror.restype = ctypes.c_char_p
+    L.qdse_last_error.argtypes = []
+    L.qdse_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _strerror(code):
+    try:
+        return load().qdse_strerror(code).decode()
+    except Exception:
+        return "?"
+
+
+def _last_error():
+    try:
+        return load().qdse_last_error().decode()
+    except Exception:
+        return ""
+
+
+def _check(code, what, allow=(QDSE_OK,)):
+    if code not in allow:
+        raise QdseError(code, what)
+    return code
+
+
+def _dev(t, shape, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One context of include/qdse.h: n_inst instances sharing one grid.
+
+    params: sequence of (D [GeV^2], omega [GeV], m [GeV]) per instance.
+    Unknowns per instance: x = [A(s_0..s_{N-1}) | B(s_0..s_{N-1})].
+    """
+
+    def __init__(self, n_radial, n_angle, params, interp_order=3, s_min=1e-4, s_max=1e4,
+                 precision=QDSE_FP64, stream=None):
+        import torch
+        L = load()
+        self.n, self.na, self.order = int(n_radial), int(n_angle), int(interp_order)
+        self.params = [tuple(map(float, p)) for p in params]
+        self.n_inst = len(self.params)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        g = Grid(self.n, self.na, self.order, float(s_min), float(s_max))
+        P = (Params * max(1, self.n_inst))(*[Params(*p) for p in self.params])
+        h = _vp()
+        _check(L.qdse_setup(ctypes.byref(g), P, self.n_inst, int(precision),
+                            _vp(self.stream.cuda_stream), ctypes.byref(h)), "qdse_setup")
+        self._h = h
+        self.s = np.empty(self.n)
+        self.t = np.empty(self.n + 1)
+        _check(L.qdse_nodes(h, self.s.ctypes.data_as(_dp), self.t.ctypes.data_as(_dp)),
+               "qdse_nodes")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().qdse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.n_inst, 2 * self.n)
+
+    def initial(self, A0=1.0, B0=1.0):
+        import torch
+        x = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        x[:, :self.n] = A0
+        x[:, self.n:] = B0
+        return x
+
+    def iterate(self, x, out=None, fp32=False):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        fn = load().qdse_iterate_fp32 if fp32 else load().qdse_iterate
+        _check(fn(self._h, _dev(x, self.shape, "x"), _dev(out, self.shape, "out")),
+               "qdse_iterate")
+        return out
+
+    def solve(self, x, tol=1e-10, max_iter=1000, conv_mode=QDSE_CONV_MASS):
+        """In place. Returns (status, iters[n_inst], resid[n_inst])."""
+        it = np.zeros(self.n_inst, dtype=np.int32)
+        rs = np.zeros(self.n_inst)
+        rc = load().qdse_solve(self._h, _dev(x, self.shape, "x"), float(tol), int(max_iter),
+                               int(conv_mode), it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
+        _check(rc, "qdse_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+        return rc, it, rs
+
+    def jvp(self, x, v, out=None):
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        _check(load().qdse_jvp(self._h, _dev(x, self.shape, "x"), _dev(v, self.shape, "v"),
+                               _dev(out, self.shape, "out")), "qdse_jvp")
+        return out
+
+    def vjp(self, x, w, out=None):
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        _check(load().qdse_vjp(self._h, _dev(x, self.shape, "x"), _dev(w, self.shape, "w"),
+                               _dev(out, self.shape, "out")), "qdse_vjp")
+        return out
+
+    def grad(self, xstar, g, tol=1e-12, max_iter=400):
+        """theta_bar[n_inst][3] = dL/d(D, omega, m) through the fixed point."""
+        tb = np.zeros((self.n_inst, 3))
+        rc = load().qdse_grad(self._h, _dev(xstar, self.shape, "xstar"), _dev(g, self.shape, "g"),
+                              float(tol), int(max_iter), tb.ctypes.data_as(_dp))
+        _check(rc, "qdse_grad", allow=(QDSE_OK, QDSE_NOT_CONVERGED))
+        return tb, rc
+
+    def time_contraction(self, x, reps=50):
+        """Average device milliseconds of one contraction launch (HIP events)."""
+        import torch
+        out = torch.empty_like(x)
+        ms = ctypes.c_double()
+        _check(load().qdse_time_contraction(self._h, _dev(x, self.shape, "x"),
+                                            _dev(out, self.shape, "out"), int(reps),
+                                            ctypes.byref(ms)), "qdse_time_contraction")
+        return ms.value
+
+    def kernel_matrices(self, inst=0):
+        import torch
+        K = torch.empty((3, self.n, self.n + 1), dtype=torch.float64, device=self.device)
+        _check(load().qdse_kernel_matrices(self._h, int(inst), ctypes.c_void_p(K.data_ptr())),
+               "qdse_kernel_matrices")
+        return K

@@ -1,0 +1,608 @@
+// qdse_api.cpp -- the C ABI of include/qdse.h: context set-up, sweeps,
+// the masked successive-approximation driver (HIP graph chunks), tangent and
+// adjoint products, and the implicit-function gradient (restarted GMRES on
+// (I - J)^T lambda = g with device-side Gram-Schmidt).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qdse_internal.h"
+
+using namespace qdse;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+const double PI = 3.14159265358979323846;
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+      return QDSE_EDEVICE;                                                           \
+    }                                                                                \
+  } while (0)
+
+template <class T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    g_last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+    *p = nullptr;
+    return QDSE_ENOMEM;
+  }
+  return QDSE_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+struct qdse_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;      // caller's stream
+  hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
+  qdse_grid grid{};
+  HostGrid hg;
+  int n_inst = 0, precision = 0, n_blocks = 0;
+  std::vector<qdse_params> params;
+  std::vector<double> block_omega;
+  std::vector<InstDev> inst_h;
+  size_t kstride = 0;  // doubles per kernel block (NKER * n * ldk)
+  // device data
+  double *d_s = nullptr, *d_t = nullptr, *d_W = nullptr, *d_z = nullptr, *d_wz = nullptr,
+         *d_sw = nullptr;
+  int* d_lo = nullptr;
+  double* d_K = nullptr;
+  double* d_dK = nullptr;  // omega derivatives, built on first gradient request
+  float* d_K32 = nullptr;
+  InstDev* d_inst = nullptr;
+  double* d_nodes = nullptr;  // [n_inst][10][ldk]
+  double* d_xbuf[2] = {nullptr, nullptr};
+  SolveState* d_state = nullptr;
+  SolveCtl* d_ctl = nullptr;
+  // graph of a chunk of masked sweeps
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_chunk = 0;
+  // vjp / Krylov workspace (lazy)
+  double *d_part = nullptr, *d_gq = nullptr;
+  int nchunk = 16;
+};
+
+namespace {
+
+int validate(const qdse_grid* g, const qdse_params* p, int n_inst) {
+  if (!g || !p || n_inst < 1) return QDSE_EINVAL;
+  if (g->n_radial < 4 || g->n_radial > (1 << 16)) return QDSE_EINVAL;
+  if (g->n_angle < 1 || g->n_angle > (1 << 16)) return QDSE_EINVAL;
+  if (g->interp_order != 1 && g->interp_order != 3) return QDSE_EINVAL;
+  if (!(g->s_min > 0.0) || !(g->s_max > g->s_min) || !std::isfinite(g->s_max)) return QDSE_EINVAL;
+  for (int k = 0; k < n_inst; ++k) {
+    if (!(p[k].D >= 0.0) || !std::isfinite(p[k].D)) return QDSE_EINVAL;
+    if (!(p[k].omega > 0.0) || !std::isfinite(p[k].omega)) return QDSE_EINVAL;
+    if (!std::isfinite(p[k].m)) return QDSE_EINVAL;
+  }
+  return QDSE_OK;
+}
+
+template <class T>
+int upload(T** d, const std::vector<T>& h, hipStream_t st) {
+  int rc = dalloc(d, h.size());
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return QDSE_OK;
+}
+
+int build_dK(qdse_ctx* c) {
+  if (c->d_dK) return QDSE_OK;
+  int rc = dalloc(&c->d_dK, c->kstride * c->n_blocks);
+  if (rc) return rc;
+  const HostGrid& g = c->hg;
+  for (int b = 0; b < c->n_blocks; ++b) {
+    HIPCHK(launch_precompute(c->stream, g.n, g.nq, g.na, g.ldk, c->d_s, c->d_t, c->d_W, c->d_z,
+                             c->d_wz, c->block_omega[b], 1, c->d_K + b * c->kstride,
+                             c->d_dK + b * c->kstride));
+  }
+  return QDSE_OK;
+}
+
+size_t xlen(const qdse_ctx* c) { return (size_t)c->n_inst * 2 * c->hg.n; }
+
+}  // namespace
+
+extern "C" {
+
+int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int precision,
+               void* hip_stream, qdse_ctx** out) {
+  if (!out) return QDSE_EINVAL;
+  *out = nullptr;
+  int rc = validate(grid, params, n_inst);
+  if (rc) return rc;
+  if (precision != QDSE_FP64 && precision != QDSE_FP32_REFINE) return QDSE_EINVAL;
+  qdse_ctx* c = new (std::nothrow) qdse_ctx();
+  if (!c) return QDSE_ENOMEM;
+  c->grid = *grid;
+  c->n_inst = n_inst;
+  c->precision = precision;
+  c->params.assign(params, params + n_inst);
+  c->stream = (hipStream_t)hip_stream;
+  if (build_grid(*grid, &c->hg)) {
+    delete c;
+    return QDSE_EINVAL;
+  }
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    g_last_error = "hipGetDevice failed";
+    return QDSE_EDEVICE;
+  }
+  // omega classes: instances with equal omega share kernel matrices
+  c->inst_h.resize(n_inst);
+  for (int k = 0; k < n_inst; ++k) {
+    int b = -1;
+    for (int q = 0; q < (int)c->block_omega.size(); ++q)
+      if (c->block_omega[q] == params[k].omega) b = q;
+    if (b < 0) {
+      b = (int)c->block_omega.size();
+      c->block_omega.push_back(params[k].omega);
+    }
+    const double om = params[k].omega;
+    InstDev d{};
+    d.pref = (4.0 / 3.0) / (8.0 * PI * PI * PI) * 8.0 * PI * PI * params[k].D / (om * om * om * om);
+    d.m = params[k].m;
+    d.D = params[k].D;
+    d.omega = om;
+    d.kblock = b;
+    c->inst_h[k] = d;
+  }
+  c->n_blocks = (int)c->block_omega.size();
+  const HostGrid& g = c->hg;
+  c->kstride = (size_t)NKER * g.n * g.ldk;
+  hipStream_t st = c->stream;
+#define TRY(x)            \
+  do {                    \
+    int r_ = (x);         \
+    if (r_) {             \
+      qdse_destroy(c);    \
+      return r_;          \
+    }                     \
+  } while (0)
+  TRY(upload(&c->d_s, g.s, st));
+  TRY(upload(&c->d_t, g.t, st));
+  TRY(upload(&c->d_W, g.W, st));
+  TRY(upload(&c->d_z, g.z, st));
+  TRY(upload(&c->d_wz, g.wz, st));
+  TRY(upload(&c->d_sw, g.sw, st));
+  TRY(upload(&c->d_lo, g.lo, st));
+  TRY(upload(&c->d_inst, c->inst_h, st));
+  TRY(dalloc(&c->d_K, c->kstride * c->n_blocks));
+  TRY(dalloc(&c->d_nodes, (size_t)n_inst * 10 * g.ldk));
+  TRY(dalloc(&c->d_xbuf[0], xlen(c)));
+  TRY(dalloc(&c->d_xbuf[1], xlen(c)));
+  TRY(dalloc(&c->d_state, (size_t)n_inst));
+  TRY(dalloc(&c->d_ctl, 1));
+  for (int b = 0; b < c->n_blocks; ++b) {
+    hipError_t e = launch_precompute(st, g.n, g.nq, g.na, g.ldk, c->d_s, c->d_t, c->d_W, c->d_z,
+                                     c->d_wz, c->block_omega[b], 0, c->d_K + b * c->kstride,
+                                     nullptr);
+    if (e != hipSuccess) {
+      g_last_error = std::string("precompute: ") + hipGetErrorString(e);
+      qdse_destroy(c);
+      return QDSE_EDEVICE;
+    }
+  }
+  if (precision == QDSE_FP32_REFINE) {
+    TRY(dalloc(&c->d_K32, c->kstride * c->n_blocks));
+    hipError_t e = launch_k_to_f32(st, c->d_K, c->d_K32, c->kstride * c->n_blocks);
+    if (e != hipSuccess) {
+      g_last_error = std::string("k_to_f32: ") + hipGetErrorString(e);
+      qdse_destroy(c);
+      return QDSE_EDEVICE;
+    }
+  }
+#undef TRY
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    g_last_error = "setup synchronisation failed";
+    qdse_destroy(c);
+    return QDSE_EDEVICE;
+  }
+  *out = c;
+  return QDSE_OK;
+}
+
+void qdse_destroy(qdse_ctx* c) {
+  if (!c) return;
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  void* ptrs[] = {c->d_s,     c->d_t,     c->d_W,       c->d_z,       c->d_wz,    c->d_sw,
+                  c->d_lo,    c->d_K,     c->d_dK,      c->d_K32,     c->d_inst,  c->d_nodes,
+                  c->d_xbuf[0], c->d_xbuf[1], c->d_state, c->d_ctl, c->d_part, c->d_gq};
+  for (void* p : ptrs) dfree(p);
+  delete c;
+}
+
+int qdse_dims(const qdse_ctx* c, int* n_radial, int* n_loop, int* n_angle, int* n_inst) {
+  if (!c) return QDSE_EINVAL;
+  if (n_radial) *n_radial = c->hg.n;
+  if (n_loop) *n_loop = c->hg.nq;
+  if (n_angle) *n_angle = c->hg.na;
+  if (n_inst) *n_inst = c->n_inst;
+  return QDSE_OK;
+}
+
+int qdse_nodes(const qdse_ctx* c, double* s, double* t) {
+  if (!c) return QDSE_EINVAL;
+  if (s) std::memcpy(s, c->hg.s.data(), c->hg.n * sizeof(double));
+  if (t) std::memcpy(t, c->hg.t.data(), c->hg.nq * sizeof(double));
+  return QDSE_OK;
+}
+
+int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
+  if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
+  const HostGrid& g = c->hg;
+  HIPCHK(launch_sweep_fp64(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                           c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out, c->d_nodes, nullptr,
+                           nullptr, 0, 1));
+  return QDSE_OK;
+}
+
+int qdse_iterate_fp32(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
+  if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
+  if (!c->d_K32) return QDSE_ENOTSUP;
+  return QDSE_ENOTSUP;
+}
+
+static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk) {
+  const HostGrid& g = c->hg;
+  for (int k = 1; k <= chunk; ++k) {
+    const int p = k & 1;  // sweep k reads xbuf[(k-1)%2] and writes xbuf[k%2]
+    HIPCHK(launch_sweep_fp64(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                             c->d_lo, c->d_sw, c->d_t, c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p],
+                             c->d_nodes, c->d_state, c->d_ctl, p, 1));
+  }
+  return QDSE_OK;
+}
+
+int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode, int* iters,
+               double* resid) {
+  if (!c || !d_x || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
+  if (conv_mode != QDSE_CONV_ABS && conv_mode != QDSE_CONV_MASS) return QDSE_EINVAL;
+  const int chunk = 16;  // even: a chunk ends with the iterate in xbuf[0]
+  const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
+  hipStream_t st = c->stream;
+  SolveCtl ctl{tol, conv_mode, max_iter};
+  HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
+  HIPCHK(hipMemcpyAsync(c->d_xbuf[0], d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (use_graph && (!c->graph_exec || c->graph_chunk != chunk)) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (c->graph_exec) {
+      (void)hipGraphExecDestroy(c->graph_exec);
+      c->graph_exec = nullptr;
+    }
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = record_chunk(c, c->cap_stream, chunk);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc) return rc;
+    HIPCHK(e);
+    e = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+    c->graph_chunk = chunk;
+  }
+  std::vector<SolveState> hs(c->n_inst);
+  long launched = 0;
+  const long limit = (long)max_iter + 1 + chunk;
+  bool all_done = false;
+  while (launched < limit) {
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(c->graph_exec, st));
+    } else {
+      int rc = record_chunk(c, st, chunk);
+      if (rc) return rc;
+    }
+    launched += chunk;
+    HIPCHK(hipMemcpyAsync(hs.data(), c->d_state, hs.size() * sizeof(SolveState),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    all_done = true;
+    for (const SolveState& s : hs)
+      if (s.status == 0) all_done = false;
+    if (all_done) break;
+  }
+  HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[0], xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int rc = QDSE_OK;
+  for (int k = 0; k < c->n_inst; ++k) {
+    const SolveState& s = hs[k];
+    if (iters) iters[k] = s.sweeps;
+    if (resid) resid[k] = s.resid;
+    if (s.status == 3) rc = QDSE_ENAN;
+    else if ((s.status == 2 || s.status == 0) && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
+  }
+  if (!all_done && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
+  return rc;
+}
+
+int qdse_jvp(qdse_ctx* c, const double* d_x, const double* d_v, double* d_jv) {
+  if (!c || !d_x || !d_v || !d_jv) return QDSE_EINVAL;
+  const HostGrid& g = c->hg;
+  HIPCHK(launch_jvp(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
+                    c->d_sw, c->d_t, c->d_s, d_x, d_v, d_jv, c->d_nodes));
+  return QDSE_OK;
+}
+
+static int ensure_vjp_work(qdse_ctx* c) {
+  if (c->d_part) return QDSE_OK;
+  const HostGrid& g = c->hg;
+  int rc = dalloc(&c->d_part, (size_t)c->n_inst * c->nchunk * 4 * g.ldk);
+  if (rc) return rc;
+  return dalloc(&c->d_gq, (size_t)c->n_inst * 2 * g.ldk);
+}
+
+static int vjp_on(qdse_ctx* c, const double* K, const double* d_x, const double* d_w, double* d_out) {
+  int rc = ensure_vjp_work(c);
+  if (rc) return rc;
+  const HostGrid& g = c->hg;
+  HIPCHK(launch_vjp(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, K, c->kstride, c->d_lo,
+                    c->d_sw, c->d_t, c->d_s, d_x, d_w, d_out, c->d_nodes, c->d_part, c->d_gq,
+                    c->nchunk));
+  return QDSE_OK;
+}
+
+int qdse_vjp(qdse_ctx* c, const double* d_x, const double* d_w, double* d_out) {
+  if (!c || !d_x || !d_w || !d_out || d_w == d_out) return QDSE_EINVAL;
+  return vjp_on(c, c->d_K, d_x, d_w, d_out);
+}
+
+int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol, int max_iter,
+              double* theta_bar) {
+  if (!c || !d_xstar || !d_g || !theta_bar || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
+  for (const qdse_params& p : c->params)
+    if (!(p.D > 0.0)) return QDSE_EINVAL;
+  int rc = build_dK(c);
+  if (rc) return rc;
+  const HostGrid& g = c->hg;
+  const int nI = c->n_inst, len = 2 * g.n;
+  const size_t L = xlen(c);
+  const int mres = 40;  // Krylov basis size before a restart
+  hipStream_t st = c->stream;
+
+  double *d_V = nullptr, *d_w = nullptr, *d_lam = nullptr, *d_r = nullptr, *d_h = nullptr,
+         *d_y = nullptr, *d_y1 = nullptr, *d_y2 = nullptr, *d_eB = nullptr, *d_sc = nullptr;
+  struct Guard {
+    std::vector<double*> ps;
+    ~Guard() {
+      for (double* p : ps) dfree(p);
+    }
+  } guard;
+#define ALLOC(p, n)                 \
+  do {                              \
+    int r_ = dalloc(&(p), (n));     \
+    if (r_) return r_;              \
+    guard.ps.push_back(p);          \
+  } while (0)
+  ALLOC(d_V, (size_t)(mres + 1) * L);
+  ALLOC(d_w, L);
+  ALLOC(d_lam, L);
+  ALLOC(d_r, L);
+  ALLOC(d_h, (size_t)nI * (mres + 2));
+  ALLOC(d_y, (size_t)nI * (mres + 1));
+  ALLOC(d_y1, L);
+  ALLOC(d_y2, L);
+  ALLOC(d_eB, L);
+  ALLOC(d_sc, (size_t)nI);
+#undef ALLOC
+  HIPCHK(hipMemsetAsync(d_lam, 0, L * sizeof(double), st));
+
+  // norms of g for the relative stopping test
+  std::vector<double> gnorm(nI), hh((size_t)nI * (mres + 2)), tmp(nI);
+  HIPCHK(launch_batched_dot(st, nI, len, d_g, 0, d_g, len, 1, d_sc));
+  HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < nI; ++k) gnorm[k] = std::sqrt(tmp[k]);
+
+  // A lambda = lambda - J^T lambda
+  auto apply = [&](const double* in, double* out_) -> int {
+    int r = vjp_on(c, c->d_K, d_xstar, in, out_);
+    if (r) return r;
+    HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));  // out = in - J^T in
+    return QDSE_OK;
+  };
+
+  bool converged = false;
+  int total = 0;
+  std::vector<double> beta(nI), cs((size_t)nI * mres), sn((size_t)nI * mres),
+      Hm((size_t)nI * (mres + 1) * mres), gvec((size_t)nI * (mres + 1)), ysol((size_t)nI * (mres + 1));
+  while (!converged && total < max_iter) {
+    // r = g - A lambda
+    rc = apply(d_lam, d_r);
+    if (rc) return rc;
+    HIPCHK(launch_axpby(st, nI, len, -1.0, d_r, nullptr, d_g, d_r));
+    HIPCHK(launch_batched_dot(st, nI, len, d_r, 0, d_r, len, 1, d_sc));
+    HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    converged = true;
+    for (int k = 0; k < nI; ++k) {
+      beta[k] = std::sqrt(tmp[k]);
+      if (beta[k] > tol * gnorm[k]) converged = false;
+      tmp[k] = beta[k] > 0.0 ? 1.0 / beta[k] : 0.0;
+    }
+    if (converged) break;
+    HIPCHK(hipMemcpyAsync(d_sc, tmp.data(), nI * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_axpby(st, nI, len, 0.0, d_r, d_sc, d_r, d_V));  // v0 = r / beta
+    std::fill(Hm.begin(), Hm.end(), 0.0);
+    std::fill(gvec.begin(), gvec.end(), 0.0);
+    for (int k = 0; k < nI; ++k) gvec[(size_t)k * (mres + 1)] = beta[k];
+    int kdim = 0;
+    for (int j = 0; j < mres && total < max_iter; ++j, ++total) {
+      double* vj = d_V + (size_t)j * L;
+      double* vn = d_V + (size_t)(j + 1) * L;
+      rc = apply(vj, d_w);
+      if (rc) return rc;
+      // two passes of classical Gram-Schmidt, coefficients summed on the host
+      std::vector<double> hcol((size_t)nI * (j + 1), 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        HIPCHK(launch_batched_dot(st, nI, len, d_V, L, d_w, len, j + 1, d_h));
+        HIPCHK(launch_gs_update(st, nI, len, d_V, L, j + 1, d_h, j + 1, d_w));
+        HIPCHK(hipMemcpyAsync(hh.data(), d_h, (size_t)nI * (j + 1) * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t q = 0; q < hcol.size(); ++q) hcol[q] += hh[q];
+      }
+      HIPCHK(launch_batched_dot(st, nI, len, d_w, 0, d_w, len, 1, d_sc));
+      HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool all_small = true;
+      for (int k = 0; k < nI; ++k) {
+        double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;  // column-major (mres+1) x mres
+        double* gk = gvec.data() + (size_t)k * (mres + 1);
+        const double hn = std::sqrt(tmp[k]);
+        for (int i = 0; i <= j; ++i) Hk[(size_t)j * (mres + 1) + i] = hcol[(size_t)k * (j + 1) + i];
+        Hk[(size_t)j * (mres + 1) + j + 1] = hn;
+        // previous Givens rotations, then a new one to zero H[j+1][j]
+        for (int i = 0; i < j; ++i) {
+          const double a = Hk[(size_t)j * (mres + 1) + i], b = Hk[(size_t)j * (mres + 1) + i + 1];
+          const double cc = cs[(size_t)k * mres + i], ss = sn[(size_t)k * mres + i];
+          Hk[(size_t)j * (mres + 1) + i] = cc * a + ss * b;
+          Hk[(size_t)j * (mres + 1) + i + 1] = -ss * a + cc * b;
+        }
+        const double a = Hk[(size_t)j * (mres + 1) + j], b = hn;
+        const double rr = std::hypot(a, b);
+        const double cc = rr > 0.0 ? a / rr : 1.0, ss = rr > 0.0 ? b / rr : 0.0;
+        cs[(size_t)k * mres + j] = cc;
+        sn[(size_t)k * mres + j] = ss;
+        Hk[(size_t)j * (mres + 1) + j] = rr;
+        Hk[(size_t)j * (mres + 1) + j + 1] = 0.0;
+        gk[j + 1] = -ss * gk[j];
+        gk[j] = cc * gk[j];
+        if (std::fabs(gk[j + 1]) > tol * gnorm[k]) all_small = false;
+        tmp[k] = hn > 0.0 ? 1.0 / hn : 0.0;
+      }
+      HIPCHK(hipMemcpyAsync(d_sc, tmp.data(), nI * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(launch_axpby(st, nI, len, 0.0, d_w, d_sc, d_w, vn));
+      kdim = j + 1;
+      if (all_small) {
+        ++total;
+        break;
+      }
+    }
+    // solve the triangular systems and update lambda += V y
+    for (int k = 0; k < nI; ++k) {
+      const double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;
+      const double* gk = gvec.data() + (size_t)k * (mres + 1);
+      double* yk = ysol.data() + (size_t)k * (mres + 1);
+      for (int i = kdim - 1; i >= 0; --i) {
+        double acc = gk[i];
+        for (int q = i + 1; q < kdim; ++q) acc -= Hk[(size_t)q * (mres + 1) + i] * yk[q];
+        const double d = Hk[(size_t)i * (mres + 1) + i];
+        yk[i] = d != 0.0 ? acc / d : 0.0;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(d_y, ysol.data(), (size_t)nI * (mres + 1) * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(launch_combine(st, nI, len, d_V, L, kdim, d_y, mres + 1, 1.0, d_lam));
+  }
+  // theta_bar = lambda^T dF/dtheta
+  HIPCHK(launch_sweep_fp64(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
+                           c->d_sw, c->d_t, c->d_s, d_xstar, d_y1, c->d_nodes, nullptr, nullptr, 0,
+                           0));  // F - f0
+  HIPCHK(launch_sweep_fp64(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_dK, c->kstride, c->d_lo,
+                           c->d_sw, c->d_t, c->d_s, d_xstar, d_y2, c->d_nodes, nullptr, nullptr, 0,
+                           0));  // pref * S(dK/domega)
+  {
+    std::vector<double> eB(L, 0.0);
+    for (int k = 0; k < nI; ++k)
+      for (int i = 0; i < g.n; ++i) eB[(size_t)k * len + g.n + i] = 1.0;
+    HIPCHK(hipMemcpyAsync(d_eB, eB.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+    std::vector<double> d1(nI), d2(nI), d3(nI);
+    HIPCHK(launch_batched_dot(st, nI, len, d_y1, 0, d_lam, len, 1, d_sc));
+    HIPCHK(hipMemcpyAsync(d1.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_batched_dot(st, nI, len, d_y2, 0, d_lam, len, 1, d_sc));
+    HIPCHK(hipMemcpyAsync(d2.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_batched_dot(st, nI, len, d_eB, 0, d_lam, len, 1, d_sc));
+    HIPCHK(hipMemcpyAsync(d3.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < nI; ++k) {
+      const double D = c->params[k].D, om = c->params[k].omega;
+      theta_bar[3 * k + 0] = d1[k] / D;
+      theta_bar[3 * k + 1] = -4.0 / om * d1[k] + d2[k];
+      theta_bar[3 * k + 2] = d3[k];
+    }
+  }
+  return converged ? QDSE_OK : QDSE_NOT_CONVERGED;
+}
+
+int qdse_kernel_matrices(qdse_ctx* c, int inst, double* d_K) {
+  if (!c || !d_K || inst < 0 || inst >= c->n_inst) return QDSE_EINVAL;
+  const HostGrid& g = c->hg;
+  const double* src = c->d_K + (size_t)c->inst_h[inst].kblock * c->kstride;
+  HIPCHK(hipMemcpy2DAsync(d_K, g.nq * sizeof(double), src, g.ldk * sizeof(double),
+                          g.nq * sizeof(double), (size_t)NKER * g.n, hipMemcpyDeviceToDevice,
+                          c->stream));
+  return QDSE_OK;
+}
+
+int qdse_time_contraction(qdse_ctx* c, const double* d_x, double* d_out, int reps,
+                          double* avg_ms) {
+  if (!c || !d_x || !d_out || d_x == d_out || reps < 1 || !avg_ms) return QDSE_EINVAL;
+  const HostGrid& g = c->hg;
+  hipStream_t st = c->stream;
+  HIPCHK(launch_nodes_only(st, c->n_inst, g.n, g.nq, g.ldk, c->d_lo, c->d_sw, c->d_t, d_x,
+                           c->d_nodes));
+  std::vector<hipEvent_t> ev(2 * reps, nullptr);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  int rc = QDSE_OK;
+  for (int r = 0; r < reps && rc == QDSE_OK; ++r) {
+    if (hipEventRecord(ev[2 * r], st) != hipSuccess ||
+        launch_contraction_only(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                                c->d_s, d_x, d_out, c->d_nodes) != hipSuccess ||
+        hipEventRecord(ev[2 * r + 1], st) != hipSuccess)
+      rc = QDSE_EDEVICE;
+  }
+  double tot = 0.0;
+  if (rc == QDSE_OK && hipStreamSynchronize(st) == hipSuccess) {
+    for (int r = 0; r < reps; ++r) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess) rc = QDSE_EDEVICE;
+      tot += ms;
+    }
+  } else {
+    rc = QDSE_EDEVICE;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) {
+    g_last_error = "qdse_time_contraction: HIP event timing failed";
+    return rc;
+  }
+  *avg_ms = tot / reps;
+  return QDSE_OK;
+}
+
+const char* qdse_strerror(int code) {
+  switch (code) {
+    case QDSE_OK: return "ok";
+    case QDSE_NOT_CONVERGED: return "not converged within the iteration limit";
+    case QDSE_EINVAL: return "invalid argument";
+    case QDSE_ENOMEM: return "out of memory";
+    case QDSE_EDEVICE: return "HIP device error";
+    case QDSE_ENAN: return "iterate became NaN or infinite";
+    case QDSE_ENOTSUP: return "not supported by this context";
+    default: return "unknown status code";
+  }
+}
+
+const char* qdse_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

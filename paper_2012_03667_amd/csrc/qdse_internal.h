@@ -1,0 +1,94 @@
+// qdse_internal.h -- shared declarations of the gfx950 gap-equation library
+// (host grid construction, kernel launchers and the context layout).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/qdse.h"
+
+namespace qdse {
+
+// Host copy of one discretisation (see qdse_grid.cpp).
+struct HostGrid {
+  int n = 0, nq = 0, na = 0, ldk = 0;
+  std::vector<double> u, s;       // external nodes: ln p^2 and p^2        [n]
+  std::vector<double> uq, t, W;   // loop nodes: ln q^2, q^2, weight t^2 du [nq]
+  std::vector<double> z, wz;      // angular nodes and w_a sqrt(1 - z_a^2)  [na]
+  std::vector<int> lo;            // stencil base index                     [nq]
+  std::vector<double> sw;         // stencil weights                        [nq][4]
+};
+
+void gauss_legendre(int n, double* x, double* w);
+int build_grid(const qdse_grid& g, HostGrid* hg);
+
+// Per-instance constants on the device.
+struct InstDev {
+  double pref;   // C_F/(8 pi^3) * 8 pi^2 D / omega^4: multiplies every loop sum
+  double m;      // current mass
+  double D;      // interaction strength (for parameter derivatives)
+  double omega;  // interaction range
+  int kblock;    // which kernel-matrix block (omega class) the instance uses
+  int pad;
+};
+
+// Controls of a masked successive-approximation run (device copy).
+struct SolveCtl {
+  double tol;
+  int mode;      // QDSE_CONV_ABS or QDSE_CONV_MASS
+  int max_iter;
+};
+
+// Per-instance state of a masked run (device).
+struct SolveState {
+  int status;                   // 0 running, 1 converged, 2 max_iter, 3 non-finite
+  int sweeps;                   // sweeps done while running
+  double resid;                 // test statistic of the deciding sweep
+  unsigned long long metric[2]; // bits of the non-negative max over rows, per parity
+};
+
+// Matrices per kernel block: K_T, K_3, K_0 (see qdse_kernels.hip).
+constexpr int NKER = 3;
+
+// ---- launchers (qdse_kernels.hip); all asynchronous on `st` --------------
+hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, const double* s,
+                             const double* t, const double* W, const double* z, const double* wz,
+                             double omega, int with_domega, double* K, double* dK);
+hipError_t launch_k_to_f32(hipStream_t st, const double* K, float* K32, size_t count);
+hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state);
+// One FP64 sweep: node functions, then the contraction and update. With
+// state != nullptr the run is masked (frozen instances carry their iterate).
+// add_f0 = 0 drops the inhomogeneous terms (1, m) from the output.
+hipError_t launch_sweep_fp64(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                             const InstDev* inst, const double* K, size_t kstride, const int* lo,
+                             const double* sw, const double* t, const double* s,
+                             const double* x_in, double* x_out, double* nodes, SolveState* state,
+                             const SolveCtl* ctl, int parity, int add_f0);
+hipError_t launch_contraction_only(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                                  const InstDev* inst, const double* K, size_t kstride,
+                                  const double* s, const double* x_in, double* x_out,
+                                  const double* nodes);
+hipError_t launch_nodes_only(hipStream_t st, int n_inst, int n, int nq, int ldk, const int* lo,
+                             const double* sw, const double* t, const double* x, double* nodes);
+hipError_t launch_jvp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
+                      const double* K, size_t kstride, const int* lo, const double* sw,
+                      const double* t, const double* s, const double* x, const double* v,
+                      double* jv, double* nodes);
+hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
+                      const double* K, size_t kstride, const int* lo, const double* sw,
+                      const double* t, const double* s, const double* x, const double* w,
+                      double* out, double* nodes, double* part, double* gq, int nchunk);
+hipError_t launch_batched_dot(hipStream_t st, int n_inst, int len, const double* a, size_t lda,
+                              const double* b, size_t ldb, int nvec, double* out);
+// w[inst][:] -= sum_v h[inst * hstride + v] V[v][inst][:]  (Gram-Schmidt step)
+hipError_t launch_gs_update(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
+                            int nvec, const double* h, int hstride, double* w);
+// out[inst][:] = beta * out[inst][:] + sum_v y[inst * ystride + v] V[v][inst][:]
+hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
+                          int nvec, const double* y, int ystride, double beta, double* out);
+// dst[inst][:] = alpha * a[inst][:] + scale[inst] * b[inst][:] (scale may be null: 1)
+hipError_t launch_axpby(hipStream_t st, int n_inst, int len, double alpha, const double* a,
+                        const double* scale, const double* b, double* dst);
+
+}  // namespace qdse

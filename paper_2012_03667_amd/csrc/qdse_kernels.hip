@@ -1,0 +1,665 @@
+// qdse_kernels.hip -- gfx950 kernels of the Ball-Chiu quark gap-equation
+// solver (arXiv:2012.03667, Sec. II eqs. dsesys/dsesys2, Sec. III).
+//
+// Every sweep of the successive approximation evaluates, for each external
+// node p^2 = s_i, a radial x angular Gauss-Legendre sum over loop nodes
+// q^2 = t_j and angles z_a. Nothing in the angular sum depends on the unknowns
+// A, B, so it is done once per (grid, omega) by k_precompute; a sweep is then
+// an O(N^2) contraction of three angular-integrated matrices with per-loop-node
+// functions of the interpolated A(t_j), B(t_j).
+//
+// Angular algebra. With r = sqrt(s t), k^2 = (sqrt s - sqrt t)^2 + 2 r (1 - z)
+// and P = p + q, the transverse projector of the Landau-gauge gluon makes the
+// bracketed factors of eq. dsesys2 collapse to
+//   I_A1 factor  2 t (1-z^2)/k^2,           I_A2 factor  t (s+t)(1-z^2)/k^2,
+//   I_A3 factor  [3 r z (s+t) - 2 s t (1+2z^2)]/(s k^2),
+//   I_B1 factor = I_B3 factor = 2 s t (1-z^2)/k^2,   I_B2 factor 1,
+// so three angular sums per (i, j) suffice:
+//   S_T = sum_a w_a sqrt(1-z_a^2) E (1-z_a^2)/k^2,
+//   S_3 = sum_a w_a sqrt(1-z_a^2) E [3 r z (s+t) - 2 s t (1+2 z^2)]/k^2,
+//   S_0 = sum_a w_a sqrt(1-z_a^2) E,              E = exp(-k^2/omega^2).
+// Stored matrices (radial weight W_j = w_j t_j^2 and L_ij = 1/(t_j - s_i),
+// the singular kernel of Sec. II, folded in):
+//   K_T = W t L S_T,   K_3 = W S_3 / (2 s),   K_0 = 3 W S_0 / 2.
+// With sigma_V = A(t)/Delta, sigma_S = B(t)/Delta, Delta = t A(t)^2 + B(t)^2:
+//   A'_i = 1 + pref [ -sum_j K_T (2 sigma_S dB + (s_i+t_j) sigma_V dA)
+//                     + sum_j K_3 sigma_V sA ]
+//   B'_i = m + pref [ 2 s_i sum_j K_T (sigma_S dA - sigma_V dB)
+//                     + sum_j K_0 sigma_S sA ]
+// where dA = A(t_j) - A(s_i), dB = B(t_j) - B(s_i), sA = A(t_j) + A(s_i)
+// (the Ball-Chiu difference quotients and sigma_A, eq. (2)), and
+// pref = C_F/(8 pi^3) * 8 pi^2 D/omega^4. The differences are formed directly
+// in FP64 before they multiply the singular kernel.
+
+#include "qdse_internal.h"
+
+namespace qdse {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Forward-mode dual number: value and directional derivative.
+struct Dual {
+  double v, d;
+  __device__ Dual() = default;
+  __device__ constexpr Dual(double a, double b) : v(a), d(b) {}
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ inline Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+__device__ inline Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ inline Dual dual_fma(Dual a, Dual b, Dual c) { return a * b + c; }
+__device__ inline double dual_fma(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline Dual wave_sum(Dual x) { return {wave_sum(x.v), wave_sum(x.d)}; }
+
+template <class T> __device__ inline T make(double v, double d);
+template <> __device__ inline double make<double>(double v, double) { return v; }
+template <> __device__ inline Dual make<Dual>(double v, double d) { return {v, d}; }
+__device__ inline double val(double x) { return x; }
+__device__ inline double val(Dual x) { return x.v; }
+__device__ inline double tan_(Dual x) { return x.d; }
+
+// ---------------------------------------------------------------- precompute
+// One thread per (i, j); the angular sum runs over a in registers. Writes the
+// three matrices (and optionally their omega derivatives) of one omega class,
+// zero in the padding columns j >= nq.
+__global__ void k_precompute(int n, int nq, int na, int ldk, const double* __restrict__ s_,
+                             const double* __restrict__ t_, const double* __restrict__ W_,
+                             const double* __restrict__ z_, const double* __restrict__ wz_,
+                             double omega, int with_domega, double* __restrict__ K,
+                             double* __restrict__ dK) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * ldk) return;
+  const int i = (int)(idx / ldk), j = (int)(idx % ldk);
+  const size_t mat = (size_t)n * ldk;
+  const size_t o = (size_t)i * ldk + j;
+  if (j >= nq) {
+    K[o] = 0.0;
+    K[mat + o] = 0.0;
+    K[2 * mat + o] = 0.0;
+    if (with_domega) {
+      dK[o] = 0.0;
+      dK[mat + o] = 0.0;
+      dK[2 * mat + o] = 0.0;
+    }
+    return;
+  }
+  const double s = s_[i], t = t_[j];
+  const double rs = sqrt(s), rt = sqrt(t), r = rs * rt;
+  const double d0 = (rs - rt) * (rs - rt);
+  const double inv_om2 = 1.0 / (omega * omega);
+  double sT = 0.0, s3 = 0.0, s0 = 0.0, dT = 0.0, d3 = 0.0, dd0 = 0.0;
+  for (int a = 0; a < na; ++a) {
+    const double z = z_[a], w = wz_[a];
+    const double omz = 1.0 - z, opz = 1.0 + z;
+    const double k2 = fma(2.0 * r, omz, d0);
+    const double E = w * exp(-k2 * inv_om2);
+    const double tr = omz * opz / k2;
+    const double f3 = (3.0 * r * z * (s + t) - 2.0 * s * t * (1.0 + 2.0 * z * z)) / k2;
+    sT = fma(E, tr, sT);
+    s3 = fma(E, f3, s3);
+    s0 += E;
+    if (with_domega) {  // d/domega exp(-k^2/omega^2) = 2 k^2/omega^3 exp(...)
+      const double g = E * k2;
+      dT = fma(g, tr, dT);
+      d3 = fma(g, f3, d3);
+      dd0 += g;
+    }
+  }
+  const double W = W_[j], L = 1.0 / (t - s);
+  K[o] = W * t * L * sT;
+  K[mat + o] = W * s3 / (2.0 * s);
+  K[2 * mat + o] = 1.5 * W * s0;
+  if (with_domega) {
+    const double c = 2.0 / (omega * omega * omega);
+    dK[o] = c * W * t * L * dT;
+    dK[mat + o] = c * W * d3 / (2.0 * s);
+    dK[2 * mat + o] = c * 1.5 * W * dd0;
+  }
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t cnt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = (float)a[i];
+}
+
+// ---------------------------------------------------------------- masked runs
+__device__ inline double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Status of an instance at the start of a sweep, from the test statistic of
+// the previous sweep. Every block evaluates it the same way; block 0 records
+// it. Returns nonzero if the instance is frozen.
+__device__ inline int decide(SolveState* st, const SolveCtl* ctl, int parity, bool writer) {
+  SolveState& S = *st;
+  int status = S.status;
+  if (status != 0) return status;
+  const double prev = bits_to_double(S.metric[parity ^ 1]);
+  if (S.sweeps > 0) {
+    if (!(prev <= 1.7976931348623157e308)) status = 3;  // NaN or inf
+    else if (prev < ctl->tol) status = 1;
+  }
+  if (status == 0 && S.sweeps >= ctl->max_iter) status = 2;
+  if (writer && threadIdx.x == 0) {
+    if (status != 0) {
+      S.status = status;
+      S.resid = prev;
+    }
+    S.metric[parity] = 0ull;  // cleared for this sweep's reduction
+  }
+  return status;
+}
+
+__global__ void k_solve_init(int n_inst, SolveState* st) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_inst) return;
+  st[k].status = 0;
+  st[k].sweeps = 0;
+  st[k].resid = __longlong_as_double(0x7ff0000000000000ll);
+  st[k].metric[0] = 0x7ff0000000000000ull;  // +inf: no sweep yet
+  st[k].metric[1] = 0x7ff0000000000000ull;
+}
+
+// ---------------------------------------------------------------- node functions
+// Interpolated A, B at the loop nodes (4-point stencil with a base index known
+// from the interleaving, eq. chazhiresult and its cubic analogue) and the
+// functions the contraction needs: nodes[inst][5][ldk] =
+// {A(t), B(t), sigma_V, sigma_S, t sigma_V}, plus their tangents for Dual.
+template <class T>
+__device__ inline void node_values(int n, int j, const int* lo, const double* sw, double tj,
+                                   const double* xA, const double* xB, const double* vA,
+                                   const double* vB, T* out) {
+  const int b = lo[j];
+  const double* w = sw + 4 * j;
+  T Aq = make<T>(0.0, 0.0), Bq = make<T>(0.0, 0.0);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const T wl = make<T>(w[l], 0.0);
+    Aq = Aq + wl * make<T>(xA[b + l], vA ? vA[b + l] : 0.0);
+    Bq = Bq + wl * make<T>(xB[b + l], vB ? vB[b + l] : 0.0);
+  }
+  const T tt = make<T>(tj, 0.0);
+  const T Dl = tt * Aq * Aq + Bq * Bq;
+  const T sV = Aq / Dl, sS = Bq / Dl;
+  out[0] = Aq;
+  out[1] = Bq;
+  out[2] = sV;
+  out[3] = sS;
+  out[4] = tt * sV;
+}
+
+__global__ void k_nodes(int n, int nq, int ldk, const int* __restrict__ lo,
+                        const double* __restrict__ sw, const double* __restrict__ t,
+                        const double* __restrict__ x, double* __restrict__ nodes,
+                        SolveState* state, const SolveCtl* ctl, int parity) {
+  const int inst = blockIdx.y;
+  if (state && decide(state + inst, ctl, parity, blockIdx.x == 0)) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nq) return;
+  const double* xA = x + (size_t)inst * 2 * n;
+  double v[5];
+  node_values<double>(n, j, lo, sw, t[j], xA, xA + n, nullptr, nullptr, v);
+  double* o = nodes + (size_t)inst * 5 * ldk;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) o[(size_t)c * ldk + j] = v[c];
+}
+
+__global__ void k_nodes_dual(int n, int nq, int ldk, const int* __restrict__ lo,
+                             const double* __restrict__ sw, const double* __restrict__ t,
+                             const double* __restrict__ x, const double* __restrict__ vdir,
+                             double* __restrict__ nodes) {
+  const int inst = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nq) return;
+  const double* xA = x + (size_t)inst * 2 * n;
+  const double* vA = vdir + (size_t)inst * 2 * n;
+  Dual v[5];
+  node_values<Dual>(n, j, lo, sw, t[j], xA, xA + n, vA, vA + n, v);
+  double* o = nodes + (size_t)inst * 10 * ldk;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    o[(size_t)c * ldk + j] = v[c].v;
+    o[(size_t)(5 + c) * ldk + j] = v[c].d;
+  }
+}
+
+// ---------------------------------------------------------------- contraction
+// One 64-lane wavefront per (instance, external row i): lanes stride over
+// loop nodes j (coalesced K rows), accumulate the four sums of the direct
+// difference form, reduce across the wave, and lane 0 applies the update.
+template <class T>
+__device__ inline void row_accumulate(int nq, int ldk, size_t mat, const double* Ki,
+                                      const double* nd, const double* ndt, double s, T Ai, T Bi,
+                                      int lane, T acc[4]) {
+  for (int j = lane; j < nq; j += WAVE) {
+    const double kT = Ki[j], k3 = Ki[mat + j], k0 = Ki[2 * mat + j];
+    const T Aq = make<T>(nd[j], ndt ? ndt[j] : 0.0);
+    const T Bq = make<T>(nd[ldk + j], ndt ? ndt[ldk + j] : 0.0);
+    const T sV = make<T>(nd[2 * ldk + j], ndt ? ndt[2 * ldk + j] : 0.0);
+    const T sS = make<T>(nd[3 * ldk + j], ndt ? ndt[3 * ldk + j] : 0.0);
+    const T tsV = make<T>(nd[4 * ldk + j], ndt ? ndt[4 * ldk + j] : 0.0);
+    const T dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
+    const T sc = make<T>(s, 0.0);
+    // 2 sigma_S dB + (s + t) sigma_V dA
+    const T e = make<T>(2.0, 0.0) * sS * dB + (sc * sV + tsV) * dA;
+    acc[0] = acc[0] + make<T>(kT, 0.0) * e;
+    acc[1] = acc[1] + make<T>(k3, 0.0) * (sV * sA);
+    acc[2] = acc[2] + make<T>(kT, 0.0) * (sS * dA - sV * dB);
+    acc[3] = acc[3] + make<T>(k0, 0.0) * (sS * sA);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = wave_sum(acc[c]);
+}
+
+// Specialised FP64 body (explicit FMAs) for the hot sweep.
+__device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const double* __restrict__ Ki,
+                                          const double* __restrict__ nd, double s, double Ai,
+                                          double Bi, int lane, double acc[4]) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int j = lane; j < nq; j += WAVE) {
+    const double kT = Ki[j], k3 = Ki[mat + j], k0 = Ki[2 * mat + j];
+    const double Aq = nd[j], Bq = nd[ldk + j], sV = nd[2 * ldk + j], sS = nd[3 * ldk + j],
+                 tsV = nd[4 * ldk + j];
+    const double dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
+    const double e = fma(2.0 * sS, dB, fma(s, sV, tsV) * dA);
+    a0 = fma(kT, e, a0);
+    a1 = fma(k3, sV * sA, a1);
+    a2 = fma(kT, fma(sS, dA, -(sV * dB)), a2);
+    a3 = fma(k0, sS * sA, a3);
+  }
+  acc[0] = wave_sum(a0);
+  acc[1] = wave_sum(a1);
+  acc[2] = wave_sum(a2);
+  acc[3] = wave_sum(a3);
+}
+
+__device__ inline double test_stat(int mode, double An, double Bn, double Ao, double Bo) {
+  const double dA = fabs(An - Ao);
+  if (mode == QDSE_CONV_ABS) return fmax(dA, fabs(Bn - Bo));
+  const double Mn = Bn / An, Mo = Bo / Ao;
+  return fmax(dA, fabs(Mn - Mo) / fabs(Mn));
+}
+
+__global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ldk,
+                                               const InstDev* __restrict__ inst_,
+                                               const double* __restrict__ K, size_t kstride,
+                                               const double* __restrict__ s_,
+                                               const double* __restrict__ nodes,
+                                               const double* __restrict__ x_in,
+                                               double* __restrict__ x_out, SolveState* state,
+                                               const SolveCtl* ctl, int parity, int add_f0) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (row >= (long)n_inst * n) return;
+  const int inst = (int)(row / n), i = (int)(row % n);
+  const double* xi = x_in + (size_t)inst * 2 * n;
+  double* xo = x_out + (size_t)inst * 2 * n;
+  if (state && state[inst].status != 0) {  // frozen: carry the iterate along
+    if (lane == 0) {
+      xo[i] = xi[i];
+      xo[n + i] = xi[n + i];
+    }
+    return;
+  }
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
+  const double* nd = nodes + (size_t)inst * 5 * ldk;
+  const double s = s_[i];
+  const double Ai = xi[i], Bi = xi[n + i];
+  double acc[4];
+  row_accumulate_f64(nq, ldk, mat, Ki, nd, s, Ai, Bi, lane, acc);
+  if (lane == 0) {
+    const double An = (add_f0 ? 1.0 : 0.0) + P.pref * (acc[1] - acc[0]);
+    const double Bn = (add_f0 ? P.m : 0.0) + P.pref * fma(2.0 * s, acc[2], acc[3]);
+    xo[i] = An;
+    xo[n + i] = Bn;
+    if (state) {
+      const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
+      atomicMax(&state[inst].metric[parity], bits);
+      if (i == 0) state[inst].sweeps += 1;
+    }
+  }
+}
+
+// Tangent sweep: jv = dF/dx v, the same arithmetic in dual numbers.
+__global__ void __launch_bounds__(256) k_sweep_dual(int n_inst, int n, int nq, int ldk,
+                                                    const InstDev* __restrict__ inst_,
+                                                    const double* __restrict__ K, size_t kstride,
+                                                    const double* __restrict__ s_,
+                                                    const double* __restrict__ nodes,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ vdir,
+                                                    double* __restrict__ jv) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (row >= (long)n_inst * n) return;
+  const int inst = (int)(row / n), i = (int)(row % n);
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
+  const double* nd = nodes + (size_t)inst * 10 * ldk;
+  const double* xi = x + (size_t)inst * 2 * n;
+  const double* vi = vdir + (size_t)inst * 2 * n;
+  const Dual Ai{xi[i], vi[i]}, Bi{xi[n + i], vi[n + i]};
+  Dual acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  row_accumulate<Dual>(nq, ldk, mat, Ki, nd, nd + 5 * ldk, s_[i], Ai, Bi, lane, acc);
+  if (lane == 0) {
+    const double s = s_[i];
+    jv[(size_t)inst * 2 * n + i] = P.pref * (acc[1].d - acc[0].d);
+    jv[(size_t)inst * 2 * n + n + i] = P.pref * fma(2.0 * s, acc[2].d, acc[3].d);
+  }
+}
+
+// ---------------------------------------------------------------- reverse mode
+// Adjoint of one sweep. With abar_i = pref wA_i and bbar_i = pref wB_i the
+// accumulators of row i carry adjoints (-abar, abar, 2 s_i bbar, bbar).
+// Row part: d/dA_i and d/dB_i through dA, dB, sA (one wavefront per row).
+__global__ void __launch_bounds__(256) k_vjp_rows(int n_inst, int n, int nq, int ldk,
+                                                  const InstDev* __restrict__ inst_,
+                                                  const double* __restrict__ K, size_t kstride,
+                                                  const double* __restrict__ s_,
+                                                  const double* __restrict__ t_,
+                                                  const double* __restrict__ nodes,
+                                                  const double* __restrict__ w,
+                                                  double* __restrict__ out) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (row >= (long)n_inst * n) return;
+  const int inst = (int)(row / n), i = (int)(row % n);
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
+  const double* nd = nodes + (size_t)inst * 5 * ldk;
+  const double s = s_[i];
+  const double ab = P.pref * w[(size_t)inst * 2 * n + i];
+  const double bb = P.pref * w[(size_t)inst * 2 * n + n + i];
+  double gA = 0.0, gB = 0.0;
+  for (int j = lane; j < nq; j += WAVE) {
+    const double kT = Ki[j], k3 = Ki[mat + j], k0 = Ki[2 * mat + j];
+    const double sV = nd[2 * ldk + j], sS = nd[3 * ldk + j], t = t_[j];
+    // dF/ddA = -ab kT (s+t) sV + 2 s bb kT sS ; dF/dsA = ab k3 sV + bb k0 sS
+    const double gdA = kT * (2.0 * s * bb * sS - ab * (s + t) * sV);
+    const double gsA = ab * k3 * sV + bb * k0 * sS;
+    // dF/ddB = -2 ab kT sS - 2 s bb kT sV
+    const double gdB = -2.0 * kT * (ab * sS + s * bb * sV);
+    gA += gsA - gdA;
+    gB -= gdB;
+  }
+  gA = wave_sum(gA);
+  gB = wave_sum(gB);
+  if (lane == 0) {
+    out[(size_t)inst * 2 * n + i] = gA;
+    out[(size_t)inst * 2 * n + n + i] = gB;
+  }
+}
+
+// Column part: per loop node j, partial sums over a chunk of rows of the
+// adjoints of A(t_j), B(t_j) (through dA, dB, sA) and of sigma_V, sigma_S.
+// One thread per (instance, j, chunk); lanes over j read K rows coalesced.
+__global__ void k_vjp_cols(int n_inst, int n, int nq, int ldk, int nchunk,
+                           const InstDev* __restrict__ inst_, const double* __restrict__ K,
+                           size_t kstride, const double* __restrict__ s_,
+                           const double* __restrict__ t_, const double* __restrict__ nodes,
+                           const double* __restrict__ x, const double* __restrict__ w,
+                           double* __restrict__ part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y, inst = blockIdx.z;
+  if (j >= nq) return;
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  const double* Kb = K + (size_t)P.kblock * kstride;
+  const double* nd = nodes + (size_t)inst * 5 * ldk;
+  const double* xi = x + (size_t)inst * 2 * n;
+  const double* wi = w + (size_t)inst * 2 * n;
+  const double Aq = nd[j], Bq = nd[ldk + j], sV = nd[2 * ldk + j], sS = nd[3 * ldk + j];
+  const double t = t_[j];
+  const int r0 = (int)((long)n * chunk / nchunk), r1 = (int)((long)n * (chunk + 1) / nchunk);
+  double gAq = 0.0, gBq = 0.0, gsV = 0.0, gsS = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const double kT = Kb[(size_t)i * ldk + j], k3 = Kb[mat + (size_t)i * ldk + j],
+                 k0 = Kb[2 * mat + (size_t)i * ldk + j];
+    const double s = s_[i], Ai = xi[i], Bi = xi[n + i];
+    const double ab = P.pref * wi[i], bb = P.pref * wi[n + i];
+    const double dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
+    const double gdA = kT * (2.0 * s * bb * sS - ab * (s + t) * sV);
+    const double gsA = ab * k3 * sV + bb * k0 * sS;
+    const double gdB = -2.0 * kT * (ab * sS + s * bb * sV);
+    gAq += gdA + gsA;
+    gBq += gdB;
+    gsS += kT * (2.0 * s * bb * dA - 2.0 * ab * dB) + bb * k0 * sA;
+    gsV += ab * k3 * sA - kT * (ab * (s + t) * dA + 2.0 * s * bb * dB);
+  }
+  double* o = part + (((size_t)inst * nchunk + chunk) * 4) * ldk;
+  o[j] = gAq;
+  o[ldk + j] = gBq;
+  o[2 * ldk + j] = gsV;
+  o[3 * ldk + j] = gsS;
+}
+
+// Sum the row chunks in a fixed order and push the adjoints of sigma_V,
+// sigma_S through sigma = (A or B)/Delta, Delta = t A^2 + B^2: adjoints of
+// A(t_j), B(t_j) into gq[inst][2][ldk].
+__global__ void k_vjp_nodes(int n_inst, int nq, int ldk, int nchunk, const double* __restrict__ t_,
+                            const double* __restrict__ nodes, const double* __restrict__ part,
+                            double* __restrict__ gq) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int inst = blockIdx.y;
+  if (j >= nq) return;
+  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < nchunk; ++c) {
+    const double* o = part + (((size_t)inst * nchunk + c) * 4) * ldk;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] += o[(size_t)k * ldk + j];
+  }
+  const double* nd = nodes + (size_t)inst * 5 * ldk;
+  const double Aq = nd[j], Bq = nd[ldk + j], sV = nd[2 * ldk + j], sS = nd[3 * ldk + j];
+  const double t = t_[j];
+  const double Dl = t * Aq * Aq + Bq * Bq;
+  const double gD = -(g[2] * sV + g[3] * sS) / Dl;
+  gq[(size_t)inst * 2 * ldk + j] = g[0] + g[2] / Dl + gD * 2.0 * t * Aq;
+  gq[(size_t)inst * 2 * ldk + ldk + j] = g[1] + g[3] / Dl + gD * 2.0 * Bq;
+}
+
+// Transpose of the interpolation: external node l gathers the adjoints of
+// every loop node whose stencil contains it; adds the row part in place.
+__global__ void k_vjp_scatter(int n_inst, int n, int nq, int ldk, const int* __restrict__ lo,
+                              const double* __restrict__ sw, const double* __restrict__ gq,
+                              double* __restrict__ out) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int inst = blockIdx.y;
+  if (l >= n) return;
+  double gA = 0.0, gB = 0.0;
+  const int j0 = l - 4 < 0 ? 0 : l - 4, j1 = l + 4 > nq - 1 ? nq - 1 : l + 4;
+  for (int j = j0; j <= j1; ++j) {
+    const int b = lo[j];
+    if (l >= b && l < b + 4) {
+      const double wl = sw[4 * j + (l - b)];
+      gA += wl * gq[(size_t)inst * 2 * ldk + j];
+      gB += wl * gq[(size_t)inst * 2 * ldk + ldk + j];
+    }
+  }
+  out[(size_t)inst * 2 * n + l] += gA;
+  out[(size_t)inst * 2 * n + n + l] += gB;
+}
+
+// ---------------------------------------------------------------- small vector ops
+// out[inst * nvec + v] = sum_k a[v][inst][k] b[inst][k], one block per
+// (instance, vector), fixed reduction order.
+__global__ void k_batched_dot(int len, const double* __restrict__ a, size_t lda,
+                              const double* __restrict__ b, size_t ldb, int nvec,
+                              double* __restrict__ out) {
+  const int inst = blockIdx.x, v = blockIdx.y;
+  const double* av = a + (size_t)v * lda + (size_t)inst * len;
+  const double* bv = b + (size_t)inst * ldb;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < len; k += blockDim.x) acc = fma(av[k], bv[k], acc);
+  __shared__ double red[256 / WAVE];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sacc = 0.0;
+    for (int k = 0; k < (int)(blockDim.x / WAVE); ++k) sacc += red[k];
+    out[(size_t)inst * nvec + v] = sacc;
+  }
+}
+
+__global__ void k_gs_update(int n_inst, int len, const double* __restrict__ V, size_t ldv, int nvec,
+                            const double* __restrict__ h, int hstride, double* __restrict__ w) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n_inst * len) return;
+  const int inst = (int)(e / len);
+  double acc = w[e];
+  for (int v = 0; v < nvec; ++v) acc -= h[(size_t)inst * hstride + v] * V[(size_t)v * ldv + e];
+  w[e] = acc;
+}
+
+__global__ void k_combine(int n_inst, int len, const double* __restrict__ V, size_t ldv, int nvec,
+                          const double* __restrict__ y, int ystride, double beta,
+                          double* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n_inst * len) return;
+  const int inst = (int)(e / len);
+  double acc = beta == 0.0 ? 0.0 : beta * out[e];
+  for (int v = 0; v < nvec; ++v) acc += y[(size_t)inst * ystride + v] * V[(size_t)v * ldv + e];
+  out[e] = acc;
+}
+
+__global__ void k_axpby(int n_inst, int len, double alpha, const double* __restrict__ a,
+                        const double* __restrict__ scale, const double* __restrict__ b,
+                        double* __restrict__ dst) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n_inst * len) return;
+  const double sc = scale ? scale[e / len] : 1.0;
+  dst[e] = (alpha == 0.0 ? 0.0 : alpha * a[e]) + sc * b[e];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, const double* s,
+                             const double* t, const double* W, const double* z, const double* wz,
+                             double omega, int with_domega, double* K, double* dK) {
+  const long total = (long)n * ldk;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_precompute, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, n, nq,
+                     na, ldk, s, t, W, z, wz, omega, with_domega, K, dK);
+  return hipGetLastError();
+}
+
+hipError_t launch_k_to_f32(hipStream_t st, const double* K, float* K32, size_t count) {
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, K, K32,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state) {
+  hipLaunchKernelGGL(k_solve_init, dim3((n_inst + 255) / 256), dim3(256), 0, st, n_inst, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_fp64(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                             const InstDev* inst, const double* K, size_t kstride, const int* lo,
+                             const double* sw, const double* t, const double* s,
+                             const double* x_in, double* x_out, double* nodes, SolveState* state,
+                             const SolveCtl* ctl, int parity, int add_f0) {
+  hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
+                     sw, t, x_in, nodes, state, ctl, parity);
+  const long rows = (long)n_inst * n;
+  hipLaunchKernelGGL(k_sweep, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n, nq,
+                     ldk, inst, K, kstride, s, nodes, x_in, x_out, state, ctl, parity, add_f0);
+  return hipGetLastError();
+}
+
+hipError_t launch_contraction_only(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                                  const InstDev* inst, const double* K, size_t kstride,
+                                  const double* s, const double* x_in, double* x_out,
+                                  const double* nodes) {
+  const long rows = (long)n_inst * n;
+  hipLaunchKernelGGL(k_sweep, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n, nq,
+                     ldk, inst, K, kstride, s, nodes, x_in, x_out, (SolveState*)nullptr,
+                     (const SolveCtl*)nullptr, 0, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_nodes_only(hipStream_t st, int n_inst, int n, int nq, int ldk, const int* lo,
+                             const double* sw, const double* t, const double* x, double* nodes) {
+  hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
+                     sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_jvp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
+                      const double* K, size_t kstride, const int* lo, const double* sw,
+                      const double* t, const double* s, const double* x, const double* v,
+                      double* jv, double* nodes) {
+  hipLaunchKernelGGL(k_nodes_dual, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk,
+                     lo, sw, t, x, v, nodes);
+  const long rows = (long)n_inst * n;
+  hipLaunchKernelGGL(k_sweep_dual, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n,
+                     nq, ldk, inst, K, kstride, s, nodes, x, v, jv);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
+                      const double* K, size_t kstride, const int* lo, const double* sw,
+                      const double* t, const double* s, const double* x, const double* w,
+                      double* out, double* nodes, double* part, double* gq, int nchunk) {
+  hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
+                     sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 0);
+  const long rows = (long)n_inst * n;
+  hipLaunchKernelGGL(k_vjp_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n, nq,
+                     ldk, inst, K, kstride, s, t, nodes, w, out);
+  hipLaunchKernelGGL(k_vjp_cols, dim3((nq + 63) / 64, nchunk, n_inst), dim3(64), 0, st, n_inst, n,
+                     nq, ldk, nchunk, inst, K, kstride, s, t, nodes, x, w, part);
+  hipLaunchKernelGGL(k_vjp_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n_inst, nq,
+                     ldk, nchunk, t, nodes, part, gq);
+  hipLaunchKernelGGL(k_vjp_scatter, dim3((n + 255) / 256, n_inst), dim3(256), 0, st, n_inst, n, nq,
+                     ldk, lo, sw, gq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_dot(hipStream_t st, int n_inst, int len, const double* a, size_t lda,
+                              const double* b, size_t ldb, int nvec, double* out) {
+  hipLaunchKernelGGL(k_batched_dot, dim3(n_inst, nvec), dim3(256), 0, st, len, a, lda, b, ldb, nvec,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_update(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
+                            int nvec, const double* h, int hstride, double* w) {
+  const long tot = (long)n_inst * len;
+  hipLaunchKernelGGL(k_gs_update, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n_inst, len,
+                     V, ldv, nvec, h, hstride, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
+                          int nvec, const double* y, int ystride, double beta, double* out) {
+  const long tot = (long)n_inst * len;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n_inst, len, V,
+                     ldv, nvec, y, ystride, beta, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(hipStream_t st, int n_inst, int len, double alpha, const double* a,
+                        const double* scale, const double* b, double* dst) {
+  const long tot = (long)n_inst * len;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n_inst, len,
+                     alpha, a, scale, b, dst);
+  return hipGetLastError();
+}
+
+}  // namespace qdse

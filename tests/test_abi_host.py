@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/qdse.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "qdse.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qdse_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2012_03667_amd as Q
+    if not os.path.exists(Q.library_path()):
+        from paper_2012_03667_amd import build
+        build.build()
+    return Q.load()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "qdse_setup" in names and "qdse_solve" in names and "qdse_grad" in names
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_setup_rejects_bad_arguments_before_hip(L):
+    from paper_2012_03667_amd._lib import Grid, Params
+    h = ctypes.c_void_p()
+    p = (Params * 1)(Params(0.55, 0.678, 0.0))
+    good = dict(n_radial=64, n_angle=32, interp_order=3, s_min=1e-4, s_max=1e4)
+    bad = [dict(good, n_radial=3), dict(good, n_angle=0), dict(good, interp_order=2),
+           dict(good, s_min=0.0), dict(good, s_max=1e-5)]
+    for b in bad:
+        g = Grid(**b)
+        assert L.qdse_setup(ctypes.byref(g), p, 1, 0, None, ctypes.byref(h)) == -1, b
+    g = Grid(**good)
+    assert L.qdse_setup(ctypes.byref(g), p, 0, 0, None, ctypes.byref(h)) == -1
+    assert L.qdse_setup(ctypes.byref(g), p, 1, 7, None, ctypes.byref(h)) == -1
+    assert L.qdse_setup(ctypes.byref(g), p, 1, 0, None, None) == -1
+    for badp in (Params(-1.0, 0.5, 0.0), Params(1.0, 0.0, 0.0), Params(1.0, 0.5, float("nan"))):
+        pp = (Params * 1)(badp)
+        assert L.qdse_setup(ctypes.byref(g), pp, 1, 0, None, ctypes.byref(h)) == -1
+
+
+def test_entry_points_reject_null_context(L):
+    assert L.qdse_iterate(None, None, None) == -1
+    assert L.qdse_solve(None, None, ctypes.c_double(1e-10), 10, 0, None, None) == -1
+    assert L.qdse_jvp(None, None, None, None) == -1
+    assert L.qdse_vjp(None, None, None, None) == -1
+    assert L.qdse_grad(None, None, None, ctypes.c_double(1e-10), 10, None) == -1
+    assert L.qdse_dims(None, None, None, None, None) == -1
+    L.qdse_destroy(None)
+
+
+def test_strerror_names_every_code(L):
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert L.qdse_strerror(code) and L.qdse_strerror(code) != b"unknown status code"
+    assert L.qdse_strerror(99) == b"unknown status code"
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2012_03667_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dp, f)).read()
+                assert "oracle" not in src.lower(), f

@@ -1,0 +1,213 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerance (FP64 path): both sides sum the same O(N * M) terms in FP64 with
+different association and algebraically equal, differently rounded angular
+factors, so each output differs by a few thousand ulps of the largest term at
+most; relative to the output that is ~1e-13. The criterion is
+|gpu - oracle| <= 1e-12 * max(|oracle|, 1e-8 * max|oracle|) per array (A, B
+and M = B/A), the floor keeping the chiral-limit B -> 0 tail meaningful.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import qdse_oracle as O  # noqa: E402
+
+RTOL = 1e-12
+KAPPA, OMEGA = 0.8, 0.5
+
+
+def rel_err(gpu, ref):
+    """max |gpu - ref| / max(|ref|, 1e-8 max|ref|)."""
+    den = np.maximum(np.abs(ref), 1e-8 * np.max(np.abs(ref)))
+    return float(np.max(np.abs(gpu - ref) / den))
+
+
+def errs(x_gpu, x_ref, n):
+    A, B = x_gpu[:n], x_gpu[n:]
+    Ar, Br = x_ref[:n], x_ref[n:]
+    return rel_err(A, Ar), rel_err(B, Br), rel_err(B / A, Br / Ar)
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_03667_amd as Q
+    Q.load()
+    return Q
+
+
+def smooth_x(s, rng, wigner=False):
+    A = 1.0 + rng.uniform(0.5, 1.5) / (1 + s / rng.uniform(0.1, 1.0))
+    B = 0.0 * s if wigner else rng.uniform(0.2, 0.6) / (1 + s / rng.uniform(0.1, 1.0)) + 0.005
+    return np.concatenate([A, B])
+
+
+def oracle_grid(n, na, order, s_min=1e-4, s_max=1e4):
+    return O.vac_grid(n, na, s_min=s_min, s_max=s_max, order=order)
+
+
+CASES = [  # (n, na, order, s_min, s_max): several tiles and ragged tails
+    (64, 32, 3, 1e-4, 1e4),
+    (37, 7, 1, 1e-4, 1e4),
+    (150, 100, 1, 1e-4, 1e4),
+    (130, 65, 3, 1e-3, 1e3),
+    (4, 1, 3, 1e-2, 1e2),
+]
+
+
+@pytest.mark.parametrize("n,na,order,smin,smax", CASES)
+def test_one_sweep_matches_oracle(Q, n, na, order, smin, smax):
+    print(f"case sweep n={n} na={na} order={order}", flush=True)
+    rng = np.random.default_rng(n * 1000 + na)
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.0), (1.3, 0.6, 0.1)]
+    S = Q.Solver(n, na, params, interp_order=order, s_min=smin, s_max=smax)
+    g = oracle_grid(n, na, order, smin, smax)
+    assert np.allclose(S.s, g.s, rtol=1e-14) and np.allclose(S.t, g.t, rtol=1e-14)
+    xs = [smooth_x(g.s, rng) for _ in params]
+    x = torch.tensor(np.stack(xs), device="cuda")
+    y = S.iterate(x).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        ref = O.F(g, O.Params(D, om, m), xs[k])
+        eA, eB, eM = errs(y[k], ref, n)
+        assert max(eA, eB, eM) < RTOL, (k, eA, eB, eM)
+
+
+def test_sweep_exact_limits(Q):
+    """Free limit (D = 0) and Wigner solution (m = 0, B = 0) hold exactly on the GPU too."""
+    n = 48
+    S = Q.Solver(n, 16, [(0.0, 0.5, 0.005), (1.024, 0.5, 0.0)])
+    rng = np.random.default_rng(3)
+    x = torch.tensor(np.stack([smooth_x(S.s, rng), smooth_x(S.s, rng, wigner=True)]), device="cuda")
+    y = S.iterate(x).cpu().numpy()
+    assert np.all(y[0, :n] == 1.0) and np.all(y[0, n:] == 0.005)
+    assert np.all(y[1, n:] == 0.0)
+
+
+def test_jvp_matches_oracle_complex_step(Q):
+    n, na = 40, 24
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.0)]
+    S = Q.Solver(n, na, params)
+    g = oracle_grid(n, na, 3)
+    rng = np.random.default_rng(11)
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    vs = rng.normal(size=xs.shape)
+    jv = S.jvp(torch.tensor(xs, device="cuda"), torch.tensor(vs, device="cuda")).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        ref = O.jvp(g, O.Params(D, om, m), xs[k], vs[k])
+        assert np.max(np.abs(jv[k] - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_vjp_is_transpose_of_oracle_jacobian(Q):
+    n, na = 24, 16
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.02)]
+    S = Q.Solver(n, na, params)
+    g = oracle_grid(n, na, 3)
+    rng = np.random.default_rng(12)
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    ws = rng.normal(size=xs.shape)
+    out = S.vjp(torch.tensor(xs, device="cuda"), torch.tensor(ws, device="cuda")).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        J = O.jacobian(g, O.Params(D, om, m), xs[k])
+        ref = J.T @ ws[k]
+        assert np.max(np.abs(out[k] - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_solve_matches_oracle_picard_paper_workload(Q):
+    """Sec. IV Table 1 workload: the GPU stops after the same 11 sweeps with the
+    same iterate, for the 2-point (paper) and 4-point interpolations."""
+    n, na = 150, 100
+    for order in (1, 3):
+        S = Q.Solver(n, na, [(0.55, 0.678, 0.0), (0.55, 0.678, 0.005)], interp_order=order)
+        x = S.initial(1.0, 1.0)
+        rc, it, rs = S.solve(x, tol=0.005, max_iter=100, conv_mode=Q.QDSE_CONV_ABS)
+        assert rc == Q.QDSE_OK
+        g = oracle_grid(n, na, order)
+        for k, m in enumerate((0.0, 0.005)):
+            xr, itr, rr, _ = O.picard(g, O.Params(0.55, 0.678, m), np.ones(2 * n), 0.005, mode=0)
+            assert it[k] == itr
+            assert max(errs(x[k].cpu().numpy(), xr, n)) < RTOL
+        assert it[0] == 11
+
+
+def test_solve_converged_matches_oracle(Q):
+    """Tight convergence (1e-12 on max |dM/M| and |dA|) at the paper's parameters
+    and at N = 64, M = 32 with the config-1 interaction at the bare->BC level the
+    fixed-point iteration still contracts."""
+    n, na = 64, 32
+    params = [(0.55, 0.678, 0.005), (0.55, 0.678, 0.0)]
+    S = Q.Solver(n, na, params)
+    x = S.initial(1.0, 0.3)
+    rc, it, rs = S.solve(x, tol=1e-12, max_iter=500, conv_mode=Q.QDSE_CONV_MASS)
+    assert rc == Q.QDSE_OK, (rc, it, rs)
+    g = oracle_grid(n, na, 3)
+    for k, (D, om, m) in enumerate(params):
+        x0 = np.concatenate([np.ones(n), np.full(n, 0.3)])
+        xr, itr, rr, _ = O.picard(g, O.Params(D, om, m), x0, 1e-12, max_iter=500, mode=1)
+        assert abs(int(it[k]) - itr) <= 1
+        assert max(errs(x[k].cpu().numpy(), xr, n)) < RTOL
+
+
+def test_solve_reports_non_convergence_and_nan(Q):
+    n = 32
+    S = Q.Solver(n, 16, [(0.55, 0.678, 0.005), (0.55, 0.678, 0.005)])
+    x = S.initial(1.0, 1.0)
+    x[1, 3] = float("nan")
+    rc, it, rs = S.solve(x, tol=1e-14, max_iter=3, conv_mode=Q.QDSE_CONV_ABS)
+    assert rc == Q.QDSE_ENAN
+    assert it[0] == 3
+    assert not np.isfinite(rs[1])
+
+
+def test_graph_replay_equals_eager(Q):
+    n = 64
+    params = [(0.55, 0.678, 0.005)] * 3
+    S = Q.Solver(n, 32, params)
+    outs = []
+    for flag in (None, "1", None):
+        if flag:
+            os.environ["QDSE_NO_GRAPH"] = flag
+        else:
+            os.environ.pop("QDSE_NO_GRAPH", None)
+        x = S.initial(1.0, 1.0)
+        rc, it, rs = S.solve(x, tol=1e-11, max_iter=300)
+        torch.cuda.synchronize()
+        outs.append((x.cpu().numpy(), it.copy()))
+    os.environ.pop("QDSE_NO_GRAPH", None)
+    for xo, it in outs[1:]:
+        assert np.array_equal(xo, outs[0][0]) and np.array_equal(it, outs[0][1])
+
+
+def test_full_size_sampled_rows(Q):
+    """512 x 128 (the scaled-up vacuum workload), the launch shape the benchmark
+    times: one sweep compared row by row on a sample of rows, and the converged
+    iterate of the paper's interaction checked to be a fixed point of the
+    oracle's map on sampled rows."""
+    n, na = 512, 128
+    rng = np.random.default_rng(512)
+    rows = np.sort(np.concatenate([[0, 1, 255, 510, 511], rng.choice(n, 11, replace=False)]))
+    g = oracle_grid(n, na, 3)
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (KAPPA ** 3 / OMEGA, OMEGA, 0.0)]
+    S = Q.Solver(n, na, params)
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    y = S.iterate(torch.tensor(xs, device="cuda")).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        a, b = O.F_rows(g, O.Params(D, om, m), xs[k], rows)
+        ref = np.concatenate([a, b])
+        got = np.concatenate([y[k, rows], y[k, n + rows]])
+        assert max(errs(got, ref, len(rows))) < RTOL
+    S2 = Q.Solver(n, na, [(0.55, 0.678, 0.005)])
+    x = S2.initial(1.0, 1.0)
+    rc, it, rs = S2.solve(x, tol=1e-12, max_iter=500)
+    assert rc == Q.QDSE_OK
+    xs = x[0].cpu().numpy()
+    a, b = O.F_rows(g, O.Params(0.55, 0.678, 0.005), xs, rows)
+    # a fixed point of the oracle's map to within the stopping tolerance
+    assert np.max(np.abs(a - xs[rows])) < 1e-11
+    assert np.max(np.abs(b / a - xs[n + rows] / xs[rows]) / np.abs(b / a)) < 1e-11
