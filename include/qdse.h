@@ -74,7 +74,8 @@ enum {
 /* Convergence test of qdse_solve. */
 enum {
   QDSE_CONV_ABS = 0,  /* max_i |A'-A| < tol and max_i |B'-B| < tol (eq. jifenab2) */
-  QDSE_CONV_MASS = 1  /* max_i |M'-M|/|M'| < tol and max_i |A'-A| < tol, M = B/A  */
+  QDSE_CONV_MASS = 1  /* max_i |M'-M|/max(|M'|, 1e-8 GeV) < tol and
+                         max_i |A'-A| < tol, M = B/A                           */
 };
 
 /* Builds the grids, the interpolation stencils and the angular-integrated

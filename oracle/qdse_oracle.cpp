@@ -125,7 +125,7 @@ double dot4(const double* a, const double* b) {
 // paper's "t" vector).
 template <class T>
 void integrand(double s, double t, double z, T Ap, T Bp, T Aq, T Bq, double lam,
-               T* IA, T* IB) {
+               T* IA, T* IB, double* k2_out = nullptr) {
   const double p[4] = {0.0, 0.0, 0.0, std::sqrt(s)};
   const double sn = std::sqrt(1.0 - z * z);
   const double q[4] = {0.0, 0.0, std::sqrt(t) * sn, std::sqrt(t) * z};
@@ -135,6 +135,7 @@ void integrand(double s, double t, double z, T Ap, T Bp, T Aq, T Bq, double lam,
     P[c] = p[c] + q[c];
   }
   const double k2 = dot4(k, k), pq = dot4(p, q);
+  if (k2_out) *k2_out = k2;
   const double pP = dot4(p, P), qP = dot4(q, P), PP = dot4(P, P);
   const double kp = dot4(k, p), kq = dot4(k, q), kP = dot4(k, P);
 
@@ -171,10 +172,10 @@ void row_sums(const qo_vac_grid* g, const qo_vac_par* par, T Ai, T Bi,
     const double Wj = g->wq[j] * t * t;  // dt t = du t^2
     for (int a = 0; a < g->na; ++a) {
       const double z = g->z[a];
-      const double k2 = s + t - 2.0 * std::sqrt(s * t) * z;
-      const double gk = gnorm * std::exp(-k2 / om2);
       T IA, IB;
-      integrand(s, t, z, Ai, Bi, Aq[j], Bq[j], par->lam, &IA, &IB);
+      double k2;  // squared gluon momentum k = p - q, from the four-vectors
+      integrand(s, t, z, Ai, Bi, Aq[j], Bq[j], par->lam, &IA, &IB, &k2);
+      const double gk = gnorm * std::exp(-k2 / om2);
       const double w = Wj * g->wz[a] * std::sqrt(1.0 - z * z) * gk;
       accA += w * IA / Dq;
       accB += w * IB / Dq;

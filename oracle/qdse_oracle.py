@@ -239,15 +239,21 @@ def integrand(s, t, z, Ap, Bp, Aq, Bq, lam=1.0):
 # Drivers
 # --------------------------------------------------------------------------
 
+M_FLOOR = 1e-8  # GeV
+
+
 def converged(x_old, x_new, n, tol, mode):
     """Convergence test. mode 0: the paper's per-point absolute test on A and B
-    (Sec. II eq. jifenab2). mode 1: max |dM/M| < tol and max |dA| < tol."""
+    (Sec. II eq. jifenab2). mode 1: max |dM|/max(|M|, M_FLOOR) < tol and
+    max |dA| < tol, M = B/A; the floor (1e-8 GeV) keeps the test finite where
+    the chiral-limit mass function vanishes."""
     Ao, Bo, An, Bn = x_old[:n], x_old[n:], x_new[:n], x_new[n:]
     if mode == 0:
         r = max(np.max(np.abs(An - Ao)), np.max(np.abs(Bn - Bo)))
     else:
         Mo, Mn = Bo / Ao, Bn / An
-        r = max(np.max(np.abs(Mn - Mo) / np.abs(Mn)), np.max(np.abs(An - Ao)))
+        r = max(np.max(np.abs(Mn - Mo) / np.maximum(np.abs(Mn), M_FLOOR)),
+                np.max(np.abs(An - Ao)))
     return r < tol, r
 
 

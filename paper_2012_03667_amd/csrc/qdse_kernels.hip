@@ -38,6 +38,8 @@ namespace qdse {
 namespace {
 
 constexpr int WAVE = 64;
+// Floor (GeV) of the relative mass-function test, where M = B/A vanishes.
+constexpr double kMassFloor = 1e-8;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -287,7 +289,7 @@ __device__ inline double test_stat(int mode, double An, double Bn, double Ao, do
   const double dA = fabs(An - Ao);
   if (mode == QDSE_CONV_ABS) return fmax(dA, fabs(Bn - Bo));
   const double Mn = Bn / An, Mo = Bo / Ao;
-  return fmax(dA, fabs(Mn - Mo) / fabs(Mn));
+  return fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloor));
 }
 
 __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ldk,
