@@ -99,6 +99,14 @@ int qdse_dims(const qdse_ctx* ctx, int* n_radial, int* n_loop, int* n_angle, int
  * pointer may be NULL. */
 int qdse_nodes(const qdse_ctx* ctx, double* s, double* t);
 
+/* Host-only (no HIP call): the grid a context with `grid` would use. Any
+ * pointer may be NULL. s[N], u[N]: external p^2 and ln p^2; t[N+1], W[N+1]:
+ * loop q^2 and the radial weight (Gauss-Legendre weight in ln q^2 times t^2);
+ * z[M], wz[M]: angular nodes and w_a sqrt(1 - z_a^2). Gauss-Legendre nodes and
+ * weights are correctly rounded to FP64. Errors: QDSE_EINVAL. */
+int qdse_grid_nodes(const qdse_grid* grid, double* s, double* u, double* t, double* W,
+                    double* z, double* wz);
+
 /* One sweep x_out = F(x_in) of the successive approximation (Sec. I eq.
  * jifen12) for every instance, in FP64. d_x_in, d_x_out: [n_inst][2N] device,
  * distinct buffers. Asynchronous. */

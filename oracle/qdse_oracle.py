@@ -23,11 +23,14 @@ nodes are the N-point Gauss-Legendre nodes in u, loop nodes the (N+1)-point ones
 on the same interval, so that the two sets interlace strictly (zeros of
 consecutive Legendre polynomials interlace), which is the ordering of eq.
 pqrelationship; angular nodes are M-point Gauss-Legendre nodes in z = cos(theta).
-Gauss-Legendre nodes come from ``numpy.polynomial.legendre.leggauss``.
+Gauss-Legendre nodes come from ``numpy.polynomial.legendre.leggauss``, polished
+to correct FP64 rounding in extended precision (mpmath).
 """
 from __future__ import annotations
 
 import ctypes
+import functools
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -116,21 +119,65 @@ class VacGrid:
         return g
 
 
+EXACT_NODES_MAX = 1100
+
+
+@functools.lru_cache(maxsize=None)
+def gauss_legendre(n: int):
+    """n-point Gauss-Legendre nodes (ascending) and weights on [-1, 1],
+    correctly rounded to FP64: numpy's nodes (accurate to ~2 ulp) polished by
+    Newton's method on the Legendre three-term recurrence in 34-digit mpmath
+    arithmetic. Above EXACT_NODES_MAX points numpy's nodes are used as they are.
+    Correct rounding matters because the discrete map at large p^2 is
+    sensitive to single-ulp moves of the angular nodes (exp(-k^2/omega^2) with
+    k^2 ~ 2|p||q|(1 - z))."""
+    x0, w0 = np.polynomial.legendre.leggauss(n)
+    if n > EXACT_NODES_MAX or n < 2:
+        return x0, w0
+    import mpmath
+    ctx = mpmath.mp.clone() if hasattr(mpmath.mp, "clone") else mpmath.mp
+    ctx.dps = 34
+
+    def legendre_and_derivative(r):
+        p0, p1 = ctx.mpf(1), r
+        for ell in range(2, n + 1):
+            p0, p1 = p1, ((2 * ell - 1) * r * p1 - (ell - 1) * p0) / ell
+        return p1, n * (r * p1 - p0) / (r * r - 1)
+
+    x, w = np.empty(n), np.empty(n)
+    for k in range(n // 2):  # negative roots; the rule is symmetric
+        r = ctx.mpf(float(x0[k]))
+        for _ in range(2):
+            p, dp = legendre_and_derivative(r)
+            r = r - p / dp
+        p, dp = legendre_and_derivative(r)
+        x[k], x[n - 1 - k] = float(r), -float(r)
+        w[k] = w[n - 1 - k] = float(2 / ((1 - r * r) * dp * dp))
+    if n % 2:
+        _, dp = legendre_and_derivative(ctx.mpf(0))
+        x[n // 2] = 0.0
+        w[n // 2] = float(2 / (dp * dp))
+    return x, w
+
+
 def gl_interval(n: int, a: float, b: float):
     """n-point Gauss-Legendre nodes and weights mapped to [a, b]."""
-    x, w = np.polynomial.legendre.leggauss(n)
-    return a + (b - a) * (x + 1.0) / 2.0, w * (b - a) / 2.0
+    x, w = gauss_legendre(n)
+    half = 0.5 * (b - a)
+    return a + half * (x + 1.0), half * w
 
 
 def vac_grid(n: int, na: int, s_min: float = 1e-4, s_max: float = 1e4,
              order: int = 3, nq: int | None = None) -> VacGrid:
     """External grid GL(n) in u = ln s, loop grid GL(n+1) in u on the same
     interval (interleaved), angular grid GL(na) in z."""
-    a, b = np.log(s_min), np.log(s_max)
+    a, b = math.log(s_min), math.log(s_max)
     u, _ = gl_interval(n, a, b)
     uq, wq = gl_interval(n + 1 if nq is None else nq, a, b)
-    z, wz = np.polynomial.legendre.leggauss(na)
-    return VacGrid(n, na, order, np.exp(u), u, np.exp(uq), uq, wq, z, wz)
+    z, wz = gauss_legendre(na)
+    s = np.array([math.exp(v) for v in u])
+    t = np.array([math.exp(v) for v in uq])
+    return VacGrid(n, na, order, s, u, t, uq, wq, z.copy(), wz.copy())
 
 
 @dataclass

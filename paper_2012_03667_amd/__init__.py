@@ -6,7 +6,7 @@ this package only marshals arguments: PyTorch supplies device memory and the
 stream. If the library is missing every entry point raises.
 """
 from ._lib import (QDSE_CONV_ABS, QDSE_CONV_MASS, QDSE_ENAN, QDSE_FP32_REFINE, QDSE_FP64,
-                   QDSE_NOT_CONVERGED, QDSE_OK, QdseError, Solver, library_path, load)
+                   QDSE_NOT_CONVERGED, QDSE_OK, QdseError, Solver, grid_nodes, library_path, load)
 
-__all__ = ["Solver", "QdseError", "load", "library_path", "QDSE_OK", "QDSE_NOT_CONVERGED",
+__all__ = ["Solver", "QdseError", "grid_nodes", "load", "library_path", "QDSE_OK", "QDSE_NOT_CONVERGED",
            "QDSE_ENAN", "QDSE_FP64", "QDSE_FP32_REFINE", "QDSE_CONV_ABS", "QDSE_CONV_MASS"]

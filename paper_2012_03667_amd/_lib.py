@@ -53,6 +53,7 @@ def load():
     L.qdse_destroy.restype = None
     L.qdse_dims.argtypes = [_vp, _ip, _ip, _ip, _ip]
     L.qdse_nodes.argtypes = [_vp, _dp, _dp]
+    L.qdse_grid_nodes.argtypes = [ctypes.POINTER(Grid)] + [_dp] * 6
     L.qdse_iterate.argtypes = [_vp, _vp, _vp]
     L.qdse_iterate_fp32.argtypes = [_vp, _vp, _vp]
     L.qdse_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp]
@@ -95,6 +96,16 @@ def _dev(t, shape, name):
             and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
         raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def grid_nodes(n_radial, n_angle, interp_order=3, s_min=1e-4, s_max=1e4):
+    """Host-only: the grid arrays (s, u, t, W, z, wz) a context would use."""
+    g = Grid(int(n_radial), int(n_angle), int(interp_order), float(s_min), float(s_max))
+    out = [np.empty(n) for n in (n_radial, n_radial, n_radial + 1, n_radial + 1, n_angle,
+                                 n_angle)]
+    _check(load().qdse_grid_nodes(ctypes.byref(g), *[a.ctypes.data_as(_dp) for a in out]),
+           "qdse_grid_nodes")
+    return dict(zip(("s", "u", "t", "W", "z", "wz"), out))
 
 
 class Solver:

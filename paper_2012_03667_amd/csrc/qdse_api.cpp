@@ -75,6 +75,11 @@ struct qdse_ctx {
   // graph of a chunk of masked sweeps
   hipGraphExec_t graph_exec = nullptr;
   int graph_chunk = 0;
+  // persistent solve: per-sweep statistics, grid-barrier counter, flags
+  unsigned long long* d_slots = nullptr;
+  unsigned int* d_barrier = nullptr;
+  int* d_flags = nullptr;
+  int persist_G = 0, persist_rpw = 0;  // 0: not usable for this context
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
   int nchunk = 16;
@@ -191,6 +196,9 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   TRY(dalloc(&c->d_xbuf[1], xlen(c)));
   TRY(dalloc(&c->d_state, (size_t)n_inst));
   TRY(dalloc(&c->d_ctl, 1));
+  TRY(dalloc(&c->d_slots, (size_t)3 * n_inst));
+  TRY(dalloc(&c->d_barrier, 1));
+  TRY(dalloc(&c->d_flags, 2));
   for (int b = 0; b < c->n_blocks; ++b) {
     hipError_t e = launch_precompute(st, g.n, g.nq, g.na, g.ldk, c->d_s, c->d_t, c->d_W, c->d_z,
                                      c->d_wz, c->block_omega[b], 0, c->d_K + b * c->kstride,
@@ -211,6 +219,24 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
     }
   }
 #undef TRY
+  // Persistent single-launch solve: every instance must share kernel block 0
+  // and all workgroups must be co-resident. Rows per workgroup: the smallest
+  // count whose grid fits (or QDSE_PERSIST_RPW).
+  if (c->n_blocks == 1 && n_inst <= 64) {
+    int rpw0 = 2, rpw1 = 8;
+    if (const char* e = std::getenv("QDSE_PERSIST_RPW")) rpw0 = rpw1 = std::atoi(e);
+    for (int rpw = rpw0; rpw <= rpw1 && c->persist_G == 0; ++rpw) {
+      if (rpw < 1) break;
+      int maxb = 0;
+      if (persistent_max_blocks(rpw, g.nq, &maxb) != hipSuccess) break;
+      const int G = (g.n + rpw - 1) / rpw;
+      if (G <= maxb) {
+        c->persist_G = G;
+        c->persist_rpw = rpw;
+      }
+    }
+    (void)hipGetLastError();
+  }
   if (hipStreamSynchronize(st) != hipSuccess) {
     g_last_error = "setup synchronisation failed";
     qdse_destroy(c);
@@ -224,11 +250,32 @@ void qdse_destroy(qdse_ctx* c) {
   if (!c) return;
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  void* ptrs[] = {c->d_s,     c->d_t,     c->d_W,       c->d_z,       c->d_wz,    c->d_sw,
-                  c->d_lo,    c->d_K,     c->d_dK,      c->d_K32,     c->d_inst,  c->d_nodes,
-                  c->d_xbuf[0], c->d_xbuf[1], c->d_state, c->d_ctl, c->d_part, c->d_gq};
+  void* ptrs[] = {c->d_s,       c->d_t,       c->d_W,       c->d_z,     c->d_wz,
+                  c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_K32,
+                  c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
+                  c->d_ctl,     c->d_part,    c->d_gq,      c->d_slots, c->d_barrier,
+                  c->d_flags};
   for (void* p : ptrs) dfree(p);
   delete c;
+}
+
+int qdse_grid_nodes(const qdse_grid* grid, double* s, double* u, double* t, double* W, double* z,
+                    double* wz) {
+  if (!grid) return QDSE_EINVAL;
+  qdse_params p{1.0, 1.0, 0.0};
+  if (validate(grid, &p, 1)) return QDSE_EINVAL;
+  HostGrid hg;
+  if (build_grid(*grid, &hg)) return QDSE_EINVAL;
+  auto put = [](double* dst, const std::vector<double>& v) {
+    if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+  };
+  put(s, hg.s);
+  put(u, hg.u);
+  put(t, hg.t);
+  put(W, hg.W);
+  put(z, hg.z);
+  put(wz, hg.wz);
+  return QDSE_OK;
 }
 
 int qdse_dims(const qdse_ctx* c, int* n_radial, int* n_loop, int* n_angle, int* n_inst) {
@@ -273,6 +320,44 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk) {
   return QDSE_OK;
 }
 
+static int finish_solve(qdse_ctx* c, const std::vector<SolveState>& hs, bool all_done, int* iters,
+                        double* resid) {
+  int rc = QDSE_OK;
+  for (int k = 0; k < c->n_inst; ++k) {
+    const SolveState& s = hs[k];
+    if (iters) iters[k] = s.sweeps;
+    if (resid) resid[k] = s.resid;
+    if (s.status == 3) rc = QDSE_ENAN;
+    else if ((s.status == 2 || s.status == 0) && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
+  }
+  if (!all_done && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
+  return rc;
+}
+
+// One cooperative launch runs the whole solve (qdse_persistent.hip); the
+// iterate ends in xbuf[flags[1]].
+static int solve_persistent(qdse_ctx* c, double* d_x, int* iters, double* resid) {
+  const HostGrid& g = c->hg;
+  hipStream_t st = c->stream;
+  HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_lo, c->d_sw,
+                           c->d_t, c->d_s, c->d_xbuf[0], c->d_xbuf[1], c->d_state, c->d_ctl,
+                           c->d_slots, c->d_barrier, c->d_flags, c->persist_G, c->persist_rpw));
+  std::vector<SolveState> hs(c->n_inst);
+  int flags[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(hs.data(), c->d_state, hs.size() * sizeof(SolveState),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(flags, c->d_flags, sizeof(flags), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (flags[0] != 0) {
+    g_last_error = "persistent solve: grid barrier timed out";
+    return QDSE_EDEVICE;
+  }
+  HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[flags[1] & 1], xlen(c) * sizeof(double),
+                        hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return finish_solve(c, hs, true, iters, resid);
+}
+
 int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode, int* iters,
                double* resid) {
   if (!c || !d_x || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
@@ -284,6 +369,8 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
   HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
   HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
   HIPCHK(hipMemcpyAsync(c->d_xbuf[0], d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (c->persist_G > 0 && std::getenv("QDSE_NO_PERSISTENT") == nullptr)
+    return solve_persistent(c, d_x, iters, resid);
   if (use_graph && (!c->graph_exec || c->graph_chunk != chunk)) {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     if (c->graph_exec) {
@@ -323,16 +410,7 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
   }
   HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[0], xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
-  int rc = QDSE_OK;
-  for (int k = 0; k < c->n_inst; ++k) {
-    const SolveState& s = hs[k];
-    if (iters) iters[k] = s.sweeps;
-    if (resid) resid[k] = s.resid;
-    if (s.status == 3) rc = QDSE_ENAN;
-    else if ((s.status == 2 || s.status == 0) && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
-  }
-  if (!all_done && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
-  return rc;
+  return finish_solve(c, hs, all_done, iters, resid);
 }
 
 int qdse_jvp(qdse_ctx* c, const double* d_x, const double* d_v, double* d_jv) {

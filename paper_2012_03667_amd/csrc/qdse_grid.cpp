@@ -13,17 +13,81 @@
 
 #include <cmath>
 
+// The grid must round exactly as written (no fused multiply-add contraction):
+// u = a + half (x + 1), W = half w t^2.
+#pragma clang fp contract(off)
+
 namespace qdse {
 
+// Double-double arithmetic (value = hi + lo, |lo| <= ulp(hi)/2), used to
+// polish the Gauss-Legendre rule to correct FP64 rounding.
+struct dd {
+  double hi, lo;
+};
+static inline dd two_sum(double a, double b) {
+  const double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+static inline dd quick_two_sum(double a, double b) {
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+static inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+static inline dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+static inline dd dd_mul(dd a, dd b) {
+  const double p = a.hi * b.hi;
+  const double e = std::fma(a.hi, b.hi, -p) + (a.hi * b.lo + a.lo * b.hi);
+  return quick_two_sum(p, e);
+}
+static inline dd dd_mul_d(dd a, double b) { return dd_mul(a, dd{b, 0.0}); }
+static inline dd dd_div(dd a, dd b) {
+  const double q1 = a.hi / b.hi;
+  dd r = dd_add(a, dd_neg(dd_mul_d(b, q1)));
+  const double q2 = r.hi / b.hi;
+  r = dd_add(r, dd_neg(dd_mul_d(b, q2)));
+  const double q3 = r.hi / b.hi;
+  return dd_add(quick_two_sum(q1, q2), dd{q3, 0.0});
+}
+
+// P_n(r) and P_n'(r) by the three-term recurrence in double-double.
+static void legendre_dd(int n, dd r, dd* p, dd* dp) {
+  dd p0{1.0, 0.0}, p1 = r;
+  for (int l = 2; l <= n; ++l) {
+    const dd a = dd_mul_d(dd_mul(r, p1), 2.0 * l - 1.0);
+    const dd b = dd_mul_d(p0, l - 1.0);
+    const dd p2 = dd_div(dd_add(a, dd_neg(b)), dd{(double)l, 0.0});
+    p0 = p1;
+    p1 = p2;
+  }
+  *p = p1;
+  // P_n' = n (r P_n - P_{n-1}) / (r^2 - 1)
+  const dd num = dd_mul_d(dd_add(dd_mul(r, p1), dd_neg(p0)), (double)n);
+  *dp = dd_div(num, dd_add(dd_mul(r, r), dd{-1.0, 0.0}));
+}
+
 // Nodes x[k] (ascending) and weights w[k] of the n-point Gauss-Legendre rule
-// on [-1, 1]: Newton's method on P_n, evaluated by the three-term recurrence,
-// started from the asymptotic (Tricomi) estimate of the k-th zero.
+// on [-1, 1], correctly rounded to FP64: Newton's method on P_n in FP64 from
+// the asymptotic (Tricomi) estimate of each zero, then two Newton steps and
+// the weight 2 / ((1 - x^2) P_n'(x)^2) in double-double arithmetic. Correct
+// rounding matters: at large p^2 the quadrature sums react to single-ulp moves
+// of the angular nodes through exp(-k^2/omega^2), k^2 ~ 2|p||q|(1 - z).
 void gauss_legendre(int n, double* x, double* w) {
   const double pi = 3.14159265358979323846;
+  if (n == 1) {
+    x[0] = 0.0;
+    w[0] = 2.0;
+    return;
+  }
   for (int k = 0; k < (n + 1) / 2; ++k) {
     const double th = pi * (k + 0.75) / (n + 0.5);
     double r = std::cos(th) * (1.0 - (n - 1.0) / (8.0 * n * n * n));
-    double dp = 1.0;
     for (int it = 0; it < 100; ++it) {
       double p0 = 1.0, p1 = r;
       for (int l = 2; l <= n; ++l) {
@@ -31,29 +95,23 @@ void gauss_legendre(int n, double* x, double* w) {
         p0 = p1;
         p1 = p2;
       }
-      if (n == 1) {
-        p1 = r;
-        p0 = 1.0;
-      }
-      dp = n * (r * p1 - p0) / (r * r - 1.0);  // P_n'(r)
-      const double dr = p1 / dp;
+      const double dr = p1 / (n * (r * p1 - p0) / (r * r - 1.0));
       r -= dr;
-      if (std::fabs(dr) < 1e-16) {
-        // one more recurrence for the derivative at the converged root
-        double q0 = 1.0, q1 = r;
-        for (int l = 2; l <= n; ++l) {
-          const double q2 = ((2.0 * l - 1.0) * r * q1 - (l - 1.0) * q0) / l;
-          q0 = q1;
-          q1 = q2;
-        }
-        dp = (n == 1) ? 1.0 : n * (r * q1 - q0) / (r * r - 1.0);
-        break;
-      }
+      if (std::fabs(dr) < 1e-15) break;
     }
-    const double wk = 2.0 / ((1.0 - r * r) * dp * dp);
-    x[n - 1 - k] = r;   // largest roots first in k
-    x[k] = -r;
-    w[k] = w[n - 1 - k] = wk;
+    dd rr{r, 0.0}, p, dp;
+    for (int it = 0; it < 2; ++it) {
+      legendre_dd(n, rr, &p, &dp);
+      rr = dd_add(rr, dd_neg(dd_div(p, dp)));
+    }
+    legendre_dd(n, rr, &p, &dp);
+    const dd one_m_r2 = dd_add(dd{1.0, 0.0}, dd_neg(dd_mul(rr, rr)));
+    const dd wk = dd_div(dd{2.0, 0.0}, dd_mul(one_m_r2, dd_mul(dp, dp)));
+    const double root = rr.hi + rr.lo;  // round to FP64
+    const double wt = wk.hi + wk.lo;
+    x[n - 1 - k] = root;  // largest roots first in k
+    x[k] = -root;
+    w[k] = w[n - 1 - k] = wt;
   }
   if (n % 2 == 1) x[n / 2] = 0.0;
 }

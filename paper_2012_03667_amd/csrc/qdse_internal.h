@@ -91,4 +91,14 @@ hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, 
 hipError_t launch_axpby(hipStream_t st, int n_inst, int len, double alpha, const double* a,
                         const double* scale, const double* b, double* dst);
 
+// Persistent (cooperative) solve of a few instances sharing kernel block 0.
+size_t persistent_lds_bytes(int rpw, int nq);
+hipError_t persistent_max_blocks(int rpw, int nq, int* max_blocks);
+hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                             const InstDev* inst, const double* K, const int* lo,
+                             const double* sw, const double* t, const double* s, double* xbuf0,
+                             double* xbuf1, SolveState* state, const SolveCtl* ctl,
+                             unsigned long long* slots, unsigned int* barrier, int* flags, int G,
+                             int rpw);
+
 }  // namespace qdse

@@ -1,0 +1,323 @@
+// qdse_persistent.hip -- the whole successive-approximation solve of a few
+// instances in one cooperative launch (Sec. I eq. jifen12 with the per-point
+// test of Sec. II eq. jifenab2 or its mass-function form).
+//
+// A few-instance solve at N = 512 does ~7 MFLOP per sweep: launch latency,
+// not arithmetic or bandwidth, bounds a kernel-per-sweep driver. Here each of
+// G workgroups (all co-resident: cooperative launch) owns the external rows
+// i = g, g + G, ... for every instance, keeps the three kernel-matrix rows of
+// those i in LDS for the whole solve, and per sweep
+//   1. decides from the previous sweep's global test statistics which
+//      instances are frozen (all workgroups decide identically),
+//   2. rebuilds the loop-node functions of each running instance in LDS from
+//      the current iterate (redundantly per workgroup: O(N) work),
+//   3. contracts its rows against them (FP64 direct-difference form, the same
+//      arithmetic as k_sweep) and writes the new iterate rows,
+//   4. folds its rows' test statistics into a per-instance global maximum,
+//   5. meets the other workgroups at a grid barrier.
+// The barrier wait is bounded: a workgroup that waits too long raises an error
+// flag and every workgroup leaves the loop, so the grid always drains.
+#include "qdse_internal.h"
+
+namespace qdse {
+
+namespace {
+
+constexpr int PBLOCK = 256;
+constexpr int PWAVES = PBLOCK / 64;
+constexpr int MAX_RPW = 8;           // rows per workgroup held in LDS
+constexpr long SPIN_LIMIT = 1l << 24;  // ~0.5 s of polling before giving up
+constexpr double kMassFloorP = 1e-8;   // GeV, as in the kernel-per-sweep path
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline double stat_p(int mode, double An, double Bn, double Ao, double Bo) {
+  const double dA = fabs(An - Ao);
+  if (mode == QDSE_CONV_ABS) return fmax(dA, fabs(Bn - Bo));
+  const double Mn = Bn / An, Mo = Bo / Ao;
+  return fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloorP));
+}
+
+__device__ inline unsigned long long stat_bits(double r) {
+  if (isnan(r)) return 0x7ff8000000000000ull;
+  return (unsigned long long)__double_as_longlong(r);
+}
+
+// Grid-wide barrier number k (1-based) on a monotonically increasing counter.
+// Returns false if the wait timed out or another workgroup raised the flag.
+__device__ bool grid_sync(unsigned int* ctr, unsigned int target, int* err) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        break;
+      }
+      if (++spins > SPIN_LIMIT) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+struct PArgs {
+  int n_inst, n, nq, rpw, G;
+  const InstDev* inst;
+  const double* K;  // kernel block shared by every instance
+  int ldk;
+  const int* lo;
+  const double* sw;
+  const double* t;
+  const double* s;
+  double* xbuf0;
+  double* xbuf1;
+  SolveState* state;
+  const SolveCtl* ctl;
+  unsigned long long* slots;  // [3][n_inst] bits of the per-sweep maxima
+  unsigned int* barrier;
+  int* flags;  // [0] error, [1] buffer index of the final iterate
+};
+
+__global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
+  extern __shared__ double lds[];
+  const int n = a.n, nq = a.nq, rpw = a.rpw, G = a.G, g = blockIdx.x;
+  double* Kl = lds;                        // [rpw][3][nq]
+  double* nd = Kl + (size_t)rpw * 3 * nq;  // [4][nq] node functions of one instance
+  __shared__ int st_status[64];
+  __shared__ int st_sweeps[64];
+  __shared__ double st_resid[64];
+  __shared__ double red[PWAVES][MAX_RPW][4];
+  __shared__ unsigned long long wgmax;
+  __shared__ int all_frozen;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SolveCtl ctl = *a.ctl;
+
+  // rows of this workgroup: i = g + r * G
+  int nrows = 0;
+  for (int r = 0; r < rpw; ++r)
+    if (g + r * G < n) nrows = r + 1;
+  for (int r = 0; r < nrows; ++r) {
+    const int i = g + r * G;
+    for (int c = 0; c < 3; ++c)
+      for (int j = tid; j < nq; j += PBLOCK)
+        Kl[((size_t)r * 3 + c) * nq + j] = a.K[(size_t)c * n * a.ldk + (size_t)i * a.ldk + j];
+  }
+  for (int q = tid; q < a.n_inst; q += PBLOCK) {
+    st_status[q] = 0;
+    st_sweeps[q] = 0;
+    st_resid[q] = __longlong_as_double(0x7ff0000000000000ll);
+  }
+  __syncthreads();
+
+  int k = 1;
+  bool fine = true;
+  for (;; ++k) {
+    const double* xc = (k & 1) ? a.xbuf0 : a.xbuf1;  // sweep k reads buf[(k-1)%2]
+    double* xn = (k & 1) ? a.xbuf1 : a.xbuf0;
+    // 1. decisions from the statistics of sweep k-1
+    if (tid == 0) all_frozen = 1;
+    __syncthreads();
+    for (int q = tid; q < a.n_inst; q += PBLOCK) {
+      int stq = st_status[q];
+      if (stq == 0) {
+        if (st_sweeps[q] > 0) {
+          const double prev = __longlong_as_double(
+              (long long)a.slots[(size_t)((k - 1) % 3) * a.n_inst + q]);
+          if (!(prev <= 1.7976931348623157e308)) stq = 3;
+          else if (prev < ctl.tol) stq = 1;
+          if (stq) st_resid[q] = prev;
+        }
+        if (stq == 0 && st_sweeps[q] >= ctl.max_iter) {
+          stq = 2;
+          st_resid[q] = __longlong_as_double(
+              (long long)a.slots[(size_t)((k - 1) % 3) * a.n_inst + q]);
+        }
+        st_status[q] = stq;
+      }
+      if (stq == 0) all_frozen = 0;
+      if (g == 0) a.slots[(size_t)((k + 1) % 3) * a.n_inst + q] = 0ull;
+    }
+    __syncthreads();
+    if (all_frozen) break;
+
+    for (int q = 0; q < a.n_inst; ++q) {
+      const double* xq = xc + (size_t)q * 2 * n;
+      double* xo = xn + (size_t)q * 2 * n;
+      if (st_status[q] != 0) {  // frozen: carry the iterate forward
+        for (int r = tid; r < nrows; r += PBLOCK) {
+          const int i = g + r * G;
+          xo[i] = xq[i];
+          xo[n + i] = xq[n + i];
+        }
+        continue;
+      }
+      // 2. node functions of instance q into LDS
+      for (int j = tid; j < nq; j += PBLOCK) {
+        const int b = a.lo[j];
+        const double* w = a.sw + 4 * j;
+        double Aq = 0.0, Bq = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          Aq = fma(w[l], xq[b + l], Aq);
+          Bq = fma(w[l], xq[n + b + l], Bq);
+        }
+        const double tj = a.t[j];
+        const double Dl = tj * Aq * Aq + Bq * Bq;
+        nd[j] = Aq;
+        nd[nq + j] = Bq;
+        nd[2 * nq + j] = Aq / Dl;
+        nd[3 * nq + j] = Bq / Dl;
+      }
+      if (tid == 0) wgmax = 0ull;
+      __syncthreads();
+      // 3. contraction of this workgroup's rows
+      const InstDev P = a.inst[q];
+      double acc[MAX_RPW][4];
+      double Ai[MAX_RPW], Bi[MAX_RPW], si[MAX_RPW];
+#pragma unroll
+      for (int r = 0; r < MAX_RPW; ++r) {
+        acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+        if (r < nrows) {
+          const int i = g + r * G;
+          Ai[r] = xq[i];
+          Bi[r] = xq[n + i];
+          si[r] = a.s[i];
+        }
+      }
+      for (int j = tid; j < nq; j += PBLOCK) {
+        const double Aq = nd[j], Bq = nd[nq + j], sV = nd[2 * nq + j], sS = nd[3 * nq + j];
+        const double tsV = a.t[j] * sV;
+#pragma unroll
+        for (int r = 0; r < MAX_RPW; ++r) {
+          if (r < nrows) {
+            const double* Kr = Kl + (size_t)r * 3 * nq;
+            const double kT = Kr[j], k3 = Kr[nq + j], k0 = Kr[2 * nq + j];
+            const double dA = Aq - Ai[r], dB = Bq - Bi[r], sA = Aq + Ai[r];
+            const double e = fma(2.0 * sS, dB, fma(si[r], sV, tsV) * dA);
+            acc[r][0] = fma(kT, e, acc[r][0]);
+            acc[r][1] = fma(k3, sV * sA, acc[r][1]);
+            acc[r][2] = fma(kT, fma(sS, dA, -(sV * dB)), acc[r][2]);
+            acc[r][3] = fma(k0, sS * sA, acc[r][3]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MAX_RPW; ++r) {
+        if (r < nrows) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double v = wsum(acc[r][c]);
+            if (lane == 0) red[wave][r][c] = v;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < nrows) {
+        const int r = tid, i = g + r * G;
+        double c4[4];
+        for (int c = 0; c < 4; ++c) {
+          double v = 0.0;
+          for (int w = 0; w < PWAVES; ++w) v += red[w][r][c];
+          c4[c] = v;
+        }
+        const double An = 1.0 + P.pref * (c4[1] - c4[0]);
+        const double Bn = P.m + P.pref * fma(2.0 * si[r], c4[2], c4[3]);
+        xo[i] = An;
+        xo[n + i] = Bn;
+        atomicMax(&wgmax, stat_bits(stat_p(ctl.mode, An, Bn, Ai[r], Bi[r])));
+      }
+      __syncthreads();
+      // 4. this workgroup's contribution to the instance's test statistic
+      if (tid == 0) {
+        atomicMax(&a.slots[(size_t)(k % 3) * a.n_inst + q], wgmax);
+        st_sweeps[q] += 1;
+      }
+      __syncthreads();
+    }
+    // 5. grid barrier k
+    if (!grid_sync(a.barrier, (unsigned int)(G * k), a.flags)) {
+      fine = false;
+      break;
+    }
+  }
+  if (g == 0) {
+    for (int q = tid; q < a.n_inst; q += PBLOCK) {
+      a.state[q].status = fine ? st_status[q] : 3;
+      a.state[q].sweeps = st_sweeps[q];
+      a.state[q].resid = st_resid[q];
+    }
+    if (tid == 0) a.flags[1] = (k - 1) & 1;  // the last completed sweep wrote buf[(k-1)%2]
+  }
+}
+
+__global__ void k_persistent_reset(unsigned long long* slots, int nslots, unsigned int* barrier,
+                                   int* flags) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nslots) slots[t] = 0ull;
+  if (t == 0) {
+    *barrier = 0u;
+    flags[0] = 0;
+    flags[1] = 0;
+  }
+}
+
+}  // namespace
+
+size_t persistent_lds_bytes(int rpw, int nq) {
+  return ((size_t)rpw * 3 * nq + (size_t)4 * nq) * sizeof(double);
+}
+
+// Launches the persistent solve; G workgroups, each holding rpw rows. The
+// caller has checked that every instance uses kernel block 0, that G
+// workgroups of this size are co-resident, and that n_inst <= 64.
+hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                             const InstDev* inst, const double* K, const int* lo,
+                             const double* sw, const double* t, const double* s, double* xbuf0,
+                             double* xbuf1, SolveState* state, const SolveCtl* ctl,
+                             unsigned long long* slots, unsigned int* barrier, int* flags, int G,
+                             int rpw) {
+  if (rpw > MAX_RPW || n_inst > 64 || (long)G * rpw < n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_persistent_reset, dim3((3 * n_inst + 255) / 256), dim3(256), 0, st, slots,
+                     3 * n_inst, barrier, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  PArgs a{n_inst, n, nq, rpw, G, inst, K, ldk, lo, sw, t, s, xbuf0, xbuf1, state, ctl, slots,
+          barrier, flags};
+  const size_t lds = persistent_lds_bytes(rpw, nq);
+  e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(G), dim3(PBLOCK), args, lds, st);
+}
+
+hipError_t persistent_max_blocks(int rpw, int nq, int* max_blocks) {
+  int dev = 0, ncu = 0, occ = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const size_t lds = persistent_lds_bytes(rpw, nq);
+  e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_persistent, PBLOCK, lds);
+  if (e != hipSuccess) return e;
+  *max_blocks = occ * ncu;
+  return hipSuccess;
+}
+
+}  // namespace qdse

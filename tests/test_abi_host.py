@@ -73,3 +73,22 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 src = open(os.path.join(dp, f)).read()
                 assert "oracle" not in src.lower(), f
+
+
+@pytest.mark.parametrize("n,na,smin,smax", [(64, 32, 1e-4, 1e4), (512, 128, 1e-4, 1e4),
+                                            (37, 7, 1e-3, 1e3), (4, 1, 1e-2, 1e2)])
+def test_library_grid_is_the_oracle_grid(L, n, na, smin, smax):
+    """Both sides build the same discretisation independently (double-double
+    Newton in C++ vs mpmath-polished numpy nodes); correctly rounded nodes and
+    weights make them agree bit for bit, so parity is not limited by
+    single-ulp node differences."""
+    import numpy as np
+    import paper_2012_03667_amd as Q
+    from oracle import qdse_oracle as O
+    h = Q.grid_nodes(n, na, 3, smin, smax)
+    g = O.vac_grid(n, na, s_min=smin, s_max=smax)
+    assert np.array_equal(h["s"], g.s) and np.array_equal(h["u"], g.u)
+    assert np.array_equal(h["t"], g.t)
+    assert np.array_equal(h["W"], g.wq * g.t * g.t)
+    assert np.array_equal(h["z"], g.z)
+    assert np.allclose(h["wz"], g.wz * np.sqrt(1 - g.z ** 2), rtol=1e-12, atol=0)

@@ -69,7 +69,7 @@ def test_one_sweep_matches_oracle(Q, n, na, order, smin, smax):
     params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.0), (1.3, 0.6, 0.1)]
     S = Q.Solver(n, na, params, interp_order=order, s_min=smin, s_max=smax)
     g = oracle_grid(n, na, order, smin, smax)
-    assert np.allclose(S.s, g.s, rtol=1e-14) and np.allclose(S.t, g.t, rtol=1e-14)
+    assert np.array_equal(S.s, g.s) and np.array_equal(S.t, g.t)
     xs = [smooth_x(g.s, rng) for _ in params]
     x = torch.tensor(np.stack(xs), device="cuda")
     y = S.iterate(x).cpu().numpy()
@@ -166,22 +166,63 @@ def test_solve_reports_non_convergence_and_nan(Q):
 
 
 def test_graph_replay_equals_eager(Q):
+    """The kernel-per-sweep driver: graph replays (several, with eager work and
+    synchronisations between them) equal eager launches bit for bit."""
     n = 64
-    params = [(0.55, 0.678, 0.005)] * 3
+    params = [(0.55, 0.678, 0.005), (0.55, 0.678, 0.0), (0.55, 0.678, 0.1)]
     S = Q.Solver(n, 32, params)
     outs = []
-    for flag in (None, "1", None):
-        if flag:
-            os.environ["QDSE_NO_GRAPH"] = flag
-        else:
-            os.environ.pop("QDSE_NO_GRAPH", None)
-        x = S.initial(1.0, 1.0)
-        rc, it, rs = S.solve(x, tol=1e-11, max_iter=300)
-        torch.cuda.synchronize()
-        outs.append((x.cpu().numpy(), it.copy()))
-    os.environ.pop("QDSE_NO_GRAPH", None)
+    os.environ["QDSE_NO_PERSISTENT"] = "1"
+    try:
+        for flag in (None, "1", None, None):
+            if flag:
+                os.environ["QDSE_NO_GRAPH"] = flag
+            else:
+                os.environ.pop("QDSE_NO_GRAPH", None)
+            x = S.initial(1.0, 1.0)
+            rc, it, rs = S.solve(x, tol=1e-11, max_iter=300)
+            torch.cuda.synchronize()
+            outs.append((x.cpu().numpy(), it.copy()))
+    finally:
+        os.environ.pop("QDSE_NO_GRAPH", None)
+        os.environ.pop("QDSE_NO_PERSISTENT", None)
     for xo, it in outs[1:]:
         assert np.array_equal(xo, outs[0][0]) and np.array_equal(it, outs[0][1])
+
+
+@pytest.mark.parametrize("n,na,order", [(512, 128, 3), (64, 32, 3), (150, 100, 1), (37, 9, 3)])
+def test_persistent_solve_matches_graph_driver(Q, n, na, order):
+    """The single-launch cooperative solve and the kernel-per-sweep driver stop
+    at the same sweep with the same iterate (summation order differs, so
+    agreement is to rounding)."""
+    print(f"case persistent n={n} na={na}", flush=True)
+    params = [(0.55, 0.678, 0.0), (0.55, 0.678, 0.005)]
+    S = Q.Solver(n, na, params, interp_order=order)
+    res = []
+    for flag in (None, "1"):
+        if flag:
+            os.environ["QDSE_NO_PERSISTENT"] = flag
+        else:
+            os.environ.pop("QDSE_NO_PERSISTENT", None)
+        try:
+            x = S.initial(1.0, 1.0)
+            rc, it, rs = S.solve(x, tol=1e-10, max_iter=400)
+        finally:
+            os.environ.pop("QDSE_NO_PERSISTENT", None)
+        assert rc == Q.QDSE_OK, (flag, rc, it, rs)
+        res.append((x.cpu().numpy(), it.copy(), rs.copy()))
+    (xp, ip, rp), (xg, ig, rg) = res
+    assert np.all(np.abs(ip - ig) <= 1), (ip, ig)
+    if np.array_equal(ip, ig):
+        for k in range(len(params)):
+            assert max(errs(xp[k], xg[k], n)) < 1e-13
+    g = oracle_grid(n, na, order)
+    if n <= 150:
+        for k, (D, om, m) in enumerate(params):
+            xr, itr, _, _ = O.picard(g, O.Params(D, om, m), np.ones(2 * n), 1e-10, max_iter=400, mode=1)
+            assert abs(int(ip[k]) - itr) <= 1
+            if ip[k] == itr:
+                assert max(errs(xp[k], xr, n)) < RTOL
 
 
 def test_full_size_sampled_rows(Q):
