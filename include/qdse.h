@@ -61,7 +61,7 @@ enum {
   QDSE_ENOMEM = -2,   /* device or host allocation failed                    */
   QDSE_EDEVICE = -3,  /* a HIP call failed (message via qdse_last_error)     */
   QDSE_ENAN = -4,     /* an iterate became NaN or infinite                   */
-  QDSE_ENOTSUP = -5   /* option not available for this context             */
+  QDSE_ENOTSUP = -5   /* option not available for this context              */
 };
 
 /* Arithmetic of the contraction over loop nodes, the only O(N^2) step. */
@@ -81,7 +81,9 @@ enum {
 /* Builds the grids, the interpolation stencils and the angular-integrated
  * kernel matrices for n_inst instances that share `grid` and have their own
  * `params[inst]` (instances with equal omega share one set of matrices).
- * precision: QDSE_FP64 or QDSE_FP32_REFINE (the latter also keeps FP32 copies).
+ * precision: QDSE_FP64 or QDSE_FP32_REFINE (the latter also builds the FP32
+ * matrices of the matrix-core sweep and needs one common omega: QDSE_ENOTSUP
+ * otherwise).
  * hip_stream: a hipStream_t (NULL = the null stream). On success *out owns all
  * device memory of the context until qdse_destroy.
  * Errors: QDSE_EINVAL (grid or params out of range, n_inst < 1, out == NULL),
@@ -127,6 +129,12 @@ int qdse_iterate_fp32(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
  * Synchronises the stream. */
 int qdse_solve(qdse_ctx* ctx, double* d_x, double tol, int max_iter, int conv_mode,
                int* iters, double* resid);
+
+/* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may
+ * be NULL): FP32 matrix-core sweeps (QDSE_FP32_REFINE contexts) and FP64
+ * sweeps. The FP32 phase stops at max(tol, 1e-6) on the same test; the FP64
+ * phase then runs to tol. */
+int qdse_solve_stats(const qdse_ctx* ctx, int* sweeps_fp32, int* sweeps_fp64);
 
 /* Jacobian-vector product d_jv = (dF/dx)(d_x) d_v for every instance (FP64,
  * forward mode through interpolation, node functions and contraction).

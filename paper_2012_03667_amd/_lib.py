@@ -57,6 +57,7 @@ def load():
     L.qdse_iterate.argtypes = [_vp, _vp, _vp]
     L.qdse_iterate_fp32.argtypes = [_vp, _vp, _vp]
     L.qdse_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp]
+    L.qdse_solve_stats.argtypes = [_vp, _ip, _ip]
     L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_vjp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _dp]
@@ -174,6 +175,14 @@ class Solver:
                                int(conv_mode), it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
         _check(rc, "qdse_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
         return rc, it, rs
+
+    def solve_stats(self):
+        """(FP32 sweeps, FP64 sweeps) per instance of the last solve."""
+        a = np.zeros(self.n_inst, dtype=np.int32)
+        b = np.zeros(self.n_inst, dtype=np.int32)
+        _check(load().qdse_solve_stats(self._h, a.ctypes.data_as(_ip), b.ctypes.data_as(_ip)),
+               "qdse_solve_stats")
+        return a, b
 
     def jvp(self, x, v, out=None):
         import torch

@@ -66,7 +66,12 @@ struct qdse_ctx {
   int* d_lo = nullptr;
   double* d_K = nullptr;
   double* d_dK = nullptr;  // omega derivatives, built on first gradient request
-  float* d_K32 = nullptr;
+  float* d_M32 = nullptr;  // FP32 MFMA path: [5][nq4][ldi]
+  float* d_C32 = nullptr;  // FP32 node columns: [6][nq4][ldb]
+  int nq4 = 0, ldi = 0, ldb = 0;
+  size_t mstride32 = 0, cstride32 = 0;
+  hipGraphExec_t graph32_exec = nullptr;
+  std::vector<int> last_sweeps32, last_sweeps64;
   InstDev* d_inst = nullptr;
   double* d_nodes = nullptr;  // [n_inst][10][ldk]
   double* d_xbuf[2] = {nullptr, nullptr};
@@ -210,10 +215,24 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
     }
   }
   if (precision == QDSE_FP32_REFINE) {
-    TRY(dalloc(&c->d_K32, c->kstride * c->n_blocks));
-    hipError_t e = launch_k_to_f32(st, c->d_K, c->d_K32, c->kstride * c->n_blocks);
+    if (c->n_blocks != 1) {  // the matrix-core path needs one shared matrix set
+      qdse_destroy(c);
+      return QDSE_ENOTSUP;
+    }
+    c->nq4 = (g.nq + 3) & ~3;
+    c->ldi = (g.n + 31) & ~31;
+    c->ldb = (n_inst + 63) & ~63;
+    c->mstride32 = (size_t)c->nq4 * c->ldi;
+    c->cstride32 = (size_t)c->nq4 * c->ldb;
+    TRY(dalloc(&c->d_M32, 5 * c->mstride32));
+    TRY(dalloc(&c->d_C32, 6 * c->cstride32));
+    hipError_t e = hipMemsetAsync(c->d_M32, 0, 5 * c->mstride32 * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_C32, 0, 6 * c->cstride32 * sizeof(float), st);
+    if (e == hipSuccess)
+      e = launch_build_m32(st, g.n, g.nq, g.ldk, c->ldi, c->d_K, c->d_s, c->d_t, c->d_M32,
+                           c->mstride32);
     if (e != hipSuccess) {
-      g_last_error = std::string("k_to_f32: ") + hipGetErrorString(e);
+      g_last_error = std::string("fp32 setup: ") + hipGetErrorString(e);
       qdse_destroy(c);
       return QDSE_EDEVICE;
     }
@@ -249,12 +268,13 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
 void qdse_destroy(qdse_ctx* c) {
   if (!c) return;
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph32_exec) (void)hipGraphExecDestroy(c->graph32_exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void* ptrs[] = {c->d_s,       c->d_t,       c->d_W,       c->d_z,     c->d_wz,
-                  c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_K32,
+                  c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_M32,
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
                   c->d_ctl,     c->d_part,    c->d_gq,      c->d_slots, c->d_barrier,
-                  c->d_flags};
+                  c->d_flags,   c->d_C32};
   for (void* p : ptrs) dfree(p);
   delete c;
 }
@@ -305,17 +325,73 @@ int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
 
 int qdse_iterate_fp32(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
   if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
-  if (!c->d_K32) return QDSE_ENOTSUP;
-  return QDSE_ENOTSUP;
+  if (!c->d_M32) return QDSE_ENOTSUP;
+  const HostGrid& g = c->hg;
+  HIPCHK(launch_sweep_fp32(c->stream, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32,
+                           c->mstride32, c->d_C32, c->cstride32, c->d_inst, c->d_lo, c->d_sw,
+                           c->d_t, c->d_s, d_x_in, d_x_out, nullptr, nullptr, 0));
+  return QDSE_OK;
 }
 
-static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk) {
+static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, bool fp32) {
   const HostGrid& g = c->hg;
   for (int k = 1; k <= chunk; ++k) {
     const int p = k & 1;  // sweep k reads xbuf[(k-1)%2] and writes xbuf[k%2]
-    HIPCHK(launch_sweep_fp64(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                             c->d_lo, c->d_sw, c->d_t, c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p],
-                             c->d_nodes, c->d_state, c->d_ctl, p, 1));
+    if (fp32) {
+      HIPCHK(launch_sweep_fp32(st, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32, c->mstride32,
+                               c->d_C32, c->cstride32, c->d_inst, c->d_lo, c->d_sw, c->d_t,
+                               c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p], c->d_state, c->d_ctl, p));
+    } else {
+      HIPCHK(launch_sweep_fp64(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                               c->d_lo, c->d_sw, c->d_t, c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p],
+                               c->d_nodes, c->d_state, c->d_ctl, p, 1));
+    }
+  }
+  return QDSE_OK;
+}
+
+// Masked sweeps from xbuf[0] until every instance is frozen; the iterate ends
+// in xbuf[0]. hs receives the final per-instance state.
+static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, bool fp32,
+                      std::vector<SolveState>& hs, bool* all_done) {
+  const int chunk = 16;  // even: a chunk ends with the iterate in xbuf[0]
+  const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
+  hipStream_t st = c->stream;
+  SolveCtl ctl{tol, conv_mode, max_iter};
+  HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
+  hipGraphExec_t& exec = fp32 ? c->graph32_exec : c->graph_exec;
+  if (use_graph && !exec) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = record_chunk(c, c->cap_stream, chunk, fp32);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc) return rc;
+    HIPCHK(e);
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+  }
+  hs.assign(c->n_inst, SolveState{});
+  long launched = 0;
+  const long limit = (long)max_iter + 1 + chunk;
+  *all_done = false;
+  while (launched < limit) {
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(exec, st));
+    } else {
+      int rc = record_chunk(c, st, chunk, fp32);
+      if (rc) return rc;
+    }
+    launched += chunk;
+    HIPCHK(hipMemcpyAsync(hs.data(), c->d_state, hs.size() * sizeof(SolveState),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *all_done = true;
+    for (const SolveState& s : hs)
+      if (s.status == 0) *all_done = false;
+    if (*all_done) break;
   }
   return QDSE_OK;
 }
@@ -362,55 +438,54 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
                double* resid) {
   if (!c || !d_x || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
   if (conv_mode != QDSE_CONV_ABS && conv_mode != QDSE_CONV_MASS) return QDSE_EINVAL;
-  const int chunk = 16;  // even: a chunk ends with the iterate in xbuf[0]
-  const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
   hipStream_t st = c->stream;
-  SolveCtl ctl{tol, conv_mode, max_iter};
-  HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
-  HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
+  c->last_sweeps32.assign(c->n_inst, 0);
+  c->last_sweeps64.assign(c->n_inst, 0);
   HIPCHK(hipMemcpyAsync(c->d_xbuf[0], d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (c->persist_G > 0 && std::getenv("QDSE_NO_PERSISTENT") == nullptr)
-    return solve_persistent(c, d_x, iters, resid);
-  if (use_graph && (!c->graph_exec || c->graph_chunk != chunk)) {
-    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    if (c->graph_exec) {
-      (void)hipGraphExecDestroy(c->graph_exec);
-      c->graph_exec = nullptr;
-    }
-    hipGraph_t graph;
-    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = record_chunk(c, c->cap_stream, chunk);
-    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
-    if (rc) return rc;
-    HIPCHK(e);
-    e = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    HIPCHK(e);
-    c->graph_chunk = chunk;
-  }
-  std::vector<SolveState> hs(c->n_inst);
-  long launched = 0;
-  const long limit = (long)max_iter + 1 + chunk;
+  std::vector<SolveState> hs;
   bool all_done = false;
-  while (launched < limit) {
-    if (use_graph) {
-      HIPCHK(hipGraphLaunch(c->graph_exec, st));
-    } else {
-      int rc = record_chunk(c, st, chunk);
-      if (rc) return rc;
+  if (c->precision == QDSE_FP32_REFINE) {
+    // FP32 matrix-core sweeps down to the switch tolerance, then FP64 sweeps
+    double tol32 = 1e-6;
+    if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
+    if (tol32 < tol) tol32 = tol;
+    int rc = run_masked(c, tol32, max_iter, conv_mode, true, hs, &all_done);
+    if (rc) return rc;
+    for (int k = 0; k < c->n_inst; ++k) c->last_sweeps32[k] = hs[k].sweeps;
+  } else {
+    SolveCtl ctl{tol, conv_mode, max_iter};
+    HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
+    if (c->persist_G > 0 && std::getenv("QDSE_NO_PERSISTENT") == nullptr) {
+      int rc = solve_persistent(c, d_x, iters, resid);
+      if (rc >= 0 && c->n_inst > 0) {
+        // sweeps are reported through iters; keep the breakdown too
+        std::vector<SolveState> h2(c->n_inst);
+        (void)hipMemcpy(h2.data(), c->d_state, h2.size() * sizeof(SolveState),
+                        hipMemcpyDeviceToHost);
+        for (int k = 0; k < c->n_inst; ++k) c->last_sweeps64[k] = h2[k].sweeps;
+      }
+      return rc;
     }
-    launched += chunk;
-    HIPCHK(hipMemcpyAsync(hs.data(), c->d_state, hs.size() * sizeof(SolveState),
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    all_done = true;
-    for (const SolveState& s : hs)
-      if (s.status == 0) all_done = false;
-    if (all_done) break;
+  }
+  int rc = run_masked(c, tol, max_iter, conv_mode, false, hs, &all_done);
+  if (rc) return rc;
+  for (int k = 0; k < c->n_inst; ++k) {
+    c->last_sweeps64[k] = hs[k].sweeps;
+    hs[k].sweeps += c->last_sweeps32[k];
   }
   HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[0], xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   return finish_solve(c, hs, all_done, iters, resid);
+}
+
+int qdse_solve_stats(const qdse_ctx* c, int* sweeps_fp32, int* sweeps_fp64) {
+  if (!c) return QDSE_EINVAL;
+  for (int k = 0; k < c->n_inst; ++k) {
+    if (sweeps_fp32) sweeps_fp32[k] = k < (int)c->last_sweeps32.size() ? c->last_sweeps32[k] : 0;
+    if (sweeps_fp64) sweeps_fp64[k] = k < (int)c->last_sweeps64.size() ? c->last_sweeps64[k] : 0;
+  }
+  return QDSE_OK;
 }
 
 int qdse_jvp(qdse_ctx* c, const double* d_x, const double* d_v, double* d_jv) {

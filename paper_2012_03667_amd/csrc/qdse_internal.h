@@ -55,7 +55,6 @@ constexpr int NKER = 3;
 hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, const double* s,
                              const double* t, const double* W, const double* z, const double* wz,
                              double omega, int with_domega, double* K, double* dK);
-hipError_t launch_k_to_f32(hipStream_t st, const double* K, float* K32, size_t count);
 hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state);
 // One FP64 sweep: node functions, then the contraction and update. With
 // state != nullptr the run is masked (frozen instances carry their iterate).
@@ -90,6 +89,16 @@ hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, 
 // dst[inst][:] = alpha * a[inst][:] + scale[inst] * b[inst][:] (scale may be null: 1)
 hipError_t launch_axpby(hipStream_t st, int n_inst, int len, double alpha, const double* a,
                         const double* scale, const double* b, double* dst);
+
+// FP32 MFMA sweep (qdse_mfma.hip): five transposed FP32 matrices per kernel
+// block and six FP32 node columns per instance.
+hipError_t launch_build_m32(hipStream_t st, int n, int nq, int ldk, int ldi, const double* K,
+                            const double* s, const double* t, float* MT, size_t mstride);
+hipError_t launch_sweep_fp32(hipStream_t st, int n_inst, int n, int nq, int ldi, int ldb,
+                             const float* MT, size_t mstride, float* C, size_t cstride,
+                             const InstDev* inst, const int* lo, const double* sw, const double* t,
+                             const double* s, const double* x_in, double* x_out,
+                             SolveState* state, const SolveCtl* ctl, int parity);
 
 // Persistent (cooperative) solve of a few instances sharing kernel block 0.
 size_t persistent_lds_bytes(int rpw, int nq);

@@ -131,11 +131,6 @@ __global__ void k_precompute(int n, int nq, int na, int ldk, const double* __res
   }
 }
 
-__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t cnt) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) b[i] = (float)a[i];
-}
-
 // ---------------------------------------------------------------- masked runs
 __device__ inline double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
@@ -558,12 +553,6 @@ hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, con
   const int bs = 256;
   hipLaunchKernelGGL(k_precompute, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, n, nq,
                      na, ldk, s, t, W, z, wz, omega, with_domega, K, dK);
-  return hipGetLastError();
-}
-
-hipError_t launch_k_to_f32(hipStream_t st, const double* K, float* K32, size_t count) {
-  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, K, K32,
-                     count);
   return hipGetLastError();
 }
 

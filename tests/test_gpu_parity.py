@@ -252,3 +252,55 @@ def test_full_size_sampled_rows(Q):
     # a fixed point of the oracle's map to within the stopping tolerance
     assert np.max(np.abs(a - xs[rows])) < 1e-11
     assert np.max(np.abs(b / a - xs[n + rows] / xs[rows]) / np.abs(b / a)) < 1e-11
+
+
+# ---------------------------------------------------------------- FP32 matrix-core path
+def test_fp32_sweep_close_to_oracle(Q):
+    """One FP32 sweep (split form on the matrix cores, FP32 accumulation) against
+    the FP64 oracle. FP32 rounding (6e-8) of O(N) accumulated terms, amplified by
+    the cancellation of the split differences near the singular diagonal, bounds
+    the error; the FP64 refinement removes it."""
+    for n, na, nb in ((64, 32, 3), (512, 128, 70)):
+        print(f"case fp32 sweep n={n} nb={nb}", flush=True)
+        rng = np.random.default_rng(7 + n)
+        ms = rng.uniform(0, 0.2, nb)
+        params = [(0.55, 0.678, float(m)) for m in ms]
+        S = Q.Solver(n, na, params, precision=Q.QDSE_FP32_REFINE)
+        g = oracle_grid(n, na, 3)
+        xs = np.stack([smooth_x(g.s, rng) for _ in params])
+        y = S.iterate(torch.tensor(xs, device="cuda"), fp32=True).cpu().numpy()
+        y64 = S.iterate(torch.tensor(xs, device="cuda")).cpu().numpy()
+        worst = 0.0
+        check = range(nb) if n <= 64 else (0, nb // 2, nb - 1)
+        for k in check:
+            if n <= 64:
+                ref = O.F(g, O.Params(*params[k]), xs[k])
+            else:
+                ref = y64[k]  # FP64 sweep, itself pinned to the oracle above
+            worst = max(worst, max(errs(y[k], ref, n)))
+        print("fp32 sweep worst rel err", worst, flush=True)
+        assert worst < 1e-4, worst
+
+
+def test_fp32_refined_solve_meets_1e7(Q):
+    """Batched FP32 sweeps to 1e-6, FP64 sweeps to 1e-9 on max|dM/M|, |dA|: the
+    result is within 1e-7 (relative, A, B, M) of the oracle's fixed point
+    converged to 1e-13."""
+    n, na, nb = 64, 32, 40
+    rng = np.random.default_rng(41)
+    ms = rng.uniform(0, 0.2, nb)
+    params = [(0.55, 0.678, float(m)) for m in ms]
+    S = Q.Solver(n, na, params, precision=Q.QDSE_FP32_REFINE)
+    x = S.initial(1.0, 1.0)
+    rc, it, rs = S.solve(x, tol=1e-9, max_iter=600)
+    assert rc == Q.QDSE_OK, (rc, it, rs)
+    n32, n64 = S.solve_stats()
+    assert np.all(n32 > 0) and np.all(n64 > 0)
+    g = oracle_grid(n, na, 3)
+    xg = x.cpu().numpy()
+    worst = 0.0
+    for k in (0, 7, 19, nb - 1):
+        xr, itr, rr, _ = O.picard(g, O.Params(*params[k]), np.ones(2 * n), 1e-13, max_iter=600, mode=1)
+        worst = max(worst, max(errs(xg[k], xr, n)))
+    print("fp32+refine worst rel err vs oracle fixed point", worst, "sweeps", n32[:4], n64[:4], flush=True)
+    assert worst < 1e-7, worst
