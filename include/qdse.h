@@ -167,10 +167,10 @@ int qdse_grad(qdse_ctx* ctx, const double* d_xstar, const double* d_g, double to
  * after the transverse-projector algebra (see the kernel source). */
 int qdse_kernel_matrices(qdse_ctx* ctx, int inst, double* d_K);
 
-/* Diagnostics: average device duration in milliseconds of the contraction
- * kernel of one FP64 sweep (the O(N^2) step) at d_x, over `reps` launches on
- * the context's stream, each bracketed by its own pair of HIP events. d_out
- * [n_inst][2N] receives F(d_x). Synchronises the stream. */
+/* Diagnostics: average device duration in milliseconds of the kernel of one
+ * FP64 sweep (node functions and the O(N^2) contraction, one launch) at d_x,
+ * over `reps` launches on the context's stream, each bracketed by its own pair
+ * of HIP events. d_out [n_inst][2N] receives F(d_x). Synchronises the stream. */
 int qdse_time_contraction(qdse_ctx* ctx, const double* d_x, double* d_out, int reps,
                           double* avg_ms);
 

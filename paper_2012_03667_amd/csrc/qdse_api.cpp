@@ -84,7 +84,7 @@ struct qdse_ctx {
   unsigned long long* d_slots = nullptr;
   unsigned int* d_barrier = nullptr;
   int* d_flags = nullptr;
-  int persist_G = 0, persist_rpw = 0;  // 0: not usable for this context
+  int persist_G = 0, persist_rpw = 0, persist_gsz = 1;  // G = 0: not usable
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
   int nchunk = 16;
@@ -242,16 +242,24 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   // and all workgroups must be co-resident. Rows per workgroup: the smallest
   // count whose grid fits (or QDSE_PERSIST_RPW).
   if (c->n_blocks == 1 && n_inst <= 64) {
-    int rpw0 = 2, rpw1 = 8;
+    int rpw0 = 4, rpw1 = 8;
     if (const char* e = std::getenv("QDSE_PERSIST_RPW")) rpw0 = rpw1 = std::atoi(e);
+    int dev_lds = 65536;
+    (void)hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     for (int rpw = rpw0; rpw <= rpw1 && c->persist_G == 0; ++rpw) {
       if (rpw < 1) break;
+      // node functions of as many instances as fit next to the matrix rows
+      const long left = (long)dev_lds - 4096 - (long)rpw * 3 * g.nq * 8;
+      int gsz = (int)(left / ((long)4 * g.nq * 8));
+      if (gsz < 1) continue;
+      if (gsz > n_inst) gsz = n_inst;
       int maxb = 0;
-      if (persistent_max_blocks(rpw, g.nq, &maxb) != hipSuccess) break;
+      if (persistent_max_blocks(rpw, g.nq, gsz, &maxb) != hipSuccess) break;
       const int G = (g.n + rpw - 1) / rpw;
       if (G <= maxb) {
         c->persist_G = G;
         c->persist_rpw = rpw;
+        c->persist_gsz = gsz;
       }
     }
     (void)hipGetLastError();
@@ -317,9 +325,9 @@ int qdse_nodes(const qdse_ctx* c, double* s, double* t) {
 int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
   if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
   const HostGrid& g = c->hg;
-  HIPCHK(launch_sweep_fp64(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                           c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out, c->d_nodes, nullptr,
-                           nullptr, 0, 1));
+  HIPCHK(launch_sweep_fused(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                            c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out, nullptr, nullptr, 1,
+                            1));
   return QDSE_OK;
 }
 
@@ -340,11 +348,11 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, bool fp32) {
     if (fp32) {
       HIPCHK(launch_sweep_fp32(st, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32, c->mstride32,
                                c->d_C32, c->cstride32, c->d_inst, c->d_lo, c->d_sw, c->d_t,
-                               c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p], c->d_state, c->d_ctl, p));
+                               c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p], c->d_state, c->d_ctl, k));
     } else {
-      HIPCHK(launch_sweep_fp64(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                               c->d_lo, c->d_sw, c->d_t, c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p],
-                               c->d_nodes, c->d_state, c->d_ctl, p, 1));
+      HIPCHK(launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                                c->d_lo, c->d_sw, c->d_t, c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p],
+                                c->d_state, c->d_ctl, k, 1));
     }
   }
   return QDSE_OK;
@@ -354,7 +362,7 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, bool fp32) {
 // in xbuf[0]. hs receives the final per-instance state.
 static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, bool fp32,
                       std::vector<SolveState>& hs, bool* all_done) {
-  const int chunk = 16;  // even: a chunk ends with the iterate in xbuf[0]
+  const int chunk = 12;  // multiple of 6: ends in xbuf[0] with the slot cycle intact
   const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
   hipStream_t st = c->stream;
   SolveCtl ctl{tol, conv_mode, max_iter};
@@ -417,7 +425,8 @@ static int solve_persistent(qdse_ctx* c, double* d_x, int* iters, double* resid)
   hipStream_t st = c->stream;
   HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_lo, c->d_sw,
                            c->d_t, c->d_s, c->d_xbuf[0], c->d_xbuf[1], c->d_state, c->d_ctl,
-                           c->d_slots, c->d_barrier, c->d_flags, c->persist_G, c->persist_rpw));
+                           c->d_slots, c->d_barrier, c->d_flags, c->persist_G, c->persist_rpw,
+                           c->persist_gsz, std::getenv("QDSE_PERSIST_PLAIN") ? 0 : 1));
   std::vector<SolveState> hs(c->n_inst);
   int flags[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(hs.data(), c->d_state, hs.size() * sizeof(SolveState),
@@ -669,10 +678,10 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
   }
   // theta_bar = lambda^T dF/dtheta
   HIPCHK(launch_sweep_fp64(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
-                           c->d_sw, c->d_t, c->d_s, d_xstar, d_y1, c->d_nodes, nullptr, nullptr, 0,
+                           c->d_sw, c->d_t, c->d_s, d_xstar, d_y1, c->d_nodes, nullptr, nullptr, 1,
                            0));  // F - f0
   HIPCHK(launch_sweep_fp64(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_dK, c->kstride, c->d_lo,
-                           c->d_sw, c->d_t, c->d_s, d_xstar, d_y2, c->d_nodes, nullptr, nullptr, 0,
+                           c->d_sw, c->d_t, c->d_s, d_xstar, d_y2, c->d_nodes, nullptr, nullptr, 1,
                            0));  // pref * S(dK/domega)
   {
     std::vector<double> eB(L, 0.0);
@@ -712,15 +721,14 @@ int qdse_time_contraction(qdse_ctx* c, const double* d_x, double* d_out, int rep
   if (!c || !d_x || !d_out || d_x == d_out || reps < 1 || !avg_ms) return QDSE_EINVAL;
   const HostGrid& g = c->hg;
   hipStream_t st = c->stream;
-  HIPCHK(launch_nodes_only(st, c->n_inst, g.n, g.nq, g.ldk, c->d_lo, c->d_sw, c->d_t, d_x,
-                           c->d_nodes));
   std::vector<hipEvent_t> ev(2 * reps, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = QDSE_OK;
   for (int r = 0; r < reps && rc == QDSE_OK; ++r) {
     if (hipEventRecord(ev[2 * r], st) != hipSuccess ||
-        launch_contraction_only(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                                c->d_s, d_x, d_out, c->d_nodes) != hipSuccess ||
+        launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
+                           c->d_sw, c->d_t, c->d_s, d_x, d_out, nullptr, nullptr, 1,
+                           1) != hipSuccess ||
         hipEventRecord(ev[2 * r + 1], st) != hipSuccess)
       rc = QDSE_EDEVICE;
   }

@@ -45,7 +45,8 @@ struct SolveState {
   int status;                   // 0 running, 1 converged, 2 max_iter, 3 non-finite
   int sweeps;                   // sweeps done while running
   double resid;                 // test statistic of the deciding sweep
-  unsigned long long metric[2]; // bits of the non-negative max over rows, per parity
+  unsigned long long metric[3]; // bits of the non-negative max over rows; sweep k uses
+                                // slot k%3, reads slot (k-1)%3, clears slot (k+1)%3
 };
 
 // Matrices per kernel block: K_T, K_3, K_0 (see qdse_kernels.hip).
@@ -56,14 +57,22 @@ hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, con
                              const double* t, const double* W, const double* z, const double* wz,
                              double omega, int with_domega, double* K, double* dK);
 hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state);
-// One FP64 sweep: node functions, then the contraction and update. With
-// state != nullptr the run is masked (frozen instances carry their iterate).
-// add_f0 = 0 drops the inhomogeneous terms (1, m) from the output.
+// One FP64 sweep: node functions, then the contraction and update (two
+// kernels). With state != nullptr the run is masked (frozen instances carry
+// their iterate); k is the 1-based sweep index inside a chunk (a multiple of 6
+// sweeps). add_f0 = 0 drops the inhomogeneous terms (1, m) from the output.
 hipError_t launch_sweep_fp64(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const InstDev* inst, const double* K, size_t kstride, const int* lo,
                              const double* sw, const double* t, const double* s,
                              const double* x_in, double* x_out, double* nodes, SolveState* state,
-                             const SolveCtl* ctl, int parity, int add_f0);
+                             const SolveCtl* ctl, int k, int add_f0);
+// The same sweep as one kernel: each workgroup rebuilds the node functions of
+// its instance in LDS and contracts 16 rows (bitwise the same arithmetic).
+hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                              const InstDev* inst, const double* K, size_t kstride, const int* lo,
+                              const double* sw, const double* t, const double* s,
+                              const double* x_in, double* x_out, SolveState* state,
+                              const SolveCtl* ctl, int k, int add_f0);
 hipError_t launch_contraction_only(hipStream_t st, int n_inst, int n, int nq, int ldk,
                                   const InstDev* inst, const double* K, size_t kstride,
                                   const double* s, const double* x_in, double* x_out,
@@ -98,16 +107,16 @@ hipError_t launch_sweep_fp32(hipStream_t st, int n_inst, int n, int nq, int ldi,
                              const float* MT, size_t mstride, float* C, size_t cstride,
                              const InstDev* inst, const int* lo, const double* sw, const double* t,
                              const double* s, const double* x_in, double* x_out,
-                             SolveState* state, const SolveCtl* ctl, int parity);
+                             SolveState* state, const SolveCtl* ctl, int k);
 
 // Persistent (cooperative) solve of a few instances sharing kernel block 0.
-size_t persistent_lds_bytes(int rpw, int nq);
-hipError_t persistent_max_blocks(int rpw, int nq, int* max_blocks);
+size_t persistent_lds_bytes(int rpw, int nq, int gsz);
+hipError_t persistent_max_blocks(int rpw, int nq, int gsz, int* max_blocks);
 hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const InstDev* inst, const double* K, const int* lo,
                              const double* sw, const double* t, const double* s, double* xbuf0,
                              double* xbuf1, SolveState* state, const SolveCtl* ctl,
                              unsigned long long* slots, unsigned int* barrier, int* flags, int G,
-                             int rpw);
+                             int rpw, int gsz, int coherent);
 
 }  // namespace qdse

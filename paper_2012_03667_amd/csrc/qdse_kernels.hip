@@ -134,14 +134,15 @@ __global__ void k_precompute(int n, int nq, int na, int ldk, const double* __res
 // ---------------------------------------------------------------- masked runs
 __device__ inline double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-// Status of an instance at the start of a sweep, from the test statistic of
-// the previous sweep. Every block evaluates it the same way; block 0 records
-// it. Returns nonzero if the instance is frozen.
-__device__ inline int decide(SolveState* st, const SolveCtl* ctl, int parity, bool writer) {
+// Status of an instance at the start of sweep k (1-based within a chunk whose
+// length is a multiple of 6), from the test statistic of sweep k-1. Every
+// block evaluates it the same way; the writer block records it and clears the
+// slot that sweep k+1 will fill.
+__device__ inline int decide(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
   SolveState& S = *st;
   int status = S.status;
   if (status != 0) return status;
-  const double prev = bits_to_double(S.metric[parity ^ 1]);
+  const double prev = bits_to_double(S.metric[(k + 2) % 3]);
   if (S.sweeps > 0) {
     if (!(prev <= 1.7976931348623157e308)) status = 3;  // NaN or inf
     else if (prev < ctl->tol) status = 1;
@@ -152,7 +153,7 @@ __device__ inline int decide(SolveState* st, const SolveCtl* ctl, int parity, bo
       S.status = status;
       S.resid = prev;
     }
-    S.metric[parity] = 0ull;  // cleared for this sweep's reduction
+    S.metric[(k + 1) % 3] = 0ull;
   }
   return status;
 }
@@ -164,7 +165,8 @@ __global__ void k_solve_init(int n_inst, SolveState* st) {
   st[k].sweeps = 0;
   st[k].resid = __longlong_as_double(0x7ff0000000000000ll);
   st[k].metric[0] = 0x7ff0000000000000ull;  // +inf: no sweep yet
-  st[k].metric[1] = 0x7ff0000000000000ull;
+  st[k].metric[1] = 0ull;                   // filled by sweep 1
+  st[k].metric[2] = 0ull;
 }
 
 // ---------------------------------------------------------------- node functions
@@ -198,9 +200,9 @@ __device__ inline void node_values(int n, int j, const int* lo, const double* sw
 __global__ void k_nodes(int n, int nq, int ldk, const int* __restrict__ lo,
                         const double* __restrict__ sw, const double* __restrict__ t,
                         const double* __restrict__ x, double* __restrict__ nodes,
-                        SolveState* state, const SolveCtl* ctl, int parity) {
+                        SolveState* state, const SolveCtl* ctl, int k) {
   const int inst = blockIdx.y;
-  if (state && decide(state + inst, ctl, parity, blockIdx.x == 0)) return;
+  if (state && decide(state + inst, ctl, k, blockIdx.x == 0)) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nq) return;
   const double* xA = x + (size_t)inst * 2 * n;
@@ -294,7 +296,7 @@ __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ld
                                                const double* __restrict__ nodes,
                                                const double* __restrict__ x_in,
                                                double* __restrict__ x_out, SolveState* state,
-                                               const SolveCtl* ctl, int parity, int add_f0) {
+                                               const SolveCtl* ctl, int k, int add_f0) {
   const int lane = threadIdx.x & (WAVE - 1);
   const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (row >= (long)n_inst * n) return;
@@ -324,8 +326,69 @@ __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ld
     if (state) {
       const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
       const unsigned long long bits = (unsigned long long)__double_as_longlong(isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
-      atomicMax(&state[inst].metric[parity], bits);
+      atomicMax(&state[inst].metric[k % 3], bits);
       if (i == 0) state[inst].sweeps += 1;
+    }
+  }
+}
+
+// Fused sweep: one workgroup = (instance, 16 consecutive rows); the node
+// functions of the instance are rebuilt in LDS by every workgroup (O(N) work
+// against O(16 N) for the rows), then each wavefront contracts four rows with
+// exactly the per-row arithmetic of k_sweep.
+constexpr int FUSED_ROWS = 16;
+
+__global__ void __launch_bounds__(256) k_sweep_fused(
+    int n_inst, int n, int nq, int ldk, const InstDev* __restrict__ inst_,
+    const double* __restrict__ K, size_t kstride, const int* __restrict__ lo,
+    const double* __restrict__ sw, const double* __restrict__ t_, const double* __restrict__ s_,
+    const double* __restrict__ x_in, double* __restrict__ x_out, SolveState* state,
+    const SolveCtl* ctl, int k, int add_f0) {
+  extern __shared__ double nd[];  // [5][ldk]
+  const int inst = blockIdx.y;
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const double* xi = x_in + (size_t)inst * 2 * n;
+  double* xo = x_out + (size_t)inst * 2 * n;
+  const int r0 = blockIdx.x * FUSED_ROWS;
+  if (state && decide(state + inst, ctl, k, blockIdx.x == 0)) {  // frozen: carry along
+    for (int r = threadIdx.x; r < FUSED_ROWS; r += blockDim.x) {
+      const int i = r0 + r;
+      if (i < n) {
+        xo[i] = xi[i];
+        xo[n + i] = xi[n + i];
+      }
+    }
+    return;
+  }
+  for (int j = threadIdx.x; j < nq; j += blockDim.x) {
+    double v[5];
+    node_values<double>(n, j, lo, sw, t_[j], xi, xi + n, nullptr, nullptr, v);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) nd[(size_t)c * ldk + j] = v[c];
+  }
+  __syncthreads();
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  for (int rr = 0; rr < FUSED_ROWS / 4; ++rr) {
+    const int i = r0 + wave * (FUSED_ROWS / 4) + rr;
+    if (i >= n) break;
+    const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
+    const double s = s_[i];
+    const double Ai = xi[i], Bi = xi[n + i];
+    double acc[4];
+    row_accumulate_f64(nq, ldk, mat, Ki, nd, s, Ai, Bi, lane, acc);
+    if (lane == 0) {
+      const double An = (add_f0 ? 1.0 : 0.0) + P.pref * (acc[1] - acc[0]);
+      const double Bn = (add_f0 ? P.m : 0.0) + P.pref * fma(2.0 * s, acc[2], acc[3]);
+      xo[i] = An;
+      xo[n + i] = Bn;
+      if (state) {
+        const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(
+            isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
+        atomicMax(&state[inst].metric[k % 3], bits);
+        if (i == 0) state[inst].sweeps += 1;
+      }
     }
   }
 }
@@ -565,12 +628,24 @@ hipError_t launch_sweep_fp64(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const InstDev* inst, const double* K, size_t kstride, const int* lo,
                              const double* sw, const double* t, const double* s,
                              const double* x_in, double* x_out, double* nodes, SolveState* state,
-                             const SolveCtl* ctl, int parity, int add_f0) {
+                             const SolveCtl* ctl, int k, int add_f0) {
   hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
-                     sw, t, x_in, nodes, state, ctl, parity);
+                     sw, t, x_in, nodes, state, ctl, k);
   const long rows = (long)n_inst * n;
   hipLaunchKernelGGL(k_sweep, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n, nq,
-                     ldk, inst, K, kstride, s, nodes, x_in, x_out, state, ctl, parity, add_f0);
+                     ldk, inst, K, kstride, s, nodes, x_in, x_out, state, ctl, k, add_f0);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                              const InstDev* inst, const double* K, size_t kstride, const int* lo,
+                              const double* sw, const double* t, const double* s,
+                              const double* x_in, double* x_out, SolveState* state,
+                              const SolveCtl* ctl, int k, int add_f0) {
+  const size_t lds = (size_t)5 * ldk * sizeof(double);
+  hipLaunchKernelGGL(k_sweep_fused, dim3((n + FUSED_ROWS - 1) / FUSED_ROWS, n_inst), dim3(256),
+                     lds, st, n_inst, n, nq, ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out,
+                     state, ctl, k, add_f0);
   return hipGetLastError();
 }
 
@@ -581,14 +656,14 @@ hipError_t launch_contraction_only(hipStream_t st, int n_inst, int n, int nq, in
   const long rows = (long)n_inst * n;
   hipLaunchKernelGGL(k_sweep, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n, nq,
                      ldk, inst, K, kstride, s, nodes, x_in, x_out, (SolveState*)nullptr,
-                     (const SolveCtl*)nullptr, 0, 1);
+                     (const SolveCtl*)nullptr, 1, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_nodes_only(hipStream_t st, int n_inst, int n, int nq, int ldk, const int* lo,
                              const double* sw, const double* t, const double* x, double* nodes) {
   hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
-                     sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 0);
+                     sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 1);
   return hipGetLastError();
 }
 
@@ -609,7 +684,7 @@ hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const 
                       const double* t, const double* s, const double* x, const double* w,
                       double* out, double* nodes, double* part, double* gq, int nchunk) {
   hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
-                     sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 0);
+                     sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 1);
   const long rows = (long)n_inst * n;
   hipLaunchKernelGGL(k_vjp_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n, nq,
                      ldk, inst, K, kstride, s, t, nodes, w, out);

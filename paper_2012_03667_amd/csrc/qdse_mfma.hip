@@ -57,15 +57,15 @@ __global__ void k_build_m32(int n, int nq, int ldk, int ldi, const double* __res
 __global__ void k_nodes32(int n, int nq, int ldb, const int* __restrict__ lo,
                           const double* __restrict__ sw, const double* __restrict__ t,
                           const double* __restrict__ x, float* __restrict__ C, size_t cstride,
-                          SolveState* state, const SolveCtl* ctl, int parity);
+                          SolveState* state, const SolveCtl* ctl, int k);
 
 __device__ inline double bits2d(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-__device__ inline int decide32(SolveState* st, const SolveCtl* ctl, int parity, bool writer) {
+__device__ inline int decide32(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
   SolveState& S = *st;
   int status = S.status;
   if (status != 0) return status;
-  const double prev = bits2d(S.metric[parity ^ 1]);
+  const double prev = bits2d(S.metric[(k + 2) % 3]);
   if (S.sweeps > 0) {
     if (!(prev <= 1.7976931348623157e308)) status = 3;
     else if (prev < ctl->tol) status = 1;
@@ -76,7 +76,7 @@ __device__ inline int decide32(SolveState* st, const SolveCtl* ctl, int parity, 
       S.status = status;
       S.resid = prev;
     }
-    S.metric[parity] = 0ull;
+    S.metric[(k + 1) % 3] = 0ull;
   }
   return status;
 }
@@ -84,10 +84,10 @@ __device__ inline int decide32(SolveState* st, const SolveCtl* ctl, int parity, 
 __global__ void k_nodes32(int n, int nq, int ldb, const int* __restrict__ lo,
                           const double* __restrict__ sw, const double* __restrict__ t,
                           const double* __restrict__ x, float* __restrict__ C, size_t cstride,
-                          SolveState* state, const SolveCtl* ctl, int parity) {
+                          SolveState* state, const SolveCtl* ctl, int k) {
   const int inst = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (state && decide32(state + inst, ctl, parity, blockIdx.x == 0 && threadIdx.x == 0)) return;
+  if (state && decide32(state + inst, ctl, k, blockIdx.x == 0 && threadIdx.x == 0)) return;
   if (j >= nq) return;
   const double* xA = x + (size_t)inst * 2 * n;
   const int b = lo[j];
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(256) k_mfma_sweep(
     int n_inst, int n, int nq4, int ldi, int ldb, const float* __restrict__ MT, size_t mstride,
     const float* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
     const double* __restrict__ s_, const double* __restrict__ x_in, double* __restrict__ x_out,
-    SolveState* state, const SolveCtl* ctl, int parity) {
+    SolveState* state, const SolveCtl* ctl, int k) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i0 = blockIdx.x * 32;
   const int b0 = blockIdx.y * 64 + wave * 16;
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) k_mfma_sweep(
   if (state && inst_ok && status == 0) {
     // lanes lane, lane+16, lane+32, lane+48 hold the same instance
     unsigned long long bits = (unsigned long long)__double_as_longlong(worst);
-    atomicMax(&state[inst].metric[parity], bits);
+    atomicMax(&state[inst].metric[k % 3], bits);
     if (i0 == 0 && lk == 0) state[inst].sweeps += 1;
   }
 }
@@ -224,13 +224,13 @@ hipError_t launch_sweep_fp32(hipStream_t st, int n_inst, int n, int nq, int ldi,
                              const float* MT, size_t mstride, float* C, size_t cstride,
                              const InstDev* inst, const int* lo, const double* sw, const double* t,
                              const double* s, const double* x_in, double* x_out,
-                             SolveState* state, const SolveCtl* ctl, int parity) {
+                             SolveState* state, const SolveCtl* ctl, int k) {
   hipLaunchKernelGGL(k_nodes32, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldb, lo,
-                     sw, t, x_in, C, cstride, state, ctl, parity);
+                     sw, t, x_in, C, cstride, state, ctl, k);
   const int nq4 = (nq + 3) & ~3;
   hipLaunchKernelGGL(k_mfma_sweep, dim3((n + 31) / 32, (n_inst + 63) / 64), dim3(256), 0, st,
                      n_inst, n, nq4, ldi, ldb, MT, mstride, C, cstride, inst, s, x_in, x_out, state,
-                     ctl, parity);
+                     ctl, k);
   return hipGetLastError();
 }
 

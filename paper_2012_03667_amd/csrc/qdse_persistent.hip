@@ -49,14 +49,16 @@ __device__ inline unsigned long long stat_bits(double r) {
 
 // Grid-wide barrier number k (1-based) on a monotonically increasing counter.
 // Returns false if the wait timed out or another workgroup raised the flag.
-__device__ bool grid_sync(unsigned int* ctr, unsigned int target, int* err) {
+__device__ bool grid_sync(unsigned int* ctr, unsigned int target, int* err, bool coherent_data) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
+    // release: this workgroup's iterate rows and statistics before the arrival
     __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    // poll without ordering (no cache invalidation per poll), then one acquire
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         ok = 0;
         break;
@@ -66,15 +68,33 @@ __device__ bool grid_sync(unsigned int* ctr, unsigned int target, int* err) {
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
+    if (!coherent_data)  // agent-wide acquire: other workgroups' plain stores
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return ok != 0;
 }
 
+// Iterate exchange between workgroups. With coherent = 1 every load and store
+// of the iterate is an agent-scope relaxed atomic (coherent across the XCDs'
+// L2 caches without invalidating them); ordering comes from the release on
+// barrier arrival. With coherent = 0 plain accesses plus an agent-scope
+// acquire after the barrier are used.
+__device__ inline double ld_x(const double* p, int coherent) {
+  return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+__device__ inline void st_x(double* p, double v, int coherent) {
+  if (coherent)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
 struct PArgs {
-  int n_inst, n, nq, rpw, G;
+  int n_inst, n, nq, rpw, G, gsz;  // gsz: instances whose node functions share LDS
+  int coherent;  // 1: iterate exchanged with agent-scope atomic loads/stores
   const InstDev* inst;
   const double* K;  // kernel block shared by every instance
   int ldk;
@@ -134,121 +154,133 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       int stq = st_status[q];
       if (stq == 0) {
         if (st_sweeps[q] > 0) {
-          const double prev = __longlong_as_double(
-              (long long)a.slots[(size_t)((k - 1) % 3) * a.n_inst + q]);
+          const double prev = __longlong_as_double((long long)__hip_atomic_load(
+              &a.slots[(size_t)((k - 1) % 3) * a.n_inst + q], __ATOMIC_RELAXED,
+              __HIP_MEMORY_SCOPE_AGENT));
           if (!(prev <= 1.7976931348623157e308)) stq = 3;
           else if (prev < ctl.tol) stq = 1;
           if (stq) st_resid[q] = prev;
         }
         if (stq == 0 && st_sweeps[q] >= ctl.max_iter) {
           stq = 2;
-          st_resid[q] = __longlong_as_double(
-              (long long)a.slots[(size_t)((k - 1) % 3) * a.n_inst + q]);
+          st_resid[q] = __longlong_as_double((long long)__hip_atomic_load(
+              &a.slots[(size_t)((k - 1) % 3) * a.n_inst + q], __ATOMIC_RELAXED,
+              __HIP_MEMORY_SCOPE_AGENT));
         }
         st_status[q] = stq;
       }
       if (stq == 0) all_frozen = 0;
-      if (g == 0) a.slots[(size_t)((k + 1) % 3) * a.n_inst + q] = 0ull;
+      if (g == 0)
+        __hip_atomic_store(&a.slots[(size_t)((k + 1) % 3) * a.n_inst + q], 0ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     if (all_frozen) break;
 
-    for (int q = 0; q < a.n_inst; ++q) {
-      const double* xq = xc + (size_t)q * 2 * n;
-      double* xo = xn + (size_t)q * 2 * n;
-      if (st_status[q] != 0) {  // frozen: carry the iterate forward
-        for (int r = tid; r < nrows; r += PBLOCK) {
-          const int i = g + r * G;
-          xo[i] = xq[i];
-          xo[n + i] = xq[n + i];
-        }
-        continue;
-      }
-      // 2. node functions of instance q into LDS
-      for (int j = tid; j < nq; j += PBLOCK) {
+    for (int q0 = 0; q0 < a.n_inst; q0 += a.gsz) {
+      const int q1 = min(a.n_inst, q0 + a.gsz);
+      // 2. node functions of the running instances q0..q1-1 into LDS, one pass
+      for (int e = tid; e < (q1 - q0) * nq; e += PBLOCK) {
+        const int q = q0 + e / nq, j = e % nq;
+        if (st_status[q] != 0) continue;
+        const double* xq = xc + (size_t)q * 2 * n;
         const int b = a.lo[j];
         const double* w = a.sw + 4 * j;
         double Aq = 0.0, Bq = 0.0;
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-          Aq = fma(w[l], xq[b + l], Aq);
-          Bq = fma(w[l], xq[n + b + l], Bq);
+          Aq = fma(w[l], ld_x(xq + b + l, a.coherent), Aq);
+          Bq = fma(w[l], ld_x(xq + n + b + l, a.coherent), Bq);
         }
         const double tj = a.t[j];
         const double Dl = tj * Aq * Aq + Bq * Bq;
-        nd[j] = Aq;
-        nd[nq + j] = Bq;
-        nd[2 * nq + j] = Aq / Dl;
-        nd[3 * nq + j] = Bq / Dl;
+        double* ndq = nd + (size_t)(q - q0) * 4 * nq;
+        ndq[j] = Aq;
+        ndq[nq + j] = Bq;
+        ndq[2 * nq + j] = Aq / Dl;
+        ndq[3 * nq + j] = Bq / Dl;
       }
-      if (tid == 0) wgmax = 0ull;
       __syncthreads();
-      // 3. contraction of this workgroup's rows
-      const InstDev P = a.inst[q];
-      double acc[MAX_RPW][4];
-      double Ai[MAX_RPW], Bi[MAX_RPW], si[MAX_RPW];
-#pragma unroll
-      for (int r = 0; r < MAX_RPW; ++r) {
-        acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
-        if (r < nrows) {
-          const int i = g + r * G;
-          Ai[r] = xq[i];
-          Bi[r] = xq[n + i];
-          si[r] = a.s[i];
+      for (int q = q0; q < q1; ++q) {
+        const double* xq = xc + (size_t)q * 2 * n;
+        double* xo = xn + (size_t)q * 2 * n;
+        if (st_status[q] != 0) {  // frozen: carry the iterate forward
+          for (int r = tid; r < nrows; r += PBLOCK) {
+            const int i = g + r * G;
+            st_x(xo + i, ld_x(xq + i, a.coherent), a.coherent);
+            st_x(xo + n + i, ld_x(xq + n + i, a.coherent), a.coherent);
+          }
+          continue;
         }
-      }
-      for (int j = tid; j < nq; j += PBLOCK) {
-        const double Aq = nd[j], Bq = nd[nq + j], sV = nd[2 * nq + j], sS = nd[3 * nq + j];
-        const double tsV = a.t[j] * sV;
+        const double* ndq = nd + (size_t)(q - q0) * 4 * nq;
+        if (tid == 0) wgmax = 0ull;
+        // 3. contraction of this workgroup's rows
+        const InstDev P = a.inst[q];
+        double acc[MAX_RPW][4];
+        double Ai[MAX_RPW], Bi[MAX_RPW], si[MAX_RPW];
+#pragma unroll
+        for (int r = 0; r < MAX_RPW; ++r) {
+          acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+          if (r < nrows) {
+            const int i = g + r * G;
+            Ai[r] = ld_x(xq + i, a.coherent);
+            Bi[r] = ld_x(xq + n + i, a.coherent);
+            si[r] = a.s[i];
+          }
+        }
+        for (int j = tid; j < nq; j += PBLOCK) {
+          const double Aq = ndq[j], Bq = ndq[nq + j], sV = ndq[2 * nq + j], sS = ndq[3 * nq + j];
+          const double tsV = a.t[j] * sV;
+#pragma unroll
+          for (int r = 0; r < MAX_RPW; ++r) {
+            if (r < nrows) {
+              const double* Kr = Kl + (size_t)r * 3 * nq;
+              const double kT = Kr[j], k3 = Kr[nq + j], k0 = Kr[2 * nq + j];
+              const double dA = Aq - Ai[r], dB = Bq - Bi[r], sA = Aq + Ai[r];
+              const double e = fma(2.0 * sS, dB, fma(si[r], sV, tsV) * dA);
+              acc[r][0] = fma(kT, e, acc[r][0]);
+              acc[r][1] = fma(k3, sV * sA, acc[r][1]);
+              acc[r][2] = fma(kT, fma(sS, dA, -(sV * dB)), acc[r][2]);
+              acc[r][3] = fma(k0, sS * sA, acc[r][3]);
+            }
+          }
+        }
 #pragma unroll
         for (int r = 0; r < MAX_RPW; ++r) {
           if (r < nrows) {
-            const double* Kr = Kl + (size_t)r * 3 * nq;
-            const double kT = Kr[j], k3 = Kr[nq + j], k0 = Kr[2 * nq + j];
-            const double dA = Aq - Ai[r], dB = Bq - Bi[r], sA = Aq + Ai[r];
-            const double e = fma(2.0 * sS, dB, fma(si[r], sV, tsV) * dA);
-            acc[r][0] = fma(kT, e, acc[r][0]);
-            acc[r][1] = fma(k3, sV * sA, acc[r][1]);
-            acc[r][2] = fma(kT, fma(sS, dA, -(sV * dB)), acc[r][2]);
-            acc[r][3] = fma(k0, sS * sA, acc[r][3]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const double v = wsum(acc[r][c]);
+              if (lane == 0) red[wave][r][c] = v;
+            }
           }
         }
-      }
-#pragma unroll
-      for (int r = 0; r < MAX_RPW; ++r) {
-        if (r < nrows) {
-#pragma unroll
+        __syncthreads();
+        if (tid < nrows) {
+          const int r = tid, i = g + r * G;
+          double c4[4];
           for (int c = 0; c < 4; ++c) {
-            const double v = wsum(acc[r][c]);
-            if (lane == 0) red[wave][r][c] = v;
+            double v = 0.0;
+            for (int w = 0; w < PWAVES; ++w) v += red[w][r][c];
+            c4[c] = v;
           }
+          const double An = 1.0 + P.pref * (c4[1] - c4[0]);
+          const double Bn = P.m + P.pref * fma(2.0 * si[r], c4[2], c4[3]);
+          st_x(xo + i, An, a.coherent);
+          st_x(xo + n + i, Bn, a.coherent);
+          atomicMax(&wgmax, stat_bits(stat_p(ctl.mode, An, Bn, Ai[r], Bi[r])));
         }
-      }
-      __syncthreads();
-      if (tid < nrows) {
-        const int r = tid, i = g + r * G;
-        double c4[4];
-        for (int c = 0; c < 4; ++c) {
-          double v = 0.0;
-          for (int w = 0; w < PWAVES; ++w) v += red[w][r][c];
-          c4[c] = v;
+        __syncthreads();
+        // 4. this workgroup's contribution to the instance's test statistic
+        if (tid == 0) {
+          atomicMax(&a.slots[(size_t)(k % 3) * a.n_inst + q], wgmax);
+          st_sweeps[q] += 1;
         }
-        const double An = 1.0 + P.pref * (c4[1] - c4[0]);
-        const double Bn = P.m + P.pref * fma(2.0 * si[r], c4[2], c4[3]);
-        xo[i] = An;
-        xo[n + i] = Bn;
-        atomicMax(&wgmax, stat_bits(stat_p(ctl.mode, An, Bn, Ai[r], Bi[r])));
-      }
-      __syncthreads();
-      // 4. this workgroup's contribution to the instance's test statistic
-      if (tid == 0) {
-        atomicMax(&a.slots[(size_t)(k % 3) * a.n_inst + q], wgmax);
-        st_sweeps[q] += 1;
       }
       __syncthreads();
     }
     // 5. grid barrier k
-    if (!grid_sync(a.barrier, (unsigned int)(G * k), a.flags)) {
+    if (!grid_sync(a.barrier, (unsigned int)(G * k), a.flags, a.coherent != 0)) {
       fine = false;
       break;
     }
@@ -276,8 +308,8 @@ __global__ void k_persistent_reset(unsigned long long* slots, int nslots, unsign
 
 }  // namespace
 
-size_t persistent_lds_bytes(int rpw, int nq) {
-  return ((size_t)rpw * 3 * nq + (size_t)4 * nq) * sizeof(double);
+size_t persistent_lds_bytes(int rpw, int nq, int gsz) {
+  return ((size_t)rpw * 3 * nq + (size_t)4 * nq * gsz) * sizeof(double);
 }
 
 // Launches the persistent solve; G workgroups, each holding rpw rows. The
@@ -288,15 +320,15 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const double* sw, const double* t, const double* s, double* xbuf0,
                              double* xbuf1, SolveState* state, const SolveCtl* ctl,
                              unsigned long long* slots, unsigned int* barrier, int* flags, int G,
-                             int rpw) {
-  if (rpw > MAX_RPW || n_inst > 64 || (long)G * rpw < n) return hipErrorInvalidValue;
+                             int rpw, int gsz, int coherent) {
+  if (rpw > MAX_RPW || n_inst > 64 || (long)G * rpw < n || gsz < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_persistent_reset, dim3((3 * n_inst + 255) / 256), dim3(256), 0, st, slots,
                      3 * n_inst, barrier, flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  PArgs a{n_inst, n, nq, rpw, G, inst, K, ldk, lo, sw, t, s, xbuf0, xbuf1, state, ctl, slots,
-          barrier, flags};
-  const size_t lds = persistent_lds_bytes(rpw, nq);
+  PArgs a{n_inst, n, nq, rpw, G, gsz, coherent, inst, K, ldk, lo, sw, t, s, xbuf0, xbuf1, state,
+          ctl, slots, barrier, flags};
+  const size_t lds = persistent_lds_bytes(rpw, nq, gsz);
   e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds);
   if (e != hipSuccess) return e;
@@ -304,13 +336,13 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
   return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(G), dim3(PBLOCK), args, lds, st);
 }
 
-hipError_t persistent_max_blocks(int rpw, int nq, int* max_blocks) {
+hipError_t persistent_max_blocks(int rpw, int nq, int gsz, int* max_blocks) {
   int dev = 0, ncu = 0, occ = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = persistent_lds_bytes(rpw, nq);
+  const size_t lds = persistent_lds_bytes(rpw, nq, gsz);
   e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds);
   if (e != hipSuccess) return e;
