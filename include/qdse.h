@@ -130,6 +130,17 @@ int qdse_iterate_fp32(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
 int qdse_solve(qdse_ctx* ctx, double* d_x, double tol, int max_iter, int conv_mode,
                int* iters, double* resid);
 
+/* Newton's method on the fixed-point residual R(x) = F(x) - x for every
+ * instance, for fixed points where successive approximation does not contract:
+ * each step solves (I - J) dx = R by restarted GMRES with Jacobian-vector
+ * products (to ||.||_2 relative tolerance lin_tol) and sets x += dx. Stops when
+ * max_i |R_i| < tol for every instance or after max_newton steps. d_x: in
+ * initial guess, out last iterate. steps[n_inst], resid[n_inst] (host, may be
+ * NULL): Newton steps and final max|R|. Returns QDSE_OK, QDSE_NOT_CONVERGED or
+ * QDSE_ENAN. Synchronises the stream. */
+int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double lin_tol,
+                int* steps, double* resid);
+
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may
  * be NULL): FP32 matrix-core sweeps (QDSE_FP32_REFINE contexts) and FP64
  * sweeps. The FP32 phase stops at max(tol, 1e-6) on the same test; the FP64

@@ -58,6 +58,7 @@ def load():
     L.qdse_iterate_fp32.argtypes = [_vp, _vp, _vp]
     L.qdse_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp]
     L.qdse_solve_stats.argtypes = [_vp, _ip, _ip]
+    L.qdse_newton.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]
     L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_vjp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _dp]
@@ -174,6 +175,15 @@ class Solver:
         rc = load().qdse_solve(self._h, _dev(x, self.shape, "x"), float(tol), int(max_iter),
                                int(conv_mode), it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
         _check(rc, "qdse_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+        return rc, it, rs
+
+    def newton(self, x, tol=1e-12, max_newton=30, lin_tol=1e-10):
+        """In place Newton-Krylov. Returns (status, steps[n_inst], max|F(x)-x|[n_inst])."""
+        it = np.zeros(self.n_inst, dtype=np.int32)
+        rs = np.zeros(self.n_inst)
+        rc = load().qdse_newton(self._h, _dev(x, self.shape, "x"), float(tol), int(max_newton),
+                                float(lin_tol), it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
+        _check(rc, "qdse_newton", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
         return rc, it, rs
 
     def solve_stats(self):

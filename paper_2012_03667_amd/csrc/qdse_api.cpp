@@ -528,77 +528,66 @@ int qdse_vjp(qdse_ctx* c, const double* d_x, const double* d_w, double* d_out) {
   return vjp_on(c, c->d_K, d_x, d_w, d_out);
 }
 
-int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol, int max_iter,
-              double* theta_bar) {
-  if (!c || !d_xstar || !d_g || !theta_bar || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
-  for (const qdse_params& p : c->params)
-    if (!(p.D > 0.0)) return QDSE_EINVAL;
-  int rc = build_dK(c);
-  if (rc) return rc;
-  const HostGrid& g = c->hg;
-  const int nI = c->n_inst, len = 2 * g.n;
+}  // extern "C"
+
+namespace {
+
+// Device buffers freed on scope exit.
+struct DevBufs {
+  std::vector<double*> ps;
+  ~DevBufs() {
+    for (double* p : ps) dfree(p);
+  }
+  int alloc(double** p, size_t n) {
+    int r = dalloc(p, n);
+    if (r == QDSE_OK) ps.push_back(*p);
+    return r;
+  }
+};
+
+// Restarted GMRES(mres) for every instance at once (block-diagonal operator):
+// solves op(sol) = b to ||r||_2 <= tol ||b||_2 per instance, starting from
+// sol = 0. Arnoldi vectors, Gram-Schmidt (two classical passes) and the basis
+// combinations run on the device; the small Hessenberg least-squares problems
+// (Givens rotations) run on the host. Returns QDSE_OK or QDSE_NOT_CONVERGED.
+template <class Op>
+int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, double tol,
+                  int max_iter, int* steps_out) {
+  const int nI = c->n_inst, len = 2 * c->hg.n;
   const size_t L = xlen(c);
-  const int mres = 40;  // Krylov basis size before a restart
+  const int mres = 40;
   hipStream_t st = c->stream;
-
-  double *d_V = nullptr, *d_w = nullptr, *d_lam = nullptr, *d_r = nullptr, *d_h = nullptr,
-         *d_y = nullptr, *d_y1 = nullptr, *d_y2 = nullptr, *d_eB = nullptr, *d_sc = nullptr;
-  struct Guard {
-    std::vector<double*> ps;
-    ~Guard() {
-      for (double* p : ps) dfree(p);
-    }
-  } guard;
-#define ALLOC(p, n)                 \
-  do {                              \
-    int r_ = dalloc(&(p), (n));     \
-    if (r_) return r_;              \
-    guard.ps.push_back(p);          \
-  } while (0)
-  ALLOC(d_V, (size_t)(mres + 1) * L);
-  ALLOC(d_w, L);
-  ALLOC(d_lam, L);
-  ALLOC(d_r, L);
-  ALLOC(d_h, (size_t)nI * (mres + 2));
-  ALLOC(d_y, (size_t)nI * (mres + 1));
-  ALLOC(d_y1, L);
-  ALLOC(d_y2, L);
-  ALLOC(d_eB, L);
-  ALLOC(d_sc, (size_t)nI);
-#undef ALLOC
-  HIPCHK(hipMemsetAsync(d_lam, 0, L * sizeof(double), st));
-
-  // norms of g for the relative stopping test
-  std::vector<double> gnorm(nI), hh((size_t)nI * (mres + 2)), tmp(nI);
-  HIPCHK(launch_batched_dot(st, nI, len, d_g, 0, d_g, len, 1, d_sc));
+  DevBufs buf;
+  double *d_V, *d_w, *d_r, *d_h, *d_y, *d_sc;
+  int rc;
+  if ((rc = buf.alloc(&d_V, (size_t)(mres + 1) * L)) || (rc = buf.alloc(&d_w, L)) ||
+      (rc = buf.alloc(&d_r, L)) || (rc = buf.alloc(&d_h, (size_t)nI * (mres + 2))) ||
+      (rc = buf.alloc(&d_y, (size_t)nI * (mres + 1))) || (rc = buf.alloc(&d_sc, (size_t)nI)))
+    return rc;
+  std::vector<double> tmp(nI), bnorm(nI), hh((size_t)nI * (mres + 2));
+  std::vector<double> zero(L, 0.0);
+  HIPCHK(hipMemcpyAsync(d_sol, zero.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_batched_dot(st, nI, len, d_b, 0, d_b, len, 1, d_sc));
   HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  for (int k = 0; k < nI; ++k) gnorm[k] = std::sqrt(tmp[k]);
-
-  // A lambda = lambda - J^T lambda
-  auto apply = [&](const double* in, double* out_) -> int {
-    int r = vjp_on(c, c->d_K, d_xstar, in, out_);
-    if (r) return r;
-    HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));  // out = in - J^T in
-    return QDSE_OK;
-  };
+  for (int k = 0; k < nI; ++k) bnorm[k] = std::sqrt(tmp[k]);
 
   bool converged = false;
   int total = 0;
   std::vector<double> beta(nI), cs((size_t)nI * mres), sn((size_t)nI * mres),
-      Hm((size_t)nI * (mres + 1) * mres), gvec((size_t)nI * (mres + 1)), ysol((size_t)nI * (mres + 1));
-  while (!converged && total < max_iter) {
-    // r = g - A lambda
-    rc = apply(d_lam, d_r);
-    if (rc) return rc;
-    HIPCHK(launch_axpby(st, nI, len, -1.0, d_r, nullptr, d_g, d_r));
+      Hm((size_t)nI * (mres + 1) * mres), gvec((size_t)nI * (mres + 1)),
+      ysol((size_t)nI * (mres + 1));
+  while (total < max_iter) {
+    // r = b - op(sol)
+    if ((rc = apply(d_sol, d_r))) return rc;
+    HIPCHK(launch_axpby(st, nI, len, -1.0, d_r, nullptr, d_b, d_r));
     HIPCHK(launch_batched_dot(st, nI, len, d_r, 0, d_r, len, 1, d_sc));
     HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     converged = true;
     for (int k = 0; k < nI; ++k) {
       beta[k] = std::sqrt(tmp[k]);
-      if (beta[k] > tol * gnorm[k]) converged = false;
+      if (!(beta[k] <= tol * bnorm[k])) converged = false;
       tmp[k] = beta[k] > 0.0 ? 1.0 / beta[k] : 0.0;
     }
     if (converged) break;
@@ -608,12 +597,11 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
     std::fill(gvec.begin(), gvec.end(), 0.0);
     for (int k = 0; k < nI; ++k) gvec[(size_t)k * (mres + 1)] = beta[k];
     int kdim = 0;
-    for (int j = 0; j < mres && total < max_iter; ++j, ++total) {
+    for (int j = 0; j < mres && total < max_iter; ++j) {
+      ++total;
       double* vj = d_V + (size_t)j * L;
       double* vn = d_V + (size_t)(j + 1) * L;
-      rc = apply(vj, d_w);
-      if (rc) return rc;
-      // two passes of classical Gram-Schmidt, coefficients summed on the host
+      if ((rc = apply(vj, d_w))) return rc;
       std::vector<double> hcol((size_t)nI * (j + 1), 0.0);
       for (int pass = 0; pass < 2; ++pass) {
         HIPCHK(launch_batched_dot(st, nI, len, d_V, L, d_w, len, j + 1, d_h));
@@ -631,37 +619,33 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
         double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;  // column-major (mres+1) x mres
         double* gk = gvec.data() + (size_t)k * (mres + 1);
         const double hn = std::sqrt(tmp[k]);
-        for (int i = 0; i <= j; ++i) Hk[(size_t)j * (mres + 1) + i] = hcol[(size_t)k * (j + 1) + i];
-        Hk[(size_t)j * (mres + 1) + j + 1] = hn;
-        // previous Givens rotations, then a new one to zero H[j+1][j]
-        for (int i = 0; i < j; ++i) {
-          const double a = Hk[(size_t)j * (mres + 1) + i], b = Hk[(size_t)j * (mres + 1) + i + 1];
+        double* col = Hk + (size_t)j * (mres + 1);
+        for (int i = 0; i <= j; ++i) col[i] = hcol[(size_t)k * (j + 1) + i];
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {  // earlier rotations
+          const double a = col[i], b = col[i + 1];
           const double cc = cs[(size_t)k * mres + i], ss = sn[(size_t)k * mres + i];
-          Hk[(size_t)j * (mres + 1) + i] = cc * a + ss * b;
-          Hk[(size_t)j * (mres + 1) + i + 1] = -ss * a + cc * b;
+          col[i] = cc * a + ss * b;
+          col[i + 1] = -ss * a + cc * b;
         }
-        const double a = Hk[(size_t)j * (mres + 1) + j], b = hn;
+        const double a = col[j], b = hn;
         const double rr = std::hypot(a, b);
         const double cc = rr > 0.0 ? a / rr : 1.0, ss = rr > 0.0 ? b / rr : 0.0;
         cs[(size_t)k * mres + j] = cc;
         sn[(size_t)k * mres + j] = ss;
-        Hk[(size_t)j * (mres + 1) + j] = rr;
-        Hk[(size_t)j * (mres + 1) + j + 1] = 0.0;
+        col[j] = rr;
+        col[j + 1] = 0.0;
         gk[j + 1] = -ss * gk[j];
         gk[j] = cc * gk[j];
-        if (std::fabs(gk[j + 1]) > tol * gnorm[k]) all_small = false;
+        if (!(std::fabs(gk[j + 1]) <= tol * bnorm[k])) all_small = false;
         tmp[k] = hn > 0.0 ? 1.0 / hn : 0.0;
       }
       HIPCHK(hipMemcpyAsync(d_sc, tmp.data(), nI * sizeof(double), hipMemcpyHostToDevice, st));
       HIPCHK(launch_axpby(st, nI, len, 0.0, d_w, d_sc, d_w, vn));
       kdim = j + 1;
-      if (all_small) {
-        ++total;
-        break;
-      }
+      if (all_small) break;
     }
-    // solve the triangular systems and update lambda += V y
-    for (int k = 0; k < nI; ++k) {
+    for (int k = 0; k < nI; ++k) {  // back substitution, then sol += V y
       const double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;
       const double* gk = gvec.data() + (size_t)k * (mres + 1);
       double* yk = ysol.data() + (size_t)k * (mres + 1);
@@ -674,8 +658,51 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
     }
     HIPCHK(hipMemcpyAsync(d_y, ysol.data(), (size_t)nI * (mres + 1) * sizeof(double),
                           hipMemcpyHostToDevice, st));
-    HIPCHK(launch_combine(st, nI, len, d_V, L, kdim, d_y, mres + 1, 1.0, d_lam));
+    HIPCHK(launch_combine(st, nI, len, d_V, L, kdim, d_y, mres + 1, 1.0, d_sol));
   }
+  if (!converged) {  // final residual check after the last update
+    if ((rc = apply(d_sol, d_r))) return rc;
+    HIPCHK(launch_axpby(st, nI, len, -1.0, d_r, nullptr, d_b, d_r));
+    HIPCHK(launch_batched_dot(st, nI, len, d_r, 0, d_r, len, 1, d_sc));
+    HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    converged = true;
+    for (int k = 0; k < nI; ++k)
+      if (!(std::sqrt(tmp[k]) <= tol * bnorm[k])) converged = false;
+  }
+  if (steps_out) *steps_out = total;
+  return converged ? QDSE_OK : QDSE_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol, int max_iter,
+              double* theta_bar) {
+  if (!c || !d_xstar || !d_g || !theta_bar || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
+  for (const qdse_params& p : c->params)
+    if (!(p.D > 0.0)) return QDSE_EINVAL;
+  int rc = build_dK(c);
+  if (rc) return rc;
+  const HostGrid& g = c->hg;
+  const int nI = c->n_inst, len = 2 * g.n;
+  const size_t L = xlen(c);
+  hipStream_t st = c->stream;
+  DevBufs buf;
+  double *d_lam, *d_y1, *d_y2, *d_eB, *d_sc;
+  if ((rc = buf.alloc(&d_lam, L)) || (rc = buf.alloc(&d_y1, L)) || (rc = buf.alloc(&d_y2, L)) ||
+      (rc = buf.alloc(&d_eB, L)) || (rc = buf.alloc(&d_sc, (size_t)nI)))
+    return rc;
+  // (I - J^T) lambda = g
+  auto apply = [&](const double* in, double* out_) -> int {
+    int r = vjp_on(c, c->d_K, d_xstar, in, out_);
+    if (r) return r;
+    HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));
+    return QDSE_OK;
+  };
+  const int grc = gmres_batched(c, apply, d_g, d_lam, tol, max_iter, nullptr);
+  if (grc < 0) return grc;
   // theta_bar = lambda^T dF/dtheta
   HIPCHK(launch_sweep_fp64(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
                            c->d_sw, c->d_t, c->d_s, d_xstar, d_y1, c->d_nodes, nullptr, nullptr, 1,
@@ -683,27 +710,78 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
   HIPCHK(launch_sweep_fp64(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_dK, c->kstride, c->d_lo,
                            c->d_sw, c->d_t, c->d_s, d_xstar, d_y2, c->d_nodes, nullptr, nullptr, 1,
                            0));  // pref * S(dK/domega)
-  {
-    std::vector<double> eB(L, 0.0);
-    for (int k = 0; k < nI; ++k)
-      for (int i = 0; i < g.n; ++i) eB[(size_t)k * len + g.n + i] = 1.0;
-    HIPCHK(hipMemcpyAsync(d_eB, eB.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
-    std::vector<double> d1(nI), d2(nI), d3(nI);
-    HIPCHK(launch_batched_dot(st, nI, len, d_y1, 0, d_lam, len, 1, d_sc));
-    HIPCHK(hipMemcpyAsync(d1.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(launch_batched_dot(st, nI, len, d_y2, 0, d_lam, len, 1, d_sc));
-    HIPCHK(hipMemcpyAsync(d2.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(launch_batched_dot(st, nI, len, d_eB, 0, d_lam, len, 1, d_sc));
-    HIPCHK(hipMemcpyAsync(d3.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int k = 0; k < nI; ++k) {
-      const double D = c->params[k].D, om = c->params[k].omega;
-      theta_bar[3 * k + 0] = d1[k] / D;
-      theta_bar[3 * k + 1] = -4.0 / om * d1[k] + d2[k];
-      theta_bar[3 * k + 2] = d3[k];
-    }
+  std::vector<double> eB(L, 0.0);
+  for (int k = 0; k < nI; ++k)
+    for (int i = 0; i < g.n; ++i) eB[(size_t)k * len + g.n + i] = 1.0;
+  HIPCHK(hipMemcpyAsync(d_eB, eB.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<double> d1(nI), d2(nI), d3(nI);
+  HIPCHK(launch_batched_dot(st, nI, len, d_y1, 0, d_lam, len, 1, d_sc));
+  HIPCHK(hipMemcpyAsync(d1.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(launch_batched_dot(st, nI, len, d_y2, 0, d_lam, len, 1, d_sc));
+  HIPCHK(hipMemcpyAsync(d2.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(launch_batched_dot(st, nI, len, d_eB, 0, d_lam, len, 1, d_sc));
+  HIPCHK(hipMemcpyAsync(d3.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < nI; ++k) {
+    const double D = c->params[k].D, om = c->params[k].omega;
+    theta_bar[3 * k + 0] = d1[k] / D;                 // F - f0 is linear in D
+    theta_bar[3 * k + 1] = -4.0 / om * d1[k] + d2[k];  // pref ~ omega^-4, and the Gaussian
+    theta_bar[3 * k + 2] = d3[k];                     // dB'/dm = 1
   }
-  return converged ? QDSE_OK : QDSE_NOT_CONVERGED;
+  return grc;
+}
+
+int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin_tol,
+                int* steps, double* resid) {
+  if (!c || !d_x || !(tol > 0.0) || max_newton < 1 || !(lin_tol > 0.0)) return QDSE_EINVAL;
+  const HostGrid& g = c->hg;
+  const int nI = c->n_inst, len = 2 * g.n;
+  const size_t L = xlen(c);
+  hipStream_t st = c->stream;
+  DevBufs buf;
+  double *d_F, *d_dx, *d_sc;
+  int rc;
+  if ((rc = buf.alloc(&d_F, L)) || (rc = buf.alloc(&d_dx, L)) || (rc = buf.alloc(&d_sc, (size_t)nI)))
+    return rc;
+  std::vector<double> h(L), rmax(nI, 0.0);
+  auto apply = [&](const double* in, double* out_) -> int {  // (I - J(x)) v
+    HIPCHK(launch_jvp(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo, c->d_sw,
+                      c->d_t, c->d_s, d_x, in, out_, c->d_nodes));
+    HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));
+    return QDSE_OK;
+  };
+  int it = 0;
+  bool done = false, bad = false;
+  for (;; ++it) {
+    // residual R = F(x) - x, max-norm per instance
+    HIPCHK(launch_sweep_fused(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
+                              c->d_sw, c->d_t, c->d_s, d_x, d_F, nullptr, nullptr, 1, 1));
+    HIPCHK(launch_axpby(st, nI, len, -1.0, d_x, nullptr, d_F, d_F));
+    HIPCHK(hipMemcpyAsync(h.data(), d_F, L * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    done = true;
+    for (int k = 0; k < nI; ++k) {
+      double r = 0.0;
+      for (int e = 0; e < len; ++e) {
+        const double v = std::fabs(h[(size_t)k * len + e]);
+        if (!(v <= r)) r = v;  // NaN propagates
+      }
+      rmax[k] = r;
+      if (!(r < tol)) done = false;
+      if (!std::isfinite(r)) bad = true;
+    }
+    if (done || bad || it >= max_newton) break;
+    rc = gmres_batched(c, apply, d_F, d_dx, lin_tol, 400, nullptr);
+    if (rc < 0) return rc;
+    HIPCHK(launch_axpby(st, nI, len, 1.0, d_x, nullptr, d_dx, d_x));  // x += dx
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < nI; ++k) {
+    if (steps) steps[k] = it;
+    if (resid) resid[k] = rmax[k];
+  }
+  if (bad) return QDSE_ENAN;
+  return done ? QDSE_OK : QDSE_NOT_CONVERGED;
 }
 
 int qdse_kernel_matrices(qdse_ctx* c, int inst, double* d_K) {

@@ -67,7 +67,7 @@ hipError_t launch_sweep_fp64(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const double* x_in, double* x_out, double* nodes, SolveState* state,
                              const SolveCtl* ctl, int k, int add_f0);
 // The same sweep as one kernel: each workgroup rebuilds the node functions of
-// its instance in LDS and contracts 16 rows (bitwise the same arithmetic).
+// its instance in LDS and contracts 8 rows (bitwise the same arithmetic).
 hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk,
                               const InstDev* inst, const double* K, size_t kstride, const int* lo,
                               const double* sw, const double* t, const double* s,

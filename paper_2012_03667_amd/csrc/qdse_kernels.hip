@@ -264,17 +264,38 @@ __device__ inline void row_accumulate(int nq, int ldk, size_t mat, const double*
 __device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const double* __restrict__ Ki,
                                           const double* __restrict__ nd, double s, double Ai,
                                           double Bi, int lane, double acc[4]) {
+  // Loads of U consecutive lane strides are issued before any arithmetic so
+  // that a wavefront has ~8 U loads in flight; the accumulation order per lane
+  // is still j = lane, lane + 64, ... .
+  constexpr int U = 4;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  for (int j = lane; j < nq; j += WAVE) {
-    const double kT = Ki[j], k3 = Ki[mat + j], k0 = Ki[2 * mat + j];
-    const double Aq = nd[j], Bq = nd[ldk + j], sV = nd[2 * ldk + j], sS = nd[3 * ldk + j],
-                 tsV = nd[4 * ldk + j];
-    const double dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
-    const double e = fma(2.0 * sS, dB, fma(s, sV, tsV) * dA);
-    a0 = fma(kT, e, a0);
-    a1 = fma(k3, sV * sA, a1);
-    a2 = fma(kT, fma(sS, dA, -(sV * dB)), a2);
-    a3 = fma(k0, sS * sA, a3);
+  for (int jb = lane; jb < nq; jb += U * WAVE) {
+    double kT[U], k3[U], k0[U], Aq[U], Bq[U], sV[U], sS[U], tsV[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = jb + u * WAVE;
+      if (j < nq) {
+        kT[u] = Ki[j];
+        k3[u] = Ki[mat + j];
+        k0[u] = Ki[2 * mat + j];
+        Aq[u] = nd[j];
+        Bq[u] = nd[ldk + j];
+        sV[u] = nd[2 * ldk + j];
+        sS[u] = nd[3 * ldk + j];
+        tsV[u] = nd[4 * ldk + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (jb + u * WAVE < nq) {
+        const double dA = Aq[u] - Ai, dB = Bq[u] - Bi, sA = Aq[u] + Ai;
+        const double e = fma(2.0 * sS[u], dB, fma(s, sV[u], tsV[u]) * dA);
+        a0 = fma(kT[u], e, a0);
+        a1 = fma(k3[u], sV[u] * sA, a1);
+        a2 = fma(kT[u], fma(sS[u], dA, -(sV[u] * dB)), a2);
+        a3 = fma(k0[u], sS[u] * sA, a3);
+      }
+    }
   }
   acc[0] = wave_sum(a0);
   acc[1] = wave_sum(a1);
@@ -332,11 +353,11 @@ __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ld
   }
 }
 
-// Fused sweep: one workgroup = (instance, 16 consecutive rows); the node
+// Fused sweep: one workgroup = (instance, 8 consecutive rows); the node
 // functions of the instance are rebuilt in LDS by every workgroup (O(N) work
-// against O(16 N) for the rows), then each wavefront contracts four rows with
+// against O(8 N) for the rows), then each wavefront contracts two rows with
 // exactly the per-row arithmetic of k_sweep.
-constexpr int FUSED_ROWS = 16;
+constexpr int FUSED_ROWS = 8;
 
 __global__ void __launch_bounds__(256) k_sweep_fused(
     int n_inst, int n, int nq, int ldk, const InstDev* __restrict__ inst_,

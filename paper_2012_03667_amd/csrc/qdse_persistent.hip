@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
     for (int q0 = 0; q0 < a.n_inst; q0 += a.gsz) {
       const int q1 = min(a.n_inst, q0 + a.gsz);
       // 2. node functions of the running instances q0..q1-1 into LDS, one pass
+#pragma unroll 4
       for (int e = tid; e < (q1 - q0) * nq; e += PBLOCK) {
         const int q = q0 + e / nq, j = e % nq;
         if (st_status[q] != 0) continue;

@@ -304,3 +304,78 @@ def test_fp32_refined_solve_meets_1e7(Q):
         worst = max(worst, max(errs(xg[k], xr, n)))
     print("fp32+refine worst rel err vs oracle fixed point", worst, "sweeps", n32[:4], n64[:4], flush=True)
     assert worst < 1e-7, worst
+
+
+# ---------------------------------------------------------------- Newton-Krylov and the adjoint
+def test_newton_krylov_matches_oracle_fixed_point(Q):
+    n, na = 64, 32
+    params = [(0.55, 0.678, 0.005), (0.55, 0.678, 0.0)]
+    S = Q.Solver(n, na, params)
+    x = S.initial(1.0, 1.0)
+    rc, steps, res = S.newton(x, tol=1e-12, max_newton=30, lin_tol=1e-10)
+    assert rc == Q.QDSE_OK, (rc, steps, res)
+    assert np.all(steps <= 12) and np.all(res < 1e-12)
+    g = oracle_grid(n, na, 3)
+    for k, (D, om, m) in enumerate(params):
+        xr, _, rr = O.newton(g, O.Params(D, om, m), np.ones(2 * n), tol=1e-14)
+        assert max(errs(x[k].cpu().numpy(), xr, n)) < 1e-11
+
+
+def _loss_grad(x, s, n, target):
+    A, B = x[:n], x[n:]
+    M = B / A
+    L = np.sum((M - target) ** 2)
+    gA = -2 * (M - target) * B / A ** 2
+    gB = 2 * (M - target) / A
+    return L, np.concatenate([gA, gB])
+
+
+def test_adjoint_gradient_matches_oracle_and_central_differences(Q):
+    """dL/d(D, omega, m) at the fixed point, L = sum_p (M(p^2) - M_target(p^2))^2
+    with a seeded synthetic target: the GPU's implicit adjoint (GMRES on
+    (I - J)^T lambda = dL/dx) against (a) the oracle's dense implicit-function
+    formula g^T (I - J)^{-1} dF/dtheta and (b) central differences of the
+    oracle's converged loss (h = 1e-6, fixed points to 1e-14), to 1e-6 relative."""
+    n, na = 48, 24
+    rng = np.random.default_rng(55)
+    params = [(0.55, 0.678, 0.005), (0.50, 0.70, 0.02)]
+    S = Q.Solver(n, na, params)
+    x = S.initial(1.0, 1.0)
+    rc, it, rs = S.solve(x, tol=1e-14, max_iter=2000, conv_mode=Q.QDSE_CONV_ABS)
+    assert rc == Q.QDSE_OK
+    g = oracle_grid(n, na, 3)
+    xs = x.cpu().numpy()
+    gs, targets = [], []
+    for k in range(len(params)):
+        M0, Lam2 = rng.uniform(0.3, 0.5), rng.uniform(0.5, 2.0)
+        target = 0.005 + M0 / (1 + g.s / Lam2)
+        targets.append(target)
+        gs.append(_loss_grad(xs[k], g.s, n, target)[1])
+    tb, grc = S.grad(x, torch.tensor(np.stack(gs), device="cuda"), tol=1e-13, max_iter=400)
+    assert grc == Q.QDSE_OK
+    for k, (D, om, m) in enumerate(params):
+        p = O.Params(D, om, m)
+        xr, _, rr = O.newton(g, p, xs[k], tol=1e-14)
+        J = O.jacobian(g, p, xr)
+        f0 = np.concatenate([np.ones(n), np.full(n, m)])
+        dF_dD = (O.F(g, p, xr) - f0) / D
+        h = 1e-3
+        Fw = lambda w: O.F(g, O.Params(D, w, m), xr)
+        dF_dw = (-Fw(om + 2 * h) + 8 * Fw(om + h) - 8 * Fw(om - h) + Fw(om - 2 * h)) / (12 * h)
+        dF_dm = np.concatenate([np.zeros(n), np.ones(n)])
+        lam = np.linalg.solve((np.eye(2 * n) - J).T, _loss_grad(xr, g.s, n, targets[k])[1])
+        ref = np.array([lam @ dF_dD, lam @ dF_dw, lam @ dF_dm])
+        assert np.allclose(tb[k], ref, rtol=1e-8, atol=1e-12 * np.max(np.abs(ref))), (tb[k], ref)
+        # central differences of the converged loss
+        fd = []
+        for j in range(3):
+            th = [D, om, m]
+            Ls = []
+            for sgn in (+1, -1):
+                th2 = list(th)
+                th2[j] += sgn * 1e-6
+                xf, _, _ = O.newton(g, O.Params(*th2), xr, tol=1e-14)
+                Ls.append(_loss_grad(xf, g.s, n, targets[k])[0])
+            fd.append((Ls[0] - Ls[1]) / 2e-6)
+        fd = np.array(fd)
+        assert np.allclose(tb[k], fd, rtol=1e-6, atol=1e-9 * np.max(np.abs(fd))), (tb[k], fd)
