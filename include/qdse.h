@@ -178,11 +178,14 @@ int qdse_grad(qdse_ctx* ctx, const double* d_xstar, const double* d_g, double to
  * after the transverse-projector algebra (see the kernel source). */
 int qdse_kernel_matrices(qdse_ctx* ctx, int inst, double* d_K);
 
-/* Diagnostics: average device duration in milliseconds of the kernel of one
- * FP64 sweep (node functions and the O(N^2) contraction, one launch) at d_x,
- * over `reps` launches on the context's stream, each bracketed by its own pair
- * of HIP events. d_out [n_inst][2N] receives F(d_x). Synchronises the stream. */
-int qdse_time_contraction(qdse_ctx* ctx, const double* d_x, double* d_out, int reps,
+/* Diagnostics: average device duration in milliseconds of one sweep kernel at
+ * d_x over `reps` launches on the context's stream, each bracketed by its own
+ * pair of HIP events. fp32 = 0: the fused FP64 sweep kernel (node functions and
+ * the O(N^2) contraction in one launch); fp32 = 1: the FP32 matrix-core
+ * contraction kernel alone (node columns built once before; QDSE_FP32_REFINE
+ * contexts only, else QDSE_ENOTSUP). d_out [n_inst][2N] receives the sweep.
+ * Synchronises the stream. */
+int qdse_time_contraction(qdse_ctx* ctx, int fp32, const double* d_x, double* d_out, int reps,
                           double* avg_ms);
 
 /* Human-readable name of a status code. */

@@ -63,7 +63,7 @@ def load():
     L.qdse_vjp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _dp]
     L.qdse_kernel_matrices.argtypes = [_vp, ctypes.c_int, _vp]
-    L.qdse_time_contraction.argtypes = [_vp, _vp, _vp, ctypes.c_int, _dp]
+    L.qdse_time_contraction.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _dp]
     L.qdse_strerror.argtypes = [ctypes.c_int]
     L.qdse_strerror.restype = ctypes.c_char_p
     L.qdse_last_error.argtypes = []
@@ -216,12 +216,12 @@ class Solver:
         _check(rc, "qdse_grad", allow=(QDSE_OK, QDSE_NOT_CONVERGED))
         return tb, rc
 
-    def time_contraction(self, x, reps=50):
-        """Average device milliseconds of one contraction launch (HIP events)."""
+    def time_contraction(self, x, reps=50, fp32=False):
+        """Average device milliseconds of one sweep-kernel launch (HIP events)."""
         import torch
         out = torch.empty_like(x)
         ms = ctypes.c_double()
-        _check(load().qdse_time_contraction(self._h, _dev(x, self.shape, "x"),
+        _check(load().qdse_time_contraction(self._h, int(bool(fp32)), _dev(x, self.shape, "x"),
                                             _dev(out, self.shape, "out"), int(reps),
                                             ctypes.byref(ms)), "qdse_time_contraction")
         return ms.value

@@ -465,7 +465,7 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
     SolveCtl ctl{tol, conv_mode, max_iter};
     HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
     HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
-    if (c->persist_G > 0 && std::getenv("QDSE_NO_PERSISTENT") == nullptr) {
+    if (c->persist_G > 0 && std::getenv("QDSE_PERSISTENT") != nullptr) {
       int rc = solve_persistent(c, d_x, iters, resid);
       if (rc >= 0 && c->n_inst > 0) {
         // sweeps are reported through iters; keep the breakdown too
@@ -794,21 +794,29 @@ int qdse_kernel_matrices(qdse_ctx* c, int inst, double* d_K) {
   return QDSE_OK;
 }
 
-int qdse_time_contraction(qdse_ctx* c, const double* d_x, double* d_out, int reps,
+int qdse_time_contraction(qdse_ctx* c, int fp32, const double* d_x, double* d_out, int reps,
                           double* avg_ms) {
   if (!c || !d_x || !d_out || d_x == d_out || reps < 1 || !avg_ms) return QDSE_EINVAL;
+  if (fp32 && !c->d_M32) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
   hipStream_t st = c->stream;
+  if (fp32)  // node columns once; then only the matrix-core kernel is timed
+    HIPCHK(launch_sweep_fp32(st, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32, c->mstride32,
+                             c->d_C32, c->cstride32, c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s,
+                             d_x, d_out, nullptr, nullptr, 1));
   std::vector<hipEvent_t> ev(2 * reps, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = QDSE_OK;
   for (int r = 0; r < reps && rc == QDSE_OK; ++r) {
-    if (hipEventRecord(ev[2 * r], st) != hipSuccess ||
-        launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
-                           c->d_sw, c->d_t, c->d_s, d_x, d_out, nullptr, nullptr, 1,
-                           1) != hipSuccess ||
-        hipEventRecord(ev[2 * r + 1], st) != hipSuccess)
-      rc = QDSE_EDEVICE;
+    hipError_t e = hipEventRecord(ev[2 * r], st);
+    if (e == hipSuccess)
+      e = fp32 ? launch_mfma_only(st, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32, c->mstride32,
+                                  c->d_C32, c->cstride32, c->d_inst, c->d_s, d_x, d_out)
+               : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
+                                    c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out,
+                                    nullptr, nullptr, 1, 1);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], st);
+    if (e != hipSuccess) rc = QDSE_EDEVICE;
   }
   double tot = 0.0;
   if (rc == QDSE_OK && hipStreamSynchronize(st) == hipSuccess) {

@@ -109,6 +109,11 @@ hipError_t launch_sweep_fp32(hipStream_t st, int n_inst, int n, int nq, int ldi,
                              const double* s, const double* x_in, double* x_out,
                              SolveState* state, const SolveCtl* ctl, int k);
 
+hipError_t launch_mfma_only(hipStream_t st, int n_inst, int n, int nq, int ldi, int ldb,
+                            const float* MT, size_t mstride, const float* C, size_t cstride,
+                            const InstDev* inst, const double* s, const double* x_in,
+                            double* x_out);
+
 // Persistent (cooperative) solve of a few instances sharing kernel block 0.
 size_t persistent_lds_bytes(int rpw, int nq, int gsz);
 hipError_t persistent_max_blocks(int rpw, int nq, int gsz, int* max_blocks);

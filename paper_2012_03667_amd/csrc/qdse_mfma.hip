@@ -234,4 +234,15 @@ hipError_t launch_sweep_fp32(hipStream_t st, int n_inst, int n, int nq, int ldi,
   return hipGetLastError();
 }
 
+hipError_t launch_mfma_only(hipStream_t st, int n_inst, int n, int nq, int ldi, int ldb,
+                            const float* MT, size_t mstride, const float* C, size_t cstride,
+                            const InstDev* inst, const double* s, const double* x_in,
+                            double* x_out) {
+  const int nq4 = (nq + 3) & ~3;
+  hipLaunchKernelGGL(k_mfma_sweep, dim3((n + 31) / 32, (n_inst + 63) / 64), dim3(256), 0, st,
+                     n_inst, n, nq4, ldi, ldb, MT, mstride, C, cstride, inst, s, x_in, x_out,
+                     (SolveState*)nullptr, (const SolveCtl*)nullptr, 1);
+  return hipGetLastError();
+}
+
 }  // namespace qdse

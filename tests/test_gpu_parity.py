@@ -172,7 +172,6 @@ def test_graph_replay_equals_eager(Q):
     params = [(0.55, 0.678, 0.005), (0.55, 0.678, 0.0), (0.55, 0.678, 0.1)]
     S = Q.Solver(n, 32, params)
     outs = []
-    os.environ["QDSE_NO_PERSISTENT"] = "1"
     try:
         for flag in (None, "1", None, None):
             if flag:
@@ -185,30 +184,29 @@ def test_graph_replay_equals_eager(Q):
             outs.append((x.cpu().numpy(), it.copy()))
     finally:
         os.environ.pop("QDSE_NO_GRAPH", None)
-        os.environ.pop("QDSE_NO_PERSISTENT", None)
     for xo, it in outs[1:]:
         assert np.array_equal(xo, outs[0][0]) and np.array_equal(it, outs[0][1])
 
 
 @pytest.mark.parametrize("n,na,order", [(512, 128, 3), (64, 32, 3), (150, 100, 1), (37, 9, 3)])
 def test_persistent_solve_matches_graph_driver(Q, n, na, order):
-    """The single-launch cooperative solve and the kernel-per-sweep driver stop
-    at the same sweep with the same iterate (summation order differs, so
-    agreement is to rounding)."""
+    """The single-launch cooperative solve (opt-in) and the kernel-per-sweep
+    driver stop at the same sweep with the same iterate (summation order
+    differs, so agreement is to rounding)."""
     print(f"case persistent n={n} na={na}", flush=True)
     params = [(0.55, 0.678, 0.0), (0.55, 0.678, 0.005)]
     S = Q.Solver(n, na, params, interp_order=order)
     res = []
-    for flag in (None, "1"):
+    for flag in ("1", None):
         if flag:
-            os.environ["QDSE_NO_PERSISTENT"] = flag
+            os.environ["QDSE_PERSISTENT"] = flag
         else:
-            os.environ.pop("QDSE_NO_PERSISTENT", None)
+            os.environ.pop("QDSE_PERSISTENT", None)
         try:
             x = S.initial(1.0, 1.0)
             rc, it, rs = S.solve(x, tol=1e-10, max_iter=400)
         finally:
-            os.environ.pop("QDSE_NO_PERSISTENT", None)
+            os.environ.pop("QDSE_PERSISTENT", None)
         assert rc == Q.QDSE_OK, (flag, rc, it, rs)
         res.append((x.cpu().numpy(), it.copy(), rs.copy()))
     (xp, ip, rp), (xg, ig, rg) = res
