@@ -188,6 +188,61 @@ int qdse_kernel_matrices(qdse_ctx* ctx, int inst, double* d_K);
 int qdse_time_contraction(qdse_ctx* ctx, int fp32, const double* d_x, double* d_out, int reps,
                           double* avg_ms);
 
+/* ---------------------------------------------------------------------------
+ * Finite chemical potential mu, T = 0 (the extension named in Sec. II and V of
+ * the paper). Unknowns A(p~), B(p~), C(p~) are complex, p~ = (p_vec, p4 + i mu):
+ *   S^-1(p~) = i gamma_vec.p_vec A + i gamma_4 (p4 + i mu) C + B,
+ * on an external grid |p_vec| (n_space Gauss-Legendre nodes in ln|p_vec| on
+ * [r_min, r_max]) x p4 > 0 (n_time Gauss-Legendre nodes in v, p4 = lam4 sinh v,
+ * v in [0, asinh(p4_max/lam4)]); values at p4 < 0 follow from
+ * F(|p|, -p4) = F(|p|, p4)^*. The loop grid has one more node per direction on
+ * the same intervals (interleaved, so brackets are known in advance), q4 of
+ * both signs, and n_angle Gauss-Legendre nodes in the cosine of the angle
+ * between p_vec and q_vec (flat weight). The vertex is the Ball-Chiu vertex
+ * written with p~, q~ (Sigma_A on the spatial gammas, Sigma_C on gamma_4,
+ * difference quotients over q~^2 - p~^2), which satisfies the Ward-Takahashi
+ * identity with S^-1(p~); interaction and colour factor as in the vacuum.
+ * Unknown layout per instance: complex128 [3][n_space][n_time] (A, B, C),
+ * |p_vec|-major; a batch is instance-major. All instances share the grid.
+ * ------------------------------------------------------------------------- */
+typedef struct qdse_mu_ctx qdse_mu_ctx;
+
+typedef struct {
+  int n_space;      /* >= 4 external |p_vec| nodes                          */
+  int n_time;       /* >= 4 external p4 > 0 nodes                           */
+  int n_angle;      /* 1..256 angular nodes                                 */
+  int interp_order; /* 1 or 3 (per direction of the 2-D tensor stencil)    */
+  double r_min, r_max;   /* |p_vec| range, GeV, 0 < r_min < r_max           */
+  double p4_max, lam4;   /* p4 range [0, p4_max] and sinh-map scale, GeV    */
+} qdse_mu_grid;
+
+typedef struct {
+  double D, omega, m; /* as qdse_params                                    */
+  double mu;          /* quark chemical potential, GeV, >= 0               */
+} qdse_mu_params;
+
+/* Builds a finite-mu context for n_inst instances. Errors as qdse_setup. */
+int qdse_mu_setup(const qdse_mu_grid* grid, const qdse_mu_params* params, int n_inst,
+                  void* hip_stream, qdse_mu_ctx** out);
+void qdse_mu_destroy(qdse_mu_ctx* ctx);
+
+/* Host-only grid arrays (any pointer may be NULL): external ps[n_space],
+ * p4[n_time]; loop qs[n_space+1], q4[n_time+1] with measure weights
+ * wqs = |q|^2 d|q| and wq4 = dq4 per node; angular z[n_angle], wz[n_angle]. */
+int qdse_mu_grid_nodes(const qdse_mu_grid* grid, double* ps, double* p4, double* qs,
+                       double* q4, double* wqs, double* wq4, double* z, double* wz);
+
+/* One finite-mu sweep for every instance (complex128 device arrays, distinct).
+ * Asynchronous. */
+int qdse_mu_iterate(qdse_mu_ctx* ctx, const double* d_x_in, double* d_x_out);
+
+/* Successive approximation from d_x until max |F' - F| over the three
+ * functions and the grid (complex modulus) < tol for every instance, or
+ * max_iter sweeps. iters, resid: host [n_inst] (may be NULL). Returns QDSE_OK,
+ * QDSE_NOT_CONVERGED or QDSE_ENAN. Synchronises the stream. */
+int qdse_mu_solve(qdse_mu_ctx* ctx, double* d_x, double tol, int max_iter, int* iters,
+                  double* resid);
+
 /* Human-readable name of a status code. */
 const char* qdse_strerror(int code);
 

@@ -39,6 +39,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qdse_oracle.cpp")
+_SRC_MU = os.path.join(_HERE, "qdse_oracle_mu.cpp")
 _LIB = os.path.join(_HERE, "libqdse_oracle.so")
 _lib = None
 
@@ -48,7 +49,7 @@ def build(force: bool = True) -> str:
     contraction, IEEE semantics)."""
     if force or not os.path.exists(_LIB):
         cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
-               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB + ".tmp"]
+               "-ffp-contract=off", "-fno-fast-math", _SRC, _SRC_MU, "-o", _LIB + ".tmp"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -66,10 +67,21 @@ class _Par(ctypes.Structure):
                 ("m", ctypes.c_double), ("lam", ctypes.c_double)]
 
 
+class _MuGrid(ctypes.Structure):
+    _fields_ = [(nm, ctypes.c_int) for nm in ("ns", "n4", "nqs", "nq4", "na", "order")] + [
+        (nm, ctypes.POINTER(ctypes.c_double))
+        for nm in ("ps", "us", "p4", "v4", "qs", "uqs", "wqs", "q4", "vq4", "wq4", "z", "wz")]
+
+
+class _MuPar(ctypes.Structure):
+    _fields_ = [(nm, ctypes.c_double) for nm in ("D", "omega", "m", "mu")]
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+                os.path.getmtime(_SRC), os.path.getmtime(_SRC_MU)):
             build()
         L = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -82,6 +94,10 @@ def lib():
         L.qo_interp.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp, ip]
         L.qo_integrand.argtypes = [ctypes.c_double] * 8 + [dp, dp]
         L.qo_integrand.restype = None
+        L.qo_mu_map.argtypes = [ctypes.POINTER(_MuGrid), ctypes.POINTER(_MuPar), dp, dp, ip,
+                                ctypes.c_int, dp, dp, ctypes.c_int]
+        L.qo_mu_projections.argtypes = [ctypes.c_double] * 6 + [dp, dp, dp]
+        L.qo_mu_projections.restype = None
         _lib = L
     return _lib
 
@@ -382,3 +398,95 @@ def spectral_radius(g, p, x, nthreads=None):
     eigenvalues themselves."""
     ev = np.linalg.eigvals(jacobian(g, p, x, nthreads))
     return float(np.max(np.abs(ev))), ev
+
+
+# --------------------------------------------------------------------------
+# Finite chemical potential (qdse_oracle_mu.cpp)
+# --------------------------------------------------------------------------
+
+@dataclass
+class MuGrid:
+    """External (|p_vec|, p4 > 0) grid, loop (|q_vec|, |q4|) grid (one more node
+    per direction on the same log intervals, interleaved), angular grid in
+    cos(theta) with flat weight."""
+    ns: int
+    n4: int
+    na: int
+    order: int
+    ps: np.ndarray
+    us: np.ndarray
+    p4: np.ndarray
+    v4: np.ndarray
+    qs: np.ndarray
+    uqs: np.ndarray
+    wqs: np.ndarray
+    q4: np.ndarray
+    vq4: np.ndarray
+    wq4: np.ndarray
+    z: np.ndarray
+    wz: np.ndarray
+
+    @property
+    def ne(self):
+        return self.ns * self.n4
+
+    def _c(self):
+        arrs = [self.ps, self.us, self.p4, self.v4, self.qs, self.uqs, self.wqs, self.q4,
+                self.vq4, self.wq4, self.z, self.wz]
+        g = _MuGrid(self.ns, self.n4, len(self.qs), len(self.q4), self.na, self.order,
+                    *[_dp(a) for a in arrs])
+        g._keep = self
+        return g
+
+
+def mu_grid(ns: int, n4: int, na: int, r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0.5,
+            order: int = 3) -> MuGrid:
+    """|p_vec| on GL(ns) in ln|p| over [r_min, r_max]; p4 = lam4 sinh(v) with v on
+    GL(n4) over [0, asinh(p4_max/lam4)]; loop grids GL(ns+1), GL(n4+1) on the same
+    intervals; angle GL(na) in cos(theta) with flat weight. Loop weights carry
+    the measure: |q|^2 d|q| = |q|^3 dln|q| and dq4 = lam4 cosh(v) dv."""
+    a, b = math.log(r_min), math.log(r_max)
+    us, _ = gl_interval(ns, a, b)
+    uqs, wu = gl_interval(ns + 1, a, b)
+    vmax = math.asinh(p4_max / lam4)
+    v4, _ = gl_interval(n4, 0.0, vmax)
+    vq4, wv = gl_interval(n4 + 1, 0.0, vmax)
+    z, wz = gauss_legendre(na)
+    ps = np.array([math.exp(t) for t in us])
+    qs = np.array([math.exp(t) for t in uqs])
+    p4 = np.array([lam4 * math.sinh(t) for t in v4])
+    q4 = np.array([lam4 * math.sinh(t) for t in vq4])
+    wqs = np.array([w * q * q * q for w, q in zip(wu, qs)])
+    wq4 = np.array([w * (lam4 * math.cosh(t)) for w, t in zip(wv, vq4)])
+    return MuGrid(ns, n4, na, order, ps, us, p4, v4, qs, uqs, wqs, q4, vq4, wq4, z.copy(),
+                  wz.copy())
+
+
+def F_mu(g: MuGrid, D, omega, m, mu, x: np.ndarray, rows=None, nthreads=None):
+    """One finite-mu sweep. x: complex [3][ns*n4] (A, B, C), |p_vec|-major.
+    Returns complex [3][ne] (or [3][len(rows)])."""
+    x = np.ascontiguousarray(x, dtype=np.complex128).reshape(3, g.ne)
+    xr, xi = np.ascontiguousarray(x.real), np.ascontiguousarray(x.imag)
+    if rows is None:
+        rp, cnt = None, g.ne
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        rp, cnt = _ip(rows), len(rows)
+    orr, oi = np.empty(3 * cnt), np.empty(3 * cnt)
+    gc = g._c()
+    pc = _MuPar(D, omega, m, mu)
+    rc = lib().qo_mu_map(ctypes.byref(gc), ctypes.byref(pc), _dp(xr), _dp(xi), rp,
+                         0 if rows is None else cnt, _dp(orr), _dp(oi), _threads(nthreads))
+    if rc:
+        raise ValueError("oracle: bad finite-mu grid")
+    return (orr + 1j * oi).reshape(3, cnt)
+
+
+def mu_projections(pabs, p4, qabs, q4, z, mu, fp, fq):
+    """(A, B, C) projections of T gamma S(q~) Gamma(q~, p~) at one point, without
+    g(k^2); fp, fq: complex (A, B, C) at p~ and q~."""
+    a = np.empty(6)
+    fpa = np.array([v for c in fp for v in (c.real, c.imag)])
+    fqa = np.array([v for c in fq for v in (c.real, c.imag)])
+    lib().qo_mu_projections(pabs, p4, qabs, q4, z, mu, _dp(fpa), _dp(fqa), _dp(a))
+    return complex(a[0], a[1]), complex(a[2], a[3]), complex(a[4], a[5])

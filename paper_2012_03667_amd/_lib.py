@@ -31,6 +31,18 @@ class Params(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double), ("omega", ctypes.c_double), ("m", ctypes.c_double)]
 
 
+class MuGrid(ctypes.Structure):
+    _fields_ = [("n_space", ctypes.c_int), ("n_time", ctypes.c_int), ("n_angle", ctypes.c_int),
+                ("interp_order", ctypes.c_int), ("r_min", ctypes.c_double),
+                ("r_max", ctypes.c_double), ("p4_max", ctypes.c_double),
+                ("lam4", ctypes.c_double)]
+
+
+class MuParams(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("omega", ctypes.c_double), ("m", ctypes.c_double),
+                ("mu", ctypes.c_double)]
+
+
 _lib = None
 _vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
 
@@ -64,6 +76,13 @@ def load():
     L.qdse_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _dp]
     L.qdse_kernel_matrices.argtypes = [_vp, ctypes.c_int, _vp]
     L.qdse_time_contraction.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _dp]
+    L.qdse_mu_setup.argtypes = [ctypes.POINTER(MuGrid), ctypes.POINTER(MuParams), ctypes.c_int,
+                                _vp, ctypes.POINTER(_vp)]
+    L.qdse_mu_destroy.argtypes = [_vp]
+    L.qdse_mu_destroy.restype = None
+    L.qdse_mu_grid_nodes.argtypes = [ctypes.POINTER(MuGrid)] + [_dp] * 8
+    L.qdse_mu_iterate.argtypes = [_vp, _vp, _vp]
+    L.qdse_mu_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]
     L.qdse_strerror.argtypes = [ctypes.c_int]
     L.qdse_strerror.restype = ctypes.c_char_p
     L.qdse_last_error.argtypes = []
@@ -232,3 +251,73 @@ class Solver:
         _check(load().qdse_kernel_matrices(self._h, int(inst), ctypes.c_void_p(K.data_ptr())),
                "qdse_kernel_matrices")
         return K
+
+
+def mu_grid_nodes(n_space, n_time, n_angle, interp_order=3, r_min=1e-2, r_max=1e2, p4_max=1e2,
+                  lam4=0.5):
+    """Host-only: the finite-mu grid arrays a context would use."""
+    g = MuGrid(int(n_space), int(n_time), int(n_angle), int(interp_order), float(r_min),
+               float(r_max), float(p4_max), float(lam4))
+    sizes = (n_space, n_time, n_space + 1, n_time + 1, n_space + 1, n_time + 1, n_angle, n_angle)
+    out = [np.empty(k) for k in sizes]
+    _check(load().qdse_mu_grid_nodes(ctypes.byref(g), *[a.ctypes.data_as(_dp) for a in out]),
+           "qdse_mu_grid_nodes")
+    return dict(zip(("ps", "p4", "qs", "q4", "wqs", "wq4", "z", "wz"), out))
+
+
+class MuSolver:
+    """Finite-mu context: unknowns complex128 [n_inst][3][n_space*n_time] (A, B, C)."""
+
+    def __init__(self, n_space, n_time, n_angle, params, interp_order=3, r_min=1e-2, r_max=1e2,
+                 p4_max=1e2, lam4=0.5, stream=None):
+        import torch
+        L = load()
+        self.ns, self.n4, self.na = int(n_space), int(n_time), int(n_angle)
+        self.params = [tuple(map(float, p)) for p in params]
+        self.n_inst = len(self.params)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        g = MuGrid(self.ns, self.n4, self.na, int(interp_order), float(r_min), float(r_max),
+                   float(p4_max), float(lam4))
+        P = (MuParams * self.n_inst)(*[MuParams(*p) for p in self.params])
+        h = _vp()
+        _check(L.qdse_mu_setup(ctypes.byref(g), P, self.n_inst, _vp(self.stream.cuda_stream),
+                               ctypes.byref(h)), "qdse_mu_setup")
+        self._h = h
+
+    @property
+    def shape(self):
+        return (self.n_inst, 3, self.ns * self.n4)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().qdse_mu_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _cdev(self, t, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128
+                and t.is_contiguous() and tuple(t.shape) == self.shape):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape {self.shape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def iterate(self, x, out=None):
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        _check(load().qdse_mu_iterate(self._h, self._cdev(x, "x"), self._cdev(out, "out")),
+               "qdse_mu_iterate")
+        return out
+
+    def solve(self, x, tol=1e-10, max_iter=500):
+        it = np.zeros(self.n_inst, dtype=np.int32)
+        rs = np.zeros(self.n_inst)
+        rc = load().qdse_mu_solve(self._h, self._cdev(x, "x"), float(tol), int(max_iter),
+                                  it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
+        _check(rc, "qdse_mu_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+        return rc, it, rs

@@ -120,8 +120,7 @@ void gauss_legendre(int n, double* x, double* w) {
 // every loop node, using the bracket (s_{j-1}, s_j) known from the
 // interleaving. order 3: nodes j-2..j+1 shifted to stay inside the grid.
 // order 1: nodes j-1, j (eq. chazhiresult), the end value beyond either end.
-static void build_stencils(int n, int order, const double* u, const double* uq,
-                           int* lo, double* sw) {
+void build_stencils(int n, int order, const double* u, const double* uq, int* lo, double* sw) {
   const int nq = n + 1;
   for (int j = 0; j < nq; ++j) {
     double* w = sw + 4 * j;
@@ -190,6 +189,69 @@ int build_grid(const qdse_grid& g, HostGrid* hg) {
   hg->lo.resize(nq);
   hg->sw.resize(4 * nq);
   build_stencils(n, g.interp_order, hg->u.data(), hg->uq.data(), hg->lo.data(), hg->sw.data());
+  return 0;
+}
+
+int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h) {
+  const int ns = g.n_space, n4 = g.n_time, na = g.n_angle;
+  h->ns = ns;
+  h->n4 = n4;
+  h->nqs = ns + 1;
+  h->nq4 = n4 + 1;
+  h->na = na;
+  const double a = std::log(g.r_min), b = std::log(g.r_max);
+  const double half = 0.5 * (b - a);
+  const double vmax = std::asinh(g.p4_max / g.lam4);
+  const double hv = 0.5 * (vmax - 0.0);
+  std::vector<double> x(ns + 2), w(ns + 2);
+  // |p_vec|: Gauss-Legendre in ln|p|; loop |q|: one more node, weight |q|^3 dln|q|
+  h->us.resize(ns);
+  h->ps.resize(ns);
+  gauss_legendre(ns, x.data(), w.data());
+  for (int i = 0; i < ns; ++i) {
+    h->us[i] = a + half * (x[i] + 1.0);
+    h->ps[i] = std::exp(h->us[i]);
+  }
+  h->uqs.resize(ns + 1);
+  h->qs.resize(ns + 1);
+  h->wqs.resize(ns + 1);
+  gauss_legendre(ns + 1, x.data(), w.data());
+  for (int j = 0; j <= ns; ++j) {
+    h->uqs[j] = a + half * (x[j] + 1.0);
+    h->qs[j] = std::exp(h->uqs[j]);
+    h->wqs[j] = half * w[j] * h->qs[j] * h->qs[j] * h->qs[j];
+  }
+  // p4 = lam4 sinh(v), v Gauss-Legendre on [0, asinh(p4_max/lam4)]; dq4 = lam4 cosh(v) dv
+  std::vector<double> y(n4 + 2), wy(n4 + 2);
+  h->v4.resize(n4);
+  h->p4.resize(n4);
+  gauss_legendre(n4, y.data(), wy.data());
+  for (int i = 0; i < n4; ++i) {
+    h->v4[i] = 0.0 + hv * (y[i] + 1.0);
+    h->p4[i] = g.lam4 * std::sinh(h->v4[i]);
+  }
+  h->vq4.resize(n4 + 1);
+  h->q4.resize(n4 + 1);
+  h->wq4.resize(n4 + 1);
+  gauss_legendre(n4 + 1, y.data(), wy.data());
+  for (int j = 0; j <= n4; ++j) {
+    h->vq4[j] = 0.0 + hv * (y[j] + 1.0);
+    h->q4[j] = g.lam4 * std::sinh(h->vq4[j]);
+    h->wq4[j] = hv * wy[j] * (g.lam4 * std::cosh(h->vq4[j]));
+  }
+  h->z.resize(na);
+  h->wz.resize(na);
+  gauss_legendre(na, h->z.data(), h->wz.data());
+  for (int i = 0; i < ns; ++i)
+    if (!(h->qs[i] < h->ps[i] && h->ps[i] < h->qs[i + 1])) return -1;
+  for (int i = 0; i < n4; ++i)
+    if (!(h->q4[i] < h->p4[i] && h->p4[i] < h->q4[i + 1])) return -1;
+  h->lo_s.resize(ns + 1);
+  h->sw_s.resize(4 * (ns + 1));
+  build_stencils(ns, g.interp_order, h->us.data(), h->uqs.data(), h->lo_s.data(), h->sw_s.data());
+  h->lo_4.resize(n4 + 1);
+  h->sw_4.resize(4 * (n4 + 1));
+  build_stencils(n4, g.interp_order, h->v4.data(), h->vq4.data(), h->lo_4.data(), h->sw_4.data());
   return 0;
 }
 

@@ -22,6 +22,19 @@ struct HostGrid {
 
 void gauss_legendre(int n, double* x, double* w);
 int build_grid(const qdse_grid& g, HostGrid* hg);
+void build_stencils(int n, int order, const double* u, const double* uq, int* lo, double* sw);
+
+// Host copy of a finite-mu discretisation.
+struct HostMuGrid {
+  int ns = 0, n4 = 0, nqs = 0, nq4 = 0, na = 0;
+  std::vector<double> us, ps, v4, p4;          // external nodes and grid variables
+  std::vector<double> uqs, qs, wqs;            // loop |q|, weight |q|^2 d|q|
+  std::vector<double> vq4, q4, wq4;            // loop |q4|, weight dq4
+  std::vector<double> z, wz;                   // angle, flat weight
+  std::vector<int> lo_s, lo_4;                 // stencil bases per direction
+  std::vector<double> sw_s, sw_4;              // stencil weights per direction
+};
+int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h);
 
 // Per-instance constants on the device.
 struct InstDev {
@@ -43,7 +56,11 @@ struct SolveCtl {
 // Per-instance state of a masked run (device).
 struct SolveState {
   int status;                   // 0 running, 1 converged, 2 max_iter, 3 non-finite
-  int sweeps;                   // sweeps done while running
+  int sweeps;                   // sweeps done while running (for the host)
+  int sweeps_slot[3];           // the same count per sweep slot: sweep k reads slot
+                                // (k-1)%3 and writes slot k%3, so no block of a
+                                // launch sees a value written in that launch
+  int pad;
   double resid;                 // test statistic of the deciding sweep
   unsigned long long metric[3]; // bits of the non-negative max over rows; sweep k uses
                                 // slot k%3, reads slot (k-1)%3, clears slot (k+1)%3
@@ -113,6 +130,16 @@ hipError_t launch_mfma_only(hipStream_t st, int n_inst, int n, int nq, int ldi, 
                             const float* MT, size_t mstride, const float* C, size_t cstride,
                             const InstDev* inst, const double* s, const double* x_in,
                             double* x_out);
+
+// Finite-mu sweep (qdse_mu.hip); x, L complex interleaved.
+hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, int nq4, int na,
+                           const double* ps, const double* p4, const double* qs, const double* q4,
+                           const double* wqs, const double* wq4, const double* z, const double* wz,
+                           const int* lo_s, const double* sw_s, const int* lo_4,
+                           const double* sw_4, double mu, double D, double omega, double m,
+                           const double* x_in, double* x_out, double* L);
+hipError_t launch_mu_stat(hipStream_t st, int n_inst, int ne, const double* x_old,
+                          const double* x_new, unsigned long long* stat);
 
 // Persistent (cooperative) solve of a few instances sharing kernel block 0.
 size_t persistent_lds_bytes(int rpw, int nq, int gsz);

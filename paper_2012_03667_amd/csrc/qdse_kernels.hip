@@ -140,19 +140,25 @@ __device__ inline double bits_to_double(unsigned long long b) { return __longlon
 // slot that sweep k+1 will fill.
 __device__ inline int decide(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
   SolveState& S = *st;
+  // Inputs written only by earlier launches: the status (a frozen instance
+  // stays frozen; within a launch every block derives the same status from the
+  // same inputs), the sweep count of slot (k-1)%3 and the statistic of sweep k-1.
   int status = S.status;
-  if (status != 0) return status;
+  const int done = S.sweeps_slot[(k + 2) % 3];
   const double prev = bits_to_double(S.metric[(k + 2) % 3]);
-  if (S.sweeps > 0) {
-    if (!(prev <= 1.7976931348623157e308)) status = 3;  // NaN or inf
-    else if (prev < ctl->tol) status = 1;
-  }
-  if (status == 0 && S.sweeps >= ctl->max_iter) status = 2;
-  if (writer && threadIdx.x == 0) {
-    if (status != 0) {
-      S.status = status;
-      S.resid = prev;
+  if (status == 0) {
+    if (done > 0) {
+      if (!(prev <= 1.7976931348623157e308)) status = 3;  // NaN or inf
+      else if (prev < ctl->tol) status = 1;
     }
+    if (status == 0 && done >= ctl->max_iter) status = 2;
+  }
+  if (writer && threadIdx.x == 0) {
+    if (status != 0 && S.status == 0) S.resid = prev;
+    S.status = status;
+    const int now = done + (status == 0 ? 1 : 0);
+    S.sweeps_slot[k % 3] = now;
+    S.sweeps = now;
     S.metric[(k + 1) % 3] = 0ull;
   }
   return status;
@@ -163,6 +169,7 @@ __global__ void k_solve_init(int n_inst, SolveState* st) {
   if (k >= n_inst) return;
   st[k].status = 0;
   st[k].sweeps = 0;
+  st[k].sweeps_slot[0] = st[k].sweeps_slot[1] = st[k].sweeps_slot[2] = 0;
   st[k].resid = __longlong_as_double(0x7ff0000000000000ll);
   st[k].metric[0] = 0x7ff0000000000000ull;  // +inf: no sweep yet
   st[k].metric[1] = 0ull;                   // filled by sweep 1
@@ -348,7 +355,6 @@ __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ld
       const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
       const unsigned long long bits = (unsigned long long)__double_as_longlong(isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
       atomicMax(&state[inst].metric[k % 3], bits);
-      if (i == 0) state[inst].sweeps += 1;
     }
   }
 }
@@ -408,7 +414,6 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
         const unsigned long long bits = (unsigned long long)__double_as_longlong(
             isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
         atomicMax(&state[inst].metric[k % 3], bits);
-        if (i == 0) state[inst].sweeps += 1;
       }
     }
   }

@@ -61,21 +61,25 @@ __global__ void k_nodes32(int n, int nq, int ldb, const int* __restrict__ lo,
 
 __device__ inline double bits2d(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+// Masked-run decision at the start of sweep k (same rule as the FP64 sweep).
 __device__ inline int decide32(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
   SolveState& S = *st;
   int status = S.status;
-  if (status != 0) return status;
+  const int done = S.sweeps_slot[(k + 2) % 3];
   const double prev = bits2d(S.metric[(k + 2) % 3]);
-  if (S.sweeps > 0) {
-    if (!(prev <= 1.7976931348623157e308)) status = 3;
-    else if (prev < ctl->tol) status = 1;
-  }
-  if (status == 0 && S.sweeps >= ctl->max_iter) status = 2;
-  if (writer) {
-    if (status != 0) {
-      S.status = status;
-      S.resid = prev;
+  if (status == 0) {
+    if (done > 0) {
+      if (!(prev <= 1.7976931348623157e308)) status = 3;
+      else if (prev < ctl->tol) status = 1;
     }
+    if (status == 0 && done >= ctl->max_iter) status = 2;
+  }
+  if (writer) {
+    if (status != 0 && S.status == 0) S.resid = prev;
+    S.status = status;
+    const int now = done + (status == 0 ? 1 : 0);
+    S.sweeps_slot[k % 3] = now;
+    S.sweeps = now;
     S.metric[(k + 1) % 3] = 0ull;
   }
   return status;
@@ -206,7 +210,6 @@ __global__ void __launch_bounds__(256) k_mfma_sweep(
     // lanes lane, lane+16, lane+32, lane+48 hold the same instance
     unsigned long long bits = (unsigned long long)__double_as_longlong(worst);
     atomicMax(&state[inst].metric[k % 3], bits);
-    if (i0 == 0 && lk == 0) state[inst].sweeps += 1;
   }
 }
 

@@ -1,0 +1,223 @@
+// qdse_mu_api.cpp -- C ABI of the finite-mu solver (include/qdse.h):
+// context set-up, sweeps and the successive-approximation driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qdse_internal.h"
+
+using namespace qdse;
+
+struct qdse_mu_ctx {
+  hipStream_t stream = nullptr;
+  HostMuGrid hg;
+  int n_inst = 0;
+  std::vector<qdse_mu_params> params;
+  double *d_ps = nullptr, *d_p4 = nullptr, *d_qs = nullptr, *d_q4 = nullptr, *d_wqs = nullptr,
+         *d_wq4 = nullptr, *d_z = nullptr, *d_wz = nullptr, *d_sw_s = nullptr, *d_sw_4 = nullptr;
+  int *d_lo_s = nullptr, *d_lo_4 = nullptr;
+  double* d_L = nullptr;      // interpolated loop values [inst][3][nl] complex
+  double* d_xb[2] = {nullptr, nullptr};
+  unsigned long long* d_stat = nullptr;
+};
+
+namespace {
+
+int mu_validate(const qdse_mu_grid* g) {
+  if (!g) return QDSE_EINVAL;
+  if (g->n_space < 4 || g->n_time < 4 || g->n_space > 4096 || g->n_time > 4096) return QDSE_EINVAL;
+  if (g->n_angle < 1 || g->n_angle > 256) return QDSE_EINVAL;
+  if (g->interp_order != 1 && g->interp_order != 3) return QDSE_EINVAL;
+  if (!(g->r_min > 0.0) || !(g->r_max > g->r_min) || !std::isfinite(g->r_max)) return QDSE_EINVAL;
+  if (!(g->p4_max > 0.0) || !(g->lam4 > 0.0) || !std::isfinite(g->p4_max)) return QDSE_EINVAL;
+  return QDSE_OK;
+}
+
+template <class T>
+int up(T** d, const std::vector<T>& h, hipStream_t st) {
+  if (hipMalloc((void**)d, h.size() * sizeof(T)) != hipSuccess) {
+    *d = nullptr;
+    return QDSE_ENOMEM;
+  }
+  if (hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
+    return QDSE_EDEVICE;
+  return QDSE_OK;
+}
+
+size_t mu_xlen(const qdse_mu_ctx* c) {  // doubles per batch
+  return (size_t)c->n_inst * 3 * c->hg.ns * c->hg.n4 * 2;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qdse_mu_grid_nodes(const qdse_mu_grid* grid, double* ps, double* p4, double* qs, double* q4,
+                       double* wqs, double* wq4, double* z, double* wz) {
+  if (mu_validate(grid)) return QDSE_EINVAL;
+  HostMuGrid h;
+  if (build_mu_grid(*grid, &h)) return QDSE_EINVAL;
+  auto put = [](double* d, const std::vector<double>& v) {
+    if (d) std::memcpy(d, v.data(), v.size() * sizeof(double));
+  };
+  put(ps, h.ps);
+  put(p4, h.p4);
+  put(qs, h.qs);
+  put(q4, h.q4);
+  put(wqs, h.wqs);
+  put(wq4, h.wq4);
+  put(z, h.z);
+  put(wz, h.wz);
+  return QDSE_OK;
+}
+
+void qdse_mu_destroy(qdse_mu_ctx* c) {
+  if (!c) return;
+  void* ptrs[] = {c->d_ps,   c->d_p4,   c->d_qs, c->d_q4,    c->d_wqs,   c->d_wq4, c->d_z,
+                  c->d_wz,   c->d_sw_s, c->d_sw_4, c->d_lo_s, c->d_lo_4, c->d_L,   c->d_xb[0],
+                  c->d_xb[1], c->d_stat};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+int qdse_mu_setup(const qdse_mu_grid* grid, const qdse_mu_params* params, int n_inst,
+                  void* hip_stream, qdse_mu_ctx** out) {
+  if (!out) return QDSE_EINVAL;
+  *out = nullptr;
+  if (mu_validate(grid) || !params || n_inst < 1 || n_inst > 65535) return QDSE_EINVAL;
+  for (int k = 0; k < n_inst; ++k) {
+    const qdse_mu_params& p = params[k];
+    if (!(p.D >= 0.0) || !std::isfinite(p.D) || !(p.omega > 0.0) || !std::isfinite(p.omega) ||
+        !std::isfinite(p.m) || !(p.mu >= 0.0) || !std::isfinite(p.mu))
+      return QDSE_EINVAL;
+  }
+  qdse_mu_ctx* c = new (std::nothrow) qdse_mu_ctx();
+  if (!c) return QDSE_ENOMEM;
+  c->stream = (hipStream_t)hip_stream;
+  c->n_inst = n_inst;
+  c->params.assign(params, params + n_inst);
+  if (build_mu_grid(*grid, &c->hg)) {
+    delete c;
+    return QDSE_EINVAL;
+  }
+  const HostMuGrid& h = c->hg;
+  hipStream_t st = c->stream;
+  int rc = QDSE_OK;
+  if (!rc) rc = up(&c->d_ps, h.ps, st);
+  if (!rc) rc = up(&c->d_p4, h.p4, st);
+  if (!rc) rc = up(&c->d_qs, h.qs, st);
+  if (!rc) rc = up(&c->d_q4, h.q4, st);
+  if (!rc) rc = up(&c->d_wqs, h.wqs, st);
+  if (!rc) rc = up(&c->d_wq4, h.wq4, st);
+  if (!rc) rc = up(&c->d_z, h.z, st);
+  if (!rc) rc = up(&c->d_wz, h.wz, st);
+  if (!rc) rc = up(&c->d_sw_s, h.sw_s, st);
+  if (!rc) rc = up(&c->d_sw_4, h.sw_4, st);
+  if (!rc) rc = up(&c->d_lo_s, h.lo_s, st);
+  if (!rc) rc = up(&c->d_lo_4, h.lo_4, st);
+  const size_t nl = (size_t)h.nqs * h.nq4;
+  if (!rc && hipMalloc((void**)&c->d_L, (size_t)n_inst * 3 * nl * 2 * sizeof(double)) != hipSuccess)
+    rc = QDSE_ENOMEM;
+  for (int b = 0; b < 2 && !rc; ++b)
+    if (hipMalloc((void**)&c->d_xb[b], mu_xlen(c) * sizeof(double)) != hipSuccess) rc = QDSE_ENOMEM;
+  if (!rc && hipMalloc((void**)&c->d_stat, (size_t)n_inst * sizeof(unsigned long long)) != hipSuccess)
+    rc = QDSE_ENOMEM;
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = QDSE_EDEVICE;
+  if (rc) {
+    qdse_mu_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return QDSE_OK;
+}
+
+// One sweep of every instance whose flag in `frozen` is 0 (nullptr: all);
+// frozen instances are copied forward. Instances share the grid; their
+// parameters enter as kernel arguments, one launch per instance.
+static int mu_sweep(qdse_mu_ctx* c, const double* in, double* out, const std::vector<int>* frozen) {
+  const HostMuGrid& h = c->hg;
+  const size_t per = (size_t)3 * h.ns * h.n4 * 2;
+  const size_t nl2 = (size_t)3 * h.nqs * h.nq4 * 2;
+  for (int k = 0; k < c->n_inst; ++k) {
+    if (frozen && (*frozen)[k]) {
+      if (hipMemcpyAsync(out + k * per, in + k * per, per * sizeof(double),
+                         hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return QDSE_EDEVICE;
+      continue;
+    }
+    const qdse_mu_params& p = c->params[k];
+    hipError_t e = launch_mu_sweep(c->stream, 1, h.ns, h.n4, h.nqs, h.nq4, h.na, c->d_ps, c->d_p4,
+                                   c->d_qs, c->d_q4, c->d_wqs, c->d_wq4, c->d_z, c->d_wz,
+                                   c->d_lo_s, c->d_sw_s, c->d_lo_4, c->d_sw_4, p.mu, p.D, p.omega,
+                                   p.m, in + k * per, out + k * per, c->d_L + k * nl2);
+    if (e != hipSuccess) return QDSE_EDEVICE;
+  }
+  return QDSE_OK;
+}
+
+int qdse_mu_iterate(qdse_mu_ctx* c, const double* d_x_in, double* d_x_out) {
+  if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
+  return mu_sweep(c, d_x_in, d_x_out, nullptr);
+}
+
+int qdse_mu_solve(qdse_mu_ctx* c, double* d_x, double tol, int max_iter, int* iters,
+                  double* resid) {
+  if (!c || !d_x || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
+  hipStream_t st = c->stream;
+  const int ne = c->hg.ns * c->hg.n4;
+  if (hipMemcpyAsync(c->d_xb[0], d_x, mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+      hipSuccess)
+    return QDSE_EDEVICE;
+  std::vector<unsigned long long> bits(c->n_inst);
+  std::vector<int> done(c->n_inst, 0), it(c->n_inst, 0);
+  std::vector<double> res(c->n_inst, INFINITY);
+  int cur = 0, rc = QDSE_OK;
+  for (int k = 1; k <= max_iter; ++k) {
+    std::vector<unsigned long long> zero(c->n_inst, 0ull);
+    if (hipMemcpyAsync(c->d_stat, zero.data(), zero.size() * sizeof(unsigned long long),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+      return QDSE_EDEVICE;
+    if ((rc = mu_sweep(c, c->d_xb[cur], c->d_xb[cur ^ 1], &done))) return rc;
+    if (launch_mu_stat(st, c->n_inst, ne, c->d_xb[cur], c->d_xb[cur ^ 1], c->d_stat) != hipSuccess)
+      return QDSE_EDEVICE;
+    if (hipMemcpyAsync(bits.data(), c->d_stat, bits.size() * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return QDSE_EDEVICE;
+    cur ^= 1;
+    bool all = true, bad = false;
+    for (int q = 0; q < c->n_inst; ++q) {
+      double r;
+      std::memcpy(&r, &bits[q], sizeof(double));
+      if (!done[q]) {
+        it[q] = k;
+        res[q] = r;
+        if (!(r <= 1.7976931348623157e308)) bad = true;
+        else if (r < tol) done[q] = 1;
+      }
+      if (!done[q]) all = false;
+    }
+    // converged instances are frozen (copied forward) from the next sweep on
+    if (all || bad) {
+      rc = bad ? QDSE_ENAN : QDSE_OK;
+      break;
+    }
+    if (k == max_iter) rc = QDSE_NOT_CONVERGED;
+  }
+  if (hipMemcpyAsync(d_x, c->d_xb[cur], mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return QDSE_EDEVICE;
+  for (int q = 0; q < c->n_inst; ++q) {
+    if (iters) iters[q] = it[q];
+    if (resid) resid[q] = res[q];
+  }
+  return rc;
+}
+
+}  // extern "C"

@@ -92,3 +92,14 @@ def test_library_grid_is_the_oracle_grid(L, n, na, smin, smax):
     assert np.array_equal(h["W"], g.wq * g.t * g.t)
     assert np.array_equal(h["z"], g.z)
     assert np.allclose(h["wz"], g.wz * np.sqrt(1 - g.z ** 2), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("ns,n4,na", [(8, 8, 6), (128, 128, 32), (10, 7, 5)])
+def test_library_mu_grid_is_the_oracle_grid(L, ns, n4, na):
+    import numpy as np
+    import paper_2012_03667_amd as Q
+    from oracle import qdse_oracle as O
+    h = Q.mu_grid_nodes(ns, n4, na, 3, 1e-2, 1e2, 1e2, 0.5)
+    g = O.mu_grid(ns, n4, na, r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0.5)
+    for k in ("ps", "p4", "qs", "q4", "wqs", "wq4", "z", "wz"):
+        assert np.array_equal(h[k], getattr(g, k)), k

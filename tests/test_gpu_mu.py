@@ -1,0 +1,97 @@
+"""Finite chemical potential: the HIP sweep (scalar four-vector algebra)
+against the oracle (explicit complex Dirac matrices), through the C ABI.
+Tolerance as for the vacuum FP64 path: 1e-12 relative per function (complex
+modulus), with a floor of 1e-8 of the largest value."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import qdse_oracle as O  # noqa: E402
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_03667_amd as Q
+    Q.load()
+    return Q
+
+
+def smooth_mu(g, rng):
+    P2 = (g.ps[:, None] ** 2 + g.p4[None, :] ** 2).ravel()
+    P4 = np.broadcast_to(g.p4[None, :], (g.ns, g.n4)).ravel()
+    a, b = rng.uniform(0.5, 1.2, 2)
+    A = 1 + a / (1 + P2 / 0.4) + 0.05j * P4 / (1 + P2)
+    B = 0.005 + b / (1 + P2 / 0.5) - 0.03j * P4 / (1 + P2)
+    C = 1 + 1.1 * a / (1 + P2 / 0.35) + 0.04j * P4 / (1 + P2)
+    return np.stack([A, B, C])
+
+
+def rel(gpu, ref):
+    den = np.maximum(np.abs(ref), 1e-8 * np.max(np.abs(ref)))
+    return float(np.max(np.abs(gpu - ref) / den))
+
+
+@pytest.mark.parametrize("ns,n4,na,order,mu", [(8, 8, 6, 3, 0.3), (10, 7, 5, 1, 0.3),
+                                               (9, 12, 8, 3, 0.0), (6, 5, 3, 3, 0.45)])
+def test_mu_sweep_matches_oracle(Q, ns, n4, na, order, mu):
+    print(f"case mu sweep {ns}x{n4}x{na} order {order} mu {mu}", flush=True)
+    rng = np.random.default_rng(ns * 100 + n4)
+    kw = dict(r_min=1e-2, r_max=8.0, p4_max=8.0, lam4=0.5)
+    params = [(0.55, 0.678, 0.005, mu), (1.024, 0.5, 0.0, mu)]
+    S = Q.MuSolver(ns, n4, na, params, interp_order=order, **kw)
+    g = O.mu_grid(ns, n4, na, order=order, **kw)
+    xs = [smooth_mu(g, rng) for _ in params]
+    x = torch.tensor(np.stack(xs), device="cuda")
+    y = S.iterate(x).cpu().numpy()
+    for k, (D, om, m, mu_) in enumerate(params):
+        ref = O.F_mu(g, D, om, m, mu_, xs[k])
+        for f in range(3):
+            assert rel(y[k, f], ref[f]) < RTOL, (k, f, rel(y[k, f], ref[f]))
+
+
+def test_mu_full_size_sampled_rows(Q):
+    """The 128 x 128 external grid with 129 x 129 x 2 loop points and 32 angles
+    at mu = 0.3 GeV: one sweep compared on sampled external points."""
+    ns = n4 = 128
+    na = 32
+    mu = 0.3
+    rng = np.random.default_rng(128)
+    S = Q.MuSolver(ns, n4, na, [(0.55, 0.678, 0.005, mu)])
+    g = O.mu_grid(ns, n4, na)
+    x0 = smooth_mu(g, rng)
+    y = S.iterate(torch.tensor(x0[None], device="cuda")).cpu().numpy()[0]
+    rows = np.sort(rng.choice(g.ne, 6, replace=False))
+    ref = O.F_mu(g, 0.55, 0.678, 0.005, mu, x0, rows=rows)
+    for f in range(3):
+        assert rel(y[f, rows], ref[f]) < RTOL, (f, rel(y[f, rows], ref[f]))
+
+
+def test_mu_solve_matches_oracle_picard(Q):
+    ns, n4, na, mu = 8, 8, 6, 0.25
+    kw = dict(r_min=1e-2, r_max=8.0, p4_max=8.0)
+    S = Q.MuSolver(ns, n4, na, [(0.55, 0.678, 0.005, mu)], **kw)
+    g = O.mu_grid(ns, n4, na, **kw)
+    x = torch.zeros(S.shape, dtype=torch.complex128, device="cuda")
+    x[0, 0] = 1.0
+    x[0, 1] = 0.3
+    x[0, 2] = 1.0
+    rc, it, rs = S.solve(x, tol=1e-11, max_iter=300)
+    assert rc == Q.QDSE_OK, (rc, it, rs)
+    xr = np.zeros((3, g.ne), complex)
+    xr[0], xr[1], xr[2] = 1.0, 0.3, 1.0
+    for k in range(1, 301):
+        xn = O.F_mu(g, 0.55, 0.678, 0.005, mu, xr)
+        r = np.max(np.abs(xn - xr))
+        xr = xn
+        if r < 1e-11:
+            break
+    assert abs(int(it[0]) - k) <= 1
+    got = x[0].cpu().numpy()
+    for f in range(3):
+        assert rel(got[f], xr[f]) < 1e-11

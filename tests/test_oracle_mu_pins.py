@@ -1,0 +1,105 @@
+"""Pins of the finite-mu oracle (explicit complex Dirac algebra) against the
+pinned vacuum oracle and exact properties."""
+import numpy as np
+import pytest
+
+from oracle import qdse_oracle as O
+from tests.test_oracle_pins import G, I4, slash
+
+rng = np.random.default_rng(2012)
+
+
+def sinv_mu(v, A, B, C):
+    """i gamma_vec.v_vec A + i gamma_4 v_4 C + B for a complex four-vector v."""
+    return 1j * (A * sum(v[m] * G[m] for m in range(3)) + C * v[3] * G[3]) + B * I4
+
+
+def vertex_mu(q, p, fq, fp):
+    Aq, Bq, Cq = fq
+    Ap, Bp, Cp = fp
+    P = p + q
+    dq = q @ q - p @ p
+    sA, sC = (Aq + Ap) / 2, (Cq + Cp) / 2
+    dA, dB, dC = (Aq - Ap) / dq, (Bq - Bp) / dq, (Cq - Cp) / dq
+    Pv = sum(P[m] * G[m] for m in range(3))
+    return [(sA if nu < 3 else sC) * G[nu] + P[nu] * (dA / 2 * Pv + dC / 2 * P[3] * G[3] - 1j * dB * I4)
+            for nu in range(4)]
+
+
+def test_finite_mu_vertex_ward_takahashi():
+    """i (q~ - p~).Gamma = S^-1(q~) - S^-1(p~) with complex p~ = (p_vec, p4 + i mu)."""
+    for _ in range(40):
+        mu = rng.uniform(0, 0.5)
+        p = np.array([*rng.normal(size=3), rng.normal() + 1j * mu])
+        q = np.array([*rng.normal(size=3), rng.normal() + 1j * mu])
+        fp = rng.uniform(0.5, 2, 3) + 1j * rng.uniform(-.3, .3, 3)
+        fq = rng.uniform(0.5, 2, 3) + 1j * rng.uniform(-.3, .3, 3)
+        Gam = vertex_mu(q, p, fq, fp)
+        lhs = 1j * sum((q - p)[nu] * Gam[nu] for nu in range(4))
+        rhs = sinv_mu(q, *fq) - sinv_mu(p, *fp)
+        assert np.allclose(lhs, rhs, atol=1e-12)
+
+
+def test_finite_mu_projections_reduce_to_vacuum_integrand():
+    """At mu = 0 with C = A (real), |p_vec|^2 A-proj + p4^2 C-proj is the vacuum
+    A projection times p^2 and the B projections agree: the finite-mu algebra
+    against the vacuum integrand pinned by the Dirac-trace test."""
+    worst = 0.0
+    for _ in range(200):
+        pabs, qabs = rng.uniform(0.05, 3, 2)
+        p4, q4 = rng.uniform(-2, 2, 2)
+        z = rng.uniform(-1, 1)
+        Ap, Aq = rng.uniform(0.8, 2.5, 2)
+        Bp, Bq = rng.uniform(-0.2, 0.8, 2)
+        a, b, c = O.mu_projections(pabs, p4, qabs, q4, z, 0.0, (Ap, Bp, Ap), (Aq, Bq, Aq))
+        s, t = pabs ** 2 + p4 ** 2, qabs ** 2 + q4 ** 2
+        z4 = (pabs * qabs * z + p4 * q4) / np.sqrt(s * t)
+        IA, IB = O.integrand(s, t, z4, Ap, Bp, Aq, Bq, 1.0)
+        Dq = t * Aq ** 2 + Bq ** 2
+        lhs = pabs ** 2 * a + p4 ** 2 * c
+        for x, y in ((lhs, s * IA / Dq), (b, IB / Dq)):
+            assert abs(x.imag) < 1e-12
+            worst = max(worst, abs(x.real - y) / (1 + abs(y)))
+    assert worst < 1e-12, worst
+
+
+def test_finite_mu_free_limit_and_wigner():
+    g = O.mu_grid(6, 5, 4, r_max=8, p4_max=8)
+    x = np.stack([1.2 + 0.1j * rng.normal(size=g.ne), 0.3 + 0.05j * rng.normal(size=g.ne),
+                  1.1 + 0.1j * rng.normal(size=g.ne)])
+    y = O.F_mu(g, 0.0, 0.6, 0.005, 0.3, x)
+    assert np.all(y[0] == 1.0) and np.all(y[1] == 0.005) and np.all(y[2] == 1.0)
+    x[1] = 0.0
+    y = O.F_mu(g, 0.55, 0.678, 0.0, 0.3, x)
+    assert np.all(y[1] == 0.0)
+
+
+@pytest.mark.slow
+def test_finite_mu_at_zero_mu_approaches_vacuum_continuum():
+    """mu = 0 and an O(4)-symmetric input A(p^2) = C(p^2), B(p^2): as the
+    (|p_vec|, p4, angle) grid is refined the finite-mu sweep approaches the
+    vacuum sweep at p^2 = |p_vec|^2 + p4^2 (the vacuum map on a fine grid,
+    itself pinned to continuum quadrature). Pins the finite-mu measure, the
+    q4 symmetrisation and the 2-D interpolation."""
+    D, om, m = 0.55, 0.678, 0.005
+    Af = lambda s: 1 + 0.8 / (1 + s / 0.3)
+    Bf = lambda s: 0.005 + 0.4 / (1 + s / 0.5)
+    gv = O.vac_grid(256, 256, s_min=1e-4, s_max=64.0)
+    xv = np.concatenate([Af(gv.s), Bf(gv.s)])
+    yv = O.F(gv, O.Params(D, om, m), xv)
+    errs = []
+    for ns, na in ((10, 8), (20, 16)):
+        g = O.mu_grid(ns, ns, na, r_min=1e-2, r_max=8.0, p4_max=8.0)
+        P2 = (g.ps[:, None] ** 2 + g.p4[None, :] ** 2).ravel()
+        x = np.stack([Af(P2), Bf(P2), Af(P2)]).astype(complex)
+        rows = [e for e in range(g.ne) if 0.05 < P2[e] < 2.0][::3]
+        y = O.F_mu(g, D, om, m, 0.0, x, rows=rows)
+        refA = np.interp(np.log(P2[rows]), np.log(gv.s), yv[:gv.n])
+        refB = np.interp(np.log(P2[rows]), np.log(gv.s), yv[gv.n:])
+        assert np.max(np.abs(y.imag)) < 1e-12
+        e = max(np.max(np.abs(y[0].real - refA) / np.abs(refA - 1)),
+                np.max(np.abs(y[2].real - refA) / np.abs(refA - 1)),
+                np.max(np.abs(y[1].real - refB) / np.abs(refB - m)))
+        errs.append(e)
+    assert errs[1] < errs[0] / 3, errs
+    assert errs[1] < 0.03, errs
