@@ -11,9 +11,10 @@ One step = reset both instances to the initial functions and solve them.
 Also reported on the same grid and interaction:
 * `batched`: 1024 instances with m ~ U[0, 0.2] GeV solved at equal accuracy
   (1e-7 relative to the oracle's fixed point: test tolerance 1e-8) by
-  (a) FP32 matrix-core sweeps to 1e-6 followed by FP64 sweeps, and
-  (b) FP64 sweeps only; plus the plain two-instance solver at the same
-  tolerance, for the equal-accuracy comparison.
+  (a) FP32 matrix-core sweeps to 1e-6 followed by FP64 matrix-core sweeps,
+  (b) FP64 matrix-core sweeps only and (c) FP64 direct-difference sweeps only;
+  plus the plain two-instance solver at the same tolerance, for the
+  equal-accuracy comparison.
 * `roofline`: the fused FP64 sweep kernel of the headline solve (HBM bound),
   and `roofline_fp32`: the FP32 MFMA contraction of the batch (MFMA bound),
   each timed live with HIP events on the library's stream.
@@ -150,9 +151,16 @@ def main():
         del S32
         S64 = Q.Solver(n, na, pb, interp_order=3)
         dt64, x64, it64 = timed_solves(S64, S64.initial(1.0, 1.0), tol_eq, args.batch_steps, 1)
-        res["fp64"] = {"solves_per_s": B * args.batch_steps / dt64,
-                       "ms_per_batch": 1e3 * dt64 / args.batch_steps,
-                       "sweeps_max": int(it64.max()), "sweeps_mean": float(it64.mean())}
+        res["fp64_direct"] = {"solves_per_s": B * args.batch_steps / dt64,
+                              "ms_per_batch": 1e3 * dt64 / args.batch_steps,
+                              "sweeps_max": int(it64.max()), "sweeps_mean": float(it64.mean())}
+        Smm = Q.Solver(n, na, pb, interp_order=3, precision=Q.QDSE_FP64_MATRIX)
+        dtm, xmm, itm = timed_solves(Smm, Smm.initial(1.0, 1.0), tol_eq, args.batch_steps, 1)
+        res["fp64_mfma"] = {"solves_per_s": B * args.batch_steps / dtm,
+                            "ms_per_batch": 1e3 * dtm / args.batch_steps,
+                            "sweeps_max": int(itm.max()), "sweeps_mean": float(itm.mean())}
+        ms_mm64 = Smm.time_contraction(x64, reps=50, which=2)
+        del Smm
         a32, a64 = x32.cpu().numpy(), x64.cpu().numpy()
         d = np.abs(a32 - a64) / np.maximum(np.abs(a64), 1e-8 * np.abs(a64).max(axis=1, keepdims=True))
         res["max_rel_diff_fp32_vs_fp64"] = float(d.max())
@@ -162,17 +170,23 @@ def main():
         line["batched"] = res
         # MFMA roofline of the FP32 contraction at this batch
         S32 = Q.Solver(n, na, pb, interp_order=3, precision=Q.QDSE_FP32_REFINE)
-        ms32 = S32.time_contraction(x64, reps=50, fp32=True)
+        ms32 = S32.time_contraction(x64, reps=50, which=1)
         flops = 16.0 * n * nq * B  # eight FP32 products per instance-row, 2 flop per MAC
         tf = flops / (ms32 * 1e-3) / 1e12
         line["roofline_fp32"] = {
-            "bound": "mfma", "kernel": "k_mfma_sweep (FP32 contraction, batch)",
+            "bound": "mfma", "kernel": "k_mm_sweep<float> (FP32 contraction, batch)",
             "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tf / FP32_MFMA_PEAK_TFLOPS, "traffic": None, "avg_kernel_us": ms32 * 1e3,
             "alg_flops_per_launch": flops}
         ms64 = S64.time_contraction(x64, reps=20)
-        line["batched"]["fp64_sweep_kernel_us"] = ms64 * 1e3
-        line["batched"]["fp32_contraction_kernel_us"] = ms32 * 1e3
+        line["batched"]["fp64_direct_sweep_kernel_us"] = ms64 * 1e3
+        line["batched"]["fp32_mfma_contraction_kernel_us"] = ms32 * 1e3
+        line["batched"]["fp64_mfma_contraction_kernel_us"] = ms_mm64 * 1e3
+        line["roofline_fp64_mfma"] = {
+            "bound": "mfma", "kernel": "k_mm_sweep<double> (FP64 contraction, batch)",
+            "achieved": flops / (ms_mm64 * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+            "frac": flops / (ms_mm64 * 1e-3) / 1e12 / 78.6, "traffic": None,
+            "avg_kernel_us": ms_mm64 * 1e3, "alg_flops_per_launch": flops}
         del S32, S64
         batch_x0 = a64[0]
     else:

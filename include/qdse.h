@@ -66,9 +66,11 @@ enum {
 
 /* Arithmetic of the contraction over loop nodes, the only O(N^2) step. */
 enum {
-  QDSE_FP64 = 0,        /* FP64 throughout (direct difference form)          */
-  QDSE_FP32_REFINE = 1  /* FP32 MFMA contraction with FP32 accumulation for
-                           the sweeps, then FP64 sweeps until the test holds  */
+  QDSE_FP64 = 0,         /* FP64 throughout (direct difference form)          */
+  QDSE_FP32_REFINE = 1,  /* FP32 MFMA contraction with FP32 accumulation for
+                            the sweeps, then FP64 matrix-core sweeps until
+                            the test holds                                   */
+  QDSE_FP64_MATRIX = 2   /* FP64 MFMA contraction (split form) for batches    */
 };
 
 /* Convergence test of qdse_solve. */
@@ -81,9 +83,9 @@ enum {
 /* Builds the grids, the interpolation stencils and the angular-integrated
  * kernel matrices for n_inst instances that share `grid` and have their own
  * `params[inst]` (instances with equal omega share one set of matrices).
- * precision: QDSE_FP64 or QDSE_FP32_REFINE (the latter also builds the FP32
- * matrices of the matrix-core sweep and needs one common omega: QDSE_ENOTSUP
- * otherwise).
+ * precision: QDSE_FP64, QDSE_FP32_REFINE or QDSE_FP64_MATRIX (the last two
+ * build the matrices of the matrix-core sweeps and need one common omega:
+ * QDSE_ENOTSUP otherwise).
  * hip_stream: a hipStream_t (NULL = the null stream). On success *out owns all
  * device memory of the context until qdse_destroy.
  * Errors: QDSE_EINVAL (grid or params out of range, n_inst < 1, out == NULL),
@@ -118,6 +120,10 @@ int qdse_iterate(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
  * QDSE_FP32_REFINE, else QDSE_ENOTSUP). Asynchronous. */
 int qdse_iterate_fp32(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
 
+/* Same sweep with the FP64 MFMA contraction in split form (contexts set up
+ * with QDSE_FP32_REFINE or QDSE_FP64_MATRIX, else QDSE_ENOTSUP). Asynchronous. */
+int qdse_iterate_fp64_matrix(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
+
 /* Successive approximation from the initial functions in d_x (Sec. II eq.
  * jifenab1 gives A0 = B0 = 1; any start is accepted) until the test `conv_mode`
  * holds with tolerance tol (Sec. II eq. jifenab2) or max_iter sweeps are done;
@@ -144,7 +150,7 @@ int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double l
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may
  * be NULL): FP32 matrix-core sweeps (QDSE_FP32_REFINE contexts) and FP64
  * sweeps. The FP32 phase stops at max(tol, 1e-6) on the same test; the FP64
- * phase then runs to tol. */
+ * phase (matrix-core split form) then runs to tol. */
 int qdse_solve_stats(const qdse_ctx* ctx, int* sweeps_fp32, int* sweeps_fp64);
 
 /* Jacobian-vector product d_jv = (dF/dx)(d_x) d_v for every instance (FP64,
@@ -180,12 +186,13 @@ int qdse_kernel_matrices(qdse_ctx* ctx, int inst, double* d_K);
 
 /* Diagnostics: average device duration in milliseconds of one sweep kernel at
  * d_x over `reps` launches on the context's stream, each bracketed by its own
- * pair of HIP events. fp32 = 0: the fused FP64 sweep kernel (node functions and
- * the O(N^2) contraction in one launch); fp32 = 1: the FP32 matrix-core
- * contraction kernel alone (node columns built once before; QDSE_FP32_REFINE
- * contexts only, else QDSE_ENOTSUP). d_out [n_inst][2N] receives the sweep.
+ * pair of HIP events. which = 0: the fused FP64 sweep kernel (node functions
+ * and the O(N^2) contraction in one launch); 1: the FP32 matrix-core
+ * contraction kernel alone; 2: the FP64 matrix-core contraction kernel alone
+ * (node columns are built once before; 1 and 2 need a context with the
+ * matrix-core data, else QDSE_ENOTSUP). d_out [n_inst][2N] receives the sweep.
  * Synchronises the stream. */
-int qdse_time_contraction(qdse_ctx* ctx, int fp32, const double* d_x, double* d_out, int reps,
+int qdse_time_contraction(qdse_ctx* ctx, int which, const double* d_x, double* d_out, int reps,
                           double* avg_ms);
 
 /* ---------------------------------------------------------------------------

@@ -11,7 +11,7 @@ _LIBPATH = os.path.join(_HERE, "libqdse.so")
 
 QDSE_OK, QDSE_NOT_CONVERGED = 0, 1
 QDSE_EINVAL, QDSE_ENOMEM, QDSE_EDEVICE, QDSE_ENAN, QDSE_ENOTSUP = -1, -2, -3, -4, -5
-QDSE_FP64, QDSE_FP32_REFINE = 0, 1
+QDSE_FP64, QDSE_FP32_REFINE, QDSE_FP64_MATRIX = 0, 1, 2
 QDSE_CONV_ABS, QDSE_CONV_MASS = 0, 1
 
 
@@ -68,6 +68,7 @@ def load():
     L.qdse_grid_nodes.argtypes = [ctypes.POINTER(Grid)] + [_dp] * 6
     L.qdse_iterate.argtypes = [_vp, _vp, _vp]
     L.qdse_iterate_fp32.argtypes = [_vp, _vp, _vp]
+    L.qdse_iterate_fp64_matrix.argtypes = [_vp, _vp, _vp]
     L.qdse_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp]
     L.qdse_solve_stats.argtypes = [_vp, _ip, _ip]
     L.qdse_newton.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]
@@ -178,11 +179,14 @@ class Solver:
         x[:, self.n:] = B0
         return x
 
-    def iterate(self, x, out=None, fp32=False):
+    def iterate(self, x, out=None, fp32=False, matrix=False):
+        """One sweep: FP64 direct (default), FP32 MFMA (fp32=True) or FP64 MFMA
+        split form (matrix=True)."""
         import torch
         if out is None:
             out = torch.empty_like(x)
-        fn = load().qdse_iterate_fp32 if fp32 else load().qdse_iterate
+        fn = (load().qdse_iterate_fp32 if fp32 else
+              load().qdse_iterate_fp64_matrix if matrix else load().qdse_iterate)
         _check(fn(self._h, _dev(x, self.shape, "x"), _dev(out, self.shape, "out")),
                "qdse_iterate")
         return out
@@ -235,12 +239,13 @@ class Solver:
         _check(rc, "qdse_grad", allow=(QDSE_OK, QDSE_NOT_CONVERGED))
         return tb, rc
 
-    def time_contraction(self, x, reps=50, fp32=False):
-        """Average device milliseconds of one sweep-kernel launch (HIP events)."""
+    def time_contraction(self, x, reps=50, which=0):
+        """Average device milliseconds of one sweep-kernel launch (HIP events):
+        which = 0 fused FP64 sweep, 1 FP32 matrix-core, 2 FP64 matrix-core."""
         import torch
         out = torch.empty_like(x)
         ms = ctypes.c_double()
-        _check(load().qdse_time_contraction(self._h, int(bool(fp32)), _dev(x, self.shape, "x"),
+        _check(load().qdse_time_contraction(self._h, int(which), _dev(x, self.shape, "x"),
                                             _dev(out, self.shape, "out"), int(reps),
                                             ctypes.byref(ms)), "qdse_time_contraction")
         return ms.value

@@ -66,11 +66,13 @@ struct qdse_ctx {
   int* d_lo = nullptr;
   double* d_K = nullptr;
   double* d_dK = nullptr;  // omega derivatives, built on first gradient request
-  float* d_M32 = nullptr;  // FP32 MFMA path: [5][nq4][ldi]
-  float* d_C32 = nullptr;  // FP32 node columns: [6][nq4][ldb]
-  int nq4 = 0, ldi = 0, ldb = 0;
-  size_t mstride32 = 0, cstride32 = 0;
-  hipGraphExec_t graph32_exec = nullptr;
+  // matrix-core paths: FP32 and FP64 matrices and node columns (mm_layout)
+  MmLayout mm;
+  float* d_M32 = nullptr;
+  float* d_C32 = nullptr;
+  double* d_M64 = nullptr;
+  double* d_C64 = nullptr;
+  hipGraphExec_t graph32_exec = nullptr, graphmm_exec = nullptr;
   std::vector<int> last_sweeps32, last_sweeps64;
   InstDev* d_inst = nullptr;
   double* d_nodes = nullptr;  // [n_inst][10][ldk]
@@ -139,7 +141,8 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   *out = nullptr;
   int rc = validate(grid, params, n_inst);
   if (rc) return rc;
-  if (precision != QDSE_FP64 && precision != QDSE_FP32_REFINE) return QDSE_EINVAL;
+  if (precision != QDSE_FP64 && precision != QDSE_FP32_REFINE && precision != QDSE_FP64_MATRIX)
+    return QDSE_EINVAL;
   qdse_ctx* c = new (std::nothrow) qdse_ctx();
   if (!c) return QDSE_ENOMEM;
   c->grid = *grid;
@@ -214,25 +217,32 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
       return QDSE_EDEVICE;
     }
   }
-  if (precision == QDSE_FP32_REFINE) {
+  if (precision == QDSE_FP32_REFINE || precision == QDSE_FP64_MATRIX) {
     if (c->n_blocks != 1) {  // the matrix-core path needs one shared matrix set
       qdse_destroy(c);
       return QDSE_ENOTSUP;
     }
-    c->nq4 = (g.nq + 3) & ~3;
-    c->ldi = (g.n + 31) & ~31;
-    c->ldb = (n_inst + 63) & ~63;
-    c->mstride32 = (size_t)c->nq4 * c->ldi;
-    c->cstride32 = (size_t)c->nq4 * c->ldb;
-    TRY(dalloc(&c->d_M32, 5 * c->mstride32));
-    TRY(dalloc(&c->d_C32, 6 * c->cstride32));
-    hipError_t e = hipMemsetAsync(c->d_M32, 0, 5 * c->mstride32 * sizeof(float), st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_C32, 0, 6 * c->cstride32 * sizeof(float), st);
+    c->mm = mm_layout(g.n, g.nq, n_inst);
+    const MmLayout& L = c->mm;
+    // FP64 matrix-core sweeps serve both precisions (the refinement of FP32)
+    TRY(dalloc(&c->d_M64, 5 * L.mstride));
+    TRY(dalloc(&c->d_C64, 6 * L.cstride));
+    hipError_t e = hipMemsetAsync(c->d_M64, 0, 5 * L.mstride * sizeof(double), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_C64, 0, 6 * L.cstride * sizeof(double), st);
     if (e == hipSuccess)
-      e = launch_build_m32(st, g.n, g.nq, g.ldk, c->ldi, c->d_K, c->d_s, c->d_t, c->d_M32,
-                           c->mstride32);
+      e = launch_build_mm<double>(st, g.n, g.nq, g.ldk, L, c->d_K, c->d_s, c->d_t, c->d_M64);
+    if (e == hipSuccess && precision == QDSE_FP32_REFINE) {
+      if (dalloc(&c->d_M32, 5 * L.mstride) || dalloc(&c->d_C32, 6 * L.cstride)) {
+        qdse_destroy(c);
+        return QDSE_ENOMEM;
+      }
+      e = hipMemsetAsync(c->d_M32, 0, 5 * L.mstride * sizeof(float), st);
+      if (e == hipSuccess) e = hipMemsetAsync(c->d_C32, 0, 6 * L.cstride * sizeof(float), st);
+      if (e == hipSuccess)
+        e = launch_build_mm<float>(st, g.n, g.nq, g.ldk, L, c->d_K, c->d_s, c->d_t, c->d_M32);
+    }
     if (e != hipSuccess) {
-      g_last_error = std::string("fp32 setup: ") + hipGetErrorString(e);
+      g_last_error = std::string("matrix-core setup: ") + hipGetErrorString(e);
       qdse_destroy(c);
       return QDSE_EDEVICE;
     }
@@ -277,12 +287,13 @@ void qdse_destroy(qdse_ctx* c) {
   if (!c) return;
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph32_exec) (void)hipGraphExecDestroy(c->graph32_exec);
+  if (c->graphmm_exec) (void)hipGraphExecDestroy(c->graphmm_exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void* ptrs[] = {c->d_s,       c->d_t,       c->d_W,       c->d_z,     c->d_wz,
                   c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_M32,
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
                   c->d_ctl,     c->d_part,    c->d_gq,      c->d_slots, c->d_barrier,
-                  c->d_flags,   c->d_C32};
+                  c->d_flags,   c->d_C32,     c->d_M64,     c->d_C64};
   for (void* p : ptrs) dfree(p);
   delete c;
 }
@@ -335,24 +346,43 @@ int qdse_iterate_fp32(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
   if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
   if (!c->d_M32) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
-  HIPCHK(launch_sweep_fp32(c->stream, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32,
-                           c->mstride32, c->d_C32, c->cstride32, c->d_inst, c->d_lo, c->d_sw,
-                           c->d_t, c->d_s, d_x_in, d_x_out, nullptr, nullptr, 0));
+  HIPCHK(launch_sweep_mm<float>(c->stream, c->n_inst, g.n, g.nq, c->mm, c->d_M32, c->d_C32,
+                                c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out,
+                                nullptr, nullptr, 1, true));
   return QDSE_OK;
 }
 
-static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, bool fp32) {
+int qdse_iterate_fp64_matrix(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
+  if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
+  if (!c->d_M64) return QDSE_ENOTSUP;
+  const HostGrid& g = c->hg;
+  HIPCHK(launch_sweep_mm<double>(c->stream, c->n_inst, g.n, g.nq, c->mm, c->d_M64, c->d_C64,
+                                 c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out,
+                                 nullptr, nullptr, 1, true));
+  return QDSE_OK;
+}
+
+// Sweep kinds of a masked run.
+enum { SWEEP_DIRECT = 0, SWEEP_MM32 = 1, SWEEP_MM64 = 2 };
+
+static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
   const HostGrid& g = c->hg;
   for (int k = 1; k <= chunk; ++k) {
     const int p = k & 1;  // sweep k reads xbuf[(k-1)%2] and writes xbuf[k%2]
-    if (fp32) {
-      HIPCHK(launch_sweep_fp32(st, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32, c->mstride32,
-                               c->d_C32, c->cstride32, c->d_inst, c->d_lo, c->d_sw, c->d_t,
-                               c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p], c->d_state, c->d_ctl, k));
+    const double* xi = c->d_xbuf[p ^ 1];
+    double* xo = c->d_xbuf[p];
+    if (kind == SWEEP_MM32) {
+      HIPCHK(launch_sweep_mm<float>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M32, c->d_C32, c->d_inst,
+                                    c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_state, c->d_ctl,
+                                    k, true));
+    } else if (kind == SWEEP_MM64) {
+      HIPCHK(launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64, c->d_C64,
+                                     c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo,
+                                     c->d_state, c->d_ctl, k, true));
     } else {
       HIPCHK(launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                                c->d_lo, c->d_sw, c->d_t, c->d_s, c->d_xbuf[p ^ 1], c->d_xbuf[p],
-                                c->d_state, c->d_ctl, k, 1));
+                                c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_state, c->d_ctl,
+                                k, 1));
     }
   }
   return QDSE_OK;
@@ -360,7 +390,7 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, bool fp32) {
 
 // Masked sweeps from xbuf[0] until every instance is frozen; the iterate ends
 // in xbuf[0]. hs receives the final per-instance state.
-static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, bool fp32,
+static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int kind,
                       std::vector<SolveState>& hs, bool* all_done) {
   const int chunk = 12;  // multiple of 6: ends in xbuf[0] with the slot cycle intact
   const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
@@ -368,12 +398,14 @@ static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, bool
   SolveCtl ctl{tol, conv_mode, max_iter};
   HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
   HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
-  hipGraphExec_t& exec = fp32 ? c->graph32_exec : c->graph_exec;
+  hipGraphExec_t& exec = kind == SWEEP_MM32   ? c->graph32_exec
+                         : kind == SWEEP_MM64 ? c->graphmm_exec
+                                              : c->graph_exec;
   if (use_graph && !exec) {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = record_chunk(c, c->cap_stream, chunk, fp32);
+    int rc = record_chunk(c, c->cap_stream, chunk, kind);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
     if (rc) return rc;
     HIPCHK(e);
@@ -389,7 +421,7 @@ static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, bool
     if (use_graph) {
       HIPCHK(hipGraphLaunch(exec, st));
     } else {
-      int rc = record_chunk(c, st, chunk, fp32);
+      int rc = record_chunk(c, st, chunk, kind);
       if (rc) return rc;
     }
     launched += chunk;
@@ -458,10 +490,10 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
     double tol32 = 1e-6;
     if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
     if (tol32 < tol) tol32 = tol;
-    int rc = run_masked(c, tol32, max_iter, conv_mode, true, hs, &all_done);
+    int rc = run_masked(c, tol32, max_iter, conv_mode, SWEEP_MM32, hs, &all_done);
     if (rc) return rc;
     for (int k = 0; k < c->n_inst; ++k) c->last_sweeps32[k] = hs[k].sweeps;
-  } else {
+  } else if (c->precision == QDSE_FP64) {
     SolveCtl ctl{tol, conv_mode, max_iter};
     HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
     HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
@@ -477,7 +509,8 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
       return rc;
     }
   }
-  int rc = run_masked(c, tol, max_iter, conv_mode, false, hs, &all_done);
+  const int kind = c->precision == QDSE_FP64 ? SWEEP_DIRECT : SWEEP_MM64;
+  int rc = run_masked(c, tol, max_iter, conv_mode, kind, hs, &all_done);
   if (rc) return rc;
   for (int k = 0; k < c->n_inst; ++k) {
     c->last_sweeps64[k] = hs[k].sweeps;
@@ -794,27 +827,36 @@ int qdse_kernel_matrices(qdse_ctx* c, int inst, double* d_K) {
   return QDSE_OK;
 }
 
-int qdse_time_contraction(qdse_ctx* c, int fp32, const double* d_x, double* d_out, int reps,
+int qdse_time_contraction(qdse_ctx* c, int which, const double* d_x, double* d_out, int reps,
                           double* avg_ms) {
   if (!c || !d_x || !d_out || d_x == d_out || reps < 1 || !avg_ms) return QDSE_EINVAL;
-  if (fp32 && !c->d_M32) return QDSE_ENOTSUP;
+  if (which < 0 || which > 2) return QDSE_EINVAL;
+  if ((which == 1 && !c->d_M32) || (which == 2 && !c->d_M64)) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
   hipStream_t st = c->stream;
-  if (fp32)  // node columns once; then only the matrix-core kernel is timed
-    HIPCHK(launch_sweep_fp32(st, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32, c->mstride32,
-                             c->d_C32, c->cstride32, c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s,
-                             d_x, d_out, nullptr, nullptr, 1));
+  if (which == 1)  // node columns once; then only the matrix-core kernel is timed
+    HIPCHK(launch_sweep_mm<float>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M32, c->d_C32, c->d_inst,
+                                  c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out, nullptr, nullptr,
+                                  1, true));
+  if (which == 2)
+    HIPCHK(launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64, c->d_C64,
+                                   c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out, nullptr,
+                                   nullptr, 1, true));
   std::vector<hipEvent_t> ev(2 * reps, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = QDSE_OK;
   for (int r = 0; r < reps && rc == QDSE_OK; ++r) {
     hipError_t e = hipEventRecord(ev[2 * r], st);
     if (e == hipSuccess)
-      e = fp32 ? launch_mfma_only(st, c->n_inst, g.n, g.nq, c->ldi, c->ldb, c->d_M32, c->mstride32,
-                                  c->d_C32, c->cstride32, c->d_inst, c->d_s, d_x, d_out)
-               : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
-                                    c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out,
-                                    nullptr, nullptr, 1, 1);
+      e = which == 1   ? launch_sweep_mm<float>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M32,
+                                                c->d_C32, c->d_inst, c->d_lo, c->d_sw, c->d_t,
+                                                c->d_s, d_x, d_out, nullptr, nullptr, 1, false)
+          : which == 2 ? launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64,
+                                                 c->d_C64, c->d_inst, c->d_lo, c->d_sw, c->d_t,
+                                                 c->d_s, d_x, d_out, nullptr, nullptr, 1, false)
+                       : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
+                                            c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x,
+                                            d_out, nullptr, nullptr, 1, 1);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], st);
     if (e != hipSuccess) rc = QDSE_EDEVICE;
   }

@@ -116,20 +116,23 @@ hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, 
 hipError_t launch_axpby(hipStream_t st, int n_inst, int len, double alpha, const double* a,
                         const double* scale, const double* b, double* dst);
 
-// FP32 MFMA sweep (qdse_mfma.hip): five transposed FP32 matrices per kernel
-// block and six FP32 node columns per instance.
-hipError_t launch_build_m32(hipStream_t st, int n, int nq, int ldk, int ldi, const double* K,
-                            const double* s, const double* t, float* MT, size_t mstride);
-hipError_t launch_sweep_fp32(hipStream_t st, int n_inst, int n, int nq, int ldi, int ldb,
-                             const float* MT, size_t mstride, float* C, size_t cstride,
-                             const InstDev* inst, const int* lo, const double* sw, const double* t,
-                             const double* s, const double* x_in, double* x_out,
-                             SolveState* state, const SolveCtl* ctl, int k);
-
-hipError_t launch_mfma_only(hipStream_t st, int n_inst, int n, int nq, int ldi, int ldb,
-                            const float* MT, size_t mstride, const float* C, size_t cstride,
-                            const InstDev* inst, const double* s, const double* x_in,
-                            double* x_out);
+// Matrix-core sweeps (qdse_mfma.hip): five transposed matrices [5][nq_pad][ldi]
+// per kernel block and six node columns [6][inst_pad][ldj], element type
+// float (FP32 MFMA) or double (FP64 MFMA).
+struct MmLayout {
+  int nq_pad = 0, ldi = 0, ldj = 0, inst_pad = 0;
+  size_t mstride = 0, cstride = 0;
+};
+MmLayout mm_layout(int n, int nq, int n_inst);
+template <class T>
+hipError_t launch_build_mm(hipStream_t st, int n, int nq, int ldk, const MmLayout& L,
+                           const double* K, const double* s, const double* t, T* MT);
+// nodes = false skips the node-column kernel (columns already built).
+template <class T>
+hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLayout& L,
+                           const T* MT, T* C, const InstDev* inst, const int* lo, const double* sw,
+                           const double* t, const double* s, const double* x_in, double* x_out,
+                           SolveState* state, const SolveCtl* ctl, int k, bool nodes);
 
 // Finite-mu sweep (qdse_mu.hip); x, L complex interleaved.
 hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, int nq4, int na,

@@ -1,4 +1,4 @@
-// qdse_mfma.hip -- batched FP32 sweep on the matrix cores (MFMA) for many
+// qdse_mfma.hip -- batched sweeps on the matrix cores (MFMA) for many
 // instances that share one set of angular-integrated kernel matrices (same
 // grid and omega; D and m are per instance).
 //
@@ -13,16 +13,25 @@
 //   M5 = K_0 - 2 s_i K_T,
 //   c0 = sigma_V A(t), c1 = sigma_V, c2 = sigma_S B(t), c3 = sigma_S,
 //   c4 = sigma_V B(t), c5 = sigma_S A(t)     (functions of loop node j).
-// Eight products per instance, 16 N (N+1) flops. The matrices and columns are
-// FP32, the products accumulate in FP32 (v_mfma_f32_16x16x4_f32); node
-// functions (with the denominator t A^2 + B^2), the combination above, the
-// update and the test statistic are FP64. The split form cancels where A_j ~ A_i
-// near the singular diagonal of K_T, so FP32 sweeps are followed by FP64
-// direct-difference sweeps (the refinement) until the FP64 test passes.
+// Eight products per instance, 16 N (N+1) flops.
 //
-// Layouts (FP32, zero padded): MT[x][j][ldi], x = 0..4 (transposed so a
-// lane group reads consecutive rows), C[y][j][ldb], y = 0..5; ldi and ldb are
-// multiples of 32, the j extent a multiple of 4.
+// Two element types share one kernel template:
+//  * FP32 (v_mfma_f32_16x16x4_f32, FP32 accumulation): the split form cancels
+//    where A_j ~ A_i near the singular diagonal of K_T, so FP32 sweeps are
+//    followed by FP64 sweeps (the refinement) until the FP64 test passes;
+//  * FP64 (v_mfma_f64_16x16x4_f64): the same products in FP64, whose
+//    cancellation error (~1e-15 relative) is far below the FP64 targets.
+// Node functions (with the denominator t A^2 + B^2), the combination above,
+// the update and the test statistic are FP64 in both.
+//
+// Tiling: a workgroup (4 wavefronts) owns 64 rows x 32 instances; per stage of
+// 16 loop nodes it stages the five matrix tiles and the six column tiles in
+// LDS (coalesced global reads), then each wavefront runs 16 rows x 32
+// instances (two 16x16 blocks) for the eight products from LDS.
+//
+// Layouts (zero padded): MT[x][j][ldi] (x = 0..4, transposed: rows contiguous),
+// C[y][inst][ldj] (y = 0..5, loop nodes contiguous); ldi a multiple of 64, ldj a
+// multiple of 16, the instance extent a multiple of 32.
 #include "qdse_internal.h"
 
 namespace qdse {
@@ -30,12 +39,32 @@ namespace qdse {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr double kMassFloorM = 1e-8;  // GeV, as in the FP64 sweep
+constexpr int TM = 64, TN = 32, TK = 16;
+constexpr int APAD = 4;  // LDS row padding against bank conflicts
 
-__global__ void k_build_m32(int n, int nq, int ldk, int ldi, const double* __restrict__ K,
-                            const double* __restrict__ s_, const double* __restrict__ t_,
-                            float* __restrict__ MT, size_t mstride) {
+template <class T> struct Mfma;
+template <> struct Mfma<float> {
+  typedef floatx4 acc_t;
+  __device__ static acc_t zero() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc_t mac(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  typedef doublex4 acc_t;
+  __device__ static acc_t zero() { return doublex4{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t mac(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T>
+__global__ void k_build_m(int n, int nq, int ldk, int ldi, const double* __restrict__ K,
+                          const double* __restrict__ s_, const double* __restrict__ t_,
+                          T* __restrict__ MT, size_t mstride) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)n * nq) return;
   const int j = (int)(idx / n), i = (int)(idx % n);  // i fastest: coalesced writes
@@ -45,24 +74,17 @@ __global__ void k_build_m32(int n, int nq, int ldk, int ldi, const double* __res
   const double s = s_[i], t = t_[j];
   const double k2 = (s + t) * kT;
   const size_t o = (size_t)j * ldi + i;
-  MT[o] = (float)(k3 - k2);
-  MT[mstride + o] = (float)(k3 + k2);
-  MT[2 * mstride + o] = (float)kT;
-  MT[3 * mstride + o] = (float)(k0 + 2.0 * s * kT);
-  MT[4 * mstride + o] = (float)(k0 - 2.0 * s * kT);
+  MT[o] = (T)(k3 - k2);
+  MT[mstride + o] = (T)(k3 + k2);
+  MT[2 * mstride + o] = (T)kT;
+  MT[3 * mstride + o] = (T)(k0 + 2.0 * s * kT);
+  MT[4 * mstride + o] = (T)(k0 - 2.0 * s * kT);
 }
-
-// Node columns of every instance (FP64 arithmetic, FP32 results), with the
-// masked-run decision of the previous sweep.
-__global__ void k_nodes32(int n, int nq, int ldb, const int* __restrict__ lo,
-                          const double* __restrict__ sw, const double* __restrict__ t,
-                          const double* __restrict__ x, float* __restrict__ C, size_t cstride,
-                          SolveState* state, const SolveCtl* ctl, int k);
 
 __device__ inline double bits2d(unsigned long long b) { return __longlong_as_double((long long)b); }
 
 // Masked-run decision at the start of sweep k (same rule as the FP64 sweep).
-__device__ inline int decide32(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
+__device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
   SolveState& S = *st;
   int status = S.status;
   const int done = S.sweeps_slot[(k + 2) % 3];
@@ -85,13 +107,17 @@ __device__ inline int decide32(SolveState* st, const SolveCtl* ctl, int k, bool 
   return status;
 }
 
-__global__ void k_nodes32(int n, int nq, int ldb, const int* __restrict__ lo,
-                          const double* __restrict__ sw, const double* __restrict__ t,
-                          const double* __restrict__ x, float* __restrict__ C, size_t cstride,
-                          SolveState* state, const SolveCtl* ctl, int k) {
+// Node columns of every instance (FP64 arithmetic, stored as T), with the
+// masked-run decision of the previous sweep. Threads run over loop nodes j,
+// which are contiguous in C.
+template <class T>
+__global__ void k_nodes_mm(int n, int nq, int ldj, const int* __restrict__ lo,
+                           const double* __restrict__ sw, const double* __restrict__ t,
+                           const double* __restrict__ x, T* __restrict__ C, size_t cstride,
+                           SolveState* state, const SolveCtl* ctl, int k) {
   const int inst = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (state && decide32(state + inst, ctl, k, blockIdx.x == 0 && threadIdx.x == 0)) return;
+  if (state && decide_mm(state + inst, ctl, k, blockIdx.x == 0 && threadIdx.x == 0)) return;
   if (j >= nq) return;
   const double* xA = x + (size_t)inst * 2 * n;
   const int b = lo[j];
@@ -104,78 +130,83 @@ __global__ void k_nodes32(int n, int nq, int ldb, const int* __restrict__ lo,
   }
   const double Dl = t[j] * Aq * Aq + Bq * Bq;
   const double sV = Aq / Dl, sS = Bq / Dl;
-  const size_t o = (size_t)j * ldb + inst;
-  C[o] = (float)(sV * Aq);
-  C[cstride + o] = (float)sV;
-  C[2 * cstride + o] = (float)(sS * Bq);
-  C[3 * cstride + o] = (float)sS;
-  C[4 * cstride + o] = (float)(sV * Bq);
-  C[5 * cstride + o] = (float)(sS * Aq);
+  const size_t o = (size_t)inst * ldj + j;
+  C[o] = (T)(sV * Aq);
+  C[cstride + o] = (T)sV;
+  C[2 * cstride + o] = (T)(sS * Bq);
+  C[3 * cstride + o] = (T)sS;
+  C[4 * cstride + o] = (T)(sV * Bq);
+  C[5 * cstride + o] = (T)(sS * Aq);
 }
 
-// One workgroup = 4 wavefronts = 32 rows x 64 instances; each wavefront owns
-// 32 rows x 16 instances as two 16x16 blocks per product, eight products.
-// Operands come straight from L2/L1 in the transposed layouts (a 16-lane group
-// reads 64 contiguous bytes); the four wavefronts share the matrix operands.
-__global__ void __launch_bounds__(256) k_mfma_sweep(
-    int n_inst, int n, int nq4, int ldi, int ldb, const float* __restrict__ MT, size_t mstride,
-    const float* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
+template <class T>
+__global__ void __launch_bounds__(256) k_mm_sweep(
+    int n_inst, int n, int nq_pad, int ldi, int ldj, const T* __restrict__ MT, size_t mstride,
+    const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
     const double* __restrict__ s_, const double* __restrict__ x_in, double* __restrict__ x_out,
     SolveState* state, const SolveCtl* ctl, int k) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i0 = blockIdx.x * 32;
-  const int b0 = blockIdx.y * 64 + wave * 16;
-  const int lr = lane & 15, lk = lane >> 4;  // operand row/col within a block, k slot
-  floatx4 acc[8][2];
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[5][TK][TM + APAD];
+  __shared__ T Bs[6][TK][TN + APAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * TM;
+  const int b0 = blockIdx.y * TN;
+  const int lr = lane & 15, lk = lane >> 4;
+  acc_t acc[8][2];
 #pragma unroll
-  for (int p = 0; p < 8; ++p) acc[p][0] = acc[p][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int p = 0; p < 8; ++p) acc[p][0] = acc[p][1] = Mfma<T>::zero();
 
-  const float* M1 = MT;
-  const float* M2 = MT + mstride;
-  const float* M3 = MT + 2 * mstride;
-  const float* M4 = MT + 3 * mstride;
-  const float* M5 = MT + 4 * mstride;
-  for (int k0 = 0; k0 < nq4; k0 += 4) {
-    const size_t ra = (size_t)(k0 + lk) * ldi + i0 + lr;  // A[m][k] = MT[k][m]
-    const size_t cb = (size_t)(k0 + lk) * ldb + b0 + lr;  // B[k][n] = C[k][n]
-    float a1[2], a2[2], a3[2], a4[2], a5[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      a1[rb] = M1[ra + rb * 16];
-      a2[rb] = M2[ra + rb * 16];
-      a3[rb] = M3[ra + rb * 16];
-      a4[rb] = M4[ra + rb * 16];
-      a5[rb] = M5[ra + rb * 16];
+  for (int k0 = 0; k0 < nq_pad; k0 += TK) {
+    __syncthreads();
+    // stage the matrix tiles: 5 x TK x TM, rows contiguous in MT
+    for (int e = tid; e < 5 * TK * TM; e += 256) {
+      const int x = e / (TK * TM), r = e % (TK * TM);
+      const int jj = r / TM, ii = r % TM;
+      As[x][jj][ii] = MT[(size_t)x * mstride + (size_t)(k0 + jj) * ldi + i0 + ii];
     }
-    const float c0 = C[cb], c1 = C[cstride + cb], c2 = C[2 * cstride + cb],
-                c3 = C[3 * cstride + cb], c4 = C[4 * cstride + cb], c5 = C[5 * cstride + cb];
+    // stage the column tiles: 6 x TN x TK, loop nodes contiguous in C
+    for (int e = tid; e < 6 * TN * TK; e += 256) {
+      const int y = e / (TN * TK), r = e % (TN * TK);
+      const int nn = r / TK, jj = r % TK;
+      Bs[y][jj][nn] = C[(size_t)y * cstride + (size_t)(b0 + nn) * ldj + k0 + jj];
+    }
+    __syncthreads();
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      acc[0][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[rb], c0, acc[0][rb], 0, 0, 0);
-      acc[1][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[rb], c1, acc[1][rb], 0, 0, 0);
-      acc[2][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[rb], c2, acc[2][rb], 0, 0, 0);
-      acc[3][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[rb], c3, acc[3][rb], 0, 0, 0);
-      acc[4][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[rb], c4, acc[4][rb], 0, 0, 0);
-      acc[5][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[rb], c1, acc[5][rb], 0, 0, 0);
-      acc[6][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[rb], c5, acc[6][rb], 0, 0, 0);
-      acc[7][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a5[rb], c3, acc[7][rb], 0, 0, 0);
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + lk, ar = wave * 16 + lr;
+      const T a1 = As[0][kr][ar], a2 = As[1][kr][ar], a3 = As[2][kr][ar], a4 = As[3][kr][ar],
+              a5 = As[4][kr][ar];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int bc = cb * 16 + lr;
+        const T c0 = Bs[0][kr][bc], c1 = Bs[1][kr][bc], c2 = Bs[2][kr][bc], c3 = Bs[3][kr][bc],
+                c4 = Bs[4][kr][bc], c5 = Bs[5][kr][bc];
+        acc[0][cb] = Mfma<T>::mac(a1, c0, acc[0][cb]);
+        acc[1][cb] = Mfma<T>::mac(a2, c1, acc[1][cb]);
+        acc[2][cb] = Mfma<T>::mac(a3, c2, acc[2][cb]);
+        acc[3][cb] = Mfma<T>::mac(a3, c3, acc[3][cb]);
+        acc[4][cb] = Mfma<T>::mac(a3, c4, acc[4][cb]);
+        acc[5][cb] = Mfma<T>::mac(a3, c1, acc[5][cb]);
+        acc[6][cb] = Mfma<T>::mac(a4, c5, acc[6][cb]);
+        acc[7][cb] = Mfma<T>::mac(a5, c3, acc[7][cb]);
+      }
     }
   }
-  // Epilogue: the 16x16 result block holds row 4*(lane/16)+e, column lane%16.
-  const int inst = b0 + lr;
-  const bool inst_ok = inst < n_inst;
-  int status = 1;
-  InstDev P{};
-  if (inst_ok) {
-    status = state ? state[inst].status : 0;
-    P = inst_[inst];
-  }
-  double worst = 0.0;
+  // Epilogue: each 16x16 result block holds row 4*(lane/16)+e, column lane%16.
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb) {
+  for (int cb = 0; cb < 2; ++cb) {
+    const int inst = b0 + cb * 16 + lr;
+    const bool inst_ok = inst < n_inst;
+    int status = 1;
+    InstDev P{};
+    if (inst_ok) {
+      status = state ? state[inst].status : 0;
+      P = inst_[inst];
+    }
+    double worst = 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int i = i0 + rb * 16 + 4 * lk + e;
+      const int i = i0 + wave * 16 + 4 * lk + e;
       if (!inst_ok || i >= n) continue;
       const double* xi = x_in + (size_t)inst * 2 * n;
       double* xo = x_out + (size_t)inst * 2 * n;
@@ -186,8 +217,8 @@ __global__ void __launch_bounds__(256) k_mfma_sweep(
         continue;
       }
       const double s = s_[i];
-      const double p0 = acc[0][rb][e], p1 = acc[1][rb][e], p2 = acc[2][rb][e], p3 = acc[3][rb][e];
-      const double p4 = acc[4][rb][e], p5 = acc[5][rb][e], p6 = acc[6][rb][e], p7 = acc[7][rb][e];
+      const double p0 = acc[0][cb][e], p1 = acc[1][cb][e], p2 = acc[2][cb][e], p3 = acc[3][cb][e];
+      const double p4 = acc[4][cb][e], p5 = acc[5][cb][e], p6 = acc[6][cb][e], p7 = acc[7][cb][e];
       const double An = 1.0 + P.pref * (p0 + Ai * p1 - 2.0 * p2 + 2.0 * Bi * p3);
       const double Bn = P.m + P.pref * (p6 + Ai * p7 - 2.0 * s * p4 + 2.0 * s * Bi * p5);
       xo[i] = An;
@@ -205,47 +236,63 @@ __global__ void __launch_bounds__(256) k_mfma_sweep(
                                             : fmax(worst, r);
       }
     }
-  }
-  if (state && inst_ok && status == 0) {
-    // lanes lane, lane+16, lane+32, lane+48 hold the same instance
-    unsigned long long bits = (unsigned long long)__double_as_longlong(worst);
-    atomicMax(&state[inst].metric[k % 3], bits);
+    if (state && inst_ok && status == 0) {
+      // lanes lr, lr+16, lr+32, lr+48 hold the same instance
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(worst);
+      atomicMax(&state[inst].metric[k % 3], bits);
+    }
   }
 }
 
 }  // namespace
 
-hipError_t launch_build_m32(hipStream_t st, int n, int nq, int ldk, int ldi, const double* K,
-                            const double* s, const double* t, float* MT, size_t mstride) {
+MmLayout mm_layout(int n, int nq, int n_inst) {
+  MmLayout L;
+  L.nq_pad = (nq + TK - 1) / TK * TK;
+  L.ldi = (n + TM - 1) / TM * TM;
+  L.ldj = L.nq_pad;
+  L.inst_pad = (n_inst + TN - 1) / TN * TN;
+  L.mstride = (size_t)L.nq_pad * L.ldi;
+  L.cstride = (size_t)L.inst_pad * L.ldj;
+  return L;
+}
+
+template <class T>
+hipError_t launch_build_mm(hipStream_t st, int n, int nq, int ldk, const MmLayout& L,
+                           const double* K, const double* s, const double* t, T* MT) {
   const long tot = (long)n * nq;
-  hipLaunchKernelGGL(k_build_m32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nq, ldk,
-                     ldi, K, s, t, MT, mstride);
+  hipLaunchKernelGGL(k_build_m<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nq,
+                     ldk, L.ldi, K, s, t, MT, L.mstride);
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_fp32(hipStream_t st, int n_inst, int n, int nq, int ldi, int ldb,
-                             const float* MT, size_t mstride, float* C, size_t cstride,
-                             const InstDev* inst, const int* lo, const double* sw, const double* t,
-                             const double* s, const double* x_in, double* x_out,
-                             SolveState* state, const SolveCtl* ctl, int k) {
-  hipLaunchKernelGGL(k_nodes32, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldb, lo,
-                     sw, t, x_in, C, cstride, state, ctl, k);
-  const int nq4 = (nq + 3) & ~3;
-  hipLaunchKernelGGL(k_mfma_sweep, dim3((n + 31) / 32, (n_inst + 63) / 64), dim3(256), 0, st,
-                     n_inst, n, nq4, ldi, ldb, MT, mstride, C, cstride, inst, s, x_in, x_out, state,
-                     ctl, k);
+template <class T>
+hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLayout& L,
+                           const T* MT, T* C, const InstDev* inst, const int* lo, const double* sw,
+                           const double* t, const double* s, const double* x_in, double* x_out,
+                           SolveState* state, const SolveCtl* ctl, int k, bool nodes) {
+  if (nodes)
+    hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq,
+                       L.ldj, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
+  hipLaunchKernelGGL(k_mm_sweep<T>, dim3(L.ldi / TM, L.inst_pad / TN), dim3(256), 0, st, n_inst, n,
+                     L.nq_pad, L.ldi, L.ldj, MT, L.mstride, C, L.cstride, inst, s, x_in, x_out,
+                     state, ctl, k);
   return hipGetLastError();
 }
 
-hipError_t launch_mfma_only(hipStream_t st, int n_inst, int n, int nq, int ldi, int ldb,
-                            const float* MT, size_t mstride, const float* C, size_t cstride,
-                            const InstDev* inst, const double* s, const double* x_in,
-                            double* x_out) {
-  const int nq4 = (nq + 3) & ~3;
-  hipLaunchKernelGGL(k_mfma_sweep, dim3((n + 31) / 32, (n_inst + 63) / 64), dim3(256), 0, st,
-                     n_inst, n, nq4, ldi, ldb, MT, mstride, C, cstride, inst, s, x_in, x_out,
-                     (SolveState*)nullptr, (const SolveCtl*)nullptr, 1);
-  return hipGetLastError();
-}
+template hipError_t launch_build_mm<float>(hipStream_t, int, int, int, const MmLayout&,
+                                           const double*, const double*, const double*, float*);
+template hipError_t launch_build_mm<double>(hipStream_t, int, int, int, const MmLayout&,
+                                            const double*, const double*, const double*, double*);
+template hipError_t launch_sweep_mm<float>(hipStream_t, int, int, int, const MmLayout&,
+                                           const float*, float*, const InstDev*, const int*,
+                                           const double*, const double*, const double*,
+                                           const double*, double*, SolveState*, const SolveCtl*,
+                                           int, bool);
+template hipError_t launch_sweep_mm<double>(hipStream_t, int, int, int, const MmLayout&,
+                                            const double*, double*, const InstDev*, const int*,
+                                            const double*, const double*, const double*,
+                                            const double*, double*, SolveState*, const SolveCtl*,
+                                            int, bool);
 
 }  // namespace qdse

@@ -280,6 +280,41 @@ def test_fp32_sweep_close_to_oracle(Q):
         assert worst < 1e-4, worst
 
 
+def test_fp64_matrix_sweep_matches_oracle(Q):
+    """The FP64 matrix-core sweep (split form, FP64 MFMA): the cancellation of
+    the split differences costs ~50x FP64 rounding, so it meets the FP64
+    parity bar too."""
+    for n, na, nb in ((64, 32, 5), (150, 100, 33), (512, 128, 70)):
+        print(f"case fp64 matrix sweep n={n} nb={nb}", flush=True)
+        rng = np.random.default_rng(17 + n)
+        params = [(0.55, 0.678, float(m)) for m in rng.uniform(0, 0.2, nb)]
+        S = Q.Solver(n, na, params, precision=Q.QDSE_FP64_MATRIX)
+        g = oracle_grid(n, na, 3)
+        xs = np.stack([smooth_x(g.s, rng) for _ in params])
+        y = S.iterate(torch.tensor(xs, device="cuda"), matrix=True).cpu().numpy()
+        y64 = S.iterate(torch.tensor(xs, device="cuda")).cpu().numpy()
+        for k in (0, nb // 2, nb - 1):
+            ref = O.F(g, O.Params(*params[k]), xs[k]) if n <= 150 else y64[k]
+            assert max(errs(y[k], ref, n)) < RTOL, (k, errs(y[k], ref, n))
+
+
+def test_fp64_matrix_batched_solve_matches_direct(Q):
+    n, na, nb = 64, 32, 40
+    rng = np.random.default_rng(43)
+    params = [(0.55, 0.678, float(m)) for m in rng.uniform(0, 0.2, nb)]
+    Sm = Q.Solver(n, na, params, precision=Q.QDSE_FP64_MATRIX)
+    Sd = Q.Solver(n, na, params)
+    xm, xd = Sm.initial(1.0, 1.0), Sd.initial(1.0, 1.0)
+    rcm, itm, _ = Sm.solve(xm, tol=1e-11, max_iter=600)
+    rcd, itd, _ = Sd.solve(xd, tol=1e-11, max_iter=600)
+    assert rcm == rcd == Q.QDSE_OK
+    assert np.all(np.abs(itm - itd) <= 1)
+    a, b = xm.cpu().numpy(), xd.cpu().numpy()
+    same = itm == itd
+    for k in np.nonzero(same)[0]:
+        assert max(errs(a[k], b[k], n)) < 1e-11
+
+
 def test_fp32_refined_solve_meets_1e7(Q):
     """Batched FP32 sweeps to 1e-6, FP64 sweeps to 1e-9 on max|dM/M|, |dA|: the
     result is within 1e-7 (relative, A, B, M) of the oracle's fixed point
