@@ -117,10 +117,10 @@ hipError_t launch_axpby(hipStream_t st, int n_inst, int len, double alpha, const
                         const double* scale, const double* b, double* dst);
 
 // Matrix-core sweeps (qdse_mfma.hip): five transposed matrices [5][nq_pad][ldi]
-// per kernel block and six node columns [6][inst_pad][ldj], element type
-// float (FP32 MFMA) or double (FP64 MFMA).
+// per kernel block and six node columns [6][nq_pad][ldb], element type float
+// (FP32 MFMA) or double (FP64 MFMA).
 struct MmLayout {
-  int nq_pad = 0, ldi = 0, ldj = 0, inst_pad = 0;
+  int nq_pad = 0, ldi = 0, ldb = 0;
   size_t mstride = 0, cstride = 0;
 };
 MmLayout mm_layout(int n, int nq, int n_inst);

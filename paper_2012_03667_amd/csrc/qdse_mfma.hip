@@ -24,14 +24,16 @@
 // Node functions (with the denominator t A^2 + B^2), the combination above,
 // the update and the test statistic are FP64 in both.
 //
-// Tiling: a workgroup (4 wavefronts) owns 64 rows x 32 instances; per stage of
-// 16 loop nodes it stages the five matrix tiles and the six column tiles in
-// LDS (coalesced global reads), then each wavefront runs 16 rows x 32
-// instances (two 16x16 blocks) for the eight products from LDS.
+// Tiling: a workgroup of two wavefronts owns 32 rows (FP32; 16 rows for FP64,
+// whose accumulators are twice as wide) x 32 instances in blocks of 16 x 16,
+// eight products each; the two wavefronts split the loop
+// nodes in halves and their partial products are added through LDS before
+// the FP64 epilogue. Operands are read straight from L2/L1 in layouts where a
+// 16-lane group reads contiguous memory, with the next k-step prefetched.
 //
-// Layouts (zero padded): MT[x][j][ldi] (x = 0..4, transposed: rows contiguous),
-// C[y][inst][ldj] (y = 0..5, loop nodes contiguous); ldi a multiple of 64, ldj a
-// multiple of 16, the instance extent a multiple of 32.
+// Layouts (zero padded): MT[x][j][ldi] (x = 0..4, rows contiguous),
+// C[y][j][ldb] (y = 0..5, instances contiguous); ldi and ldb multiples of 32,
+// the loop-node extent nq_pad a multiple of 8.
 #include "qdse_internal.h"
 
 namespace qdse {
@@ -42,12 +44,15 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr double kMassFloorM = 1e-8;  // GeV, as in the FP64 sweep
-constexpr int TM = 64, TN = 32, TK = 16;
-constexpr int APAD = 4;  // LDS row padding against bank conflicts
+constexpr int TM_MAX = 32, TN = 32, KSPLIT = 2, KSTEP = 4;
 
 template <class T> struct Mfma;
+// Output layout of one 16x16 block: register e of lane l holds row
+// row(l / 16, e), column l % 16 (FP32: 4 (l/16) + e; FP64: l/16 + 4 e).
 template <> struct Mfma<float> {
   typedef floatx4 acc_t;
+  static constexpr int RB = 2;  // 16-row blocks per wavefront
+  __device__ static int row(int g, int e) { return 4 * g + e; }
   __device__ static acc_t zero() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
   __device__ static acc_t mac(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -55,6 +60,8 @@ template <> struct Mfma<float> {
 };
 template <> struct Mfma<double> {
   typedef doublex4 acc_t;
+  static constexpr int RB = 1;
+  __device__ static int row(int g, int e) { return g + 4 * e; }
   __device__ static acc_t zero() { return doublex4{0.0, 0.0, 0.0, 0.0}; }
   __device__ static acc_t mac(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -108,91 +115,145 @@ __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool
 }
 
 // Node columns of every instance (FP64 arithmetic, stored as T), with the
-// masked-run decision of the previous sweep. Threads run over loop nodes j,
-// which are contiguous in C.
+// masked-run decision of the previous sweep. A block covers 32 loop nodes x
+// 32 instances: threads compute with j fastest (the interpolation stencils
+// read the iterate contiguously), the six columns pass through LDS, and the
+// stores run with the instance index fastest (contiguous in C).
 template <class T>
-__global__ void k_nodes_mm(int n, int nq, int ldj, const int* __restrict__ lo,
-                           const double* __restrict__ sw, const double* __restrict__ t,
-                           const double* __restrict__ x, T* __restrict__ C, size_t cstride,
-                           SolveState* state, const SolveCtl* ctl, int k) {
-  const int inst = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (state && decide_mm(state + inst, ctl, k, blockIdx.x == 0 && threadIdx.x == 0)) return;
-  if (j >= nq) return;
-  const double* xA = x + (size_t)inst * 2 * n;
-  const int b = lo[j];
-  const double* w = sw + 4 * j;
-  double Aq = 0.0, Bq = 0.0;
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    Aq = fma(w[l], xA[b + l], Aq);
-    Bq = fma(w[l], xA[n + b + l], Bq);
+__global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int ldb,
+                                                  const int* __restrict__ lo,
+                                                  const double* __restrict__ sw,
+                                                  const double* __restrict__ t,
+                                                  const double* __restrict__ x,
+                                                  T* __restrict__ C, size_t cstride,
+                                                  SolveState* state, const SolveCtl* ctl, int k) {
+  __shared__ T tile[6][32][33];
+  __shared__ int frozen[32];
+  const int j0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
+  const int tid = threadIdx.x;
+  if (tid < 32) {
+    const int inst = b0 + tid;
+    int st = 1;
+    if (inst < n_inst)
+      st = state ? decide_mm(state + inst, ctl, k, blockIdx.x == 0) : 0;
+    frozen[tid] = st;
   }
-  const double Dl = t[j] * Aq * Aq + Bq * Bq;
-  const double sV = Aq / Dl, sS = Bq / Dl;
-  const size_t o = (size_t)inst * ldj + j;
-  C[o] = (T)(sV * Aq);
-  C[cstride + o] = (T)sV;
-  C[2 * cstride + o] = (T)(sS * Bq);
-  C[3 * cstride + o] = (T)sS;
-  C[4 * cstride + o] = (T)(sV * Bq);
-  C[5 * cstride + o] = (T)(sS * Aq);
+  __syncthreads();
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int jj = e % 32, bb = e / 32;
+    const int j = j0 + jj, inst = b0 + bb;
+    if (j >= nq || inst >= n_inst || frozen[bb]) continue;
+    const double* xA = x + (size_t)inst * 2 * n;
+    const int b = lo[j];
+    const double* w = sw + 4 * j;
+    double Aq = 0.0, Bq = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      Aq = fma(w[l], xA[b + l], Aq);
+      Bq = fma(w[l], xA[n + b + l], Bq);
+    }
+    const double Dl = t[j] * Aq * Aq + Bq * Bq;
+    const double sV = Aq / Dl, sS = Bq / Dl;
+    tile[0][bb][jj] = (T)(sV * Aq);
+    tile[1][bb][jj] = (T)sV;
+    tile[2][bb][jj] = (T)(sS * Bq);
+    tile[3][bb][jj] = (T)sS;
+    tile[4][bb][jj] = (T)(sV * Bq);
+    tile[5][bb][jj] = (T)(sS * Aq);
+  }
+  __syncthreads();
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int bb = e % 32, jj = e / 32;
+    const int j = j0 + jj, inst = b0 + bb;
+    if (j >= nq || inst >= n_inst || frozen[bb]) continue;
+    const size_t o = (size_t)j * ldb + inst;
+#pragma unroll
+    for (int y = 0; y < 6; ++y) C[(size_t)y * cstride + o] = tile[y][bb][jj];
+  }
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_mm_sweep(
-    int n_inst, int n, int nq_pad, int ldi, int ldj, const T* __restrict__ MT, size_t mstride,
+__global__ void __launch_bounds__(128) k_mm_sweep(
+    int n_inst, int n, int nq_pad, int ldi, int ldb, const T* __restrict__ MT, size_t mstride,
     const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
     const double* __restrict__ s_, const double* __restrict__ x_in, double* __restrict__ x_out,
     SolveState* state, const SolveCtl* ctl, int k) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[5][TK][TM + APAD];
-  __shared__ T Bs[6][TK][TN + APAD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int i0 = blockIdx.x * TM;
-  const int b0 = blockIdx.y * TN;
+  constexpr int RB = Mfma<T>::RB, TM = 16 * RB;
+  __shared__ acc_t part[8][RB][2][64];  // second wavefront's partial products
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * TM, b0 = blockIdx.y * TN;
   const int lr = lane & 15, lk = lane >> 4;
-  acc_t acc[8][2];
+  const int half = nq_pad / KSPLIT;  // a multiple of KSTEP
+  const int kb = wave * half, ke = kb + half;
+  acc_t acc[8][RB][2];
 #pragma unroll
-  for (int p = 0; p < 8; ++p) acc[p][0] = acc[p][1] = Mfma<T>::zero();
-
-  for (int k0 = 0; k0 < nq_pad; k0 += TK) {
-    __syncthreads();
-    // stage the matrix tiles: 5 x TK x TM, rows contiguous in MT
-    for (int e = tid; e < 5 * TK * TM; e += 256) {
-      const int x = e / (TK * TM), r = e % (TK * TM);
-      const int jj = r / TM, ii = r % TM;
-      As[x][jj][ii] = MT[(size_t)x * mstride + (size_t)(k0 + jj) * ldi + i0 + ii];
-    }
-    // stage the column tiles: 6 x TN x TK, loop nodes contiguous in C
-    for (int e = tid; e < 6 * TN * TK; e += 256) {
-      const int y = e / (TN * TK), r = e % (TN * TK);
-      const int nn = r / TK, jj = r % TK;
-      Bs[y][jj][nn] = C[(size_t)y * cstride + (size_t)(b0 + nn) * ldj + k0 + jj];
-    }
-    __syncthreads();
+  for (int p = 0; p < 8; ++p)
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      const int kr = kk + lk, ar = wave * 16 + lr;
-      const T a1 = As[0][kr][ar], a2 = As[1][kr][ar], a3 = As[2][kr][ar], a4 = As[3][kr][ar],
-              a5 = As[4][kr][ar];
+    for (int r = 0; r < RB; ++r) acc[p][r][0] = acc[p][r][1] = Mfma<T>::zero();
+  const T* M1 = MT;
+  const T* M2 = MT + mstride;
+  const T* M3 = MT + 2 * mstride;
+  const T* M4 = MT + 3 * mstride;
+  const T* M5 = MT + 4 * mstride;
+  T a[5][RB], c[6][2], an[5][RB], cn[6][2];
+  auto load = [&](int k0, T (&A)[5][RB], T (&B)[6][2]) {
+    const size_t ra = (size_t)(k0 + lk) * ldi + i0 + lr;  // A[m][k] = MT[k][m]
+    const size_t rc = (size_t)(k0 + lk) * ldb + b0 + lr;  // B[k][n] = C[k][n]
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      A[0][r] = M1[ra + 16 * r];
+      A[1][r] = M2[ra + 16 * r];
+      A[2][r] = M3[ra + 16 * r];
+      A[3][r] = M4[ra + 16 * r];
+      A[4][r] = M5[ra + 16 * r];
+    }
+#pragma unroll
+    for (int y = 0; y < 6; ++y)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) B[y][cb] = C[(size_t)y * cstride + rc + 16 * cb];
+  };
+  load(kb, a, c);
+  for (int k0 = kb; k0 < ke; k0 += KSTEP) {
+    if (k0 + KSTEP < ke) load(k0 + KSTEP, an, cn);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
-        const int bc = cb * 16 + lr;
-        const T c0 = Bs[0][kr][bc], c1 = Bs[1][kr][bc], c2 = Bs[2][kr][bc], c3 = Bs[3][kr][bc],
-                c4 = Bs[4][kr][bc], c5 = Bs[5][kr][bc];
-        acc[0][cb] = Mfma<T>::mac(a1, c0, acc[0][cb]);
-        acc[1][cb] = Mfma<T>::mac(a2, c1, acc[1][cb]);
-        acc[2][cb] = Mfma<T>::mac(a3, c2, acc[2][cb]);
-        acc[3][cb] = Mfma<T>::mac(a3, c3, acc[3][cb]);
-        acc[4][cb] = Mfma<T>::mac(a3, c4, acc[4][cb]);
-        acc[5][cb] = Mfma<T>::mac(a3, c1, acc[5][cb]);
-        acc[6][cb] = Mfma<T>::mac(a4, c5, acc[6][cb]);
-        acc[7][cb] = Mfma<T>::mac(a5, c3, acc[7][cb]);
+        acc[0][r][cb] = Mfma<T>::mac(a[0][r], c[0][cb], acc[0][r][cb]);
+        acc[1][r][cb] = Mfma<T>::mac(a[1][r], c[1][cb], acc[1][r][cb]);
+        acc[2][r][cb] = Mfma<T>::mac(a[2][r], c[2][cb], acc[2][r][cb]);
+        acc[3][r][cb] = Mfma<T>::mac(a[2][r], c[3][cb], acc[3][r][cb]);
+        acc[4][r][cb] = Mfma<T>::mac(a[2][r], c[4][cb], acc[4][r][cb]);
+        acc[5][r][cb] = Mfma<T>::mac(a[2][r], c[1][cb], acc[5][r][cb]);
+        acc[6][r][cb] = Mfma<T>::mac(a[3][r], c[5][cb], acc[6][r][cb]);
+        acc[7][r][cb] = Mfma<T>::mac(a[4][r], c[3][cb], acc[7][r][cb]);
       }
-    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) a[q][r] = an[q][r];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c[q][0] = cn[q][0], c[q][1] = cn[q][1];
   }
-  // Epilogue: each 16x16 result block holds row 4*(lane/16)+e, column lane%16.
+  // add the second half's partial products (fixed order: half 0 + half 1)
+  if (wave == 1) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) part[p][r][cb][lane] = acc[p][r][cb];
+  }
+  __syncthreads();
+  if (wave == 1) return;
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[p][r][cb] += part[p][r][cb][lane];
+  // Epilogue (FP64)
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) {
     const int inst = b0 + cb * 16 + lr;
@@ -205,35 +266,39 @@ __global__ void __launch_bounds__(256) k_mm_sweep(
     }
     double worst = 0.0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int i = i0 + wave * 16 + 4 * lk + e;
-      if (!inst_ok || i >= n) continue;
-      const double* xi = x_in + (size_t)inst * 2 * n;
-      double* xo = x_out + (size_t)inst * 2 * n;
-      const double Ai = xi[i], Bi = xi[n + i];
-      if (status != 0) {
-        xo[i] = Ai;
-        xo[n + i] = Bi;
-        continue;
-      }
-      const double s = s_[i];
-      const double p0 = acc[0][cb][e], p1 = acc[1][cb][e], p2 = acc[2][cb][e], p3 = acc[3][cb][e];
-      const double p4 = acc[4][cb][e], p5 = acc[5][cb][e], p6 = acc[6][cb][e], p7 = acc[7][cb][e];
-      const double An = 1.0 + P.pref * (p0 + Ai * p1 - 2.0 * p2 + 2.0 * Bi * p3);
-      const double Bn = P.m + P.pref * (p6 + Ai * p7 - 2.0 * s * p4 + 2.0 * s * Bi * p5);
-      xo[i] = An;
-      xo[n + i] = Bn;
-      if (state) {
-        double r;
-        const double dA = fabs(An - Ai);
-        if (ctl->mode == QDSE_CONV_ABS) {
-          r = fmax(dA, fabs(Bn - Bi));
-        } else {
-          const double Mn = Bn / An, Mo = Bi / Ai;
-          r = fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloorM));
+    for (int r = 0; r < RB; ++r) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 16 * r + Mfma<T>::row(lk, e);
+        if (!inst_ok || i >= n) continue;
+        const double* xi = x_in + (size_t)inst * 2 * n;
+        double* xo = x_out + (size_t)inst * 2 * n;
+        const double Ai = xi[i], Bi = xi[n + i];
+        if (status != 0) {
+          xo[i] = Ai;
+          xo[n + i] = Bi;
+          continue;
         }
-        worst = (isnan(r) || isnan(worst)) ? __longlong_as_double(0x7ff8000000000000ll)
-                                            : fmax(worst, r);
+        const double s = s_[i];
+        const double p0 = acc[0][r][cb][e], p1 = acc[1][r][cb][e], p2 = acc[2][r][cb][e],
+                     p3 = acc[3][r][cb][e], p4 = acc[4][r][cb][e], p5 = acc[5][r][cb][e],
+                     p6 = acc[6][r][cb][e], p7 = acc[7][r][cb][e];
+        const double An = 1.0 + P.pref * (p0 + Ai * p1 - 2.0 * p2 + 2.0 * Bi * p3);
+        const double Bn = P.m + P.pref * (p6 + Ai * p7 - 2.0 * s * p4 + 2.0 * s * Bi * p5);
+        xo[i] = An;
+        xo[n + i] = Bn;
+        if (state) {
+          double rr;
+          const double dA = fabs(An - Ai);
+          if (ctl->mode == QDSE_CONV_ABS) {
+            rr = fmax(dA, fabs(Bn - Bi));
+          } else {
+            const double Mn = Bn / An, Mo = Bi / Ai;
+            rr = fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloorM));
+          }
+          worst = (isnan(rr) || isnan(worst)) ? __longlong_as_double(0x7ff8000000000000ll)
+                                              : fmax(worst, rr);
+        }
       }
     }
     if (state && inst_ok && status == 0) {
@@ -248,12 +313,11 @@ __global__ void __launch_bounds__(256) k_mm_sweep(
 
 MmLayout mm_layout(int n, int nq, int n_inst) {
   MmLayout L;
-  L.nq_pad = (nq + TK - 1) / TK * TK;
-  L.ldi = (n + TM - 1) / TM * TM;
-  L.ldj = L.nq_pad;
-  L.inst_pad = (n_inst + TN - 1) / TN * TN;
+  L.nq_pad = (nq + KSPLIT * KSTEP - 1) / (KSPLIT * KSTEP) * (KSPLIT * KSTEP);
+  L.ldi = (n + TM_MAX - 1) / TM_MAX * TM_MAX;
+  L.ldb = (n_inst + TN - 1) / TN * TN;
   L.mstride = (size_t)L.nq_pad * L.ldi;
-  L.cstride = (size_t)L.inst_pad * L.ldj;
+  L.cstride = (size_t)L.nq_pad * L.ldb;
   return L;
 }
 
@@ -272,11 +336,11 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
                            const double* t, const double* s, const double* x_in, double* x_out,
                            SolveState* state, const SolveCtl* ctl, int k, bool nodes) {
   if (nodes)
-    hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq,
-                       L.ldj, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
-  hipLaunchKernelGGL(k_mm_sweep<T>, dim3(L.ldi / TM, L.inst_pad / TN), dim3(256), 0, st, n_inst, n,
-                     L.nq_pad, L.ldi, L.ldj, MT, L.mstride, C, L.cstride, inst, s, x_in, x_out,
-                     state, ctl, k);
+    hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
+                       n, nq, L.ldb, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
+  hipLaunchKernelGGL(k_mm_sweep<T>, dim3(L.ldi / (16 * Mfma<T>::RB), L.ldb / TN), dim3(64 * KSPLIT), 0, st,
+                     n_inst, n, L.nq_pad, L.ldi, L.ldb, MT, L.mstride, C, L.cstride, inst, s, x_in,
+                     x_out, state, ctl, k);
   return hipGetLastError();
 }
 
