@@ -4,6 +4,7 @@
 // (I - J)^T lambda = g with device-side Gram-Schmidt).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -79,9 +80,14 @@ struct qdse_ctx {
   double* d_xbuf[2] = {nullptr, nullptr};
   SolveState* d_state = nullptr;
   SolveCtl* d_ctl = nullptr;
-  // graph of a chunk of masked sweeps
+  // graph of a chunk of masked sweeps; pinned copies of the solve state of
+  // the last two chunks, with their completion events
   hipGraphExec_t graph_exec = nullptr;
-  int graph_chunk = 0;
+  int chunk = 12;       // sweeps per graph launch (multiple of 6)
+  int pipeline = 1;     // chunks in flight beyond the one whose state is read
+  int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
+  SolveState* h_state = nullptr;  // [2][n_inst], hipHostMalloc
+  hipEvent_t ev[2] = {nullptr, nullptr};
   // persistent solve: per-sweep statistics, grid-barrier counter, flags
   unsigned long long* d_slots = nullptr;
   unsigned int* d_barrier = nullptr;
@@ -205,8 +211,34 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   TRY(dalloc(&c->d_state, (size_t)n_inst));
   TRY(dalloc(&c->d_ctl, 1));
   TRY(dalloc(&c->d_slots, (size_t)3 * n_inst));
-  TRY(dalloc(&c->d_barrier, 1));
+  TRY(dalloc(&c->d_barrier, persistent_barrier_words()));
   TRY(dalloc(&c->d_flags, 2));
+  if (hipHostMalloc((void**)&c->h_state, 2 * (size_t)n_inst * sizeof(SolveState),
+                    hipHostMallocDefault) != hipSuccess) {
+    c->h_state = nullptr;
+    g_last_error = "hipHostMalloc failed";
+    qdse_destroy(c);
+    return QDSE_ENOMEM;
+  }
+  for (int q = 0; q < 2; ++q)
+    if (hipEventCreateWithFlags(&c->ev[q], hipEventDisableTiming) != hipSuccess) {
+      c->ev[q] = nullptr;
+      g_last_error = "hipEventCreate failed";
+      qdse_destroy(c);
+      return QDSE_EDEVICE;
+    }
+  // Launch shape of the FP64 sweep: fewer rows per workgroup when the batch
+  // would otherwise leave compute units idle.
+  c->fused_rows = (long)n_inst * ((g.n + 7) / 8) < 512 ? 4 : 8;
+  if (const char* e = std::getenv("QDSE_FUSED_ROWS")) {
+    const int r = std::atoi(e);
+    if (r == 4 || r == 8 || r == 16) c->fused_rows = r;
+  }
+  if (const char* e = std::getenv("QDSE_CHUNK")) {
+    const int ch = std::atoi(e);
+    if (ch >= 6 && ch <= 120 && ch % 6 == 0) c->chunk = ch;
+  }
+  if (const char* e = std::getenv("QDSE_PIPELINE")) c->pipeline = std::atoi(e) != 0;
   for (int b = 0; b < c->n_blocks; ++b) {
     hipError_t e = launch_precompute(st, g.n, g.nq, g.na, g.ldk, c->d_s, c->d_t, c->d_W, c->d_z,
                                      c->d_wz, c->block_omega[b], 0, c->d_K + b * c->kstride,
@@ -250,21 +282,25 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
 #undef TRY
   // Persistent single-launch solve: every instance must share kernel block 0
   // and all workgroups must be co-resident. Rows per workgroup: the smallest
-  // count whose grid fits (or QDSE_PERSIST_RPW).
+  // count (from one row set per compute unit) whose grid fits, or
+  // QDSE_PERSIST_RPW.
   if (c->n_blocks == 1 && n_inst <= 64) {
-    int rpw0 = 4, rpw1 = 8;
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    int rpw0 = std::max(1, (g.n + ncu - 1) / ncu), rpw1 = 8;
     if (const char* e = std::getenv("QDSE_PERSIST_RPW")) rpw0 = rpw1 = std::atoi(e);
     int dev_lds = 65536;
     (void)hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     for (int rpw = rpw0; rpw <= rpw1 && c->persist_G == 0; ++rpw) {
       if (rpw < 1) break;
-      // node functions of as many instances as fit next to the matrix rows
+      // iterate and node functions of as many instances as fit next to the
+      // matrix rows
       const long left = (long)dev_lds - 4096 - (long)rpw * 3 * g.nq * 8;
-      int gsz = (int)(left / ((long)4 * g.nq * 8));
+      int gsz = (int)(left / ((long)(2 * g.n + 4 * g.nq) * 8));
       if (gsz < 1) continue;
       if (gsz > n_inst) gsz = n_inst;
       int maxb = 0;
-      if (persistent_max_blocks(rpw, g.nq, gsz, &maxb) != hipSuccess) break;
+      if (persistent_max_blocks(rpw, g.n, g.nq, gsz, &maxb) != hipSuccess) break;
       const int G = (g.n + rpw - 1) / rpw;
       if (G <= maxb) {
         c->persist_G = G;
@@ -289,6 +325,9 @@ void qdse_destroy(qdse_ctx* c) {
   if (c->graph32_exec) (void)hipGraphExecDestroy(c->graph32_exec);
   if (c->graphmm_exec) (void)hipGraphExecDestroy(c->graphmm_exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (hipEvent_t e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->h_state) (void)hipHostFree(c->h_state);
   void* ptrs[] = {c->d_s,       c->d_t,       c->d_W,       c->d_z,     c->d_wz,
                   c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_M32,
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
@@ -338,7 +377,7 @@ int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
   const HostGrid& g = c->hg;
   HIPCHK(launch_sweep_fused(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
                             c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out, nullptr, nullptr, 1,
-                            1));
+                            1, c->fused_rows));
   return QDSE_OK;
 }
 
@@ -382,17 +421,21 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
     } else {
       HIPCHK(launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
                                 c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_state, c->d_ctl,
-                                k, 1));
+                                k, 1, c->fused_rows));
     }
   }
   return QDSE_OK;
 }
 
 // Masked sweeps from xbuf[0] until every instance is frozen; the iterate ends
-// in xbuf[0]. hs receives the final per-instance state.
+// in xbuf[0]. hs receives the final per-instance state. Each graph launch runs
+// c->chunk sweeps and is followed by an asynchronous copy of the state into
+// pinned memory; with pipelining the next chunk is queued before the host
+// reads the previous copy, so the device never waits for the host (the extra
+// chunk after convergence consists of masked sweeps that leave x unchanged).
 static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int kind,
                       std::vector<SolveState>& hs, bool* all_done) {
-  const int chunk = 12;  // multiple of 6: ends in xbuf[0] with the slot cycle intact
+  const int chunk = c->chunk;  // multiple of 6: ends in xbuf[0] with the slot cycle intact
   const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
   hipStream_t st = c->stream;
   SolveCtl ctl{tol, conv_mode, max_iter};
@@ -413,9 +456,17 @@ static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int 
     (void)hipGraphDestroy(graph);
     HIPCHK(e);
   }
-  hs.assign(c->n_inst, SolveState{});
+  const int nI = c->n_inst;
+  const size_t bytes = (size_t)nI * sizeof(SolveState);
+  auto done_in = [&](int slot) {
+    const SolveState* h = c->h_state + (size_t)slot * nI;
+    for (int q = 0; q < nI; ++q)
+      if (h[q].status == 0) return false;
+    return true;
+  };
   long launched = 0;
   const long limit = (long)max_iter + 1 + chunk;
+  int cur = 0, last = -1;
   *all_done = false;
   while (launched < limit) {
     if (use_graph) {
@@ -425,14 +476,21 @@ static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int 
       if (rc) return rc;
     }
     launched += chunk;
-    HIPCHK(hipMemcpyAsync(hs.data(), c->d_state, hs.size() * sizeof(SolveState),
+    HIPCHK(hipMemcpyAsync(c->h_state + (size_t)cur * nI, c->d_state, bytes,
                           hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    *all_done = true;
-    for (const SolveState& s : hs)
-      if (s.status == 0) *all_done = false;
-    if (*all_done) break;
+    HIPCHK(hipEventRecord(c->ev[cur], st));
+    // state to inspect: the previous chunk's when pipelining, else this one's
+    const int probe = c->pipeline ? last : cur;
+    last = cur;
+    cur ^= 1;
+    if (probe < 0) continue;
+    HIPCHK(hipEventSynchronize(c->ev[probe]));
+    if (done_in(probe)) break;
   }
+  HIPCHK(hipStreamSynchronize(st));
+  // the newest copy is final (masked sweeps leave a frozen state unchanged)
+  hs.assign(c->h_state + (size_t)last * nI, c->h_state + (size_t)last * nI + nI);
+  *all_done = last >= 0 && done_in(last);
   return QDSE_OK;
 }
 
@@ -788,7 +846,8 @@ int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin
   for (;; ++it) {
     // residual R = F(x) - x, max-norm per instance
     HIPCHK(launch_sweep_fused(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
-                              c->d_sw, c->d_t, c->d_s, d_x, d_F, nullptr, nullptr, 1, 1));
+                              c->d_sw, c->d_t, c->d_s, d_x, d_F, nullptr, nullptr, 1, 1,
+                              c->fused_rows));
     HIPCHK(launch_axpby(st, nI, len, -1.0, d_x, nullptr, d_F, d_F));
     HIPCHK(hipMemcpyAsync(h.data(), d_F, L * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -856,7 +915,7 @@ int qdse_time_contraction(qdse_ctx* c, int which, const double* d_x, double* d_o
                                                  c->d_s, d_x, d_out, nullptr, nullptr, 1, false)
                        : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
                                             c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x,
-                                            d_out, nullptr, nullptr, 1, 1);
+                                            d_out, nullptr, nullptr, 1, 1, c->fused_rows);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], st);
     if (e != hipSuccess) rc = QDSE_EDEVICE;
   }

@@ -89,7 +89,7 @@ hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk
                               const InstDev* inst, const double* K, size_t kstride, const int* lo,
                               const double* sw, const double* t, const double* s,
                               const double* x_in, double* x_out, SolveState* state,
-                              const SolveCtl* ctl, int k, int add_f0);
+                              const SolveCtl* ctl, int k, int add_f0, int rows);
 hipError_t launch_contraction_only(hipStream_t st, int n_inst, int n, int nq, int ldk,
                                   const InstDev* inst, const double* K, size_t kstride,
                                   const double* s, const double* x_in, double* x_out,
@@ -145,8 +145,9 @@ hipError_t launch_mu_stat(hipStream_t st, int n_inst, int ne, const double* x_ol
                           const double* x_new, unsigned long long* stat);
 
 // Persistent (cooperative) solve of a few instances sharing kernel block 0.
-size_t persistent_lds_bytes(int rpw, int nq, int gsz);
-hipError_t persistent_max_blocks(int rpw, int nq, int gsz, int* max_blocks);
+size_t persistent_lds_bytes(int rpw, int n, int nq, int gsz);
+size_t persistent_barrier_words();
+hipError_t persistent_max_blocks(int rpw, int n, int nq, int gsz, int* max_blocks);
 hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const InstDev* inst, const double* K, const int* lo,
                              const double* sw, const double* t, const double* s, double* xbuf0,

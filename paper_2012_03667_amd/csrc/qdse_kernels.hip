@@ -359,12 +359,12 @@ __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ld
   }
 }
 
-// Fused sweep: one workgroup = (instance, 8 consecutive rows); the node
+// Fused sweep: one workgroup = (instance, ROWS consecutive rows); the node
 // functions of the instance are rebuilt in LDS by every workgroup (O(N) work
-// against O(8 N) for the rows), then each wavefront contracts two rows with
-// exactly the per-row arithmetic of k_sweep.
-constexpr int FUSED_ROWS = 8;
-
+// against O(ROWS N) for the rows), then each wavefront contracts ROWS / 4 rows
+// with exactly the per-row arithmetic of k_sweep. Fewer rows per workgroup
+// spread a small batch over more compute units.
+template <int ROWS>
 __global__ void __launch_bounds__(256) k_sweep_fused(
     int n_inst, int n, int nq, int ldk, const InstDev* __restrict__ inst_,
     const double* __restrict__ K, size_t kstride, const int* __restrict__ lo,
@@ -376,9 +376,9 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
   const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const double* xi = x_in + (size_t)inst * 2 * n;
   double* xo = x_out + (size_t)inst * 2 * n;
-  const int r0 = blockIdx.x * FUSED_ROWS;
+  const int r0 = blockIdx.x * ROWS;
   if (state && decide(state + inst, ctl, k, blockIdx.x == 0)) {  // frozen: carry along
-    for (int r = threadIdx.x; r < FUSED_ROWS; r += blockDim.x) {
+    for (int r = threadIdx.x; r < ROWS; r += blockDim.x) {
       const int i = r0 + r;
       if (i < n) {
         xo[i] = xi[i];
@@ -396,8 +396,8 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
   __syncthreads();
   const InstDev P = inst_[inst];
   const size_t mat = (size_t)n * ldk;
-  for (int rr = 0; rr < FUSED_ROWS / 4; ++rr) {
-    const int i = r0 + wave * (FUSED_ROWS / 4) + rr;
+  for (int rr = 0; rr < ROWS / 4; ++rr) {
+    const int i = r0 + wave * (ROWS / 4) + rr;
     if (i >= n) break;
     const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
     const double s = s_[i];
@@ -667,11 +667,12 @@ hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk
                               const InstDev* inst, const double* K, size_t kstride, const int* lo,
                               const double* sw, const double* t, const double* s,
                               const double* x_in, double* x_out, SolveState* state,
-                              const SolveCtl* ctl, int k, int add_f0) {
+                              const SolveCtl* ctl, int k, int add_f0, int rows) {
   const size_t lds = (size_t)5 * ldk * sizeof(double);
-  hipLaunchKernelGGL(k_sweep_fused, dim3((n + FUSED_ROWS - 1) / FUSED_ROWS, n_inst), dim3(256),
-                     lds, st, n_inst, n, nq, ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out,
-                     state, ctl, k, add_f0);
+  if (rows != 4 && rows != 8 && rows != 16) return hipErrorInvalidValue;
+  auto kern = rows == 4 ? k_sweep_fused<4> : rows == 8 ? k_sweep_fused<8> : k_sweep_fused<16>;
+  hipLaunchKernelGGL(kern, dim3((n + rows - 1) / rows, n_inst), dim3(256), lds, st, n_inst, n, nq,
+                     ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out, state, ctl, k, add_f0);
   return hipGetLastError();
 }
 

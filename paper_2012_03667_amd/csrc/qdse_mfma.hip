@@ -181,8 +181,24 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int RB = Mfma<T>::RB, TM = 16 * RB;
   __shared__ acc_t part[8][RB][2][64];  // second wavefront's partial products
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i0 = blockIdx.x * TM, b0 = blockIdx.y * TN;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop
+  // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs
+  // (workgroup w to XCD w % 8). When the instance blocks divide evenly, XCD x
+  // owns the instance blocks ib = x (mod 8) and walks their row blocks, so a
+  // node-column panel is fetched into one XCD's L2 and reused from there.
+  const int n_rb = ldi / TM, n_ib = ldb / TN;
+  const int w = blockIdx.x;
+  int rb, ib;
+  if (n_ib % 8 == 0) {
+    const int xcd = w % 8, kth = w / 8;
+    ib = (kth / n_rb) * 8 + xcd;
+    rb = kth % n_rb;
+  } else {
+    rb = w % n_rb;
+    ib = w / n_rb;
+  }
+  const int i0 = rb * TM, b0 = ib * TN;
   const int lr = lane & 15, lk = lane >> 4;
   const int half = nq_pad / KSPLIT;  // a multiple of KSTEP
   const int kb = wave * half, ke = kb + half;
@@ -213,22 +229,27 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) B[y][cb] = C[(size_t)y * cstride + rc + 16 * cb];
   };
-  load(kb, a, c);
-  for (int k0 = kb; k0 < ke; k0 += KSTEP) {
-    if (k0 + KSTEP < ke) load(k0 + KSTEP, an, cn);
+  auto mma = [&](const T (&A)[5][RB], const T (&B)[6][2]) {
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
-        acc[0][r][cb] = Mfma<T>::mac(a[0][r], c[0][cb], acc[0][r][cb]);
-        acc[1][r][cb] = Mfma<T>::mac(a[1][r], c[1][cb], acc[1][r][cb]);
-        acc[2][r][cb] = Mfma<T>::mac(a[2][r], c[2][cb], acc[2][r][cb]);
-        acc[3][r][cb] = Mfma<T>::mac(a[2][r], c[3][cb], acc[3][r][cb]);
-        acc[4][r][cb] = Mfma<T>::mac(a[2][r], c[4][cb], acc[4][r][cb]);
-        acc[5][r][cb] = Mfma<T>::mac(a[2][r], c[1][cb], acc[5][r][cb]);
-        acc[6][r][cb] = Mfma<T>::mac(a[3][r], c[5][cb], acc[6][r][cb]);
-        acc[7][r][cb] = Mfma<T>::mac(a[4][r], c[3][cb], acc[7][r][cb]);
+        acc[0][r][cb] = Mfma<T>::mac(A[0][r], B[0][cb], acc[0][r][cb]);
+        acc[1][r][cb] = Mfma<T>::mac(A[1][r], B[1][cb], acc[1][r][cb]);
+        acc[2][r][cb] = Mfma<T>::mac(A[2][r], B[2][cb], acc[2][r][cb]);
+        acc[3][r][cb] = Mfma<T>::mac(A[2][r], B[3][cb], acc[3][r][cb]);
+        acc[4][r][cb] = Mfma<T>::mac(A[2][r], B[4][cb], acc[4][r][cb]);
+        acc[5][r][cb] = Mfma<T>::mac(A[2][r], B[1][cb], acc[5][r][cb]);
+        acc[6][r][cb] = Mfma<T>::mac(A[3][r], B[5][cb], acc[6][r][cb]);
+        acc[7][r][cb] = Mfma<T>::mac(A[4][r], B[3][cb], acc[7][r][cb]);
       }
+  };
+  // software pipeline: the operands of step k0 + KSTEP load while step k0
+  // runs; the last step is peeled so the loop body has no branch
+  load(kb, a, c);
+  for (int k0 = kb; k0 + KSTEP < ke; k0 += KSTEP) {
+    load(k0 + KSTEP, an, cn);
+    mma(a, c);
 #pragma unroll
     for (int q = 0; q < 5; ++q)
 #pragma unroll
@@ -236,6 +257,7 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
 #pragma unroll
     for (int q = 0; q < 6; ++q) c[q][0] = cn[q][0], c[q][1] = cn[q][1];
   }
+  mma(a, c);
   // add the second half's partial products (fixed order: half 0 + half 1)
   if (wave == 1) {
 #pragma unroll
@@ -338,7 +360,7 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
   if (nodes)
     hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
                        n, nq, L.ldb, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
-  hipLaunchKernelGGL(k_mm_sweep<T>, dim3(L.ldi / (16 * Mfma<T>::RB), L.ldb / TN), dim3(64 * KSPLIT), 0, st,
+  hipLaunchKernelGGL(k_mm_sweep<T>, dim3((L.ldi / (16 * Mfma<T>::RB)) * (L.ldb / TN)), dim3(64 * KSPLIT), 0, st,
                      n_inst, n, L.nq_pad, L.ldi, L.ldb, MT, L.mstride, C, L.cstride, inst, s, x_in,
                      x_out, state, ctl, k);
   return hipGetLastError();

@@ -9,12 +9,21 @@
 // those i in LDS for the whole solve, and per sweep
 //   1. decides from the previous sweep's global test statistics which
 //      instances are frozen (all workgroups decide identically),
-//   2. rebuilds the loop-node functions of each running instance in LDS from
-//      the current iterate (redundantly per workgroup: O(N) work),
+//   2. copies the current iterate of a group of instances into LDS (coalesced
+//      coherent loads) and rebuilds their loop-node functions there
+//      (redundantly per workgroup: O(N) work),
 //   3. contracts its rows against them (FP64 direct-difference form, the same
 //      arithmetic as k_sweep) and writes the new iterate rows,
 //   4. folds its rows' test statistics into a per-instance global maximum,
 //   5. meets the other workgroups at a grid barrier.
+// Iterate and statistics travel through coherent (agent-scope) atomic loads,
+// stores and read-modify-writes, which reach the level shared by all L2
+// caches; a workgroup arrives at the barrier only after every one of its
+// memory operations has been acknowledged (s_waitcnt 0), so no cache
+// write-back or invalidation is needed. Arrivals are spread over NCTR
+// counters on separate cache lines (workgroup g adds to counter g % NCTR),
+// and wavefront 0 polls all of them at once. A plain variant (ordinary
+// accesses, release on arrival, acquire after the wait) is kept for checks.
 // The barrier wait is bounded: a workgroup that waits too long raises an error
 // flag and every workgroup leaves the loop, so the grid always drains.
 #include "qdse_internal.h"
@@ -28,6 +37,8 @@ constexpr int PWAVES = PBLOCK / 64;
 constexpr int MAX_RPW = 8;           // rows per workgroup held in LDS
 constexpr long SPIN_LIMIT = 1l << 24;  // ~0.5 s of polling before giving up
 constexpr double kMassFloorP = 1e-8;   // GeV, as in the kernel-per-sweep path
+constexpr int NCTR = 8;                // arrival counters
+constexpr int CTR_STRIDE = 32;         // unsigned ints between counters (128 bytes)
 
 __device__ inline double wsum(double v) {
 #pragma unroll
@@ -47,31 +58,55 @@ __device__ inline unsigned long long stat_bits(double r) {
   return (unsigned long long)__double_as_longlong(r);
 }
 
-// Grid-wide barrier number k (1-based) on a monotonically increasing counter.
-// Returns false if the wait timed out or another workgroup raised the flag.
-__device__ bool grid_sync(unsigned int* ctr, unsigned int target, int* err, bool coherent_data) {
+// Grid-wide barrier number k (1-based) on NCTR monotonically increasing
+// counters. Returns false if the wait timed out or another workgroup raised
+// the error flag.
+__device__ bool grid_sync(unsigned int* ctr, int G, unsigned int k, int* err,
+                          bool coherent_data) {
   __shared__ int ok;
+  if (coherent_data) __builtin_amdgcn_s_waitcnt(0);  // this thread's accesses acknowledged
   __syncthreads();
-  if (threadIdx.x == 0) {
-    ok = 1;
-    // release: this workgroup's iterate rows and statistics before the arrival
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+      ok = 1;
+      unsigned int* mine = ctr + (blockIdx.x % NCTR) * CTR_STRIDE;
+      if (coherent_data)
+        __hip_atomic_fetch_add(mine, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else  // release: this workgroup's plain stores before the arrival
+        __hip_atomic_fetch_add(mine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // arrivals expected on counter `lane`: k times the workgroups g < G with
+    // g % NCTR == lane
+    const unsigned int target =
+        lane < NCTR ? k * (unsigned int)((G - lane + NCTR - 1) / NCTR) : 0u;
     long spins = 0;
-    // poll without ordering (no cache invalidation per poll), then one acquire
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        ok = 0;
-        break;
+    bool good = true;
+    for (;;) {
+      bool reached = true;
+      if (lane < NCTR)
+        reached = __hip_atomic_load(ctr + lane * CTR_STRIDE, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) >= target;
+      if (__all(reached)) break;
+      int bad = 0;
+      if (lane == 0) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) bad = 1;
+        if (++spins > SPIN_LIMIT) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+        }
       }
-      if (++spins > SPIN_LIMIT) {
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
+      if (__shfl(bad, 0, 64)) {
+        good = false;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    if (!coherent_data)  // agent-wide acquire: other workgroups' plain stores
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (lane == 0) {
+      if (!good) ok = 0;
+      if (!coherent_data)  // agent-wide acquire: other workgroups' plain stores
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
   }
   __syncthreads();
   return ok != 0;
@@ -114,8 +149,9 @@ struct PArgs {
 __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   extern __shared__ double lds[];
   const int n = a.n, nq = a.nq, rpw = a.rpw, G = a.G, g = blockIdx.x;
-  double* Kl = lds;                        // [rpw][3][nq]
-  double* nd = Kl + (size_t)rpw * 3 * nq;  // [4][nq] node functions of one instance
+  double* Kl = lds;                            // [rpw][3][nq]
+  double* xs = Kl + (size_t)rpw * 3 * nq;      // [gsz][2n] iterate of a group
+  double* nd = xs + (size_t)a.gsz * 2 * n;     // [gsz][4][nq] node functions
   __shared__ int st_status[64];
   __shared__ int st_sweeps[64];
   __shared__ double st_resid[64];
@@ -179,19 +215,25 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
 
     for (int q0 = 0; q0 < a.n_inst; q0 += a.gsz) {
       const int q1 = min(a.n_inst, q0 + a.gsz);
-      // 2. node functions of the running instances q0..q1-1 into LDS, one pass
+      // 2. iterate of the group into LDS, then the node functions of its
+      //    running instances
+      for (int e = tid; e < (q1 - q0) * 2 * n; e += PBLOCK) {
+        const int q = q0 + e / (2 * n);
+        if (st_status[q] == 0) xs[e] = ld_x(xc + (size_t)q0 * 2 * n + e, a.coherent);
+      }
+      __syncthreads();
 #pragma unroll 4
       for (int e = tid; e < (q1 - q0) * nq; e += PBLOCK) {
         const int q = q0 + e / nq, j = e % nq;
         if (st_status[q] != 0) continue;
-        const double* xq = xc + (size_t)q * 2 * n;
+        const double* xq = xs + (size_t)(q - q0) * 2 * n;
         const int b = a.lo[j];
         const double* w = a.sw + 4 * j;
         double Aq = 0.0, Bq = 0.0;
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-          Aq = fma(w[l], ld_x(xq + b + l, a.coherent), Aq);
-          Bq = fma(w[l], ld_x(xq + n + b + l, a.coherent), Bq);
+          Aq = fma(w[l], xq[b + l], Aq);
+          Bq = fma(w[l], xq[n + b + l], Bq);
         }
         const double tj = a.t[j];
         const double Dl = tj * Aq * Aq + Bq * Bq;
@@ -214,6 +256,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
           continue;
         }
         const double* ndq = nd + (size_t)(q - q0) * 4 * nq;
+        const double* xsq = xs + (size_t)(q - q0) * 2 * n;
         if (tid == 0) wgmax = 0ull;
         // 3. contraction of this workgroup's rows
         const InstDev P = a.inst[q];
@@ -224,8 +267,8 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
           acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
           if (r < nrows) {
             const int i = g + r * G;
-            Ai[r] = ld_x(xq + i, a.coherent);
-            Bi[r] = ld_x(xq + n + i, a.coherent);
+            Ai[r] = xsq[i];
+            Bi[r] = xsq[n + i];
             si[r] = a.s[i];
           }
         }
@@ -281,7 +324,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       __syncthreads();
     }
     // 5. grid barrier k
-    if (!grid_sync(a.barrier, (unsigned int)(G * k), a.flags, a.coherent != 0)) {
+    if (!grid_sync(a.barrier, G, (unsigned int)k, a.flags, a.coherent != 0)) {
       fine = false;
       break;
     }
@@ -300,8 +343,8 @@ __global__ void k_persistent_reset(unsigned long long* slots, int nslots, unsign
                                    int* flags) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nslots) slots[t] = 0ull;
+  if (t < NCTR) barrier[t * CTR_STRIDE] = 0u;
   if (t == 0) {
-    *barrier = 0u;
     flags[0] = 0;
     flags[1] = 0;
   }
@@ -309,9 +352,11 @@ __global__ void k_persistent_reset(unsigned long long* slots, int nslots, unsign
 
 }  // namespace
 
-size_t persistent_lds_bytes(int rpw, int nq, int gsz) {
-  return ((size_t)rpw * 3 * nq + (size_t)4 * nq * gsz) * sizeof(double);
+size_t persistent_lds_bytes(int rpw, int n, int nq, int gsz) {
+  return ((size_t)rpw * 3 * nq + (size_t)gsz * (2 * n + 4 * nq)) * sizeof(double);
 }
+
+size_t persistent_barrier_words() { return (size_t)NCTR * CTR_STRIDE; }
 
 // Launches the persistent solve; G workgroups, each holding rpw rows. The
 // caller has checked that every instance uses kernel block 0, that G
@@ -329,7 +374,7 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
   if (e != hipSuccess) return e;
   PArgs a{n_inst, n, nq, rpw, G, gsz, coherent, inst, K, ldk, lo, sw, t, s, xbuf0, xbuf1, state,
           ctl, slots, barrier, flags};
-  const size_t lds = persistent_lds_bytes(rpw, nq, gsz);
+  const size_t lds = persistent_lds_bytes(rpw, n, nq, gsz);
   e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds);
   if (e != hipSuccess) return e;
@@ -337,13 +382,13 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
   return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(G), dim3(PBLOCK), args, lds, st);
 }
 
-hipError_t persistent_max_blocks(int rpw, int nq, int gsz, int* max_blocks) {
+hipError_t persistent_max_blocks(int rpw, int n, int nq, int gsz, int* max_blocks) {
   int dev = 0, ncu = 0, occ = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = persistent_lds_bytes(rpw, nq, gsz);
+  const size_t lds = persistent_lds_bytes(rpw, n, nq, gsz);
   e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds);
   if (e != hipSuccess) return e;
