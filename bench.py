@@ -32,6 +32,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
+COPY_BYTES = 1 << 30
+
+
+def counter_traffic(summary, source):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (profiles/*.md: lines 'fetch_bytes_per_dispatch:', 'write_bytes_per_dispatch:'
+    already scaled by the copy-kernel calibration, and 'source_sha256:' of the
+    kernel's source file when the counters were taken). None when the summary
+    is missing or the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_2012_03667_amd", "csrc", source)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    vals = {}
+    for ln in open(path):
+        if ":" in ln and ln.split(":", 1)[0].strip() in (
+                "fetch_bytes_per_dispatch", "write_bytes_per_dispatch", "source_sha256"):
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if len(vals) != 3:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != vals["source_sha256"]:
+        return None
+    return float(vals["fetch_bytes_per_dispatch"]) + float(vals["write_bytes_per_dispatch"])
 
 
 def main():
@@ -44,7 +70,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 256 MiB device copy (reference for HBM byte counters)")
+                    help="also run one cold 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -123,7 +149,8 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_sweep_fused (FP64 sweep, 2 instances)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": counter_traffic("k_sweep_fused_512x128_2inst.md", "qdse_kernels.hip"),
             "avg_kernel_us": avg_ms * 1e3, "alg_bytes_per_launch": alg_bytes,
         },
     }
@@ -176,7 +203,9 @@ def main():
         line["roofline_fp32"] = {
             "bound": "mfma", "kernel": "k_mm_sweep<float> (FP32 contraction, batch)",
             "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": tf / FP32_MFMA_PEAK_TFLOPS, "traffic": None, "avg_kernel_us": ms32 * 1e3,
+            "frac": tf / FP32_MFMA_PEAK_TFLOPS,
+            "traffic": counter_traffic("k_mm_sweep_fp32_512x128_1024inst.md", "qdse_mfma.hip"),
+            "avg_kernel_us": ms32 * 1e3,
             "alg_flops_per_launch": flops}
         ms64 = S64.time_contraction(x64, reps=20)
         line["batched"]["fp64_direct_sweep_kernel_us"] = ms64 * 1e3
@@ -184,8 +213,9 @@ def main():
         line["batched"]["fp64_mfma_contraction_kernel_us"] = ms_mm64 * 1e3
         line["roofline_fp64_mfma"] = {
             "bound": "mfma", "kernel": "k_mm_sweep<double> (FP64 contraction, batch)",
-            "achieved": flops / (ms_mm64 * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-            "frac": flops / (ms_mm64 * 1e-3) / 1e12 / 78.6, "traffic": None,
+            "achieved": flops / (ms_mm64 * 1e-3) / 1e12, "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": flops / (ms_mm64 * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "traffic": counter_traffic("k_mm_sweep_fp64_512x128_1024inst.md", "qdse_mfma.hip"),
             "avg_kernel_us": ms_mm64 * 1e3, "alg_flops_per_launch": flops}
         del S32, S64
         batch_x0 = a64[0]
@@ -193,10 +223,16 @@ def main():
         batch_x0 = None
 
     if args.copy_calibration:
-        a = torch.empty(256 * 2 ** 20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        # source written first, then 1 GiB of other data, so that the copy reads
+        # its source from HBM (the 256 MB Infinity Cache holds at most the tail
+        # of the second buffer)
+        a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        evict = torch.empty_like(a).fill_(2.0)
         b = torch.empty_like(a)
+        torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b, evict
 
     if not args.no_cpu_baseline:
         from oracle import qdse_oracle as O

@@ -185,13 +185,17 @@ int qdse_grad(qdse_ctx* ctx, const double* d_xstar, const double* d_g, double to
 int qdse_kernel_matrices(qdse_ctx* ctx, int inst, double* d_K);
 
 /* Diagnostics: average device duration in milliseconds of one sweep kernel at
- * d_x over `reps` launches on the context's stream, each bracketed by its own
- * pair of HIP events. which = 0: the fused FP64 sweep kernel (node functions
- * and the O(N^2) contraction in one launch); 1: the FP32 matrix-core
- * contraction kernel alone; 2: the FP64 matrix-core contraction kernel alone
- * (node columns are built once before; 1 and 2 need a context with the
- * matrix-core data, else QDSE_ENOTSUP). d_out [n_inst][2N] receives the sweep.
- * Synchronises the stream. */
+ * d_x over `reps` launches on the context's stream; each launch carries a
+ * start and a stop HIP event on its own dispatch packet, so the figure is the
+ * kernel's execution time without launch gaps. The kernels run exactly as in
+ * a solve (masked-run decision, per-instance test statistics) against a
+ * private solve state whose tolerance is never met. which = 0: the fused FP64
+ * sweep kernel (node functions and the O(N^2) contraction in one launch);
+ * 1: the FP32 matrix-core contraction kernel alone; 2: the FP64 matrix-core
+ * contraction kernel alone (node columns are built once before; 1 and 2 need
+ * a context with the matrix-core data, else QDSE_ENOTSUP). d_out [n_inst][2N]
+ * receives the sweep. Allocates the private state on first use; synchronises
+ * the stream. */
 int qdse_time_contraction(qdse_ctx* ctx, int which, const double* d_x, double* d_out, int reps,
                           double* avg_ms);
 

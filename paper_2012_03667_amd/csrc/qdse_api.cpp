@@ -83,8 +83,9 @@ struct qdse_ctx {
   // graph of a chunk of masked sweeps; pinned copies of the solve state of
   // the last two chunks, with their completion events
   hipGraphExec_t graph_exec = nullptr;
-  int chunk = 12;       // sweeps per graph launch (multiple of 6)
-  int pipeline = 1;     // chunks in flight beyond the one whose state is read
+  int chunk = 24;       // sweeps per graph launch, FP64 direct sweeps (multiple of 6)
+  int chunk_mm = 12;    // the same for matrix-core sweeps (masked sweeps cost more)
+  int pipeline = 0;     // 1: queue the next chunk before reading the last state
   int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
   SolveState* h_state = nullptr;  // [2][n_inst], hipHostMalloc
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -96,6 +97,9 @@ struct qdse_ctx {
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
   int nchunk = 16;
+  // private state for kernel timing
+  SolveState* d_tstate = nullptr;
+  SolveCtl* d_tctl = nullptr;
 };
 
 namespace {
@@ -332,7 +336,8 @@ void qdse_destroy(qdse_ctx* c) {
                   c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_M32,
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
                   c->d_ctl,     c->d_part,    c->d_gq,      c->d_slots, c->d_barrier,
-                  c->d_flags,   c->d_C32,     c->d_M64,     c->d_C64};
+                  c->d_flags,   c->d_C32,     c->d_M64,     c->d_C64,     c->d_tstate,
+                  c->d_tctl};
   for (void* p : ptrs) dfree(p);
   delete c;
 }
@@ -435,7 +440,8 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
 // chunk after convergence consists of masked sweeps that leave x unchanged).
 static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int kind,
                       std::vector<SolveState>& hs, bool* all_done) {
-  const int chunk = c->chunk;  // multiple of 6: ends in xbuf[0] with the slot cycle intact
+  // multiple of 6: ends in xbuf[0] with the slot cycle intact
+  const int chunk = kind == SWEEP_DIRECT ? c->chunk : c->chunk_mm;
   const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
   hipStream_t st = c->stream;
   SolveCtl ctl{tol, conv_mode, max_iter};
@@ -893,30 +899,41 @@ int qdse_time_contraction(qdse_ctx* c, int which, const double* d_x, double* d_o
   if ((which == 1 && !c->d_M32) || (which == 2 && !c->d_M64)) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
   hipStream_t st = c->stream;
+  // The kernels run as in a solve (masked-run decision, test statistics) on a
+  // private state whose tolerance is never met, so no instance freezes.
+  if (!c->d_tstate) {
+    int r = dalloc(&c->d_tstate, (size_t)c->n_inst);
+    if (!r) r = dalloc(&c->d_tctl, 1);
+    if (r) return r;
+  }
+  const SolveCtl never{0.0, QDSE_CONV_MASS, 1 << 30};
+  HIPCHK(hipMemcpyAsync(c->d_tctl, &never, sizeof(never), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_solve_init(st, c->n_inst, c->d_tstate));
   if (which == 1)  // node columns once; then only the matrix-core kernel is timed
     HIPCHK(launch_sweep_mm<float>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M32, c->d_C32, c->d_inst,
-                                  c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out, nullptr, nullptr,
-                                  1, true));
+                                  c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out, c->d_tstate,
+                                  c->d_tctl, 1, true));
   if (which == 2)
     HIPCHK(launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64, c->d_C64,
-                                   c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out, nullptr,
-                                   nullptr, 1, true));
+                                   c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out,
+                                   c->d_tstate, c->d_tctl, 1, true));
   std::vector<hipEvent_t> ev(2 * reps, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = QDSE_OK;
   for (int r = 0; r < reps && rc == QDSE_OK; ++r) {
-    hipError_t e = hipEventRecord(ev[2 * r], st);
-    if (e == hipSuccess)
-      e = which == 1   ? launch_sweep_mm<float>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M32,
-                                                c->d_C32, c->d_inst, c->d_lo, c->d_sw, c->d_t,
-                                                c->d_s, d_x, d_out, nullptr, nullptr, 1, false)
-          : which == 2 ? launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64,
-                                                 c->d_C64, c->d_inst, c->d_lo, c->d_sw, c->d_t,
-                                                 c->d_s, d_x, d_out, nullptr, nullptr, 1, false)
-                       : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
-                                            c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x,
-                                            d_out, nullptr, nullptr, 1, 1, c->fused_rows);
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], st);
+    // events travel on the kernel's own dispatch packet: kernel time only
+    hipEvent_t e0 = ev[2 * r], e1 = ev[2 * r + 1];
+    const hipError_t e =
+        which == 1   ? launch_sweep_mm<float>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M32, c->d_C32,
+                                              c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x,
+                                              d_out, c->d_tstate, c->d_tctl, 1, false, e0, e1)
+        : which == 2 ? launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64,
+                                               c->d_C64, c->d_inst, c->d_lo, c->d_sw, c->d_t,
+                                               c->d_s, d_x, d_out, c->d_tstate, c->d_tctl, 1,
+                                               false, e0, e1)
+                     : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
+                                          c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out,
+                                          c->d_tstate, c->d_tctl, r + 1, 1, c->fused_rows, e0, e1);
     if (e != hipSuccess) rc = QDSE_EDEVICE;
   }
   double tot = 0.0;

@@ -2,6 +2,7 @@
 // (host grid construction, kernel launchers and the context layout).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -84,12 +85,15 @@ hipError_t launch_sweep_fp64(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const double* x_in, double* x_out, double* nodes, SolveState* state,
                              const SolveCtl* ctl, int k, int add_f0);
 // The same sweep as one kernel: each workgroup rebuilds the node functions of
-// its instance in LDS and contracts 8 rows (bitwise the same arithmetic).
+// its instance in LDS and contracts `rows` rows (bitwise the same arithmetic).
+// With ev0/ev1 the launch carries start/stop events on its dispatch packet
+// (kernel duration only).
 hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk,
                               const InstDev* inst, const double* K, size_t kstride, const int* lo,
                               const double* sw, const double* t, const double* s,
                               const double* x_in, double* x_out, SolveState* state,
-                              const SolveCtl* ctl, int k, int add_f0, int rows);
+                              const SolveCtl* ctl, int k, int add_f0, int rows,
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_contraction_only(hipStream_t st, int n_inst, int n, int nq, int ldk,
                                   const InstDev* inst, const double* K, size_t kstride,
                                   const double* s, const double* x_in, double* x_out,
@@ -127,12 +131,14 @@ MmLayout mm_layout(int n, int nq, int n_inst);
 template <class T>
 hipError_t launch_build_mm(hipStream_t st, int n, int nq, int ldk, const MmLayout& L,
                            const double* K, const double* s, const double* t, T* MT);
-// nodes = false skips the node-column kernel (columns already built).
+// nodes = false skips the node-column kernel (columns already built); ev0/ev1
+// time the contraction kernel's dispatch as in launch_sweep_fused.
 template <class T>
 hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLayout& L,
                            const T* MT, T* C, const InstDev* inst, const int* lo, const double* sw,
                            const double* t, const double* s, const double* x_in, double* x_out,
-                           SolveState* state, const SolveCtl* ctl, int k, bool nodes);
+                           SolveState* state, const SolveCtl* ctl, int k, bool nodes,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Finite-mu sweep (qdse_mu.hip); x, L complex interleaved.
 hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, int nq4, int na,

@@ -396,6 +396,10 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
   __syncthreads();
   const InstDev P = inst_[inst];
   const size_t mat = (size_t)n * ldk;
+  // test statistic as the bits of a non-negative double (NaN above +inf),
+  // maximised over the workgroup's rows and folded in with one atomic
+  __shared__ unsigned long long wmax[4];
+  unsigned long long mine = 0ull;
   for (int rr = 0; rr < ROWS / 4; ++rr) {
     const int i = r0 + wave * (ROWS / 4) + rr;
     if (i >= n) break;
@@ -413,8 +417,17 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
         const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
         const unsigned long long bits = (unsigned long long)__double_as_longlong(
             isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
-        atomicMax(&state[inst].metric[k % 3], bits);
+        mine = bits > mine ? bits : mine;
       }
+    }
+  }
+  if (state) {
+    if (lane == 0) wmax[wave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long m = wmax[0];
+      for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+      atomicMax(&state[inst].metric[k % 3], m);
     }
   }
 }
@@ -667,12 +680,18 @@ hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk
                               const InstDev* inst, const double* K, size_t kstride, const int* lo,
                               const double* sw, const double* t, const double* s,
                               const double* x_in, double* x_out, SolveState* state,
-                              const SolveCtl* ctl, int k, int add_f0, int rows) {
+                              const SolveCtl* ctl, int k, int add_f0, int rows, hipEvent_t ev0,
+                              hipEvent_t ev1) {
   const size_t lds = (size_t)5 * ldk * sizeof(double);
   if (rows != 4 && rows != 8 && rows != 16) return hipErrorInvalidValue;
   auto kern = rows == 4 ? k_sweep_fused<4> : rows == 8 ? k_sweep_fused<8> : k_sweep_fused<16>;
-  hipLaunchKernelGGL(kern, dim3((n + rows - 1) / rows, n_inst), dim3(256), lds, st, n_inst, n, nq,
-                     ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out, state, ctl, k, add_f0);
+  const dim3 grid((n + rows - 1) / rows, n_inst);
+  if (ev0)
+    hipExtLaunchKernelGGL(kern, grid, dim3(256), (uint32_t)lds, st, ev0, ev1, 0, n_inst, n, nq,
+                          ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out, state, ctl, k, add_f0);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, n_inst, n, nq, ldk, inst, K, kstride, lo,
+                       sw, t, s, x_in, x_out, state, ctl, k, add_f0);
   return hipGetLastError();
 }
 

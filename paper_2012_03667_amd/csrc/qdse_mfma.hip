@@ -199,6 +199,23 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
     ib = w / n_rb;
   }
   const int i0 = rb * TM, b0 = ib * TN;
+  if (state) {
+    // every instance of this column block frozen (or absent): carry the
+    // iterate along and skip the contraction (both wavefronts agree)
+    bool frozen = true;
+    if (lane < TN) frozen = b0 + lane >= n_inst || state[b0 + lane].status != 0;
+    if (__all(frozen)) {
+      for (int e = threadIdx.x; e < TM * TN; e += 64 * KSPLIT) {
+        const int inst = b0 + e / TM, i = i0 + e % TM;
+        if (inst < n_inst && i < n) {
+          const size_t o = (size_t)inst * 2 * n;
+          x_out[o + i] = x_in[o + i];
+          x_out[o + n + i] = x_in[o + n + i];
+        }
+      }
+      return;
+    }
+  }
   const int lr = lane & 15, lk = lane >> 4;
   const int half = nq_pad / KSPLIT;  // a multiple of KSTEP
   const int kb = wave * half, ke = kb + half;
@@ -323,10 +340,15 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
         }
       }
     }
-    if (state && inst_ok && status == 0) {
-      // lanes lr, lr+16, lr+32, lr+48 hold the same instance
-      const unsigned long long bits = (unsigned long long)__double_as_longlong(worst);
-      atomicMax(&state[inst].metric[k % 3], bits);
+    if (state) {
+      // lanes lr, lr+16, lr+32, lr+48 hold the same instance: maximum of the
+      // statistic bits (NaN above +inf) over them, then one atomic
+      unsigned long long bits = (unsigned long long)__double_as_longlong(worst);
+      unsigned long long o = __shfl_xor(bits, 16, 64);
+      bits = o > bits ? o : bits;
+      o = __shfl_xor(bits, 32, 64);
+      bits = o > bits ? o : bits;
+      if (lk == 0 && inst_ok && status == 0) atomicMax(&state[inst].metric[k % 3], bits);
     }
   }
 }
@@ -356,13 +378,19 @@ template <class T>
 hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLayout& L,
                            const T* MT, T* C, const InstDev* inst, const int* lo, const double* sw,
                            const double* t, const double* s, const double* x_in, double* x_out,
-                           SolveState* state, const SolveCtl* ctl, int k, bool nodes) {
+                           SolveState* state, const SolveCtl* ctl, int k, bool nodes,
+                           hipEvent_t ev0, hipEvent_t ev1) {
   if (nodes)
     hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
                        n, nq, L.ldb, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
-  hipLaunchKernelGGL(k_mm_sweep<T>, dim3((L.ldi / (16 * Mfma<T>::RB)) * (L.ldb / TN)), dim3(64 * KSPLIT), 0, st,
-                     n_inst, n, L.nq_pad, L.ldi, L.ldb, MT, L.mstride, C, L.cstride, inst, s, x_in,
-                     x_out, state, ctl, k);
+  const dim3 grid((L.ldi / (16 * Mfma<T>::RB)) * (L.ldb / TN));
+  if (ev0)
+    hipExtLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT), 0, st, ev0, ev1, 0, n_inst, n,
+                          L.nq_pad, L.ldi, L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s,
+                          x_in, x_out, state, ctl, k);
+  else
+    hipLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT), 0, st, n_inst, n, L.nq_pad, L.ldi,
+                       L.ldb, MT, L.mstride, C, L.cstride, inst, s, x_in, x_out, state, ctl, k);
   return hipGetLastError();
 }
 
@@ -374,11 +402,11 @@ template hipError_t launch_sweep_mm<float>(hipStream_t, int, int, int, const MmL
                                            const float*, float*, const InstDev*, const int*,
                                            const double*, const double*, const double*,
                                            const double*, double*, SolveState*, const SolveCtl*,
-                                           int, bool);
+                                           int, bool, hipEvent_t, hipEvent_t);
 template hipError_t launch_sweep_mm<double>(hipStream_t, int, int, int, const MmLayout&,
                                             const double*, double*, const InstDev*, const int*,
                                             const double*, const double*, const double*,
                                             const double*, double*, SolveState*, const SolveCtl*,
-                                            int, bool);
+                                            int, bool, hipEvent_t, hipEvent_t);
 
 }  // namespace qdse
