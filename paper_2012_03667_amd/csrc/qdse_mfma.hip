@@ -24,11 +24,11 @@
 // Node functions (with the denominator t A^2 + B^2), the combination above,
 // the update and the test statistic are FP64 in both.
 //
-// Tiling: a workgroup of two wavefronts owns 32 rows (FP32; 16 rows for FP64,
-// whose accumulators are twice as wide) x 32 instances in blocks of 16 x 16,
-// eight products each; the two wavefronts split the loop
-// nodes in halves and their partial products are added through LDS before
-// the FP64 epilogue. Operands are read straight from L2/L1 in layouts where a
+// Tiling: a workgroup of two wavefronts owns 16 rows x 32 instances in blocks
+// of 16 x 16, eight products each (RB = 1 row block per wavefront measured
+// fastest for both element types: more workgroups, more overlap); the two
+// wavefronts split the loop nodes in halves and their partial products are
+// added through LDS before the FP64 epilogue. Operands are read straight from L2/L1 in layouts where a
 // 16-lane group reads contiguous memory, with the next k-step prefetched.
 //
 // Layouts (zero padded): MT[x][j][ldi] (x = 0..4, rows contiguous),
@@ -51,7 +51,7 @@ template <class T> struct Mfma;
 // row(l / 16, e), column l % 16 (FP32: 4 (l/16) + e; FP64: l/16 + 4 e).
 template <> struct Mfma<float> {
   typedef floatx4 acc_t;
-  static constexpr int RB = 2;  // 16-row blocks per wavefront
+  static constexpr int RB = 1;  // 16-row blocks per wavefront
   __device__ static int row(int g, int e) { return 4 * g + e; }
   __device__ static acc_t zero() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
   __device__ static acc_t mac(float a, float b, acc_t c) {
