@@ -110,6 +110,78 @@ struct MuArgs {
   double2* out;      // [inst][3][ne]
 };
 
+// The three projections of one (external point, loop point, sign of q4),
+// summed over the angle between p_vec and q_vec. With v = k_z = |p| - |q| z
+// (the component of k along p_vec) and y = 1/k^2, every scalar product above
+// is at most linear in v (|q_vec|^2 sin^2 = (|q|^2 - |p|^2) + 2|p| v - v^2
+// removes the sine), so each projection numerator is
+//   sum_{m=0,1} sum_{n=0..2} c_mn(p, q, A, B, C) v^n y^m
+// and the angular sum needs only the moments S_n = sum_t g_t v_t^n and
+// T_n = sum_t g_t y_t v_t^n (g_t = angular weight x interaction). v is the
+// small variable where the interaction is not negligible, so the expansion
+// does not cancel.
+struct MuPoint {
+  double p, q, k4;         // |p_vec|, |q_vec|, p4 - q4 (real)
+  cd pt4, qt4;             // p4 + i mu, q4 + i mu
+  cd Ap, Bp, Cp, Aq, Bq, Cq;
+};
+
+__device__ inline void mu_projections(const MuPoint& P, const double S[3], const double T[3],
+                                      cd& IA, cd& IB, cd& IC) {
+  const double p = P.p, q = P.q, k4 = P.k4;
+  const cd pt4 = P.pt4, qt4 = P.qt4, Aq = P.Aq, Bq = P.Bq, Cq = P.Cq;
+  const cd p2 = mk(p * p) + pt4 * pt4, q2 = mk(q * q) + qt4 * qt4;
+  const cd idq = inv(q2 - p2);
+  const cd sA = 0.5 * (Aq + P.Ap), sC = 0.5 * (Cq + P.Cp);
+  const cd dA = (Aq - P.Ap) * idq, dB = (Bq - P.Bp) * idq, dC = (Cq - P.Cp) * idq;
+  const cd iD = inv(Aq * Aq * (q * q) + Cq * Cq * (qt4 * qt4) + Bq * Bq);
+  const cd P4 = pt4 + qt4;
+  const double h0 = (q - p) * (q + p), pp = p * p, qqpp = q * q + p * p;
+  const cd Cqt = Cq * qt4;
+  // scalar products (constant and v coefficients)
+  const cd kP = k4 * P4 - mk(h0);
+  const cd kq0 = k4 * Cqt - h0 * Aq, kq1 = -p * Aq;
+  const cd kU = k4 * (dC * P4) - h0 * dA;
+  const cd qp0 = qqpp * Aq + Cqt * P4, qp1 = -p * Aq;
+  const cd qu0 = qqpp * (Aq * dA) + Cqt * (dC * P4), qu1 = -p * (Aq * dA);
+  const cd up0 = (q * q + 3.0 * pp) * dA + dC * (P4 * P4);
+  // TrW = tw0 + tw1 v + y (tv0 + tv1 v);  TQP = tq0 + tq1 v + y (tu0 + tu1 v)
+  const cd tw0 = 3.0 * sA + sC + 0.5 * up0, tw1 = -p * dA;
+  const cd tv0 = -(h0 * sA + (k4 * k4) * sC + 0.5 * (kU * kP)), tv1 = -2.0 * p * sA;
+  const cd tq0 = qp0, tq1 = qp1, tu0 = -(kP * kq0), tu1 = -(kP * kq1);
+  const cd BdB = Bq * dB;
+  // B: tr/4 = (B(q~) TrW - Delta_B T(Qh, P~)) / Delta
+  const cd b00 = Bq * tw0 - dB * tq0, b01 = Bq * tw1 - dB * tq1;
+  const cd b10 = Bq * tv0 - dB * tu0, b11 = Bq * tv1 - dB * tu1;
+  IB = iD * (S[0] * b00 + S[1] * b01 + T[0] * b10 + T[1] * b11);
+  // A: X = (0, |p|, 0)
+  const cd ks0 = k4 * (sC * Cqt) - h0 * (sA * Aq), ks1 = -p * (sA * Aq);
+  const cd sAAq = sA * Aq;
+  const cd xq0 = pp * Aq, xq1 = -p * Aq;
+  const cd xu0 = 2.0 * pp * dA, xu1 = -p * dA;
+  const cd a00 = -pp * sAAq - pp * qu0 + xq0 * tw0 - pp * sAAq - 0.5 * (xu0 * tq0) - 2.0 * pp * BdB;
+  const cd a01 = p * sAAq - 0.5 * (2.0 * pp * qu1 - p * qu0) + xq0 * tw1 + xq1 * tw0 + p * sAAq -
+                 0.5 * (xu0 * tq1 + xu1 * tq0) + p * BdB;
+  const cd a02 = 0.5 * p * qu1 + xq1 * tw1 - 0.5 * (xu1 * tq1);
+  const cd a10 = xq0 * tv0 - 0.5 * (xu0 * tu0);
+  const cd a11 = p * ks0 + 0.5 * p * (kP * qu0) + xq0 * tv1 + xq1 * tv0 + p * (sA * kq0) -
+                 0.5 * (xu0 * tu1 + xu1 * tu0) + p * (kP * BdB);
+  const cd a12 = p * ks1 + 0.5 * p * (kP * qu1) + xq1 * tv1 + p * (sA * kq1) - 0.5 * (xu1 * tu1);
+  IA = (iD * (1.0 / pp)) * (S[0] * a00 + S[1] * a01 + S[2] * a02 + T[0] * a10 + T[1] * a11 +
+                            T[2] * a12);
+  // C: X = (0, 0, p~4)
+  const cd XQ4 = pt4 * Cqt, XU4 = pt4 * (dC * P4);
+  const cd pk4 = k4 * pt4;
+  const cd c00 = -(pt4 * (sC * Cqt)) - 0.5 * (qu0 * (pt4 * P4)) + XQ4 * tw0 - Cqt * (sC * pt4) -
+                 0.5 * (XU4 * tq0) - BdB * (pt4 * P4);
+  const cd c01 = -0.5 * (qu1 * (pt4 * P4)) + XQ4 * tw1 - 0.5 * (XU4 * tq1);
+  const cd c10 = pk4 * ks0 + 0.5 * (qu0 * (pk4 * kP)) + XQ4 * tv0 + (sC * pk4) * kq0 -
+                 0.5 * (XU4 * tu0) + BdB * (pk4 * kP);
+  const cd c11 = pk4 * ks1 + 0.5 * (qu1 * (pk4 * kP)) + XQ4 * tv1 + (sC * pk4) * kq1 -
+                 0.5 * (XU4 * tu1);
+  IC = (iD * inv(pt4 * pt4)) * (S[0] * c00 + S[1] * c01 + T[0] * c10 + T[1] * c11);
+}
+
 __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
   __shared__ double zs[256], sns[256], wzs[256];
   const int lane = threadIdx.x & (MU_WAVE - 1);
@@ -127,76 +199,73 @@ __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
   const double pabs = a.ps[ia], p4r = a.p4[ib];
   const double2* xi = a.x + (size_t)inst * 3 * ne;
   const double2* Li = a.L + (size_t)inst * 3 * nl;
-  const cd Ap = mk(xi[e].x, xi[e].y), Bp = mk(xi[ne + e].x, xi[ne + e].y),
-           Cp = mk(xi[2 * ne + e].x, xi[2 * ne + e].y);
-  const cd pt4 = mk(p4r, a.mu);
-  const cd p2 = mk(pabs * pabs) + pt4 * pt4;
+  MuPoint P;
+  P.p = pabs;
+  P.pt4 = mk(p4r, a.mu);
+  P.Ap = mk(xi[e].x, xi[e].y);
+  P.Bp = mk(xi[ne + e].x, xi[ne + e].y);
+  P.Cp = mk(xi[2 * ne + e].x, xi[2 * ne + e].y);
   double sAr = 0, sAi = 0, sBr = 0, sBi = 0, sCr = 0, sCi = 0;
   for (int l = lane; l < nl; l += MU_WAVE) {
     const int c = l / a.nq4, d = l % a.nq4;
-    const double qa = a.qs[c];
-    const double wl = a.cw * a.wqs[c] * a.wq4[d];
+    const double qa = a.qs[c], q4a = a.q4[d];
+    const double wl = a.cw * a.gnorm * a.wqs[c] * a.wq4[d];
     const cd A0 = mk(Li[l].x, Li[l].y), B0 = mk(Li[nl + l].x, Li[nl + l].y),
              C0 = mk(Li[2 * nl + l].x, Li[2 * nl + l].y);
-    for (int sgn = -1; sgn <= 1; sgn += 2) {
-      const double q4r = sgn * a.q4[d];
-      const cd Aq = sgn < 0 ? conj(A0) : A0, Bq = sgn < 0 ? conj(B0) : B0,
-               Cq = sgn < 0 ? conj(C0) : C0;
-      const cd qt4 = mk(q4r, a.mu);
-      const cd q2 = mk(qa * qa) + qt4 * qt4;
-      const cd idq = inv(q2 - p2);
-      const cd sA = 0.5 * (Aq + Ap), sC = 0.5 * (Cq + Cp);
-      const cd dA = (Aq - Ap) * idq, dB = (Bq - Bp) * idq, dC = (Cq - Cp) * idq;
-      const cd Dl = Aq * Aq * (qa * qa) + Cq * Cq * (qt4 * qt4) + Bq * Bq;
-      const cd iD = inv(Dl);
-      const cd P4 = pt4 + qt4;
-      const double k4 = p4r - q4r;
-      for (int t = 0; t < a.na; ++t) {
-        const double z = zs[t], sn = sns[t];
-        const double qx = qa * sn, qz = qa * z;
-        const double kx = -qx, kz = pabs - qz;
-        const double k2 = kx * kx + kz * kz + k4 * k4;
-        const double ik2 = 1.0 / k2;
-        const double gw = wl * wzs[t] * a.gnorm * exp(-k2 * a.inv_om2);
-        const v3 P{mk(qx), mk(pabs + qz), P4};
-        const v3 Qh{Aq * qx, Aq * qz, Cq * qt4};
-        const v3 U{dA * P.x, dA * P.z, dC * P.t};
-        const v3 K{mk(kx), mk(kz), mk(k4)};
-        const cd kP = dot(K, P), kQ = dot(K, Qh), kU = dot(K, U);
-        const cd QP = dot(Qh, P), QU = dot(Qh, U), UP = dot(U, P);
-        const cd TQP = QP - kQ * kP * ik2;
-        const cd TrW = 3.0 * sA + sC + 0.5 * UP -
-                       (sA * (kx * kx + kz * kz) + sC * (k4 * k4) + 0.5 * kU * kP) * ik2;
-        const cd Bproj = (Bq * TrW - dB * TQP) * iD;
-        // X = (0, |p|, 0): A projection
-        const v3 QS{sA * Qh.x, sA * Qh.z, sC * Qh.t};  // Qh o Sigma'
-        const cd kQS = dot(K, QS);
-        const double Xz = pabs;
-        const cd TXQS = Xz * QS.z - (Xz * kz) * kQS * ik2;      // T(X, Qh o Sigma')
-        const cd TXP = Xz * P.z - (Xz * kz) * kP * ik2;         // T(X, P)
-        const cd XSz = sA * Xz;                                 // X o Sigma' = (0, sA |p|, 0)
-        const cd TQXS = Qh.z * XSz - kQ * (kz * XSz) * ik2;     // T(Qh, X o Sigma')
-        const cd XQ = Xz * Qh.z, XU = Xz * U.z;
-        const cd numA = -TXQS - 0.5 * QU * TXP + XQ * TrW - TQXS - 0.5 * XU * TQP -
-                        Bq * dB * TXP;
-        const cd Aproj = numA * iD * (1.0 / (pabs * pabs));
-        // X = (0, 0, p~4): C projection
-        const cd TXQS4 = pt4 * QS.t - (k4 * pt4) * kQS * ik2;
-        const cd TXP4 = pt4 * P.t - (k4 * pt4) * kP * ik2;
-        const cd XS4 = sC * pt4;
-        const cd TQXS4 = Qh.t * XS4 - kQ * (k4 * XS4) * ik2;
-        const cd XQ4 = pt4 * Qh.t, XU4 = pt4 * U.t;
-        const cd numC = -TXQS4 - 0.5 * QU * TXP4 + XQ4 * TrW - TQXS4 - 0.5 * XU4 * TQP -
-                        Bq * dB * TXP4;
-        const cd Cproj = numC * iD * inv(pt4 * pt4);
-        sAr = fma(gw, Aproj.r, sAr);
-        sAi = fma(gw, Aproj.i, sAi);
-        sBr = fma(gw, Bproj.r, sBr);
-        sBi = fma(gw, Bproj.i, sBi);
-        sCr = fma(gw, Cproj.r, sCr);
-        sCi = fma(gw, Cproj.i, sCi);
-      }
+    // angular moments for q4 = +|q4| (k4 = p4 - |q4|) and q4 = -|q4|; the
+    // geometry in the plane of p_vec and q_vec is common to both
+    const double k4p = p4r - q4a, k4m = p4r + q4a;
+    const double k4p2 = k4p * k4p, k4m2 = k4m * k4m;
+    const double ep = exp(-k4p2 * a.inv_om2), em = exp(-k4m2 * a.inv_om2);
+    double Sp[3] = {0, 0, 0}, Tp[3] = {0, 0, 0}, Sm[3] = {0, 0, 0}, Tm[3] = {0, 0, 0};
+    for (int t = 0; t < a.na; ++t) {
+      const double qx = qa * sns[t];
+      const double v = pabs - qa * zs[t];
+      const double base = qx * qx + v * v;
+      const double g = wzs[t] * exp(-base * a.inv_om2);
+      const double gp = g * ep, gm = g * em;
+      const double yp = 1.0 / (base + k4p2), ym = 1.0 / (base + k4m2);
+      const double gpv = gp * v, gmv = gm * v;
+      Sp[0] += gp;
+      Sp[1] += gpv;
+      Sp[2] = fma(gpv, v, Sp[2]);
+      Tp[0] = fma(gp, yp, Tp[0]);
+      Tp[1] = fma(gpv, yp, Tp[1]);
+      Tp[2] = fma(gpv * v, yp, Tp[2]);
+      Sm[0] += gm;
+      Sm[1] += gmv;
+      Sm[2] = fma(gmv, v, Sm[2]);
+      Tm[0] = fma(gm, ym, Tm[0]);
+      Tm[1] = fma(gmv, ym, Tm[1]);
+      Tm[2] = fma(gmv * v, ym, Tm[2]);
     }
+    P.q = qa;
+    cd IA, IB, IC;
+    // q4 > 0: the interpolated values; q4 < 0: their conjugates
+    P.k4 = k4p;
+    P.qt4 = mk(q4a, a.mu);
+    P.Aq = A0;
+    P.Bq = B0;
+    P.Cq = C0;
+    mu_projections(P, Sp, Tp, IA, IB, IC);
+    sAr = fma(wl, IA.r, sAr);
+    sAi = fma(wl, IA.i, sAi);
+    sBr = fma(wl, IB.r, sBr);
+    sBi = fma(wl, IB.i, sBi);
+    sCr = fma(wl, IC.r, sCr);
+    sCi = fma(wl, IC.i, sCi);
+    P.k4 = k4m;
+    P.qt4 = mk(-q4a, a.mu);
+    P.Aq = conj(A0);
+    P.Bq = conj(B0);
+    P.Cq = conj(C0);
+    mu_projections(P, Sm, Tm, IA, IB, IC);
+    sAr = fma(wl, IA.r, sAr);
+    sAi = fma(wl, IA.i, sAi);
+    sBr = fma(wl, IB.r, sBr);
+    sBi = fma(wl, IB.i, sBi);
+    sCr = fma(wl, IC.r, sCr);
+    sCi = fma(wl, IC.i, sCi);
   }
   sAr = wsum_mu(sAr);
   sAi = wsum_mu(sAi);
