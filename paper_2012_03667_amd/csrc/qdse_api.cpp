@@ -652,16 +652,21 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
                   int max_iter, int* steps_out) {
   const int nI = c->n_inst, len = 2 * c->hg.n;
   const size_t L = xlen(c);
-  const int mres = 40;
+  // restart length: the Jacobian is strongly non-normal (||J|| ~ 2 with a tight
+  // cluster of eigenvalues near its spectral radius), and short restarts
+  // discard the Krylov information that cluster needs
+  const int mres = std::max(1, std::min(max_iter, 120));
   hipStream_t st = c->stream;
   DevBufs buf;
   double *d_V, *d_w, *d_r, *d_h, *d_y, *d_sc;
   int rc;
+  // d_h: two Gram-Schmidt passes [2][nI][mres + 1] followed by the norms [nI]
+  const size_t hstride = (size_t)nI * (mres + 1);
   if ((rc = buf.alloc(&d_V, (size_t)(mres + 1) * L)) || (rc = buf.alloc(&d_w, L)) ||
-      (rc = buf.alloc(&d_r, L)) || (rc = buf.alloc(&d_h, (size_t)nI * (mres + 2))) ||
+      (rc = buf.alloc(&d_r, L)) || (rc = buf.alloc(&d_h, 2 * hstride + nI)) ||
       (rc = buf.alloc(&d_y, (size_t)nI * (mres + 1))) || (rc = buf.alloc(&d_sc, (size_t)nI)))
     return rc;
-  std::vector<double> tmp(nI), bnorm(nI), hh((size_t)nI * (mres + 2));
+  std::vector<double> tmp(nI), bnorm(nI), hh(2 * hstride + nI);
   std::vector<double> zero(L, 0.0);
   HIPCHK(hipMemcpyAsync(d_sol, zero.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(launch_batched_dot(st, nI, len, d_b, 0, d_b, len, 1, d_sc));
@@ -699,18 +704,21 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
       double* vj = d_V + (size_t)j * L;
       double* vn = d_V + (size_t)(j + 1) * L;
       if ((rc = apply(vj, d_w))) return rc;
+      // classical Gram-Schmidt, twice, on the device; one transfer of both
+      // coefficient sets and the new norm per iteration
       std::vector<double> hcol((size_t)nI * (j + 1), 0.0);
+      const size_t hlen = (size_t)nI * (j + 1);
       for (int pass = 0; pass < 2; ++pass) {
-        HIPCHK(launch_batched_dot(st, nI, len, d_V, L, d_w, len, j + 1, d_h));
-        HIPCHK(launch_gs_update(st, nI, len, d_V, L, j + 1, d_h, j + 1, d_w));
-        HIPCHK(hipMemcpyAsync(hh.data(), d_h, (size_t)nI * (j + 1) * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (size_t q = 0; q < hcol.size(); ++q) hcol[q] += hh[q];
+        double* hp = d_h + pass * hlen;
+        HIPCHK(launch_batched_dot(st, nI, len, d_V, L, d_w, len, j + 1, hp));
+        HIPCHK(launch_gs_update(st, nI, len, d_V, L, j + 1, hp, j + 1, d_w));
       }
-      HIPCHK(launch_batched_dot(st, nI, len, d_w, 0, d_w, len, 1, d_sc));
-      HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(launch_batched_dot(st, nI, len, d_w, 0, d_w, len, 1, d_h + 2 * hlen));
+      HIPCHK(hipMemcpyAsync(hh.data(), d_h, (2 * hlen + nI) * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      for (size_t q = 0; q < hlen; ++q) hcol[q] = hh[q] + hh[hlen + q];
+      for (int k = 0; k < nI; ++k) tmp[k] = hh[2 * hlen + k];
       bool all_small = true;
       for (int k = 0; k < nI; ++k) {
         double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;  // column-major (mres+1) x mres

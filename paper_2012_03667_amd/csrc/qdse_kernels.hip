@@ -547,6 +547,103 @@ __global__ void k_vjp_cols(int n_inst, int n, int nq, int ldk, int nchunk,
   o[3 * ldk + j] = gsS;
 }
 
+// Row and column parts in one pass over the kernel matrices: a wavefront owns
+// one row chunk; lanes run over loop nodes j = lane + 64 u (u < SLOTS), keep
+// the chunk's column partials in registers, and reduce the row sums across
+// the wavefront row by row. Node functions of the instance sit in LDS. Every
+// sum runs in the same order as in k_vjp_rows and k_vjp_cols, so the result
+// is bitwise the same with half the matrix traffic.
+template <int SLOTS>
+__global__ void __launch_bounds__(256) k_vjp_fused(int n_inst, int n, int nq, int ldk, int nchunk,
+                                                   const InstDev* __restrict__ inst_,
+                                                   const double* __restrict__ K, size_t kstride,
+                                                   const double* __restrict__ s_,
+                                                   const double* __restrict__ t_,
+                                                   const double* __restrict__ nodes,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ out,
+                                                   double* __restrict__ part) {
+  extern __shared__ double ndl[];  // [5][ldk]: A, B, sigma_V, sigma_S, t
+  const int inst = blockIdx.y;
+  const double* nd = nodes + (size_t)inst * 5 * ldk;
+  for (int j = threadIdx.x; j < nq; j += blockDim.x) {
+    ndl[j] = nd[j];
+    ndl[ldk + j] = nd[ldk + j];
+    ndl[2 * ldk + j] = nd[2 * ldk + j];
+    ndl[3 * ldk + j] = nd[3 * ldk + j];
+    ndl[4 * ldk + j] = t_[j];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int chunk = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (chunk >= nchunk) return;
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  const double* Kb = K + (size_t)P.kblock * kstride;
+  const double* xi = x + (size_t)inst * 2 * n;
+  const double* wi = w + (size_t)inst * 2 * n;
+  double* oi = out + (size_t)inst * 2 * n;
+  const int r0 = (int)((long)n * chunk / nchunk), r1 = (int)((long)n * (chunk + 1) / nchunk);
+  double cA[SLOTS], cB[SLOTS], cV[SLOTS], cS[SLOTS];
+#pragma unroll
+  for (int u = 0; u < SLOTS; ++u) cA[u] = cB[u] = cV[u] = cS[u] = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const double s = s_[i], Ai = xi[i], Bi = xi[n + i];
+    const double ab = P.pref * wi[i], bb = P.pref * wi[n + i];
+    const double* Ki = Kb + (size_t)i * ldk;
+    double gA = 0.0, gB = 0.0;
+    // all kernel-matrix loads of the row first (clamped, zero beyond nq)
+    double kTs[SLOTS], k3s[SLOTS], k0s[SLOTS];
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int j = lane + WAVE * u;
+      const int jj = j < nq ? j : nq - 1;
+      kTs[u] = Ki[jj];
+      k3s[u] = Ki[mat + jj];
+      k0s[u] = Ki[2 * mat + jj];
+      if (j >= nq) kTs[u] = k3s[u] = k0s[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int j = lane + WAVE * u;
+      const int jj = j < nq ? j : nq - 1;
+      {
+        const double kT = kTs[u], k3 = k3s[u], k0 = k0s[u];
+        const double Aq = ndl[jj], Bq = ndl[ldk + jj], sV = ndl[2 * ldk + jj],
+                     sS = ndl[3 * ldk + jj], t = ndl[4 * ldk + jj];
+        const double dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
+        const double gdA = kT * (2.0 * s * bb * sS - ab * (s + t) * sV);
+        const double gsA = ab * k3 * sV + bb * k0 * sS;
+        const double gdB = -2.0 * kT * (ab * sS + s * bb * sV);
+        gA += gsA - gdA;
+        gB -= gdB;
+        cA[u] += gdA + gsA;
+        cB[u] += gdB;
+        cS[u] += kT * (2.0 * s * bb * dA - 2.0 * ab * dB) + bb * k0 * sA;
+        cV[u] += ab * k3 * sA - kT * (ab * (s + t) * dA + 2.0 * s * bb * dB);
+      }
+    }
+    gA = wave_sum(gA);
+    gB = wave_sum(gB);
+    if (lane == 0) {
+      oi[i] = gA;
+      oi[n + i] = gB;
+    }
+  }
+  double* o = part + (((size_t)inst * nchunk + chunk) * 4) * ldk;
+#pragma unroll
+  for (int u = 0; u < SLOTS; ++u) {
+    const int j = lane + WAVE * u;
+    if (j < nq) {
+      o[j] = cA[u];
+      o[ldk + j] = cB[u];
+      o[2 * ldk + j] = cV[u];
+      o[3 * ldk + j] = cS[u];
+    }
+  }
+}
+
 // Sum the row chunks in a fixed order and push the adjoints of sigma_V,
 // sigma_S through sigma = (A or B)/Delta, Delta = t A^2 + B^2: adjoints of
 // A(t_j), B(t_j) into gq[inst][2][ldk].
@@ -684,6 +781,8 @@ hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk
                               hipEvent_t ev1) {
   const size_t lds = (size_t)5 * ldk * sizeof(double);
   if (rows != 4 && rows != 8 && rows != 16) return hipErrorInvalidValue;
+  // (one slot-templated variant that loads a whole row at once measured
+  // slower here: more registers, lower occupancy)
   auto kern = rows == 4 ? k_sweep_fused<4> : rows == 8 ? k_sweep_fused<8> : k_sweep_fused<16>;
   const dim3 grid((n + rows - 1) / rows, n_inst);
   if (ev0)
@@ -731,11 +830,25 @@ hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const 
                       double* out, double* nodes, double* part, double* gq, int nchunk) {
   hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
                      sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 1);
-  const long rows = (long)n_inst * n;
-  hipLaunchKernelGGL(k_vjp_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n, nq,
-                     ldk, inst, K, kstride, s, t, nodes, w, out);
-  hipLaunchKernelGGL(k_vjp_cols, dim3((nq + 63) / 64, nchunk, n_inst), dim3(64), 0, st, n_inst, n,
-                     nq, ldk, nchunk, inst, K, kstride, s, t, nodes, x, w, part);
+  const int slots = (nq + WAVE - 1) / WAVE;
+  const dim3 fgrid((nchunk + 3) / 4, n_inst);
+  const size_t flds = (size_t)5 * ldk * sizeof(double);
+  if (slots <= 4) {
+    hipLaunchKernelGGL(k_vjp_fused<4>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
+                       inst, K, kstride, s, t, nodes, x, w, out, part);
+  } else if (slots <= 9) {
+    hipLaunchKernelGGL(k_vjp_fused<9>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
+                       inst, K, kstride, s, t, nodes, x, w, out, part);
+  } else if (slots <= 17) {
+    hipLaunchKernelGGL(k_vjp_fused<17>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
+                       inst, K, kstride, s, t, nodes, x, w, out, part);
+  } else {  // large grids: row and column parts as two passes
+    const long rows = (long)n_inst * n;
+    hipLaunchKernelGGL(k_vjp_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n,
+                       nq, ldk, inst, K, kstride, s, t, nodes, w, out);
+    hipLaunchKernelGGL(k_vjp_cols, dim3((nq + 63) / 64, nchunk, n_inst), dim3(64), 0, st, n_inst,
+                       n, nq, ldk, nchunk, inst, K, kstride, s, t, nodes, x, w, part);
+  }
   hipLaunchKernelGGL(k_vjp_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n_inst, nq,
                      ldk, nchunk, t, nodes, part, gq);
   hipLaunchKernelGGL(k_vjp_scatter, dim3((n + 255) / 256, n_inst), dim3(256), 0, st, n_inst, n, nq,

@@ -119,6 +119,27 @@ def test_vjp_is_transpose_of_oracle_jacobian(Q):
         assert np.max(np.abs(out[k] - ref)) < 1e-11 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("n", [150, 512, 700])
+def test_vjp_inner_product_with_oracle_jvp(Q, n):
+    """<J^T w, v> from the GPU reverse sweep equals <w, J v> with J v from the
+    oracle's complex-step tangent, at grids that use each register layout of
+    the single-pass reverse kernel (loop nodes up to 256, 576 and 1088)."""
+    na = 16
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.02)]
+    S = Q.Solver(n, na, params)
+    g = oracle_grid(n, na, 3)
+    rng = np.random.default_rng(13)
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    ws = rng.normal(size=xs.shape)
+    vs = rng.normal(size=xs.shape)
+    out = S.vjp(torch.tensor(xs, device="cuda"), torch.tensor(ws, device="cuda")).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        jv = O.jvp(g, O.Params(D, om, m), xs[k], vs[k])
+        lhs, rhs = float(out[k] @ vs[k]), float(ws[k] @ jv)
+        scale = float(np.abs(ws[k] * jv).sum())
+        assert abs(lhs - rhs) < 1e-11 * scale, (n, k, lhs, rhs, scale)
+
+
 def test_solve_matches_oracle_picard_paper_workload(Q):
     """Sec. IV Table 1 workload: the GPU stops after the same 11 sweeps with the
     same iterate, for the 2-point (paper) and 4-point interpolations."""
