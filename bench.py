@@ -33,6 +33,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_VALU_PEAK_TFLOPS = 78.6
+MU_FLOPS_PER_PAIR = 1673
+MU_FLOPS_PER_ANGLE = 89
 COPY_BYTES = 1 << 30
 
 
@@ -121,6 +124,53 @@ def gradient_batch(Q, np, torch, B):
     }
 
 
+def mixed_batch(Q, np, torch, B):
+    """B vacuum instances (paper interaction) with m ~ U[0, 0.2] GeV, radial
+    grid sizes uniform in {128, 256, 384, 512} and 64 or 128 angular nodes
+    (seed 4). Instances are grouped by grid class (one context per class,
+    kernel matrices shared inside a class) and each class is solved to 1e-7
+    accuracy (tol 1e-8) with FP32 MFMA sweeps + FP64 MFMA refinement, and
+    with FP64 MFMA sweeps only; all classes are driven together by
+    qdse_solve_group, each on its own stream."""
+    rng = np.random.default_rng(4)
+    m = rng.uniform(0.0, 0.2, B)
+    nr = rng.choice([128, 256, 384, 512], B)
+    nan = rng.choice([64, 128], B)
+    classes = sorted(set(zip(nr.tolist(), nan.tolist())))
+    out = {"instances": B, "classes": len(classes),
+           "class_sizes": {f"{n}x{na}": int(np.sum((nr == n) & (nan == na))) for n, na in classes}}
+    tot = {}
+    for prec in (Q.QDSE_FP32_REFINE, Q.QDSE_FP64_MATRIX):
+        solvers, x0s = [], []
+        for (n, na) in classes:  # one context and one stream per class
+            sel = np.nonzero((nr == n) & (nan == na))[0]
+            params = [(0.55, 0.678, float(m[k])) for k in sel]
+            S = Q.Solver(n, na, params, interp_order=3, precision=prec, stream=torch.cuda.Stream())
+            solvers.append(S)
+            x0s.append(S.initial(1.0, 1.0))
+        torch.cuda.synchronize()
+        xs = [x.clone() for x in x0s]
+        Q.solve_group(solvers, xs, tol=1e-8, max_iter=2000)  # warm-up (graph capture)
+        xs = [x.clone() for x in x0s]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, its, rss = Q.solve_group(solvers, xs, tol=1e-8, max_iter=2000)
+        torch.cuda.synchronize()
+        tot[prec] = time.perf_counter() - t0
+        if rc != Q.QDSE_OK:
+            raise SystemExit(f"mixed batch did not converge: rc={rc}")
+        for S in solvers:
+            S.close()
+    out["fp32_refined_solves_per_s"] = B / tot[Q.QDSE_FP32_REFINE]
+    out["fp64_mfma_solves_per_s"] = B / tot[Q.QDSE_FP64_MATRIX]
+    out["fp32_refined_ms"] = 1e3 * tot[Q.QDSE_FP32_REFINE]
+    out["fp64_mfma_ms"] = 1e3 * tot[Q.QDSE_FP64_MATRIX]
+    out["workload"] = ("vacuum, paper interaction, m~U[0,0.2], N_r in {128,256,384,512} x N_a in "
+                       "{64,128} (seed 4), tol 1e-8; one context and stream per class, "
+                       "qdse_solve_group")
+    return out
+
+
 def finite_mu(Q, torch):
     """Finite mu = 0.3 GeV, T = 0, paper interaction, m = 5 MeV: external
     128 |p_vec| x 128 p4 nodes, loop 129 x 129 nodes with q4 of both signs and
@@ -141,9 +191,20 @@ def finite_mu(Q, torch):
     dt = (time.perf_counter() - t0) / reps
     points = ns * n4 * (ns + 1) * (n4 + 1) * 2 * na
     S.close()
+    # FP64 operations of the sweep kernel per (external point, loop point)
+    # pair, both signs of q4 included, as compiled (FMA = 2, mul/add = 1):
+    # the angle-independent coefficient algebra plus one moment update per
+    # angle; counted from the gfx950 code of k_mu_sweep.
+    pairs = ns * n4 * (ns + 1) * (n4 + 1)
+    flops = pairs * (MU_FLOPS_PER_PAIR + MU_FLOPS_PER_ANGLE * na)
+    tf = flops / dt / 1e12
     return {"workload": "mu=0.3 GeV, 128x128 external, 129x129x2 loop points x 32 angles, m=5 MeV",
             "sweep_ms": 1e3 * dt, "integrand_points_per_sweep": points,
-            "integrand_points_per_s": points / dt}
+            "integrand_points_per_s": points / dt,
+            "roofline": {"bound": "alu", "kernel": "k_mu_sweep (FP64 VALU)", "achieved": tf,
+                         "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                         "flops_per_sweep": flops}}
 
 
 def main():
@@ -157,6 +218,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-mu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--grad-batch", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one cold 1 GiB device copy (reference for HBM byte counters)")
@@ -314,6 +376,10 @@ def main():
     # ---- gradient batch: per-instance interaction, solve + implicit adjoint
     if not args.no_grad:
         line["gradient_batch"] = gradient_batch(Q, np, torch, args.grad_batch)
+
+    # ---- mixed grid classes (vacuum instances), grouped by class
+    if not args.no_mixed:
+        line["mixed_batch_vacuum"] = mixed_batch(Q, np, torch, args.batch)
 
     # ---- finite chemical potential: one sweep of the 128 x 128 x 32 grid
     if not args.no_mu:

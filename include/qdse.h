@@ -136,6 +136,18 @@ int qdse_iterate_fp64_matrix(qdse_ctx* ctx, const double* d_x_in, double* d_x_ou
 int qdse_solve(qdse_ctx* ctx, double* d_x, double tol, int max_iter, int conv_mode,
                int* iters, double* resid);
 
+/* The same solve for several contexts at once (for example one per grid
+ * class of a mixed batch): ctxs[n_ctx] distinct contexts, d_x[q] the device
+ * unknowns of context q, iters[q] / resid[q] host arrays of its n_inst
+ * entries (the outer arrays may be NULL, or any entry). Each context runs its
+ * own phases on its own stream; the contexts' work overlaps only if their
+ * streams differ (set at qdse_setup). Returns QDSE_OK if every instance of
+ * every context passed, else the most severe code of any context (a
+ * negative code before QDSE_NOT_CONVERGED); outputs as for qdse_solve.
+ * Synchronises every context's stream. */
+int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int max_iter,
+                     int conv_mode, int** iters, double** resid);
+
 /* Newton's method on the fixed-point residual R(x) = F(x) - x for every
  * instance, for fixed points where successive approximation does not contract:
  * each step solves (I - J) dx = R by restarted GMRES with Jacobian-vector

@@ -70,6 +70,9 @@ def load():
     L.qdse_iterate_fp32.argtypes = [_vp, _vp, _vp]
     L.qdse_iterate_fp64_matrix.argtypes = [_vp, _vp, _vp]
     L.qdse_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp]
+    L.qdse_solve_group.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                   ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(_ip), ctypes.POINTER(_dp)]
     L.qdse_solve_stats.argtypes = [_vp, _ip, _ip]
     L.qdse_newton.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]
     L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
@@ -268,6 +271,24 @@ def mu_grid_nodes(n_space, n_time, n_angle, interp_order=3, r_min=1e-2, r_max=1e
     _check(load().qdse_mu_grid_nodes(ctypes.byref(g), *[a.ctypes.data_as(_dp) for a in out]),
            "qdse_mu_grid_nodes")
     return dict(zip(("ps", "p4", "qs", "q4", "wqs", "wq4", "z", "wz"), out))
+
+
+def solve_group(solvers, xs, tol=1e-10, max_iter=1000, conv_mode=QDSE_CONV_MASS):
+    """qdse_solve_group: solves several contexts together (their work overlaps
+    when their streams differ). xs[q] is solvers[q]'s unknown tensor (in
+    place). Returns (status, [iters per context], [resid per context])."""
+    n = len(solvers)
+    if n != len(xs) or n == 0:
+        raise ValueError("one unknown tensor per solver is required")
+    H = (_vp * n)(*[S._h for S in solvers])
+    X = (_vp * n)(*[_dev(x, S.shape, "x") for S, x in zip(solvers, xs)])
+    its = [np.zeros(S.n_inst, dtype=np.int32) for S in solvers]
+    rss = [np.zeros(S.n_inst) for S in solvers]
+    I = (_ip * n)(*[a.ctypes.data_as(_ip) for a in its])
+    R = (_dp * n)(*[a.ctypes.data_as(_dp) for a in rss])
+    rc = load().qdse_solve_group(H, n, X, float(tol), int(max_iter), int(conv_mode), I, R)
+    _check(rc, "qdse_solve_group", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+    return rc, its, rss
 
 
 class MuSolver:

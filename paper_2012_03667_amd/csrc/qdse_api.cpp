@@ -85,7 +85,6 @@ struct qdse_ctx {
   hipGraphExec_t graph_exec = nullptr;
   int chunk = 24;       // sweeps per graph launch, FP64 direct sweeps (multiple of 6)
   int chunk_mm = 12;    // the same for matrix-core sweeps (masked sweeps cost more)
-  int pipeline = 0;     // 1: queue the next chunk before reading the last state
   int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
   SolveState* h_state = nullptr;  // [2][n_inst], hipHostMalloc
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -242,7 +241,6 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
     const int ch = std::atoi(e);
     if (ch >= 6 && ch <= 120 && ch % 6 == 0) c->chunk = ch;
   }
-  if (const char* e = std::getenv("QDSE_PIPELINE")) c->pipeline = std::atoi(e) != 0;
   for (int b = 0; b < c->n_blocks; ++b) {
     hipError_t e = launch_precompute(st, g.n, g.nq, g.na, g.ldk, c->d_s, c->d_t, c->d_W, c->d_z,
                                      c->d_wz, c->block_omega[b], 0, c->d_K + b * c->kstride,
@@ -432,17 +430,31 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
   return QDSE_OK;
 }
 
-// Masked sweeps from xbuf[0] until every instance is frozen; the iterate ends
-// in xbuf[0]. hs receives the final per-instance state. Each graph launch runs
-// c->chunk sweeps and is followed by an asynchronous copy of the state into
-// pinned memory; with pipelining the next chunk is queued before the host
-// reads the previous copy, so the device never waits for the host (the extra
-// chunk after convergence consists of masked sweeps that leave x unchanged).
-static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int kind,
-                      std::vector<SolveState>& hs, bool* all_done) {
-  // multiple of 6: ends in xbuf[0] with the slot cycle intact
-  const int chunk = kind == SWEEP_DIRECT ? c->chunk : c->chunk_mm;
-  const bool use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
+// Masked sweeps from xbuf[0] until every instance is frozen, as a stepper
+// so that several contexts (each on its own stream) can be driven together:
+// begin() prepares one phase (tolerance, sweep kind, graph of `chunk`
+// sweeps), launch() enqueues one chunk followed by an asynchronous copy of the
+// solve state into pinned memory and an event, wait() blocks on the last
+// chunk's event and decides whether the phase is over. The iterate always
+// ends in xbuf[0] (chunks are multiples of 6 sweeps: even, and the three
+// statistic slots come back to the same position).
+struct MaskedRun {
+  qdse_ctx* c = nullptr;
+  int kind = 0, chunk = 12, slot = 0;
+  long launched = 0, limit = 0;
+  bool use_graph = true, all_done = false;
+  hipGraphExec_t exec = nullptr;
+};
+
+static int masked_begin(MaskedRun& r, qdse_ctx* c, double tol, int max_iter, int conv_mode,
+                        int kind) {
+  r.c = c;
+  r.kind = kind;
+  r.chunk = kind == SWEEP_DIRECT ? c->chunk : c->chunk_mm;
+  r.use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
+  r.launched = 0;
+  r.limit = (long)max_iter + 1 + r.chunk;
+  r.all_done = false;
   hipStream_t st = c->stream;
   SolveCtl ctl{tol, conv_mode, max_iter};
   HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
@@ -450,11 +462,11 @@ static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int 
   hipGraphExec_t& exec = kind == SWEEP_MM32   ? c->graph32_exec
                          : kind == SWEEP_MM64 ? c->graphmm_exec
                                               : c->graph_exec;
-  if (use_graph && !exec) {
+  if (r.use_graph && !exec) {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = record_chunk(c, c->cap_stream, chunk, kind);
+    int rc = record_chunk(c, c->cap_stream, r.chunk, kind);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
     if (rc) return rc;
     HIPCHK(e);
@@ -462,42 +474,44 @@ static int run_masked(qdse_ctx* c, double tol, int max_iter, int conv_mode, int 
     (void)hipGraphDestroy(graph);
     HIPCHK(e);
   }
-  const int nI = c->n_inst;
-  const size_t bytes = (size_t)nI * sizeof(SolveState);
-  auto done_in = [&](int slot) {
-    const SolveState* h = c->h_state + (size_t)slot * nI;
-    for (int q = 0; q < nI; ++q)
-      if (h[q].status == 0) return false;
-    return true;
-  };
-  long launched = 0;
-  const long limit = (long)max_iter + 1 + chunk;
-  int cur = 0, last = -1;
-  *all_done = false;
-  while (launched < limit) {
-    if (use_graph) {
-      HIPCHK(hipGraphLaunch(exec, st));
-    } else {
-      int rc = record_chunk(c, st, chunk, kind);
-      if (rc) return rc;
-    }
-    launched += chunk;
-    HIPCHK(hipMemcpyAsync(c->h_state + (size_t)cur * nI, c->d_state, bytes,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(c->ev[cur], st));
-    // state to inspect: the previous chunk's when pipelining, else this one's
-    const int probe = c->pipeline ? last : cur;
-    last = cur;
-    cur ^= 1;
-    if (probe < 0) continue;
-    HIPCHK(hipEventSynchronize(c->ev[probe]));
-    if (done_in(probe)) break;
-  }
-  HIPCHK(hipStreamSynchronize(st));
-  // the newest copy is final (masked sweeps leave a frozen state unchanged)
-  hs.assign(c->h_state + (size_t)last * nI, c->h_state + (size_t)last * nI + nI);
-  *all_done = last >= 0 && done_in(last);
+  r.exec = exec;
   return QDSE_OK;
+}
+
+static int masked_launch(MaskedRun& r) {
+  qdse_ctx* c = r.c;
+  hipStream_t st = c->stream;
+  if (r.use_graph) {
+    HIPCHK(hipGraphLaunch(r.exec, st));
+  } else {
+    int rc = record_chunk(c, st, r.chunk, r.kind);
+    if (rc) return rc;
+  }
+  r.launched += r.chunk;
+  r.slot ^= 1;
+  HIPCHK(hipMemcpyAsync(c->h_state + (size_t)r.slot * c->n_inst, c->d_state,
+                        (size_t)c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(c->ev[r.slot], st));
+  return QDSE_OK;
+}
+
+// *over: the phase has ended (every instance frozen, or the sweep limit).
+static int masked_wait(MaskedRun& r, bool* over) {
+  qdse_ctx* c = r.c;
+  HIPCHK(hipEventSynchronize(c->ev[r.slot]));
+  const SolveState* h = c->h_state + (size_t)r.slot * c->n_inst;
+  bool done = true;
+  for (int q = 0; q < c->n_inst; ++q)
+    if (h[q].status == 0) done = false;
+  r.all_done = done;
+  *over = done || r.launched >= r.limit;
+  return QDSE_OK;
+}
+
+static void masked_state(const MaskedRun& r, std::vector<SolveState>& hs) {
+  const qdse_ctx* c = r.c;
+  const SolveState* h = c->h_state + (size_t)r.slot * c->n_inst;
+  hs.assign(h, h + c->n_inst);
 }
 
 static int finish_solve(qdse_ctx* c, const std::vector<SolveState>& hs, bool all_done, int* iters,
@@ -539,50 +553,140 @@ static int solve_persistent(qdse_ctx* c, double* d_x, int* iters, double* resid)
   return finish_solve(c, hs, true, iters, resid);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Solve of several contexts at once: every context runs its phases (FP32
+// matrix-core sweeps then FP64, or one FP64 phase) on its own stream; the
+// host waits on one context's chunk while the chunks of the others run.
+struct GroupEntry {
+  qdse_ctx* c;
+  double* d_x;
+  int* iters;
+  double* resid;
+  MaskedRun run;
+  int phase = 0;  // 0: first phase, 1: FP64 after FP32, 2: finished
+  bool all_done = false;
+  std::vector<SolveState> hs;
+  int rc = QDSE_OK;
+};
+
+int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
+  qdse_ctx* c = g.c;
+  if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
+    double tol32 = 1e-6;  // switch to FP64 sweeps below this change
+    if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
+    if (tol32 < tol) tol32 = tol;
+    return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32);
+  }
+  const int kind = c->precision == QDSE_FP64 ? SWEEP_DIRECT : SWEEP_MM64;
+  return masked_begin(g.run, c, tol, max_iter, conv_mode, kind);
+}
+
+int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_mode) {
+  for (GroupEntry& g : G) {
+    qdse_ctx* c = g.c;
+    c->last_sweeps32.assign(c->n_inst, 0);
+    c->last_sweeps64.assign(c->n_inst, 0);
+    HIPCHK(hipMemcpyAsync(c->d_xbuf[0], g.d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
+                          c->stream));
+    int rc = group_phase_begin(g, tol, max_iter, conv_mode);
+    if (!rc) rc = masked_launch(g.run);
+    if (rc) return rc;
+  }
+  for (;;) {
+    bool any = false;
+    for (GroupEntry& g : G) {
+      if (g.phase == 2) continue;
+      any = true;
+      bool over = false;
+      int rc = masked_wait(g.run, &over);
+      if (rc) return rc;
+      if (!over) {
+        if ((rc = masked_launch(g.run))) return rc;
+        continue;
+      }
+      qdse_ctx* c = g.c;
+      masked_state(g.run, g.hs);
+      if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
+        for (int k = 0; k < c->n_inst; ++k) c->last_sweeps32[k] = g.hs[k].sweeps;
+        g.phase = 1;
+        rc = group_phase_begin(g, tol, max_iter, conv_mode);
+        if (!rc) rc = masked_launch(g.run);
+        if (rc) return rc;
+        continue;
+      }
+      for (int k = 0; k < c->n_inst; ++k) {
+        c->last_sweeps64[k] = g.hs[k].sweeps;
+        g.hs[k].sweeps += c->last_sweeps32[k];
+      }
+      g.all_done = g.run.all_done;
+      HIPCHK(hipMemcpyAsync(g.d_x, c->d_xbuf[0], xlen(c) * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream));
+      g.phase = 2;
+    }
+    if (!any) break;
+  }
+  int worst = QDSE_OK;
+  for (GroupEntry& g : G) {
+    HIPCHK(hipStreamSynchronize(g.c->stream));
+    g.rc = finish_solve(g.c, g.hs, g.all_done, g.iters, g.resid);
+    if (g.rc < 0 ? (worst >= 0 || g.rc < worst) : (worst == QDSE_OK && g.rc != QDSE_OK))
+      worst = g.rc;
+  }
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
 int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode, int* iters,
                double* resid) {
   if (!c || !d_x || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
   if (conv_mode != QDSE_CONV_ABS && conv_mode != QDSE_CONV_MASS) return QDSE_EINVAL;
-  hipStream_t st = c->stream;
-  c->last_sweeps32.assign(c->n_inst, 0);
-  c->last_sweeps64.assign(c->n_inst, 0);
-  HIPCHK(hipMemcpyAsync(c->d_xbuf[0], d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
-  std::vector<SolveState> hs;
-  bool all_done = false;
-  if (c->precision == QDSE_FP32_REFINE) {
-    // FP32 matrix-core sweeps down to the switch tolerance, then FP64 sweeps
-    double tol32 = 1e-6;
-    if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
-    if (tol32 < tol) tol32 = tol;
-    int rc = run_masked(c, tol32, max_iter, conv_mode, SWEEP_MM32, hs, &all_done);
-    if (rc) return rc;
-    for (int k = 0; k < c->n_inst; ++k) c->last_sweeps32[k] = hs[k].sweeps;
-  } else if (c->precision == QDSE_FP64) {
+  if (c->precision == QDSE_FP64 && c->persist_G > 0 && std::getenv("QDSE_PERSISTENT") != nullptr) {
+    hipStream_t st = c->stream;
+    c->last_sweeps32.assign(c->n_inst, 0);
+    c->last_sweeps64.assign(c->n_inst, 0);
+    HIPCHK(hipMemcpyAsync(c->d_xbuf[0], d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
+                          st));
     SolveCtl ctl{tol, conv_mode, max_iter};
     HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
     HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
-    if (c->persist_G > 0 && std::getenv("QDSE_PERSISTENT") != nullptr) {
-      int rc = solve_persistent(c, d_x, iters, resid);
-      if (rc >= 0 && c->n_inst > 0) {
-        // sweeps are reported through iters; keep the breakdown too
-        std::vector<SolveState> h2(c->n_inst);
-        (void)hipMemcpy(h2.data(), c->d_state, h2.size() * sizeof(SolveState),
-                        hipMemcpyDeviceToHost);
-        for (int k = 0; k < c->n_inst; ++k) c->last_sweeps64[k] = h2[k].sweeps;
-      }
-      return rc;
+    int rc = solve_persistent(c, d_x, iters, resid);
+    if (rc >= 0 && c->n_inst > 0) {
+      std::vector<SolveState> h2(c->n_inst);
+      (void)hipMemcpy(h2.data(), c->d_state, h2.size() * sizeof(SolveState),
+                      hipMemcpyDeviceToHost);
+      for (int k = 0; k < c->n_inst; ++k) c->last_sweeps64[k] = h2[k].sweeps;
     }
+    return rc;
   }
-  const int kind = c->precision == QDSE_FP64 ? SWEEP_DIRECT : SWEEP_MM64;
-  int rc = run_masked(c, tol, max_iter, conv_mode, kind, hs, &all_done);
-  if (rc) return rc;
-  for (int k = 0; k < c->n_inst; ++k) {
-    c->last_sweeps64[k] = hs[k].sweeps;
-    hs[k].sweeps += c->last_sweeps32[k];
+  std::vector<GroupEntry> G(1);
+  G[0].c = c;
+  G[0].d_x = d_x;
+  G[0].iters = iters;
+  G[0].resid = resid;
+  return solve_group(G, tol, max_iter, conv_mode);
+}
+
+int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int max_iter,
+                     int conv_mode, int** iters, double** resid) {
+  if (!ctxs || !d_x || n_ctx < 1 || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
+  if (conv_mode != QDSE_CONV_ABS && conv_mode != QDSE_CONV_MASS) return QDSE_EINVAL;
+  std::vector<GroupEntry> G(n_ctx);
+  for (int q = 0; q < n_ctx; ++q) {
+    if (!ctxs[q] || !d_x[q]) return QDSE_EINVAL;
+    for (int p = 0; p < q; ++p)
+      if (ctxs[p] == ctxs[q]) return QDSE_EINVAL;
+    G[q].c = ctxs[q];
+    G[q].d_x = d_x[q];
+    G[q].iters = iters ? iters[q] : nullptr;
+    G[q].resid = resid ? resid[q] : nullptr;
   }
-  HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[0], xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return finish_solve(c, hs, all_done, iters, resid);
+  return solve_group(G, tol, max_iter, conv_mode);
 }
 
 int qdse_solve_stats(const qdse_ctx* c, int* sweeps_fp32, int* sweeps_fp64) {

@@ -175,6 +175,35 @@ def test_solve_converged_matches_oracle(Q):
         assert max(errs(x[k].cpu().numpy(), xr, n)) < RTOL
 
 
+def test_solve_group_equals_individual_solves(Q):
+    """qdse_solve_group over contexts with different grids and precisions, each
+    on its own stream, gives bitwise the results of solving each alone."""
+    rng = np.random.default_rng(21)
+    specs = [(64, 32, Q.QDSE_FP64), (96, 16, Q.QDSE_FP32_REFINE), (37, 7, Q.QDSE_FP64_MATRIX),
+             (130, 24, Q.QDSE_FP64)]
+    solvers, x0 = [], []
+    for n, na, prec in specs:
+        params = [(0.55, 0.678, float(m)) for m in rng.uniform(0.0, 0.1, 3)]
+        S = Q.Solver(n, na, params, precision=prec, stream=torch.cuda.Stream())
+        solvers.append(S)
+        x0.append(S.initial(1.0, 1.0))
+    torch.cuda.synchronize()
+    ref = []
+    for S, x in zip(solvers, x0):
+        y = x.clone()
+        rc, it, rs = S.solve(y, tol=1e-9, max_iter=500)
+        torch.cuda.synchronize()
+        assert rc == Q.QDSE_OK
+        ref.append((y.cpu().numpy(), it.copy()))
+    xs = [x.clone() for x in x0]
+    rc, its, rss = Q.solve_group(solvers, xs, tol=1e-9, max_iter=500)
+    torch.cuda.synchronize()
+    assert rc == Q.QDSE_OK
+    for (yr, itr), x, it in zip(ref, xs, its):
+        assert np.array_equal(x.cpu().numpy(), yr)
+        assert np.array_equal(it, itr)
+
+
 def test_solve_reports_non_convergence_and_nan(Q):
     n = 32
     S = Q.Solver(n, 16, [(0.55, 0.678, 0.005), (0.55, 0.678, 0.005)])
