@@ -171,7 +171,7 @@ def mixed_batch(Q, np, torch, B):
     return out
 
 
-def finite_mu(Q, torch):
+def finite_mu(Q, np, torch):
     """Finite mu = 0.3 GeV, T = 0, paper interaction, m = 5 MeV: external
     128 |p_vec| x 128 p4 nodes, loop 129 x 129 nodes with q4 of both signs and
     32 angles; average of 3 sweeps timed with the device synchronised."""
@@ -198,9 +198,44 @@ def finite_mu(Q, torch):
     pairs = ns * n4 * (ns + 1) * (n4 + 1)
     flops = pairs * (MU_FLOPS_PER_PAIR + MU_FLOPS_PER_ANGLE * na)
     tf = flops / dt / 1e12
+    # one complete solve from A = C = 1, B = 0.3 GeV (absolute complex change of
+    # A, B, C below 1e-8)
+    S = Q.MuSolver(ns, n4, na, [(0.55, 0.678, 0.005, 0.3)])
+    xs = x.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, it, rs = S.solve(xs, tol=1e-8, max_iter=600)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    S.close()
+    # seeded sample of the mixed workload's mu > 0 instances: mu ~ U[0, 0.4],
+    # m ~ U[0, 0.2], grid (N_r / 4)^2 with N_r in {128, ..., 512}, 64 or 128
+    # angles; per-sweep time of each (not solved here)
+    rng = np.random.default_rng(44)
+    sample = []
+    for _ in range(4):
+        g4 = int(rng.choice([128, 256, 384, 512])) // 4
+        nang = int(rng.choice([64, 128]))
+        mu, mm = float(rng.uniform(0.0, 0.4)), float(rng.uniform(0.0, 0.2))
+        S = Q.MuSolver(g4, g4, nang, [(0.55, 0.678, mm, mu)])
+        xq = torch.zeros(S.shape, dtype=torch.complex128, device="cuda")
+        xq[:, 0] = 1.0
+        xq[:, 1] = 0.3
+        xq[:, 2] = 1.0
+        yq = S.iterate(xq)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S.iterate(xq, out=yq)
+        torch.cuda.synchronize()
+        sample.append({"grid": f"{g4}x{g4}x{nang}", "mu": mu, "m": mm,
+                       "sweep_ms": 1e3 * (time.perf_counter() - t1)})
+        S.close()
     return {"workload": "mu=0.3 GeV, 128x128 external, 129x129x2 loop points x 32 angles, m=5 MeV",
             "sweep_ms": 1e3 * dt, "integrand_points_per_sweep": points,
             "integrand_points_per_s": points / dt,
+            "solve": {"rc": int(rc), "sweeps": int(it[0]), "seconds": t_solve,
+                      "solves_per_s": 1.0 / t_solve, "tol": 1e-8},
+            "mixed_workload_mu_sample": sample,
             "roofline": {"bound": "alu", "kernel": "k_mu_sweep (FP64 VALU)", "achieved": tf,
                          "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": tf / FP64_VALU_PEAK_TFLOPS, "traffic": None,
@@ -383,7 +418,7 @@ def main():
 
     # ---- finite chemical potential: one sweep of the 128 x 128 x 32 grid
     if not args.no_mu:
-        line["finite_mu"] = finite_mu(Q, torch)
+        line["finite_mu"] = finite_mu(Q, np, torch)
 
     if args.copy_calibration:
         # source written first, then 1 GiB of other data, so that the copy reads
