@@ -63,6 +63,37 @@ def counter_traffic(summary, source):
     return float(vals["fetch_bytes_per_dispatch"]) + float(vals["write_bytes_per_dispatch"])
 
 
+def paper_table1(O, np, threads):
+    """The structure of the paper's Table 1 (Sec. IV) on this host's cores:
+    the four algorithms (traditional / modified interpolation inside the loops,
+    sequential / OpenMP over external momenta, Sec. III) on the Table 1
+    workload N = 150, M = 100, D = 0.55, omega = 0.678, m = 0, A0 = B0 = 1,
+    linear interpolation, absolute test xi = 0.005. Every algorithm computes
+    the same sweep (checked bitwise in the oracle tests), so one sweep of each
+    is timed and the iteration count comes from a full solve with algorithm 4."""
+    g = O.vac_grid(150, 100, order=1)
+    p = O.Params(0.55, 0.678, 0.0)
+    x0 = np.ones(300)
+    _, iters = O.picard_paper(g, p, x0, 0.005, modified=True, nthreads=threads)
+    per = {}
+    for name, modified, th in (("alg1_traditional_sequential", False, 1),
+                               ("alg2_modified_sequential", True, 1),
+                               ("alg3_traditional_openmp", False, threads),
+                               ("alg4_modified_openmp", True, threads)):
+        t0 = time.perf_counter()
+        O.F_paper(g, p, x0, modified, th)
+        per[name] = time.perf_counter() - t0
+    a1 = per["alg1_traditional_sequential"]
+    return {
+        "workload": "N=150, M=100, D=0.55, omega=0.678, m=0, A0=B0=1, linear interpolation, xi=0.005",
+        "iterations": int(iters), "threads": threads, "seconds_per_sweep": per,
+        "estimated_solve_seconds": {k: v * iters for k, v in per.items()},
+        "speedup_vs_alg1": {k: a1 / v for k, v in per.items()},
+        "paper_seconds": {"alg1": 65, "alg2": 6, "alg3": 9, "alg4": 1,
+                          "hardware": "Intel i7 at 1.00 GHz (model not stated), GCC 9.3, OpenMP"},
+    }
+
+
 def gradient_batch(Q, np, torch, B):
     """B vacuum instances at 512 x 128 with their own interaction (one kernel
     block per instance): kappa = (D omega)^(1/3) ~ U[0.70, 0.825] GeV,
@@ -445,6 +476,7 @@ def main():
             "sample": f"one complete oracle solve of the m=5 MeV instance ({itr} sweeps, "
                       f"{tc:.1f} s, direct radial x angular sums, OpenMP over rows)",
         }
+        line["cpu_baseline"]["paper_table1"] = paper_table1(O, np, threads)
         den = np.maximum(np.abs(xr), 1e-8 * np.abs(xr).max())
         line["gpu_vs_oracle_max_rel"] = float(np.max(np.abs(xs[1] - xr) / den))
         if batch_x0 is not None:

@@ -90,8 +90,7 @@ int find_bracket(int n, const double* u, double x) {
 // order 1: the two nodes around x, constant beyond the ends (eq. chazhiresult).
 // order 3: the four nodes b-1..b+2, shifted to stay inside the grid.
 template <class T>
-T interp_one(int n, const double* u, const T* f, double x, int order) {
-  const int b = find_bracket(n, u, x);
+T interp_at(int n, const double* u, const T* f, double x, int order, int b) {
   int lo, cnt;
   if (order == 1) {
     if (b < 0) return f[0];
@@ -112,6 +111,13 @@ T interp_one(int n, const double* u, const T* f, double x, int order) {
     acc += w * f[l];
   }
   return acc;
+}
+
+// The same with the bracket found by the search above (the paper's
+// "traditional" interpolation).
+template <class T>
+T interp_one(int n, const double* u, const T* f, double x, int order) {
+  return interp_at(n, u, f, x, order, find_bracket(n, u, x));
 }
 
 double dot4(const double* a, const double* b) {
@@ -209,6 +215,44 @@ void vac_map(const qo_vac_grid* g, const qo_vac_par* par, const T* x, T* out,
   }
 }
 
+// The map as the paper organises it (Sec. III, Listing 1 / Listing 2): for
+// every external momentum, functionA and functionB each run the whole radial x
+// angular sum, and A(q^2), B(q^2) are interpolated where the integrand needs
+// them, inside the angular loop. Traditional interpolation (Sec. III A) finds
+// the bracket by searching the external grid at every call; the modified one
+// takes it from the interleaving of eq. pqrelationship (loop node j lies
+// between external nodes j-1 and j). Same arithmetic, in the same order, as
+// vac_map: the results are identical; only the work differs.
+double paper_function(const qo_vac_grid* g, const qo_vac_par* par, const double* x, int i,
+                      int which, int modified) {
+  const int n = g->n;
+  const double gnorm = 8.0 * PI * PI * par->D / std::pow(par->omega, 4);
+  const double om2 = par->omega * par->omega;
+  double acc = 0.0;
+  for (int j = 0; j < g->nq; ++j) {
+    const double t = g->t[j];
+    const double Wj = g->wq[j] * t * t;
+    for (int a = 0; a < g->na; ++a) {
+      double Aq, Bq;
+      if (modified) {
+        Aq = interp_at(n, g->u, x, g->uq[j], g->order, j - 1);
+        Bq = interp_at(n, g->u, x + n, g->uq[j], g->order, j - 1);
+      } else {
+        Aq = interp_one(n, g->u, x, g->uq[j], g->order);
+        Bq = interp_one(n, g->u, x + n, g->uq[j], g->order);
+      }
+      const double Dq = t * Aq * Aq + Bq * Bq;
+      const double z = g->z[a];
+      double IA, IB, k2;
+      integrand(g->s[i], t, z, x[i], x[n + i], Aq, Bq, par->lam, &IA, &IB, &k2);
+      const double gk = gnorm * std::exp(-k2 / om2);
+      const double w = Wj * g->wz[a] * std::sqrt(1.0 - z * z) * gk;
+      acc += w * (which == 0 ? IA : IB) / Dq;
+    }
+  }
+  return acc;
+}
+
 int check_grid(const qo_vac_grid* g) {
   if (!g || g->n < 2 || g->nq < 1 || g->na < 1) return -1;
   if (g->order != 1 && g->order != 3) return -1;
@@ -229,6 +273,22 @@ int qo_vac_map(const qo_vac_grid* g, const qo_vac_par* par, const double* x_in,
 }
 
 // Rows rows[0..nrows-1] of F(x_in): out[r] = A'(rows[r]), out[nrows+r] = B'.
+// One sweep in the paper's organisation (see paper_function): modified = 0
+// traditional interpolation, 1 modified; nthreads = 1 sequential (Listing 1),
+// more: OpenMP over external momenta (Listing 2).
+int qo_vac_map_paper(const qo_vac_grid* g, const qo_vac_par* par, const double* x_in,
+                     double* x_out, int modified, int nthreads) {
+  if (check_grid(g) || !par || !x_in || !x_out || nthreads < 1) return -1;
+  const double c = (4.0 / 3.0) / (8.0 * PI * PI * PI);
+  const int n = g->n;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int i = 0; i < n; ++i) {
+    x_out[i] = 1.0 + c * paper_function(g, par, x_in, i, 0, modified);
+    x_out[n + i] = par->m + c * paper_function(g, par, x_in, i, 1, modified);
+  }
+  return 0;
+}
+
 int qo_vac_map_rows(const qo_vac_grid* g, const qo_vac_par* par, const double* x_in,
                     const int* rows, int nrows, double* out, int nthreads) {
   if (check_grid(g)) return -1;

@@ -89,6 +89,7 @@ def lib():
         gp, pp = ctypes.POINTER(_Grid), ctypes.POINTER(_Par)
         L.qo_vac_map.argtypes = [gp, pp, dp, dp, ctypes.c_int]
         L.qo_vac_map_rows.argtypes = [gp, pp, dp, ip, ctypes.c_int, dp, ctypes.c_int]
+        L.qo_vac_map_paper.argtypes = [gp, pp, dp, dp, ctypes.c_int, ctypes.c_int]
         L.qo_vac_jvp.argtypes = [gp, pp, dp, dp, dp, ctypes.c_int]
         L.qo_vac_map_c.argtypes = [gp, pp, dp, dp, dp, dp, ctypes.c_int]
         L.qo_interp.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp, ip]
@@ -226,6 +227,38 @@ def F(g: VacGrid, p: Params, x: np.ndarray, nthreads: int | None = None) -> np.n
     if rc:
         raise ValueError("oracle: bad grid")
     return out
+
+
+def F_paper(g: VacGrid, p: Params, x: np.ndarray, modified: bool, nthreads: int = 1) -> np.ndarray:
+    """One sweep organised as the paper's code (Sec. III): functionA and
+    functionB per external momentum, interpolation inside the loops, with the
+    traditional bracket search (modified = False) or the bracket from eq.
+    pqrelationship (modified = True); nthreads = 1 is Listing 1, more is
+    Listing 2. Table 1's algorithms 1-4 are (False, 1), (True, 1), (False, P),
+    (True, P). Same values as F."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.shape == (2 * g.n,)
+    out = np.empty_like(x)
+    gc, pc = g._c(), p._c()
+    rc = lib().qo_vac_map_paper(ctypes.byref(gc), ctypes.byref(pc), _dp(x), _dp(out),
+                                int(bool(modified)), int(nthreads))
+    if rc:
+        raise ValueError("oracle: bad grid")
+    return out
+
+
+def picard_paper(g: VacGrid, p: Params, x0: np.ndarray, tol: float, modified: bool,
+                 nthreads: int = 1, max_iter: int = 1000):
+    """Successive approximation with F_paper and the paper's absolute per-point
+    test on A and B (Sec. II eq. jifenab2). Returns (x, iterations)."""
+    x = np.array(x0, dtype=np.float64)
+    for it in range(1, max_iter + 1):
+        xn = F_paper(g, p, x, modified, nthreads)
+        ok, _ = converged(x, xn, g.n, tol, 0)
+        x = xn
+        if ok:
+            return x, it
+    return x, max_iter
 
 
 def F_rows(g: VacGrid, p: Params, x: np.ndarray, rows, nthreads: int | None = None):

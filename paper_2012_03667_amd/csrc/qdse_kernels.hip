@@ -273,8 +273,9 @@ __device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const dou
                                           double Bi, int lane, double acc[4]) {
   // Loads of U consecutive lane strides are issued before any arithmetic so
   // that a wavefront has ~8 U loads in flight; the accumulation order per lane
-  // is still j = lane, lane + 64, ... .
-  constexpr int U = 4;
+  // is still j = lane, lane + 64, ... . U = 6 (two load rounds per row at
+  // 513 loop nodes) measured fastest among 4, 5, 6, 8.
+  constexpr int U = 6;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   for (int jb = lane; jb < nq; jb += U * WAVE) {
     double kT[U], k3[U], k0[U], Aq[U], Bq[U], sV[U], sS[U], tsV[U];

@@ -322,6 +322,38 @@ def test_table1_iteration_count():
     assert r < ref["xi"]
 
 
+def test_paper_algorithms_give_the_same_sweep():
+    """Table 1's four algorithms (traditional or modified interpolation inside
+    the loops, sequential or OpenMP over external momenta, Sec. III) compute
+    exactly the same sweep as the oracle map with interpolation hoisted out of
+    the loops; the modified bracket of eq. pqrelationship equals the searched
+    one on the interleaved grid."""
+    rng = np.random.default_rng(31)
+    for n, na, order in ((40, 16, 1), (33, 12, 3)):
+        g = O.vac_grid(n, na, order=order)
+        p = O.Params(0.55, 0.678, 0.005)
+        A, B = smooth_AB(g.s)
+        x = np.concatenate([A * (1 + 0.05 * rng.standard_normal(n)), B])
+        ref = O.F(g, p, x, nthreads=1)
+        for modified in (False, True):
+            for threads in (1, 4):
+                got = O.F_paper(g, p, x, modified, threads)
+                assert np.array_equal(got, ref), (n, order, modified, threads)
+
+
+def test_paper_algorithm_4_table1_iterations():
+    """Algorithm 4 of Table 1 (modified interpolation, OpenMP) on the Table 1
+    workload stops after 11 sweeps, like the hoisted oracle."""
+    with open(os.path.join(HERE, "golden", "table1.json")) as f:
+        ref = json.load(f)
+    n = ref["N"]
+    g = O.vac_grid(n, ref["M"])
+    x0 = np.concatenate([np.full(n, ref["A0"]), np.full(n, ref["B0"])])
+    x, it = O.picard_paper(g, O.Params(ref["D"], ref["omega"], 0.0), x0, ref["xi"],
+                           modified=True, nthreads=4)
+    assert it == ref["iterations"]
+
+
 def test_newton_reaches_picard_fixed_point():
     """At the paper's parameters successive approximation contracts; Newton on
     F(x) - x = 0 from the same start finds the same fixed point."""
