@@ -212,8 +212,8 @@ int qdse_time_contraction(qdse_ctx* ctx, int which, const double* d_x, double* d
                           double* avg_ms);
 
 /* ---------------------------------------------------------------------------
- * Finite chemical potential mu, T = 0 (the extension named in Sec. II and V of
- * the paper). Unknowns A(p~), B(p~), C(p~) are complex, p~ = (p_vec, p4 + i mu):
+ * Finite chemical potential mu, at T = 0 or at finite temperature (the
+ * extensions named in Sec. II and V of the paper). Unknowns A(p~), B(p~), C(p~) are complex, p~ = (p_vec, p4 + i mu):
  *   S^-1(p~) = i gamma_vec.p_vec A + i gamma_4 (p4 + i mu) C + B,
  * on an external grid |p_vec| (n_space Gauss-Legendre nodes in ln|p_vec| on
  * [r_min, r_max]) x p4 > 0 (n_time Gauss-Legendre nodes in v, p4 = lam4 sinh v,
@@ -237,6 +237,13 @@ typedef struct {
   int interp_order; /* 1 or 3 (per direction of the 2-D tensor stencil)    */
   double r_min, r_max;   /* |p_vec| range, GeV, 0 < r_min < r_max           */
   double p4_max, lam4;   /* p4 range [0, p4_max] and sinh-map scale, GeV    */
+  double T;              /* temperature, GeV: 0 gives the T = 0 grid above;
+                            T > 0 replaces p4 by the fermion Matsubara
+                            frequencies w_n = (2n+1) pi T, n < n_time, and
+                            the q4 integral by the sum over the same
+                            frequencies with weight 2 pi T (int dq4/(2pi) ->
+                            T sum_n); no interpolation in the time direction;
+                            p4_max and lam4 are then unused               */
 } qdse_mu_grid;
 
 typedef struct {
@@ -250,8 +257,9 @@ int qdse_mu_setup(const qdse_mu_grid* grid, const qdse_mu_params* params, int n_
 void qdse_mu_destroy(qdse_mu_ctx* ctx);
 
 /* Host-only grid arrays (any pointer may be NULL): external ps[n_space],
- * p4[n_time]; loop qs[n_space+1], q4[n_time+1] with measure weights
- * wqs = |q|^2 d|q| and wq4 = dq4 per node; angular z[n_angle], wz[n_angle]. */
+ * p4[n_time]; loop qs[n_space+1], q4[n_time+1] (q4[n_time] when T > 0) with
+ * measure weights wqs = |q|^2 d|q| and wq4 = dq4 per node (2 pi T when
+ * T > 0); angular z[n_angle], wz[n_angle]. */
 int qdse_mu_grid_nodes(const qdse_mu_grid* grid, double* ps, double* p4, double* qs,
                        double* q4, double* wqs, double* wq4, double* z, double* wz);
 

@@ -473,26 +473,37 @@ class MuGrid:
 
 
 def mu_grid(ns: int, n4: int, na: int, r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0.5,
-            order: int = 3) -> MuGrid:
+            order: int = 3, T: float = 0.0) -> MuGrid:
     """|p_vec| on GL(ns) in ln|p| over [r_min, r_max]; p4 = lam4 sinh(v) with v on
     GL(n4) over [0, asinh(p4_max/lam4)]; loop grids GL(ns+1), GL(n4+1) on the same
     intervals; angle GL(na) in cos(theta) with flat weight. Loop weights carry
-    the measure: |q|^2 d|q| = |q|^3 dln|q| and dq4 = lam4 cosh(v) dv."""
+    the measure: |q|^2 d|q| = |q|^3 dln|q| and dq4 = lam4 cosh(v) dv.
+    T > 0 (finite temperature, the paper's named extension): p4 runs over the
+    fermion Matsubara frequencies w_n = (2n+1) pi T, n < n4, the loop over the
+    same frequencies (both signs by conjugation) with weight 2 pi T, since
+    int dq4/(2 pi) f becomes T sum_n f(w_n); the time grid variable is w_n
+    itself, so interpolation in the time direction is at the nodes."""
     a, b = math.log(r_min), math.log(r_max)
     us, _ = gl_interval(ns, a, b)
     uqs, wu = gl_interval(ns + 1, a, b)
-    vmax = math.asinh(p4_max / lam4)
-    v4, _ = gl_interval(n4, 0.0, vmax)
-    vq4, wv = gl_interval(n4 + 1, 0.0, vmax)
     z, wz = gauss_legendre(na)
     ps = np.array([math.exp(t) for t in us])
     qs = np.array([math.exp(t) for t in uqs])
-    p4 = np.array([lam4 * math.sinh(t) for t in v4])
-    q4 = np.array([lam4 * math.sinh(t) for t in vq4])
     wqs = np.array([w * q * q * q for w, q in zip(wu, qs)])
-    wq4 = np.array([w * (lam4 * math.cosh(t)) for w, t in zip(wv, vq4)])
-    return MuGrid(ns, n4, na, order, ps, us, p4, v4, qs, uqs, wqs, q4, vq4, wq4, z.copy(),
-                  wz.copy())
+    if T > 0:
+        p4 = np.array([(2 * n + 1) * math.pi * T for n in range(n4)])
+        v4 = p4.copy()
+        q4, vq4 = p4.copy(), p4.copy()
+        wq4 = np.full(n4, 2 * math.pi * T)
+    else:
+        vmax = math.asinh(p4_max / lam4)
+        v4, _ = gl_interval(n4, 0.0, vmax)
+        vq4, wv = gl_interval(n4 + 1, 0.0, vmax)
+        p4 = np.array([lam4 * math.sinh(t) for t in v4])
+        q4 = np.array([lam4 * math.sinh(t) for t in vq4])
+        wq4 = np.array([w * (lam4 * math.cosh(t)) for w, t in zip(wv, vq4)])
+    return MuGrid(ns, n4, na, order, ps, us, p4, np.asarray(v4), qs, uqs, wqs, q4,
+                  np.asarray(vq4), wq4, z.copy(), wz.copy())
 
 
 def F_mu(g: MuGrid, D, omega, m, mu, x: np.ndarray, rows=None, nthreads=None):

@@ -35,7 +35,7 @@ class MuGrid(ctypes.Structure):
     _fields_ = [("n_space", ctypes.c_int), ("n_time", ctypes.c_int), ("n_angle", ctypes.c_int),
                 ("interp_order", ctypes.c_int), ("r_min", ctypes.c_double),
                 ("r_max", ctypes.c_double), ("p4_max", ctypes.c_double),
-                ("lam4", ctypes.c_double)]
+                ("lam4", ctypes.c_double), ("T", ctypes.c_double)]
 
 
 class MuParams(ctypes.Structure):
@@ -262,11 +262,13 @@ class Solver:
 
 
 def mu_grid_nodes(n_space, n_time, n_angle, interp_order=3, r_min=1e-2, r_max=1e2, p4_max=1e2,
-                  lam4=0.5):
-    """Host-only: the finite-mu grid arrays a context would use."""
+                  lam4=0.5, T=0.0):
+    """Host-only: the finite-mu grid arrays a context would use (T > 0:
+    Matsubara frequencies, loop frequencies = external ones)."""
     g = MuGrid(int(n_space), int(n_time), int(n_angle), int(interp_order), float(r_min),
-               float(r_max), float(p4_max), float(lam4))
-    sizes = (n_space, n_time, n_space + 1, n_time + 1, n_space + 1, n_time + 1, n_angle, n_angle)
+               float(r_max), float(p4_max), float(lam4), float(T))
+    nq4 = n_time if T > 0 else n_time + 1
+    sizes = (n_space, n_time, n_space + 1, nq4, n_space + 1, nq4, n_angle, n_angle)
     out = [np.empty(k) for k in sizes]
     _check(load().qdse_mu_grid_nodes(ctypes.byref(g), *[a.ctypes.data_as(_dp) for a in out]),
            "qdse_mu_grid_nodes")
@@ -295,7 +297,7 @@ class MuSolver:
     """Finite-mu context: unknowns complex128 [n_inst][3][n_space*n_time] (A, B, C)."""
 
     def __init__(self, n_space, n_time, n_angle, params, interp_order=3, r_min=1e-2, r_max=1e2,
-                 p4_max=1e2, lam4=0.5, stream=None):
+                 p4_max=1e2, lam4=0.5, T=0.0, stream=None):
         import torch
         L = load()
         self.ns, self.n4, self.na = int(n_space), int(n_time), int(n_angle)
@@ -304,7 +306,7 @@ class MuSolver:
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         g = MuGrid(self.ns, self.n4, self.na, int(interp_order), float(r_min), float(r_max),
-                   float(p4_max), float(lam4))
+                   float(p4_max), float(lam4), float(T))
         P = (MuParams * self.n_inst)(*[MuParams(*p) for p in self.params])
         h = _vp()
         _check(L.qdse_mu_setup(ctypes.byref(g), P, self.n_inst, _vp(self.stream.cuda_stream),

@@ -221,6 +221,32 @@ int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h) {
     h->qs[j] = std::exp(h->uqs[j]);
     h->wqs[j] = half * w[j] * h->qs[j] * h->qs[j] * h->qs[j];
   }
+  if (g.T > 0.0) {
+    // Matsubara frequencies w_n = (2n+1) pi T; the loop runs over the same
+    // frequencies (both signs in the sweep), weight 2 pi T each; the time
+    // stencil is the identity (lo at n, clamped so that lo + 3 < n4)
+    h->nq4 = n4;
+    const double pi = 3.14159265358979323846;
+    h->v4.resize(n4);
+    h->p4.resize(n4);
+    h->vq4.resize(n4);
+    h->q4.resize(n4);
+    h->wq4.resize(n4);
+    for (int i = 0; i < n4; ++i) {
+      h->p4[i] = (2.0 * i + 1.0) * pi * g.T;
+      h->v4[i] = h->p4[i];
+      h->q4[i] = h->p4[i];
+      h->vq4[i] = h->p4[i];
+      h->wq4[i] = 2.0 * pi * g.T;
+    }
+    h->lo_4.resize(n4);
+    h->sw_4.assign(4 * (size_t)n4, 0.0);
+    for (int i = 0; i < n4; ++i) {
+      const int lo = i < n4 - 4 ? i : n4 - 4;
+      h->lo_4[i] = lo;
+      h->sw_4[4 * (size_t)i + (i - lo)] = 1.0;
+    }
+  } else {
   // p4 = lam4 sinh(v), v Gauss-Legendre on [0, asinh(p4_max/lam4)]; dq4 = lam4 cosh(v) dv
   std::vector<double> y(n4 + 2), wy(n4 + 2);
   h->v4.resize(n4);
@@ -239,19 +265,20 @@ int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h) {
     h->q4[j] = g.lam4 * std::sinh(h->vq4[j]);
     h->wq4[j] = hv * wy[j] * (g.lam4 * std::cosh(h->vq4[j]));
   }
+  for (int i = 0; i < n4; ++i)
+    if (!(h->q4[i] < h->p4[i] && h->p4[i] < h->q4[i + 1])) return -1;
+  h->lo_4.resize(n4 + 1);
+  h->sw_4.resize(4 * (n4 + 1));
+  build_stencils(n4, g.interp_order, h->v4.data(), h->vq4.data(), h->lo_4.data(), h->sw_4.data());
+  }
   h->z.resize(na);
   h->wz.resize(na);
   gauss_legendre(na, h->z.data(), h->wz.data());
   for (int i = 0; i < ns; ++i)
     if (!(h->qs[i] < h->ps[i] && h->ps[i] < h->qs[i + 1])) return -1;
-  for (int i = 0; i < n4; ++i)
-    if (!(h->q4[i] < h->p4[i] && h->p4[i] < h->q4[i + 1])) return -1;
   h->lo_s.resize(ns + 1);
   h->sw_s.resize(4 * (ns + 1));
   build_stencils(ns, g.interp_order, h->us.data(), h->uqs.data(), h->lo_s.data(), h->sw_s.data());
-  h->lo_4.resize(n4 + 1);
-  h->sw_4.resize(4 * (n4 + 1));
-  build_stencils(n4, g.interp_order, h->v4.data(), h->vq4.data(), h->lo_4.data(), h->sw_4.data());
   return 0;
 }
 

@@ -33,7 +33,10 @@ int mu_validate(const qdse_mu_grid* g) {
   if (g->n_angle < 1 || g->n_angle > 256) return QDSE_EINVAL;
   if (g->interp_order != 1 && g->interp_order != 3) return QDSE_EINVAL;
   if (!(g->r_min > 0.0) || !(g->r_max > g->r_min) || !std::isfinite(g->r_max)) return QDSE_EINVAL;
-  if (!(g->p4_max > 0.0) || !(g->lam4 > 0.0) || !std::isfinite(g->p4_max)) return QDSE_EINVAL;
+  if (!(g->T >= 0.0) || !std::isfinite(g->T)) return QDSE_EINVAL;
+  if (g->T == 0.0 &&
+      (!(g->p4_max > 0.0) || !(g->lam4 > 0.0) || !std::isfinite(g->p4_max)))
+    return QDSE_EINVAL;
   return QDSE_OK;
 }
 

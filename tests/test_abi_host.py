@@ -94,12 +94,13 @@ def test_library_grid_is_the_oracle_grid(L, n, na, smin, smax):
     assert np.allclose(h["wz"], g.wz * np.sqrt(1 - g.z ** 2), rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("ns,n4,na", [(8, 8, 6), (128, 128, 32), (10, 7, 5)])
-def test_library_mu_grid_is_the_oracle_grid(L, ns, n4, na):
+@pytest.mark.parametrize("ns,n4,na,T", [(8, 8, 6, 0.0), (128, 128, 32, 0.0), (10, 7, 5, 0.0),
+                                        (8, 8, 6, 0.1), (64, 40, 16, 0.02)])
+def test_library_mu_grid_is_the_oracle_grid(L, ns, n4, na, T):
     import numpy as np
     import paper_2012_03667_amd as Q
     from oracle import qdse_oracle as O
-    h = Q.mu_grid_nodes(ns, n4, na, 3, 1e-2, 1e2, 1e2, 0.5)
-    g = O.mu_grid(ns, n4, na, r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0.5)
+    h = Q.mu_grid_nodes(ns, n4, na, 3, 1e-2, 1e2, 1e2, 0.5, T)
+    g = O.mu_grid(ns, n4, na, r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0.5, T=T)
     for k in ("ps", "p4", "qs", "q4", "wqs", "wq4", "z", "wz"):
         assert np.array_equal(h[k], getattr(g, k)), k

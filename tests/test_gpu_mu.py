@@ -95,3 +95,23 @@ def test_mu_solve_matches_oracle_picard(Q):
     got = x[0].cpu().numpy()
     for f in range(3):
         assert rel(got[f], xr[f]) < 1e-11
+
+
+@pytest.mark.parametrize("ns,n4,na,order,mu,T", [(8, 8, 6, 3, 0.3, 0.1), (10, 6, 5, 1, 0.0, 0.05),
+                                                  (7, 9, 4, 3, 0.2, 0.15)])
+def test_finite_temperature_sweep_matches_oracle(Q, ns, n4, na, order, mu, T):
+    """T > 0: Matsubara frequencies in p4 and in the loop (weight 2 pi T, no
+    interpolation in time), same integrand; GPU sweep vs oracle sweep."""
+    print(f"case finite-T sweep {ns}x{n4}x{na} order {order} mu {mu} T {T}", flush=True)
+    rng = np.random.default_rng(ns * 1000 + n4)
+    kw = dict(r_min=1e-2, r_max=8.0)
+    params = [(0.55, 0.678, 0.005, mu), (0.8, 0.6, 0.02, mu)]
+    S = Q.MuSolver(ns, n4, na, params, interp_order=order, T=T, **kw)
+    g = O.mu_grid(ns, n4, na, order=order, T=T, **kw)
+    xs = [smooth_mu(g, rng) for _ in params]
+    x = torch.tensor(np.stack(xs), device="cuda")
+    y = S.iterate(x).cpu().numpy()
+    for k, (D, om, m, mu_) in enumerate(params):
+        ref = O.F_mu(g, D, om, m, mu_, xs[k])
+        for f in range(3):
+            assert rel(y[k, f], ref[f]) < RTOL, (k, f, rel(y[k, f], ref[f]))
