@@ -119,11 +119,12 @@ def test_vjp_is_transpose_of_oracle_jacobian(Q):
         assert np.max(np.abs(out[k] - ref)) < 1e-11 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("n", [150, 512, 700])
+@pytest.mark.parametrize("n", [150, 512, 700, 1200])
 def test_vjp_inner_product_with_oracle_jvp(Q, n):
     """<J^T w, v> from the GPU reverse sweep equals <w, J v> with J v from the
     oracle's complex-step tangent, at grids that use each register layout of
-    the single-pass reverse kernel (loop nodes up to 256, 576 and 1088)."""
+    the single-pass reverse kernel (loop nodes up to 256, 576 and 1088) and the
+    two-pass form beyond."""
     na = 16
     params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.02)]
     S = Q.Solver(n, na, params)
@@ -303,6 +304,29 @@ def test_full_size_sampled_rows(Q):
 
 
 # ---------------------------------------------------------------- FP32 matrix-core path
+def test_large_grid_sampled_rows(Q):
+    """A grid four times the benchmark's (2048 radial nodes, 2049 loop nodes):
+    long matrix rows, many row blocks and a batch of three instances; sampled
+    rows against the oracle, plus a sweep of the FP64 matrix-core path on the
+    same rows."""
+    n, na = 2048, 8
+    rng = np.random.default_rng(2048)
+    rows = np.sort(np.concatenate([[0, 1, 1023, 2046, 2047], rng.choice(n, 7, replace=False)]))
+    g = oracle_grid(n, na, 3)
+    params = [(0.55, 0.678, 0.005), (0.55, 0.678, 0.0), (0.55, 0.678, 0.05)]
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    for prec in (Q.QDSE_FP64, Q.QDSE_FP64_MATRIX):
+        S = Q.Solver(n, na, params, precision=prec)
+        xt = torch.tensor(xs, device="cuda")
+        y = (S.iterate(xt) if prec == Q.QDSE_FP64 else S.iterate(xt, matrix=True)).cpu().numpy()
+        for k, (D, om, m) in enumerate(params):
+            a, b = O.F_rows(g, O.Params(D, om, m), xs[k], rows)
+            ref = np.concatenate([a, b])
+            got = np.concatenate([y[k, rows], y[k, n + rows]])
+            assert max(errs(got, ref, len(rows))) < RTOL, (prec, k)
+        S.close()
+
+
 def test_fp32_sweep_close_to_oracle(Q):
     """One FP32 sweep (split form on the matrix cores, FP32 accumulation) against
     the FP64 oracle. FP32 rounding (6e-8) of O(N) accumulated terms, amplified by
