@@ -266,6 +266,7 @@ def finite_mu(Q, np, torch):
             "integrand_points_per_s": points / dt,
             "solve": {"rc": int(rc), "sweeps": int(it[0]), "seconds": t_solve,
                       "solves_per_s": 1.0 / t_solve, "tol": 1e-8},
+
             "mixed_workload_mu_sample": sample,
             "roofline": {"bound": "alu", "kernel": "k_mu_sweep (FP64 VALU)", "achieved": tf,
                          "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -274,6 +274,19 @@ int qdse_mu_iterate(qdse_mu_ctx* ctx, const double* d_x_in, double* d_x_out);
 int qdse_mu_solve(qdse_mu_ctx* ctx, double* d_x, double tol, int max_iter, int* iters,
                   double* resid);
 
+/* The same fixed point found with Anderson mixing of depth `depth` (0..16;
+ * 0 is plain successive approximation): with g = F(x) and f = g - x at the
+ * current iterate, the next iterate is g - dG gamma, where dG, dF hold the
+ * differences of the last `depth` images and residuals and gamma minimises
+ * |f - dF gamma| (real coefficients on the real and imaginary parts). The
+ * stopping test and outputs are those of qdse_mu_solve (iters counts sweeps);
+ * a converged instance returns F(x) of its last iterate. The paper iterates
+ * plainly; the mixing only reaches the same fixed point in fewer sweeps where
+ * successive approximation contracts slowly. Allocates its history on the
+ * device per call; synchronises the stream. */
+int qdse_mu_solve_anderson(qdse_mu_ctx* ctx, double* d_x, double tol, int max_iter, int depth,
+                           int* iters, double* resid);
+
 /* Human-readable name of a status code. */
 const char* qdse_strerror(int code);
 

@@ -87,6 +87,8 @@ def load():
     L.qdse_mu_grid_nodes.argtypes = [ctypes.POINTER(MuGrid)] + [_dp] * 8
     L.qdse_mu_iterate.argtypes = [_vp, _vp, _vp]
     L.qdse_mu_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]
+    L.qdse_mu_solve_anderson.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         _ip, _dp]
     L.qdse_strerror.argtypes = [ctypes.c_int]
     L.qdse_strerror.restype = ctypes.c_char_p
     L.qdse_last_error.argtypes = []
@@ -342,10 +344,16 @@ class MuSolver:
                "qdse_mu_iterate")
         return out
 
-    def solve(self, x, tol=1e-10, max_iter=500):
+    def solve(self, x, tol=1e-10, max_iter=500, anderson=None):
+        """In place; anderson = depth m uses qdse_mu_solve_anderson."""
         it = np.zeros(self.n_inst, dtype=np.int32)
         rs = np.zeros(self.n_inst)
-        rc = load().qdse_mu_solve(self._h, self._cdev(x, "x"), float(tol), int(max_iter),
-                                  it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
+        if anderson is None:
+            rc = load().qdse_mu_solve(self._h, self._cdev(x, "x"), float(tol), int(max_iter),
+                                      it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
+        else:
+            rc = load().qdse_mu_solve_anderson(self._h, self._cdev(x, "x"), float(tol),
+                                               int(max_iter), int(anderson),
+                                               it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
         _check(rc, "qdse_mu_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
         return rc, it, rs

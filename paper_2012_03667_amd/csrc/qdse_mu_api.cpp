@@ -2,6 +2,7 @@
 // context set-up, sweeps and the successive-approximation driver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -217,6 +218,176 @@ int qdse_mu_solve(qdse_mu_ctx* c, double* d_x, double tol, int max_iter, int* it
       hipStreamSynchronize(st) != hipSuccess)
     return QDSE_EDEVICE;
   for (int q = 0; q < c->n_inst; ++q) {
+    if (iters) iters[q] = it[q];
+    if (resid) resid[q] = res[q];
+  }
+  return rc;
+}
+
+int qdse_mu_solve_anderson(qdse_mu_ctx* c, double* d_x, double tol, int max_iter, int depth,
+                           int* iters, double* resid) {
+  if (!c || !d_x || !(tol > 0.0) || max_iter < 1 || depth < 0 || depth > 16) return QDSE_EINVAL;
+  hipStream_t st = c->stream;
+  const HostMuGrid& h = c->hg;
+  const int ne = h.ns * h.n4;
+  const size_t L = (size_t)3 * ne * 2;  // doubles per instance (complex as pairs)
+  const int nI = c->n_inst, m = depth;
+  // per instance: x, g = F(x), f = g - x, previous f and g, and the histories
+  // dF[m], dG[m] of their differences (ring buffers)
+  std::vector<double*> bufs;
+  auto alloc = [&](double** p, size_t n) -> int {
+    if (hipMalloc((void**)p, n * sizeof(double)) != hipSuccess) {
+      *p = nullptr;
+      return QDSE_ENOMEM;
+    }
+    bufs.push_back(*p);
+    return QDSE_OK;
+  };
+  struct Free {
+    std::vector<double*>& b;
+    ~Free() {
+      for (double* p : b) (void)hipFree(p);
+    }
+  } guard{bufs};
+  double *d_g, *d_f, *d_fp, *d_gp, *d_dF, *d_dG, *d_dot;
+  int rc;
+  if ((rc = alloc(&d_g, L * nI)) || (rc = alloc(&d_f, L * nI)) || (rc = alloc(&d_fp, L * nI)) ||
+      (rc = alloc(&d_gp, L * nI)) || (rc = alloc(&d_dF, L * nI * (m > 0 ? m : 1))) ||
+      (rc = alloc(&d_dG, L * nI * (m > 0 ? m : 1))) || (rc = alloc(&d_dot, (size_t)(m + 1) * (m + 1))))
+    return rc;
+  double* d_xc = c->d_xb[0];
+  if (hipMemcpyAsync(d_xc, d_x, mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+      hipSuccess)
+    return QDSE_EDEVICE;
+  std::vector<int> done(nI, 0), it(nI, 0), hist(nI, 0), head(nI, 0);
+  std::vector<double> res(nI, INFINITY);
+  std::vector<unsigned long long> bits(nI);
+  std::vector<double> G((size_t)(m + 1) * (m + 1)), gam(m > 0 ? m : 1);
+  rc = QDSE_NOT_CONVERGED;
+  for (int k = 1; k <= max_iter; ++k) {
+    // g = F(x) for the running instances, statistic max |g - x|
+    std::vector<unsigned long long> zero(nI, 0ull);
+    if (hipMemcpyAsync(c->d_stat, zero.data(), zero.size() * sizeof(unsigned long long),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+      return QDSE_EDEVICE;
+    if (int e = mu_sweep(c, d_xc, d_g, &done)) return e;
+    if (launch_mu_stat(st, nI, ne, d_xc, d_g, c->d_stat) != hipSuccess) return QDSE_EDEVICE;
+    if (hipMemcpyAsync(bits.data(), c->d_stat, nI * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return QDSE_EDEVICE;
+    bool all = true, bad = false;
+    for (int q = 0; q < nI; ++q) {
+      if (done[q]) continue;
+      double r;
+      std::memcpy(&r, &bits[q], sizeof(double));
+      it[q] = k;
+      res[q] = r;
+      if (!(r <= 1.7976931348623157e308)) bad = true;
+      else if (r < tol) done[q] = 2;  // the image g is returned for this instance
+      if (!done[q]) all = false;
+    }
+    if (bad) {
+      rc = QDSE_ENAN;
+      break;
+    }
+    for (int q = 0; q < nI; ++q) {
+      double* xq = d_xc + q * L;
+      double* gq = d_g + q * L;
+      if (done[q] == 2) {  // converged on this sweep: keep F(x)
+        if (hipMemcpyAsync(xq, gq, L * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+          return QDSE_EDEVICE;
+        done[q] = 1;
+        continue;
+      }
+      if (done[q]) continue;
+      double* fq = d_f + q * L;
+      double* fpq = d_fp + q * L;
+      double* gpq = d_gp + q * L;
+      double* dFq = d_dF + (size_t)q * m * L;
+      double* dGq = d_dG + (size_t)q * m * L;
+      if (launch_axpby(st, 1, (int)L, -1.0, xq, nullptr, gq, fq) != hipSuccess)  // f = g - x
+        return QDSE_EDEVICE;
+      if (m > 0 && k > 1) {  // new history column: f - f_prev, g - g_prev
+        const int slot = head[q];
+        if (launch_axpby(st, 1, (int)L, -1.0, fpq, nullptr, fq, dFq + slot * L) != hipSuccess ||
+            launch_axpby(st, 1, (int)L, -1.0, gpq, nullptr, gq, dGq + slot * L) != hipSuccess)
+          return QDSE_EDEVICE;
+        head[q] = (slot + 1) % m;
+        if (hist[q] < m) ++hist[q];
+      }
+      if (m > 0 &&
+          (hipMemcpyAsync(fpq, fq, L * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+           hipMemcpyAsync(gpq, gq, L * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess))
+        return QDSE_EDEVICE;
+      const int mk = hist[q];
+      if (mk == 0) {  // plain successive approximation step
+        if (hipMemcpyAsync(xq, gq, L * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+          return QDSE_EDEVICE;
+        continue;
+      }
+      // least squares min |f - dF gamma|: normal equations dF^T dF gamma = dF^T f
+      for (int a = 0; a < mk; ++a)
+        if (launch_batched_dot(st, 1, (int)L, dFq, L, dFq + a * L, L, mk,
+                               d_dot + (size_t)a * mk) != hipSuccess)
+          return QDSE_EDEVICE;
+      if (launch_batched_dot(st, 1, (int)L, dFq, L, fq, L, mk, d_dot + (size_t)mk * mk) !=
+          hipSuccess)
+        return QDSE_EDEVICE;
+      if (hipMemcpyAsync(G.data(), d_dot, (size_t)(mk + 1) * mk * sizeof(double),
+                         hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return QDSE_EDEVICE;
+      // G[a * mk + b] = <dF_b, dF_a>; rhs[b] = G[mk * mk + b]; Tikhonov shift
+      // of 1e-14 of the largest diagonal keeps nearly dependent columns solvable
+      std::vector<double> Aq((size_t)mk * mk), bq(mk);
+      double dmax = 0.0;
+      for (int a = 0; a < mk; ++a) dmax = std::fmax(dmax, G[(size_t)a * mk + a]);
+      for (int a = 0; a < mk; ++a) {
+        for (int b = 0; b < mk; ++b) Aq[(size_t)a * mk + b] = G[(size_t)a * mk + b];
+        Aq[(size_t)a * mk + a] += 1e-14 * dmax;
+        bq[a] = G[(size_t)mk * mk + a];
+      }
+      for (int a = 0; a < mk; ++a) {  // Gaussian elimination with partial pivoting
+        int piv = a;
+        for (int r = a + 1; r < mk; ++r)
+          if (std::fabs(Aq[(size_t)r * mk + a]) > std::fabs(Aq[(size_t)piv * mk + a])) piv = r;
+        if (piv != a) {
+          for (int b = 0; b < mk; ++b) std::swap(Aq[(size_t)a * mk + b], Aq[(size_t)piv * mk + b]);
+          std::swap(bq[a], bq[piv]);
+        }
+        const double d = Aq[(size_t)a * mk + a];
+        if (d == 0.0) continue;
+        for (int r = a + 1; r < mk; ++r) {
+          const double f = Aq[(size_t)r * mk + a] / d;
+          for (int b = a; b < mk; ++b) Aq[(size_t)r * mk + b] -= f * Aq[(size_t)a * mk + b];
+          bq[r] -= f * bq[a];
+        }
+      }
+      for (int a = mk - 1; a >= 0; --a) {
+        double acc = bq[a];
+        for (int b = a + 1; b < mk; ++b) acc -= Aq[(size_t)a * mk + b] * gam[b];
+        const double d = Aq[(size_t)a * mk + a];
+        gam[a] = d != 0.0 ? acc / d : 0.0;
+      }
+      // x = g - dG gamma
+      for (int a = 0; a < mk; ++a) gam[a] = -gam[a];
+      if (hipMemcpyAsync(xq, gq, L * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(d_dot, gam.data(), mk * sizeof(double), hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          launch_combine(st, 1, (int)L, dGq, L, mk, d_dot, mk, 1.0, xq) != hipSuccess)
+        return QDSE_EDEVICE;
+    }
+    if (all) {
+      rc = QDSE_OK;
+      break;
+    }
+  }
+  if (hipMemcpyAsync(d_x, d_xc, mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return QDSE_EDEVICE;
+  for (int q = 0; q < nI; ++q) {
     if (iters) iters[q] = it[q];
     if (resid) resid[q] = res[q];
   }

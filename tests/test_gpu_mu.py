@@ -115,3 +115,35 @@ def test_finite_temperature_sweep_matches_oracle(Q, ns, n4, na, order, mu, T):
         ref = O.F_mu(g, D, om, m, mu_, xs[k])
         for f in range(3):
             assert rel(y[k, f], ref[f]) < RTOL, (k, f, rel(y[k, f], ref[f]))
+
+
+@pytest.mark.parametrize("depth", [0, 5])
+def test_mu_anderson_solve_reaches_oracle_fixed_point(Q, depth):
+    """Anderson mixing (qdse_mu_solve_anderson) reaches the oracle's Picard
+    fixed point; depth 0 is plain successive approximation; depth 5 needs
+    fewer sweeps."""
+    ns, n4, na, mu = 8, 8, 6, 0.3
+    kw = dict(r_min=1e-2, r_max=8.0, p4_max=8.0)
+    S = Q.MuSolver(ns, n4, na, [(0.55, 0.678, 0.005, mu), (0.55, 0.678, 0.05, mu)], **kw)
+    g = O.mu_grid(ns, n4, na, **kw)
+    x = torch.zeros(S.shape, dtype=torch.complex128, device="cuda")
+    x[:, 0] = 1.0
+    x[:, 1] = 0.3
+    x[:, 2] = 1.0
+    rc, it, rs = S.solve(x, tol=1e-12, max_iter=400, anderson=depth)
+    assert rc == Q.QDSE_OK, (rc, it, rs)
+    for k, m in enumerate((0.005, 0.05)):
+        xr = np.zeros((3, g.ne), complex)
+        xr[0], xr[1], xr[2] = 1.0, 0.3, 1.0
+        for n_sw in range(1, 401):
+            xn = O.F_mu(g, 0.55, 0.678, m, mu, xr)
+            r = np.max(np.abs(xn - xr))
+            xr = xn
+            if r < 1e-13:
+                break
+        got = x[k].cpu().numpy()
+        for f in range(3):
+            assert rel(got[f], xr[f]) < 1e-10, (k, f, rel(got[f], xr[f]))
+        if depth:
+            assert it[k] < 0.6 * n_sw, (it[k], n_sw)
+
