@@ -24,11 +24,13 @@
 // Node functions (with the denominator t A^2 + B^2), the combination above,
 // the update and the test statistic are FP64 in both.
 //
-// Tiling: a workgroup of two wavefronts owns 16 rows x 32 instances in blocks
-// of 16 x 16, eight products each (RB = 1 row block per wavefront measured
-// fastest for both element types: more workgroups, more overlap); the two
-// wavefronts split the loop nodes in halves and their partial products are
-// added through LDS before the FP64 epilogue. Operands are read straight from L2/L1 in layouts where a
+// Tiling: a workgroup of four wavefronts owns 32 rows x 32 instances: two row
+// groups of 16 rows (they read the same node-column panel, the second read
+// served from the CU's L1), each split over the loop nodes in two halves
+// whose partial products are added through LDS before the FP64 epilogue; a
+// wavefront accumulates 16 rows x 32 instances in blocks of 16 x 16, eight
+// products each (one 16-row block per wavefront measured fastest for both
+// element types; four row groups per workgroup measured no faster). Operands are read straight from L2/L1 in layouts where a
 // 16-lane group reads contiguous memory, with the next k-step prefetched.
 //
 // Layouts (zero padded): MT[x][j][ldi] (x = 0..4, rows contiguous),
@@ -45,6 +47,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr double kMassFloorM = 1e-8;  // GeV, as in the FP64 sweep
 constexpr int TM_MAX = 32, TN = 32, KSPLIT = 2, KSTEP = 4;
+constexpr int RH = 2;  // row groups per workgroup (they share the node-column panel)
 
 template <class T> struct Mfma;
 // Output layout of one 16x16 block: register e of lane l holds row
@@ -173,21 +176,22 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
 }
 
 template <class T>
-__global__ void __launch_bounds__(128) k_mm_sweep(
+__global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
     int n_inst, int n, int nq_pad, int ldi, int ldb, const T* __restrict__ MT, size_t mstride,
     const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
     const double* __restrict__ s_, const double* __restrict__ x_in, double* __restrict__ x_out,
     SolveState* state, const SolveCtl* ctl, int k) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int RB = Mfma<T>::RB, TM = 16 * RB;
-  __shared__ acc_t part[8][RB][2][64];  // second wavefront's partial products
+  __shared__ acc_t part[RH][8][RB][2][64];  // partial products of the second K half
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop
+  const int kh = wave % KSPLIT, rh = wave / KSPLIT;
   // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs
   // (workgroup w to XCD w % 8). When the instance blocks divide evenly, XCD x
   // owns the instance blocks ib = x (mod 8) and walks their row blocks, so a
   // node-column panel is fetched into one XCD's L2 and reused from there.
-  const int n_rb = ldi / TM, n_ib = ldb / TN;
+  const int n_rb = ldi / (TM * RH), n_ib = ldb / TN;
   const int w = blockIdx.x;
   int rb, ib;
   if (n_ib % 8 == 0) {
@@ -198,15 +202,16 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
     rb = w % n_rb;
     ib = w / n_rb;
   }
-  const int i0 = rb * TM, b0 = ib * TN;
+  const int ib0 = rb * TM * RH;  // first row of the workgroup
+  const int i0 = ib0 + rh * TM, b0 = ib * TN;
   if (state) {
     // every instance of this column block frozen (or absent): carry the
-    // iterate along and skip the contraction (both wavefronts agree)
+    // iterate along and skip the contraction (all wavefronts agree)
     bool frozen = true;
     if (lane < TN) frozen = b0 + lane >= n_inst || state[b0 + lane].status != 0;
     if (__all(frozen)) {
-      for (int e = threadIdx.x; e < TM * TN; e += 64 * KSPLIT) {
-        const int inst = b0 + e / TM, i = i0 + e % TM;
+      for (int e = threadIdx.x; e < TM * RH * TN; e += 64 * KSPLIT * RH) {
+        const int inst = b0 + e / (TM * RH), i = ib0 + e % (TM * RH);
         if (inst < n_inst && i < n) {
           const size_t o = (size_t)inst * 2 * n;
           x_out[o + i] = x_in[o + i];
@@ -218,7 +223,7 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
   }
   const int lr = lane & 15, lk = lane >> 4;
   const int half = nq_pad / KSPLIT;  // a multiple of KSTEP
-  const int kb = wave * half, ke = kb + half;
+  const int kb = kh * half, ke = kb + half;
   acc_t acc[8][RB][2];
 #pragma unroll
   for (int p = 0; p < 8; ++p)
@@ -276,22 +281,22 @@ __global__ void __launch_bounds__(128) k_mm_sweep(
   }
   mma(a, c);
   // add the second half's partial products (fixed order: half 0 + half 1)
-  if (wave == 1) {
+  if (kh == 1) {
 #pragma unroll
     for (int p = 0; p < 8; ++p)
 #pragma unroll
       for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) part[p][r][cb][lane] = acc[p][r][cb];
+        for (int cb = 0; cb < 2; ++cb) part[rh][p][r][cb][lane] = acc[p][r][cb];
   }
   __syncthreads();
-  if (wave == 1) return;
+  if (kh == 1) return;
 #pragma unroll
   for (int p = 0; p < 8; ++p)
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[p][r][cb] += part[p][r][cb][lane];
+      for (int cb = 0; cb < 2; ++cb) acc[p][r][cb] += part[rh][p][r][cb][lane];
   // Epilogue (FP64)
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) {
@@ -383,13 +388,13 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
   if (nodes)
     hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
                        n, nq, L.ldb, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
-  const dim3 grid((L.ldi / (16 * Mfma<T>::RB)) * (L.ldb / TN));
+  const dim3 grid((L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN));
   if (ev0)
-    hipExtLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT), 0, st, ev0, ev1, 0, n_inst, n,
+    hipExtLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT * RH), 0, st, ev0, ev1, 0, n_inst, n,
                           L.nq_pad, L.ldi, L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s,
                           x_in, x_out, state, ctl, k);
   else
-    hipLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT), 0, st, n_inst, n, L.nq_pad, L.ldi,
+    hipLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT * RH), 0, st, n_inst, n, L.nq_pad, L.ldi,
                        L.ldb, MT, L.mstride, C, L.cstride, inst, s, x_in, x_out, state, ctl, k);
   return hipGetLastError();
 }
