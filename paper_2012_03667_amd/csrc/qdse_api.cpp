@@ -73,7 +73,6 @@ struct qdse_ctx {
   float* d_C32 = nullptr;
   double* d_M64 = nullptr;
   double* d_C64 = nullptr;
-  hipGraphExec_t graph32_exec = nullptr, graphmm_exec = nullptr;
   std::vector<int> last_sweeps32, last_sweeps64;
   InstDev* d_inst = nullptr;
   double* d_nodes = nullptr;  // [n_inst][10][ldk]
@@ -82,11 +81,12 @@ struct qdse_ctx {
   SolveCtl* d_ctl = nullptr;
   // graph of a chunk of masked sweeps; pinned copies of the solve state of
   // the last two chunks, with their completion events
-  hipGraphExec_t graph_exec = nullptr;
+  std::vector<std::pair<int, hipGraphExec_t>> graphs[3];  // per sweep kind: (length, graph)
   int chunk = 24;       // sweeps per graph launch, FP64 direct sweeps (multiple of 6)
   int chunk_mm = 12;    // the same for matrix-core sweeps (masked sweeps cost more)
   int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
-  SolveState* h_state = nullptr;  // [2][n_inst], hipHostMalloc
+  SolveState* h_state = nullptr;  // [2][n_inst], hipHostMalloc; [0] is the sweeps' mirror
+  SolveState* d_mirror = nullptr;  // device address of h_state
   hipEvent_t ev[2] = {nullptr, nullptr};
   // persistent solve: per-sweep statistics, grid-barrier counter, flags
   unsigned long long* d_slots = nullptr;
@@ -222,7 +222,12 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
     g_last_error = "hipHostMalloc failed";
     qdse_destroy(c);
     return QDSE_ENOMEM;
+  }  if (hipHostGetDevicePointer((void**)&c->d_mirror, c->h_state, 0) != hipSuccess) {
+    g_last_error = "hipHostGetDevicePointer failed";
+    qdse_destroy(c);
+    return QDSE_EDEVICE;
   }
+
   for (int q = 0; q < 2; ++q)
     if (hipEventCreateWithFlags(&c->ev[q], hipEventDisableTiming) != hipSuccess) {
       c->ev[q] = nullptr;
@@ -323,9 +328,8 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
 
 void qdse_destroy(qdse_ctx* c) {
   if (!c) return;
-  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-  if (c->graph32_exec) (void)hipGraphExecDestroy(c->graph32_exec);
-  if (c->graphmm_exec) (void)hipGraphExecDestroy(c->graphmm_exec);
+  for (auto& v : c->graphs)
+    for (auto& e : v) (void)hipGraphExecDestroy(e.second);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -430,89 +434,168 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
   return QDSE_OK;
 }
 
-// Masked sweeps from xbuf[0] until every instance is frozen, as a stepper
-// so that several contexts (each on its own stream) can be driven together:
-// begin() prepares one phase (tolerance, sweep kind, graph of `chunk`
-// sweeps), launch() enqueues one chunk followed by an asynchronous copy of the
-// solve state into pinned memory and an event, wait() blocks on the last
-// chunk's event and decides whether the phase is over. The iterate always
-// ends in xbuf[0] (chunks are multiples of 6 sweeps: even, and the three
-// statistic slots come back to the same position).
-struct MaskedRun {
-  qdse_ctx* c = nullptr;
-  int kind = 0, chunk = 12, slot = 0;
-  long launched = 0, limit = 0;
-  bool use_graph = true, all_done = false;
+// Graph of `len` masked sweeps of one kind, instantiated on first use and
+// kept for the life of the context.
+static int chunk_graph(qdse_ctx* c, int kind, int len, hipGraphExec_t* out) {
+  for (const auto& e : c->graphs[kind])
+    if (e.first == len) {
+      *out = e.second;
+      return QDSE_OK;
+    }
+  if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph;
+  HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = record_chunk(c, c->cap_stream, len, kind);
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  if (rc) return rc;
+  HIPCHK(e);
   hipGraphExec_t exec = nullptr;
-};
-
-static int masked_begin(MaskedRun& r, qdse_ctx* c, double tol, int max_iter, int conv_mode,
-                        int kind) {
-  r.c = c;
-  r.kind = kind;
-  r.chunk = kind == SWEEP_DIRECT ? c->chunk : c->chunk_mm;
-  r.use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
-  r.launched = 0;
-  r.limit = (long)max_iter + 1 + r.chunk;
-  r.all_done = false;
-  hipStream_t st = c->stream;
-  SolveCtl ctl{tol, conv_mode, max_iter};
-  HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
-  HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
-  hipGraphExec_t& exec = kind == SWEEP_MM32   ? c->graph32_exec
-                         : kind == SWEEP_MM64 ? c->graphmm_exec
-                                              : c->graph_exec;
-  if (r.use_graph && !exec) {
-    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    hipGraph_t graph;
-    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = record_chunk(c, c->cap_stream, r.chunk, kind);
-    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
-    if (rc) return rc;
-    HIPCHK(e);
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    HIPCHK(e);
-  }
-  r.exec = exec;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(e);
+  c->graphs[kind].push_back({len, exec});
+  *out = exec;
   return QDSE_OK;
 }
 
-static int masked_launch(MaskedRun& r) {
+// Masked sweeps from xbuf[0] until every instance is frozen, as a stepper
+// so that several contexts (each on its own stream) can be driven together.
+// begin() starts one phase (tolerance, sweep kind) and enqueues the first
+// two chunks; a chunk is a graph of a multiple of 6 sweeps followed by an
+// event, so the iterate ends every chunk in xbuf[0] and the three statistic
+// slots come back to the same position. The deciding block of the last sweep
+// of every chunk writes each instance's state into a pinned host mirror (no
+// copies in the stream). wait() blocks on the oldest chunk in flight and, unless the phase
+// is over, enqueues the next chunk while the other one runs: its length is
+// the number of sweeps the slowest running instance still needs, predicted
+// from the decay of its test statistic, minus the sweeps already enqueued
+// (at least 6 when nothing is in flight, at most the first chunk's length). The GPU thus never waits for the
+// host between chunks, and a phase ends a few frozen sweeps (a frozen sweep
+// only copies its rows) after the last instance freezes. Results do not
+// depend on the chunking.
+struct MaskedRun {
+  qdse_ctx* c = nullptr;
+  int kind = 0, first = 24;
+  double tol = 0.0;
+  long launched = 0, limit = 0;  // sweeps enqueued; sweeps that freeze every instance
+  bool use_graph = true, all_done = false;
+  int q_len[2] = {0, 0}, q_ev[2] = {0, 0}, nq = 0;  // chunks in flight, oldest first
+  int next_ev = 0;
+  std::vector<SolveState> snap;  // mirror as read at the last wait
+  std::vector<double> r_prev;    // statistic of each instance at the previous read
+  std::vector<int> s_prev;       // and the sweep count it belongs to
+};
+
+static int masked_launch(MaskedRun& r, int len) {
   qdse_ctx* c = r.c;
   hipStream_t st = c->stream;
+  if (r.nq >= 2) return QDSE_EINVAL;
   if (r.use_graph) {
-    HIPCHK(hipGraphLaunch(r.exec, st));
+    hipGraphExec_t exec = nullptr;
+    int rc = chunk_graph(c, r.kind, len, &exec);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(exec, st));
   } else {
-    int rc = record_chunk(c, st, r.chunk, r.kind);
+    int rc = record_chunk(c, st, len, r.kind);
     if (rc) return rc;
   }
-  r.launched += r.chunk;
-  r.slot ^= 1;
-  HIPCHK(hipMemcpyAsync(c->h_state + (size_t)r.slot * c->n_inst, c->d_state,
-                        (size_t)c->n_inst * sizeof(SolveState), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipEventRecord(c->ev[r.slot], st));
+  const int e = r.next_ev;
+  r.next_ev ^= 1;
+  HIPCHK(hipEventRecord(c->ev[e], st));
+  r.q_len[r.nq] = len;
+  r.q_ev[r.nq] = e;
+  ++r.nq;
+  r.launched += len;
   return QDSE_OK;
+}
+
+// x_src: starting iterate copied into xbuf[0] (nullptr: continue from xbuf[0]).
+static int masked_begin(MaskedRun& r, qdse_ctx* c, double tol, int max_iter, int conv_mode,
+                        int kind, const double* x_src) {
+  r.c = c;
+  r.kind = kind;
+  r.tol = tol;
+  r.first = kind == SWEEP_DIRECT ? c->chunk : c->chunk_mm;
+  r.use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
+  r.launched = 0;
+  // max_iter + 1 sweeps freeze every instance (the sweep after max_iter
+  // running sweeps records status 2)
+  r.limit = (long)max_iter + 1;
+  r.all_done = false;
+  r.nq = 0;
+  r.r_prev.assign(c->n_inst, -1.0);
+  r.s_prev.assign(c->n_inst, 0);
+  HIPCHK(launch_solve_init(c->stream, c->n_inst, c->d_state, c->d_ctl,
+                           SolveCtl{tol, conv_mode, max_iter, c->d_mirror, c->d_state}, x_src,
+                           c->d_xbuf[0], x_src ? (long)xlen(c) : 0));
+  int rc = masked_launch(r, r.first);
+  if (!rc && r.launched < r.limit) rc = masked_launch(r, 6);
+  return rc;
+}
+
+// Total sweeps of the phase after which every running instance has frozen
+// and its freeze is recorded. An instance at sweep count s has statistic r1
+// from sweep s - 1 and r0 from sweep s - 2; r decays by a factor rho per
+// sweep, estimated since the previous read (or from r1 / r0 at the first),
+// so r falls below tol after j more sweeps and sweep s + j records the
+// freeze. Without a usable rate, the phase's first chunk length.
+static long predict_total(MaskedRun& r) {
+  const qdse_ctx* c = r.c;
+  long total = 0;
+  for (int q = 0; q < c->n_inst; ++q) {
+    const SolveState& h = r.snap[q];
+    if (h.status != 0) continue;
+    const int s = h.sweeps;
+    double r1, r0;
+    std::memcpy(&r1, &h.metric[0], sizeof(double));
+    std::memcpy(&r0, &h.metric[1], sizeof(double));
+    double rho = -1.0;
+    if (s >= 2 && r.r_prev[q] > 0.0 && s > r.s_prev[q])
+      rho = std::pow(r1 / r.r_prev[q], 1.0 / (double)(s - r.s_prev[q]));
+    else if (s >= 3 && r0 > 0.0)
+      rho = r1 / r0;
+    long j;
+    if (s < 2) j = r.first;
+    else if (!(r1 >= r.tol)) j = 1;
+    else if (rho > 0.0 && rho < 0.99) j = (long)std::ceil(std::log(r.tol / r1) / std::log(rho));
+    else j = r.first;
+    j = std::min<long>(std::max<long>(j, 1), 1l << 20);
+    total = std::max(total, (long)s + j);
+    if (s >= 2) {
+      r.r_prev[q] = r1;
+      r.s_prev[q] = s;
+    }
+  }
+  return total;
 }
 
 // *over: the phase has ended (every instance frozen, or the sweep limit).
 static int masked_wait(MaskedRun& r, bool* over) {
   qdse_ctx* c = r.c;
-  HIPCHK(hipEventSynchronize(c->ev[r.slot]));
-  const SolveState* h = c->h_state + (size_t)r.slot * c->n_inst;
+  if (r.nq == 0) return QDSE_EINVAL;
+  HIPCHK(hipEventSynchronize(c->ev[r.q_ev[0]]));
+  const long read = r.launched - (r.nq > 1 ? r.q_len[1] : 0);  // sweeps finished
+  r.q_len[0] = r.q_len[1];
+  r.q_ev[0] = r.q_ev[1];
+  --r.nq;
+  // snapshot of the mirror (later sweeps may be updating it: statuses only
+  // move from running to frozen, and a frozen instance's entry no longer changes)
+  r.snap.assign(c->h_state, c->h_state + c->n_inst);
   bool done = true;
   for (int q = 0; q < c->n_inst; ++q)
-    if (h[q].status == 0) done = false;
+    if (r.snap[q].status == 0) done = false;
   r.all_done = done;
-  *over = done || r.launched >= r.limit;
-  return QDSE_OK;
+  *over = done || read >= r.limit;
+  if (*over) return QDSE_OK;  // chunks still in flight only carry frozen iterates along
+  long extra = std::min(predict_total(r), r.limit) - r.launched;
+  if (extra <= 0 && r.nq > 0) return QDSE_OK;
+  // no chunk longer than the phase's first: an early rate estimate can be far
+  // off (e.g. right after the switch from FP32 to FP64 sweeps)
+  const long len = std::min<long>(r.first, std::max<long>(6, (extra + 5) / 6 * 6));
+  return masked_launch(r, (int)len);
 }
 
-static void masked_state(const MaskedRun& r, std::vector<SolveState>& hs) {
-  const qdse_ctx* c = r.c;
-  const SolveState* h = c->h_state + (size_t)r.slot * c->n_inst;
-  hs.assign(h, h + c->n_inst);
-}
+static void masked_state(const MaskedRun& r, std::vector<SolveState>& hs) { hs = r.snap; }
 
 static int finish_solve(qdse_ctx* c, const std::vector<SolveState>& hs, bool all_done, int* iters,
                         double* resid) {
@@ -578,10 +661,10 @@ int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
     double tol32 = 1e-6;  // switch to FP64 sweeps below this change
     if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
     if (tol32 < tol) tol32 = tol;
-    return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32);
+    return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32, g.d_x);
   }
   const int kind = c->precision == QDSE_FP64 ? SWEEP_DIRECT : SWEEP_MM64;
-  return masked_begin(g.run, c, tol, max_iter, conv_mode, kind);
+  return masked_begin(g.run, c, tol, max_iter, conv_mode, kind, g.phase == 0 ? g.d_x : nullptr);
 }
 
 int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_mode) {
@@ -589,10 +672,7 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
     qdse_ctx* c = g.c;
     c->last_sweeps32.assign(c->n_inst, 0);
     c->last_sweeps64.assign(c->n_inst, 0);
-    HIPCHK(hipMemcpyAsync(c->d_xbuf[0], g.d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
-                          c->stream));
     int rc = group_phase_begin(g, tol, max_iter, conv_mode);
-    if (!rc) rc = masked_launch(g.run);
     if (rc) return rc;
   }
   for (;;) {
@@ -603,17 +683,13 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
       bool over = false;
       int rc = masked_wait(g.run, &over);
       if (rc) return rc;
-      if (!over) {
-        if ((rc = masked_launch(g.run))) return rc;
-        continue;
-      }
+      if (!over) continue;
       qdse_ctx* c = g.c;
       masked_state(g.run, g.hs);
       if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
         for (int k = 0; k < c->n_inst; ++k) c->last_sweeps32[k] = g.hs[k].sweeps;
         g.phase = 1;
         rc = group_phase_begin(g, tol, max_iter, conv_mode);
-        if (!rc) rc = masked_launch(g.run);
         if (rc) return rc;
         continue;
       }

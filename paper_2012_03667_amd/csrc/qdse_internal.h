@@ -47,13 +47,6 @@ struct InstDev {
   int pad;
 };
 
-// Controls of a masked successive-approximation run (device copy).
-struct SolveCtl {
-  double tol;
-  int mode;      // QDSE_CONV_ABS or QDSE_CONV_MASS
-  int max_iter;
-};
-
 // Per-instance state of a masked run (device).
 struct SolveState {
   int status;                   // 0 running, 1 converged, 2 max_iter, 3 non-finite
@@ -67,6 +60,20 @@ struct SolveState {
                                 // slot k%3, reads slot (k-1)%3, clears slot (k+1)%3
 };
 
+// Controls of a masked successive-approximation run (device copy).
+struct SolveCtl {
+  double tol;
+  int mode;      // QDSE_CONV_ABS or QDSE_CONV_MASS
+  int max_iter;
+  // Optional host mirror (pinned, device-visible): the deciding block of
+  // every sixth sweep (k a multiple of 6, so the last sweep of every chunk)
+  // writes the instance's new status, sweep count and resid, and the test
+  // statistics of the two previous sweeps (metric[0]: sweep `sweeps` - 1,
+  // metric[1]: sweeps - 2), at mirror[state - base].
+  SolveState* mirror;
+  const SolveState* base;
+};
+
 // Matrices per kernel block: K_T, K_3, K_0 (see qdse_kernels.hip).
 constexpr int NKER = 3;
 
@@ -74,7 +81,12 @@ constexpr int NKER = 3;
 hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, const double* s,
                              const double* t, const double* W, const double* z, const double* wz,
                              double omega, int with_domega, double* K, double* dK);
-hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state);
+// Fresh solve states; optionally also the controls (ctl, v) and a copy of the
+// starting iterate x_src -> x_dst (xlen doubles).
+hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state,
+                             SolveCtl* ctl = nullptr, SolveCtl v = SolveCtl{},
+                             const double* x_src = nullptr, double* x_dst = nullptr,
+                             long xlen = 0);
 // One FP64 sweep: node functions, then the contraction and update (two
 // kernels). With state != nullptr the run is masked (frozen instances carry
 // their iterate); k is the 1-based sweep index inside a chunk (a multiple of 6

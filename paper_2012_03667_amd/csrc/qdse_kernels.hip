@@ -134,6 +134,17 @@ __global__ void k_precompute(int n, int nq, int na, int ldk, const double* __res
 // ---------------------------------------------------------------- masked runs
 __device__ inline double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+__device__ inline void mirror_state(const SolveCtl* ctl, const SolveState* st, int status, int now,
+                                    double resid, unsigned long long last,
+                                    unsigned long long before) {
+  SolveState* m = ctl->mirror + (st - ctl->base);
+  m->status = status;
+  m->sweeps = now;
+  m->resid = resid;
+  m->metric[0] = last;
+  m->metric[1] = before;
+}
+
 // Status of an instance at the start of sweep k (1-based within a chunk whose
 // length is a multiple of 6), from the test statistic of sweep k-1. Every
 // block evaluates it the same way; the writer block records it and clears the
@@ -154,19 +165,30 @@ __device__ inline int decide(SolveState* st, const SolveCtl* ctl, int k, bool wr
     if (status == 0 && done >= ctl->max_iter) status = 2;
   }
   if (writer && threadIdx.x == 0) {
+    const unsigned long long before = S.metric[(k + 1) % 3];  // sweep k-2, cleared below
     if (status != 0 && S.status == 0) S.resid = prev;
     S.status = status;
     const int now = done + (status == 0 ? 1 : 0);
     S.sweeps_slot[k % 3] = now;
     S.sweeps = now;
     S.metric[(k + 1) % 3] = 0ull;
+    if (ctl->mirror && k % 6 == 0) mirror_state(ctl, st, status, now, S.resid, S.metric[(k + 2) % 3], before);
   }
   return status;
 }
 
-__global__ void k_solve_init(int n_inst, SolveState* st) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_inst) return;
+// Start of a masked run: fresh per-instance states, the run's controls (when
+// ctl is given) and the starting iterate copied into the run's buffer (when
+// x_src is given), in one launch.
+__global__ void k_solve_init(int n_inst, SolveState* st, SolveCtl* ctl, SolveCtl v,
+                             const double* __restrict__ x_src, double* __restrict__ x_dst,
+                             long xlen) {
+  const long e0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ctl && e0 == 0) *ctl = v;
+  if (x_src)
+    for (long e = e0; e < xlen; e += (long)gridDim.x * blockDim.x) x_dst[e] = x_src[e];
+  if (e0 >= n_inst) return;
+  const int k = (int)e0;
   st[k].status = 0;
   st[k].sweeps = 0;
   st[k].sweeps_slot[0] = st[k].sweeps_slot[1] = st[k].sweeps_slot[2] = 0;
@@ -756,8 +778,12 @@ hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, con
   return hipGetLastError();
 }
 
-hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state) {
-  hipLaunchKernelGGL(k_solve_init, dim3((n_inst + 255) / 256), dim3(256), 0, st, n_inst, state);
+hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state, SolveCtl* ctl,
+                             SolveCtl v, const double* x_src, double* x_dst, long xlen) {
+  long threads = n_inst;
+  if (x_src && xlen > threads) threads = xlen < (1l << 20) ? xlen : (1l << 20);
+  hipLaunchKernelGGL(k_solve_init, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st,
+                     n_inst, state, ctl, v, x_src, x_dst, xlen);
   return hipGetLastError();
 }
 

@@ -107,12 +107,21 @@ __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool
     if (status == 0 && done >= ctl->max_iter) status = 2;
   }
   if (writer) {
+    const unsigned long long before = S.metric[(k + 1) % 3];  // sweep k-2, cleared below
     if (status != 0 && S.status == 0) S.resid = prev;
     S.status = status;
     const int now = done + (status == 0 ? 1 : 0);
     S.sweeps_slot[k % 3] = now;
     S.sweeps = now;
     S.metric[(k + 1) % 3] = 0ull;
+    if (ctl->mirror && k % 6 == 0) {  // host mirror (see SolveCtl)
+      SolveState* m = ctl->mirror + (st - ctl->base);
+      m->status = status;
+      m->sweeps = now;
+      m->resid = S.resid;
+      m->metric[0] = S.metric[(k + 2) % 3];
+      m->metric[1] = before;
+    }
   }
   return status;
 }
