@@ -481,6 +481,8 @@ struct MaskedRun {
   bool use_graph = true, all_done = false;
   int q_len[2] = {0, 0}, q_ev[2] = {0, 0}, nq = 0;  // chunks in flight, oldest first
   int next_ev = 0;
+  double* out = nullptr;  // final phase: the caller's iterate buffer
+  long out_at = -1;       // `launched` when the copy xbuf[0] -> out was last enqueued
   std::vector<SolveState> snap;  // mirror as read at the last wait
   std::vector<double> r_prev;    // statistic of each instance at the previous read
   std::vector<int> s_prev;       // and the sweep count it belongs to
@@ -509,9 +511,10 @@ static int masked_launch(MaskedRun& r, int len) {
   return QDSE_OK;
 }
 
-// x_src: starting iterate copied into xbuf[0] (nullptr: continue from xbuf[0]).
+// x_src: starting iterate copied into xbuf[0] (nullptr: continue from xbuf[0]);
+// out: where the phase's result goes (nullptr: a later phase follows).
 static int masked_begin(MaskedRun& r, qdse_ctx* c, double tol, int max_iter, int conv_mode,
-                        int kind, const double* x_src) {
+                        int kind, const double* x_src, double* out) {
   r.c = c;
   r.kind = kind;
   r.tol = tol;
@@ -525,6 +528,8 @@ static int masked_begin(MaskedRun& r, qdse_ctx* c, double tol, int max_iter, int
   r.nq = 0;
   r.r_prev.assign(c->n_inst, -1.0);
   r.s_prev.assign(c->n_inst, 0);
+  r.out = out;
+  r.out_at = -1;
   HIPCHK(launch_solve_init(c->stream, c->n_inst, c->d_state, c->d_ctl,
                            SolveCtl{tol, conv_mode, max_iter, c->d_mirror, c->d_state}, x_src,
                            c->d_xbuf[0], x_src ? (long)xlen(c) : 0));
@@ -588,7 +593,16 @@ static int masked_wait(MaskedRun& r, bool* over) {
   *over = done || read >= r.limit;
   if (*over) return QDSE_OK;  // chunks still in flight only carry frozen iterates along
   long extra = std::min(predict_total(r), r.limit) - r.launched;
-  if (extra <= 0 && r.nq > 0) return QDSE_OK;
+  if (extra <= 0 && r.nq > 0) {
+    // the chunk in flight is predicted to be the last: enqueue the copy of
+    // the result behind it now (if more chunks follow, it is repeated)
+    if (r.out && r.out_at != r.launched) {
+      HIPCHK(hipMemcpyAsync(r.out, c->d_xbuf[0], xlen(c) * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream));
+      r.out_at = r.launched;
+    }
+    return QDSE_OK;
+  }
   // no chunk longer than the phase's first: an early rate estimate can be far
   // off (e.g. right after the switch from FP32 to FP64 sweeps)
   const long len = std::min<long>(r.first, std::max<long>(6, (extra + 5) / 6 * 6));
@@ -661,10 +675,11 @@ int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
     double tol32 = 1e-6;  // switch to FP64 sweeps below this change
     if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
     if (tol32 < tol) tol32 = tol;
-    return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32, g.d_x);
+    return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32, g.d_x, nullptr);
   }
   const int kind = c->precision == QDSE_FP64 ? SWEEP_DIRECT : SWEEP_MM64;
-  return masked_begin(g.run, c, tol, max_iter, conv_mode, kind, g.phase == 0 ? g.d_x : nullptr);
+  return masked_begin(g.run, c, tol, max_iter, conv_mode, kind, g.phase == 0 ? g.d_x : nullptr,
+                      g.d_x);
 }
 
 int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_mode) {
@@ -698,8 +713,9 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
         g.hs[k].sweeps += c->last_sweeps32[k];
       }
       g.all_done = g.run.all_done;
-      HIPCHK(hipMemcpyAsync(g.d_x, c->d_xbuf[0], xlen(c) * sizeof(double),
-                            hipMemcpyDeviceToDevice, c->stream));
+      if (g.run.out_at != g.run.launched)  // not yet enqueued behind the last chunk
+        HIPCHK(hipMemcpyAsync(g.d_x, c->d_xbuf[0], xlen(c) * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
       g.phase = 2;
     }
     if (!any) break;
