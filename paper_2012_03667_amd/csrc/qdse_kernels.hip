@@ -41,10 +41,32 @@ constexpr int WAVE = 64;
 // Floor (GeV) of the relative mass-function test, where M = B/A vanishes.
 constexpr double kMassFloor = 1e-8;
 
+// A 64-bit value moved across lanes by a DPP control (two 32-bit halves);
+// lanes of rows outside ROWS receive 0.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes (all active), returned in every lane: butterflies
+// inside each row of 16 lanes (two quad permutations, the half-row and row
+// mirrors), then the broadcasts of lanes 15 and 31 gather the four row sums
+// in lane 63, which is read back as a scalar. Register-to-register moves
+// only, no LDS round trips.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_move<0x140, 0xF>(v);  // row_mirror: the row sum in every lane of the row
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3: the total in row 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 // Forward-mode dual number: value and directional derivative.
@@ -204,17 +226,14 @@ __global__ void k_solve_init(int n_inst, SolveState* st, SolveCtl* ctl, SolveCtl
 // functions the contraction needs: nodes[inst][5][ldk] =
 // {A(t), B(t), sigma_V, sigma_S, t sigma_V}, plus their tangents for Dual.
 template <class T>
-__device__ inline void node_values(int n, int j, const int* lo, const double* sw, double tj,
-                                   const double* xA, const double* xB, const double* vA,
-                                   const double* vB, T* out) {
-  const int b = lo[j];
-  const double* w = sw + 4 * j;
+__device__ inline void node_core(const double w[4], const T xa[4], const T xb[4], double tj,
+                                 T* out) {
   T Aq = make<T>(0.0, 0.0), Bq = make<T>(0.0, 0.0);
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
     const T wl = make<T>(w[l], 0.0);
-    Aq = Aq + wl * make<T>(xA[b + l], vA ? vA[b + l] : 0.0);
-    Bq = Bq + wl * make<T>(xB[b + l], vB ? vB[b + l] : 0.0);
+    Aq = Aq + wl * xa[l];
+    Bq = Bq + wl * xb[l];
   }
   const T tt = make<T>(tj, 0.0);
   const T Dl = tt * Aq * Aq + Bq * Bq;
@@ -224,6 +243,22 @@ __device__ inline void node_values(int n, int j, const int* lo, const double* sw
   out[2] = sV;
   out[3] = sS;
   out[4] = tt * sV;
+}
+
+template <class T>
+__device__ inline void node_values(int n, int j, const int* lo, const double* sw, double tj,
+                                   const double* xA, const double* xB, const double* vA,
+                                   const double* vB, T* out) {
+  const int b = lo[j];
+  double w[4];
+  T xa[4], xb[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    w[l] = sw[4 * j + l];
+    xa[l] = make<T>(xA[b + l], vA ? vA[b + l] : 0.0);
+    xb[l] = make<T>(xB[b + l], vB ? vB[b + l] : 0.0);
+  }
+  node_core<T>(w, xa, xb, tj, out);
 }
 
 __global__ void k_nodes(int n, int nq, int ldk, const int* __restrict__ lo,
@@ -289,17 +324,29 @@ __device__ inline void row_accumulate(int nq, int ldk, size_t mat, const double*
   for (int c = 0; c < 4; ++c) acc[c] = wave_sum(acc[c]);
 }
 
-// Specialised FP64 body (explicit FMAs) for the hot sweep.
-__device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const double* __restrict__ Ki,
-                                          const double* __restrict__ nd, double s, double Ai,
-                                          double Bi, int lane, double acc[4]) {
+// One loop node's contribution to the four row sums (explicit FMAs).
+__device__ inline void row_term(double kT, double k3, double k0, double Aq, double Bq, double sV,
+                                double sS, double tsV, double s, double Ai, double Bi, double& a0,
+                                double& a1, double& a2, double& a3) {
+  const double dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
+  const double e = fma(2.0 * sS, dB, fma(s, sV, tsV) * dA);
+  a0 = fma(kT, e, a0);
+  a1 = fma(k3, sV * sA, a1);
+  a2 = fma(kT, fma(sS, dA, -(sV * dB)), a2);
+  a3 = fma(k0, sS * sA, a3);
+}
+
+// Lane sums of the FP64 hot sweep over j = j0, j0 + 64, ... < nq.
+__device__ inline void row_stream_f64(int j0, int nq, int ldk, size_t mat,
+                                      const double* __restrict__ Ki, const double* __restrict__ nd,
+                                      double s, double Ai, double Bi, double& a0, double& a1,
+                                      double& a2, double& a3) {
   // Loads of U consecutive lane strides are issued before any arithmetic so
   // that a wavefront has ~8 U loads in flight; the accumulation order per lane
-  // is still j = lane, lane + 64, ... . U = 6 (two load rounds per row at
+  // is still j = j0, j0 + 64, ... . U = 6 (two load rounds per row at
   // 513 loop nodes) measured fastest among 4, 5, 6, 8.
   constexpr int U = 6;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  for (int jb = lane; jb < nq; jb += U * WAVE) {
+  for (int jb = j0; jb < nq; jb += U * WAVE) {
     double kT[U], k3[U], k0[U], Aq[U], Bq[U], sV[U], sS[U], tsV[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -316,17 +363,19 @@ __device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const dou
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (jb + u * WAVE < nq) {
-        const double dA = Aq[u] - Ai, dB = Bq[u] - Bi, sA = Aq[u] + Ai;
-        const double e = fma(2.0 * sS[u], dB, fma(s, sV[u], tsV[u]) * dA);
-        a0 = fma(kT[u], e, a0);
-        a1 = fma(k3[u], sV[u] * sA, a1);
-        a2 = fma(kT[u], fma(sS[u], dA, -(sV[u] * dB)), a2);
-        a3 = fma(k0[u], sS[u] * sA, a3);
-      }
-    }
+    for (int u = 0; u < U; ++u)
+      if (jb + u * WAVE < nq)
+        row_term(kT[u], k3[u], k0[u], Aq[u], Bq[u], sV[u], sS[u], tsV[u], s, Ai, Bi, a0, a1, a2,
+                 a3);
   }
+}
+
+// Specialised FP64 body for the hot sweep: lane sums, then wave sums.
+__device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const double* __restrict__ Ki,
+                                          const double* __restrict__ nd, double s, double Ai,
+                                          double Bi, int lane, double acc[4]) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  row_stream_f64(lane, nq, ldk, mat, Ki, nd, s, Ai, Bi, a0, a1, a2, a3);
   acc[0] = wave_sum(a0);
   acc[1] = wave_sum(a1);
   acc[2] = wave_sum(a2);
@@ -442,6 +491,135 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
             isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
         mine = bits > mine ? bits : mine;
       }
+    }
+  }
+  if (state) {
+    if (lane == 0) wmax[wave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long m = wmax[0];
+      for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+      atomicMax(&state[inst].metric[k % 3], m);
+    }
+  }
+}
+
+// Small-batch sweep, one row per wavefront (four rows per workgroup). With
+// about one workgroup per compute unit a launch lasts as long as one
+// workgroup's chain of reads, so they are ordered for latency: the iterate
+// values and stencil weights of all of a thread's nodes go out first (vector
+// reads complete in issue order), then the row's kernel entries (held in
+// registers) and its own values; the node functions are built while the
+// kernel entries are still arriving, then the masked-run decision is taken.
+// After the barrier the contraction consumes the registers (nodes
+// beyond ROW_PF lane strides are streamed as in k_sweep). Same per-row
+// arithmetic and order as k_sweep.
+constexpr int ROW_PF = 9;   // lane strides held in registers: nq <= 576 in one round
+constexpr int NODE_PT = 3;  // nodes per thread per pass of the node build
+__global__ void __launch_bounds__(256) k_sweep_row(
+    int n_inst, int n, int nq, int ldk, const InstDev* __restrict__ inst_,
+    const double* __restrict__ K, size_t kstride, const int* __restrict__ lo,
+    const double* __restrict__ sw, const double* __restrict__ t_, const double* __restrict__ s_,
+    const double* __restrict__ x_in, double* __restrict__ x_out, SolveState* state,
+    const SolveCtl* ctl, int k, int add_f0) {
+  extern __shared__ double nd[];  // [5][ldk] and one spare slot
+  const int inst = blockIdx.y;
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const double* xi = x_in + (size_t)inst * 2 * n;
+  double* xo = x_out + (size_t)inst * 2 * n;
+  const int i = blockIdx.x * 4 + wave;
+  const int ic = i < n ? i : n - 1;  // rows past n read row n - 1 and write nothing
+  // Loop node j lies between external nodes j - 1 and j (the loop grid
+  // interleaves the external one), so its 4-point stencil starts at
+  // clamp(j - 2, 0, n - 4), the base the grid's stencil table holds: the
+  // iterate reads need no table read first.
+  double w[NODE_PT][4], tj[NODE_PT], xa[NODE_PT][4], xb[NODE_PT][4];
+  auto node_reads = [&](int jb) {
+#pragma unroll
+    for (int q = 0; q < NODE_PT; ++q) {
+      const int j = min(jb + q * 256, nq - 1);
+      const int b = min(max(j - 2, 0), n - 4);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        xa[q][l] = xi[b + l];
+        xb[q][l] = xi[n + b + l];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NODE_PT; ++q) {
+      const int j = min(jb + q * 256, nq - 1);
+      tj[q] = t_[j];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) w[q][l] = sw[4 * j + l];
+    }
+  };
+  node_reads(threadIdx.x);
+  __builtin_amdgcn_sched_barrier(0);  // keep these reads ahead of the kernel-row reads
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  const double* Ki = K + (size_t)P.kblock * kstride + (size_t)ic * ldk;
+  double kT[ROW_PF], k3[ROW_PF], k0[ROW_PF];
+#pragma unroll
+  for (int u = 0; u < ROW_PF; ++u) {
+    const int j = min(lane + u * WAVE, nq - 1);
+    kT[u] = Ki[j];
+    k3[u] = Ki[mat + j];
+    k0[u] = Ki[2 * mat + j];
+  }
+  const double s = s_[ic], Ai = xi[ic], Bi = xi[n + ic];
+  __builtin_amdgcn_sched_barrier(0);
+  // Every node of the pass is computed and stored, the clamped ones into one
+  // spare slot past the five columns, so that no read can be moved into a
+  // conditional block behind the kernel-row reads.
+  auto nodes = [&](int jb) {
+#pragma unroll
+    for (int q = 0; q < NODE_PT; ++q) {
+      double v[5];
+      node_core<double>(w[q], xa[q], xb[q], tj[q], v);
+      const int j = jb + q * 256;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) nd[j < nq ? c * ldk + j : 5 * ldk] = v[c];
+    }
+  };
+  // the first pass outside the loop, so that its waits count only its own reads
+  nodes(threadIdx.x);
+  for (int jb = threadIdx.x + NODE_PT * 256; jb < nq; jb += NODE_PT * 256) {
+    node_reads(jb);
+    nodes(jb);
+  }
+  // (after the node build: the deciding thread's own waits then hold up no
+  // node arithmetic)
+  const int status = state ? decide(state + inst, ctl, k, blockIdx.x == 0) : 0;
+  __syncthreads();
+  if (status != 0) {  // frozen (the same for every wavefront): carry along
+    if (lane == 0 && i < n) {
+      xo[i] = Ai;
+      xo[n + i] = Bi;
+    }
+    return;
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+  for (int u = 0; u < ROW_PF; ++u) {
+    const int j = lane + u * WAVE;
+    if (j < nq)
+      row_term(kT[u], k3[u], k0[u], nd[j], nd[ldk + j], nd[2 * ldk + j], nd[3 * ldk + j],
+               nd[4 * ldk + j], s, Ai, Bi, a0, a1, a2, a3);
+  }
+  row_stream_f64(lane + ROW_PF * WAVE, nq, ldk, mat, Ki, nd, s, Ai, Bi, a0, a1, a2, a3);
+  const double acc0 = wave_sum(a0), acc1 = wave_sum(a1), acc2 = wave_sum(a2),
+               acc3 = wave_sum(a3);
+  __shared__ unsigned long long wmax[4];
+  unsigned long long mine = 0ull;
+  if (lane == 0 && i < n) {
+    const double An = (add_f0 ? 1.0 : 0.0) + P.pref * (acc1 - acc0);
+    const double Bn = (add_f0 ? P.m : 0.0) + P.pref * fma(2.0 * s, acc2, acc3);
+    xo[i] = An;
+    xo[n + i] = Bn;
+    if (state) {
+      const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
+      mine = (unsigned long long)__double_as_longlong(
+          isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
     }
   }
   if (state) {
@@ -806,11 +984,11 @@ hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk
                               const double* x_in, double* x_out, SolveState* state,
                               const SolveCtl* ctl, int k, int add_f0, int rows, hipEvent_t ev0,
                               hipEvent_t ev1) {
-  const size_t lds = (size_t)5 * ldk * sizeof(double);
+  const size_t lds = ((size_t)5 * ldk + 1) * sizeof(double);
   if (rows != 4 && rows != 8 && rows != 16) return hipErrorInvalidValue;
   // (one slot-templated variant that loads a whole row at once measured
   // slower here: more registers, lower occupancy)
-  auto kern = rows == 4 ? k_sweep_fused<4> : rows == 8 ? k_sweep_fused<8> : k_sweep_fused<16>;
+  auto kern = rows == 4 ? k_sweep_row : rows == 8 ? k_sweep_fused<8> : k_sweep_fused<16>;
   const dim3 grid((n + rows - 1) / rows, n_inst);
   if (ev0)
     hipExtLaunchKernelGGL(kern, grid, dim3(256), (uint32_t)lds, st, ev0, ev1, 0, n_inst, n, nq,
