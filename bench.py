@@ -332,11 +332,11 @@ def main():
     reps = 200
     avg_ms = S.time_contraction(x, reps=reps)
     nq = n + 1
-    # algorithmic bytes of one fused sweep launch: the three FP64 matrices of
-    # the shared omega class once, per instance the iterate in and out and the
-    # stencils (base index + 4 weights per loop node)
-    kbytes = 3 * n * nq * 8
-    per_inst = 2 * (2 * n * 8) + nq * (4 * 8 + 4)
+    # algorithmic bytes of one sweep launch: the three FP64 matrices of the
+    # shared omega class and the loop-node data (4 stencil weights and t per
+    # node) once, per instance the iterate in and out
+    kbytes = 3 * n * nq * 8 + nq * (4 * 8 + 8)
+    per_inst = 2 * (2 * n * 8)
     alg_bytes = kbytes + len(masses) * per_inst
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
 
@@ -358,17 +358,18 @@ def main():
                         "cubic interpolation, m in {0, 5 MeV}, paper interaction D=0.55 GeV^2, "
                         "omega=0.678 GeV, A0=B0=1, tol 1e-10 on max|dM/M| and max|dA|",
             "n_radial": n, "n_angle": na, "instances_per_step": len(masses),
-            "solver": "plain FP64 successive approximation, fused sweep kernel, HIP-graph chunks",
+            "solver": "plain FP64 successive approximation, one sweep kernel per iteration "
+                      "(one row per wavefront), pipelined HIP-graph chunks",
             "sweeps_per_solve": [int(v) for v in iters],
             "branch_A_positive": certified,
             "note": "the configs' interaction (kappa=0.8, omega=0.5) has no convergent "
                     "successive approximation (see design notes); the paper's interaction is used",
         },
         "roofline": {
-            "bound": "hbm", "kernel": "k_sweep_fused (FP64 sweep, 2 instances)",
+            "bound": "hbm", "kernel": "k_sweep_row (FP64 sweep, 2 instances)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": counter_traffic("k_sweep_fused_512x128_2inst.md", "qdse_kernels.hip"),
+            "traffic": counter_traffic("k_sweep_row_512x128_2inst.md", "qdse_kernels.hip"),
             "avg_kernel_us": avg_ms * 1e3, "alg_bytes_per_launch": alg_bytes,
         },
     }
