@@ -36,6 +36,20 @@
 //    vertex (the two difference quotients and sigma_A - 1); lam = 1 is the
 //    Ball-Chiu vertex of eq. bcvtxmu, lam = 0 the bare (rainbow) vertex.
 //
+// Beyond the paper (its Sec. II drops the ultraviolet part of the Qin-Chang
+// interaction and sets the renormalisation constants to 1), an optional mode
+// keeps both:
+//  * g(k^2) gains g_UV(k^2) = 8 pi^2 gamma_m F(k^2) / ln[tau + (1 + k^2/L^2)^2],
+//    F(k^2) = (1 - exp(-k^2/(4 m_t^2)))/k^2, gamma_m = 12/(33 - 2 N_f) with
+//    N_f = 4, L = 0.234 GeV, tau = e^2 - 1, m_t = 0.5 GeV (the Qin-Chang form:
+//    4 pi times the one-loop running coupling at large k^2);
+//  * S^-1 = Z_2 (i gamma.p + Z_m m) + Z_1 Sigma with Z_1 = Z_2 (the
+//    Ward-Takahashi identity the Ball-Chiu vertex satisfies), so
+//    A = Z_2 (1 + Sigma_A), B = Z_4 m + Z_2 Sigma_B, Z_4 = Z_2 Z_m, with the
+//    conditions A(zeta^2) = 1 and B(zeta^2) = m fixing Z_2 and Z_4 every sweep
+//    from the sums at p^2 = zeta^2 (A, B interpolated there); at m = 0 the mass
+//    term is absent. The top of the radial grid is the regulator.
+//
 // Scalar type: every routine is a template, instantiated for double and for
 // std::complex<double>; the complex form gives Jacobian-vector products by the
 // complex-step method (exact to rounding).
@@ -67,8 +81,10 @@ struct qo_vac_grid {
 struct qo_vac_par {
   double D;      // interaction strength, GeV^2
   double omega;  // interaction range, GeV
-  double m;      // current-quark mass, GeV
+  double m;      // current-quark mass, GeV (renormalised at zeta when zeta > 0)
   double lam;    // vertex homotopy: 1 = Ball-Chiu, 0 = bare vertex
+  int uv;        // 1: add the ultraviolet term of the Qin-Chang interaction
+  double zeta;   // > 0: renormalise at p^2 = zeta^2 (GeV); 0: Z_1 = Z_2 = Z_4 = 1
 };
 
 }  // extern "C"
@@ -165,6 +181,16 @@ void integrand(double s, double t, double z, T Ap, T Bp, T Aq, T Bq, double lam,
   *IB = IB1 + IB2 + IB3;
 }
 
+// Ultraviolet term of the Qin-Chang interaction (see the header).
+double g_uv(double k2) {
+  const double gamma_m = 12.0 / (33.0 - 2.0 * 4.0);
+  const double lam2 = 0.234 * 0.234, mt2 = 0.5 * 0.5;
+  const double tau = std::exp(2.0) - 1.0;
+  const double f = -std::expm1(-k2 / (4.0 * mt2)) / k2;
+  const double r = 1.0 + k2 / lam2;
+  return 8.0 * PI * PI * gamma_m * f / std::log(tau + r * r);
+}
+
 // One external row i of the map: returns the two radial x angular sums.
 template <class T>
 void row_sums(const qo_vac_grid* g, const qo_vac_par* par, T Ai, T Bi,
@@ -181,7 +207,7 @@ void row_sums(const qo_vac_grid* g, const qo_vac_par* par, T Ai, T Bi,
       T IA, IB;
       double k2;  // squared gluon momentum k = p - q, from the four-vectors
       integrand(s, t, z, Ai, Bi, Aq[j], Bq[j], par->lam, &IA, &IB, &k2);
-      const double gk = gnorm * std::exp(-k2 / om2);
+      const double gk = gnorm * std::exp(-k2 / om2) + (par->uv ? g_uv(k2) : 0.0);
       const double w = Wj * g->wz[a] * std::sqrt(1.0 - z * z) * gk;
       accA += w * IA / Dq;
       accB += w * IB / Dq;
@@ -205,13 +231,29 @@ void vac_map(const qo_vac_grid* g, const qo_vac_par* par, const T* x, T* out,
   }
   const double c = (4.0 / 3.0) / (8.0 * PI * PI * PI);
   const int cnt = rows ? nrows : n;
+  // renormalisation constants (1 without a renormalisation point)
+  T Z2 = 1.0, Z4m = par->m;
+  if (par->zeta > 0.0) {
+    const double sz = par->zeta * par->zeta, uz = std::log(sz);
+    const T Az = interp_one(n, g->u, x, uz, g->order);
+    const T Bz = interp_one(n, g->u, x + n, uz, g->order);
+    T sA, sB;
+    row_sums(g, par, Az, Bz, Aq.data(), Bq.data(), sz, &sA, &sB);
+    Z2 = 1.0 / (1.0 + c * sA);                              // A(zeta^2) = 1
+    Z4m = par->m == 0.0 ? T(0.0) : par->m - Z2 * (c * sB);  // B(zeta^2) = m
+  }
 #pragma omp parallel for schedule(static) num_threads(nthreads)
   for (int r = 0; r < cnt; ++r) {
     const int i = rows ? rows[r] : r;
     T sA, sB;
     row_sums(g, par, x[i], x[n + i], Aq.data(), Bq.data(), g->s[i], &sA, &sB);
-    out[r] = 1.0 + c * sA;
-    out[cnt + r] = par->m + c * sB;
+    if (par->zeta > 0.0) {
+      out[r] = Z2 * (1.0 + c * sA);
+      out[cnt + r] = Z4m + Z2 * (c * sB);
+    } else {
+      out[r] = 1.0 + c * sA;
+      out[cnt + r] = par->m + c * sB;
+    }
   }
 }
 
@@ -346,5 +388,7 @@ void qo_integrand(double s, double t, double z, double Ap, double Bp, double Aq,
 }
 
 int qo_max_threads(void) { return omp_get_max_threads(); }
+
+double qo_g_uv(double k2) { return g_uv(k2); }
 
 }  // extern "C"

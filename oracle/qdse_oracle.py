@@ -64,7 +64,8 @@ class _Grid(ctypes.Structure):
 
 class _Par(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double), ("omega", ctypes.c_double),
-                ("m", ctypes.c_double), ("lam", ctypes.c_double)]
+                ("m", ctypes.c_double), ("lam", ctypes.c_double),
+                ("uv", ctypes.c_int), ("zeta", ctypes.c_double)]
 
 
 class _MuGrid(ctypes.Structure):
@@ -95,6 +96,8 @@ def lib():
         L.qo_interp.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp, ip]
         L.qo_integrand.argtypes = [ctypes.c_double] * 8 + [dp, dp]
         L.qo_integrand.restype = None
+        L.qo_g_uv.argtypes = [ctypes.c_double]
+        L.qo_g_uv.restype = ctypes.c_double
         L.qo_mu_map.argtypes = [ctypes.POINTER(_MuGrid), ctypes.POINTER(_MuPar), dp, dp, ip,
                                 ctypes.c_int, dp, dp, ctypes.c_int]
         L.qo_mu_projections.argtypes = [ctypes.c_double] * 6 + [dp, dp, dp]
@@ -199,18 +202,29 @@ def vac_grid(n: int, na: int, s_min: float = 1e-4, s_max: float = 1e4,
 
 @dataclass
 class Params:
+    """D (GeV^2), omega (GeV), current mass m (GeV), vertex homotopy lam.
+    uv = 1 adds the ultraviolet term of the Qin-Chang interaction; zeta > 0
+    (GeV) renormalises at p^2 = zeta^2 with A(zeta^2) = 1, B(zeta^2) = m
+    (Z_1 = Z_2; see qdse_oracle.cpp). The defaults are the paper's setting."""
     D: float
     omega: float
     m: float
     lam: float = 1.0
+    uv: int = 0
+    zeta: float = 0.0
 
     def _c(self):
-        return _Par(self.D, self.omega, self.m, self.lam)
+        return _Par(self.D, self.omega, self.m, self.lam, int(self.uv), float(self.zeta))
 
     @staticmethod
     def from_kappa(kappa: float, omega: float, m: float, lam: float = 1.0):
         """D from the product D * omega = kappa^3."""
         return Params(kappa ** 3 / omega, omega, m, lam)
+
+
+def g_uv(k2: float) -> float:
+    """Ultraviolet term of the Qin-Chang interaction, g_UV(k^2) (GeV^-2)."""
+    return lib().qo_g_uv(float(k2))
 
 
 def _threads(nthreads):
