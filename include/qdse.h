@@ -93,6 +93,35 @@ enum {
 int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst,
                int precision, void* hip_stream, qdse_ctx** out);
 
+/* Renormalised setting with the full Qin-Chang interaction, beyond the
+ * paper: Sec. II (after eq. IRGsQC) keeps only the infrared Gaussian of the
+ * Qin-Chang interaction and sets the renormalisation constants to 1. Here
+ *  - uv = 1 adds its ultraviolet term, g_UV(k^2) = 8 pi^2 gamma_m
+ *    (1 - exp(-k^2/(4 m_t^2))) / (k^2 ln[tau + (1 + k^2/L^2)^2]) with
+ *    gamma_m = 12/25, L = 0.234 GeV, tau = e^2 - 1, m_t = 0.5 GeV (4 pi times
+ *    the one-loop running coupling at large k^2); the top of the radial grid
+ *    is the regulator;
+ *  - every sweep is renormalised at p^2 = zeta^2: with the vertex constant
+ *    Z_1 = Z_2 (the Ward-Takahashi identity of the Ball-Chiu vertex),
+ *    A = Z_2 (1 + Sigma_A), B = Z_4 m + Z_2 Sigma_B, where Sigma are the loop
+ *    sums of eq. dsesys at the current iterate and Z_2, Z_4 follow from
+ *    A(zeta^2) = 1 and B(zeta^2) = m (params[].m is the current mass at zeta;
+ *    m = 0: no mass term). A and B at zeta^2 are interpolated from the
+ *    iterate like the loop values. */
+typedef struct {
+  int uv;       /* 0 or 1: the ultraviolet term of the interaction          */
+  double zeta;  /* renormalisation point in GeV, s_min < zeta^2 < s_max     */
+} qdse_qc;
+
+/* qdse_setup for the renormalised setting above (FP64 sweeps only). The
+ * context supports qdse_iterate, qdse_solve, qdse_solve_group,
+ * qdse_solve_stats, qdse_dims, qdse_nodes and qdse_time_contraction (which =
+ * 0 times the sums kernel); the other entry points return QDSE_ENOTSUP.
+ * Errors: as qdse_setup, and QDSE_EINVAL for qc == NULL, uv not 0 or 1, or
+ * zeta^2 outside (s_min, s_max) or equal to a loop node. */
+int qdse_setup_qc(const qdse_grid* grid, const qdse_params* params, int n_inst,
+                  const qdse_qc* qc, void* hip_stream, qdse_ctx** out);
+
 /* Releases every resource of ctx (NULL is allowed). */
 void qdse_destroy(qdse_ctx* ctx);
 

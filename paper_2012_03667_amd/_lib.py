@@ -38,6 +38,10 @@ class MuGrid(ctypes.Structure):
                 ("lam4", ctypes.c_double), ("T", ctypes.c_double)]
 
 
+class Qc(ctypes.Structure):
+    _fields_ = [("uv", ctypes.c_int), ("zeta", ctypes.c_double)]
+
+
 class MuParams(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double), ("omega", ctypes.c_double), ("m", ctypes.c_double),
                 ("mu", ctypes.c_double)]
@@ -61,6 +65,8 @@ def load():
     L = ctypes.CDLL(_LIBPATH)
     L.qdse_setup.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.c_int,
                              ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+    L.qdse_setup_qc.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.c_int,
+                                ctypes.POINTER(Qc), _vp, ctypes.POINTER(_vp)]
     L.qdse_destroy.argtypes = [_vp]
     L.qdse_destroy.restype = None
     L.qdse_dims.argtypes = [_vp, _ip, _ip, _ip, _ip]
@@ -140,10 +146,13 @@ class Solver:
 
     params: sequence of (D [GeV^2], omega [GeV], m [GeV]) per instance.
     Unknowns per instance: x = [A(s_0..s_{N-1}) | B(s_0..s_{N-1})].
+    zeta (GeV): the renormalised Qin-Chang setting of qdse_setup_qc
+    (renormalisation at p^2 = zeta^2, m = current mass there; uv = 1 adds the
+    ultraviolet term of the interaction); None: the paper's setting.
     """
 
     def __init__(self, n_radial, n_angle, params, interp_order=3, s_min=1e-4, s_max=1e4,
-                 precision=QDSE_FP64, stream=None):
+                 precision=QDSE_FP64, stream=None, zeta=None, uv=1):
         import torch
         L = load()
         self.n, self.na, self.order = int(n_radial), int(n_angle), int(interp_order)
@@ -154,8 +163,14 @@ class Solver:
         g = Grid(self.n, self.na, self.order, float(s_min), float(s_max))
         P = (Params * max(1, self.n_inst))(*[Params(*p) for p in self.params])
         h = _vp()
-        _check(L.qdse_setup(ctypes.byref(g), P, self.n_inst, int(precision),
-                            _vp(self.stream.cuda_stream), ctypes.byref(h)), "qdse_setup")
+        if zeta is None:
+            _check(L.qdse_setup(ctypes.byref(g), P, self.n_inst, int(precision),
+                                _vp(self.stream.cuda_stream), ctypes.byref(h)), "qdse_setup")
+        else:
+            q = Qc(int(uv), float(zeta))
+            _check(L.qdse_setup_qc(ctypes.byref(g), P, self.n_inst, ctypes.byref(q),
+                                   _vp(self.stream.cuda_stream), ctypes.byref(h)),
+                   "qdse_setup_qc")
         self._h = h
         self.s = np.empty(self.n)
         self.t = np.empty(self.n + 1)

@@ -58,7 +58,7 @@ struct qdse_ctx {
   HostGrid hg;
   int n_inst = 0, precision = 0, n_blocks = 0;
   std::vector<qdse_params> params;
-  std::vector<double> block_omega;
+  std::vector<double> block_omega, block_D;
   std::vector<InstDev> inst_h;
   size_t kstride = 0;  // doubles per kernel block (NKER * n * ldk)
   // device data
@@ -79,9 +79,15 @@ struct qdse_ctx {
   double* d_xbuf[2] = {nullptr, nullptr};
   SolveState* d_state = nullptr;
   SolveCtl* d_ctl = nullptr;
+  // renormalised Qin-Chang mode (qdse_setup_qc): kernel matrices with one more
+  // row at p^2 = zeta^2, the sums of a sweep, the renormalisation point
+  int qc = 0, krows = 0;
+  QcPoint zp{};
+  double* d_sK = nullptr;   // [n + 1] external p^2 and zeta^2
+  double* d_sig = nullptr;  // [n_inst][2 (n + 1)]
   // graph of a chunk of masked sweeps; pinned copies of the solve state of
   // the last two chunks, with their completion events
-  std::vector<std::pair<int, hipGraphExec_t>> graphs[3];  // per sweep kind: (length, graph)
+  std::vector<std::pair<int, hipGraphExec_t>> graphs[4];  // per sweep kind: (length, graph)
   int chunk = 24;       // sweeps per graph launch, FP64 direct sweeps (multiple of 6)
   int chunk_mm = 12;    // the same for matrix-core sweeps (masked sweeps cost more)
   int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
@@ -144,14 +150,20 @@ size_t xlen(const qdse_ctx* c) { return (size_t)c->n_inst * 2 * c->hg.n; }
 
 extern "C" {
 
-int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int precision,
-               void* hip_stream, qdse_ctx** out) {
+static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_inst,
+                      int precision, const qdse_qc* qc, void* hip_stream, qdse_ctx** out) {
   if (!out) return QDSE_EINVAL;
   *out = nullptr;
   int rc = validate(grid, params, n_inst);
   if (rc) return rc;
   if (precision != QDSE_FP64 && precision != QDSE_FP32_REFINE && precision != QDSE_FP64_MATRIX)
     return QDSE_EINVAL;
+  if (qc) {
+    const double z2 = qc->zeta * qc->zeta;
+    if (!(qc->zeta > 0.0) || !(z2 > grid->s_min) || !(z2 < grid->s_max)) return QDSE_EINVAL;
+    if (qc->uv != 0 && qc->uv != 1) return QDSE_EINVAL;
+    if (precision != QDSE_FP64) return QDSE_ENOTSUP;
+  }
   qdse_ctx* c = new (std::nothrow) qdse_ctx();
   if (!c) return QDSE_ENOMEM;
   c->grid = *grid;
@@ -168,19 +180,24 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
     g_last_error = "hipGetDevice failed";
     return QDSE_EDEVICE;
   }
-  // omega classes: instances with equal omega share kernel matrices
+  // interaction classes: instances with equal omega share kernel matrices
+  // (equal omega and D when the ultraviolet term is on: D no longer factors
+  // out of the interaction)
+  const bool uv = qc && qc->uv;
   c->inst_h.resize(n_inst);
   for (int k = 0; k < n_inst; ++k) {
     int b = -1;
     for (int q = 0; q < (int)c->block_omega.size(); ++q)
-      if (c->block_omega[q] == params[k].omega) b = q;
+      if (c->block_omega[q] == params[k].omega && (!uv || c->block_D[q] == params[k].D)) b = q;
     if (b < 0) {
       b = (int)c->block_omega.size();
       c->block_omega.push_back(params[k].omega);
+      c->block_D.push_back(params[k].D);
     }
     const double om = params[k].omega;
     InstDev d{};
-    d.pref = (4.0 / 3.0) / (8.0 * PI * PI * PI) * 8.0 * PI * PI * params[k].D / (om * om * om * om);
+    d.pref = (4.0 / 3.0) / (8.0 * PI * PI * PI) *
+             (uv ? 1.0 : 8.0 * PI * PI * params[k].D / (om * om * om * om));
     d.m = params[k].m;
     d.D = params[k].D;
     d.omega = om;
@@ -189,7 +206,18 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   }
   c->n_blocks = (int)c->block_omega.size();
   const HostGrid& g = c->hg;
-  c->kstride = (size_t)NKER * g.n * g.ldk;
+  c->qc = qc ? 1 : 0;
+  c->krows = g.n + c->qc;
+  if (qc) {
+    const double z2 = qc->zeta * qc->zeta;
+    for (double tj : g.t)
+      if (tj == z2) {  // the matrix row would divide by t - p^2 = 0
+        delete c;
+        return QDSE_EINVAL;
+      }
+    c->zp = qc_point(g, grid->interp_order, z2);
+  }
+  c->kstride = (size_t)NKER * c->krows * g.ldk;
   hipStream_t st = c->stream;
 #define TRY(x)            \
   do {                    \
@@ -208,6 +236,12 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   TRY(upload(&c->d_lo, g.lo, st));
   TRY(upload(&c->d_inst, c->inst_h, st));
   TRY(dalloc(&c->d_K, c->kstride * c->n_blocks));
+  if (qc) {
+    std::vector<double> sK(g.s);
+    sK.push_back(c->zp.s);
+    TRY(upload(&c->d_sK, sK, st));
+    TRY(dalloc(&c->d_sig, (size_t)n_inst * 2 * c->krows));
+  }
   TRY(dalloc(&c->d_nodes, (size_t)n_inst * 10 * g.ldk));
   TRY(dalloc(&c->d_xbuf[0], xlen(c)));
   TRY(dalloc(&c->d_xbuf[1], xlen(c)));
@@ -222,7 +256,8 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
     g_last_error = "hipHostMalloc failed";
     qdse_destroy(c);
     return QDSE_ENOMEM;
-  }  if (hipHostGetDevicePointer((void**)&c->d_mirror, c->h_state, 0) != hipSuccess) {
+  }
+  if (hipHostGetDevicePointer((void**)&c->d_mirror, c->h_state, 0) != hipSuccess) {
     g_last_error = "hipHostGetDevicePointer failed";
     qdse_destroy(c);
     return QDSE_EDEVICE;
@@ -247,9 +282,11 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
     if (ch >= 6 && ch <= 120 && ch % 6 == 0) c->chunk = ch;
   }
   for (int b = 0; b < c->n_blocks; ++b) {
-    hipError_t e = launch_precompute(st, g.n, g.nq, g.na, g.ldk, c->d_s, c->d_t, c->d_W, c->d_z,
-                                     c->d_wz, c->block_omega[b], 0, c->d_K + b * c->kstride,
-                                     nullptr);
+    const double om = c->block_omega[b];
+    const double gir = uv ? 8.0 * PI * PI * c->block_D[b] / (om * om * om * om) : 1.0;
+    hipError_t e = launch_precompute(st, c->krows, g.nq, g.na, g.ldk, qc ? c->d_sK : c->d_s,
+                                     c->d_t, c->d_W, c->d_z, c->d_wz, om, 0,
+                                     c->d_K + b * c->kstride, nullptr, gir, uv ? 1 : 0);
     if (e != hipSuccess) {
       g_last_error = std::string("precompute: ") + hipGetErrorString(e);
       qdse_destroy(c);
@@ -291,7 +328,7 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   // and all workgroups must be co-resident. Rows per workgroup: the smallest
   // count (from one row set per compute unit) whose grid fits, or
   // QDSE_PERSIST_RPW.
-  if (c->n_blocks == 1 && n_inst <= 64) {
+  if (c->n_blocks == 1 && n_inst <= 64 && !c->qc) {
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
     int rpw0 = std::max(1, (g.n + ncu - 1) / ncu), rpw1 = 8;
@@ -326,6 +363,20 @@ int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int
   return QDSE_OK;
 }
 
+int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int precision,
+               void* hip_stream, qdse_ctx** out) {
+  return setup_impl(grid, params, n_inst, precision, nullptr, hip_stream, out);
+}
+
+int qdse_setup_qc(const qdse_grid* grid, const qdse_params* params, int n_inst,
+                  const qdse_qc* qc, void* hip_stream, qdse_ctx** out) {
+  if (!qc) {
+    if (out) *out = nullptr;
+    return QDSE_EINVAL;
+  }
+  return setup_impl(grid, params, n_inst, QDSE_FP64, qc, hip_stream, out);
+}
+
 void qdse_destroy(qdse_ctx* c) {
   if (!c) return;
   for (auto& v : c->graphs)
@@ -339,7 +390,7 @@ void qdse_destroy(qdse_ctx* c) {
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
                   c->d_ctl,     c->d_part,    c->d_gq,      c->d_slots, c->d_barrier,
                   c->d_flags,   c->d_C32,     c->d_M64,     c->d_C64,     c->d_tstate,
-                  c->d_tctl};
+                  c->d_tctl,    c->d_sK,      c->d_sig};
   for (void* p : ptrs) dfree(p);
   delete c;
 }
@@ -382,6 +433,12 @@ int qdse_nodes(const qdse_ctx* c, double* s, double* t) {
 int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
   if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
   const HostGrid& g = c->hg;
+  if (c->qc) {
+    HIPCHK(launch_qc_sweep(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                           c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, d_x_in, d_x_out, c->d_nodes,
+                           c->d_sig, nullptr, nullptr, 1));
+    return QDSE_OK;
+  }
   HIPCHK(launch_sweep_fused(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
                             c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out, nullptr, nullptr, 1,
                             1, c->fused_rows));
@@ -409,7 +466,7 @@ int qdse_iterate_fp64_matrix(qdse_ctx* c, const double* d_x_in, double* d_x_out)
 }
 
 // Sweep kinds of a masked run.
-enum { SWEEP_DIRECT = 0, SWEEP_MM32 = 1, SWEEP_MM64 = 2 };
+enum { SWEEP_DIRECT = 0, SWEEP_MM32 = 1, SWEEP_MM64 = 2, SWEEP_QC = 3 };
 
 static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
   const HostGrid& g = c->hg;
@@ -425,6 +482,10 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
       HIPCHK(launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64, c->d_C64,
                                      c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo,
                                      c->d_state, c->d_ctl, k, true));
+    } else if (kind == SWEEP_QC) {
+      HIPCHK(launch_qc_sweep(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                             c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, xi, xo, c->d_nodes, c->d_sig,
+                             c->d_state, c->d_ctl, k));
     } else {
       HIPCHK(launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
                                 c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_state, c->d_ctl,
@@ -518,7 +579,7 @@ static int masked_begin(MaskedRun& r, qdse_ctx* c, double tol, int max_iter, int
   r.c = c;
   r.kind = kind;
   r.tol = tol;
-  r.first = kind == SWEEP_DIRECT ? c->chunk : c->chunk_mm;
+  r.first = kind == SWEEP_DIRECT || kind == SWEEP_QC ? c->chunk : c->chunk_mm;
   r.use_graph = std::getenv("QDSE_NO_GRAPH") == nullptr;
   r.launched = 0;
   // max_iter + 1 sweeps freeze every instance (the sweep after max_iter
@@ -677,7 +738,9 @@ int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
     if (tol32 < tol) tol32 = tol;
     return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32, g.d_x, nullptr);
   }
-  const int kind = c->precision == QDSE_FP64 ? SWEEP_DIRECT : SWEEP_MM64;
+  const int kind = c->qc                         ? SWEEP_QC
+                   : c->precision == QDSE_FP64 ? SWEEP_DIRECT
+                                               : SWEEP_MM64;
   return masked_begin(g.run, c, tol, max_iter, conv_mode, kind, g.phase == 0 ? g.d_x : nullptr,
                       g.d_x);
 }
@@ -792,6 +855,7 @@ int qdse_solve_stats(const qdse_ctx* c, int* sweeps_fp32, int* sweeps_fp64) {
 
 int qdse_jvp(qdse_ctx* c, const double* d_x, const double* d_v, double* d_jv) {
   if (!c || !d_x || !d_v || !d_jv) return QDSE_EINVAL;
+  if (c->qc) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
   HIPCHK(launch_jvp(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
                     c->d_sw, c->d_t, c->d_s, d_x, d_v, d_jv, c->d_nodes));
@@ -818,6 +882,7 @@ static int vjp_on(qdse_ctx* c, const double* K, const double* d_x, const double*
 
 int qdse_vjp(qdse_ctx* c, const double* d_x, const double* d_w, double* d_out) {
   if (!c || !d_x || !d_w || !d_out || d_w == d_out) return QDSE_EINVAL;
+  if (c->qc) return QDSE_ENOTSUP;
   return vjp_on(c, c->d_K, d_x, d_w, d_out);
 }
 
@@ -982,6 +1047,7 @@ extern "C" {
 int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol, int max_iter,
               double* theta_bar) {
   if (!c || !d_xstar || !d_g || !theta_bar || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
+  if (c->qc) return QDSE_ENOTSUP;
   for (const qdse_params& p : c->params)
     if (!(p.D > 0.0)) return QDSE_EINVAL;
   int rc = build_dK(c);
@@ -1035,6 +1101,7 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
 int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin_tol,
                 int* steps, double* resid) {
   if (!c || !d_x || !(tol > 0.0) || max_newton < 1 || !(lin_tol > 0.0)) return QDSE_EINVAL;
+  if (c->qc) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
   const int nI = c->n_inst, len = 2 * g.n;
   const size_t L = xlen(c);
@@ -1088,6 +1155,7 @@ int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin
 
 int qdse_kernel_matrices(qdse_ctx* c, int inst, double* d_K) {
   if (!c || !d_K || inst < 0 || inst >= c->n_inst) return QDSE_EINVAL;
+  if (c->qc) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
   const double* src = c->d_K + (size_t)c->inst_h[inst].kblock * c->kstride;
   HIPCHK(hipMemcpy2DAsync(d_K, g.nq * sizeof(double), src, g.ldk * sizeof(double),
@@ -1135,9 +1203,12 @@ int qdse_time_contraction(qdse_ctx* c, int which, const double* d_x, double* d_o
                                                c->d_C64, c->d_inst, c->d_lo, c->d_sw, c->d_t,
                                                c->d_s, d_x, d_out, c->d_tstate, c->d_tctl, 1,
                                                false, e0, e1)
-                     : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
-                                          c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out,
-                                          c->d_tstate, c->d_tctl, r + 1, 1, c->fused_rows, e0, e1);
+        : c->qc ? launch_qc_sweep(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                                  c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, d_x, d_out,
+                                  c->d_nodes, c->d_sig, c->d_tstate, c->d_tctl, r + 1, e0, e1)
+                : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
+                                     c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out,
+                                     c->d_tstate, c->d_tctl, r + 1, 1, c->fused_rows, e0, e1);
     if (e != hipSuccess) rc = QDSE_EDEVICE;
   }
   double tot = 0.0;

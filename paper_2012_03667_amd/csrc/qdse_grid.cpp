@@ -11,6 +11,7 @@
 // paper's modified interpolation (eq. chazhiresult) relies on.
 #include "qdse_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 // The grid must round exactly as written (no fused multiply-add contraction):
@@ -280,6 +281,43 @@ int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h) {
   h->sw_s.resize(4 * (ns + 1));
   build_stencils(ns, g.interp_order, h->us.data(), h->uqs.data(), h->lo_s.data(), h->sw_s.data());
   return 0;
+}
+
+// Interpolation stencil at an arbitrary p^2 = s inside the grid, with the
+// rule of the loop-node stencils: bracket u_b < ln s <= u_{b+1} by search;
+// order 1: the two bracketing nodes (the end value beyond the grid), order 3:
+// the four nodes b-1..b+2 shifted to stay inside the grid, Lagrange in u.
+QcPoint qc_point(const HostGrid& g, int order, double s) {
+  const int n = g.n;
+  const double x = std::log(s);
+  int b = -1;
+  for (int i = 0; i < n; ++i)
+    if (g.u[i] < x) b = i;
+  QcPoint p{};
+  p.s = s;
+  if (order == 1) {
+    if (b < 0) {
+      p.base = 0;
+      p.w[0] = 1.0;
+    } else if (b >= n - 1) {
+      p.base = n - 4;
+      p.w[3] = 1.0;
+    } else {
+      p.base = std::min(b, n - 4);
+      const double h = g.u[b + 1] - g.u[b];
+      p.w[b - p.base] = (g.u[b + 1] - x) / h;
+      p.w[b + 1 - p.base] = (x - g.u[b]) / h;
+    }
+    return p;
+  }
+  p.base = std::min(std::max(b - 1, 0), n - 4);
+  for (int l = 0; l < 4; ++l) {
+    double c = 1.0;
+    for (int k = 0; k < 4; ++k)
+      if (k != l) c *= (x - g.u[p.base + k]) / (g.u[p.base + l] - g.u[p.base + k]);
+    p.w[l] = c;
+  }
+  return p;
 }
 
 }  // namespace qdse

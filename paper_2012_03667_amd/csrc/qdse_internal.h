@@ -78,9 +78,34 @@ struct SolveCtl {
 constexpr int NKER = 3;
 
 // ---- launchers (qdse_kernels.hip); all asynchronous on `st` --------------
+// Kernel matrices of one interaction class for n external rows. gir and uv
+// select the interaction: uv = 0: exp(-k^2/omega^2) (D/omega^4 stays in the
+// instance's pref); uv = 1: gir exp(-k^2/omega^2) + the ultraviolet term of
+// the Qin-Chang interaction (pref without D).
 hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, const double* s,
                              const double* t, const double* W, const double* z, const double* wz,
-                             double omega, int with_domega, double* K, double* dK);
+                             double omega, int with_domega, double* K, double* dK,
+                             double gir = 1.0, int uv = 0);
+
+// Renormalisation point of the renormalised mode: p^2 = s and the 4-point
+// stencil (base, weights) that interpolates the iterate there.
+struct QcPoint {
+  double s;
+  double w[4];
+  int base;
+  int pad;
+};
+QcPoint qc_point(const HostGrid& g, int order, double s);
+// One sweep with renormalisation at zp (three kernels: node functions with
+// the masked-run decision, the sums of the n + 1 rows into sig
+// [n_inst][2 (n + 1)], the update). K has n + 1 rows per matrix; ev0/ev1 time
+// the sums kernel.
+hipError_t launch_qc_sweep(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                           const InstDev* inst, const double* K, size_t kstride, const int* lo,
+                           const double* sw, const double* t, const double* s, const QcPoint& zp,
+                           const double* x_in, double* x_out, double* nodes, double* sig,
+                           SolveState* state, const SolveCtl* ctl, int k,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Fresh solve states; optionally also the controls (ctl, v) and a copy of the
 // starting iterate x_src -> x_dst (xlen doubles).
 hipError_t launch_solve_init(hipStream_t st, int n_inst, SolveState* state,

@@ -94,6 +94,22 @@ __device__ inline double val(double x) { return x; }
 __device__ inline double val(Dual x) { return x.v; }
 __device__ inline double tan_(Dual x) { return x.d; }
 
+// Ultraviolet term of the Qin-Chang interaction, the part Sec. II leaves out:
+// 8 pi^2 gamma_m F(k^2) / ln[tau + (1 + k^2/L^2)^2] with F(k^2) =
+// (1 - exp(-k^2/(4 m_t^2)))/k^2, gamma_m = 12/25 (four flavours),
+// L = 0.234 GeV, tau = e^2 - 1, m_t = 0.5 GeV; at large k^2 it is 4 pi times
+// the one-loop running coupling.
+__device__ inline double g_uv_qc(double k2) {
+  constexpr double kPi = 3.14159265358979323846;
+  constexpr double kGammaM = 12.0 / 25.0;
+  constexpr double kInvL2 = 1.0 / (0.234 * 0.234);
+  constexpr double kInv4Mt2 = 1.0 / (4.0 * 0.5 * 0.5);
+  constexpr double kTau = 6.38905609893065022723;  // e^2 - 1
+  const double ff = -expm1(-k2 * kInv4Mt2) / k2;
+  const double q = fma(k2, kInvL2, 1.0);
+  return 8.0 * kPi * kPi * kGammaM * ff / log(fma(q, q, kTau));
+}
+
 // ---------------------------------------------------------------- precompute
 // One thread per (i, j); the angular sum runs over a in registers. Writes the
 // three matrices (and optionally their omega derivatives) of one omega class,
@@ -101,8 +117,8 @@ __device__ inline double tan_(Dual x) { return x.d; }
 __global__ void k_precompute(int n, int nq, int na, int ldk, const double* __restrict__ s_,
                              const double* __restrict__ t_, const double* __restrict__ W_,
                              const double* __restrict__ z_, const double* __restrict__ wz_,
-                             double omega, int with_domega, double* __restrict__ K,
-                             double* __restrict__ dK) {
+                             double omega, int with_domega, double gir, int uv,
+                             double* __restrict__ K, double* __restrict__ dK) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)n * ldk) return;
   const int i = (int)(idx / ldk), j = (int)(idx % ldk);
@@ -128,7 +144,7 @@ __global__ void k_precompute(int n, int nq, int na, int ldk, const double* __res
     const double z = z_[a], w = wz_[a];
     const double omz = 1.0 - z, opz = 1.0 + z;
     const double k2 = fma(2.0 * r, omz, d0);
-    const double E = w * exp(-k2 * inv_om2);
+    const double E = uv ? w * fma(gir, exp(-k2 * inv_om2), g_uv_qc(k2)) : w * exp(-k2 * inv_om2);
     const double tr = omz * opz / k2;
     const double f3 = (3.0 * r * z * (s + t) - 2.0 * s * t * (1.0 + 2.0 * z * z)) / k2;
     sT = fma(E, tr, sT);
@@ -633,6 +649,110 @@ __global__ void __launch_bounds__(256) k_sweep_row(
   }
 }
 
+// ---------------------------------------------------------------- renormalised mode
+// Sums of one sweep with a renormalisation point: one wavefront per external
+// row i < n and one for row n, p^2 = zeta^2, whose A and B are interpolated
+// from the iterate with the stencil of zp (the kernel matrices carry that
+// row as their last one). sig[inst][r] = Sigma_A(row r) and
+// sig[inst][(n+1) + r] = Sigma_B(row r), the loop sums times pref without
+// the inhomogeneous terms. Instances frozen at the start of this sweep are
+// skipped. Same per-row arithmetic as k_sweep.
+__global__ void __launch_bounds__(256) k_qc_sums(int n_inst, int n, int nq, int ldk,
+                                                 const InstDev* __restrict__ inst_,
+                                                 const double* __restrict__ K, size_t kstride,
+                                                 const double* __restrict__ s_, QcPoint zp,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ nodes,
+                                                 double* __restrict__ sig,
+                                                 const SolveState* state) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int rows = n + 1;
+  const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (row >= (long)n_inst * rows) return;
+  const int inst = (int)(row / rows), i = (int)(row % rows);
+  if (state && state[inst].status != 0) return;
+  const InstDev P = inst_[inst];
+  const double* xi = x + (size_t)inst * 2 * n;
+  double Ai, Bi, s;
+  if (i < n) {
+    Ai = xi[i];
+    Bi = xi[n + i];
+    s = s_[i];
+  } else {
+    Ai = 0.0;
+    Bi = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      Ai = fma(zp.w[l], xi[zp.base + l], Ai);
+      Bi = fma(zp.w[l], xi[n + zp.base + l], Bi);
+    }
+    s = zp.s;
+  }
+  const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
+  const double* nd = nodes + (size_t)inst * 5 * ldk;
+  double acc[4];
+  row_accumulate_f64(nq, ldk, (size_t)rows * ldk, Ki, nd, s, Ai, Bi, lane, acc);
+  if (lane == 0) {
+    double* sg = sig + (size_t)inst * 2 * rows;
+    sg[i] = P.pref * (acc[1] - acc[0]);
+    sg[rows + i] = P.pref * fma(2.0 * s, acc[2], acc[3]);
+  }
+}
+
+// Update with the renormalisation constants of this sweep: Z_2 = 1/(1 +
+// Sigma_A(zeta^2)) makes A(zeta^2) = 1 and Z_4 m = m - Z_2 Sigma_B(zeta^2)
+// makes B(zeta^2) = m (no mass term at m = 0); then A = Z_2 (1 + Sigma_A),
+// B = Z_4 m + Z_2 Sigma_B (vertex constant Z_1 = Z_2). One workgroup per
+// instance; in a masked run frozen instances carry their iterate and the
+// others fold their test statistic in with one atomic.
+__global__ void __launch_bounds__(256) k_qc_update(int n_inst, int n,
+                                                   const InstDev* __restrict__ inst_,
+                                                   const double* __restrict__ sig,
+                                                   const double* __restrict__ x_in,
+                                                   double* __restrict__ x_out, SolveState* state,
+                                                   const SolveCtl* ctl, int k) {
+  const int inst = blockIdx.x;
+  const double* xi = x_in + (size_t)inst * 2 * n;
+  double* xo = x_out + (size_t)inst * 2 * n;
+  if (state && state[inst].status != 0) {
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) xo[i] = xi[i];
+    return;
+  }
+  const int rows = n + 1;
+  const double* sg = sig + (size_t)inst * 2 * rows;
+  const double m = inst_[inst].m;
+  const double Z2 = 1.0 / (1.0 + sg[n]);
+  const double Z4m = m == 0.0 ? 0.0 : m - Z2 * sg[rows + n];
+  unsigned long long mine = 0ull;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double An = Z2 * (1.0 + sg[i]);
+    const double Bn = Z4m + Z2 * sg[rows + i];
+    xo[i] = An;
+    xo[n + i] = Bn;
+    if (state) {
+      const double r = test_stat(ctl->mode, An, Bn, xi[i], xi[n + i]);
+      const unsigned long long b = (unsigned long long)__double_as_longlong(
+          isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
+      mine = b > mine ? b : mine;
+    }
+  }
+  if (!state) return;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const unsigned long long v = __shfl_xor(mine, o, WAVE);
+    mine = v > mine ? v : mine;
+  }
+  __shared__ unsigned long long wmax[4];
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  if (lane == 0) wmax[wave] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mm = wmax[0];
+    for (int w = 1; w < 4; ++w) mm = wmax[w] > mm ? wmax[w] : mm;
+    atomicMax(&state[inst].metric[k % 3], mm);
+  }
+}
+
 // Tangent sweep: jv = dF/dx v, the same arithmetic in dual numbers.
 __global__ void __launch_bounds__(256) k_sweep_dual(int n_inst, int n, int nq, int ldk,
                                                     const InstDev* __restrict__ inst_,
@@ -948,11 +1068,35 @@ __global__ void k_axpby(int n_inst, int len, double alpha, const double* __restr
 // ---------------------------------------------------------------- launchers
 hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, const double* s,
                              const double* t, const double* W, const double* z, const double* wz,
-                             double omega, int with_domega, double* K, double* dK) {
+                             double omega, int with_domega, double* K, double* dK, double gir,
+                             int uv) {
   const long total = (long)n * ldk;
   const int bs = 256;
   hipLaunchKernelGGL(k_precompute, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, n, nq,
-                     na, ldk, s, t, W, z, wz, omega, with_domega, K, dK);
+                     na, ldk, s, t, W, z, wz, omega, with_domega, gir, uv, K, dK);
+  return hipGetLastError();
+}
+
+hipError_t launch_qc_sweep(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                           const InstDev* inst, const double* K, size_t kstride, const int* lo,
+                           const double* sw, const double* t, const double* s, const QcPoint& zp,
+                           const double* x_in, double* x_out, double* nodes, double* sig,
+                           SolveState* state, const SolveCtl* ctl, int k, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
+                     sw, t, x_in, nodes, state, ctl, k);
+  const long rows = (long)n_inst * (n + 1);
+  const dim3 grid((unsigned)((rows + 3) / 4));
+  if (ev0)
+    hipExtLaunchKernelGGL(k_qc_sums, grid, dim3(256), 0, st, ev0, ev1, 0, n_inst, n, nq, ldk, inst,
+                          K, kstride, s, zp, (const double*)x_in, (const double*)nodes, sig,
+                          (const SolveState*)state);
+  else
+    hipLaunchKernelGGL(k_qc_sums, grid, dim3(256), 0, st, n_inst, n, nq, ldk, inst, K, kstride, s,
+                       zp, (const double*)x_in, (const double*)nodes, sig,
+                       (const SolveState*)state);
+  hipLaunchKernelGGL(k_qc_update, dim3(n_inst), dim3(256), 0, st, n_inst, n, inst,
+                     (const double*)sig, x_in, x_out, state, ctl, k);
   return hipGetLastError();
 }
 

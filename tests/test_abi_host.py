@@ -50,6 +50,21 @@ def test_setup_rejects_bad_arguments_before_hip(L):
         assert L.qdse_setup(ctypes.byref(g), pp, 1, 0, None, ctypes.byref(h)) == -1
 
 
+def test_setup_qc_rejects_bad_arguments_before_hip(L):
+    from paper_2012_03667_amd._lib import Grid, Params, Qc
+    h = ctypes.c_void_p()
+    p = (Params * 1)(Params(0.55, 0.678, 0.0034))
+    g = Grid(n_radial=64, n_angle=32, interp_order=3, s_min=1e-4, s_max=1e4)
+    assert L.qdse_setup_qc(ctypes.byref(g), p, 1, None, None, ctypes.byref(h)) == -1
+    for q in (Qc(2, 19.0), Qc(1, 0.0), Qc(1, -19.0), Qc(1, 100.0), Qc(1, 1e-2),
+              Qc(1, float("nan"))):
+        assert L.qdse_setup_qc(ctypes.byref(g), p, 1, ctypes.byref(q), None,
+                               ctypes.byref(h)) == -1, (q.uv, q.zeta)
+    bad = Grid(n_radial=3, n_angle=32, interp_order=3, s_min=1e-4, s_max=1e4)
+    q = Qc(1, 19.0)
+    assert L.qdse_setup_qc(ctypes.byref(bad), p, 1, ctypes.byref(q), None, ctypes.byref(h)) == -1
+
+
 def test_entry_points_reject_null_context(L):
     assert L.qdse_iterate(None, None, None) == -1
     assert L.qdse_solve(None, None, ctypes.c_double(1e-10), 10, 0, None, None) == -1
