@@ -1,0 +1,140 @@
+"""Parity of the renormalised Qin-Chang setting (qdse_setup_qc: ultraviolet
+term of the interaction, renormalisation at zeta) with the CPU oracle, through
+the C ABI. Same tolerance argument as the vacuum sweeps: the sums are FP64
+sums of the same terms in a different order and Z_2 is a ratio of such sums.
+B' = Z_4 m + Z_2 Sigma_B adds two terms that largely cancel (the mass
+counterterm), so B' is compared relative to the larger of |B'| and the two
+terms, |Z_2 Sigma_B| (the oracle's B' at m = 0, which does not depend on m)
+and |Z_4 m| (the difference of the two)."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import qdse_oracle as O  # noqa: E402
+
+RTOL = 1e-12
+
+
+def rel_err(gpu, ref):
+    den = np.maximum(np.abs(ref), 1e-8 * np.max(np.abs(ref)))
+    return float(np.max(np.abs(gpu - ref) / den))
+
+
+def errs(x_gpu, x_ref, n, x_ref0=None):
+    """Errors of A, B and M = B/A; with x_ref0 (the oracle at m = 0) B and M
+    are measured against the scale of the cancelling terms."""
+    A, B = x_gpu[:n], x_gpu[n:]
+    Ar, Br = x_ref[:n], x_ref[n:]
+    if x_ref0 is None:
+        return rel_err(A, Ar), rel_err(B, Br), rel_err(B / A, Br / Ar)
+    B0 = x_ref0[n:]
+    z4m = Br[0] - B0[0]
+    scale = np.maximum.reduce([np.abs(Br), np.abs(B0), np.full(n, abs(z4m)),
+                               np.full(n, 1e-8 * np.max(np.abs(Br)))])
+    eB = float(np.max(np.abs(B - Br) / scale))
+    eM = float(np.max(np.abs(B / A - Br / Ar) / (scale / np.abs(Ar))))
+    return rel_err(A, Ar), eB, eM
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_03667_amd as Q
+    Q.load()
+    return Q
+
+
+def smooth_x(s, rng):
+    A = 1.0 + rng.uniform(0.3, 0.8) / (1 + s / rng.uniform(0.1, 1.0))
+    B = rng.uniform(0.2, 0.5) / (1 + s / rng.uniform(0.1, 1.0)) + 0.003
+    return np.concatenate([A, B])
+
+
+CASES = [  # (n, na, order, zeta): off-node and at-node renormalisation points
+    (64, 32, 3, 19.0),
+    (37, 7, 1, 5.0),
+    (130, 65, 3, 2.0),
+    (96, 16, 3, None),  # zeta^2 at external node 80
+]
+
+
+@pytest.mark.parametrize("n,na,order,zeta", CASES)
+def test_renormalised_sweep_matches_oracle(Q, n, na, order, zeta):
+    g = O.vac_grid(n, na, order=order)
+    if zeta is None:
+        zeta = math.sqrt(g.s[80])
+    print(f"case qc sweep n={n} na={na} order={order} zeta={zeta}", flush=True)
+    rng = np.random.default_rng(n + 7)
+    params = [(0.55, 0.678, 0.0034), (0.55, 0.678, 0.0), (1.024, 0.5, 0.02)]
+    S = Q.Solver(n, na, params, interp_order=order, zeta=zeta)
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    y = S.iterate(torch.tensor(xs, device="cuda")).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        ref = O.F(g, O.Params(D, om, m, 1.0, 1, zeta), xs[k])
+        ref0 = O.F(g, O.Params(D, om, 0.0, 1.0, 1, zeta), xs[k])
+        e = errs(y[k], ref, n, ref0)
+        assert max(e) < RTOL, (k, e)
+    S.close()
+
+
+def test_renormalised_solve_matches_oracle_fixed_point(Q):
+    n, na = 64, 32
+    g = O.vac_grid(n, na)
+    params = [(0.55, 0.678, 0.0034), (0.55, 0.678, 0.0)]
+    print("case qc solve n=64", flush=True)
+    S = Q.Solver(n, na, params, zeta=19.0)
+    x = S.initial(1.0, 1.0)
+    rc, it, rs = S.solve(x, tol=1e-11, max_iter=500)
+    torch.cuda.synchronize()
+    assert rc == Q.QDSE_OK, (rc, it, rs)
+    xg = x.cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        xr, itr = O.picard(g, O.Params(D, om, m, 1.0, 1, 19.0), np.ones(2 * n), 1e-11,
+                           max_iter=500, mode=1)[:2]
+        assert abs(int(it[k]) - itr) <= 1, (k, it[k], itr)
+        assert max(errs(xg[k], xr, n)) < 1e-10
+        # the renormalisation condition at the fixed point, through the
+        # same interpolation as the sweep
+        assert abs(np.interp(math.log(361.0), g.u, xg[k, :n]) - 1.0) < 1e-3
+    S.close()
+
+
+def test_renormalised_large_grid_sampled_rows(Q):
+    """The benchmark's grid (512 x 128), three instances, sampled rows."""
+    n, na = 512, 128
+    g = O.vac_grid(n, na)
+    rng = np.random.default_rng(512)
+    rows = np.sort(np.concatenate([[0, 1, 255, 510, 511], rng.choice(n, 5, replace=False)]))
+    params = [(0.55, 0.678, 0.0034), (0.55, 0.678, 0.0), (0.6, 0.7, 0.01)]
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    print("case qc sampled rows n=512", flush=True)
+    S = Q.Solver(n, na, params, zeta=19.0)
+    y = S.iterate(torch.tensor(xs, device="cuda")).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        a, b = O.F_rows(g, O.Params(D, om, m, 1.0, 1, 19.0), xs[k], rows)
+        a0, b0 = O.F_rows(g, O.Params(D, om, 0.0, 1.0, 1, 19.0), xs[k], rows)
+        ref, ref0 = np.concatenate([a, b]), np.concatenate([a0, b0])
+        got = np.concatenate([y[k, rows], y[k, n + rows]])
+        e = errs(got, ref, len(rows), ref0)
+        assert max(e) < RTOL, (k, e)
+    S.close()
+
+
+def test_renormalised_context_rejects_unsupported_calls(Q):
+    from paper_2012_03667_amd._lib import load, _vp
+    S = Q.Solver(16, 8, [(0.55, 0.678, 0.0034)], zeta=19.0)
+    x = S.initial(1.0, 1.0)
+    y = torch.empty_like(x)
+    L = load()
+    p = _vp(x.data_ptr())
+    ENOTSUP = -5  # include/qdse.h
+    assert L.qdse_jvp(S._h, p, p, _vp(y.data_ptr())) == ENOTSUP
+    assert L.qdse_vjp(S._h, p, p, _vp(y.data_ptr())) == ENOTSUP
+    assert L.qdse_iterate_fp32(S._h, p, _vp(y.data_ptr())) == ENOTSUP
+    S.close()
