@@ -202,6 +202,48 @@ def mixed_batch(Q, np, torch, B):
     return out
 
 
+def renormalised_qc(Q, np, torch, reps=20):
+    """Renormalised Qin-Chang setting (ultraviolet term of the interaction,
+    renormalisation at zeta = 19 GeV) on the headline's 512 x 128 grid with its
+    infrared parameters, m(zeta) in {3.4 MeV, 0}: converged solves/s (tol
+    1e-10 on M and A), and the sums kernel against the HBM roofline."""
+    n, na, zeta = 512, 128, 19.0
+    params = [(0.55, 0.678, 0.0034), (0.55, 0.678, 0.0)]
+    S = Q.Solver(n, na, params, zeta=zeta)
+    x0 = S.initial(1.0, 1.0)
+    x = torch.empty_like(x0)
+    for _ in range(3):
+        x.copy_(x0)
+        S.solve(x, tol=1e-10, max_iter=2000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x.copy_(x0)
+        rc, it, rs = S.solve(x, tol=1e-10, max_iter=2000)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    xs = x.cpu().numpy()
+    ms = S.time_contraction(x, reps=200)
+    S.close()
+    nq = n + 1
+    # sums kernel: three FP64 matrices with n + 1 rows, the loop-node functions
+    # (5 per node) and the iterate read, 2 (n + 1) sums written, per instance
+    alg = 3 * (n + 1) * nq * 8 + len(params) * (5 * nq * 8 + 2 * n * 8 + 2 * (n + 1) * 8)
+    ach = alg / (ms * 1e-3) / 1e9
+    return {
+        "workload": "512x128, D=0.55 GeV^2, omega=0.678 GeV plus the Qin-Chang ultraviolet term, "
+                    "renormalised at zeta=19 GeV, m(zeta) in {3.4 MeV, 0}, A0=B0=1, tol 1e-10",
+        "rc": int(rc), "sweeps": [int(v) for v in it], "solves_per_s": len(params) / dt,
+        "ms_per_step": dt * 1e3,
+        "M_at_p2_1e-4": [float(xs[k, n] / xs[k, 0]) for k in range(len(params))],
+        "A_at_p2_1e-4": [float(xs[k, 0]) for k in range(len(params))],
+        "roofline": {"bound": "hbm", "kernel": "k_qc_sums (sums of the n + 1 rows, 2 instances)",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "avg_kernel_us": ms * 1e3, "alg_bytes_per_launch": alg},
+    }
+
+
 def finite_mu(Q, np, torch):
     """Finite mu = 0.3 GeV, T = 0, paper interaction, m = 5 MeV: external
     128 |p_vec| x 128 p4 nodes, loop 129 x 129 nodes with q4 of both signs and
@@ -286,6 +328,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-mu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-qc", action="store_true")
     ap.add_argument("--grad-batch", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one cold 1 GiB device copy (reference for HBM byte counters)")
@@ -448,6 +491,10 @@ def main():
     # ---- mixed grid classes (vacuum instances), grouped by class
     if not args.no_mixed:
         line["mixed_batch_vacuum"] = mixed_batch(Q, np, torch, args.batch)
+
+    # ---- renormalised Qin-Chang setting (ultraviolet term, renormalisation)
+    if not args.no_qc:
+        line["renormalised_qc"] = renormalised_qc(Q, np, torch)
 
     # ---- finite chemical potential: one sweep of the 128 x 128 x 32 grid
     if not args.no_mu:
