@@ -316,6 +316,63 @@ int qdse_mu_solve(qdse_mu_ctx* ctx, double* d_x, double tol, int max_iter, int* 
 int qdse_mu_solve_anderson(qdse_mu_ctx* ctx, double* d_x, double tol, int max_iter, int depth,
                            int* iters, double* resid);
 
+/* ---- the general system the paper starts from (Sec. I) ------------------
+ * Two nonlinear integral equations of the second kind on [a, b] (eq. jifen1):
+ *   u(x) = f1(x) + int [K1(x,t) F11(u,v)(t) + Kbar(x,t) F12(u,v)(t)] dt
+ *   v(x) = f2(x) + int [K2(x,t) F21(u,v)(t) + Kbar(x,t) F22(u,v)(t)] dt
+ * (eq. jifen1 prints F21 twice; the second is read as F22), with the
+ * singular kernel of eq. jifen3 taken as Kbar = |x - t|^-alpha for
+ * 0 < alpha < 1 and as 1/(x - t) for alpha = 1, solved by successive
+ * approximation (eq. jifen12) on the quark equation's discretisation:
+ * unknowns at the n Gauss-Legendre nodes x_i of [a, b], integrals on the
+ * n + 1 Gauss-Legendre nodes t_j (weights w_j; the two sets interlace, so
+ * x_i != t_j), u(t_j) and v(t_j) by Lagrange interpolation on the x grid
+ * (2- or 4-point, as eq. chazhiresult and its cubic analogue). The
+ * nonlinearities are quadratics F(u, v) = c0 + c1 u + c2 v + c3 u^2 +
+ * c4 u v + c5 v^2. */
+typedef struct qdse_fred_ctx qdse_fred_ctx;
+
+typedef struct {
+  int n;             /* external nodes, 4 <= n <= 65536                       */
+  int interp_order;  /* 1 or 3                                                */
+  double a, b;       /* the interval, a < b                                   */
+  double alpha;      /* singular exponent, 0 < alpha <= 1                     */
+} qdse_fred_grid;
+
+typedef struct {
+  double c[6];       /* F(u, v) = c0 + c1 u + c2 v + c3 u^2 + c4 u v + c5 v^2 */
+} qdse_fred_poly;
+
+/* Host arrays x [n], t [n+1], w [n+1] of the discretisation (no device use).
+ * Errors: QDSE_EINVAL. */
+int qdse_fred_nodes(const qdse_fred_grid* grid, double* x, double* t, double* w);
+
+/* F: host [4] = F11, F12, F21, F22. d_K1, d_K2: device [n][n+1] row-major,
+ * K(x_i, t_j); d_f: device [2n] = f1(x_i) | f2(x_i). The three device arrays
+ * stay owned by the caller and are read by every later call (keep them
+ * alive and unchanged). Unknowns: device [2n] = u(x_i) | v(x_i).
+ * Errors: QDSE_EINVAL (grid out of range, NULL pointer, non-finite
+ * coefficient), QDSE_ENOMEM, QDSE_EDEVICE. */
+int qdse_fred_setup(const qdse_fred_grid* grid, const qdse_fred_poly* F, const double* d_K1,
+                    const double* d_K2, const double* d_f, void* hip_stream,
+                    qdse_fred_ctx** out);
+void qdse_fred_destroy(qdse_fred_ctx* ctx);
+
+/* One sweep of eq. jifen12, asynchronous on the context's stream. */
+int qdse_fred_iterate(qdse_fred_ctx* ctx, const double* d_in, double* d_out);
+
+/* Successive approximation from d_uv (in place) until max |uv' - uv| < tol
+ * (the test of eq. jifenab2 on u and v) or max_iter sweeps; *iters = sweeps
+ * done, *resid = the last change (either may be NULL). Returns QDSE_OK,
+ * QDSE_NOT_CONVERGED or QDSE_ENAN; synchronises the stream. */
+int qdse_fred_solve(qdse_fred_ctx* ctx, double* d_uv, double tol, int max_iter, int* iters,
+                    double* resid);
+
+/* Average duration of the row kernel over `reps` sweeps d_in -> d_out (events
+ * on its dispatch packet), in ms. */
+int qdse_fred_time_sweep(qdse_fred_ctx* ctx, const double* d_in, double* d_out, int reps,
+                         double* avg_ms);
+
 /* Human-readable name of a status code. */
 const char* qdse_strerror(int code);
 

@@ -42,6 +42,15 @@ class Qc(ctypes.Structure):
     _fields_ = [("uv", ctypes.c_int), ("zeta", ctypes.c_double)]
 
 
+class FredGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("interp_order", ctypes.c_int), ("a", ctypes.c_double),
+                ("b", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class FredPoly(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double * 6)]
+
+
 class MuParams(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double), ("omega", ctypes.c_double), ("m", ctypes.c_double),
                 ("mu", ctypes.c_double)]
@@ -95,6 +104,14 @@ def load():
     L.qdse_mu_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]
     L.qdse_mu_solve_anderson.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                          _ip, _dp]
+    L.qdse_fred_nodes.argtypes = [ctypes.POINTER(FredGrid), _dp, _dp, _dp]
+    L.qdse_fred_setup.argtypes = [ctypes.POINTER(FredGrid), ctypes.POINTER(FredPoly), _vp, _vp,
+                                  _vp, _vp, ctypes.POINTER(_vp)]
+    L.qdse_fred_destroy.argtypes = [_vp]
+    L.qdse_fred_destroy.restype = None
+    L.qdse_fred_iterate.argtypes = [_vp, _vp, _vp]
+    L.qdse_fred_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]
+    L.qdse_fred_time_sweep.argtypes = [_vp, _vp, _vp, ctypes.c_int, _dp]
     L.qdse_strerror.argtypes = [ctypes.c_int]
     L.qdse_strerror.restype = ctypes.c_char_p
     L.qdse_last_error.argtypes = []
@@ -372,3 +389,76 @@ class MuSolver:
                                                it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
         _check(rc, "qdse_mu_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
         return rc, it, rs
+
+
+def fred_nodes(n, a, b, alpha=0.5, interp_order=3):
+    """Host-only: x [n], t [n+1], w [n+1] of the general system's grid."""
+    g = FredGrid(int(n), int(interp_order), float(a), float(b), float(alpha))
+    x, t, w = np.empty(n), np.empty(n + 1), np.empty(n + 1)
+    _check(load().qdse_fred_nodes(ctypes.byref(g), x.ctypes.data_as(_dp), t.ctypes.data_as(_dp),
+                                  w.ctypes.data_as(_dp)), "qdse_fred_nodes")
+    return x, t, w
+
+
+class FredSolver:
+    """The general system of Sec. I (qdse_fred_* in include/qdse.h).
+
+    F: 4 x 6 coefficients (F11, F12, F21, F22 as quadratics in u, v);
+    K1, K2: float64 CUDA tensors [n, n+1] (K(x_i, t_j)); f: [2n] = f1 | f2.
+    The tensors are kept referenced for the solver's lifetime.
+    """
+
+    def __init__(self, n, a, b, alpha, F, K1, K2, f, interp_order=3, stream=None):
+        import torch
+        L = load()
+        self.n = int(n)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._keep = (K1, K2, f)
+        g = FredGrid(self.n, int(interp_order), float(a), float(b), float(alpha))
+        Fc = np.asarray(F, dtype=np.float64).reshape(4, 6)
+        P = (FredPoly * 4)(*[FredPoly((ctypes.c_double * 6)(*row)) for row in Fc])
+        h = _vp()
+        _check(L.qdse_fred_setup(ctypes.byref(g), P,
+                                 _dev(K1, (self.n, self.n + 1), "K1"),
+                                 _dev(K2, (self.n, self.n + 1), "K2"),
+                                 _dev(f, (2 * self.n,), "f"), _vp(self.stream.cuda_stream),
+                                 ctypes.byref(h)), "qdse_fred_setup")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().qdse_fred_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, uv, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(uv)
+        _check(load().qdse_fred_iterate(self._h, _dev(uv, (2 * self.n,), "uv"),
+                                        _dev(out, (2 * self.n,), "out")), "qdse_fred_iterate")
+        return out
+
+    def solve(self, uv, tol=1e-12, max_iter=1000):
+        """In place. Returns (status, sweeps, last change)."""
+        it = ctypes.c_int(0)
+        r = ctypes.c_double(0.0)
+        rc = _check(load().qdse_fred_solve(self._h, _dev(uv, (2 * self.n,), "uv"), float(tol),
+                                           int(max_iter), ctypes.byref(it), ctypes.byref(r)),
+                    "qdse_fred_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+        return rc, it.value, r.value
+
+    def time_sweep(self, uv, reps=50):
+        import torch
+        out = torch.empty_like(uv)
+        ms = ctypes.c_double(0.0)
+        _check(load().qdse_fred_time_sweep(self._h, _dev(uv, (2 * self.n,), "uv"),
+                                           _dev(out, (2 * self.n,), "out"), int(reps),
+                                           ctypes.byref(ms)), "qdse_fred_time_sweep")
+        return ms.value
+

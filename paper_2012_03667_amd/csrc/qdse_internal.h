@@ -187,6 +187,17 @@ hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, 
 hipError_t launch_mu_stat(hipStream_t st, int n_inst, int ne, const double* x_old,
                           const double* x_new, unsigned long long* stat);
 
+// General second-kind system (qdse_fred.hip): one sweep on n external and
+// n + 1 loop nodes; K1, K2 [n][n+1] row-major, coef [4][6], G [4][n+1]
+// workspace, stat (optional) receives max |uv' - uv| as double bits.
+hipError_t launch_fred_sweep(hipStream_t st, int n, double alpha, const double* x,
+                             const double* t, const double* w, const int* lo, const double* sw,
+                             const double* coef, const double* K1, const double* K2,
+                             const double* f, const double* uv_in, double* uv_out, double* G,
+                             unsigned long long* stat, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
+void gl_nodes_on(int n, double a, double b, double* x, double* w);
+
 // Persistent (cooperative) solve of a few instances sharing kernel block 0.
 size_t persistent_lds_bytes(int rpw, int n, int nq, int gsz);
 size_t persistent_barrier_words();

@@ -65,6 +65,29 @@ def test_setup_qc_rejects_bad_arguments_before_hip(L):
     assert L.qdse_setup_qc(ctypes.byref(bad), p, 1, ctypes.byref(q), None, ctypes.byref(h)) == -1
 
 
+def test_fred_entry_points_reject_bad_arguments_before_hip(L):
+    import numpy as np
+    from paper_2012_03667_amd._lib import FredGrid, FredPoly
+    dp = ctypes.POINTER(ctypes.c_double)
+    x, t, w = np.empty(70), np.empty(71), np.empty(71)
+    args = [a.ctypes.data_as(dp) for a in (x, t, w)]
+    good = dict(n=64, interp_order=3, a=0.0, b=1.0, alpha=0.5)
+    assert L.qdse_fred_nodes(ctypes.byref(FredGrid(**good)), *args) == 0
+    for bad in (dict(good, n=3), dict(good, interp_order=2), dict(good, a=1.0),
+                dict(good, alpha=0.0), dict(good, alpha=1.5), dict(good, b=float("inf"))):
+        assert L.qdse_fred_nodes(ctypes.byref(FredGrid(**bad)), *args) == -1, bad
+    h = ctypes.c_void_p()
+    F = (FredPoly * 4)()
+    g = FredGrid(**good)
+    assert L.qdse_fred_setup(ctypes.byref(g), F, None, None, None, None, ctypes.byref(h)) == -1
+    F[1].c[2] = float("nan")
+    p = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert L.qdse_fred_setup(ctypes.byref(g), F, p, p, p, None, ctypes.byref(h)) == -1
+    assert L.qdse_fred_iterate(None, None, None) == -1
+    assert L.qdse_fred_solve(None, None, ctypes.c_double(1e-10), 10, None, None) == -1
+    L.qdse_fred_destroy(None)
+
+
 def test_entry_points_reject_null_context(L):
     assert L.qdse_iterate(None, None, None) == -1
     assert L.qdse_solve(None, None, ctypes.c_double(1e-10), 10, 0, None, None) == -1
