@@ -244,6 +244,44 @@ def renormalised_qc(Q, np, torch, reps=20):
     }
 
 
+def general_system(Q, np, torch, n=4096, reps=50):
+    """The general system of Sec. I at n = 4096 (alpha = 1/2): one sweep's row
+    kernel against the HBM roofline (the two caller matrices K1, K2 are the
+    traffic) and a contracting solve to 1e-12."""
+    a, b, alpha = 0.0, 1.0, 0.5
+    rng = np.random.default_rng(4096)
+    x, t, w = Q.fred_nodes(n, a, b, alpha)
+    K1 = 0.1 * np.exp(-(x[:, None] - t[None, :]) ** 2)
+    K2 = 0.1 * np.cos(x[:, None] + 2 * t[None, :])
+    F = rng.uniform(-1, 1, (4, 6)) * np.array([0.1, 0.2, 0.2, 0.05, 0.05, 0.05])
+    f = np.concatenate([1.0 + 0.3 * np.sin(x), 0.5 * np.cos(x)])
+    dev = lambda a_: torch.tensor(np.ascontiguousarray(a_), device="cuda")  # noqa: E731
+    dK1, dK2, df = dev(K1), dev(K2), dev(f)
+    del K1, K2
+    S = Q.FredSolver(n, a, b, alpha, F, dK1, dK2, df)
+    uv = dev(np.ones(2 * n))
+    ms = S.time_sweep(uv, reps=reps)
+    x0 = uv.clone()
+    S.solve(uv, tol=1e-12, max_iter=500)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uv.copy_(x0)
+    rc, it, r = S.solve(uv, tol=1e-12, max_iter=500)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S.close()
+    nq = n + 1
+    alg = 2 * n * nq * 8 + 4 * nq * 8 + nq * 8 + 3 * 2 * n * 8
+    ach = alg / (ms * 1e-3) / 1e9
+    return {
+        "workload": f"n={n} on [0, 1], alpha=1/2, K1 Gaussian, K2 cosine (0.1 scale), seeded quadratic F",
+        "sweep_kernel_us": ms * 1e3, "solve": {"rc": int(rc), "sweeps": int(it), "seconds": dt},
+        "roofline": {"bound": "hbm", "kernel": "k_fred_rows", "achieved": ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "avg_kernel_us": ms * 1e3, "alg_bytes_per_launch": alg},
+    }
+
+
 def finite_mu(Q, np, torch):
     """Finite mu = 0.3 GeV, T = 0, paper interaction, m = 5 MeV: external
     128 |p_vec| x 128 p4 nodes, loop 129 x 129 nodes with q4 of both signs and
@@ -329,6 +367,7 @@ def main():
     ap.add_argument("--no-mu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-qc", action="store_true")
+    ap.add_argument("--no-fred", action="store_true")
     ap.add_argument("--grad-batch", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one cold 1 GiB device copy (reference for HBM byte counters)")
@@ -495,6 +534,10 @@ def main():
     # ---- renormalised Qin-Chang setting (ultraviolet term, renormalisation)
     if not args.no_qc:
         line["renormalised_qc"] = renormalised_qc(Q, np, torch)
+
+    # ---- the general second-kind system of Sec. I
+    if not args.no_fred:
+        line["general_system"] = general_system(Q, np, torch)
 
     # ---- finite chemical potential: one sweep of the 128 x 128 x 32 grid
     if not args.no_mu:
