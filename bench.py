@@ -226,9 +226,10 @@ def renormalised_qc(Q, np, torch, reps=20):
     ms = S.time_contraction(x, reps=200)
     S.close()
     nq = n + 1
-    # sums kernel: three FP64 matrices with n + 1 rows, the loop-node functions
-    # (5 per node) and the iterate read, 2 (n + 1) sums written, per instance
-    alg = 3 * (n + 1) * nq * 8 + len(params) * (5 * nq * 8 + 2 * n * 8 + 2 * (n + 1) * 8)
+    # sums kernel: three FP64 matrices with n + 1 rows and the loop-node
+    # weights and t once; per instance the iterate read and 2 (n + 1) sums
+    # written
+    alg = 3 * (n + 1) * nq * 8 + nq * 40 + len(params) * (2 * n * 8 + 2 * (n + 1) * 8)
     ach = alg / (ms * 1e-3) / 1e9
     return {
         "workload": "512x128, D=0.55 GeV^2, omega=0.678 GeV plus the Qin-Chang ultraviolet term, "
@@ -237,7 +238,7 @@ def renormalised_qc(Q, np, torch, reps=20):
         "ms_per_step": dt * 1e3,
         "M_at_p2_1e-4": [float(xs[k, n] / xs[k, 0]) for k in range(len(params))],
         "A_at_p2_1e-4": [float(xs[k, 0]) for k in range(len(params))],
-        "roofline": {"bound": "hbm", "kernel": "k_qc_sums (sums of the n + 1 rows, 2 instances)",
+        "roofline": {"bound": "hbm", "kernel": "k_sweep_row<true> (renormalised sums of the n + 1 rows, 2 instances)",
                      "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
                      "avg_kernel_us": ms * 1e3, "alg_bytes_per_launch": alg},

@@ -435,8 +435,8 @@ int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
   const HostGrid& g = c->hg;
   if (c->qc) {
     HIPCHK(launch_qc_sweep(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                           c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, d_x_in, d_x_out, c->d_nodes,
-                           c->d_sig, nullptr, nullptr, 1));
+                           c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, d_x_in, d_x_out, c->d_sig,
+                           nullptr, nullptr, 1));
     return QDSE_OK;
   }
   HIPCHK(launch_sweep_fused(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
@@ -484,8 +484,8 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
                                      c->d_state, c->d_ctl, k, true));
     } else if (kind == SWEEP_QC) {
       HIPCHK(launch_qc_sweep(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                             c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, xi, xo, c->d_nodes, c->d_sig,
-                             c->d_state, c->d_ctl, k));
+                             c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, xi, xo, c->d_sig, c->d_state,
+                             c->d_ctl, k));
     } else {
       HIPCHK(launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
                                 c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_state, c->d_ctl,
@@ -1205,7 +1205,7 @@ int qdse_time_contraction(qdse_ctx* c, int which, const double* d_x, double* d_o
                                                false, e0, e1)
         : c->qc ? launch_qc_sweep(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
                                   c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, d_x, d_out,
-                                  c->d_nodes, c->d_sig, c->d_tstate, c->d_tctl, r + 1, e0, e1)
+                                  c->d_sig, c->d_tstate, c->d_tctl, r + 1, e0, e1)
                 : launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K,
                                      c->kstride, c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_out,
                                      c->d_tstate, c->d_tctl, r + 1, 1, c->fused_rows, e0, e1);

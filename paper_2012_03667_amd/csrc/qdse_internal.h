@@ -96,14 +96,13 @@ struct QcPoint {
   int pad;
 };
 QcPoint qc_point(const HostGrid& g, int order, double s);
-// One sweep with renormalisation at zp (three kernels: node functions with
-// the masked-run decision, the sums of the n + 1 rows into sig
-// [n_inst][2 (n + 1)], the update). K has n + 1 rows per matrix; ev0/ev1 time
-// the sums kernel.
+// One sweep with renormalisation at zp (two kernels: the sums of the n + 1
+// rows into sig [n_inst][2 (n + 1)] with the masked-run decision, then the
+// update). K has n + 1 rows per matrix; ev0/ev1 time the sums kernel.
 hipError_t launch_qc_sweep(hipStream_t st, int n_inst, int n, int nq, int ldk,
                            const InstDev* inst, const double* K, size_t kstride, const int* lo,
                            const double* sw, const double* t, const double* s, const QcPoint& zp,
-                           const double* x_in, double* x_out, double* nodes, double* sig,
+                           const double* x_in, double* x_out, double* sig,
                            SolveState* state, const SolveCtl* ctl, int k,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Fresh solve states; optionally also the controls (ctl, v) and a copy of the

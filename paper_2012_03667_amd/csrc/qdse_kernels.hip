@@ -532,19 +532,27 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
 // arithmetic and order as k_sweep.
 constexpr int ROW_PF = 9;   // lane strides held in registers: nq <= 576 in one round
 constexpr int NODE_PT = 3;  // nodes per thread per pass of the node build
+//
+// QC = true is the renormalised mode's sums kernel: the matrices have n + 1
+// rows, row n (p^2 = zeta^2) takes A and B interpolated with the stencil of
+// zp, and each wavefront writes its row's loop sums times pref (without the
+// inhomogeneous terms) to sig[inst][i], sig[inst][(n+1) + i] for the update
+// kernel; frozen instances write nothing.
+template <bool QC>
 __global__ void __launch_bounds__(256) k_sweep_row(
     int n_inst, int n, int nq, int ldk, const InstDev* __restrict__ inst_,
     const double* __restrict__ K, size_t kstride, const int* __restrict__ lo,
     const double* __restrict__ sw, const double* __restrict__ t_, const double* __restrict__ s_,
     const double* __restrict__ x_in, double* __restrict__ x_out, SolveState* state,
-    const SolveCtl* ctl, int k, int add_f0) {
+    const SolveCtl* ctl, int k, int add_f0, QcPoint zp, double* __restrict__ sig) {
   extern __shared__ double nd[];  // [5][ldk] and one spare slot
   const int inst = blockIdx.y;
   const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
   const double* xi = x_in + (size_t)inst * 2 * n;
   double* xo = x_out + (size_t)inst * 2 * n;
+  const int rows = QC ? n + 1 : n;
   const int i = blockIdx.x * 4 + wave;
-  const int ic = i < n ? i : n - 1;  // rows past n read row n - 1 and write nothing
+  const int ic = i < rows ? i : rows - 1;  // rows past the last read it and write nothing
   // Loop node j lies between external nodes j - 1 and j (the loop grid
   // interleaves the external one), so its 4-point stencil starts at
   // clamp(j - 2, 0, n - 4), the base the grid's stencil table holds: the
@@ -572,7 +580,7 @@ __global__ void __launch_bounds__(256) k_sweep_row(
   node_reads(threadIdx.x);
   __builtin_amdgcn_sched_barrier(0);  // keep these reads ahead of the kernel-row reads
   const InstDev P = inst_[inst];
-  const size_t mat = (size_t)n * ldk;
+  const size_t mat = (size_t)rows * ldk;
   const double* Ki = K + (size_t)P.kblock * kstride + (size_t)ic * ldk;
   double kT[ROW_PF], k3[ROW_PF], k0[ROW_PF];
 #pragma unroll
@@ -582,7 +590,21 @@ __global__ void __launch_bounds__(256) k_sweep_row(
     k3[u] = Ki[mat + j];
     k0[u] = Ki[2 * mat + j];
   }
-  const double s = s_[ic], Ai = xi[ic], Bi = xi[n + ic];
+  double s, Ai, Bi;
+  if (QC && ic == n) {  // the renormalisation point
+    s = zp.s;
+    Ai = 0.0;
+    Bi = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      Ai = fma(zp.w[l], xi[zp.base + l], Ai);
+      Bi = fma(zp.w[l], xi[n + zp.base + l], Bi);
+    }
+  } else {
+    s = s_[ic];
+    Ai = xi[ic];
+    Bi = xi[n + ic];
+  }
   __builtin_amdgcn_sched_barrier(0);
   // Every node of the pass is computed and stored, the clamped ones into one
   // spare slot past the five columns, so that no read can be moved into a
@@ -608,7 +630,7 @@ __global__ void __launch_bounds__(256) k_sweep_row(
   const int status = state ? decide(state + inst, ctl, k, blockIdx.x == 0) : 0;
   __syncthreads();
   if (status != 0) {  // frozen (the same for every wavefront): carry along
-    if (lane == 0 && i < n) {
+    if (!QC && lane == 0 && i < n) {
       xo[i] = Ai;
       xo[n + i] = Bi;
     }
@@ -625,6 +647,14 @@ __global__ void __launch_bounds__(256) k_sweep_row(
   row_stream_f64(lane + ROW_PF * WAVE, nq, ldk, mat, Ki, nd, s, Ai, Bi, a0, a1, a2, a3);
   const double acc0 = wave_sum(a0), acc1 = wave_sum(a1), acc2 = wave_sum(a2),
                acc3 = wave_sum(a3);
+  if (QC) {
+    if (lane == 0 && i < rows) {
+      double* sg = sig + (size_t)inst * 2 * rows;
+      sg[i] = P.pref * (acc1 - acc0);
+      sg[rows + i] = P.pref * fma(2.0 * s, acc2, acc3);
+    }
+    return;
+  }
   __shared__ unsigned long long wmax[4];
   unsigned long long mine = 0ull;
   if (lane == 0 && i < n) {
@@ -650,55 +680,6 @@ __global__ void __launch_bounds__(256) k_sweep_row(
 }
 
 // ---------------------------------------------------------------- renormalised mode
-// Sums of one sweep with a renormalisation point: one wavefront per external
-// row i < n and one for row n, p^2 = zeta^2, whose A and B are interpolated
-// from the iterate with the stencil of zp (the kernel matrices carry that
-// row as their last one). sig[inst][r] = Sigma_A(row r) and
-// sig[inst][(n+1) + r] = Sigma_B(row r), the loop sums times pref without
-// the inhomogeneous terms. Instances frozen at the start of this sweep are
-// skipped. Same per-row arithmetic as k_sweep.
-__global__ void __launch_bounds__(256) k_qc_sums(int n_inst, int n, int nq, int ldk,
-                                                 const InstDev* __restrict__ inst_,
-                                                 const double* __restrict__ K, size_t kstride,
-                                                 const double* __restrict__ s_, QcPoint zp,
-                                                 const double* __restrict__ x,
-                                                 const double* __restrict__ nodes,
-                                                 double* __restrict__ sig,
-                                                 const SolveState* state) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int rows = n + 1;
-  const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-  if (row >= (long)n_inst * rows) return;
-  const int inst = (int)(row / rows), i = (int)(row % rows);
-  if (state && state[inst].status != 0) return;
-  const InstDev P = inst_[inst];
-  const double* xi = x + (size_t)inst * 2 * n;
-  double Ai, Bi, s;
-  if (i < n) {
-    Ai = xi[i];
-    Bi = xi[n + i];
-    s = s_[i];
-  } else {
-    Ai = 0.0;
-    Bi = 0.0;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      Ai = fma(zp.w[l], xi[zp.base + l], Ai);
-      Bi = fma(zp.w[l], xi[n + zp.base + l], Bi);
-    }
-    s = zp.s;
-  }
-  const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
-  const double* nd = nodes + (size_t)inst * 5 * ldk;
-  double acc[4];
-  row_accumulate_f64(nq, ldk, (size_t)rows * ldk, Ki, nd, s, Ai, Bi, lane, acc);
-  if (lane == 0) {
-    double* sg = sig + (size_t)inst * 2 * rows;
-    sg[i] = P.pref * (acc[1] - acc[0]);
-    sg[rows + i] = P.pref * fma(2.0 * s, acc[2], acc[3]);
-  }
-}
-
 // Update with the renormalisation constants of this sweep: Z_2 = 1/(1 +
 // Sigma_A(zeta^2)) makes A(zeta^2) = 1 and Z_4 m = m - Z_2 Sigma_B(zeta^2)
 // makes B(zeta^2) = m (no mass term at m = 0); then A = Z_2 (1 + Sigma_A),
@@ -1080,21 +1061,18 @@ hipError_t launch_precompute(hipStream_t st, int n, int nq, int na, int ldk, con
 hipError_t launch_qc_sweep(hipStream_t st, int n_inst, int n, int nq, int ldk,
                            const InstDev* inst, const double* K, size_t kstride, const int* lo,
                            const double* sw, const double* t, const double* s, const QcPoint& zp,
-                           const double* x_in, double* x_out, double* nodes, double* sig,
+                           const double* x_in, double* x_out, double* sig,
                            SolveState* state, const SolveCtl* ctl, int k, hipEvent_t ev0,
                            hipEvent_t ev1) {
-  hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
-                     sw, t, x_in, nodes, state, ctl, k);
-  const long rows = (long)n_inst * (n + 1);
-  const dim3 grid((unsigned)((rows + 3) / 4));
+  const size_t lds = ((size_t)5 * ldk + 1) * sizeof(double);
+  const dim3 grid((n + 1 + 3) / 4, n_inst);
   if (ev0)
-    hipExtLaunchKernelGGL(k_qc_sums, grid, dim3(256), 0, st, ev0, ev1, 0, n_inst, n, nq, ldk, inst,
-                          K, kstride, s, zp, (const double*)x_in, (const double*)nodes, sig,
-                          (const SolveState*)state);
+    hipExtLaunchKernelGGL(k_sweep_row<true>, grid, dim3(256), (uint32_t)lds, st, ev0, ev1, 0,
+                          n_inst, n, nq, ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out, state,
+                          ctl, k, 0, zp, sig);
   else
-    hipLaunchKernelGGL(k_qc_sums, grid, dim3(256), 0, st, n_inst, n, nq, ldk, inst, K, kstride, s,
-                       zp, (const double*)x_in, (const double*)nodes, sig,
-                       (const SolveState*)state);
+    hipLaunchKernelGGL(k_sweep_row<true>, grid, dim3(256), lds, st, n_inst, n, nq, ldk, inst, K,
+                       kstride, lo, sw, t, s, x_in, x_out, state, ctl, k, 0, zp, sig);
   hipLaunchKernelGGL(k_qc_update, dim3(n_inst), dim3(256), 0, st, n_inst, n, inst,
                      (const double*)sig, x_in, x_out, state, ctl, k);
   return hipGetLastError();
@@ -1132,8 +1110,20 @@ hipError_t launch_sweep_fused(hipStream_t st, int n_inst, int n, int nq, int ldk
   if (rows != 4 && rows != 8 && rows != 16) return hipErrorInvalidValue;
   // (one slot-templated variant that loads a whole row at once measured
   // slower here: more registers, lower occupancy)
-  auto kern = rows == 4 ? k_sweep_row : rows == 8 ? k_sweep_fused<8> : k_sweep_fused<16>;
   const dim3 grid((n + rows - 1) / rows, n_inst);
+  if (rows == 4) {
+    const QcPoint none{};
+    if (ev0)
+      hipExtLaunchKernelGGL(k_sweep_row<false>, grid, dim3(256), (uint32_t)lds, st, ev0, ev1, 0,
+                            n_inst, n, nq, ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out,
+                            state, ctl, k, add_f0, none, (double*)nullptr);
+    else
+      hipLaunchKernelGGL(k_sweep_row<false>, grid, dim3(256), lds, st, n_inst, n, nq, ldk, inst,
+                         K, kstride, lo, sw, t, s, x_in, x_out, state, ctl, k, add_f0, none,
+                         (double*)nullptr);
+    return hipGetLastError();
+  }
+  auto kern = rows == 8 ? k_sweep_fused<8> : k_sweep_fused<16>;
   if (ev0)
     hipExtLaunchKernelGGL(kern, grid, dim3(256), (uint32_t)lds, st, ev0, ev1, 0, n_inst, n, nq,
                           ldk, inst, K, kstride, lo, sw, t, s, x_in, x_out, state, ctl, k, add_f0);
