@@ -170,13 +170,14 @@ def mixed_batch(Q, np, torch, B):
     classes = sorted(set(zip(nr.tolist(), nan.tolist())))
     out = {"instances": B, "classes": len(classes),
            "class_sizes": {f"{n}x{na}": int(np.sum((nr == n) & (nan == na))) for n, na in classes}}
-    tot = {}
+    tot, shapes = {}, {}
     for prec in (Q.QDSE_FP32_REFINE, Q.QDSE_FP64_MATRIX):
         solvers, x0s = [], []
         for (n, na) in classes:  # one context and one stream per class
             sel = np.nonzero((nr == n) & (nan == na))[0]
             params = [(0.55, 0.678, float(m[k])) for k in sel]
             S = Q.Solver(n, na, params, interp_order=3, precision=prec, stream=torch.cuda.Stream())
+            shapes[(prec, n, na)] = S.autotune(reps=10)["mm_row_groups"]  # per class
             solvers.append(S)
             x0s.append(S.initial(1.0, 1.0))
         torch.cuda.synchronize()
@@ -196,9 +197,11 @@ def mixed_batch(Q, np, torch, B):
     out["fp64_mfma_solves_per_s"] = B / tot[Q.QDSE_FP64_MATRIX]
     out["fp32_refined_ms"] = 1e3 * tot[Q.QDSE_FP32_REFINE]
     out["fp64_mfma_ms"] = 1e3 * tot[Q.QDSE_FP64_MATRIX]
+    out["autotuned_row_groups"] = {("fp32" if p == Q.QDSE_FP32_REFINE else "fp64") + f"_{n}x{na}": v
+                                   for (p, n, na), v in shapes.items()}
     out["workload"] = ("vacuum, paper interaction, m~U[0,0.2], N_r in {128,256,384,512} x N_a in "
-                       "{64,128} (seed 4), tol 1e-8; one context and stream per class, "
-                       "qdse_solve_group")
+                       "{64,128} (seed 4), tol 1e-8; one context and stream per class (launch shape "
+                       "autotuned per class), qdse_solve_group")
     return out
 
 
@@ -470,6 +473,7 @@ def main():
         res["plain_fp64_2inst"] = {"solves_per_s": len(masses) * args.steps / dtp,
                                    "sweeps": [int(v) for v in itp]}
         S32 = Q.Solver(n, na, pb, interp_order=3, precision=Q.QDSE_FP32_REFINE)
+        tuned = {"fp32_mfma_row_groups": S32.autotune(reps=10)["mm_row_groups"]}
         xb0 = S32.initial(1.0, 1.0)
         dt32, x32, it32 = timed_solves(S32, xb0, tol_eq, args.batch_steps, 1)
         n32, n64 = S32.solve_stats()
@@ -479,11 +483,13 @@ def main():
             "fp32_sweeps_mean": float(n32.mean()), "fp64_sweeps_mean": float(n64.mean())}
         del S32
         S64 = Q.Solver(n, na, pb, interp_order=3)
+        tuned["fp64_direct_rows_per_workgroup"] = S64.autotune(reps=5)["fused_rows"]
         dt64, x64, it64 = timed_solves(S64, S64.initial(1.0, 1.0), tol_eq, args.batch_steps, 1)
         res["fp64_direct"] = {"solves_per_s": B * args.batch_steps / dt64,
                               "ms_per_batch": 1e3 * dt64 / args.batch_steps,
                               "sweeps_max": int(it64.max()), "sweeps_mean": float(it64.mean())}
         Smm = Q.Solver(n, na, pb, interp_order=3, precision=Q.QDSE_FP64_MATRIX)
+        tuned["fp64_mfma_row_groups"] = Smm.autotune(reps=10)["mm_row_groups"]
         dtm, xmm, itm = timed_solves(Smm, Smm.initial(1.0, 1.0), tol_eq, args.batch_steps, 1)
         res["fp64_mfma"] = {"solves_per_s": B * args.batch_steps / dtm,
                             "ms_per_batch": 1e3 * dtm / args.batch_steps,
@@ -494,16 +500,18 @@ def main():
         d = np.abs(a32 - a64) / np.maximum(np.abs(a64), 1e-8 * np.abs(a64).max(axis=1, keepdims=True))
         res["max_rel_diff_fp32_vs_fp64"] = float(d.max())
         res["instances"] = B
+        res["autotuned"] = tuned
         res["workload"] = ("512x128 paper interaction, m ~ U[0, 0.2] GeV (seed 4, m[0] = 5 MeV), "
-                           "tol 1e-8 (1e-7 accuracy target)")
+                           "tol 1e-8 (1e-7 accuracy target); launch shapes from qdse_autotune")
         line["batched"] = res
         # MFMA roofline of the FP32 contraction at this batch
         S32 = Q.Solver(n, na, pb, interp_order=3, precision=Q.QDSE_FP32_REFINE)
+        rh32 = S32.autotune(reps=10)["mm_row_groups"]
         ms32 = S32.time_contraction(x64, reps=50, which=1)
         flops = 16.0 * n * nq * B  # eight FP32 products per instance-row, 2 flop per MAC
         tf = flops / (ms32 * 1e-3) / 1e12
         line["roofline_fp32"] = {
-            "bound": "mfma", "kernel": "k_mm_sweep<float> (FP32 contraction, batch)",
+            "bound": "mfma", "kernel": f"k_mm_sweep<float, {rh32}> (FP32 contraction, batch)",
             "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tf / FP32_MFMA_PEAK_TFLOPS,
             "traffic": counter_traffic("k_mm_sweep_fp32_512x128_1024inst.md", "qdse_mfma.hip"),
@@ -514,7 +522,8 @@ def main():
         line["batched"]["fp32_mfma_contraction_kernel_us"] = ms32 * 1e3
         line["batched"]["fp64_mfma_contraction_kernel_us"] = ms_mm64 * 1e3
         line["roofline_fp64_mfma"] = {
-            "bound": "mfma", "kernel": "k_mm_sweep<double> (FP64 contraction, batch)",
+            "bound": "mfma",
+            "kernel": f"k_mm_sweep<double, {tuned['fp64_mfma_row_groups']}> (FP64 contraction, batch)",
             "achieved": flops / (ms_mm64 * 1e-3) / 1e12, "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": flops / (ms_mm64 * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
             "traffic": counter_traffic("k_mm_sweep_fp64_512x128_1024inst.md", "qdse_mfma.hip"),

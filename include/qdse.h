@@ -93,6 +93,23 @@ enum {
 int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst,
                int precision, void* hip_stream, qdse_ctx** out);
 
+/* Picks the launch shape of the context's sweep by timing the candidates on
+ * its own batch (reps timed launches each, the kernels as a solve runs them):
+ * rows per workgroup of the FP64 sweep (4: one row per wavefront, 8 or 16)
+ * for QDSE_FP64 contexts, row groups of 16 rows per workgroup of the
+ * matrix-core contraction (1 or 2; timed on the FP32 kernel for
+ * QDSE_FP32_REFINE, which uses it for its FP64 refinement too) otherwise.
+ * cache_path (may be NULL): a JSON object of earlier winners keyed by device,
+ * path, grid and batch size; a hit sets the shape without timing, a miss
+ * times and adds the winner (the file is rewritten). Outputs (each may be
+ * NULL): the chosen fused_rows and mm_row_groups, from_cache = 1 on a hit.
+ * Renormalised contexts have one shape (nothing is timed). Overwrites the
+ * context's work buffers; synchronises the stream.
+ * Errors: QDSE_EINVAL (ctx NULL, reps < 1, cache file not writable),
+ * QDSE_EDEVICE. */
+int qdse_autotune(qdse_ctx* ctx, int reps, const char* cache_path, int* fused_rows,
+                  int* mm_row_groups, int* from_cache);
+
 /* Renormalised setting with the full Qin-Chang interaction, beyond the
  * paper: Sec. II (after eq. IRGsQC) keeps only the infrared Gaussian of the
  * Qin-Chang interaction and sets the renormalisation constants to 1. Here

@@ -104,6 +104,7 @@ def load():
     L.qdse_mu_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]
     L.qdse_mu_solve_anderson.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                          _ip, _dp]
+    L.qdse_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip]
     L.qdse_fred_nodes.argtypes = [ctypes.POINTER(FredGrid), _dp, _dp, _dp]
     L.qdse_fred_setup.argtypes = [ctypes.POINTER(FredGrid), ctypes.POINTER(FredPoly), _vp, _vp,
                                   _vp, _vp, ctypes.POINTER(_vp)]
@@ -275,6 +276,15 @@ class Solver:
                               float(tol), int(max_iter), tb.ctypes.data_as(_dp))
         _check(rc, "qdse_grad", allow=(QDSE_OK, QDSE_NOT_CONVERGED))
         return tb, rc
+
+    def autotune(self, reps=20, cache=None):
+        """qdse_autotune: times the launch shapes on this batch and keeps the
+        fastest (cache: path of a JSON file of winners). Returns a dict."""
+        fr, rh, hit = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(load().qdse_autotune(self._h, int(reps), None if cache is None else str(cache).encode(),
+                                    ctypes.byref(fr), ctypes.byref(rh), ctypes.byref(hit)),
+               "qdse_autotune")
+        return {"fused_rows": fr.value, "mm_row_groups": rh.value, "from_cache": bool(hit.value)}
 
     def time_contraction(self, x, reps=50, which=0):
         """Average device milliseconds of one sweep-kernel launch (HIP events):

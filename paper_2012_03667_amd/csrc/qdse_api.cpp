@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -299,6 +301,10 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
       return QDSE_ENOTSUP;
     }
     c->mm = mm_layout(g.n, g.nq, n_inst);
+    if (const char* e = std::getenv("QDSE_MM_RH")) {
+      const int r = std::atoi(e);
+      if (r == 1 || r == 2) c->mm.rh = r;
+    }
     const MmLayout& L = c->mm;
     // FP64 matrix-core sweeps serve both precisions (the refinement of FP32)
     TRY(dalloc(&c->d_M64, 5 * L.mstride));
@@ -1244,5 +1250,127 @@ const char* qdse_strerror(int code) {
 }
 
 const char* qdse_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+namespace {
+
+// Flat JSON object {"key": integer, ...} of earlier tuning winners.
+std::vector<std::pair<std::string, long>> read_tune_cache(const char* path) {
+  std::vector<std::pair<std::string, long>> out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  size_t p = 0;
+  for (;;) {
+    const size_t a = text.find('"', p);
+    if (a == std::string::npos) break;
+    const size_t b = text.find('"', a + 1);
+    if (b == std::string::npos) break;
+    const size_t colon = text.find(':', b);
+    if (colon == std::string::npos) break;
+    char* end = nullptr;
+    const long v = std::strtol(text.c_str() + colon + 1, &end, 10);
+    if (end == text.c_str() + colon + 1) break;
+    out.push_back({text.substr(a + 1, b - a - 1), v});
+    p = (size_t)(end - text.c_str());
+  }
+  return out;
+}
+
+int write_tune_cache(const char* path, const std::vector<std::pair<std::string, long>>& kv) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) return QDSE_EINVAL;
+    f << "{\n";
+    for (size_t q = 0; q < kv.size(); ++q)
+      f << "  \"" << kv[q].first << "\": " << kv[q].second << (q + 1 < kv.size() ? ",\n" : "\n");
+    f << "}\n";
+    if (!f) return QDSE_EINVAL;
+  }
+  return std::rename(tmp.c_str(), path) == 0 ? QDSE_OK : QDSE_EINVAL;
+}
+
+void drop_graphs(qdse_ctx* c, int kind) {
+  for (auto& e : c->graphs[kind]) (void)hipGraphExecDestroy(e.second);
+  c->graphs[kind].clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int qdse_autotune(qdse_ctx* c, int reps, const char* cache_path, int* fused_rows,
+                  int* mm_row_groups, int* from_cache) {
+  if (!c || reps < 1) return QDSE_EINVAL;
+  if (from_cache) *from_cache = 0;
+  const HostGrid& g = c->hg;
+  const bool mm = c->d_M64 != nullptr;
+  char dev[64] = "gfx";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+    std::snprintf(dev, sizeof dev, "%s", prop.gcnArchName);
+  for (char* q = dev; *q; ++q)
+    if (*q == '"' || *q == ':') *q = '_';
+  char key[192];
+  std::snprintf(key, sizeof key, "%s|%s|n=%d|na=%d|inst=%d", dev,
+                c->qc ? "qc" : mm ? (c->d_M32 ? "mm32" : "mm64") : "fp64", g.n, g.na, c->n_inst);
+  int best = -1;
+  std::vector<std::pair<std::string, long>> cache;
+  if (cache_path) {
+    cache = read_tune_cache(cache_path);
+    for (auto& e : cache)
+      if (e.first == key) best = (int)e.second;
+  }
+  const bool hit = best > 0;
+  if (!hit && !c->qc) {
+    // time every candidate on the context's own batch (A = B = 1 start, the
+    // kernels as a solve runs them, nothing frozen)
+    std::vector<double> ones(xlen(c), 1.0);
+    HIPCHK(hipMemcpyAsync(c->d_xbuf[0], ones.data(), ones.size() * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const std::vector<int> cand = mm ? std::vector<int>{1, 2} : std::vector<int>{4, 8, 16};
+    double best_ms = 0.0;
+    for (int v : cand) {
+      if (mm)
+        c->mm.rh = v;
+      else
+        c->fused_rows = v;
+      double ms = 0.0;
+      // one untimed round, then the timed one
+      int rc = qdse_time_contraction(c, mm ? (c->d_M32 ? 1 : 2) : 0, c->d_xbuf[0], c->d_xbuf[1],
+                                     2, &ms);
+      if (!rc) rc = qdse_time_contraction(c, mm ? (c->d_M32 ? 1 : 2) : 0, c->d_xbuf[0],
+                                          c->d_xbuf[1], reps, &ms);
+      if (rc) return rc;
+      if (best < 0 || ms < best_ms) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+  }
+  if (c->qc) best = 4;  // the renormalised sweep has one launch shape
+  if (mm) {
+    c->mm.rh = best == 1 ? 1 : 2;
+    drop_graphs(c, SWEEP_MM32);
+    drop_graphs(c, SWEEP_MM64);
+  } else if (!c->qc) {
+    c->fused_rows = (best == 8 || best == 16) ? best : 4;
+    drop_graphs(c, SWEEP_DIRECT);
+  }
+  if (cache_path && !hit && !c->qc) {
+    cache.push_back({key, (long)best});
+    int rc = write_tune_cache(cache_path, cache);
+    if (rc) return rc;
+  }
+  if (fused_rows) *fused_rows = c->fused_rows;
+  if (mm_row_groups) *mm_row_groups = c->mm.rh;
+  if (from_cache) *from_cache = hit ? 1 : 0;
+  return QDSE_OK;
+}
 
 }  // extern "C"

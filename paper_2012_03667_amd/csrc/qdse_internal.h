@@ -162,6 +162,7 @@ hipError_t launch_axpby(hipStream_t st, int n_inst, int len, double alpha, const
 struct MmLayout {
   int nq_pad = 0, ldi = 0, ldb = 0;
   size_t mstride = 0, cstride = 0;
+  int rh = 2;  // row groups of 16 rows per workgroup of the contraction (1 or 2)
 };
 MmLayout mm_layout(int n, int nq, int n_inst);
 template <class T>

@@ -47,7 +47,6 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr double kMassFloorM = 1e-8;  // GeV, as in the FP64 sweep
 constexpr int TM_MAX = 32, TN = 32, KSPLIT = 2, KSTEP = 4;
-constexpr int RH = 2;  // row groups per workgroup (they share the node-column panel)
 
 template <class T> struct Mfma;
 // Output layout of one 16x16 block: register e of lane l holds row
@@ -184,7 +183,9 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
   }
 }
 
-template <class T>
+// RH: row groups of 16 rows per workgroup (they share the node-column panel);
+// 1 or 2, chosen per context (MmLayout::rh, qdse_autotune).
+template <class T, int RH>
 __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
     int n_inst, int n, int nq_pad, int ldi, int ldb, const T* __restrict__ MT, size_t mstride,
     const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
@@ -397,14 +398,21 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
   if (nodes)
     hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
                        n, nq, L.ldb, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
-  const dim3 grid((L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN));
-  if (ev0)
-    hipExtLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT * RH), 0, st, ev0, ev1, 0, n_inst, n,
-                          L.nq_pad, L.ldi, L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s,
-                          x_in, x_out, state, ctl, k);
+  auto launch = [&](auto kern, int RH) {
+    const dim3 grid((L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN));
+    if (ev0)
+      hipExtLaunchKernelGGL(kern, grid, dim3(64 * KSPLIT * RH), 0, st, ev0, ev1, 0, n_inst, n,
+                            L.nq_pad, L.ldi, L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s,
+                            x_in, x_out, state, ctl, k);
+    else
+      hipLaunchKernelGGL(kern, grid, dim3(64 * KSPLIT * RH), 0, st, n_inst, n, L.nq_pad, L.ldi,
+                         L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s, x_in, x_out, state,
+                         ctl, k);
+  };
+  if (L.rh == 1)
+    launch(k_mm_sweep<T, 1>, 1);
   else
-    hipLaunchKernelGGL(k_mm_sweep<T>, grid, dim3(64 * KSPLIT * RH), 0, st, n_inst, n, L.nq_pad, L.ldi,
-                       L.ldb, MT, L.mstride, C, L.cstride, inst, s, x_in, x_out, state, ctl, k);
+    launch(k_mm_sweep<T, 2>, 2);
   return hipGetLastError();
 }
 
