@@ -13,6 +13,13 @@
  * bracket known in advance (Sec. III A, eq. chazhiresult; 2-point as in the
  * paper or 4-point).
  *
+ * Besides the paper's vacuum setting: batched matrix-core sweeps
+ * (precision), Newton-Krylov solves, tangent/adjoint sweeps and implicit
+ * gradients (qdse_jvp, qdse_vjp, qdse_grad), a launch-shape autotuner
+ * (qdse_autotune), the renormalised setting with the full Qin-Chang
+ * interaction (qdse_setup_qc), finite chemical potential and temperature
+ * (qdse_mu_*), and the general two-equation system of Sec. I (qdse_fred_*).
+ *
  * Conventions for every entry point:
  *  - Pointers named d_* are DEVICE pointers (HIP device memory of the GPU that
  *    was current at qdse_setup); all others are host pointers. The caller owns
