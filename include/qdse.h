@@ -397,6 +397,16 @@ int qdse_fred_solve(qdse_fred_ctx* ctx, double* d_uv, double tol, int max_iter, 
 int qdse_fred_time_sweep(qdse_fred_ctx* ctx, const double* d_in, double* d_out, int reps,
                          double* avg_ms);
 
+/* The ceilings quoted by the rooflines, measured on the current device:
+ * copy_gbs: read + write bandwidth of a 1 GiB streaming copy (larger than
+ * the Infinity Cache); mfma32_tflops / mfma64_tflops: dense rate of
+ * back-to-back v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 with
+ * independent accumulators on every compute unit. Each output may be NULL
+ * (skipped). Allocates and frees its own buffers; synchronises hip_stream.
+ * Errors: QDSE_ENOMEM, QDSE_EDEVICE. */
+int qdse_measure_peaks(void* hip_stream, double* copy_gbs, double* mfma32_tflops,
+                       double* mfma64_tflops);
+
 /* Human-readable name of a status code. */
 const char* qdse_strerror(int code);
 

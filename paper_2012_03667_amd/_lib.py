@@ -104,6 +104,7 @@ def load():
     L.qdse_mu_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]
     L.qdse_mu_solve_anderson.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                          _ip, _dp]
+    L.qdse_measure_peaks.argtypes = [_vp, _dp, _dp, _dp]
     L.qdse_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip]
     L.qdse_fred_nodes.argtypes = [ctypes.POINTER(FredGrid), _dp, _dp, _dp]
     L.qdse_fred_setup.argtypes = [ctypes.POINTER(FredGrid), ctypes.POINTER(FredPoly), _vp, _vp,
@@ -471,4 +472,15 @@ class FredSolver:
                                            _dev(out, (2 * self.n,), "out"), int(reps),
                                            ctypes.byref(ms)), "qdse_fred_time_sweep")
         return ms.value
+
+
+def measure_peaks(stream=None):
+    """qdse_measure_peaks on the current device: dict of copy GB/s and the
+    FP32 / FP64 matrix-core TFLOP/s."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    c, m32, m64 = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(load().qdse_measure_peaks(_vp(st.cuda_stream), ctypes.byref(c), ctypes.byref(m32),
+                                     ctypes.byref(m64)), "qdse_measure_peaks")
+    return {"copy_GBs": c.value, "mfma_fp32_TFLOPs": m32.value, "mfma_fp64_TFLOPs": m64.value}
 

@@ -1,0 +1,118 @@
+// qdse_peaks.hip -- the ceilings the rooflines are quoted against, measured
+// on the device at hand: a streaming copy (HBM read + write bandwidth) and
+// back-to-back matrix-core instructions of the two types the contraction uses
+// (v_mfma_f32_16x16x4f32, v_mfma_f64_16x16x4f64), each with independent
+// accumulators so that the issue rate, not a dependency, bounds the loop.
+#include "qdse_internal.h"
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_copy(const double4* __restrict__ a,
+                                              double4* __restrict__ b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+constexpr int kChains = 8;  // independent accumulators per wavefront
+
+__global__ void __launch_bounds__(256) k_mfma32(int iters, float seed, float* out) {
+  floatx4 acc[kChains];
+  for (int c = 0; c < kChains; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const float a = seed + threadIdx.x * 1e-7f, b = seed - threadIdx.x * 1e-7f;
+  for (int it = 0; it < iters; ++it)
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+  float s = 0.f;
+  for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  if (s == 1234.5f) out[blockIdx.x] = s;  // keeps the loop; never true for the seeds used
+}
+
+__global__ void __launch_bounds__(256) k_mfma64(int iters, double seed, double* out) {
+  doublex4 acc[kChains];
+  for (int c = 0; c < kChains; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+  const double a = seed + threadIdx.x * 1e-9, b = seed - threadIdx.x * 1e-9;
+  for (int it = 0; it < iters; ++it)
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+  double s = 0.0;
+  for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  if (s == 1234.5) out[blockIdx.x] = s;
+}
+
+template <class F>
+int time_ms(hipStream_t st, int reps, F&& launch, double* ms_out) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return QDSE_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return QDSE_EDEVICE;
+  }
+  launch();  // warm-up
+  (void)hipEventRecord(e0, st);
+  for (int r = 0; r < reps; ++r) launch();
+  (void)hipEventRecord(e1, st);
+  int rc = QDSE_OK;
+  float ms = 0.f;
+  if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+    rc = QDSE_EDEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = ms / reps;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int qdse_measure_peaks(void* hip_stream, double* copy_gbs, double* mfma32_tflops,
+                                  double* mfma64_tflops) {
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) != hipSuccess) return QDSE_EDEVICE;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  int rc = QDSE_OK;
+  if (copy_gbs) {
+    // 1 GiB each way, larger than the 256 MB Infinity Cache
+    const long n4 = (1l << 30) / (long)sizeof(double4);
+    double4 *a = nullptr, *b = nullptr;
+    if (hipMalloc((void**)&a, n4 * sizeof(double4)) != hipSuccess ||
+        hipMalloc((void**)&b, n4 * sizeof(double4)) != hipSuccess) {
+      rc = QDSE_ENOMEM;
+    } else if (hipMemsetAsync(a, 0, n4 * sizeof(double4), st) != hipSuccess) {
+      rc = QDSE_EDEVICE;
+    } else {
+      double ms = 0.0;
+      rc = time_ms(st, 5, [&] {
+        hipLaunchKernelGGL(k_copy, dim3(ncu * 16), dim3(256), 0, st, (const double4*)a, b, n4);
+      }, &ms);
+      if (!rc) *copy_gbs = 2.0 * n4 * sizeof(double4) / (ms * 1e-3) / 1e9;
+    }
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (rc) return rc;
+  }
+  float* o32 = nullptr;
+  if (hipMalloc((void**)&o32, 64 * 1024 * sizeof(double)) != hipSuccess) return QDSE_ENOMEM;
+  const int iters = 2000, blocks = ncu * 8;  // eight wavefront-groups of four per compute unit
+  const double inst = (double)blocks * 4 * iters * kChains;  // wavefront instructions
+  if (mfma32_tflops) {
+    double ms = 0.0;
+    rc = time_ms(st, 3, [&] {
+      hipLaunchKernelGGL(k_mfma32, dim3(blocks), dim3(256), 0, st, iters, 0.5f, o32);
+    }, &ms);
+    if (!rc) *mfma32_tflops = inst * 2.0 * 16 * 16 * 4 / (ms * 1e-3) / 1e12;
+  }
+  if (!rc && mfma64_tflops) {
+    double ms = 0.0;
+    rc = time_ms(st, 3, [&] {
+      hipLaunchKernelGGL(k_mfma64, dim3(blocks), dim3(256), 0, st, iters, 0.5, (double*)o32);
+    }, &ms);
+    if (!rc) *mfma64_tflops = inst * 2.0 * 16 * 16 * 4 / (ms * 1e-3) / 1e12;
+  }
+  (void)hipFree(o32);
+  return rc;
+}
