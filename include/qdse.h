@@ -141,8 +141,9 @@ typedef struct {
  * context supports qdse_iterate, qdse_solve, qdse_solve_group,
  * qdse_solve_stats, qdse_dims, qdse_nodes and qdse_time_contraction (which =
  * 0 times the sums kernel); the other entry points return QDSE_ENOTSUP.
- * Errors: as qdse_setup, and QDSE_EINVAL for qc == NULL, uv not 0 or 1, or
- * zeta^2 outside (s_min, s_max) or equal to a loop node. */
+ * Errors: as qdse_setup, and QDSE_EINVAL for qc == NULL, uv not 0 or 1,
+ * zeta^2 outside (s_min, s_max) or equal to a loop node, or a grid whose node
+ * functions do not fit one workgroup's LDS (about N > 4080 on gfx950). */
 int qdse_setup_qc(const qdse_grid* grid, const qdse_params* params, int n_inst,
                   const qdse_qc* qc, void* hip_stream, qdse_ctx** out);
 
@@ -255,7 +256,10 @@ int qdse_kernel_matrices(qdse_ctx* ctx, int inst, double* d_K);
  * kernel's execution time without launch gaps. The kernels run exactly as in
  * a solve (masked-run decision, per-instance test statistics) against a
  * private solve state whose tolerance is never met. which = 0: the fused FP64
- * sweep kernel (node functions and the O(N^2) contraction in one launch);
+ * sweep kernel (node functions and the O(N^2) contraction in one launch;
+ * QDSE_ENOTSUP on grids whose node functions do not fit one workgroup's LDS,
+ * about N > 4080 on gfx950, where sweeps use a node kernel plus a contraction
+ * kernel with the same arithmetic);
  * 1: the FP32 matrix-core contraction kernel alone; 2: the FP64 matrix-core
  * contraction kernel alone (node columns are built once before; 1 and 2 need
  * a context with the matrix-core data, else QDSE_ENOTSUP). d_out [n_inst][2N]

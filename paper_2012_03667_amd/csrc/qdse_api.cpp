@@ -93,6 +93,7 @@ struct qdse_ctx {
   int chunk = 24;       // sweeps per graph launch, FP64 direct sweeps (multiple of 6)
   int chunk_mm = 12;    // the same for matrix-core sweeps (masked sweeps cost more)
   int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
+  int fused_fits = 1;   // its node functions fit the LDS of one workgroup
   SolveState* h_state = nullptr;  // [2][n_inst], hipHostMalloc; [0] is the sweeps' mirror
   SolveState* d_mirror = nullptr;  // device address of h_state
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -181,6 +182,17 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
     delete c;
     g_last_error = "hipGetDevice failed";
     return QDSE_EDEVICE;
+  }
+  {
+    // the one-kernel FP64 sweep keeps five node functions per loop node in LDS
+    int lds_max = 65536;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    c->fused_fits = ((size_t)5 * c->hg.ldk + 1) * sizeof(double) <= (size_t)lds_max;
+    if (qc && !c->fused_fits) {  // the renormalised sweep has only the one-kernel form
+      delete c;
+      g_last_error = "renormalised setting: grid too large for the node functions in LDS";
+      return QDSE_EINVAL;
+    }
   }
   // interaction classes: instances with equal omega share kernel matrices
   // (equal omega and D when the ultraviolet term is on: D no longer factors
@@ -436,6 +448,21 @@ int qdse_nodes(const qdse_ctx* c, double* s, double* t) {
   return QDSE_OK;
 }
 
+// One FP64 sweep: the one-kernel form (node functions in LDS) when they fit
+// one workgroup's LDS, else node functions in global memory and the two-kernel
+// form; both compute every row with the same arithmetic in the same order.
+static hipError_t sweep_fp64(qdse_ctx* c, hipStream_t st, const double* xi, double* xo,
+                             SolveState* state, const SolveCtl* ctl, int k) {
+  const HostGrid& g = c->hg;
+  if (c->fused_fits)
+    return launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                              c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, state, ctl, k, 1,
+                              c->fused_rows);
+  return launch_sweep_fp64(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                           c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_nodes, state, ctl, k,
+                           1);
+}
+
 int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
   if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
   const HostGrid& g = c->hg;
@@ -445,9 +472,7 @@ int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
                            nullptr, nullptr, 1));
     return QDSE_OK;
   }
-  HIPCHK(launch_sweep_fused(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                            c->d_lo, c->d_sw, c->d_t, c->d_s, d_x_in, d_x_out, nullptr, nullptr, 1,
-                            1, c->fused_rows));
+  HIPCHK(sweep_fp64(c, c->stream, d_x_in, d_x_out, nullptr, nullptr, 1));
   return QDSE_OK;
 }
 
@@ -493,9 +518,7 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
                              c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, xi, xo, c->d_sig, c->d_state,
                              c->d_ctl, k));
     } else {
-      HIPCHK(launch_sweep_fused(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
-                                c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_state, c->d_ctl,
-                                k, 1, c->fused_rows));
+      HIPCHK(sweep_fp64(c, st, xi, xo, c->d_state, c->d_ctl, k));
     }
   }
   return QDSE_OK;
@@ -1128,9 +1151,7 @@ int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin
   bool done = false, bad = false;
   for (;; ++it) {
     // residual R = F(x) - x, max-norm per instance
-    HIPCHK(launch_sweep_fused(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
-                              c->d_sw, c->d_t, c->d_s, d_x, d_F, nullptr, nullptr, 1, 1,
-                              c->fused_rows));
+    HIPCHK(sweep_fp64(c, st, d_x, d_F, nullptr, nullptr, 1));
     HIPCHK(launch_axpby(st, nI, len, -1.0, d_x, nullptr, d_F, d_F));
     HIPCHK(hipMemcpyAsync(h.data(), d_F, L * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1175,6 +1196,7 @@ int qdse_time_contraction(qdse_ctx* c, int which, const double* d_x, double* d_o
   if (!c || !d_x || !d_out || d_x == d_out || reps < 1 || !avg_ms) return QDSE_EINVAL;
   if (which < 0 || which > 2) return QDSE_EINVAL;
   if ((which == 1 && !c->d_M32) || (which == 2 && !c->d_M64)) return QDSE_ENOTSUP;
+  if (which == 0 && !c->qc && !c->fused_fits) return QDSE_ENOTSUP;
   const HostGrid& g = c->hg;
   hipStream_t st = c->stream;
   // The kernels run as in a solve (masked-run decision, test statistics) on a
@@ -1326,7 +1348,8 @@ int qdse_autotune(qdse_ctx* c, int reps, const char* cache_path, int* fused_rows
       if (e.first == key) best = (int)e.second;
   }
   const bool hit = best > 0;
-  if (!hit && !c->qc) {
+  if (!hit && !mm && !c->qc && !c->fused_fits) best = c->fused_rows;  // only the two-kernel form
+  if (best < 0 && !c->qc) {
     // time every candidate on the context's own batch (A = B = 1 start, the
     // kernels as a solve runs them, nothing frozen)
     std::vector<double> ones(xlen(c), 1.0);

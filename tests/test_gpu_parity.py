@@ -304,14 +304,16 @@ def test_full_size_sampled_rows(Q):
 
 
 # ---------------------------------------------------------------- FP32 matrix-core path
-def test_large_grid_sampled_rows(Q):
-    """A grid four times the benchmark's (2048 radial nodes, 2049 loop nodes):
-    long matrix rows, many row blocks and a batch of three instances; sampled
-    rows against the oracle, plus a sweep of the FP64 matrix-core path on the
-    same rows."""
-    n, na = 2048, 8
-    rng = np.random.default_rng(2048)
-    rows = np.sort(np.concatenate([[0, 1, 1023, 2046, 2047], rng.choice(n, 7, replace=False)]))
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_large_grid_sampled_rows(Q, n):
+    """Grids four and eight times the benchmark's (2048 / 4096 radial nodes):
+    long matrix rows (the row kernel streams past its register-held strides),
+    many row blocks and a batch of three instances; sampled rows against the
+    oracle, plus a sweep of the FP64 matrix-core path on the same rows."""
+    na = 8
+    print(f"case large grid n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    rows = np.sort(np.concatenate([[0, 1, n // 2 - 1, n - 2, n - 1], rng.choice(n, 7, replace=False)]))
     g = oracle_grid(n, na, 3)
     params = [(0.55, 0.678, 0.005), (0.55, 0.678, 0.0), (0.55, 0.678, 0.05)]
     xs = np.stack([smooth_x(g.s, rng) for _ in params])
