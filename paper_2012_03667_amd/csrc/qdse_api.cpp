@@ -1364,7 +1364,7 @@ int qdse_autotune(qdse_ctx* c, int reps, const char* cache_path, int* fused_rows
       else
         c->fused_rows = v;
       double ms = 0.0;
-      // one untimed round, then the timed one
+      // one untimed pass, then the timed one
       int rc = qdse_time_contraction(c, mm ? (c->d_M32 ? 1 : 2) : 0, c->d_xbuf[0], c->d_xbuf[1],
                                      2, &ms);
       if (!rc) rc = qdse_time_contraction(c, mm ? (c->d_M32 ? 1 : 2) : 0, c->d_xbuf[0],

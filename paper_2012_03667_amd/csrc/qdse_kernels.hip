@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
 // After the barrier the contraction consumes the registers (nodes
 // beyond ROW_PF lane strides are streamed as in k_sweep). Same per-row
 // arithmetic and order as k_sweep.
-constexpr int ROW_PF = 9;   // lane strides held in registers: nq <= 576 in one round
+constexpr int ROW_PF = 9;   // lane strides held in registers: nq <= 576 in one pass
 constexpr int NODE_PT = 3;  // nodes per thread per pass of the node build
 //
 // QC = true is the renormalised mode's sums kernel: the matrices have n + 1
