@@ -891,21 +891,29 @@ int qdse_jvp(qdse_ctx* c, const double* d_x, const double* d_v, double* d_jv) {
   return QDSE_OK;
 }
 
+// Row chunks of the reverse sweep: 16 per instance by default; the adjoint
+// solve uses up to kVjpChunksMax when few instances are still iterating, so
+// that they are spread over more wavefronts.
+constexpr int kVjpChunksMax = 64;
+
 static int ensure_vjp_work(qdse_ctx* c) {
   if (c->d_part) return QDSE_OK;
   const HostGrid& g = c->hg;
-  int rc = dalloc(&c->d_part, (size_t)c->n_inst * c->nchunk * 4 * g.ldk);
+  int rc = dalloc(&c->d_part, (size_t)c->n_inst * kVjpChunksMax * 4 * g.ldk);
   if (rc) return rc;
   return dalloc(&c->d_gq, (size_t)c->n_inst * 2 * g.ldk);
 }
 
-static int vjp_on(qdse_ctx* c, const double* K, const double* d_x, const double* d_w, double* d_out) {
+static int vjp_on(qdse_ctx* c, const double* K, const double* d_x, const double* d_w, double* d_out,
+                  const int* d_act = nullptr, bool nodes_ready = false, int nchunk = 0) {
   int rc = ensure_vjp_work(c);
   if (rc) return rc;
   const HostGrid& g = c->hg;
+  if (nchunk <= 0) nchunk = c->nchunk;
+  nchunk = std::min(nchunk, kVjpChunksMax);
   HIPCHK(launch_vjp(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, K, c->kstride, c->d_lo,
                     c->d_sw, c->d_t, c->d_s, d_x, d_w, d_out, c->d_nodes, c->d_part, c->d_gq,
-                    c->nchunk));
+                    nchunk, d_act, nodes_ready));
   return QDSE_OK;
 }
 
@@ -921,11 +929,12 @@ namespace {
 
 // Device buffers freed on scope exit.
 struct DevBufs {
-  std::vector<double*> ps;
+  std::vector<void*> ps;
   ~DevBufs() {
-    for (double* p : ps) dfree(p);
+    for (void* p : ps) dfree(p);
   }
-  int alloc(double** p, size_t n) {
+  template <class T>
+  int alloc(T** p, size_t n) {
     int r = dalloc(p, n);
     if (r == QDSE_OK) ps.push_back(*p);
     return r;
@@ -936,7 +945,11 @@ struct DevBufs {
 // solves op(sol) = b to ||r||_2 <= tol ||b||_2 per instance, starting from
 // sol = 0. Arnoldi vectors, Gram-Schmidt (two classical passes) and the basis
 // combinations run on the device; the small Hessenberg least-squares problems
-// (Givens rotations) run on the host. Returns QDSE_OK or QDSE_NOT_CONVERGED.
+// (Givens rotations) run on the host. An instance whose residual estimate
+// meets the target leaves the operator applications for the rest of the cycle
+// (its flag in the device activity mask drops to 0, its later basis vectors
+// are zero and their coefficients too); every restart recomputes the true
+// residual of every instance. Returns QDSE_OK or QDSE_NOT_CONVERGED.
 template <class Op>
 int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, double tol,
                   int max_iter, int* steps_out) {
@@ -949,16 +962,21 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
   hipStream_t st = c->stream;
   DevBufs buf;
   double *d_V, *d_w, *d_r, *d_h, *d_y, *d_sc;
+  int* d_act;
   int rc;
   // d_h: two Gram-Schmidt passes [2][nI][mres + 1] followed by the norms [nI]
   const size_t hstride = (size_t)nI * (mres + 1);
   if ((rc = buf.alloc(&d_V, (size_t)(mres + 1) * L)) || (rc = buf.alloc(&d_w, L)) ||
       (rc = buf.alloc(&d_r, L)) || (rc = buf.alloc(&d_h, 2 * hstride + nI)) ||
-      (rc = buf.alloc(&d_y, (size_t)nI * (mres + 1))) || (rc = buf.alloc(&d_sc, (size_t)nI)))
+      (rc = buf.alloc(&d_y, (size_t)nI * (mres + 1))) || (rc = buf.alloc(&d_sc, (size_t)nI)) ||
+      (rc = buf.alloc(&d_act, (size_t)nI)))
     return rc;
   std::vector<double> tmp(nI), bnorm(nI), hh(2 * hstride + nI);
   std::vector<double> zero(L, 0.0);
+  std::vector<int> act(nI, 1), ones(nI, 1), kd(nI, 0);
+  int n_act = nI;
   HIPCHK(hipMemcpyAsync(d_sol, zero.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_act, ones.data(), nI * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(launch_batched_dot(st, nI, len, d_b, 0, d_b, len, 1, d_sc));
   HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -969,9 +987,11 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
   std::vector<double> beta(nI), cs((size_t)nI * mres), sn((size_t)nI * mres),
       Hm((size_t)nI * (mres + 1) * mres), gvec((size_t)nI * (mres + 1)),
       ysol((size_t)nI * (mres + 1));
-  while (total < max_iter) {
-    // r = b - op(sol)
-    if ((rc = apply(d_sol, d_r))) return rc;
+  // r = b - op(sol) for every instance; converged when all meet the target
+  auto true_residual = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(d_act, ones.data(), nI * sizeof(int), hipMemcpyHostToDevice, st));
+    int r = apply(d_sol, d_r, d_act, nI);
+    if (r) return r;
     HIPCHK(launch_axpby(st, nI, len, -1.0, d_r, nullptr, d_b, d_r));
     HIPCHK(launch_batched_dot(st, nI, len, d_r, 0, d_r, len, 1, d_sc));
     HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -979,38 +999,53 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
     converged = true;
     for (int k = 0; k < nI; ++k) {
       beta[k] = std::sqrt(tmp[k]);
-      if (!(beta[k] <= tol * bnorm[k])) converged = false;
-      tmp[k] = beta[k] > 0.0 ? 1.0 / beta[k] : 0.0;
+      act[k] = !(beta[k] <= tol * bnorm[k]);
+      if (act[k]) converged = false;
     }
+    return QDSE_OK;
+  };
+  while (total < max_iter) {
+    if ((rc = true_residual())) return rc;
     if (converged) break;
+    n_act = 0;
+    for (int k = 0; k < nI; ++k) {
+      tmp[k] = act[k] && beta[k] > 0.0 ? 1.0 / beta[k] : 0.0;
+      n_act += act[k];
+    }
     HIPCHK(hipMemcpyAsync(d_sc, tmp.data(), nI * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_axpby(st, nI, len, 0.0, d_r, d_sc, d_r, d_V));  // v0 = r / beta
+    HIPCHK(hipMemcpyAsync(d_act, act.data(), nI * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_axpby(st, nI, len, 0.0, d_r, d_sc, d_r, d_V));  // v0 = r / beta (0 if done)
     std::fill(Hm.begin(), Hm.end(), 0.0);
     std::fill(gvec.begin(), gvec.end(), 0.0);
+    std::fill(kd.begin(), kd.end(), 0);
     for (int k = 0; k < nI; ++k) gvec[(size_t)k * (mres + 1)] = beta[k];
     int kdim = 0;
     for (int j = 0; j < mres && total < max_iter; ++j) {
       ++total;
       double* vj = d_V + (size_t)j * L;
       double* vn = d_V + (size_t)(j + 1) * L;
-      if ((rc = apply(vj, d_w))) return rc;
+      if ((rc = apply(vj, d_w, d_act, n_act))) return rc;
       // classical Gram-Schmidt, twice, on the device; one transfer of both
       // coefficient sets and the new norm per iteration
       std::vector<double> hcol((size_t)nI * (j + 1), 0.0);
       const size_t hlen = (size_t)nI * (j + 1);
       for (int pass = 0; pass < 2; ++pass) {
         double* hp = d_h + pass * hlen;
-        HIPCHK(launch_batched_dot(st, nI, len, d_V, L, d_w, len, j + 1, hp));
-        HIPCHK(launch_gs_update(st, nI, len, d_V, L, j + 1, hp, j + 1, d_w));
+        HIPCHK(launch_batched_dot(st, nI, len, d_V, L, d_w, len, j + 1, hp, d_act));
+        HIPCHK(launch_gs_update(st, nI, len, d_V, L, j + 1, hp, j + 1, d_w, d_act));
       }
-      HIPCHK(launch_batched_dot(st, nI, len, d_w, 0, d_w, len, 1, d_h + 2 * hlen));
+      HIPCHK(launch_batched_dot(st, nI, len, d_w, 0, d_w, len, 1, d_h + 2 * hlen, d_act));
       HIPCHK(hipMemcpyAsync(hh.data(), d_h, (2 * hlen + nI) * sizeof(double),
                             hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       for (size_t q = 0; q < hlen; ++q) hcol[q] = hh[q] + hh[hlen + q];
       for (int k = 0; k < nI; ++k) tmp[k] = hh[2 * hlen + k];
-      bool all_small = true;
+      bool all_done = true, mask_changed = false;
       for (int k = 0; k < nI; ++k) {
+        if (!act[k]) {  // left the cycle earlier: its next vector is zero
+          tmp[k] = 0.0;
+          continue;
+        }
         double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;  // column-major (mres+1) x mres
         double* gk = gvec.data() + (size_t)k * (mres + 1);
         const double hn = std::sqrt(tmp[k]);
@@ -1032,21 +1067,32 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
         col[j + 1] = 0.0;
         gk[j + 1] = -ss * gk[j];
         gk[j] = cc * gk[j];
-        if (!(std::fabs(gk[j + 1]) <= tol * bnorm[k])) all_small = false;
-        tmp[k] = hn > 0.0 ? 1.0 / hn : 0.0;
+        kd[k] = j + 1;
+        if (std::fabs(gk[j + 1]) <= tol * bnorm[k]) {
+          act[k] = 0;
+          --n_act;
+          mask_changed = true;
+          tmp[k] = 0.0;
+        } else {
+          all_done = false;
+          tmp[k] = hn > 0.0 ? 1.0 / hn : 0.0;
+        }
       }
       HIPCHK(hipMemcpyAsync(d_sc, tmp.data(), nI * sizeof(double), hipMemcpyHostToDevice, st));
+      if (mask_changed)
+        HIPCHK(hipMemcpyAsync(d_act, act.data(), nI * sizeof(int), hipMemcpyHostToDevice, st));
       HIPCHK(launch_axpby(st, nI, len, 0.0, d_w, d_sc, d_w, vn));
       kdim = j + 1;
-      if (all_small) break;
+      if (all_done) break;
     }
+    std::fill(ysol.begin(), ysol.end(), 0.0);
     for (int k = 0; k < nI; ++k) {  // back substitution, then sol += V y
       const double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;
       const double* gk = gvec.data() + (size_t)k * (mres + 1);
       double* yk = ysol.data() + (size_t)k * (mres + 1);
-      for (int i = kdim - 1; i >= 0; --i) {
+      for (int i = kd[k] - 1; i >= 0; --i) {
         double acc = gk[i];
-        for (int q = i + 1; q < kdim; ++q) acc -= Hk[(size_t)q * (mres + 1) + i] * yk[q];
+        for (int q = i + 1; q < kd[k]; ++q) acc -= Hk[(size_t)q * (mres + 1) + i] * yk[q];
         const double d = Hk[(size_t)i * (mres + 1) + i];
         yk[i] = d != 0.0 ? acc / d : 0.0;
       }
@@ -1055,16 +1101,7 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
                           hipMemcpyHostToDevice, st));
     HIPCHK(launch_combine(st, nI, len, d_V, L, kdim, d_y, mres + 1, 1.0, d_sol));
   }
-  if (!converged) {  // final residual check after the last update
-    if ((rc = apply(d_sol, d_r))) return rc;
-    HIPCHK(launch_axpby(st, nI, len, -1.0, d_r, nullptr, d_b, d_r));
-    HIPCHK(launch_batched_dot(st, nI, len, d_r, 0, d_r, len, 1, d_sc));
-    HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    converged = true;
-    for (int k = 0; k < nI; ++k)
-      if (!(std::sqrt(tmp[k]) <= tol * bnorm[k])) converged = false;
-  }
+  if (!converged && (rc = true_residual())) return rc;  // after the last update
   if (steps_out) *steps_out = total;
   return converged ? QDSE_OK : QDSE_NOT_CONVERGED;
 }
@@ -1090,9 +1127,15 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
   if ((rc = buf.alloc(&d_lam, L)) || (rc = buf.alloc(&d_y1, L)) || (rc = buf.alloc(&d_y2, L)) ||
       (rc = buf.alloc(&d_eB, L)) || (rc = buf.alloc(&d_sc, (size_t)nI)))
     return rc;
-  // (I - J^T) lambda = g
-  auto apply = [&](const double* in, double* out_) -> int {
-    int r = vjp_on(c, c->d_K, d_xstar, in, out_);
+  // (I - J^T) lambda = g; the node functions of x* are built once
+  if ((rc = ensure_vjp_work(c))) return rc;
+  HIPCHK(launch_nodes_only(st, nI, g.n, g.nq, g.ldk, c->d_lo, c->d_sw, c->d_t, d_xstar,
+                           c->d_nodes));
+  auto apply = [&](const double* in, double* out_, const int* d_act, int n_active) -> int {
+    // about 1024 workgroups of four row chunks: more chunks per instance as
+    // instances drop out
+    const int nch = std::max(16, std::min(kVjpChunksMax, (4096 / std::max(1, n_active)) & ~3));
+    int r = vjp_on(c, c->d_K, d_xstar, in, out_, d_act, true, nch);
     if (r) return r;
     HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));
     return QDSE_OK;
@@ -1141,9 +1184,9 @@ int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin
   if ((rc = buf.alloc(&d_F, L)) || (rc = buf.alloc(&d_dx, L)) || (rc = buf.alloc(&d_sc, (size_t)nI)))
     return rc;
   std::vector<double> h(L), rmax(nI, 0.0);
-  auto apply = [&](const double* in, double* out_) -> int {  // (I - J(x)) v
+  auto apply = [&](const double* in, double* out_, const int* d_act, int) -> int {  // (I - J(x)) v
     HIPCHK(launch_jvp(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo, c->d_sw,
-                      c->d_t, c->d_s, d_x, in, out_, c->d_nodes));
+                      c->d_t, c->d_s, d_x, in, out_, c->d_nodes, d_act));
     HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));
     return QDSE_OK;
   };

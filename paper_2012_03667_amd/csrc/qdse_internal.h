@@ -136,19 +136,26 @@ hipError_t launch_contraction_only(hipStream_t st, int n_inst, int n, int nq, in
                                   const double* nodes);
 hipError_t launch_nodes_only(hipStream_t st, int n_inst, int n, int nq, int ldk, const int* lo,
                              const double* sw, const double* t, const double* x, double* nodes);
+// Tangent and adjoint sweeps. act (nullable, device, one int per instance):
+// instances whose flag is 0 are skipped and their outputs left as they were.
+// nodes_ready: the node functions of x are already in `nodes` (the adjoint
+// reuses them while x stays fixed).
 hipError_t launch_jvp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
                       const double* K, size_t kstride, const int* lo, const double* sw,
                       const double* t, const double* s, const double* x, const double* v,
-                      double* jv, double* nodes);
+                      double* jv, double* nodes, const int* act = nullptr);
 hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
                       const double* K, size_t kstride, const int* lo, const double* sw,
                       const double* t, const double* s, const double* x, const double* w,
-                      double* out, double* nodes, double* part, double* gq, int nchunk);
+                      double* out, double* nodes, double* part, double* gq, int nchunk,
+                      const int* act = nullptr, bool nodes_ready = false);
 hipError_t launch_batched_dot(hipStream_t st, int n_inst, int len, const double* a, size_t lda,
-                              const double* b, size_t ldb, int nvec, double* out);
+                              const double* b, size_t ldb, int nvec, double* out,
+                              const int* act = nullptr);
 // w[inst][:] -= sum_v h[inst * hstride + v] V[v][inst][:]  (Gram-Schmidt step)
 hipError_t launch_gs_update(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
-                            int nvec, const double* h, int hstride, double* w);
+                            int nvec, const double* h, int hstride, double* w,
+                            const int* act = nullptr);
 // out[inst][:] = beta * out[inst][:] + sum_v y[inst * ystride + v] V[v][inst][:]
 hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
                           int nvec, const double* y, int ystride, double beta, double* out);

@@ -296,10 +296,10 @@ __global__ void k_nodes(int n, int nq, int ldk, const int* __restrict__ lo,
 __global__ void k_nodes_dual(int n, int nq, int ldk, const int* __restrict__ lo,
                              const double* __restrict__ sw, const double* __restrict__ t,
                              const double* __restrict__ x, const double* __restrict__ vdir,
-                             double* __restrict__ nodes) {
+                             double* __restrict__ nodes, const int* __restrict__ act) {
   const int inst = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nq) return;
+  if (j >= nq || (act && !act[inst])) return;
   const double* xA = x + (size_t)inst * 2 * n;
   const double* vA = vdir + (size_t)inst * 2 * n;
   Dual v[5];
@@ -742,11 +742,13 @@ __global__ void __launch_bounds__(256) k_sweep_dual(int n_inst, int n, int nq, i
                                                     const double* __restrict__ nodes,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ vdir,
-                                                    double* __restrict__ jv) {
+                                                    double* __restrict__ jv,
+                                                    const int* __restrict__ act) {
   const int lane = threadIdx.x & (WAVE - 1);
   const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (row >= (long)n_inst * n) return;
   const int inst = (int)(row / n), i = (int)(row % n);
+  if (act && !act[inst]) return;  // (one row per wavefront: the exit is wave-uniform)
   const InstDev P = inst_[inst];
   const size_t mat = (size_t)n * ldk;
   const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
@@ -774,11 +776,13 @@ __global__ void __launch_bounds__(256) k_vjp_rows(int n_inst, int n, int nq, int
                                                   const double* __restrict__ t_,
                                                   const double* __restrict__ nodes,
                                                   const double* __restrict__ w,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out,
+                                                  const int* __restrict__ act) {
   const int lane = threadIdx.x & (WAVE - 1);
   const long row = (long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (row >= (long)n_inst * n) return;
   const int inst = (int)(row / n), i = (int)(row % n);
+  if (act && !act[inst]) return;
   const InstDev P = inst_[inst];
   const size_t mat = (size_t)n * ldk;
   const double* Ki = K + (size_t)P.kblock * kstride + (size_t)i * ldk;
@@ -814,10 +818,10 @@ __global__ void k_vjp_cols(int n_inst, int n, int nq, int ldk, int nchunk,
                            size_t kstride, const double* __restrict__ s_,
                            const double* __restrict__ t_, const double* __restrict__ nodes,
                            const double* __restrict__ x, const double* __restrict__ w,
-                           double* __restrict__ part) {
+                           double* __restrict__ part, const int* __restrict__ act) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int chunk = blockIdx.y, inst = blockIdx.z;
-  if (j >= nq) return;
+  if (j >= nq || (act && !act[inst])) return;
   const InstDev P = inst_[inst];
   const size_t mat = (size_t)n * ldk;
   const double* Kb = K + (size_t)P.kblock * kstride;
@@ -865,9 +869,11 @@ __global__ void __launch_bounds__(256) k_vjp_fused(int n_inst, int n, int nq, in
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ w,
                                                    double* __restrict__ out,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part,
+                                                   const int* __restrict__ act) {
   extern __shared__ double ndl[];  // [5][ldk]: A, B, sigma_V, sigma_S, t
   const int inst = blockIdx.y;
+  if (act && !act[inst]) return;  // the whole workgroup: before the barrier
   const double* nd = nodes + (size_t)inst * 5 * ldk;
   for (int j = threadIdx.x; j < nq; j += blockDim.x) {
     ndl[j] = nd[j];
@@ -951,10 +957,10 @@ __global__ void __launch_bounds__(256) k_vjp_fused(int n_inst, int n, int nq, in
 // A(t_j), B(t_j) into gq[inst][2][ldk].
 __global__ void k_vjp_nodes(int n_inst, int nq, int ldk, int nchunk, const double* __restrict__ t_,
                             const double* __restrict__ nodes, const double* __restrict__ part,
-                            double* __restrict__ gq) {
+                            double* __restrict__ gq, const int* __restrict__ act) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int inst = blockIdx.y;
-  if (j >= nq) return;
+  if (j >= nq || (act && !act[inst])) return;
   double g[4] = {0.0, 0.0, 0.0, 0.0};
   for (int c = 0; c < nchunk; ++c) {
     const double* o = part + (((size_t)inst * nchunk + c) * 4) * ldk;
@@ -974,10 +980,10 @@ __global__ void k_vjp_nodes(int n_inst, int nq, int ldk, int nchunk, const doubl
 // every loop node whose stencil contains it; adds the row part in place.
 __global__ void k_vjp_scatter(int n_inst, int n, int nq, int ldk, const int* __restrict__ lo,
                               const double* __restrict__ sw, const double* __restrict__ gq,
-                              double* __restrict__ out) {
+                              double* __restrict__ out, const int* __restrict__ act) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int inst = blockIdx.y;
-  if (l >= n) return;
+  if (l >= n || (act && !act[inst])) return;
   double gA = 0.0, gB = 0.0;
   const int j0 = l - 4 < 0 ? 0 : l - 4, j1 = l + 4 > nq - 1 ? nq - 1 : l + 4;
   for (int j = j0; j <= j1; ++j) {
@@ -994,11 +1000,13 @@ __global__ void k_vjp_scatter(int n_inst, int n, int nq, int ldk, const int* __r
 
 // ---------------------------------------------------------------- small vector ops
 // out[inst * nvec + v] = sum_k a[v][inst][k] b[inst][k], one block per
-// (instance, vector), fixed reduction order.
+// (instance, vector), fixed reduction order; instances with act[inst] == 0
+// are skipped (act may be null).
 __global__ void k_batched_dot(int len, const double* __restrict__ a, size_t lda,
                               const double* __restrict__ b, size_t ldb, int nvec,
-                              double* __restrict__ out) {
+                              double* __restrict__ out, const int* __restrict__ act) {
   const int inst = blockIdx.x, v = blockIdx.y;
+  if (act && !act[inst]) return;  // the whole block: before the barrier
   const double* av = a + (size_t)v * lda + (size_t)inst * len;
   const double* bv = b + (size_t)inst * ldb;
   double acc = 0.0;
@@ -1015,10 +1023,12 @@ __global__ void k_batched_dot(int len, const double* __restrict__ a, size_t lda,
 }
 
 __global__ void k_gs_update(int n_inst, int len, const double* __restrict__ V, size_t ldv, int nvec,
-                            const double* __restrict__ h, int hstride, double* __restrict__ w) {
+                            const double* __restrict__ h, int hstride, double* __restrict__ w,
+                            const int* __restrict__ act) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n_inst * len) return;
   const int inst = (int)(e / len);
+  if (act && !act[inst]) return;
   double acc = w[e];
   for (int v = 0; v < nvec; ++v) acc -= h[(size_t)inst * hstride + v] * V[(size_t)v * ldv + e];
   w[e] = acc;
@@ -1154,59 +1164,61 @@ hipError_t launch_nodes_only(hipStream_t st, int n_inst, int n, int nq, int ldk,
 hipError_t launch_jvp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
                       const double* K, size_t kstride, const int* lo, const double* sw,
                       const double* t, const double* s, const double* x, const double* v,
-                      double* jv, double* nodes) {
+                      double* jv, double* nodes, const int* act) {
   hipLaunchKernelGGL(k_nodes_dual, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk,
-                     lo, sw, t, x, v, nodes);
+                     lo, sw, t, x, v, nodes, act);
   const long rows = (long)n_inst * n;
   hipLaunchKernelGGL(k_sweep_dual, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n,
-                     nq, ldk, inst, K, kstride, s, nodes, x, v, jv);
+                     nq, ldk, inst, K, kstride, s, nodes, x, v, jv, act);
   return hipGetLastError();
 }
 
 hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const InstDev* inst,
                       const double* K, size_t kstride, const int* lo, const double* sw,
                       const double* t, const double* s, const double* x, const double* w,
-                      double* out, double* nodes, double* part, double* gq, int nchunk) {
-  hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
-                     sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 1);
+                      double* out, double* nodes, double* part, double* gq, int nchunk,
+                      const int* act, bool nodes_ready) {
+  if (!nodes_ready)
+    hipLaunchKernelGGL(k_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n, nq, ldk, lo,
+                       sw, t, x, nodes, (SolveState*)nullptr, (const SolveCtl*)nullptr, 1);
   const int slots = (nq + WAVE - 1) / WAVE;
   const dim3 fgrid((nchunk + 3) / 4, n_inst);
   const size_t flds = (size_t)5 * ldk * sizeof(double);
   if (slots <= 4) {
     hipLaunchKernelGGL(k_vjp_fused<4>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
-                       inst, K, kstride, s, t, nodes, x, w, out, part);
+                       inst, K, kstride, s, t, nodes, x, w, out, part, act);
   } else if (slots <= 9) {
     hipLaunchKernelGGL(k_vjp_fused<9>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
-                       inst, K, kstride, s, t, nodes, x, w, out, part);
+                       inst, K, kstride, s, t, nodes, x, w, out, part, act);
   } else if (slots <= 17) {
     hipLaunchKernelGGL(k_vjp_fused<17>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
-                       inst, K, kstride, s, t, nodes, x, w, out, part);
+                       inst, K, kstride, s, t, nodes, x, w, out, part, act);
   } else {  // large grids: row and column parts as two passes
     const long rows = (long)n_inst * n;
     hipLaunchKernelGGL(k_vjp_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n,
-                       nq, ldk, inst, K, kstride, s, t, nodes, w, out);
+                       nq, ldk, inst, K, kstride, s, t, nodes, w, out, act);
     hipLaunchKernelGGL(k_vjp_cols, dim3((nq + 63) / 64, nchunk, n_inst), dim3(64), 0, st, n_inst,
-                       n, nq, ldk, nchunk, inst, K, kstride, s, t, nodes, x, w, part);
+                       n, nq, ldk, nchunk, inst, K, kstride, s, t, nodes, x, w, part, act);
   }
   hipLaunchKernelGGL(k_vjp_nodes, dim3((nq + 255) / 256, n_inst), dim3(256), 0, st, n_inst, nq,
-                     ldk, nchunk, t, nodes, part, gq);
+                     ldk, nchunk, t, nodes, part, gq, act);
   hipLaunchKernelGGL(k_vjp_scatter, dim3((n + 255) / 256, n_inst), dim3(256), 0, st, n_inst, n, nq,
-                     ldk, lo, sw, gq, out);
+                     ldk, lo, sw, gq, out, act);
   return hipGetLastError();
 }
 
 hipError_t launch_batched_dot(hipStream_t st, int n_inst, int len, const double* a, size_t lda,
-                              const double* b, size_t ldb, int nvec, double* out) {
+                              const double* b, size_t ldb, int nvec, double* out, const int* act) {
   hipLaunchKernelGGL(k_batched_dot, dim3(n_inst, nvec), dim3(256), 0, st, len, a, lda, b, ldb, nvec,
-                     out);
+                     out, act);
   return hipGetLastError();
 }
 
 hipError_t launch_gs_update(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
-                            int nvec, const double* h, int hstride, double* w) {
+                            int nvec, const double* h, int hstride, double* w, const int* act) {
   const long tot = (long)n_inst * len;
   hipLaunchKernelGGL(k_gs_update, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n_inst, len,
-                     V, ldv, nvec, h, hstride, w);
+                     V, ldv, nvec, h, hstride, w, act);
   return hipGetLastError();
 }
 
