@@ -15,7 +15,7 @@
  *
  * Besides the paper's vacuum setting: batched matrix-core sweeps
  * (precision), Newton-Krylov solves, tangent/adjoint sweeps and implicit
- * gradients (qdse_jvp, qdse_vjp, qdse_grad), a launch-shape autotuner
+ * gradients (qdse_jvp, qdse_vjp, qdse_jacobian_band, qdse_grad), a launch-shape autotuner
  * (qdse_autotune), the renormalised setting with the full Qin-Chang
  * interaction (qdse_setup_qc), finite chemical potential and temperature
  * (qdse_mu_*), and the general two-equation system of Sec. I (qdse_fred_*).
@@ -227,11 +227,25 @@ int qdse_jvp(qdse_ctx* ctx, const double* d_x, const double* d_v, double* d_jv);
 /* Transposed product d_out = (dF/dx)(d_x)^T d_w (reverse mode). Asynchronous. */
 int qdse_vjp(qdse_ctx* ctx, const double* d_x, const double* d_w, double* d_out);
 
+/* Near-diagonal band of the sweep Jacobian J = dF/dx at d_x (the derivative of
+ * the map of Sec. II eqs. dsesys, dsesys2 in the direct-difference form):
+ * d_out[inst][i][o][4] (device, FP64, n_inst * N * (2 bw + 1) * 4 values)
+ * holds, for l = i - bw + o, the blocks {dF^A_i/dA_l, dF^A_i/dB_l,
+ * dF^B_i/dA_l, dF^B_i/dB_l}; entries with l outside [0, N) are zero. Row i
+ * depends on A_l, B_l through A_i, B_i themselves (l = i) and through the
+ * interpolation stencils of the loop nodes. 0 <= bw < N (QDSE_EINVAL
+ * otherwise); QDSE_ENOTSUP for a renormalised context. Asynchronous. The
+ * adjoint solve of qdse_grad factors I - band^T (bw = 2) per instance as its
+ * preconditioner. */
+int qdse_jacobian_band(qdse_ctx* ctx, const double* d_x, int bw, double* d_out);
+
 /* Gradient of a loss L(x*) through the fixed point x* = F(x*; theta), theta =
  * (D, omega, m) per instance, by implicit differentiation: solves
  * (I - J)^T lambda = d_g (J = dF/dx at d_xstar, d_g = dL/dx*) and returns
  * theta_bar = lambda^T dF/dtheta in theta_bar[n_inst][3] (host). The linear
- * solve (restarted GMRES) runs until ||residual||_2 < tol ||d_g||_2 for every
+ * solve (restarted GMRES, right-preconditioned by a banded LU of I - band(J)^T,
+ * see qdse_jacobian_band; environment QDSE_ADJ_PREC=0 switches the
+ * preconditioner off) runs until ||residual||_2 < tol ||d_g||_2 for every
  * instance or max_iter Krylov steps. Requires D > 0 for every instance
  * (QDSE_EINVAL otherwise).
  * Returns QDSE_NOT_CONVERGED if the adjoint solve did not reach tol.

@@ -92,6 +92,7 @@ def load():
     L.qdse_newton.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]
     L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_vjp.argtypes = [_vp, _vp, _vp, _vp]
+    L.qdse_jacobian_band.argtypes = [_vp, _vp, ctypes.c_int, _vp]
     L.qdse_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _dp]
     L.qdse_kernel_matrices.argtypes = [_vp, ctypes.c_int, _vp]
     L.qdse_time_contraction.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _dp]
@@ -268,6 +269,21 @@ class Solver:
         out = torch.empty_like(x) if out is None else out
         _check(load().qdse_vjp(self._h, _dev(x, self.shape, "x"), _dev(w, self.shape, "w"),
                                _dev(out, self.shape, "out")), "qdse_vjp")
+        return out
+
+    def jacobian_band(self, x, bw, out=None):
+        """Band of dF/dx at x: [n_inst][N][2 bw + 1][4] blocks (AA, AB, BA, BB)
+        for l = i - bw + o."""
+        import torch
+        n_inst, n2 = self.shape
+        shp = (n_inst, n2 // 2, 2 * int(bw) + 1, 4)
+        if out is None:
+            out = torch.empty(shp, dtype=torch.float64, device=x.device)
+        elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                  and tuple(out.shape) == shp):
+            raise ValueError(f"out must be a contiguous float64 CUDA tensor of shape {shp}")
+        _check(load().qdse_jacobian_band(self._h, _dev(x, self.shape, "x"), int(bw),
+                                         ctypes.c_void_p(out.data_ptr())), "qdse_jacobian_band")
         return out
 
     def grad(self, xstar, g, tol=1e-12, max_iter=400):

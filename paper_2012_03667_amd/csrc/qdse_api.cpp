@@ -104,6 +104,7 @@ struct qdse_ctx {
   int persist_G = 0, persist_rpw = 0, persist_gsz = 1;  // G = 0: not usable
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
+  double* d_jdiag = nullptr;  // [n_inst][n][4] for qdse_jacobian_band
   int nchunk = 16;
   // private state for kernel timing
   SolveState* d_tstate = nullptr;
@@ -408,7 +409,7 @@ void qdse_destroy(qdse_ctx* c) {
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
                   c->d_ctl,     c->d_part,    c->d_gq,      c->d_slots, c->d_barrier,
                   c->d_flags,   c->d_C32,     c->d_M64,     c->d_C64,     c->d_tstate,
-                  c->d_tctl,    c->d_sK,      c->d_sig};
+                  c->d_tctl,    c->d_sK,      c->d_sig,     c->d_jdiag};
   for (void* p : ptrs) dfree(p);
   delete c;
 }
@@ -923,6 +924,21 @@ int qdse_vjp(qdse_ctx* c, const double* d_x, const double* d_w, double* d_out) {
   return vjp_on(c, c->d_K, d_x, d_w, d_out);
 }
 
+int qdse_jacobian_band(qdse_ctx* c, const double* d_x, int bw, double* d_out) {
+  if (!c || !d_x || !d_out || bw < 0 || bw >= c->hg.n) return QDSE_EINVAL;
+  if (c->qc) return QDSE_ENOTSUP;
+  const HostGrid& g = c->hg;
+  if (!c->d_jdiag) {
+    int rc = dalloc(&c->d_jdiag, (size_t)c->n_inst * g.n * 4);
+    if (rc) return rc;
+  }
+  HIPCHK(launch_nodes_only(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_lo, c->d_sw, c->d_t, d_x,
+                           c->d_nodes));
+  HIPCHK(launch_jband(c->stream, c->n_inst, g.n, g.nq, g.ldk, bw, c->d_inst, c->d_K, c->kstride,
+                      c->d_lo, c->d_sw, c->d_s, c->d_t, c->d_nodes, d_x, c->d_jdiag, d_out, 0));
+  return QDSE_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -945,14 +961,15 @@ struct DevBufs {
 // solves op(sol) = b to ||r||_2 <= tol ||b||_2 per instance, starting from
 // sol = 0. Arnoldi vectors, Gram-Schmidt (two classical passes) and the basis
 // combinations run on the device; the small Hessenberg least-squares problems
-// (Givens rotations) run on the host. An instance whose residual estimate
+// (Givens rotations) run on the host. With use_prec the iteration is right
+// preconditioned: op(prec(y)) = b, sol = prec(y). An instance whose residual estimate
 // meets the target leaves the operator applications for the rest of the cycle
 // (its flag in the device activity mask drops to 0, its later basis vectors
 // are zero and their coefficients too); every restart recomputes the true
 // residual of every instance. Returns QDSE_OK or QDSE_NOT_CONVERGED.
-template <class Op>
-int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, double tol,
-                  int max_iter, int* steps_out) {
+template <class Op, class Prec>
+int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double* d_b,
+                  double* d_sol, double tol, int max_iter, int* steps_out) {
   const int nI = c->n_inst, len = 2 * c->hg.n;
   const size_t L = xlen(c);
   // restart length: the Jacobian is strongly non-normal (||J|| ~ 2 with a tight
@@ -961,9 +978,10 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
   const int mres = std::max(1, std::min(max_iter, 120));
   hipStream_t st = c->stream;
   DevBufs buf;
-  double *d_V, *d_w, *d_r, *d_h, *d_y, *d_sc;
+  double *d_V, *d_w, *d_r, *d_h, *d_y, *d_sc, *d_z = nullptr;
   int* d_act;
   int rc;
+  if (use_prec && (rc = buf.alloc(&d_z, L))) return rc;
   // d_h: two Gram-Schmidt passes [2][nI][mres + 1] followed by the norms [nI]
   const size_t hstride = (size_t)nI * (mres + 1);
   if ((rc = buf.alloc(&d_V, (size_t)(mres + 1) * L)) || (rc = buf.alloc(&d_w, L)) ||
@@ -1024,7 +1042,12 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
       ++total;
       double* vj = d_V + (size_t)j * L;
       double* vn = d_V + (size_t)(j + 1) * L;
-      if ((rc = apply(vj, d_w, d_act, n_act))) return rc;
+      const double* zj = vj;
+      if (use_prec) {
+        if ((rc = prec(vj, d_z, d_act))) return rc;
+        zj = d_z;
+      }
+      if ((rc = apply(zj, d_w, d_act, n_act))) return rc;
       // classical Gram-Schmidt, twice, on the device; one transfer of both
       // coefficient sets and the new norm per iteration
       std::vector<double> hcol((size_t)nI * (j + 1), 0.0);
@@ -1099,7 +1122,13 @@ int gmres_batched(qdse_ctx* c, Op apply, const double* d_b, double* d_sol, doubl
     }
     HIPCHK(hipMemcpyAsync(d_y, ysol.data(), (size_t)nI * (mres + 1) * sizeof(double),
                           hipMemcpyHostToDevice, st));
-    HIPCHK(launch_combine(st, nI, len, d_V, L, kdim, d_y, mres + 1, 1.0, d_sol));
+    if (use_prec) {  // sol += prec(V y)
+      HIPCHK(launch_combine(st, nI, len, d_V, L, kdim, d_y, mres + 1, 0.0, d_z));
+      if ((rc = prec(d_z, d_w, nullptr))) return rc;
+      HIPCHK(launch_axpby(st, nI, len, 1.0, d_sol, nullptr, d_w, d_sol));
+    } else {
+      HIPCHK(launch_combine(st, nI, len, d_V, L, kdim, d_y, mres + 1, 1.0, d_sol));
+    }
   }
   if (!converged && (rc = true_residual())) return rc;  // after the last update
   if (steps_out) *steps_out = total;
@@ -1140,7 +1169,28 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
     HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));
     return QDSE_OK;
   };
-  const int grc = gmres_batched(c, apply, d_g, d_lam, tol, max_iter, nullptr);
+  // banded preconditioner from the near-diagonal part of J at x*
+  // (QDSE_ADJ_PREC=0 in the environment switches it off)
+  const char* pe = std::getenv("QDSE_ADJ_PREC");
+  const bool use_prec = !(pe && pe[0] == '0');
+  double *d_D = nullptr, *d_Jb = nullptr, *d_F = nullptr, *d_T = nullptr;
+  int* d_ok = nullptr;
+  if (use_prec) {
+    const int wb = 2 * kPrecBand + 1;
+    if ((rc = buf.alloc(&d_D, (size_t)nI * g.n * 4)) ||
+        (rc = buf.alloc(&d_Jb, (size_t)nI * g.n * wb * 4)) ||
+        (rc = buf.alloc(&d_F, (size_t)nI * 2 * g.n * (2 * (2 * kPrecBand + 1) + 1))) ||
+        (rc = buf.alloc(&d_ok, (size_t)nI)) || (rc = buf.alloc(&d_T, L)))
+      return rc;
+    HIPCHK(launch_jband(st, nI, g.n, g.nq, g.ldk, kPrecBand, c->d_inst, c->d_K, c->kstride,
+                        c->d_lo, c->d_sw, c->d_s, c->d_t, c->d_nodes, d_xstar, d_D, d_Jb, 1));
+    HIPCHK(launch_band_lu(st, nI, g.n, d_Jb, d_F, d_ok));
+  }
+  auto prec = [&](const double* in, double* out_, const int* d_act) -> int {
+    HIPCHK(launch_band_solve(st, nI, g.n, d_F, d_ok, d_act, in, out_, d_T));
+    return QDSE_OK;
+  };
+  const int grc = gmres_batched(c, apply, prec, use_prec, d_g, d_lam, tol, max_iter, nullptr);
   if (grc < 0) return grc;
   // theta_bar = lambda^T dF/dtheta
   HIPCHK(launch_sweep_fp64(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo,
@@ -1210,7 +1260,8 @@ int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin
       if (!std::isfinite(r)) bad = true;
     }
     if (done || bad || it >= max_newton) break;
-    rc = gmres_batched(c, apply, d_F, d_dx, lin_tol, 400, nullptr);
+    auto no_prec = [](const double*, double*, const int*) -> int { return QDSE_OK; };
+    rc = gmres_batched(c, apply, no_prec, false, d_F, d_dx, lin_tol, 400, nullptr);
     if (rc < 0) return rc;
     HIPCHK(launch_axpby(st, nI, len, 1.0, d_x, nullptr, d_dx, d_x));  // x += dx
   }

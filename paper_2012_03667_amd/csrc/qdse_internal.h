@@ -156,6 +156,24 @@ hipError_t launch_batched_dot(hipStream_t st, int n_inst, int len, const double*
 hipError_t launch_gs_update(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
                             int nvec, const double* h, int hstride, double* w,
                             const int* act = nullptr);
+// Near-diagonal band of the sweep Jacobian at x (qdse_band.hip): D receives
+// the direct derivatives [n_inst][n][4]; out the blocks {AA, AB, BA, BB} of
+// J[(a,i),(b,l)] for l = i - bw .. i + bw (zero outside the grid), layout
+// [inst][i][2bw+1][4], or [i][2bw+1][4][inst] when minor != 0. nodes holds the
+// node functions of x.
+hipError_t launch_jband(hipStream_t st, int n_inst, int n, int nq, int ldk, int bw,
+                        const InstDev* inst, const double* K, size_t kstride, const int* lo,
+                        const double* sw, const double* s, const double* t, const double* nodes,
+                        const double* x, double* D, double* out, int minor);
+// Banded preconditioner of the adjoint solve: band half-width kPrecBand nodes.
+// launch_band_lu factors M = I - band(J)^T per instance from the
+// instance-minor band (F: [2n][4 kPrecBand + 3][n_inst]; ok[inst] = 0 if a
+// pivot was unsafe); launch_band_solve applies M^{-1} (act may be null; T is
+// n_inst * 2n doubles of workspace).
+constexpr int kPrecBand = 2;
+hipError_t launch_band_lu(hipStream_t st, int n_inst, int n, const double* Jb, double* F, int* ok);
+hipError_t launch_band_solve(hipStream_t st, int n_inst, int n, const double* F, const int* ok,
+                             const int* act, const double* in, double* out, double* T);
 // out[inst][:] = beta * out[inst][:] + sum_v y[inst * ystride + v] V[v][inst][:]
 hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
                           int nvec, const double* y, int ystride, double beta, double* out);

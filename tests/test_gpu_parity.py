@@ -119,6 +119,55 @@ def test_vjp_is_transpose_of_oracle_jacobian(Q):
         assert np.max(np.abs(out[k] - ref)) < 1e-11 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("n,order,bw", [(24, 3, 23), (40, 3, 2), (33, 1, 4)])
+def test_jacobian_band_matches_oracle_jacobian(Q, n, order, bw):
+    """The band of dF/dx from the analytic band kernel against the oracle's
+    complex-step Jacobian: every block entry with |i - l| <= bw (bw = N - 1:
+    the whole matrix), zero outside the grid."""
+    na = 16
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.03)]
+    S = Q.Solver(n, na, params, interp_order=order)
+    g = oracle_grid(n, na, order)
+    rng = np.random.default_rng(14)
+    xs = np.stack([smooth_x(g.s, rng) for _ in params])
+    band = S.jacobian_band(torch.tensor(xs, device="cuda"), bw).cpu().numpy()
+    for k, (D, om, m) in enumerate(params):
+        J = O.jacobian(g, O.Params(D, om, m), xs[k])
+        ref = np.zeros((n, 2 * bw + 1, 4))
+        for i in range(n):
+            for o in range(2 * bw + 1):
+                l = i - bw + o
+                if 0 <= l < n:
+                    ref[i, o] = [J[i, l], J[i, n + l], J[n + i, l], J[n + i, n + l]]
+        assert np.max(np.abs(band[k] - ref)) < 1e-11 * np.max(np.abs(ref)), k
+
+
+def test_adjoint_preconditioner_changes_no_result(Q):
+    """The banded preconditioner of the adjoint solve changes the iteration,
+    not its solution: theta_bar with and without it agree to the solve
+    tolerance."""
+    n, na = 150, 32
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (0.55, 0.678, 0.0), (0.55, 0.678, 0.02)]
+    S = Q.Solver(n, na, params)
+    x = S.initial(1.0, 1.0)
+    rc, _, _ = S.solve(x, tol=1e-12, max_iter=5000)
+    assert rc == Q.QDSE_OK
+    g = torch.tensor(np.random.default_rng(15).normal(size=tuple(x.shape)), device="cuda")
+    tb1, rc1 = S.grad(x, g, tol=1e-12, max_iter=600)
+    old = os.environ.get("QDSE_ADJ_PREC")
+    os.environ["QDSE_ADJ_PREC"] = "0"
+    try:
+        tb0, rc0 = S.grad(x, g, tol=1e-12, max_iter=600)
+    finally:
+        if old is None:
+            del os.environ["QDSE_ADJ_PREC"]
+        else:
+            os.environ["QDSE_ADJ_PREC"] = old
+    assert rc1 == Q.QDSE_OK and rc0 == Q.QDSE_OK
+    tb0, tb1 = np.asarray(tb0), np.asarray(tb1)
+    assert np.max(np.abs(tb1 - tb0)) < 1e-8 * np.max(np.abs(tb0))
+
+
 @pytest.mark.parametrize("n", [150, 512, 700, 1200])
 def test_vjp_inner_product_with_oracle_jvp(Q, n):
     """<J^T w, v> from the GPU reverse sweep equals <w, J v> with J v from the
