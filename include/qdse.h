@@ -244,7 +244,7 @@ int qdse_jacobian_band(qdse_ctx* ctx, const double* d_x, int bw, double* d_out);
  * (I - J)^T lambda = d_g (J = dF/dx at d_xstar, d_g = dL/dx*) and returns
  * theta_bar = lambda^T dF/dtheta in theta_bar[n_inst][3] (host). The linear
  * solve (restarted GMRES, right-preconditioned by a banded LU of I - band(J)^T,
- * see qdse_jacobian_band; environment QDSE_ADJ_PREC=0 switches the
+ * see qdse_jacobian_band; environment QDSE_BAND_PREC=0 switches the
  * preconditioner off) runs until ||residual||_2 < tol ||d_g||_2 for every
  * instance or max_iter Krylov steps. Requires D > 0 for every instance
  * (QDSE_EINVAL otherwise).

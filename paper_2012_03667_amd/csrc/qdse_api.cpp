@@ -1135,6 +1135,41 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
   return converged ? QDSE_OK : QDSE_NOT_CONVERGED;
 }
 
+// Banded preconditioner of the adjoint solve (qdse_band.hip): the
+// near-diagonal band of J at x (half-width kPrecBand nodes), factored per
+// instance as I - band(J)^T. Device buffers live as long as the object.
+struct BandPrec {
+  DevBufs buf;
+  double *d_D = nullptr, *d_Jb = nullptr, *d_F = nullptr, *d_T = nullptr;
+  int* d_ok = nullptr;
+  int build(qdse_ctx* c, const double* d_x) {
+    const HostGrid& g = c->hg;
+    const int nI = c->n_inst, wb = 2 * kPrecBand + 1;
+    int rc;
+    if ((rc = buf.alloc(&d_D, (size_t)nI * g.n * 4)) ||
+        (rc = buf.alloc(&d_Jb, (size_t)nI * g.n * wb * 4)) ||
+        (rc = buf.alloc(&d_F, (size_t)nI * 2 * g.n * (2 * (2 * kPrecBand + 1) + 1))) ||
+        (rc = buf.alloc(&d_ok, (size_t)nI)) || (rc = buf.alloc(&d_T, xlen(c))))
+      return rc;
+    HIPCHK(launch_nodes_only(c->stream, nI, g.n, g.nq, g.ldk, c->d_lo, c->d_sw, c->d_t, d_x,
+                             c->d_nodes));
+    HIPCHK(launch_jband(c->stream, nI, g.n, g.nq, g.ldk, kPrecBand, c->d_inst, c->d_K, c->kstride,
+                        c->d_lo, c->d_sw, c->d_s, c->d_t, c->d_nodes, d_x, d_D, d_Jb, 1));
+    HIPCHK(launch_band_lu(c->stream, nI, g.n, d_Jb, d_F, d_ok));
+    return QDSE_OK;
+  }
+  int apply(qdse_ctx* c, const double* in, double* out, const int* d_act) {
+    HIPCHK(launch_band_solve(c->stream, c->n_inst, c->hg.n, d_F, d_ok, d_act, in, out, d_T));
+    return QDSE_OK;
+  }
+};
+
+// QDSE_BAND_PREC=0 in the environment switches the preconditioner off.
+bool band_prec_enabled() {
+  const char* e = std::getenv("QDSE_BAND_PREC");
+  return !(e && e[0] == '0');
+}
+
 }  // namespace
 
 extern "C" {
@@ -1170,25 +1205,11 @@ int qdse_grad(qdse_ctx* c, const double* d_xstar, const double* d_g, double tol,
     return QDSE_OK;
   };
   // banded preconditioner from the near-diagonal part of J at x*
-  // (QDSE_ADJ_PREC=0 in the environment switches it off)
-  const char* pe = std::getenv("QDSE_ADJ_PREC");
-  const bool use_prec = !(pe && pe[0] == '0');
-  double *d_D = nullptr, *d_Jb = nullptr, *d_F = nullptr, *d_T = nullptr;
-  int* d_ok = nullptr;
-  if (use_prec) {
-    const int wb = 2 * kPrecBand + 1;
-    if ((rc = buf.alloc(&d_D, (size_t)nI * g.n * 4)) ||
-        (rc = buf.alloc(&d_Jb, (size_t)nI * g.n * wb * 4)) ||
-        (rc = buf.alloc(&d_F, (size_t)nI * 2 * g.n * (2 * (2 * kPrecBand + 1) + 1))) ||
-        (rc = buf.alloc(&d_ok, (size_t)nI)) || (rc = buf.alloc(&d_T, L)))
-      return rc;
-    HIPCHK(launch_jband(st, nI, g.n, g.nq, g.ldk, kPrecBand, c->d_inst, c->d_K, c->kstride,
-                        c->d_lo, c->d_sw, c->d_s, c->d_t, c->d_nodes, d_xstar, d_D, d_Jb, 1));
-    HIPCHK(launch_band_lu(st, nI, g.n, d_Jb, d_F, d_ok));
-  }
+  BandPrec bp;
+  const bool use_prec = band_prec_enabled();
+  if (use_prec && (rc = bp.build(c, d_xstar))) return rc;
   auto prec = [&](const double* in, double* out_, const int* d_act) -> int {
-    HIPCHK(launch_band_solve(st, nI, g.n, d_F, d_ok, d_act, in, out_, d_T));
-    return QDSE_OK;
+    return bp.apply(c, in, out_, d_act);
   };
   const int grc = gmres_batched(c, apply, prec, use_prec, d_g, d_lam, tol, max_iter, nullptr);
   if (grc < 0) return grc;
@@ -1260,6 +1281,8 @@ int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin
       if (!std::isfinite(r)) bad = true;
     }
     if (done || bad || it >= max_newton) break;
+    // (no preconditioner: away from the fixed point I - band(J) factored
+    // without pivoting can be close to singular and slow the Krylov solve)
     auto no_prec = [](const double*, double*, const int*) -> int { return QDSE_OK; };
     rc = gmres_batched(c, apply, no_prec, false, d_F, d_dx, lin_tol, 400, nullptr);
     if (rc < 0) return rc;

@@ -156,12 +156,12 @@ __global__ void __launch_bounds__(64) k_band_lu(int n_inst, int n, const double*
       for (int d = 0; d < W; ++d) R[d] = d == HB ? 1.0 : 0.0;
       return;
     }
-    const int l = r >> 1, b = r & 1;
 #pragma unroll
     for (int d = 0; d < W; ++d) {
       const int c = r + d - HB;
       if (c < 0 || c >= N) continue;
-      const int i = c >> 1, a = c & 1;
+      // (a, i): component and node of F (the column); (b, l): of x (the row)
+      const int i = c >> 1, a = c & 1, l = r >> 1, b = r & 1;
       const int o = l - i + BW;
       if (o < 0 || o >= WB) continue;
       const double jv = Jb[(((size_t)i * WB + o) * 4 + (a * 2 + b)) * n_inst + inst];

@@ -142,6 +142,18 @@ def test_jacobian_band_matches_oracle_jacobian(Q, n, order, bw):
         assert np.max(np.abs(band[k] - ref)) < 1e-11 * np.max(np.abs(ref)), k
 
 
+def _without_band_prec(fn):
+    old = os.environ.get("QDSE_BAND_PREC")
+    os.environ["QDSE_BAND_PREC"] = "0"
+    try:
+        return fn()
+    finally:
+        if old is None:
+            del os.environ["QDSE_BAND_PREC"]
+        else:
+            os.environ["QDSE_BAND_PREC"] = old
+
+
 def test_adjoint_preconditioner_changes_no_result(Q):
     """The banded preconditioner of the adjoint solve changes the iteration,
     not its solution: theta_bar with and without it agree to the solve
@@ -154,15 +166,7 @@ def test_adjoint_preconditioner_changes_no_result(Q):
     assert rc == Q.QDSE_OK
     g = torch.tensor(np.random.default_rng(15).normal(size=tuple(x.shape)), device="cuda")
     tb1, rc1 = S.grad(x, g, tol=1e-12, max_iter=600)
-    old = os.environ.get("QDSE_ADJ_PREC")
-    os.environ["QDSE_ADJ_PREC"] = "0"
-    try:
-        tb0, rc0 = S.grad(x, g, tol=1e-12, max_iter=600)
-    finally:
-        if old is None:
-            del os.environ["QDSE_ADJ_PREC"]
-        else:
-            os.environ["QDSE_ADJ_PREC"] = old
+    tb0, rc0 = _without_band_prec(lambda: S.grad(x, g, tol=1e-12, max_iter=600))
     assert rc1 == Q.QDSE_OK and rc0 == Q.QDSE_OK
     tb0, tb1 = np.asarray(tb0), np.asarray(tb1)
     assert np.max(np.abs(tb1 - tb0)) < 1e-8 * np.max(np.abs(tb0))
