@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <memory>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -957,6 +958,27 @@ struct DevBufs {
   }
 };
 
+// Page-locked host array (freed on scope exit): device transfers from and to
+// it are asynchronous, so the host writes it only after a stream
+// synchronisation that follows the last transfer reading it.
+template <class T>
+struct Pinned {
+  T* p = nullptr;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+  int alloc(size_t n) {
+    if (hipHostMalloc((void**)&p, (n ? n : 1) * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      g_last_error = "hipHostMalloc failed";
+      return QDSE_ENOMEM;
+    }
+    return QDSE_OK;
+  }
+  T& operator[](size_t i) { return p[i]; }
+  T* data() { return p; }
+};
+
 // Restarted GMRES(mres) for every instance at once (block-diagonal operator):
 // solves op(sol) = b to ||r||_2 <= tol ||b||_2 per instance, starting from
 // sol = 0. Arnoldi vectors, Gram-Schmidt (two classical passes) and the basis
@@ -989,11 +1011,18 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
       (rc = buf.alloc(&d_y, (size_t)nI * (mres + 1))) || (rc = buf.alloc(&d_sc, (size_t)nI)) ||
       (rc = buf.alloc(&d_act, (size_t)nI)))
     return rc;
-  std::vector<double> tmp(nI), bnorm(nI), hh(2 * hstride + nI);
-  std::vector<double> zero(L, 0.0);
-  std::vector<int> act(nI, 1), ones(nI, 1), kd(nI, 0);
+  // transfer buffers page-locked; the Hessenberg matrices stay uninitialised
+  // (every entry the back substitution reads is written in its cycle)
+  Pinned<double> tmp, hh;
+  Pinned<int> act, ones;
+  if ((rc = tmp.alloc(nI)) || (rc = hh.alloc(2 * hstride + nI)) || (rc = act.alloc(nI)) ||
+      (rc = ones.alloc(nI)))
+    return rc;
+  for (int k = 0; k < nI; ++k) act[k] = ones[k] = 1;
+  std::vector<double> bnorm(nI);
+  std::vector<int> kd(nI, 0);
   int n_act = nI;
-  HIPCHK(hipMemcpyAsync(d_sol, zero.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(d_sol, 0, L * sizeof(double), st));
   HIPCHK(hipMemcpyAsync(d_act, ones.data(), nI * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(launch_batched_dot(st, nI, len, d_b, 0, d_b, len, 1, d_sc));
   HIPCHK(hipMemcpyAsync(tmp.data(), d_sc, nI * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1003,8 +1032,8 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
   bool converged = false;
   int total = 0;
   std::vector<double> beta(nI), cs((size_t)nI * mres), sn((size_t)nI * mres),
-      Hm((size_t)nI * (mres + 1) * mres), gvec((size_t)nI * (mres + 1)),
-      ysol((size_t)nI * (mres + 1));
+      gvec((size_t)nI * (mres + 1)), ysol((size_t)nI * (mres + 1));
+  std::unique_ptr<double[]> Hm(new double[(size_t)nI * (mres + 1) * mres]);
   // r = b - op(sol) for every instance; converged when all meet the target
   auto true_residual = [&]() -> int {
     HIPCHK(hipMemcpyAsync(d_act, ones.data(), nI * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1033,7 +1062,6 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
     HIPCHK(hipMemcpyAsync(d_sc, tmp.data(), nI * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_act, act.data(), nI * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(launch_axpby(st, nI, len, 0.0, d_r, d_sc, d_r, d_V));  // v0 = r / beta (0 if done)
-    std::fill(Hm.begin(), Hm.end(), 0.0);
     std::fill(gvec.begin(), gvec.end(), 0.0);
     std::fill(kd.begin(), kd.end(), 0);
     for (int k = 0; k < nI; ++k) gvec[(size_t)k * (mres + 1)] = beta[k];
@@ -1069,7 +1097,7 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
           tmp[k] = 0.0;
           continue;
         }
-        double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;  // column-major (mres+1) x mres
+        double* Hk = Hm.get() + (size_t)k * (mres + 1) * mres;  // column-major (mres+1) x mres
         double* gk = gvec.data() + (size_t)k * (mres + 1);
         const double hn = std::sqrt(tmp[k]);
         double* col = Hk + (size_t)j * (mres + 1);
@@ -1110,7 +1138,7 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
     }
     std::fill(ysol.begin(), ysol.end(), 0.0);
     for (int k = 0; k < nI; ++k) {  // back substitution, then sol += V y
-      const double* Hk = Hm.data() + (size_t)k * (mres + 1) * mres;
+      const double* Hk = Hm.get() + (size_t)k * (mres + 1) * mres;
       const double* gk = gvec.data() + (size_t)k * (mres + 1);
       double* yk = ysol.data() + (size_t)k * (mres + 1);
       for (int i = kd[k] - 1; i >= 0; --i) {

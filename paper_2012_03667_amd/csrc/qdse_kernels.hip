@@ -187,20 +187,39 @@ __device__ inline void mirror_state(const SolveCtl* ctl, const SolveState* st, i
 // length is a multiple of 6), from the test statistic of sweep k-1. Every
 // block evaluates it the same way; the writer block records it and clears the
 // slot that sweep k+1 will fill.
-__device__ inline int decide(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
+// Inputs of the masked-run decision of sweep k, written only by earlier
+// launches: the status (a frozen instance stays frozen; within a launch every
+// block derives the same status from the same inputs), the sweep count of slot
+// (k-1)%3 and the statistic of sweep k-1, with the run's tolerance, iteration
+// cap and test mode. Loaded apart from decide_with so that a kernel can issue
+// these reads first and take the decision later.
+struct DecideIn {
+  int status, done, max_iter, mode;
+  double prev, tol;
+};
+__device__ inline DecideIn decide_inputs(const SolveState* st, const SolveCtl* ctl, int k) {
+  DecideIn d;
+  d.status = st->status;
+  d.done = st->sweeps_slot[(k + 2) % 3];
+  d.prev = bits_to_double(st->metric[(k + 2) % 3]);
+  d.tol = ctl->tol;
+  d.max_iter = ctl->max_iter;
+  d.mode = ctl->mode;
+  return d;
+}
+
+__device__ inline int decide_with(SolveState* st, const SolveCtl* ctl, int k, bool writer,
+                                  const DecideIn& in) {
   SolveState& S = *st;
-  // Inputs written only by earlier launches: the status (a frozen instance
-  // stays frozen; within a launch every block derives the same status from the
-  // same inputs), the sweep count of slot (k-1)%3 and the statistic of sweep k-1.
-  int status = S.status;
-  const int done = S.sweeps_slot[(k + 2) % 3];
-  const double prev = bits_to_double(S.metric[(k + 2) % 3]);
+  int status = in.status;
+  const int done = in.done;
+  const double prev = in.prev;
   if (status == 0) {
     if (done > 0) {
       if (!(prev <= 1.7976931348623157e308)) status = 3;  // NaN or inf
-      else if (prev < ctl->tol) status = 1;
+      else if (prev < in.tol) status = 1;
     }
-    if (status == 0 && done >= ctl->max_iter) status = 2;
+    if (status == 0 && done >= in.max_iter) status = 2;
   }
   if (writer && threadIdx.x == 0) {
     const unsigned long long before = S.metric[(k + 1) % 3];  // sweep k-2, cleared below
@@ -213,6 +232,10 @@ __device__ inline int decide(SolveState* st, const SolveCtl* ctl, int k, bool wr
     if (ctl->mirror && k % 6 == 0) mirror_state(ctl, st, status, now, S.resid, S.metric[(k + 2) % 3], before);
   }
   return status;
+}
+
+__device__ inline int decide(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
+  return decide_with(st, ctl, k, writer, decide_inputs(st, ctl, k));
 }
 
 // Start of a masked run: fresh per-instance states, the run's controls (when
@@ -557,6 +580,9 @@ __global__ void __launch_bounds__(256) k_sweep_row(
   // interleaves the external one), so its 4-point stencil starts at
   // clamp(j - 2, 0, n - 4), the base the grid's stencil table holds: the
   // iterate reads need no table read first.
+  // the masked-run inputs (scalar reads) go out before everything else
+  DecideIn din{};
+  if (state) din = decide_inputs(state + inst, ctl, k);
   double w[NODE_PT][4], tj[NODE_PT], xa[NODE_PT][4], xb[NODE_PT][4];
   auto node_reads = [&](int jb) {
 #pragma unroll
@@ -625,9 +651,8 @@ __global__ void __launch_bounds__(256) k_sweep_row(
     node_reads(jb);
     nodes(jb);
   }
-  // (after the node build: the deciding thread's own waits then hold up no
-  // node arithmetic)
-  const int status = state ? decide(state + inst, ctl, k, blockIdx.x == 0) : 0;
+  // (after the node build; its inputs were read at the start)
+  const int status = state ? decide_with(state + inst, ctl, k, blockIdx.x == 0, din) : 0;
   __syncthreads();
   if (status != 0) {  // frozen (the same for every wavefront): carry along
     if (!QC && lane == 0 && i < n) {
@@ -663,7 +688,7 @@ __global__ void __launch_bounds__(256) k_sweep_row(
     xo[i] = An;
     xo[n + i] = Bn;
     if (state) {
-      const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
+      const double r = test_stat(din.mode, An, Bn, Ai, Bi);
       mine = (unsigned long long)__double_as_longlong(
           isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
     }
