@@ -977,6 +977,124 @@ __global__ void __launch_bounds__(256) k_vjp_fused(int n_inst, int n, int nq, in
   }
 }
 
+// The same reverse sweep with the loop nodes of a row split between two
+// wavefronts: a workgroup holds two row chunks, wavefront h of a chunk takes
+// the lane strides u = h SH .. h SH + SH - 1 (j = lane + 64 u), so each
+// wavefront keeps half the column partials and half a row's matrix values in
+// registers (one wavefront of the one-wavefront form needs all 256 registers
+// at 513 loop nodes and runs alone on its SIMD). Each half's row sums go to
+// LDS and are added half 0 + half 1 after the chunk; the column partials are
+// those of the one-wavefront form.
+template <int SH>
+__global__ void __launch_bounds__(256) k_vjp_split(int n_inst, int n, int nq, int ldk, int nchunk,
+                                                   int rmax, const InstDev* __restrict__ inst_,
+                                                   const double* __restrict__ K, size_t kstride,
+                                                   const double* __restrict__ s_,
+                                                   const double* __restrict__ t_,
+                                                   const double* __restrict__ nodes,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ out,
+                                                   double* __restrict__ part,
+                                                   const int* __restrict__ act) {
+  extern __shared__ double ndl[];  // [5][ldk]: A, B, sigma_V, sigma_S, t; then row sums
+  const int inst = blockIdx.y;
+  if (act && !act[inst]) return;  // the whole workgroup: before the barriers
+  const double* nd = nodes + (size_t)inst * 5 * ldk;
+  for (int j = threadIdx.x; j < nq; j += blockDim.x) {
+    ndl[j] = nd[j];
+    ndl[ldk + j] = nd[ldk + j];
+    ndl[2 * ldk + j] = nd[2 * ldk + j];
+    ndl[3 * ldk + j] = nd[3 * ldk + j];
+    ndl[4 * ldk + j] = t_[j];
+  }
+  __syncthreads();
+  double* rs = ndl + 5 * ldk;  // [chunk in block 2][half 2][A, B][rmax]
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const int cl = wave >> 1, h = wave & 1;
+  const int chunk = blockIdx.x * 2 + cl;
+  const InstDev P = inst_[inst];
+  const size_t mat = (size_t)n * ldk;
+  const double* Kb = K + (size_t)P.kblock * kstride;
+  const double* xi = x + (size_t)inst * 2 * n;
+  const double* wi = w + (size_t)inst * 2 * n;
+  double* oi = out + (size_t)inst * 2 * n;
+  if (chunk < nchunk) {
+    const int r0 = (int)((long)n * chunk / nchunk), r1 = (int)((long)n * (chunk + 1) / nchunk);
+    double* rA = rs + ((cl * 2 + h) * 2 + 0) * rmax;
+    double* rB = rs + ((cl * 2 + h) * 2 + 1) * rmax;
+    double cA[SH], cB[SH], cV[SH], cS[SH];
+#pragma unroll
+    for (int u = 0; u < SH; ++u) cA[u] = cB[u] = cV[u] = cS[u] = 0.0;
+#pragma unroll 1
+    for (int i = r0; i < r1; ++i) {
+      // node values are read from LDS for every row (a compiler-only barrier
+      // keeps them out of registers across rows)
+      asm volatile("" ::: "memory");
+      const double s = s_[i], Ai = xi[i], Bi = xi[n + i];
+      const double ab = P.pref * wi[i], bb = P.pref * wi[n + i];
+      const double* Ki = Kb + (size_t)i * ldk;
+      double gA = 0.0, gB = 0.0;
+      double kTs[SH], k3s[SH], k0s[SH];
+#pragma unroll
+      for (int u = 0; u < SH; ++u) {
+        const int j = lane + WAVE * (h * SH + u);
+        const int jj = j < nq ? j : nq - 1;
+        kTs[u] = Ki[jj];
+        k3s[u] = Ki[mat + jj];
+        k0s[u] = Ki[2 * mat + jj];
+        if (j >= nq) kTs[u] = k3s[u] = k0s[u] = 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < SH; ++u) {
+        const int j = lane + WAVE * (h * SH + u);
+        const int jj = j < nq ? j : nq - 1;
+        const double kT = kTs[u], k3 = k3s[u], k0 = k0s[u];
+        const double Aq = ndl[jj], Bq = ndl[ldk + jj], sV = ndl[2 * ldk + jj],
+                     sS = ndl[3 * ldk + jj], t = ndl[4 * ldk + jj];
+        const double dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
+        const double gdA = kT * (2.0 * s * bb * sS - ab * (s + t) * sV);
+        const double gsA = ab * k3 * sV + bb * k0 * sS;
+        const double gdB = -2.0 * kT * (ab * sS + s * bb * sV);
+        gA += gsA - gdA;
+        gB -= gdB;
+        cA[u] += gdA + gsA;
+        cB[u] += gdB;
+        cS[u] += kT * (2.0 * s * bb * dA - 2.0 * ab * dB) + bb * k0 * sA;
+        cV[u] += ab * k3 * sA - kT * (ab * (s + t) * dA + 2.0 * s * bb * dB);
+      }
+      gA = wave_sum(gA);
+      gB = wave_sum(gB);
+      if (lane == 0) {
+        rA[i - r0] = gA;
+        rB[i - r0] = gB;
+      }
+    }
+    double* o = part + (((size_t)inst * nchunk + chunk) * 4) * ldk;
+#pragma unroll
+    for (int u = 0; u < SH; ++u) {
+      const int j = lane + WAVE * (h * SH + u);
+      if (j < nq) {
+        o[j] = cA[u];
+        o[ldk + j] = cB[u];
+        o[2 * ldk + j] = cV[u];
+        o[3 * ldk + j] = cS[u];
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 2 * rmax; q += blockDim.x) {
+    const int c2 = q / rmax, rr = q % rmax, ch = blockIdx.x * 2 + c2;
+    if (ch >= nchunk) continue;
+    const int r0 = (int)((long)n * ch / nchunk), r1 = (int)((long)n * (ch + 1) / nchunk);
+    if (rr >= r1 - r0) continue;
+    const double* h0 = rs + (c2 * 2 + 0) * 2 * rmax;
+    const double* h1 = rs + (c2 * 2 + 1) * 2 * rmax;
+    oi[r0 + rr] = h0[rr] + h1[rr];
+    oi[n + r0 + rr] = h0[rmax + rr] + h1[rmax + rr];
+  }
+}
+
 // Sum the row chunks in a fixed order and push the adjoints of sigma_V,
 // sigma_S through sigma = (A or B)/Delta, Delta = t A^2 + B^2: adjoints of
 // A(t_j), B(t_j) into gq[inst][2][ldk].
@@ -1209,15 +1327,18 @@ hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const 
   const int slots = (nq + WAVE - 1) / WAVE;
   const dim3 fgrid((nchunk + 3) / 4, n_inst);
   const size_t flds = (size_t)5 * ldk * sizeof(double);
+  const int rmax = (n + nchunk - 1) / nchunk;
+  const dim3 sgrid((nchunk + 1) / 2, n_inst);
+  const size_t slds = ((size_t)5 * ldk + 8 * (size_t)rmax) * sizeof(double);
   if (slots <= 4) {
     hipLaunchKernelGGL(k_vjp_fused<4>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
                        inst, K, kstride, s, t, nodes, x, w, out, part, act);
-  } else if (slots <= 9) {
-    hipLaunchKernelGGL(k_vjp_fused<9>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
-                       inst, K, kstride, s, t, nodes, x, w, out, part, act);
-  } else if (slots <= 17) {
-    hipLaunchKernelGGL(k_vjp_fused<17>, fgrid, dim3(256), flds, st, n_inst, n, nq, ldk, nchunk,
-                       inst, K, kstride, s, t, nodes, x, w, out, part, act);
+  } else if (slots <= 10) {
+    hipLaunchKernelGGL(k_vjp_split<5>, sgrid, dim3(256), slds, st, n_inst, n, nq, ldk, nchunk,
+                       rmax, inst, K, kstride, s, t, nodes, x, w, out, part, act);
+  } else if (slots <= 18) {
+    hipLaunchKernelGGL(k_vjp_split<9>, sgrid, dim3(256), slds, st, n_inst, n, nq, ldk, nchunk,
+                       rmax, inst, K, kstride, s, t, nodes, x, w, out, part, act);
   } else {  // large grids: row and column parts as two passes
     const long rows = (long)n_inst * n;
     hipLaunchKernelGGL(k_vjp_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n_inst, n,
