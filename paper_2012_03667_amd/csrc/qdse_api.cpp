@@ -1168,7 +1168,7 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
 // instance as I - band(J)^T. Device buffers live as long as the object.
 struct BandPrec {
   DevBufs buf;
-  double *d_D = nullptr, *d_Jb = nullptr, *d_F = nullptr, *d_T = nullptr;
+  double *d_D = nullptr, *d_Jb = nullptr, *d_F = nullptr;
   int* d_ok = nullptr;
   int build(qdse_ctx* c, const double* d_x) {
     const HostGrid& g = c->hg;
@@ -1177,7 +1177,7 @@ struct BandPrec {
     if ((rc = buf.alloc(&d_D, (size_t)nI * g.n * 4)) ||
         (rc = buf.alloc(&d_Jb, (size_t)nI * g.n * wb * 4)) ||
         (rc = buf.alloc(&d_F, (size_t)nI * 2 * g.n * (2 * (2 * kPrecBand + 1) + 1))) ||
-        (rc = buf.alloc(&d_ok, (size_t)nI)) || (rc = buf.alloc(&d_T, xlen(c))))
+        (rc = buf.alloc(&d_ok, (size_t)nI)))
       return rc;
     HIPCHK(launch_nodes_only(c->stream, nI, g.n, g.nq, g.ldk, c->d_lo, c->d_sw, c->d_t, d_x,
                              c->d_nodes));
@@ -1187,7 +1187,7 @@ struct BandPrec {
     return QDSE_OK;
   }
   int apply(qdse_ctx* c, const double* in, double* out, const int* d_act) {
-    HIPCHK(launch_band_solve(c->stream, c->n_inst, c->hg.n, d_F, d_ok, d_act, in, out, d_T));
+    HIPCHK(launch_band_solve(c->stream, c->n_inst, c->hg.n, d_F, d_ok, d_act, in, out));
     return QDSE_OK;
   }
 };

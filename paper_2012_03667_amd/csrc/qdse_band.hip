@@ -136,10 +136,10 @@ __global__ void k_jband(int n_inst, int n, int nq, int ldk, int bw, const InstDe
 // M = I - band(J)^T with the unknowns interleaved, r = 2 l + b (b = 0: A, 1: B):
 // M[2l+b][2i+a] = delta - J[(a,i),(b,l)], |i - l| <= BW, so |r - c| <= HB =
 // 2 BW + 1. LU without pivoting, one thread per instance, the HB + 1 active
-// rows of the band held in registers; factor rows [r][2 HB + 1][inst] (unit
-// lower multipliers left of the diagonal, U from it). ok[inst] = 0 when a
-// pivot is not safely away from zero (the solve then leaves that instance
-// unpreconditioned).
+// rows of the band held in registers; factor rows [inst][r][2 HB + 1] (unit
+// lower multipliers left of the diagonal, the reciprocal of U's diagonal at
+// offset HB, U's other entries right of it). ok[inst] = 0 when a pivot is not
+// safely away from zero (the solve then leaves that instance unpreconditioned).
 template <int BW>
 __global__ void __launch_bounds__(64) k_band_lu(int n_inst, int n, const double* __restrict__ Jb,
                                                 double* __restrict__ F, int* __restrict__ ok) {
@@ -198,7 +198,8 @@ __global__ void __launch_bounds__(64) k_band_lu(int n_inst, int n, const double*
           R[q][HB - q + cc] = fma(-f, R[0][HB + cc], R[q][HB - q + cc]);
       }
 #pragma unroll
-      for (int d = 0; d < W; ++d) F[((size_t)k * W + d) * n_inst + inst] = R[0][d];
+      for (int d = 0; d < W; ++d)
+        F[((size_t)inst * N + k) * W + d] = d == HB ? ip : R[0][d];
 #pragma unroll
       for (int q = 0; q < HB; ++q)
 #pragma unroll
@@ -210,119 +211,101 @@ __global__ void __launch_bounds__(64) k_band_lu(int n_inst, int n, const double*
   ok[inst] = good;
 }
 
-// [inst][A | B] <-> interleaved, instance-minor T[r][inst] (r = 2 l + b), so
-// that the per-instance solves below read and write coalesced.
-__global__ void k_to_minor(int n_inst, int n, const int* __restrict__ act,
-                           const double* __restrict__ in, double* __restrict__ T) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)n_inst * 2 * n) return;
-  const int inst = (int)(e % n_inst), r = (int)(e / n_inst);
-  if (act && !act[inst]) return;
-  T[e] = in[(size_t)inst * 2 * n + (r & 1) * n + (r >> 1)];
-}
-__global__ void k_from_minor(int n_inst, int n, const int* __restrict__ act,
-                             const double* __restrict__ T, double* __restrict__ out) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)n_inst * 2 * n) return;
-  const int inst = (int)(e % n_inst), r = (int)(e / n_inst);
-  if (act && !act[inst]) return;
-  out[(size_t)inst * 2 * n + (r & 1) * n + (r >> 1)] = T[e];
-}
-
-// T = M^{-1} T in place for every active instance (act may be null), one
-// thread per instance: forward substitution with the unit lower factor, then
-// backward with the upper one, keeping the last HB solution values in
-// registers. The loads of the next SOLVE_U steps are issued before the
-// arithmetic of the current ones (two register buffers), so one step waits
-// for its data only once per SOLVE_U steps. Instances with ok == 0 are left
-// unchanged (no preconditioning).
-constexpr int SOLVE_U = 8;
+// out = M^{-1} in for every active instance (act may be null), one wavefront
+// per instance. Forward substitution with the unit lower factor, then
+// backward with the upper one, 64 rows at a time: lane l reads row c0 + l
+// (its factor values and right-hand side) while the previous 64 rows are
+// being solved, the rows go to LDS, and every lane then runs the 64
+// sequential steps from LDS (the same values in every lane; lane u keeps the
+// solution of step u and writes it). In each step the terms of the older
+// solution values are added first, so a step waits on the previous one for a
+// single FMA. Instances with ok == 0 get out = in.
 template <int BW>
 __global__ void __launch_bounds__(64) k_band_solve(int n_inst, int n, const double* __restrict__ F,
                                                    const int* __restrict__ ok,
                                                    const int* __restrict__ act,
-                                                   double* __restrict__ T) {
-  constexpr int HB = 2 * BW + 1, W = 2 * HB + 1;
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= n_inst || (act && !act[inst]) || !ok[inst]) return;
+                                                   const double* __restrict__ in,
+                                                   double* __restrict__ out) {
+  constexpr int HB = 2 * BW + 1, W = 2 * HB + 1, NV = HB + 2;
+  __shared__ double buf[WAVE][NV];
+  const int inst = blockIdx.x;
+  if (act && !act[inst]) return;  // the whole workgroup (one wavefront)
+  const int lane = threadIdx.x;
   const int N = 2 * n;
-  auto Fat = [&](int r, int d) { return F[((size_t)r * W + d) * n_inst + inst]; };
-  auto Tat = [&](int r) -> double& { return T[(size_t)r * n_inst + inst]; };
-  double y[HB];
-  // forward: y[q] = solution at r - 1 - q
-  {
-    double fa[SOLVE_U][HB], va[SOLVE_U], fb[SOLVE_U][HB], vb[SOLVE_U];
-    auto load = [&](int r0, double (*f)[HB], double* v) {
-#pragma unroll
-      for (int u = 0; u < SOLVE_U; ++u) {
-        const int r = min(r0 + u, N - 1);
-        v[u] = Tat(r);
-#pragma unroll
-        for (int q = 1; q <= HB; ++q) f[u][q - 1] = Fat(r, HB - q);
-      }
-    };
-    auto step = [&](int r0, double (*f)[HB], double* v) {
-#pragma unroll
-      for (int u = 0; u < SOLVE_U; ++u) {
-        if (r0 + u >= N) break;
-        double x = v[u];
-#pragma unroll
-        for (int q = 1; q <= HB; ++q) x = fma(-f[u][q - 1], y[q - 1], x);
-#pragma unroll
-        for (int q = HB - 1; q > 0; --q) y[q] = y[q - 1];
-        y[0] = x;
-        Tat(r0 + u) = x;
-      }
-    };
-#pragma unroll
-    for (int q = 0; q < HB; ++q) y[q] = 0.0;
-    load(0, fa, va);
-    for (int r0 = 0; r0 < N; r0 += 2 * SOLVE_U) {
-      load(r0 + SOLVE_U, fb, vb);  // (rows past the end are clamped reads)
-      __builtin_amdgcn_sched_barrier(0);
-      step(r0, fa, va);
-      load(r0 + 2 * SOLVE_U, fa, va);
-      __builtin_amdgcn_sched_barrier(0);
-      step(r0 + SOLVE_U, fb, vb);
-    }
+  const double* Fi = F + (size_t)inst * N * W;
+  const double* vi = in + (size_t)inst * N;
+  double* xo = out + (size_t)inst * N;
+  auto at = [&](int r) { return (r & 1) * n + (r >> 1); };  // interleaved -> [A | B]
+  if (!ok[inst]) {
+    for (int r = lane; r < N; r += WAVE) xo[r] = vi[r];
+    return;
   }
-  // backward: y[q] = solution at r + 1 + q
-  {
-    double fa[SOLVE_U][HB + 1], va[SOLVE_U], fb[SOLVE_U][HB + 1], vb[SOLVE_U];
-    auto load = [&](int r0, double (*f)[HB + 1], double* v) {
+  double y[HB], pf[NV];
+  // forward: row r: pf[q - 1] = L[r][r - q] (q = 1..HB), pf[HB] = in[r]
+  auto fetch_f = [&](int c0) {
+    const int r = c0 + lane;
+    if (r < N) {
 #pragma unroll
-      for (int u = 0; u < SOLVE_U; ++u) {
-        const int r = max(r0 - u, 0);
-        v[u] = Tat(r);
-#pragma unroll
-        for (int q = 0; q <= HB; ++q) f[u][q] = Fat(r, HB + q);
-      }
-    };
-    auto step = [&](int r0, double (*f)[HB + 1], double* v) {
-#pragma unroll
-      for (int u = 0; u < SOLVE_U; ++u) {
-        if (r0 - u < 0) break;
-        double x = v[u];
-#pragma unroll
-        for (int q = 1; q <= HB; ++q) x = fma(-f[u][q], y[q - 1], x);
-        x /= f[u][0];
-#pragma unroll
-        for (int q = HB - 1; q > 0; --q) y[q] = y[q - 1];
-        y[0] = x;
-        Tat(r0 - u) = x;
-      }
-    };
-#pragma unroll
-    for (int q = 0; q < HB; ++q) y[q] = 0.0;
-    load(N - 1, fa, va);
-    for (int r0 = N - 1; r0 >= 0; r0 -= 2 * SOLVE_U) {
-      load(r0 - SOLVE_U, fb, vb);
-      __builtin_amdgcn_sched_barrier(0);
-      step(r0, fa, va);
-      load(r0 - 2 * SOLVE_U, fa, va);
-      __builtin_amdgcn_sched_barrier(0);
-      step(r0 - SOLVE_U, fb, vb);
+      for (int q = 1; q <= HB; ++q) pf[q - 1] = Fi[(size_t)r * W + HB - q];
+      pf[HB] = vi[at(r)];
     }
+  };
+#pragma unroll
+  for (int q = 0; q < HB; ++q) y[q] = 0.0;  // y[q]: solution at r - 1 - q
+  fetch_f(0);
+  for (int c0 = 0; c0 < N; c0 += WAVE) {
+#pragma unroll
+    for (int k = 0; k < HB + 1; ++k) buf[lane][k] = pf[k];
+    __syncthreads();
+    fetch_f(c0 + WAVE);  // the next rows' reads overlap this chunk's steps
+    const int cnt = min(WAVE, N - c0);
+    double xv = 0.0;
+#pragma unroll 8
+    for (int u = 0; u < cnt; ++u) {
+      double x = buf[u][HB];
+#pragma unroll
+      for (int q = HB; q >= 1; --q) x = fma(-buf[u][q - 1], y[q - 1], x);
+#pragma unroll
+      for (int q = HB - 1; q > 0; --q) y[q] = y[q - 1];
+      y[0] = x;
+      xv = lane == u ? x : xv;
+    }
+    if (lane < cnt) xo[at(c0 + lane)] = xv;
+    __syncthreads();
+  }
+  // backward: row r: pf[q - 1] = U[r][r + q] (q = 1..HB), pf[HB] = 1/U[r][r],
+  // pf[HB + 1] = forward solution at r
+  auto fetch_b = [&](int c0) {
+    const int r = c0 - lane;
+    if (r >= 0) {
+#pragma unroll
+      for (int q = 0; q <= HB; ++q) pf[q == 0 ? HB : q - 1] = Fi[(size_t)r * W + HB + q];
+      pf[HB + 1] = xo[at(r)];
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < HB; ++q) y[q] = 0.0;  // y[q]: solution at r + 1 + q
+  fetch_b(N - 1);
+  for (int c0 = N - 1; c0 >= 0; c0 -= WAVE) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) buf[lane][k] = pf[k];
+    __syncthreads();
+    fetch_b(c0 - WAVE);
+    const int cnt = min(WAVE, c0 + 1);
+    double xv = 0.0;
+#pragma unroll 8
+    for (int u = 0; u < cnt; ++u) {
+      double x = buf[u][HB + 1];
+#pragma unroll
+      for (int q = HB; q >= 1; --q) x = fma(-buf[u][q - 1], y[q - 1], x);
+      x *= buf[u][HB];
+#pragma unroll
+      for (int q = HB - 1; q > 0; --q) y[q] = y[q - 1];
+      y[0] = x;
+      xv = lane == u ? x : xv;
+    }
+    if (lane < cnt) xo[at(c0 - lane)] = xv;
+    __syncthreads();
   }
 }
 
@@ -348,13 +331,9 @@ hipError_t launch_band_lu(hipStream_t st, int n_inst, int n, const double* Jb, d
 }
 
 hipError_t launch_band_solve(hipStream_t st, int n_inst, int n, const double* F, const int* ok,
-                             const int* act, const double* in, double* out, double* T) {
-  const long tot = (long)n_inst * 2 * n;
-  const dim3 eg((unsigned)((tot + 255) / 256));
-  hipLaunchKernelGGL(k_to_minor, eg, dim3(256), 0, st, n_inst, n, act, in, T);
-  hipLaunchKernelGGL(k_band_solve<kPrecBand>, dim3((n_inst + 63) / 64), dim3(64), 0, st, n_inst, n,
-                     F, ok, act, T);
-  hipLaunchKernelGGL(k_from_minor, eg, dim3(256), 0, st, n_inst, n, act, T, out);
+                             const int* act, const double* in, double* out) {
+  hipLaunchKernelGGL(k_band_solve<kPrecBand>, dim3(n_inst), dim3(64), 0, st, n_inst, n, F, ok, act,
+                     in, out);
   return hipGetLastError();
 }
 

@@ -167,13 +167,13 @@ hipError_t launch_jband(hipStream_t st, int n_inst, int n, int nq, int ldk, int 
                         const double* x, double* D, double* out, int minor);
 // Banded preconditioner of the adjoint solve: band half-width kPrecBand nodes.
 // launch_band_lu factors M = I - band(J)^T per instance from the
-// instance-minor band (F: [2n][4 kPrecBand + 3][n_inst]; ok[inst] = 0 if a
-// pivot was unsafe); launch_band_solve applies M^{-1} (act may be null; T is
-// n_inst * 2n doubles of workspace).
+// instance-minor band (F: [n_inst][2n][4 kPrecBand + 3]; ok[inst] = 0 if a
+// pivot was unsafe); launch_band_solve applies M^{-1} (act may be null; in
+// and out distinct).
 constexpr int kPrecBand = 2;
 hipError_t launch_band_lu(hipStream_t st, int n_inst, int n, const double* Jb, double* F, int* ok);
 hipError_t launch_band_solve(hipStream_t st, int n_inst, int n, const double* F, const int* ok,
-                             const int* act, const double* in, double* out, double* T);
+                             const int* act, const double* in, double* out);
 // out[inst][:] = beta * out[inst][:] + sum_v y[inst * ystride + v] V[v][inst][:]
 hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
                           int nvec, const double* y, int ystride, double beta, double* out);
