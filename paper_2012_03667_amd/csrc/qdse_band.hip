@@ -135,25 +135,29 @@ __global__ void k_jband(int n_inst, int n, int nq, int ldk, int bw, const InstDe
 
 // M = I - band(J)^T with the unknowns interleaved, r = 2 l + b (b = 0: A, 1: B):
 // M[2l+b][2i+a] = delta - J[(a,i),(b,l)], |i - l| <= BW, so |r - c| <= HB =
-// 2 BW + 1. LU without pivoting, one thread per instance, the HB + 1 active
-// rows of the band held in registers; factor rows [inst][r][2 HB + 1] (unit
-// lower multipliers left of the diagonal, the reciprocal of U's diagonal at
-// offset HB, U's other entries right of it). ok[inst] = 0 when a pivot is not
-// safely away from zero (the solve then leaves that instance unpreconditioned).
+// 2 BW + 1. LU without pivoting, one wavefront per instance: the HB + 1
+// active rows of the band sit in registers (the same values in every lane),
+// the rows entering the window over the next 64 steps are assembled from the
+// band by the 64 lanes (one row each) into LDS while the current 64 steps
+// run, and lane u keeps factor row k0 + u to write it. Factor rows
+// [inst][r][2 HB + 1]: unit lower multipliers left of the diagonal, the
+// reciprocal of U's diagonal at offset HB, U's other entries right of it.
+// ok[inst] = 0 when a pivot is not safely away from zero (the solve then
+// leaves that instance unpreconditioned).
 template <int BW>
 __global__ void __launch_bounds__(64) k_band_lu(int n_inst, int n, const double* __restrict__ Jb,
                                                 double* __restrict__ F, int* __restrict__ ok) {
   constexpr int HB = 2 * BW + 1, W = 2 * HB + 1, WB = 2 * BW + 1;
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= n_inst) return;
+  __shared__ double rows[WAVE][W];
+  const int inst = blockIdx.x;
+  const int lane = threadIdx.x;
   const int N = 2 * n;
-  // row r of M, entries at offsets d = c - r + HB
+  // row r of M, entries at offsets d = c - r + HB (rows past the end: identity)
   auto load_row = [&](int r, double* R) {
 #pragma unroll
     for (int d = 0; d < W; ++d) R[d] = 0.0;
     if (r >= N) {
-#pragma unroll
-      for (int d = 0; d < W; ++d) R[d] = d == HB ? 1.0 : 0.0;
+      R[HB] = 1.0;
       return;
     }
 #pragma unroll
@@ -171,18 +175,17 @@ __global__ void __launch_bounds__(64) k_band_lu(int n_inst, int n, const double*
   double R[HB + 1][W];
 #pragma unroll
   for (int q = 0; q <= HB; ++q) load_row(q, R[q]);
+  double nxt[W], keep[W];
+  load_row(HB + 1 + lane, nxt);  // rows entering at steps 0 .. 63
   int good = 1;
-  // the rows entering the window over the next LU_PF steps are loaded
-  // together, so the wait for a row's data falls once per LU_PF steps
-  constexpr int LU_PF = 8;
-  for (int k0 = 0; k0 < N; k0 += LU_PF) {
-    double P[LU_PF][W];
+  double* Fi = F + (size_t)inst * N * W;
+  for (int k0 = 0; k0 < N; k0 += WAVE) {
 #pragma unroll
-    for (int p = 0; p < LU_PF; ++p) load_row(k0 + HB + 1 + p, P[p]);
-#pragma unroll
-    for (int p = 0; p < LU_PF; ++p) {
-      const int k = k0 + p;
-      if (k >= N) break;
+    for (int d = 0; d < W; ++d) rows[lane][d] = nxt[d];
+    __syncthreads();
+    load_row(k0 + WAVE + HB + 1 + lane, nxt);  // overlaps this chunk's steps
+    const int cnt = min(WAVE, N - k0);
+    for (int u = 0; u < cnt; ++u) {
       const double piv = R[0][HB];
       double scale = 0.0;
 #pragma unroll
@@ -198,17 +201,21 @@ __global__ void __launch_bounds__(64) k_band_lu(int n_inst, int n, const double*
           R[q][HB - q + cc] = fma(-f, R[0][HB + cc], R[q][HB - q + cc]);
       }
 #pragma unroll
-      for (int d = 0; d < W; ++d)
-        F[((size_t)inst * N + k) * W + d] = d == HB ? ip : R[0][d];
+      for (int d = 0; d < W; ++d) keep[d] = lane == u ? (d == HB ? ip : R[0][d]) : keep[d];
 #pragma unroll
       for (int q = 0; q < HB; ++q)
 #pragma unroll
         for (int d = 0; d < W; ++d) R[q][d] = R[q + 1][d];
 #pragma unroll
-      for (int d = 0; d < W; ++d) R[HB][d] = P[p][d];
+      for (int d = 0; d < W; ++d) R[HB][d] = rows[u][d];
     }
+    if (lane < cnt) {
+#pragma unroll
+      for (int d = 0; d < W; ++d) Fi[(size_t)(k0 + lane) * W + d] = keep[d];
+    }
+    __syncthreads();
   }
-  ok[inst] = good;
+  if (lane == 0) ok[inst] = good;
 }
 
 // out = M^{-1} in for every active instance (act may be null), one wavefront
@@ -325,8 +332,7 @@ hipError_t launch_jband(hipStream_t st, int n_inst, int n, int nq, int ldk, int 
 }
 
 hipError_t launch_band_lu(hipStream_t st, int n_inst, int n, const double* Jb, double* F, int* ok) {
-  const dim3 grid((n_inst + 63) / 64);
-  hipLaunchKernelGGL(k_band_lu<kPrecBand>, grid, dim3(64), 0, st, n_inst, n, Jb, F, ok);
+  hipLaunchKernelGGL(k_band_lu<kPrecBand>, dim3(n_inst), dim3(64), 0, st, n_inst, n, Jb, F, ok);
   return hipGetLastError();
 }
 
