@@ -376,15 +376,17 @@ __device__ inline void row_term(double kT, double k3, double k0, double Aq, doub
 }
 
 // Lane sums of the FP64 hot sweep over j = j0, j0 + 64, ... < nq.
+template <int U = 6>
 __device__ inline void row_stream_f64(int j0, int nq, int ldk, size_t mat,
                                       const double* __restrict__ Ki, const double* __restrict__ nd,
                                       double s, double Ai, double Bi, double& a0, double& a1,
                                       double& a2, double& a3) {
   // Loads of U consecutive lane strides are issued before any arithmetic so
   // that a wavefront has ~8 U loads in flight; the accumulation order per lane
-  // is still j = j0, j0 + 64, ... . U = 6 (two load rounds per row at
-  // 513 loop nodes) measured fastest among 4, 5, 6, 8.
-  constexpr int U = 6;
+  // is still j = j0, j0 + 64, ... whatever U. U = 6 (two load rounds per row
+  // at 513 loop nodes) measured fastest among 4, 5, 6, 8 for small batches;
+  // the many-workgroup large-batch sweep prefers U = 2 (more resident
+  // wavefronts).
   for (int jb = j0; jb < nq; jb += U * WAVE) {
     double kT[U], k3[U], k0[U], Aq[U], Bq[U], sV[U], sS[U], tsV[U];
 #pragma unroll
@@ -410,11 +412,12 @@ __device__ inline void row_stream_f64(int j0, int nq, int ldk, size_t mat,
 }
 
 // Specialised FP64 body for the hot sweep: lane sums, then wave sums.
+template <int U = 6>
 __device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const double* __restrict__ Ki,
                                           const double* __restrict__ nd, double s, double Ai,
                                           double Bi, int lane, double acc[4]) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  row_stream_f64(lane, nq, ldk, mat, Ki, nd, s, Ai, Bi, a0, a1, a2, a3);
+  row_stream_f64<U>(lane, nq, ldk, mat, Ki, nd, s, Ai, Bi, a0, a1, a2, a3);
   acc[0] = wave_sum(a0);
   acc[1] = wave_sum(a1);
   acc[2] = wave_sum(a2);
@@ -518,7 +521,7 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
     const double s = s_[i];
     const double Ai = xi[i], Bi = xi[n + i];
     double acc[4];
-    row_accumulate_f64(nq, ldk, mat, Ki, nd, s, Ai, Bi, lane, acc);
+    row_accumulate_f64<2>(nq, ldk, mat, Ki, nd, s, Ai, Bi, lane, acc);
     if (lane == 0) {
       const double An = (add_f0 ? 1.0 : 0.0) + P.pref * (acc[1] - acc[0]);
       const double Bn = (add_f0 ? P.m : 0.0) + P.pref * fma(2.0 * s, acc[2], acc[3]);
