@@ -644,8 +644,8 @@ static long predict_total(MaskedRun& r) {
     if (h.status != 0) continue;
     const int s = h.sweeps;
     double r1, r0;
-    std::memcpy(&r1, &h.metric[0], sizeof(double));
-    std::memcpy(&r0, &h.metric[1], sizeof(double));
+    std::memcpy(&r1, &h.metric[0][0], sizeof(double));
+    std::memcpy(&r0, &h.metric[1][0], sizeof(double));
     double rho = -1.0;
     if (s >= 2 && r.r_prev[q] > 0.0 && s > r.s_prev[q])
       rho = std::pow(r1 / r.r_prev[q], 1.0 / (double)(s - r.s_prev[q]));

@@ -48,6 +48,7 @@ struct InstDev {
 };
 
 // Per-instance state of a masked run (device).
+constexpr int kMetricLanes = 8;
 struct SolveState {
   int status;                   // 0 running, 1 converged, 2 max_iter, 3 non-finite
   int sweeps;                   // sweeps done while running (for the host)
@@ -56,8 +57,13 @@ struct SolveState {
                                 // launch sees a value written in that launch
   int pad;
   double resid;                 // test statistic of the deciding sweep
-  unsigned long long metric[3]; // bits of the non-negative max over rows; sweep k uses
-                                // slot k%3, reads slot (k-1)%3, clears slot (k+1)%3
+  // bits of the non-negative max over rows; sweep k uses slot k%3, reads slot
+  // (k-1)%3, clears slot (k+1)%3. Each slot has kMetricLanes words that
+  // different workgroups fold into with atomic max (workgroup w into lane
+  // w % kMetricLanes: one word for every workgroup of an instance serialises
+  // their atomics) and that readers reduce with max. In the host mirror,
+  // metric[0][0] and metric[1][0] hold the reduced statistics.
+  unsigned long long metric[3][kMetricLanes];
 };
 
 // Controls of a masked successive-approximation run (device copy).

@@ -172,6 +172,14 @@ __global__ void k_precompute(int n, int nq, int na, int ldk, const double* __res
 // ---------------------------------------------------------------- masked runs
 __device__ inline double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+// The statistic of one sweep slot: the max over its lanes.
+__device__ inline unsigned long long metric_max(const SolveState* st, int slot) {
+  unsigned long long m = st->metric[slot][0];
+#pragma unroll
+  for (int l = 1; l < kMetricLanes; ++l) m = st->metric[slot][l] > m ? st->metric[slot][l] : m;
+  return m;
+}
+
 __device__ inline void mirror_state(const SolveCtl* ctl, const SolveState* st, int status, int now,
                                     double resid, unsigned long long last,
                                     unsigned long long before) {
@@ -179,8 +187,8 @@ __device__ inline void mirror_state(const SolveCtl* ctl, const SolveState* st, i
   m->status = status;
   m->sweeps = now;
   m->resid = resid;
-  m->metric[0] = last;
-  m->metric[1] = before;
+  m->metric[0][0] = last;
+  m->metric[1][0] = before;
 }
 
 // Status of an instance at the start of sweep k (1-based within a chunk whose
@@ -201,7 +209,7 @@ __device__ inline DecideIn decide_inputs(const SolveState* st, const SolveCtl* c
   DecideIn d;
   d.status = st->status;
   d.done = st->sweeps_slot[(k + 2) % 3];
-  d.prev = bits_to_double(st->metric[(k + 2) % 3]);
+  d.prev = bits_to_double(metric_max(st, (k + 2) % 3));
   d.tol = ctl->tol;
   d.max_iter = ctl->max_iter;
   d.mode = ctl->mode;
@@ -222,14 +230,16 @@ __device__ inline int decide_with(SolveState* st, const SolveCtl* ctl, int k, bo
     if (status == 0 && done >= in.max_iter) status = 2;
   }
   if (writer && threadIdx.x == 0) {
-    const unsigned long long before = S.metric[(k + 1) % 3];  // sweep k-2, cleared below
+    const unsigned long long before = metric_max(&S, (k + 1) % 3);  // sweep k-2, cleared below
     if (status != 0 && S.status == 0) S.resid = prev;
     S.status = status;
     const int now = done + (status == 0 ? 1 : 0);
     S.sweeps_slot[k % 3] = now;
     S.sweeps = now;
-    S.metric[(k + 1) % 3] = 0ull;
-    if (ctl->mirror && k % 6 == 0) mirror_state(ctl, st, status, now, S.resid, S.metric[(k + 2) % 3], before);
+#pragma unroll
+    for (int l = 0; l < kMetricLanes; ++l) S.metric[(k + 1) % 3][l] = 0ull;
+    if (ctl->mirror && k % 6 == 0)
+      mirror_state(ctl, st, status, now, S.resid, metric_max(&S, (k + 2) % 3), before);
   }
   return status;
 }
@@ -254,9 +264,11 @@ __global__ void k_solve_init(int n_inst, SolveState* st, SolveCtl* ctl, SolveCtl
   st[k].sweeps = 0;
   st[k].sweeps_slot[0] = st[k].sweeps_slot[1] = st[k].sweeps_slot[2] = 0;
   st[k].resid = __longlong_as_double(0x7ff0000000000000ll);
-  st[k].metric[0] = 0x7ff0000000000000ull;  // +inf: no sweep yet
-  st[k].metric[1] = 0ull;                   // filled by sweep 1
-  st[k].metric[2] = 0ull;
+  for (int l = 0; l < kMetricLanes; ++l) {
+    st[k].metric[0][l] = 0x7ff0000000000000ull;  // +inf: no sweep yet
+    st[k].metric[1][l] = 0ull;                   // filled by sweep 1
+    st[k].metric[2][l] = 0ull;
+  }
 }
 
 // ---------------------------------------------------------------- node functions
@@ -468,7 +480,7 @@ __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ld
     if (state) {
       const double r = test_stat(ctl->mode, An, Bn, Ai, Bi);
       const unsigned long long bits = (unsigned long long)__double_as_longlong(isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
-      atomicMax(&state[inst].metric[k % 3], bits);
+      atomicMax(&state[inst].metric[k % 3][blockIdx.x % kMetricLanes], bits);
     }
   }
 }
@@ -541,7 +553,7 @@ __global__ void __launch_bounds__(256) k_sweep_fused(
     if (threadIdx.x == 0) {
       unsigned long long m = wmax[0];
       for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
-      atomicMax(&state[inst].metric[k % 3], m);
+      atomicMax(&state[inst].metric[k % 3][blockIdx.x % kMetricLanes], m);
     }
   }
 }
@@ -702,7 +714,7 @@ __global__ void __launch_bounds__(256) k_sweep_row(
     if (threadIdx.x == 0) {
       unsigned long long m = wmax[0];
       for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
-      atomicMax(&state[inst].metric[k % 3], m);
+      atomicMax(&state[inst].metric[k % 3][blockIdx.x % kMetricLanes], m);
     }
   }
 }
@@ -758,7 +770,7 @@ __global__ void __launch_bounds__(256) k_qc_update(int n_inst, int n,
   if (threadIdx.x == 0) {
     unsigned long long mm = wmax[0];
     for (int w = 1; w < 4; ++w) mm = wmax[w] > mm ? wmax[w] : mm;
-    atomicMax(&state[inst].metric[k % 3], mm);
+    atomicMax(&state[inst].metric[k % 3][0], mm);
   }
 }
 

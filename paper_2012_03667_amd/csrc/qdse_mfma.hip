@@ -92,12 +92,20 @@ __global__ void k_build_m(int n, int nq, int ldk, int ldi, const double* __restr
 
 __device__ inline double bits2d(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+// The statistic of one sweep slot: the max over its lanes.
+__device__ inline unsigned long long slot_max(const SolveState& S, int slot) {
+  unsigned long long m = S.metric[slot][0];
+#pragma unroll
+  for (int l = 1; l < kMetricLanes; ++l) m = S.metric[slot][l] > m ? S.metric[slot][l] : m;
+  return m;
+}
+
 // Masked-run decision at the start of sweep k (same rule as the FP64 sweep).
 __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool writer) {
   SolveState& S = *st;
   int status = S.status;
   const int done = S.sweeps_slot[(k + 2) % 3];
-  const double prev = bits2d(S.metric[(k + 2) % 3]);
+  const double prev = bits2d(slot_max(S, (k + 2) % 3));
   if (status == 0) {
     if (done > 0) {
       if (!(prev <= 1.7976931348623157e308)) status = 3;
@@ -106,20 +114,21 @@ __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool
     if (status == 0 && done >= ctl->max_iter) status = 2;
   }
   if (writer) {
-    const unsigned long long before = S.metric[(k + 1) % 3];  // sweep k-2, cleared below
+    const unsigned long long before = slot_max(S, (k + 1) % 3);  // sweep k-2, cleared below
     if (status != 0 && S.status == 0) S.resid = prev;
     S.status = status;
     const int now = done + (status == 0 ? 1 : 0);
     S.sweeps_slot[k % 3] = now;
     S.sweeps = now;
-    S.metric[(k + 1) % 3] = 0ull;
+#pragma unroll
+    for (int l = 0; l < kMetricLanes; ++l) S.metric[(k + 1) % 3][l] = 0ull;
     if (ctl->mirror && k % 6 == 0) {  // host mirror (see SolveCtl)
       SolveState* m = ctl->mirror + (st - ctl->base);
       m->status = status;
       m->sweeps = now;
       m->resid = S.resid;
-      m->metric[0] = S.metric[(k + 2) % 3];
-      m->metric[1] = before;
+      m->metric[0][0] = slot_max(S, (k + 2) % 3);
+      m->metric[1][0] = before;
     }
   }
   return status;
@@ -363,7 +372,8 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
       bits = o > bits ? o : bits;
       o = __shfl_xor(bits, 32, 64);
       bits = o > bits ? o : bits;
-      if (lk == 0 && inst_ok && status == 0) atomicMax(&state[inst].metric[k % 3], bits);
+      if (lk == 0 && inst_ok && status == 0)
+        atomicMax(&state[inst].metric[k % 3][blockIdx.x % kMetricLanes], bits);
     }
   }
 }
