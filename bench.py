@@ -572,6 +572,18 @@ def main():
                                       "FP32 matrix 157.3, FP64 matrix 78.6 TFLOP/s")
     line["roofline"]["frac_of_measured"] = (line["roofline"]["achieved"] /
                                             line["measured_peaks"]["copy_GBs"])
+    # the floor under the latency-bound headline kernel: the same grid (four rows
+    # per workgroup, one workgroup column per instance) launched empty, and
+    # streaming the same algorithmic bytes once, both timed like the kernel
+    wg = ((n + 3) // 4) * len(masses)
+    fl = Q.measure_launch_floor(wg, line["roofline"]["alg_bytes_per_launch"])
+    line["roofline"]["launch_floor"] = {
+        "workgroups": wg, "empty_kernel_us": fl["empty_us"],
+        "stream_same_bytes_us": fl["stream_read_us"],
+        "note": "packet-timed like avg_kernel_us: a launch of this grid that does nothing takes "
+                "empty_kernel_us, one that only streams the kernel's algorithmic bytes "
+                "stream_same_bytes_us; the sweep's dependent chain (iterate reads, node "
+                "functions, contraction, reductions) takes the rest"}
     if "roofline_fp32" in line:
         line["roofline_fp32"]["frac_of_measured"] = (line["roofline_fp32"]["achieved"] /
                                                      line["measured_peaks"]["mfma_fp32_TFLOPs"])

@@ -415,6 +415,17 @@ int qdse_fred_solve(qdse_fred_ctx* ctx, double* d_uv, double tol, int max_iter, 
 int qdse_fred_time_sweep(qdse_fred_ctx* ctx, const double* d_in, double* d_out, int reps,
                          double* avg_ms);
 
+/* The floor under a latency-bound launch, measured on the current device
+ * with events on each dispatch packet (as qdse_time_contraction times its
+ * kernels), averaged over 50 launches of `workgroups` x 256 threads:
+ * empty_us for a kernel that does nothing, read_us for one that streams
+ * read_bytes (rounded up to whole doubles per workgroup) once, coalesced, and
+ * writes one value per workgroup. Each output may be NULL. Allocates and
+ * frees its own buffers; synchronises hip_stream. Errors: QDSE_EINVAL
+ * (workgroups < 1, read_bytes < 0), QDSE_ENOMEM, QDSE_EDEVICE. */
+int qdse_measure_launch_floor(void* hip_stream, int workgroups, long long read_bytes,
+                              double* empty_us, double* read_us);
+
 /* The ceilings quoted by the rooflines, measured on the current device:
  * copy_gbs: read + write bandwidth of a 1 GiB streaming copy (larger than
  * the Infinity Cache); mfma32_tflops / mfma64_tflops: dense rate of

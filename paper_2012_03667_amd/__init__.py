@@ -8,7 +8,8 @@ stream. If the library is missing every entry point raises.
 from ._lib import (QDSE_CONV_ABS, QDSE_CONV_MASS, QDSE_ENAN, QDSE_FP32_REFINE, QDSE_FP64,
                    QDSE_FP64_MATRIX,
                    QDSE_NOT_CONVERGED, QDSE_OK, MuSolver, QdseError, Solver, grid_nodes, library_path, load,
-                   mu_grid_nodes, solve_group, FredSolver, fred_nodes, measure_peaks)
+                   mu_grid_nodes, solve_group, FredSolver, fred_nodes, measure_peaks,
+                   measure_launch_floor)
 
-__all__ = ["Solver", "MuSolver", "FredSolver", "fred_nodes", "measure_peaks", "solve_group", "QdseError", "grid_nodes", "mu_grid_nodes", "load", "library_path", "QDSE_OK", "QDSE_NOT_CONVERGED",
+__all__ = ["Solver", "MuSolver", "FredSolver", "fred_nodes", "measure_peaks", "measure_launch_floor", "solve_group", "QdseError", "grid_nodes", "mu_grid_nodes", "load", "library_path", "QDSE_OK", "QDSE_NOT_CONVERGED",
            "QDSE_ENAN", "QDSE_FP64", "QDSE_FP32_REFINE", "QDSE_FP64_MATRIX", "QDSE_CONV_ABS", "QDSE_CONV_MASS"]

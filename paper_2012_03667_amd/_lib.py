@@ -106,6 +106,7 @@ def load():
     L.qdse_mu_solve_anderson.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                          _ip, _dp]
     L.qdse_measure_peaks.argtypes = [_vp, _dp, _dp, _dp]
+    L.qdse_measure_launch_floor.argtypes = [_vp, ctypes.c_int, ctypes.c_longlong, _dp, _dp]
     L.qdse_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip]
     L.qdse_fred_nodes.argtypes = [ctypes.POINTER(FredGrid), _dp, _dp, _dp]
     L.qdse_fred_setup.argtypes = [ctypes.POINTER(FredGrid), ctypes.POINTER(FredPoly), _vp, _vp,
@@ -499,4 +500,17 @@ def measure_peaks(stream=None):
     _check(load().qdse_measure_peaks(_vp(st.cuda_stream), ctypes.byref(c), ctypes.byref(m32),
                                      ctypes.byref(m64)), "qdse_measure_peaks")
     return {"copy_GBs": c.value, "mfma_fp32_TFLOPs": m32.value, "mfma_fp64_TFLOPs": m64.value}
+
+
+def measure_launch_floor(workgroups, read_bytes, stream=None):
+    """qdse_measure_launch_floor: average packet-timed duration (us) of an
+    empty kernel and of a one-pass streaming read of read_bytes, both on
+    workgroups x 256 threads."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    e, r = ctypes.c_double(0), ctypes.c_double(0)
+    _check(load().qdse_measure_launch_floor(_vp(st.cuda_stream), int(workgroups), int(read_bytes),
+                                            ctypes.byref(e), ctypes.byref(r)),
+           "qdse_measure_launch_floor")
+    return {"empty_us": e.value, "stream_read_us": r.value}
 

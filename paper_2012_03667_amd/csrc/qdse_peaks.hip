@@ -3,6 +3,10 @@
 // back-to-back matrix-core instructions of the two types the contraction uses
 // (v_mfma_f32_16x16x4f32, v_mfma_f64_16x16x4f64), each with independent
 // accumulators so that the issue rate, not a dependency, bounds the loop.
+#include <vector>
+
+#include <hip/hip_ext.h>
+
 #include "qdse_internal.h"
 
 namespace {
@@ -41,6 +45,52 @@ __global__ void __launch_bounds__(256) k_mfma64(int iters, double seed, double* 
   double s = 0.0;
   for (int c = 0; c < kChains; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
   if (s == 1234.5) out[blockIdx.x] = s;
+}
+
+// Launch-floor probes: a kernel that does nothing, and one that only streams
+// `n` doubles (one coalesced pass, one store per workgroup).
+__global__ void __launch_bounds__(256) k_empty(double* out) {
+  if (threadIdx.x == 1023) out[0] = 1.0;  // never true at 256 threads
+}
+
+__global__ void __launch_bounds__(256) k_stream(const double* __restrict__ a, long per,
+                                                double* __restrict__ out) {
+  const double* p = a + (long)blockIdx.x * per;
+  double s = 0.0;
+  for (long j = threadIdx.x; j < per; j += blockDim.x) s += p[j];
+  __shared__ double r[256];
+  r[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 256; ++i) t += r[i];
+    out[blockIdx.x] = t;
+  }
+}
+
+// Average duration in ms of `reps` launches, each timed by events on its own
+// dispatch packet (kernel execution only, as the contraction timings are).
+template <class F>
+int time_packets(hipStream_t st, int reps, F&& launch, double* ms_out) {
+  std::vector<hipEvent_t> ev(2 * reps, nullptr);
+  int rc = QDSE_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) rc = QDSE_EDEVICE;
+  if (!rc) {
+    launch(nullptr, nullptr);  // warm-up
+    for (int r = 0; r < reps; ++r) launch(ev[2 * r], ev[2 * r + 1]);
+    double tot = 0.0;
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) rc = QDSE_EDEVICE;
+    for (int r = 0; r < reps && !rc; ++r) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess) rc = QDSE_EDEVICE;
+      tot += ms;
+    }
+    *ms_out = tot / reps;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return rc;
 }
 
 template <class F>
@@ -114,5 +164,37 @@ extern "C" int qdse_measure_peaks(void* hip_stream, double* copy_gbs, double* mf
     if (!rc) *mfma64_tflops = inst * 2.0 * 16 * 16 * 4 / (ms * 1e-3) / 1e12;
   }
   (void)hipFree(o32);
+  return rc;
+}
+
+extern "C" int qdse_measure_launch_floor(void* hip_stream, int workgroups, long long read_bytes,
+                                         double* empty_us, double* read_us) {
+  if (workgroups < 1 || read_bytes < 0) return QDSE_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const long per = (long)((read_bytes / (long long)sizeof(double) + workgroups - 1) / workgroups);
+  double *a = nullptr, *out = nullptr;
+  if (hipMalloc((void**)&out, (size_t)workgroups * sizeof(double)) != hipSuccess) return QDSE_ENOMEM;
+  int rc = QDSE_OK;
+  if (per > 0 && hipMalloc((void**)&a, (size_t)per * workgroups * sizeof(double)) != hipSuccess)
+    rc = QDSE_ENOMEM;
+  if (!rc && a && hipMemsetAsync(a, 0, (size_t)per * workgroups * sizeof(double), st) != hipSuccess)
+    rc = QDSE_EDEVICE;
+  double ms = 0.0;
+  if (!rc && empty_us) {
+    rc = time_packets(st, 50, [&](hipEvent_t e0, hipEvent_t e1) {
+      hipExtLaunchKernelGGL(k_empty, dim3(workgroups), dim3(256), 0, st, e0, e1, 0, out);
+    }, &ms);
+    if (!rc) *empty_us = ms * 1e3;
+  }
+  if (!rc && read_us) {
+    rc = time_packets(st, 50, [&](hipEvent_t e0, hipEvent_t e1) {
+      hipExtLaunchKernelGGL(k_stream, dim3(workgroups), dim3(256), 0, st, e0, e1, 0,
+                            (const double*)a, per, out);
+    }, &ms);
+    if (!rc) *read_us = ms * 1e3;
+  }
+  (void)hipStreamSynchronize(st);
+  if (a) (void)hipFree(a);
+  (void)hipFree(out);
   return rc;
 }

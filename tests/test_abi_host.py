@@ -94,6 +94,8 @@ def test_entry_points_reject_null_context(L):
     assert L.qdse_jvp(None, None, None, None) == -1
     assert L.qdse_vjp(None, None, None, None) == -1
     assert L.qdse_jacobian_band(None, None, 2, None) == -1
+    assert L.qdse_measure_launch_floor(None, 0, 1024, None, None) == -1
+    assert L.qdse_measure_launch_floor(None, 4, -1, None, None) == -1
     assert L.qdse_grad(None, None, None, ctypes.c_double(1e-10), 10, None) == -1
     assert L.qdse_dims(None, None, None, None, None) == -1
     L.qdse_destroy(None)
