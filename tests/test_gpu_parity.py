@@ -174,6 +174,25 @@ def test_adjoint_preconditioner_changes_no_result(Q, n):
     assert np.max(np.abs(tb1 - tb0)) < 1e-8 * np.max(np.abs(tb0))
 
 
+def test_adjoint_at_newton_fixed_point_with_and_without_preconditioner(Q):
+    """At fixed points that successive approximation cannot reach (the
+    kappa = 0.8, omega = 0.5 interaction, solved by Newton-Krylov) the adjoint
+    solve converges with the banded preconditioner and agrees with the
+    unpreconditioned one."""
+    n, na = 64, 64
+    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (KAPPA ** 3 / OMEGA, OMEGA, 0.0)]
+    S = Q.Solver(n, na, params)
+    x = S.initial(1.0, 1.0)
+    rc, steps, res = S.newton(x, tol=1e-12, max_newton=40)
+    assert rc == Q.QDSE_OK, (rc, steps, res)
+    g = torch.tensor(np.random.default_rng(16).normal(size=tuple(x.shape)), device="cuda")
+    tb1, rc1 = S.grad(x, g, tol=1e-12, max_iter=600)
+    tb0, rc0 = _without_band_prec(lambda: S.grad(x, g, tol=1e-12, max_iter=600))
+    assert rc1 == Q.QDSE_OK and rc0 == Q.QDSE_OK
+    tb0, tb1 = np.asarray(tb0), np.asarray(tb1)
+    assert np.max(np.abs(tb1 - tb0)) < 1e-9 * np.max(np.abs(tb0))
+
+
 @pytest.mark.parametrize("n", [150, 512, 700, 1200])
 def test_vjp_inner_product_with_oracle_jvp(Q, n):
     """<J^T w, v> from the GPU reverse sweep equals <w, J v> with J v from the
