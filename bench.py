@@ -99,7 +99,8 @@ def gradient_batch(Q, np, torch, B):
     block per instance): kappa = (D omega)^(1/3) ~ U[0.70, 0.825] GeV,
     omega ~ U[0.65, 0.70] GeV, m ~ U[0, 0.1] GeV (seed 5), the region where
     successive approximation converges for every mass; FP64 solve to 1e-12,
-    then dL/d(D, omega, m) by the implicit adjoint for
+    then dL/d(D, omega, m) by the implicit adjoint (banded-LU-preconditioned
+    GMRES) for
     L = sum_i (M_i - M_T(s_i))^2, M_T(s) = 0.005 + M0 / (1 + s / Lam2),
     M0 ~ U[0.3, 0.5] GeV, Lam2 ~ U[0.5, 2] GeV^2 (seed 55)."""
     n, na = 512, 128
@@ -151,7 +152,8 @@ def gradient_batch(Q, np, torch, B):
         "loss": float(np.sum((M - T) ** 2)),
         "theta_bar_finite": bool(np.all(np.isfinite(tb))),
         "workload": "512x128, kappa~U[0.70,0.825], omega~U[0.65,0.70], m~U[0,0.1] (seed 5); "
-                    "target seed 55; FP64 solve tol 1e-12 then implicit adjoint (GMRES tol 1e-12)",
+                    "target seed 55; FP64 solve tol 1e-12 then implicit adjoint (GMRES tol 1e-12, "
+                    "right-preconditioned by the banded LU of I - band(J)^T)",
     }
 
 
