@@ -367,3 +367,93 @@ def test_newton_reaches_picard_fixed_point():
     assert np.max(np.abs(xp - xn)) < 1e-12
     rho, _ = O.spectral_radius(g, p, xn)
     assert rho < 1.0
+
+
+# ---------------------------------------------------------------- drivers
+def rainbow_map(g, D, om, m, x):
+    """The Landau-gauge rainbow sweep (bare vertex) written here from the
+    textbook form: A(s) = 1 + C_F s^-1 int g(k^2) sigma_V [p.q + 2 (k.p)(k.q)/k^2],
+    B(s) = m + 3 C_F int g(k^2) sigma_S, sigma_V = A(t)/Delta, sigma_S =
+    B(t)/Delta, Delta = t A(t)^2 + B(t)^2, int d^4q/(2 pi)^4 = (8 pi^3)^-1
+    sum_j W_j sum_a w_a sqrt(1 - z_a^2), W_j = GL weight in ln t times t^2,
+    g(k^2) = (8 pi^2 / omega^4) D exp(-k^2 / omega^2); A(t), B(t) from the
+    oracle's interpolation (pinned separately by polynomial reproduction)."""
+    n = g.n
+    Aq, _ = O.interp(g.u, x[:n], g.uq, g.order)
+    Bq, _ = O.interp(g.u, x[n:], g.uq, g.order)
+    Dl = g.t * Aq ** 2 + Bq ** 2
+    s = g.s[:, None, None]
+    t = g.t[None, :, None]
+    z = g.z[None, None, :]
+    r = np.sqrt(s * t)
+    k2 = s + t - 2 * r * z
+    kp, kq = s - r * z, r * z - t
+    wgt = (g.wq * g.t ** 2)[None, :, None] * (g.wz * np.sqrt(1 - g.z ** 2))[None, None, :]
+    gk = 8 * np.pi ** 2 * D / om ** 4 * np.exp(-k2 / om ** 2)
+    c = (4 / 3) / (8 * np.pi ** 3)
+    a = 1 + c * np.sum(wgt * gk * (Aq / Dl)[None, :, None] * (r * z + 2 * kp * kq / k2), axis=(1, 2)) / g.s
+    b = m + 3 * c * np.sum(wgt * gk * (Bq / Dl)[None, :, None], axis=(1, 2))
+    return np.concatenate([a, b])
+
+
+def test_homotopy_start_is_the_rainbow_map():
+    """lam = 0 of the vertex homotopy is the bare vertex: the oracle's sweep
+    at lam = 0 equals the rainbow sweep written above, at the configurations'
+    interaction and at the paper's."""
+    g = O.vac_grid(40, 20)
+    x = rand_x(40)
+    for kap, om in ((0.8, 0.5), ((0.55 * 0.678) ** (1 / 3), 0.678)):
+        p = O.Params.from_kappa(kap, om, 0.005, lam=0.0)
+        got = O.F(g, p, x)
+        ref = rainbow_map(g, p.D, om, 0.005, x)
+        assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)) < 1e-12
+
+
+def test_continuation_endpoints():
+    """continuation(): its lam = 0 stage converges to the fixed point of the
+    rainbow sweep written above (iterated here; it contracts), and walking to
+    lam = 1 at the paper's parameters ends at successive approximation's
+    fixed point of the full Ball-Chiu sweep."""
+    n = 32
+    g = O.vac_grid(n, 24)
+    x0 = np.concatenate([np.ones(n), np.full(n, 0.3)])
+    p0 = O.Params.from_kappa(0.8, 0.5, 0.005, lam=0.0)
+    xr = x0.copy()
+    for _ in range(300):
+        xn = rainbow_map(g, p0.D, 0.5, 0.005, xr)
+        done = np.max(np.abs(xn - xr)) < 1e-14
+        xr = xn
+        if done:
+            break
+    xc, rn = O.continuation(g, p0, x0, steps=1)
+    assert rn < 1e-13
+    assert np.max(np.abs(xc - xr)) < 1e-12
+    assert xr[n] > 0.3  # dynamical mass in the infrared
+    p1 = O.Params(0.55, 0.678, 0.005)
+    xc1, rn1 = O.continuation(g, p1, x0, steps=4)
+    xp, it, r, _ = O.picard(g, p1, x0, 1e-14, max_iter=500, mode=0)
+    assert rn1 < 1e-13 and np.max(np.abs(xc1 - xp)) < 1e-12
+
+
+def test_certificate_flags():
+    """certificate(): the residual is max |F(x) - x|; A <= 0 anywhere clears
+    A_pos; a mass function whose node-to-node slope changes sign is counted
+    (slope_flips), a monotone one gives 0."""
+    n = 32
+    g = O.vac_grid(n, 24)
+    p = O.Params(0.55, 0.678, 0.005)
+    x0 = np.concatenate([np.ones(n), np.ones(n)])
+    xs, _, _, _ = O.picard(g, p, x0, 1e-14, max_iter=500, mode=0)
+    c = O.certificate(g, p, xs)
+    assert c["A_pos"] and c["slope_flips"] == 0 and c["resid"] < 1e-13
+    y = xs.copy()
+    y[3] = -0.5
+    c = O.certificate(g, p, y)
+    assert not c["A_pos"]
+    assert abs(c["resid"] - np.max(np.abs(O.F(g, p, y) - y))) == 0.0
+    y = xs.copy()
+    y[n + 5] *= 1.2  # a bump in B: the slope of M changes sign twice
+    assert O.certificate(g, p, y)["slope_flips"] == 2
+    y = xs.copy()
+    y[n + 4:n + 12] *= 1 + 0.3 * (-1) ** np.arange(8)
+    assert O.certificate(g, p, y)["slope_flips"] >= 6
