@@ -73,7 +73,8 @@ struct qo_vac_grid {
   const double* u;  // [n]  ln s
   const double* t;  // [nq] loop q^2, ascending
   const double* uq; // [nq] ln t
-  const double* wq; // [nq] quadrature weights in u = ln t
+  const double* W;  // [nq] radial weights: Gauss-Legendre weight in u = ln t
+                    //      times t^2 (t dt = t^2 du), correctly rounded
   const double* z;  // [na] angular nodes on [-1, 1]
   const double* wz; // [na] angular weights (without sqrt(1-z^2))
 };
@@ -201,7 +202,7 @@ void row_sums(const qo_vac_grid* g, const qo_vac_par* par, T Ai, T Bi,
   for (int j = 0; j < g->nq; ++j) {
     const double t = g->t[j];
     const T Dq = t * Aq[j] * Aq[j] + Bq[j] * Bq[j];
-    const double Wj = g->wq[j] * t * t;  // dt t = du t^2
+    const double Wj = g->W[j];
     for (int a = 0; a < g->na; ++a) {
       const double z = g->z[a];
       T IA, IB;
@@ -273,7 +274,7 @@ double paper_function(const qo_vac_grid* g, const qo_vac_par* par, const double*
   double acc = 0.0;
   for (int j = 0; j < g->nq; ++j) {
     const double t = g->t[j];
-    const double Wj = g->wq[j] * t * t;
+    const double Wj = g->W[j];
     for (int a = 0; a < g->na; ++a) {
       double Aq, Bq;
       if (modified) {
@@ -323,11 +324,13 @@ int qo_vac_map_paper(const qo_vac_grid* g, const qo_vac_par* par, const double* 
   if (check_grid(g) || !par || !x_in || !x_out || nthreads < 1) return -1;
   const double c = (4.0 / 3.0) / (8.0 * PI * PI * PI);
   const int n = g->n;
+  const double f0[2] = {1.0, par->m};  // inhomogeneous terms of A and B
+  // the two projections of every external momentum are separate integrals,
+  // each with its own interpolation inside the loops; OpenMP over the rows
 #pragma omp parallel for schedule(static) num_threads(nthreads)
-  for (int i = 0; i < n; ++i) {
-    x_out[i] = 1.0 + c * paper_function(g, par, x_in, i, 0, modified);
-    x_out[n + i] = par->m + c * paper_function(g, par, x_in, i, 1, modified);
-  }
+  for (int i = 0; i < n; ++i)
+    for (int which = 0; which < 2; ++which)
+      x_out[which * n + i] = f0[which] + c * paper_function(g, par, x_in, i, which, modified);
   return 0;
 }
 

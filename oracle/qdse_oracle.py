@@ -59,7 +59,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("nq", ctypes.c_int), ("na", ctypes.c_int),
                 ("order", ctypes.c_int)] + [
         (nm, ctypes.POINTER(ctypes.c_double))
-        for nm in ("s", "u", "t", "uq", "wq", "z", "wz")]
+        for nm in ("s", "u", "t", "uq", "W", "z", "wz")]
 
 
 class _Par(ctypes.Structure):
@@ -124,7 +124,7 @@ class VacGrid:
     u: np.ndarray
     t: np.ndarray
     uq: np.ndarray
-    wq: np.ndarray
+    W: np.ndarray
     z: np.ndarray
     wz: np.ndarray
 
@@ -134,7 +134,7 @@ class VacGrid:
 
     def _c(self):
         g = _Grid(self.n, self.nq, self.na, self.order,
-                  *[_dp(a) for a in (self.s, self.u, self.t, self.uq, self.wq, self.z, self.wz)])
+                  *[_dp(a) for a in (self.s, self.u, self.t, self.uq, self.W, self.z, self.wz)])
         g._keep = self  # keep arrays alive
         return g
 
@@ -180,24 +180,44 @@ def gauss_legendre(n: int):
     return x, w
 
 
-def gl_interval(n: int, a: float, b: float):
-    """n-point Gauss-Legendre nodes and weights mapped to [a, b]."""
+def _mp():
+    """A private 60-digit mpmath context: every grid quantity is an exact
+    expression of FP64 inputs, evaluated here and rounded once to FP64."""
+    import mpmath
+    ctx = mpmath.mp.clone() if hasattr(mpmath.mp, "clone") else mpmath.mp
+    ctx.dps = 60
+    return ctx
+
+
+def gl_interval(n: int, a, b, mp=None):
+    """n-point Gauss-Legendre rule mapped to [a, b] (a, b exact mpmath numbers):
+    nodes RN(a + (b - a)(x + 1)/2) for the FP64 nodes x, and the exact factors
+    (b - a)/2 * w of the weights (mpmath numbers, rounded by the caller)."""
+    mp = mp or _mp()
+    a, b = mp.mpf(a), mp.mpf(b)
     x, w = gauss_legendre(n)
-    half = 0.5 * (b - a)
-    return a + half * (x + 1.0), half * w
+    half = (b - a) / 2
+    return (np.array([float(a + (b - a) * (mp.mpf(float(v)) + 1) / 2) for v in x]),
+            [half * mp.mpf(float(v)) for v in w])
 
 
 def vac_grid(n: int, na: int, s_min: float = 1e-4, s_max: float = 1e4,
              order: int = 3, nq: int | None = None) -> VacGrid:
     """External grid GL(n) in u = ln s, loop grid GL(n+1) in u on the same
-    interval (interleaved), angular grid GL(na) in z."""
-    a, b = math.log(s_min), math.log(s_max)
-    u, _ = gl_interval(n, a, b)
-    uq, wq = gl_interval(n + 1 if nq is None else nq, a, b)
+    interval (interleaved), angular grid GL(na) in z. The grid is defined by
+    correctly rounded values (reading of Sec. III A): with a = ln s_min,
+    b = ln s_max exact and x, w the correctly rounded Gauss-Legendre rule,
+    u = RN(a + (b - a)(x + 1)/2), s = RN(e^u), and the loop weight of the
+    measure t dt = t^2 du is W = RN((b - a)/2 w t^2)."""
+    mp = _mp()
+    a, b = mp.log(mp.mpf(s_min)), mp.log(mp.mpf(s_max))
+    u, _ = gl_interval(n, a, b, mp)
+    uq, wq = gl_interval(n + 1 if nq is None else nq, a, b, mp)
     z, wz = gauss_legendre(na)
-    s = np.array([math.exp(v) for v in u])
-    t = np.array([math.exp(v) for v in uq])
-    return VacGrid(n, na, order, s, u, t, uq, wq, z.copy(), wz.copy())
+    s = np.array([float(mp.exp(mp.mpf(float(v)))) for v in u])
+    t = np.array([float(mp.exp(mp.mpf(float(v)))) for v in uq])
+    W = np.array([float(h * mp.mpf(float(tj)) ** 2) for h, tj in zip(wq, t)])
+    return VacGrid(n, na, order, s, u, t, uq, W, z.copy(), wz.copy())
 
 
 @dataclass
@@ -497,25 +517,26 @@ def mu_grid(ns: int, n4: int, na: int, r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0
     same frequencies (both signs by conjugation) with weight 2 pi T, since
     int dq4/(2 pi) f becomes T sum_n f(w_n); the time grid variable is w_n
     itself, so interpolation in the time direction is at the nodes."""
-    a, b = math.log(r_min), math.log(r_max)
-    us, _ = gl_interval(ns, a, b)
-    uqs, wu = gl_interval(ns + 1, a, b)
+    mp = _mp()
+    a, b = mp.log(mp.mpf(r_min)), mp.log(mp.mpf(r_max))
+    us, _ = gl_interval(ns, a, b, mp)
+    uqs, wu = gl_interval(ns + 1, a, b, mp)
     z, wz = gauss_legendre(na)
-    ps = np.array([math.exp(t) for t in us])
-    qs = np.array([math.exp(t) for t in uqs])
-    wqs = np.array([w * q * q * q for w, q in zip(wu, qs)])
+    ps = np.array([float(mp.exp(mp.mpf(float(t)))) for t in us])
+    qs = np.array([float(mp.exp(mp.mpf(float(t)))) for t in uqs])
+    wqs = np.array([float(w * mp.mpf(float(q)) ** 3) for w, q in zip(wu, qs)])
     if T > 0:
-        p4 = np.array([(2 * n + 1) * math.pi * T for n in range(n4)])
+        p4 = np.array([float((2 * n + 1) * mp.pi * mp.mpf(T)) for n in range(n4)])
         v4 = p4.copy()
         q4, vq4 = p4.copy(), p4.copy()
-        wq4 = np.full(n4, 2 * math.pi * T)
+        wq4 = np.full(n4, float(2 * mp.pi * mp.mpf(T)))
     else:
-        vmax = math.asinh(p4_max / lam4)
-        v4, _ = gl_interval(n4, 0.0, vmax)
-        vq4, wv = gl_interval(n4 + 1, 0.0, vmax)
-        p4 = np.array([lam4 * math.sinh(t) for t in v4])
-        q4 = np.array([lam4 * math.sinh(t) for t in vq4])
-        wq4 = np.array([w * (lam4 * math.cosh(t)) for w, t in zip(wv, vq4)])
+        vmax = mp.asinh(mp.mpf(p4_max) / mp.mpf(lam4))
+        v4, _ = gl_interval(n4, mp.mpf(0), vmax, mp)
+        vq4, wv = gl_interval(n4 + 1, mp.mpf(0), vmax, mp)
+        p4 = np.array([float(mp.mpf(lam4) * mp.sinh(mp.mpf(float(t)))) for t in v4])
+        q4 = np.array([float(mp.mpf(lam4) * mp.sinh(mp.mpf(float(t)))) for t in vq4])
+        wq4 = np.array([float(w * mp.mpf(lam4) * mp.cosh(mp.mpf(float(t)))) for w, t in zip(wv, vq4)])
     return MuGrid(ns, n4, na, order, ps, us, p4, np.asarray(v4), qs, uqs, wqs, q4,
                   np.asarray(vq4), wq4, z.copy(), wz.copy())
 

@@ -32,10 +32,13 @@ from .qdse_oracle import gl_interval
 
 
 def nodes(n: int, a: float, b: float):
-    """External nodes x (GL(n)), integration nodes t and weights w (GL(n+1))."""
-    x, _ = gl_interval(n, a, b)
-    t, w = gl_interval(n + 1, a, b)
-    return x, t, w
+    """External nodes x (GL(n)), integration nodes t and weights w (GL(n+1)),
+    correctly rounded: x = RN(a + (b - a)(x_GL + 1)/2), w = RN((b - a)/2 w_GL)."""
+    import mpmath
+    a_, b_ = mpmath.mpf(a), mpmath.mpf(b)
+    x, _ = gl_interval(n, a_, b_)
+    t, w = gl_interval(n + 1, a_, b_)
+    return x, t, np.array([float(v) for v in w])
 
 
 def interp(xg: np.ndarray, f: np.ndarray, xq: float, order: int) -> float:

@@ -33,14 +33,7 @@ bool grid_ok(const qdse_fred_grid* g) {
 
 namespace qdse {
 
-void gl_nodes_on(int n, double a, double b, double* x, double* w) {
-  gauss_legendre(n, x, w);
-  const double half = 0.5 * (b - a);
-  for (int i = 0; i < n; ++i) {
-    x[i] = a + half * (x[i] + 1.0);
-    w[i] = half * w[i];
-  }
-}
+void gl_nodes_on(int n, double a, double b, double* x, double* w) { gl_mapped(n, a, b, x, w); }
 
 }  // namespace qdse
 

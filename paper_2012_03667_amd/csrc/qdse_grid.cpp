@@ -14,8 +14,11 @@
 #include <algorithm>
 #include <cmath>
 
-// The grid must round exactly as written (no fused multiply-add contraction):
-// u = a + half (x + 1), W = half w t^2.
+// The grid is defined by correctly rounded values: with x, w the correctly
+// rounded Gauss-Legendre rule and a = ln s_min, b = ln s_max (exact),
+//   u = RN(a + (b - a)(x + 1)/2),  s = RN(exp(u)),  W = RN((b - a)/2 w t^2),
+// each evaluated in double-double arithmetic and rounded once (the same for
+// the finite-mu grids). No fused multiply-add contraction in the helpers.
 #pragma clang fp contract(off)
 
 namespace qdse {
@@ -55,6 +58,76 @@ static inline dd dd_div(dd a, dd b) {
   r = dd_add(r, dd_neg(dd_mul_d(b, q2)));
   const double q3 = r.hi / b.hi;
   return dd_add(quick_two_sum(q1, q2), dd{q3, 0.0});
+}
+static inline dd dd_from(double a) { return dd{a, 0.0}; }
+static inline dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+static inline double dd_round(dd a) { return a.hi + a.lo; }
+static inline dd dd_ldexp(dd a, int e) { return dd{std::ldexp(a.hi, e), std::ldexp(a.lo, e)}; }
+
+static const dd kDdLn2{0.6931471805599453094, 2.319046813846299558e-17};
+static const dd kDdPi{3.141592653589793116, 1.224646799147353207e-16};
+
+// exp in double-double: x = k ln 2 + r, exp(r / 2^10) by its Taylor series
+// (|r / 2^10| < 3.4e-4, 12 terms), squared ten times, scaled by 2^k.
+static dd dd_exp(dd x) {
+  const double kf = std::nearbyint(x.hi / kDdLn2.hi);
+  const dd r = dd_ldexp(dd_sub(x, dd_mul_d(kDdLn2, kf)), -10);
+  dd term = dd_from(1.0), sum = dd_from(1.0);
+  for (int i = 1; i <= 12; ++i) {
+    term = dd_div(dd_mul(term, r), dd_from((double)i));
+    sum = dd_add(sum, term);
+  }
+  for (int i = 0; i < 10; ++i) sum = dd_mul(sum, sum);
+  return dd_ldexp(sum, (int)kf);
+}
+
+// ln x (x > 0) in double-double: Newton steps y += x exp(-y) - 1 from the
+// FP64 logarithm (each step squares the relative error).
+static dd dd_log(dd x) {
+  dd y = dd_from(std::log(x.hi));
+  for (int it = 0; it < 2; ++it)
+    y = dd_add(y, dd_sub(dd_mul(x, dd_exp(dd_neg(y))), dd_from(1.0)));
+  return y;
+}
+
+static dd dd_sqrt(dd a) {
+  const double y = std::sqrt(a.hi);
+  const dd y2 = dd_mul(dd_from(y), dd_from(y));
+  return dd_add(dd_from(y), dd_div(dd_sub(a, y2), dd_from(2.0 * y)));
+}
+
+static dd dd_sinh(dd v) { return dd_ldexp(dd_sub(dd_exp(v), dd_exp(dd_neg(v))), -1); }
+static dd dd_cosh(dd v) { return dd_ldexp(dd_add(dd_exp(v), dd_exp(dd_neg(v))), -1); }
+static dd dd_asinh(dd x) { return dd_log(dd_add(x, dd_sqrt(dd_add(dd_mul(x, x), dd_from(1.0))))); }
+
+// RN(a + h (x + 1)) for a Gauss-Legendre node x of [-1, 1] mapped to an
+// interval of left end a and half length h (both double-double).
+static inline double map_node(dd a, dd h, double x) {
+  return dd_round(dd_add(a, dd_mul(h, two_sum(x, 1.0))));
+}
+
+static inline dd two_prod(double a, double b) {
+  const double p = a * b;
+  return {p, std::fma(a, b, -p)};
+}
+
+// The node u = RN(ln lo + (ln hi - ln lo)(x + 1)/2) of the grid in ln p on
+// [lo, hi]. The middle node of an odd rule (x = 0) is (ln lo + ln hi)/2 =
+// ln(lo hi)/2, which can be far smaller than ln lo (a range symmetric about
+// 1 up to the rounding of lo): it is taken from ln(1 + d), d = lo hi - 1
+// exact, by its series when |d| is small, so that it too is correctly
+// rounded.
+static double log_node(double lo, double hi, dd a, dd h, double x) {
+  if (x != 0.0) return map_node(a, h, x);
+  const dd d = dd_sub(two_prod(lo, hi), dd_from(1.0));
+  if (std::fabs(d.hi) > 1e-3) return map_node(a, h, x);
+  dd sum = dd_from(0.0), pw = d;
+  for (int k = 1; k <= 16; ++k) {  // ln(1 + d) = sum (-1)^(k+1) d^k / k
+    const dd term = dd_div(pw, dd_from((double)k));
+    sum = (k & 1) ? dd_add(sum, term) : dd_sub(sum, term);
+    pw = dd_mul(pw, d);
+  }
+  return dd_round(dd_ldexp(sum, -1));
 }
 
 // P_n(r) and P_n'(r) by the three-term recurrence in double-double.
@@ -117,6 +190,16 @@ void gauss_legendre(int n, double* x, double* w) {
   if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
+void gl_mapped(int n, double a, double b, double* x, double* w) {
+  gauss_legendre(n, x, w);
+  const dd da = dd_from(a), half = dd_ldexp(two_sum(b, -a), -1);
+  for (int i = 0; i < n; ++i) {
+    // the middle node of an odd rule is (a + b)/2, exact in double-double
+    x[i] = x[i] == 0.0 ? dd_round(dd_ldexp(two_sum(a, b), -1)) : map_node(da, half, x[i]);
+    w[i] = dd_round(dd_mul_d(half, w[i]));
+  }
+}
+
 // 4-point stencil (base index, weights) of Lagrange interpolation in u for
 // every loop node, using the bracket (s_{j-1}, s_j) known from the
 // interleaving. order 3: nodes j-2..j+1 shifted to stay inside the grid.
@@ -158,25 +241,26 @@ int build_grid(const qdse_grid& g, HostGrid* hg) {
   hg->nq = nq;
   hg->na = na;
   hg->ldk = (nq + 7) & ~7;
-  const double a = std::log(g.s_min), b = std::log(g.s_max);
-  const double half = 0.5 * (b - a);
+  const dd a = dd_log(dd_from(g.s_min)), b = dd_log(dd_from(g.s_max));
+  const dd half = dd_ldexp(dd_sub(b, a), -1);
 
   std::vector<double> x(nq), w(nq);
   hg->u.resize(n);
   hg->s.resize(n);
   gauss_legendre(n, x.data(), w.data());
   for (int i = 0; i < n; ++i) {
-    hg->u[i] = a + half * (x[i] + 1.0);
-    hg->s[i] = std::exp(hg->u[i]);
+    hg->u[i] = log_node(g.s_min, g.s_max, a, half, x[i]);
+    hg->s[i] = dd_round(dd_exp(dd_from(hg->u[i])));
   }
   hg->uq.resize(nq);
   hg->t.resize(nq);
   hg->W.resize(nq);
   gauss_legendre(nq, x.data(), w.data());
   for (int j = 0; j < nq; ++j) {
-    hg->uq[j] = a + half * (x[j] + 1.0);
-    hg->t[j] = std::exp(hg->uq[j]);
-    hg->W[j] = half * w[j] * hg->t[j] * hg->t[j];  // t dt = t^2 du
+    hg->uq[j] = log_node(g.s_min, g.s_max, a, half, x[j]);
+    hg->t[j] = dd_round(dd_exp(dd_from(hg->uq[j])));
+    const dd t = dd_from(hg->t[j]);
+    hg->W[j] = dd_round(dd_mul(dd_mul_d(half, w[j]), dd_mul(t, t)));  // t dt = t^2 du
   }
   std::vector<double> za(na), wa(na);
   gauss_legendre(na, za.data(), wa.data());
@@ -200,45 +284,44 @@ int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h) {
   h->nqs = ns + 1;
   h->nq4 = n4 + 1;
   h->na = na;
-  const double a = std::log(g.r_min), b = std::log(g.r_max);
-  const double half = 0.5 * (b - a);
-  const double vmax = std::asinh(g.p4_max / g.lam4);
-  const double hv = 0.5 * (vmax - 0.0);
+  const dd a = dd_log(dd_from(g.r_min)), b = dd_log(dd_from(g.r_max));
+  const dd half = dd_ldexp(dd_sub(b, a), -1);
   std::vector<double> x(ns + 2), w(ns + 2);
   // |p_vec|: Gauss-Legendre in ln|p|; loop |q|: one more node, weight |q|^3 dln|q|
   h->us.resize(ns);
   h->ps.resize(ns);
   gauss_legendre(ns, x.data(), w.data());
   for (int i = 0; i < ns; ++i) {
-    h->us[i] = a + half * (x[i] + 1.0);
-    h->ps[i] = std::exp(h->us[i]);
+    h->us[i] = log_node(g.r_min, g.r_max, a, half, x[i]);
+    h->ps[i] = dd_round(dd_exp(dd_from(h->us[i])));
   }
   h->uqs.resize(ns + 1);
   h->qs.resize(ns + 1);
   h->wqs.resize(ns + 1);
   gauss_legendre(ns + 1, x.data(), w.data());
   for (int j = 0; j <= ns; ++j) {
-    h->uqs[j] = a + half * (x[j] + 1.0);
-    h->qs[j] = std::exp(h->uqs[j]);
-    h->wqs[j] = half * w[j] * h->qs[j] * h->qs[j] * h->qs[j];
+    h->uqs[j] = log_node(g.r_min, g.r_max, a, half, x[j]);
+    h->qs[j] = dd_round(dd_exp(dd_from(h->uqs[j])));
+    const dd q = dd_from(h->qs[j]);
+    h->wqs[j] = dd_round(dd_mul(dd_mul_d(half, w[j]), dd_mul(q, dd_mul(q, q))));
   }
   if (g.T > 0.0) {
     // Matsubara frequencies w_n = (2n+1) pi T; the loop runs over the same
     // frequencies (both signs in the sweep), weight 2 pi T each; the time
     // stencil is the identity (lo at n, clamped so that lo + 3 < n4)
     h->nq4 = n4;
-    const double pi = 3.14159265358979323846;
+    const dd piT = dd_mul_d(kDdPi, g.T);
     h->v4.resize(n4);
     h->p4.resize(n4);
     h->vq4.resize(n4);
     h->q4.resize(n4);
     h->wq4.resize(n4);
     for (int i = 0; i < n4; ++i) {
-      h->p4[i] = (2.0 * i + 1.0) * pi * g.T;
+      h->p4[i] = dd_round(dd_mul_d(piT, 2.0 * i + 1.0));
       h->v4[i] = h->p4[i];
       h->q4[i] = h->p4[i];
       h->vq4[i] = h->p4[i];
-      h->wq4[i] = 2.0 * pi * g.T;
+      h->wq4[i] = dd_round(dd_mul_d(piT, 2.0));
     }
     h->lo_4.resize(n4);
     h->sw_4.assign(4 * (size_t)n4, 0.0);
@@ -249,22 +332,23 @@ int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h) {
     }
   } else {
   // p4 = lam4 sinh(v), v Gauss-Legendre on [0, asinh(p4_max/lam4)]; dq4 = lam4 cosh(v) dv
+  const dd hv = dd_ldexp(dd_asinh(dd_div(dd_from(g.p4_max), dd_from(g.lam4))), -1);
   std::vector<double> y(n4 + 2), wy(n4 + 2);
   h->v4.resize(n4);
   h->p4.resize(n4);
   gauss_legendre(n4, y.data(), wy.data());
   for (int i = 0; i < n4; ++i) {
-    h->v4[i] = 0.0 + hv * (y[i] + 1.0);
-    h->p4[i] = g.lam4 * std::sinh(h->v4[i]);
+    h->v4[i] = map_node(dd_from(0.0), hv, y[i]);
+    h->p4[i] = dd_round(dd_mul_d(dd_sinh(dd_from(h->v4[i])), g.lam4));
   }
   h->vq4.resize(n4 + 1);
   h->q4.resize(n4 + 1);
   h->wq4.resize(n4 + 1);
   gauss_legendre(n4 + 1, y.data(), wy.data());
   for (int j = 0; j <= n4; ++j) {
-    h->vq4[j] = 0.0 + hv * (y[j] + 1.0);
-    h->q4[j] = g.lam4 * std::sinh(h->vq4[j]);
-    h->wq4[j] = hv * wy[j] * (g.lam4 * std::cosh(h->vq4[j]));
+    h->vq4[j] = map_node(dd_from(0.0), hv, y[j]);
+    h->q4[j] = dd_round(dd_mul_d(dd_sinh(dd_from(h->vq4[j])), g.lam4));
+    h->wq4[j] = dd_round(dd_mul(dd_mul_d(dd_mul_d(hv, wy[j]), g.lam4), dd_cosh(dd_from(h->vq4[j]))));
   }
   for (int i = 0; i < n4; ++i)
     if (!(h->q4[i] < h->p4[i] && h->p4[i] < h->q4[i + 1])) return -1;

@@ -22,6 +22,8 @@ struct HostGrid {
 };
 
 void gauss_legendre(int n, double* x, double* w);
+// The n-point rule on [a, b]: x = RN(a + (b - a)(x_GL + 1)/2), w = RN((b - a)/2 w_GL).
+void gl_mapped(int n, double a, double b, double* x, double* w);
 int build_grid(const qdse_grid& g, HostGrid* hg);
 void build_stencils(int n, int order, const double* u, const double* uq, int* lo, double* sw);
 

@@ -130,7 +130,7 @@ def test_library_grid_is_the_oracle_grid(L, n, na, smin, smax):
     g = O.vac_grid(n, na, s_min=smin, s_max=smax)
     assert np.array_equal(h["s"], g.s) and np.array_equal(h["u"], g.u)
     assert np.array_equal(h["t"], g.t)
-    assert np.array_equal(h["W"], g.wq * g.t * g.t)
+    assert np.array_equal(h["W"], g.W)
     assert np.array_equal(h["z"], g.z)
     assert np.allclose(h["wz"], g.wz * np.sqrt(1 - g.z ** 2), rtol=1e-12, atol=0)
 
@@ -145,3 +145,16 @@ def test_library_mu_grid_is_the_oracle_grid(L, ns, n4, na, T):
     g = O.mu_grid(ns, n4, na, r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0.5, T=T)
     for k in ("ps", "p4", "qs", "q4", "wqs", "wq4", "z", "wz"):
         assert np.array_equal(h[k], getattr(g, k)), k
+
+
+@pytest.mark.parametrize("n,a,b", [(37, -1.0, 1.0), (64, 0.0, 1.0), (15, -0.3, 2.7), (4, 1e-3, 5.0)])
+def test_library_general_system_nodes_are_the_oracle_nodes(L, n, a, b):
+    """Sec. I's discretisation, built independently on both sides as correctly
+    rounded x = RN(a + (b - a)(x_GL + 1)/2), w = RN((b - a)/2 w_GL): equal bit
+    for bit (odd n on a symmetric interval puts a node at the exact midpoint)."""
+    import numpy as np
+    import paper_2012_03667_amd as Q
+    from oracle import qdse_oracle_fred as OF
+    x, t, w = Q.fred_nodes(n, a, b)
+    xo, to, wo = OF.nodes(n, a, b)
+    assert np.array_equal(x, xo) and np.array_equal(t, to) and np.array_equal(w, wo)

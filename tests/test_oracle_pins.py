@@ -375,7 +375,7 @@ def rainbow_map(g, D, om, m, x):
     textbook form: A(s) = 1 + C_F s^-1 int g(k^2) sigma_V [p.q + 2 (k.p)(k.q)/k^2],
     B(s) = m + 3 C_F int g(k^2) sigma_S, sigma_V = A(t)/Delta, sigma_S =
     B(t)/Delta, Delta = t A(t)^2 + B(t)^2, int d^4q/(2 pi)^4 = (8 pi^3)^-1
-    sum_j W_j sum_a w_a sqrt(1 - z_a^2), W_j = GL weight in ln t times t^2,
+    sum_j W_j sum_a w_a sqrt(1 - z_a^2), W_j = GL weight in ln t times t^2 (the grid's W),
     g(k^2) = (8 pi^2 / omega^4) D exp(-k^2 / omega^2); A(t), B(t) from the
     oracle's interpolation (pinned separately by polynomial reproduction)."""
     n = g.n
@@ -388,7 +388,7 @@ def rainbow_map(g, D, om, m, x):
     r = np.sqrt(s * t)
     k2 = s + t - 2 * r * z
     kp, kq = s - r * z, r * z - t
-    wgt = (g.wq * g.t ** 2)[None, :, None] * (g.wz * np.sqrt(1 - g.z ** 2))[None, None, :]
+    wgt = g.W[None, :, None] * (g.wz * np.sqrt(1 - g.z ** 2))[None, None, :]
     gk = 8 * np.pi ** 2 * D / om ** 4 * np.exp(-k2 / om ** 2)
     c = (4 / 3) / (8 * np.pi ** 3)
     a = 1 + c * np.sum(wgt * gk * (Aq / Dl)[None, :, None] * (r * z + 2 * kp * kq / k2), axis=(1, 2)) / g.s
