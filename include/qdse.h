@@ -227,6 +227,20 @@ int qdse_jvp(qdse_ctx* ctx, const double* d_x, const double* d_v, double* d_jv);
 /* Transposed product d_out = (dF/dx)(d_x)^T d_w (reverse mode). Asynchronous. */
 int qdse_vjp(qdse_ctx* ctx, const double* d_x, const double* d_w, double* d_out);
 
+/* qdse_vjp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result bit for bit, with the reverse sweep's workspace in
+ * a fixed device array of 4 Mi doubles (32 MiB) that the library holds on
+ * every GPU it runs on until the process ends, instead of buffers the
+ * context allocates on its first qdse_vjp. The call itself allocates
+ * nothing. A batch needs n_inst * 66 * ldk doubles, ldk = N + 1 rounded up
+ * to a multiple of 8 (at N = 512 up to 122 instances); larger batches get
+ * QDSE_EINVAL before any device work. Calls on one GPU share the array:
+ * calls that overlap in time on one GPU (two streams, or two host threads)
+ * race and give undefined results; calls ordered on one stream are safe.
+ * Nothing in the array needs to start at zero. Asynchronous. */
+int qdse_vjp_noalloc(qdse_ctx* ctx, const double* d_x, const double* d_w, double* d_out);
+
 /* Near-diagonal band of the sweep Jacobian J = dF/dx at d_x (the derivative of
  * the map of Sec. II eqs. dsesys, dsesys2 in the direct-difference form):
  * d_out[inst][i][o][4] (device, FP64, n_inst * N * (2 bw + 1) * 4 values)

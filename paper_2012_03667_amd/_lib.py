@@ -92,6 +92,7 @@ def load():
     L.qdse_newton.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]
     L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_vjp.argtypes = [_vp, _vp, _vp, _vp]
+    L.qdse_vjp_noalloc.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_jacobian_band.argtypes = [_vp, _vp, ctypes.c_int, _vp]
     L.qdse_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _dp]
     L.qdse_kernel_matrices.argtypes = [_vp, ctypes.c_int, _vp]
@@ -270,6 +271,13 @@ class Solver:
         out = torch.empty_like(x) if out is None else out
         _check(load().qdse_vjp(self._h, _dev(x, self.shape, "x"), _dev(w, self.shape, "w"),
                                _dev(out, self.shape, "out")), "qdse_vjp")
+        return out
+
+    def vjp_noalloc(self, x, w, out):
+        """qdse_vjp_noalloc: the reverse sweep with the library's fixed
+        workspace (out must be given; nothing is allocated)."""
+        _check(load().qdse_vjp_noalloc(self._h, _dev(x, self.shape, "x"), _dev(w, self.shape, "w"),
+                                       _dev(out, self.shape, "out")), "qdse_vjp_noalloc")
         return out
 
     def jacobian_band(self, x, bw, out=None):

@@ -7,7 +7,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqdse.so")
 SOURCES = ["qdse_grid.cpp", "qdse_kernels.hip", "qdse_persistent.hip", "qdse_mfma.hip",
            "qdse_mu.hip", "qdse_api.cpp", "qdse_mu_api.cpp", "qdse_fred.hip", "qdse_fred_api.cpp", "qdse_peaks.hip",
-           "qdse_band.hip"]
+           "qdse_band.hip", "qdse_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

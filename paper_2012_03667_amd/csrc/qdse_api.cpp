@@ -925,6 +925,29 @@ int qdse_vjp(qdse_ctx* c, const double* d_x, const double* d_w, double* d_out) {
   return vjp_on(c, c->d_K, d_x, d_w, d_out);
 }
 
+int qdse_vjp_noalloc(qdse_ctx* c, const double* d_x, const double* d_w, double* d_out) {
+  if (!c || !d_x || !d_w || !d_out || d_w == d_out) return QDSE_EINVAL;
+  if (c->qc) return QDSE_ENOTSUP;
+  const HostGrid& g = c->hg;
+  // the reverse sweep's workspace: row-chunk partial sums [n_inst][nchunk][4][ldk]
+  // and loop-node adjoints [n_inst][2][ldk], both written before they are read
+  const int nchunk = std::min(c->nchunk, kVjpChunksMax);
+  const size_t part = (size_t)c->n_inst * nchunk * 4 * g.ldk;
+  const size_t need = part + (size_t)c->n_inst * 2 * g.ldk;
+  if (need > kScratchDoubles) {
+    g_last_error = "qdse_vjp_noalloc: the batch needs " + std::to_string(need) +
+                   " doubles of workspace, the fixed workspace holds " +
+                   std::to_string(kScratchDoubles);
+    return QDSE_EINVAL;
+  }
+  double* ws = nullptr;
+  HIPCHK(noalloc_scratch(c->device, &ws));
+  HIPCHK(launch_vjp(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
+                    c->d_lo, c->d_sw, c->d_t, c->d_s, d_x, d_w, d_out, c->d_nodes, ws, ws + part,
+                    nchunk));
+  return QDSE_OK;
+}
+
 int qdse_jacobian_band(qdse_ctx* c, const double* d_x, int bw, double* d_out) {
   if (!c || !d_x || !d_out || bw < 0 || bw >= c->hg.n) return QDSE_EINVAL;
   if (c->qc) return QDSE_ENOTSUP;

@@ -39,6 +39,13 @@ struct HostMuGrid {
 };
 int build_mu_grid(const qdse_mu_grid& g, HostMuGrid* h);
 
+// Fixed device workspace of the entry points that allocate nothing
+// (qdse_noalloc.hip): kScratchDoubles doubles per device, shared by every
+// call on that device. noalloc_scratch returns its device address on
+// `device`, looked up once per device.
+constexpr size_t kScratchDoubles = (size_t)4 << 20;  // 32 MiB
+hipError_t noalloc_scratch(int device, double** ptr);
+
 // Per-instance constants on the device.
 struct InstDev {
   double pref;   // C_F/(8 pi^3) * 8 pi^2 D / omega^4: multiplies every loop sum
