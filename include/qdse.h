@@ -31,8 +31,12 @@
  *    qdse_solve and qdse_grad synchronise the stream before they return
  *    because they report convergence to the host.
  *  - Return value: QDSE_OK (0), QDSE_NOT_CONVERGED (1, outputs hold the last
- *    iterate), or a negative error code (outputs unspecified). Arguments are
- *    validated before any HIP call. qdse_strerror names every code.
+ *    iterate), or a negative error code (outputs unspecified, except that
+ *    QDSE_EDIVERGED and QDSE_ESPURIOUS from a solve leave the last iterate
+ *    in the caller's array). Arguments are validated before any HIP call.
+ *    qdse_strerror names every code. A batch returns its most severe
+ *    per-instance outcome (QDSE_ENAN, then QDSE_EDIVERGED, QDSE_ESPURIOUS,
+ *    QDSE_NOT_CONVERGED, QDSE_OK); qdse_solve_status gives each instance's.
  *  - A context is not thread-safe; distinct contexts are independent.
  */
 #ifndef QDSE_H
@@ -68,7 +72,34 @@ enum {
   QDSE_ENOMEM = -2,   /* device or host allocation failed                    */
   QDSE_EDEVICE = -3,  /* a HIP call failed (message via qdse_last_error)     */
   QDSE_ENAN = -4,     /* an iterate became NaN or infinite                   */
-  QDSE_ENOTSUP = -5   /* option not available for this context              */
+  QDSE_ENOTSUP = -5,  /* option not available for this context              */
+  QDSE_EDIVERGED = -6, /* successive approximation ended without passing
+                          its test after the test statistic had risen above
+                          100 times its smallest value (checked from sweep
+                          30 on, at the host's reads of the solve state):
+                          the sweep does not contract near the iterate (the
+                          paper's iteration assumes it does)             */
+  QDSE_ESPURIOUS = -7  /* the test of eq. jifenab2 passed at a fixed point
+                          that fails the branch certificate: A <= 0 at some
+                          node, A < 1 - 1e-9 at some node (not checked in
+                          the renormalised setting), or M = B/A rising from
+                          one node to the next by more than 1e-6 max|M|
+                          where |M| > 1e-3 max|M|;
+                          the physical (Nambu) solution has A = 1 +
+                          Sigma_A >= 1 and a mass function falling with
+                          p^2 (m >= 0)                                   */
+};
+
+/* Driver of qdse_solve (set at qdse_setup). */
+enum {
+  QDSE_PICARD = 0,  /* successive approximation, Sec. I eq. jifen12 (the paper's)  */
+  QDSE_NEWTON = 1,  /* Newton's method on F(x) - x from the initial functions:
+                       each step solves (I - J) dx = F(x) - x by restarted GMRES
+                       with Jacobian-vector products; at most 40 steps        */
+  QDSE_AUTO = 2     /* successive approximation, then Newton from the initial
+                       functions for every instance that did not end at a
+                       certified fixed point (not converged, diverged,
+                       spurious or non-finite)                               */
 };
 
 /* Arithmetic of the contraction over loop nodes, the only O(N^2) step. */
@@ -92,13 +123,14 @@ enum {
  * `params[inst]` (instances with equal omega share one set of matrices).
  * precision: QDSE_FP64, QDSE_FP32_REFINE or QDSE_FP64_MATRIX (the last two
  * build the matrices of the matrix-core sweeps and need one common omega:
- * QDSE_ENOTSUP otherwise).
+ * QDSE_ENOTSUP otherwise). solver: QDSE_PICARD, QDSE_NEWTON or QDSE_AUTO,
+ * the driver of qdse_solve (Newton steps always use FP64 sweeps).
  * hip_stream: a hipStream_t (NULL = the null stream). On success *out owns all
  * device memory of the context until qdse_destroy.
- * Errors: QDSE_EINVAL (grid or params out of range, n_inst < 1, out == NULL),
- * QDSE_ENOMEM, QDSE_EDEVICE. */
+ * Errors: QDSE_EINVAL (grid or params out of range, n_inst < 1, unknown
+ * precision or solver, out == NULL), QDSE_ENOMEM, QDSE_EDEVICE. */
 int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst,
-               int precision, void* hip_stream, qdse_ctx** out);
+               int precision, int solver, void* hip_stream, qdse_ctx** out);
 
 /* Picks the launch shape of the context's sweep by timing the candidates on
  * its own batch (reps timed launches each, the kernels as a solve runs them):
@@ -167,8 +199,11 @@ int qdse_grid_nodes(const qdse_grid* grid, double* s, double* u, double* t, doub
 
 /* One sweep x_out = F(x_in) of the successive approximation (Sec. I eq.
  * jifen12) for every instance, in FP64. d_x_in, d_x_out: [n_inst][2N] device,
- * distinct buffers. Asynchronous. */
-int qdse_iterate(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
+ * distinct buffers. d_resid (device [n_inst], may be NULL): the paper's
+ * per-point test statistic of this sweep (Sec. II eq. jifenab2),
+ * max_i max(|A_out - A_in|, |B_out - B_in|), per instance (NaN if any value
+ * is NaN). Asynchronous. */
+int qdse_iterate(qdse_ctx* ctx, const double* d_x_in, double* d_x_out, double* d_resid);
 
 /* Same sweep with the FP32 MFMA contraction (context set up with
  * QDSE_FP32_REFINE, else QDSE_ENOTSUP). Asynchronous. */
@@ -178,26 +213,40 @@ int qdse_iterate_fp32(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
  * with QDSE_FP32_REFINE or QDSE_FP64_MATRIX, else QDSE_ENOTSUP). Asynchronous. */
 int qdse_iterate_fp64_matrix(qdse_ctx* ctx, const double* d_x_in, double* d_x_out);
 
-/* Successive approximation from the initial functions in d_x (Sec. II eq.
- * jifenab1 gives A0 = B0 = 1; any start is accepted) until the test `conv_mode`
- * holds with tolerance tol (Sec. II eq. jifenab2) or max_iter sweeps are done;
- * each instance stops at its own first passing sweep. d_x is overwritten with
- * the last iterate of every instance. iters[n_inst] (host, may be NULL):
- * sweeps done; resid[n_inst] (host, may be NULL): the test statistic of the
- * last sweep. Returns QDSE_OK if every instance passed, QDSE_NOT_CONVERGED if
- * some hit max_iter, QDSE_ENAN if some iterate became non-finite.
- * Synchronises the stream. */
+/* Solve from the initial functions in d_x (Sec. II eq. jifenab1 gives
+ * A0 = B0 = 1; any start is accepted) with the context's driver.
+ * QDSE_PICARD: successive approximation until the test `conv_mode` holds with
+ * tolerance tol (Sec. II eq. jifenab2) or max_iter sweeps are done; each
+ * instance stops at its own first passing sweep. QDSE_NEWTON: Newton steps
+ * (at most min(max_iter, 40)) until the same test, applied to the sweep
+ * x -> F(x) at the current iterate, holds. QDSE_AUTO: successive
+ * approximation, then Newton from the initial functions for the instances
+ * whose outcome is not QDSE_OK. Every converged instance is checked against
+ * the branch certificate (QDSE_ESPURIOUS). d_x is overwritten with the last
+ * iterate of every instance. iters[n_inst] (host, may be NULL): evaluations
+ * per instance (sweeps, plus Newton's sweeps and Jacobian-vector products,
+ * each about one sweep of work); resid[n_inst] (host, may be NULL): the last
+ * test statistic. Returns the most severe per-instance outcome: QDSE_OK,
+ * QDSE_NOT_CONVERGED (max_iter reached), QDSE_ESPURIOUS, QDSE_EDIVERGED or
+ * QDSE_ENAN (qdse_solve_status lists them). Synchronises the stream. */
 int qdse_solve(qdse_ctx* ctx, double* d_x, double tol, int max_iter, int conv_mode,
                int* iters, double* resid);
+
+/* Per-instance outcome of the last qdse_solve, qdse_solve_group or
+ * qdse_newton of ctx: status[n_inst] (host) receives QDSE_OK,
+ * QDSE_NOT_CONVERGED, QDSE_ESPURIOUS, QDSE_EDIVERGED or QDSE_ENAN
+ * (QDSE_NOT_CONVERGED before any solve). Errors: QDSE_EINVAL. */
+int qdse_solve_status(const qdse_ctx* ctx, int* status);
 
 /* The same solve for several contexts at once (for example one per grid
  * class of a mixed batch): ctxs[n_ctx] distinct contexts, d_x[q] the device
  * unknowns of context q, iters[q] / resid[q] host arrays of its n_inst
  * entries (the outer arrays may be NULL, or any entry). Each context runs its
  * own phases on its own stream; the contexts' work overlaps only if their
- * streams differ (set at qdse_setup). Returns QDSE_OK if every instance of
- * every context passed, else the most severe code of any context (a
- * negative code before QDSE_NOT_CONVERGED); outputs as for qdse_solve.
+ * streams differ (set at qdse_setup). QDSE_AUTO contexts hand their
+ * uncertified instances to Newton afterwards, one context at a time;
+ * QDSE_NEWTON contexts are refused (QDSE_ENOTSUP: call qdse_solve). Returns
+ * the most severe outcome of any instance; outputs as for qdse_solve.
  * Synchronises every context's stream. */
 int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int max_iter,
                      int conv_mode, int** iters, double** resid);
@@ -205,11 +254,14 @@ int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int m
 /* Newton's method on the fixed-point residual R(x) = F(x) - x for every
  * instance, for fixed points where successive approximation does not contract:
  * each step solves (I - J) dx = R by restarted GMRES with Jacobian-vector
- * products (to ||.||_2 relative tolerance lin_tol) and sets x += dx. Stops when
- * max_i |R_i| < tol for every instance or after max_newton steps. d_x: in
- * initial guess, out last iterate. steps[n_inst], resid[n_inst] (host, may be
- * NULL): Newton steps and final max|R|. Returns QDSE_OK, QDSE_NOT_CONVERGED or
- * QDSE_ENAN. Synchronises the stream. */
+ * products (to ||.||_2 relative tolerance lin_tol) and sets x += dx. An
+ * instance stops when max_i |R_i| < tol (the norm is reduced on the device)
+ * or after max_newton steps; converged instances are checked against the
+ * branch certificate. d_x: in initial guess, out last iterate. steps[n_inst],
+ * resid[n_inst] (host, may be NULL): Newton steps and final max|R|. The
+ * Krylov workspace is allocated by the context on its first Newton or
+ * adjoint solve and reused afterwards. Returns QDSE_OK, QDSE_NOT_CONVERGED,
+ * QDSE_ESPURIOUS or QDSE_ENAN. Synchronises the stream. */
 int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double lin_tol,
                 int* steps, double* resid);
 

@@ -449,15 +449,27 @@ def continuation(g, p, x0, steps=10, tol=1e-13, nthreads=None):
 
 
 def certificate(g, p, x, nthreads=None):
-    """Physical-branch checks of a fixed point: residual, positivity of A and
-    absence of node-to-node sign alternation in the mass function."""
+    """Physical-branch checks of a fixed point (the reading of a certified
+    solution of the unrenormalised equation): residual max|F(x) - x|; A > 0
+    at every node; A >= 1 (A = 1 + Sigma_A; up to 1e-9); the mass function
+    M = B/A falling with p^2 for m >= 0 (a rise counts if it exceeds 1e-6
+    max|M| where |M| exceeds 1e-3 max|M|: the chiral-limit tail of B changes
+    sign at the 1e-6 level); and, for information, the number of
+    node-to-node sign changes of the slope of M.
+    certified = A_pos and A_ge_1 and M_falls."""
     n = g.n
     A, B = x[:n], x[n:]
+    M = B / A
     R = residual(g, p, x, nthreads)
-    dM = np.diff(B / A)
+    dM = np.diff(M)
     flips = int(np.sum(dM[1:] * dM[:-1] < 0))
-    return {"resid": float(np.max(np.abs(R))), "A_pos": bool(np.all(A > 0)),
-            "slope_flips": flips}
+    a_pos = bool(np.all(A > 0))
+    a_ge_1 = bool(np.all(A >= 1 - 1e-9))
+    big = np.maximum(np.abs(M[:-1]), np.abs(M[1:])) > 1e-3 * np.max(np.abs(M))
+    m_falls = not bool(np.any((dM > 1e-6 * np.max(np.abs(M))) & big))
+    return {"resid": float(np.max(np.abs(R))), "A_pos": a_pos, "A_ge_1": a_ge_1,
+            "M_falls": m_falls, "slope_flips": flips,
+            "certified": a_pos and a_ge_1 and m_falls}
 
 
 def spectral_radius(g, p, x, nthreads=None):

@@ -11,6 +11,8 @@ _LIBPATH = os.path.join(_HERE, "libqdse.so")
 
 QDSE_OK, QDSE_NOT_CONVERGED = 0, 1
 QDSE_EINVAL, QDSE_ENOMEM, QDSE_EDEVICE, QDSE_ENAN, QDSE_ENOTSUP = -1, -2, -3, -4, -5
+QDSE_EDIVERGED, QDSE_ESPURIOUS = -6, -7
+QDSE_PICARD, QDSE_NEWTON, QDSE_AUTO = 0, 1, 2
 QDSE_FP64, QDSE_FP32_REFINE, QDSE_FP64_MATRIX = 0, 1, 2
 QDSE_CONV_ABS, QDSE_CONV_MASS = 0, 1
 
@@ -73,7 +75,7 @@ def load():
         raise RuntimeError(f"{_LIBPATH} is missing: build it with paper_2012_03667_amd/build.py")
     L = ctypes.CDLL(_LIBPATH)
     L.qdse_setup.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.c_int,
-                             ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+                             ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
     L.qdse_setup_qc.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.c_int,
                                 ctypes.POINTER(Qc), _vp, ctypes.POINTER(_vp)]
     L.qdse_destroy.argtypes = [_vp]
@@ -81,7 +83,7 @@ def load():
     L.qdse_dims.argtypes = [_vp, _ip, _ip, _ip, _ip]
     L.qdse_nodes.argtypes = [_vp, _dp, _dp]
     L.qdse_grid_nodes.argtypes = [ctypes.POINTER(Grid)] + [_dp] * 6
-    L.qdse_iterate.argtypes = [_vp, _vp, _vp]
+    L.qdse_iterate.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_iterate_fp32.argtypes = [_vp, _vp, _vp]
     L.qdse_iterate_fp64_matrix.argtypes = [_vp, _vp, _vp]
     L.qdse_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp]
@@ -89,6 +91,7 @@ def load():
                                    ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(_ip), ctypes.POINTER(_dp)]
     L.qdse_solve_stats.argtypes = [_vp, _ip, _ip]
+    L.qdse_solve_status.argtypes = [_vp, _ip]
     L.qdse_newton.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]
     L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
     L.qdse_vjp.argtypes = [_vp, _vp, _vp, _vp]
@@ -139,6 +142,10 @@ def _last_error():
         return ""
 
 
+# outcomes of a solve that leave the iterate in the caller's array
+_OUTCOMES = (QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN, QDSE_EDIVERGED, QDSE_ESPURIOUS)
+
+
 def _check(code, what, allow=(QDSE_OK,)):
     if code not in allow:
         raise QdseError(code, what)
@@ -174,7 +181,7 @@ class Solver:
     """
 
     def __init__(self, n_radial, n_angle, params, interp_order=3, s_min=1e-4, s_max=1e4,
-                 precision=QDSE_FP64, stream=None, zeta=None, uv=1):
+                 precision=QDSE_FP64, stream=None, zeta=None, uv=1, solver=QDSE_PICARD):
         import torch
         L = load()
         self.n, self.na, self.order = int(n_radial), int(n_angle), int(interp_order)
@@ -186,7 +193,7 @@ class Solver:
         P = (Params * max(1, self.n_inst))(*[Params(*p) for p in self.params])
         h = _vp()
         if zeta is None:
-            _check(L.qdse_setup(ctypes.byref(g), P, self.n_inst, int(precision),
+            _check(L.qdse_setup(ctypes.byref(g), P, self.n_inst, int(precision), int(solver),
                                 _vp(self.stream.cuda_stream), ctypes.byref(h)), "qdse_setup")
         else:
             q = Qc(int(uv), float(zeta))
@@ -221,26 +228,41 @@ class Solver:
         x[:, self.n:] = B0
         return x
 
-    def iterate(self, x, out=None, fp32=False, matrix=False):
+    def iterate(self, x, out=None, fp32=False, matrix=False, resid=None):
         """One sweep: FP64 direct (default), FP32 MFMA (fp32=True) or FP64 MFMA
-        split form (matrix=True)."""
+        split form (matrix=True). resid (FP64 direct only): a float64 CUDA
+        tensor [n_inst] that receives the sweep's test statistic."""
         import torch
         if out is None:
             out = torch.empty_like(x)
-        fn = (load().qdse_iterate_fp32 if fp32 else
-              load().qdse_iterate_fp64_matrix if matrix else load().qdse_iterate)
-        _check(fn(self._h, _dev(x, self.shape, "x"), _dev(out, self.shape, "out")),
-               "qdse_iterate")
+        if fp32 or matrix:
+            if resid is not None:
+                raise ValueError("resid is returned by the FP64 direct sweep only")
+            fn = load().qdse_iterate_fp32 if fp32 else load().qdse_iterate_fp64_matrix
+            _check(fn(self._h, _dev(x, self.shape, "x"), _dev(out, self.shape, "out")),
+                   "qdse_iterate")
+            return out
+        r = None if resid is None else _dev(resid, (self.n_inst,), "resid")
+        _check(load().qdse_iterate(self._h, _dev(x, self.shape, "x"), _dev(out, self.shape, "out"),
+                                   r), "qdse_iterate")
         return out
 
     def solve(self, x, tol=1e-10, max_iter=1000, conv_mode=QDSE_CONV_MASS):
-        """In place. Returns (status, iters[n_inst], resid[n_inst])."""
+        """In place. Returns (status, iters[n_inst], resid[n_inst]); iters
+        counts evaluations (sweeps, and Newton's sweeps and Jacobian-vector
+        products); solve_status() gives each instance's outcome."""
         it = np.zeros(self.n_inst, dtype=np.int32)
         rs = np.zeros(self.n_inst)
         rc = load().qdse_solve(self._h, _dev(x, self.shape, "x"), float(tol), int(max_iter),
                                int(conv_mode), it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
-        _check(rc, "qdse_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+        _check(rc, "qdse_solve", allow=_OUTCOMES)
         return rc, it, rs
+
+    def solve_status(self):
+        """Per-instance outcome codes of the last solve."""
+        st = np.zeros(self.n_inst, dtype=np.int32)
+        _check(load().qdse_solve_status(self._h, st.ctypes.data_as(_ip)), "qdse_solve_status")
+        return st
 
     def newton(self, x, tol=1e-12, max_newton=30, lin_tol=1e-10):
         """In place Newton-Krylov. Returns (status, steps[n_inst], max|F(x)-x|[n_inst])."""
@@ -248,7 +270,7 @@ class Solver:
         rs = np.zeros(self.n_inst)
         rc = load().qdse_newton(self._h, _dev(x, self.shape, "x"), float(tol), int(max_newton),
                                 float(lin_tol), it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
-        _check(rc, "qdse_newton", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+        _check(rc, "qdse_newton", allow=_OUTCOMES)
         return rc, it, rs
 
     def solve_stats(self):
@@ -359,7 +381,7 @@ def solve_group(solvers, xs, tol=1e-10, max_iter=1000, conv_mode=QDSE_CONV_MASS)
     I = (_ip * n)(*[a.ctypes.data_as(_ip) for a in its])
     R = (_dp * n)(*[a.ctypes.data_as(_dp) for a in rss])
     rc = load().qdse_solve_group(H, n, X, float(tol), int(max_iter), int(conv_mode), I, R)
-    _check(rc, "qdse_solve_group", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
+    _check(rc, "qdse_solve_group", allow=_OUTCOMES)
     return rc, its, rss
 
 

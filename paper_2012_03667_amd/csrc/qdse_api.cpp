@@ -51,6 +51,77 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// Workspace of the batched Krylov solves (Newton-Krylov, adjoint): allocated
+// on the first solve that needs it and kept by the context (grown when a
+// larger restart length is requested); device buffers are zeroed once when
+// allocated, so no entry is ever read uninitialised.
+struct KrylovWork {
+  int nI = 0, mres = 0;
+  size_t L = 0;
+  double *V = nullptr, *w = nullptr, *r = nullptr, *h = nullptr, *y = nullptr, *sc = nullptr,
+         *z = nullptr, *F = nullptr, *dx = nullptr, *x0 = nullptr, *stat = nullptr,
+         *scale = nullptr;
+  int *act = nullptr, *cert = nullptr, *sel = nullptr;
+  // page-locked host mirrors (transfers from and to them are asynchronous)
+  double *tmp_h = nullptr, *hh_h = nullptr, *stat_h = nullptr, *scale_h = nullptr;
+  int *act_h = nullptr, *ones_h = nullptr, *cert_h = nullptr, *sel_h = nullptr;
+
+  void release() {
+    void* d[] = {V, w, r, h, y, sc, z, F, dx, x0, stat, scale, act, cert, sel};
+    for (void* p : d) dfree(p);
+    void* hp[] = {tmp_h, hh_h, stat_h, scale_h, act_h, ones_h, cert_h, sel_h};
+    for (void* p : hp)
+      if (p) (void)hipHostFree(p);
+    *this = KrylovWork{};
+  }
+  template <class T>
+  int host(T** p, size_t n) {
+    if (hipHostMalloc((void**)p, (n ? n : 1) * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+      *p = nullptr;
+      g_last_error = "hipHostMalloc failed";
+      return QDSE_ENOMEM;
+    }
+    std::memset(*p, 0, (n ? n : 1) * sizeof(T));
+    return QDSE_OK;
+  }
+  template <class T>
+  int dev(T** p, size_t n, hipStream_t st) {
+    int rc = dalloc(p, n);
+    if (rc) return rc;
+    if (hipMemsetAsync(*p, 0, (n ? n : 1) * sizeof(T), st) != hipSuccess) {
+      g_last_error = "hipMemsetAsync failed";
+      return QDSE_EDEVICE;
+    }
+    return QDSE_OK;
+  }
+  // buffers for nI instances of L doubles in total and restart length m
+  int ensure(int nI_, size_t L_, int m, hipStream_t st) {
+    if (V && nI == nI_ && L == L_ && mres >= m) return QDSE_OK;
+    release();
+    nI = nI_;
+    L = L_;
+    mres = m;
+    const size_t hstride = (size_t)nI * (mres + 1);
+    int rc;
+    if ((rc = dev(&V, (size_t)(mres + 1) * L, st)) || (rc = dev(&w, L, st)) ||
+        (rc = dev(&r, L, st)) || (rc = dev(&h, 2 * hstride + nI, st)) ||
+        (rc = dev(&y, hstride, st)) || (rc = dev(&sc, (size_t)nI, st)) || (rc = dev(&z, L, st)) ||
+        (rc = dev(&F, L, st)) || (rc = dev(&dx, L, st)) || (rc = dev(&x0, L, st)) ||
+        (rc = dev(&stat, (size_t)nI, st)) || (rc = dev(&scale, (size_t)nI, st)) ||
+        (rc = dev(&act, (size_t)nI, st)) || (rc = dev(&cert, (size_t)nI, st)) ||
+        (rc = dev(&sel, (size_t)nI, st)) || (rc = host(&tmp_h, (size_t)nI)) ||
+        (rc = host(&hh_h, 2 * hstride + nI)) || (rc = host(&stat_h, (size_t)nI)) ||
+        (rc = host(&scale_h, (size_t)nI)) || (rc = host(&act_h, (size_t)nI)) ||
+        (rc = host(&ones_h, (size_t)nI)) || (rc = host(&cert_h, (size_t)nI)) ||
+        (rc = host(&sel_h, (size_t)nI))) {
+      release();
+      return rc;
+    }
+    for (int k = 0; k < nI; ++k) ones_h[k] = 1;
+    return QDSE_OK;
+  }
+};
+
 }  // namespace
 
 struct qdse_ctx {
@@ -110,6 +181,10 @@ struct qdse_ctx {
   // private state for kernel timing
   SolveState* d_tstate = nullptr;
   SolveCtl* d_tctl = nullptr;
+  // driver of qdse_solve and the outcome of the last solve per instance
+  int solver = QDSE_PICARD;
+  std::vector<int> last_status, last_evals;
+  KrylovWork kw;
 };
 
 namespace {
@@ -156,13 +231,16 @@ size_t xlen(const qdse_ctx* c) { return (size_t)c->n_inst * 2 * c->hg.n; }
 extern "C" {
 
 static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_inst,
-                      int precision, const qdse_qc* qc, void* hip_stream, qdse_ctx** out) {
+                      int precision, int solver, const qdse_qc* qc, void* hip_stream,
+                      qdse_ctx** out) {
   if (!out) return QDSE_EINVAL;
   *out = nullptr;
   int rc = validate(grid, params, n_inst);
   if (rc) return rc;
   if (precision != QDSE_FP64 && precision != QDSE_FP32_REFINE && precision != QDSE_FP64_MATRIX)
     return QDSE_EINVAL;
+  if (solver != QDSE_PICARD && solver != QDSE_NEWTON && solver != QDSE_AUTO) return QDSE_EINVAL;
+  if (qc && solver != QDSE_PICARD) return QDSE_ENOTSUP;  // no tangent sweeps there
   if (qc) {
     const double z2 = qc->zeta * qc->zeta;
     if (!(qc->zeta > 0.0) || !(z2 > grid->s_min) || !(z2 < grid->s_max)) return QDSE_EINVAL;
@@ -174,6 +252,7 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
   c->grid = *grid;
   c->n_inst = n_inst;
   c->precision = precision;
+  c->solver = solver;
   c->params.assign(params, params + n_inst);
   c->stream = (hipStream_t)hip_stream;
   if (build_grid(*grid, &c->hg)) {
@@ -384,8 +463,8 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
 }
 
 int qdse_setup(const qdse_grid* grid, const qdse_params* params, int n_inst, int precision,
-               void* hip_stream, qdse_ctx** out) {
-  return setup_impl(grid, params, n_inst, precision, nullptr, hip_stream, out);
+               int solver, void* hip_stream, qdse_ctx** out) {
+  return setup_impl(grid, params, n_inst, precision, solver, nullptr, hip_stream, out);
 }
 
 int qdse_setup_qc(const qdse_grid* grid, const qdse_params* params, int n_inst,
@@ -394,7 +473,7 @@ int qdse_setup_qc(const qdse_grid* grid, const qdse_params* params, int n_inst,
     if (out) *out = nullptr;
     return QDSE_EINVAL;
   }
-  return setup_impl(grid, params, n_inst, QDSE_FP64, qc, hip_stream, out);
+  return setup_impl(grid, params, n_inst, QDSE_FP64, QDSE_PICARD, qc, hip_stream, out);
 }
 
 void qdse_destroy(qdse_ctx* c) {
@@ -412,6 +491,7 @@ void qdse_destroy(qdse_ctx* c) {
                   c->d_flags,   c->d_C32,     c->d_M64,     c->d_C64,     c->d_tstate,
                   c->d_tctl,    c->d_sK,      c->d_sig,     c->d_jdiag};
   for (void* p : ptrs) dfree(p);
+  c->kw.release();
   delete c;
 }
 
@@ -465,16 +545,18 @@ static hipError_t sweep_fp64(qdse_ctx* c, hipStream_t st, const double* xi, doub
                            1);
 }
 
-int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out) {
+int qdse_iterate(qdse_ctx* c, const double* d_x_in, double* d_x_out, double* d_resid) {
   if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
   const HostGrid& g = c->hg;
   if (c->qc) {
     HIPCHK(launch_qc_sweep(c->stream, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride,
                            c->d_lo, c->d_sw, c->d_t, c->d_s, c->zp, d_x_in, d_x_out, c->d_sig,
                            nullptr, nullptr, 1));
-    return QDSE_OK;
+  } else {
+    HIPCHK(sweep_fp64(c, c->stream, d_x_in, d_x_out, nullptr, nullptr, 1));
   }
-  HIPCHK(sweep_fp64(c, c->stream, d_x_in, d_x_out, nullptr, nullptr, 1));
+  if (d_resid)
+    HIPCHK(launch_conv_stat(c->stream, c->n_inst, g.n, QDSE_CONV_ABS, d_x_in, d_x_out, d_resid));
   return QDSE_OK;
 }
 
@@ -578,7 +660,18 @@ struct MaskedRun {
   std::vector<SolveState> snap;  // mirror as read at the last wait
   std::vector<double> r_prev;    // statistic of each instance at the previous read
   std::vector<int> s_prev;       // and the sweep count it belongs to
+  std::vector<double> r_min;     // smallest statistic seen so far per instance
+  std::vector<char> diverged;    // statistic rose above kDivergeFactor * r_min
 };
+
+// Divergence of successive approximation: after kDivergeAfter sweeps, a test
+// statistic that has risen above kDivergeFactor times the smallest one seen
+// so far (the sweep is not a contraction near the iterate), as sampled at the
+// host's reads of the solve state. An instance so marked that ends without
+// passing the test is reported as QDSE_EDIVERGED; one that later passes it is
+// judged by the branch certificate like any other.
+constexpr double kDivergeFactor = 100.0;
+constexpr int kDivergeAfter = 30;
 
 static int masked_launch(MaskedRun& r, int len) {
   qdse_ctx* c = r.c;
@@ -620,6 +713,8 @@ static int masked_begin(MaskedRun& r, qdse_ctx* c, double tol, int max_iter, int
   r.nq = 0;
   r.r_prev.assign(c->n_inst, -1.0);
   r.s_prev.assign(c->n_inst, 0);
+  r.r_min.assign(c->n_inst, HUGE_VAL);
+  r.diverged.assign(c->n_inst, 0);
   r.out = out;
   r.out_at = -1;
   HIPCHK(launch_solve_init(c->stream, c->n_inst, c->d_state, c->d_ctl,
@@ -679,8 +774,15 @@ static int masked_wait(MaskedRun& r, bool* over) {
   // move from running to frozen, and a frozen instance's entry no longer changes)
   r.snap.assign(c->h_state, c->h_state + c->n_inst);
   bool done = true;
-  for (int q = 0; q < c->n_inst; ++q)
-    if (r.snap[q].status == 0) done = false;
+  for (int q = 0; q < c->n_inst; ++q) {
+    const SolveState& h = r.snap[q];
+    if (h.status != 0) continue;
+    done = false;
+    double r1;  // statistic of sweep `sweeps` - 1
+    std::memcpy(&r1, &h.metric[0][0], sizeof(double));
+    if (h.sweeps >= 2 && r1 < r.r_min[q]) r.r_min[q] = r1;
+    if (h.sweeps >= kDivergeAfter && r1 > kDivergeFactor * r.r_min[q]) r.diverged[q] = 1;
+  }
   r.all_done = done;
   *over = done || read >= r.limit;
   if (*over) return QDSE_OK;  // chunks still in flight only carry frozen iterates along
@@ -703,18 +805,68 @@ static int masked_wait(MaskedRun& r, bool* over) {
 
 static void masked_state(const MaskedRun& r, std::vector<SolveState>& hs) { hs = r.snap; }
 
-static int finish_solve(qdse_ctx* c, const std::vector<SolveState>& hs, bool all_done, int* iters,
-                        double* resid) {
-  int rc = QDSE_OK;
-  for (int k = 0; k < c->n_inst; ++k) {
-    const SolveState& s = hs[k];
-    if (iters) iters[k] = s.sweeps;
-    if (resid) resid[k] = s.resid;
-    if (s.status == 3) rc = QDSE_ENAN;
-    else if ((s.status == 2 || s.status == 0) && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
+// Rank of a per-instance outcome: a batch returns its most severe one.
+static int severity(int code) {
+  switch (code) {
+    case QDSE_OK: return 0;
+    case QDSE_NOT_CONVERGED: return 1;
+    case QDSE_ESPURIOUS: return 2;
+    case QDSE_EDIVERGED: return 3;
+    case QDSE_ENAN: return 4;
+    default: return 5;
   }
-  if (!all_done && rc == QDSE_OK) rc = QDSE_NOT_CONVERGED;
-  return rc;
+}
+
+static int worst_of(const std::vector<int>& codes) {
+  int w = QDSE_OK;
+  for (int v : codes)
+    if (severity(v) > severity(w)) w = v;
+  return w;
+}
+
+// Branch certificate of the iterates d_x on the device (k_certify); cert_h
+// receives the flags of every instance. Synchronises the stream.
+static int certify(qdse_ctx* c, const double* d_x, std::vector<int>& cert) {
+  int rc = c->kw.ensure(c->n_inst, xlen(c), 1, c->stream);
+  if (rc) return rc;
+  hipStream_t st = c->stream;
+  HIPCHK(launch_certify(st, c->n_inst, c->hg.n, c->qc ? 0 : 1, d_x, c->kw.cert));
+  HIPCHK(hipMemcpyAsync(c->kw.cert_h, c->kw.cert, c->n_inst * sizeof(int), hipMemcpyDeviceToHost,
+                        st));
+  HIPCHK(hipStreamSynchronize(st));
+  cert.assign(c->kw.cert_h, c->kw.cert_h + c->n_inst);
+  return QDSE_OK;
+}
+
+// Outcome of every instance of a successive-approximation solve whose final
+// iterate is d_x: the solve state read back from the device after the
+// stream has drained (not the mirror), the host's divergence flags, and the
+// branch certificate of the iterate. Fills c->last_status / last_evals.
+static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diverged,
+                        const std::vector<int>& sweeps_before, int* iters, double* resid) {
+  const int nI = c->n_inst;
+  std::vector<SolveState> hs(nI);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(hs.data(), c->d_state, nI * sizeof(SolveState), hipMemcpyDeviceToHost));
+  std::vector<int> cert;
+  int rc = certify(c, d_x, cert);
+  if (rc) return rc;
+  c->last_status.assign(nI, QDSE_OK);
+  c->last_evals.assign(nI, 0);
+  c->last_sweeps64.assign(nI, 0);
+  for (int k = 0; k < nI; ++k) {
+    const SolveState& h = hs[k];
+    int code;
+    if (h.status == 3) code = QDSE_ENAN;
+    else if (h.status == 1) code = cert[k] ? QDSE_ESPURIOUS : QDSE_OK;
+    else code = (k < (int)diverged.size() && diverged[k]) ? QDSE_EDIVERGED : QDSE_NOT_CONVERGED;
+    c->last_status[k] = code;
+    c->last_sweeps64[k] = h.sweeps;
+    c->last_evals[k] = h.sweeps + (k < (int)sweeps_before.size() ? sweeps_before[k] : 0);
+    if (iters) iters[k] = c->last_evals[k];
+    if (resid) resid[k] = h.resid;
+  }
+  return worst_of(c->last_status);
 }
 
 // One cooperative launch runs the whole solve (qdse_persistent.hip); the
@@ -726,10 +878,7 @@ static int solve_persistent(qdse_ctx* c, double* d_x, int* iters, double* resid)
                            c->d_t, c->d_s, c->d_xbuf[0], c->d_xbuf[1], c->d_state, c->d_ctl,
                            c->d_slots, c->d_barrier, c->d_flags, c->persist_G, c->persist_rpw,
                            c->persist_gsz, std::getenv("QDSE_PERSIST_PLAIN") ? 0 : 1));
-  std::vector<SolveState> hs(c->n_inst);
   int flags[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(hs.data(), c->d_state, hs.size() * sizeof(SolveState),
-                        hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(flags, c->d_flags, sizeof(flags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (flags[0] != 0) {
@@ -738,8 +887,7 @@ static int solve_persistent(qdse_ctx* c, double* d_x, int* iters, double* resid)
   }
   HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[flags[1] & 1], xlen(c) * sizeof(double),
                         hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return finish_solve(c, hs, true, iters, resid);
+  return finish_solve(c, d_x, std::vector<char>(), std::vector<int>(), iters, resid);
 }
 
 }  // extern "C"
@@ -756,8 +904,8 @@ struct GroupEntry {
   double* resid;
   MaskedRun run;
   int phase = 0;  // 0: first phase, 1: FP64 after FP32, 2: finished
-  bool all_done = false;
   std::vector<SolveState> hs;
+  std::vector<char> diverged;  // in any phase
   int rc = QDSE_OK;
 };
 
@@ -795,6 +943,8 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
       if (!over) continue;
       qdse_ctx* c = g.c;
       masked_state(g.run, g.hs);
+      if (g.diverged.empty()) g.diverged.assign(c->n_inst, 0);
+      for (int k = 0; k < c->n_inst; ++k) g.diverged[k] |= g.run.diverged[k];
       if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
         for (int k = 0; k < c->n_inst; ++k) c->last_sweeps32[k] = g.hs[k].sweeps;
         g.phase = 1;
@@ -802,11 +952,6 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
         if (rc) return rc;
         continue;
       }
-      for (int k = 0; k < c->n_inst; ++k) {
-        c->last_sweeps64[k] = g.hs[k].sweeps;
-        g.hs[k].sweeps += c->last_sweeps32[k];
-      }
-      g.all_done = g.run.all_done;
       if (g.run.out_at != g.run.launched)  // not yet enqueued behind the last chunk
         HIPCHK(hipMemcpyAsync(g.d_x, c->d_xbuf[0], xlen(c) * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
@@ -816,10 +961,8 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
   }
   int worst = QDSE_OK;
   for (GroupEntry& g : G) {
-    HIPCHK(hipStreamSynchronize(g.c->stream));
-    g.rc = finish_solve(g.c, g.hs, g.all_done, g.iters, g.resid);
-    if (g.rc < 0 ? (worst >= 0 || g.rc < worst) : (worst == QDSE_OK && g.rc != QDSE_OK))
-      worst = g.rc;
+    g.rc = finish_solve(g.c, g.d_x, g.diverged, g.c->last_sweeps32, g.iters, g.resid);
+    if (severity(g.rc) > severity(worst)) worst = g.rc;
   }
   return worst;
 }
@@ -828,11 +971,101 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+int newton_impl(qdse_ctx* c, double* d_x, double tol, int mode, int max_newton, double lin_tol,
+                const std::vector<char>& want, std::vector<int>& status, std::vector<int>& steps,
+                std::vector<int>& evals, std::vector<double>& resid);
+int newton_outcome(qdse_ctx* c, const double* d_x, std::vector<int>& status);
+}  // namespace
+
+extern "C" {
+
+// Newton steps at most in the NEWTON and AUTO drivers of qdse_solve, and the
+// relative tolerance of each step's Krylov solve.
+constexpr int kSolveNewtonSteps = 40;
+constexpr double kSolveNewtonLinTol = 1e-10;
+
+// AUTO: the instances whose successive approximation did not end at a
+// certified fixed point restart from their initial functions (saved in
+// kw.x0) with Newton's method. Updates c->last_status and last_evals and the
+// host outputs of those instances.
+static int auto_fallback(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode,
+                         int* iters, double* resid) {
+  const int nI = c->n_inst;
+  std::vector<char> redo(nI, 0);
+  bool any = false;
+  for (int k = 0; k < nI; ++k)
+    if (c->last_status[k] != QDSE_OK) redo[k] = any = 1;
+  if (!any) return worst_of(c->last_status);
+  KrylovWork& W = c->kw;
+  hipStream_t st = c->stream;
+  for (int k = 0; k < nI; ++k) W.sel_h[k] = redo[k];
+  HIPCHK(hipMemcpyAsync(W.sel, W.sel_h, nI * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_select(st, nI, 2 * c->hg.n, W.sel, W.x0, d_x));
+  std::vector<int> status, steps, evals;
+  std::vector<double> rs;
+  const std::vector<int> before = c->last_evals;
+  const std::vector<int> prev = c->last_status;
+  int rc = newton_impl(c, d_x, tol, conv_mode, std::min(max_iter, kSolveNewtonSteps),
+                       kSolveNewtonLinTol, redo, status, steps, evals, rs);
+  if (rc) return rc;
+  rc = newton_outcome(c, d_x, status);
+  if (rc < 0 && severity(rc) > severity(QDSE_ENAN)) return rc;
+  for (int k = 0; k < nI; ++k) {
+    if (!redo[k]) {
+      c->last_status[k] = prev[k];
+      continue;
+    }
+    c->last_evals[k] = before[k] + evals[k];
+    if (iters) iters[k] = c->last_evals[k];
+    if (resid) resid[k] = rs[k];
+  }
+  return worst_of(c->last_status);
+}
+
+// NEWTON: Newton's method from the initial functions for every instance.
+static int newton_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode,
+                        int* iters, double* resid) {
+  std::vector<int> status, steps, evals;
+  std::vector<double> rs;
+  c->last_sweeps32.assign(c->n_inst, 0);
+  c->last_sweeps64.assign(c->n_inst, 0);
+  int rc = newton_impl(c, d_x, tol, conv_mode, std::min(max_iter, kSolveNewtonSteps),
+                       kSolveNewtonLinTol, std::vector<char>(c->n_inst, 1), status, steps, evals,
+                       rs);
+  if (rc) return rc;
+  rc = newton_outcome(c, d_x, status);
+  if (rc < 0 && severity(rc) > severity(QDSE_ENAN)) return rc;
+  c->last_evals = evals;
+  for (int k = 0; k < c->n_inst; ++k) {
+    if (iters) iters[k] = evals[k];
+    if (resid) resid[k] = rs[k];
+  }
+  return worst_of(c->last_status);
+}
+
+// AUTO keeps a copy of the initial functions for the fallback.
+static int save_start(qdse_ctx* c, const double* d_x) {
+  int rc = c->kw.ensure(c->n_inst, xlen(c), 120, c->stream);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->kw.x0, d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
+                        c->stream));
+  return QDSE_OK;
+}
+
 int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode, int* iters,
                double* resid) {
   if (!c || !d_x || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
   if (conv_mode != QDSE_CONV_ABS && conv_mode != QDSE_CONV_MASS) return QDSE_EINVAL;
-  if (c->precision == QDSE_FP64 && c->persist_G > 0 && std::getenv("QDSE_PERSISTENT") != nullptr) {
+  if (c->solver == QDSE_NEWTON) return newton_solve(c, d_x, tol, max_iter, conv_mode, iters, resid);
+  if (c->solver == QDSE_AUTO) {
+    int rc = save_start(c, d_x);
+    if (rc) return rc;
+  }
+  if (c->solver == QDSE_PICARD && c->precision == QDSE_FP64 && c->persist_G > 0 &&
+      std::getenv("QDSE_PERSISTENT") != nullptr) {
     hipStream_t st = c->stream;
     c->last_sweeps32.assign(c->n_inst, 0);
     c->last_sweeps64.assign(c->n_inst, 0);
@@ -841,21 +1074,24 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
     SolveCtl ctl{tol, conv_mode, max_iter};
     HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
     HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
-    int rc = solve_persistent(c, d_x, iters, resid);
-    if (rc >= 0 && c->n_inst > 0) {
-      std::vector<SolveState> h2(c->n_inst);
-      (void)hipMemcpy(h2.data(), c->d_state, h2.size() * sizeof(SolveState),
-                      hipMemcpyDeviceToHost);
-      for (int k = 0; k < c->n_inst; ++k) c->last_sweeps64[k] = h2[k].sweeps;
-    }
-    return rc;
+    return solve_persistent(c, d_x, iters, resid);
   }
   std::vector<GroupEntry> G(1);
   G[0].c = c;
   G[0].d_x = d_x;
   G[0].iters = iters;
   G[0].resid = resid;
-  return solve_group(G, tol, max_iter, conv_mode);
+  int rc = solve_group(G, tol, max_iter, conv_mode);
+  if (c->solver == QDSE_AUTO && (rc == QDSE_OK || severity(rc) <= severity(QDSE_ENAN)))
+    rc = auto_fallback(c, d_x, tol, max_iter, conv_mode, iters, resid);
+  return rc;
+}
+
+int qdse_solve_status(const qdse_ctx* c, int* status) {
+  if (!c || !status) return QDSE_EINVAL;
+  for (int k = 0; k < c->n_inst; ++k)
+    status[k] = k < (int)c->last_status.size() ? c->last_status[k] : QDSE_NOT_CONVERGED;
+  return QDSE_OK;
 }
 
 int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int max_iter,
@@ -871,8 +1107,23 @@ int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int m
     G[q].d_x = d_x[q];
     G[q].iters = iters ? iters[q] : nullptr;
     G[q].resid = resid ? resid[q] : nullptr;
+    if (ctxs[q]->solver == QDSE_NEWTON) return QDSE_ENOTSUP;  // use qdse_solve per context
   }
-  return solve_group(G, tol, max_iter, conv_mode);
+  for (int q = 0; q < n_ctx; ++q)
+    if (ctxs[q]->solver == QDSE_AUTO) {
+      int rc = save_start(ctxs[q], d_x[q]);
+      if (rc) return rc;
+    }
+  int worst = solve_group(G, tol, max_iter, conv_mode);
+  if (worst != QDSE_OK && severity(worst) > severity(QDSE_ENAN)) return worst;  // device errors
+  worst = QDSE_OK;
+  for (int q = 0; q < n_ctx; ++q) {
+    int rc = G[q].rc;
+    if (ctxs[q]->solver == QDSE_AUTO)
+      rc = auto_fallback(ctxs[q], d_x[q], tol, max_iter, conv_mode, G[q].iters, G[q].resid);
+    if (severity(rc) > severity(worst)) worst = rc;
+  }
+  return worst;
 }
 
 int qdse_solve_stats(const qdse_ctx* c, int* sweeps_fp32, int* sweeps_fp64) {
@@ -1012,9 +1263,20 @@ struct Pinned {
 // (its flag in the device activity mask drops to 0, its later basis vectors
 // are zero and their coefficients too); every restart recomputes the true
 // residual of every instance. Returns QDSE_OK or QDSE_NOT_CONVERGED.
+// Host view of a page-locked array of the Krylov workspace.
+template <class T>
+struct HostArr {
+  T* p;
+  T& operator[](size_t i) { return p[i]; }
+  T* data() { return p; }
+};
+
+// inst_steps (may be null): operator applications per instance while it was
+// active in a cycle.
 template <class Op, class Prec>
 int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double* d_b,
-                  double* d_sol, double tol, int max_iter, int* steps_out) {
+                  double* d_sol, double tol, int max_iter, int* steps_out,
+                  std::vector<int>* inst_steps = nullptr) {
   const int nI = c->n_inst, len = 2 * c->hg.n;
   const size_t L = xlen(c);
   // restart length: the Jacobian is strongly non-normal (||J|| ~ 2 with a tight
@@ -1022,26 +1284,18 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
   // discard the Krylov information that cluster needs
   const int mres = std::max(1, std::min(max_iter, 120));
   hipStream_t st = c->stream;
-  DevBufs buf;
-  double *d_V, *d_w, *d_r, *d_h, *d_y, *d_sc, *d_z = nullptr;
-  int* d_act;
-  int rc;
-  if (use_prec && (rc = buf.alloc(&d_z, L))) return rc;
-  // d_h: two Gram-Schmidt passes [2][nI][mres + 1] followed by the norms [nI]
-  const size_t hstride = (size_t)nI * (mres + 1);
-  if ((rc = buf.alloc(&d_V, (size_t)(mres + 1) * L)) || (rc = buf.alloc(&d_w, L)) ||
-      (rc = buf.alloc(&d_r, L)) || (rc = buf.alloc(&d_h, 2 * hstride + nI)) ||
-      (rc = buf.alloc(&d_y, (size_t)nI * (mres + 1))) || (rc = buf.alloc(&d_sc, (size_t)nI)) ||
-      (rc = buf.alloc(&d_act, (size_t)nI)))
-    return rc;
-  // transfer buffers page-locked; the Hessenberg matrices stay uninitialised
-  // (every entry the back substitution reads is written in its cycle)
-  Pinned<double> tmp, hh;
-  Pinned<int> act, ones;
-  if ((rc = tmp.alloc(nI)) || (rc = hh.alloc(2 * hstride + nI)) || (rc = act.alloc(nI)) ||
-      (rc = ones.alloc(nI)))
-    return rc;
-  for (int k = 0; k < nI; ++k) act[k] = ones[k] = 1;
+  int rc = c->kw.ensure(nI, L, mres, st);
+  if (rc) return rc;
+  KrylovWork& W = c->kw;
+  // d_h: two Gram-Schmidt passes [2][nI][j + 1] followed by the norms [nI]
+  double *d_V = W.V, *d_w = W.w, *d_r = W.r, *d_h = W.h, *d_y = W.y, *d_sc = W.sc, *d_z = W.z;
+  int* d_act = W.act;
+  // transfer buffers page-locked; the Hessenberg matrices are filled before
+  // the back substitution reads them
+  HostArr<double> tmp{W.tmp_h}, hh{W.hh_h};
+  HostArr<int> act{W.act_h}, ones{W.ones_h};
+  for (int k = 0; k < nI; ++k) act[k] = 1;
+  if (inst_steps) inst_steps->assign(nI, 0);
   std::vector<double> bnorm(nI);
   std::vector<int> kd(nI, 0);
   int n_act = nI;
@@ -1091,6 +1345,8 @@ int gmres_batched(qdse_ctx* c, Op apply, Prec prec, bool use_prec, const double*
     int kdim = 0;
     for (int j = 0; j < mres && total < max_iter; ++j) {
       ++total;
+      if (inst_steps)
+        for (int k = 0; k < nI; ++k) (*inst_steps)[k] += act[k] ? 1 : 0;
       double* vj = d_V + (size_t)j * L;
       double* vn = d_V + (size_t)(j + 1) * L;
       const double* zj = vj;
@@ -1221,6 +1477,96 @@ bool band_prec_enabled() {
   return !(e && e[0] == '0');
 }
 
+// Newton's method on R(x) = F(x) - x for the instances with want[k] != 0
+// (the others are left unchanged): each step solves (I - J) dx = R by the
+// batched restarted GMRES with Jacobian-vector products and sets x += dx. An
+// instance stops when the test statistic (mode) of the sweep x -> F(x) is
+// below tol (status QDSE_OK), when it is not finite (QDSE_ENAN), or after
+// max_newton steps (QDSE_NOT_CONVERGED). The statistic is reduced on the
+// device; only one number per instance reaches the host per step. Per
+// instance: status, steps, evaluations (sweeps and Jacobian-vector products,
+// each about one sweep of work) and the last statistic. The workspace is the
+// context's (allocated on first use). Synchronises the stream.
+int newton_impl(qdse_ctx* c, double* d_x, double tol, int mode, int max_newton, double lin_tol,
+                const std::vector<char>& want, std::vector<int>& status, std::vector<int>& steps,
+                std::vector<int>& evals, std::vector<double>& resid) {
+  const HostGrid& g = c->hg;
+  const int nI = c->n_inst, len = 2 * g.n;
+  hipStream_t st = c->stream;
+  int rc = c->kw.ensure(nI, xlen(c), 120, st);
+  if (rc) return rc;
+  KrylovWork& W = c->kw;
+  status.assign(nI, QDSE_NOT_CONVERGED);
+  steps.assign(nI, 0);
+  evals.assign(nI, 0);
+  resid.assign(nI, HUGE_VAL);
+  std::vector<char> active(want.begin(), want.end());
+  active.resize(nI, 0);
+  for (int k = 0; k < nI; ++k)
+    if (!active[k]) status[k] = QDSE_OK;  // not handed over: untouched
+  auto apply = [&](const double* in, double* out_, const int* d_act, int) -> int {  // (I - J(x)) v
+    HIPCHK(launch_jvp(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo, c->d_sw,
+                      c->d_t, c->d_s, d_x, in, out_, c->d_nodes, d_act));
+    HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));
+    return QDSE_OK;
+  };
+  auto no_prec = [](const double*, double*, const int*) -> int { return QDSE_OK; };
+  std::vector<int> gsteps;
+  for (int it = 0;; ++it) {
+    // F(x), then the test statistic of x -> F(x) per instance, on the device
+    HIPCHK(sweep_fp64(c, st, d_x, W.F, nullptr, nullptr, 1));
+    HIPCHK(launch_conv_stat(st, nI, g.n, mode, d_x, W.F, W.stat));
+    HIPCHK(hipMemcpyAsync(W.stat_h, W.stat, nI * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int n_act = 0;
+    for (int k = 0; k < nI; ++k) {
+      if (!active[k]) continue;
+      ++evals[k];
+      const double r = W.stat_h[k];
+      resid[k] = r;
+      if (!(r <= 1.7976931348623157e308)) {
+        status[k] = QDSE_ENAN;
+        active[k] = 0;
+      } else if (r < tol) {
+        status[k] = QDSE_OK;
+        active[k] = 0;
+      } else if (it >= max_newton) {
+        active[k] = 0;  // stays QDSE_NOT_CONVERGED
+      } else {
+        ++n_act;
+      }
+    }
+    if (n_act == 0) break;
+    // R = F(x) - x on the active instances, 0 on the others (their GMRES
+    // right-hand side vanishes, so they take no Krylov steps and dx = 0)
+    for (int k = 0; k < nI; ++k) W.scale_h[k] = active[k] ? 1.0 : 0.0;
+    HIPCHK(hipMemcpyAsync(W.scale, W.scale_h, nI * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_axpby(st, nI, len, -1.0, d_x, nullptr, W.F, W.F));
+    HIPCHK(launch_axpby(st, nI, len, 0.0, nullptr, W.scale, W.F, W.F));
+    rc = gmres_batched(c, apply, no_prec, false, W.F, W.dx, lin_tol, 400, nullptr, &gsteps);
+    if (rc < 0) return rc;
+    for (int k = 0; k < nI; ++k)
+      if (active[k]) {
+        evals[k] += gsteps[k];
+        ++steps[k];
+      }
+    HIPCHK(launch_axpby(st, nI, len, 1.0, d_x, nullptr, W.dx, d_x));  // x += dx
+  }
+  return QDSE_OK;
+}
+
+// Branch certificate of the instances Newton declared converged: A <= 0 or an
+// alternating mass function makes them QDSE_ESPURIOUS. Sets c->last_status.
+int newton_outcome(qdse_ctx* c, const double* d_x, std::vector<int>& status) {
+  std::vector<int> cert;
+  int rc = certify(c, d_x, cert);
+  if (rc) return rc;
+  for (int k = 0; k < c->n_inst; ++k)
+    if (status[k] == QDSE_OK && cert[k]) status[k] = QDSE_ESPURIOUS;
+  c->last_status = status;
+  return worst_of(status);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1296,56 +1642,19 @@ int qdse_newton(qdse_ctx* c, double* d_x, double tol, int max_newton, double lin
                 int* steps, double* resid) {
   if (!c || !d_x || !(tol > 0.0) || max_newton < 1 || !(lin_tol > 0.0)) return QDSE_EINVAL;
   if (c->qc) return QDSE_ENOTSUP;
-  const HostGrid& g = c->hg;
-  const int nI = c->n_inst, len = 2 * g.n;
-  const size_t L = xlen(c);
-  hipStream_t st = c->stream;
-  DevBufs buf;
-  double *d_F, *d_dx, *d_sc;
-  int rc;
-  if ((rc = buf.alloc(&d_F, L)) || (rc = buf.alloc(&d_dx, L)) || (rc = buf.alloc(&d_sc, (size_t)nI)))
-    return rc;
-  std::vector<double> h(L), rmax(nI, 0.0);
-  auto apply = [&](const double* in, double* out_, const int* d_act, int) -> int {  // (I - J(x)) v
-    HIPCHK(launch_jvp(st, nI, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->kstride, c->d_lo, c->d_sw,
-                      c->d_t, c->d_s, d_x, in, out_, c->d_nodes, d_act));
-    HIPCHK(launch_axpby(st, nI, len, -1.0, out_, nullptr, in, out_));
-    return QDSE_OK;
-  };
-  int it = 0;
-  bool done = false, bad = false;
-  for (;; ++it) {
-    // residual R = F(x) - x, max-norm per instance
-    HIPCHK(sweep_fp64(c, st, d_x, d_F, nullptr, nullptr, 1));
-    HIPCHK(launch_axpby(st, nI, len, -1.0, d_x, nullptr, d_F, d_F));
-    HIPCHK(hipMemcpyAsync(h.data(), d_F, L * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    done = true;
-    for (int k = 0; k < nI; ++k) {
-      double r = 0.0;
-      for (int e = 0; e < len; ++e) {
-        const double v = std::fabs(h[(size_t)k * len + e]);
-        if (!(v <= r)) r = v;  // NaN propagates
-      }
-      rmax[k] = r;
-      if (!(r < tol)) done = false;
-      if (!std::isfinite(r)) bad = true;
-    }
-    if (done || bad || it >= max_newton) break;
-    // (no preconditioner: away from the fixed point I - band(J) factored
-    // without pivoting can be close to singular and slow the Krylov solve)
-    auto no_prec = [](const double*, double*, const int*) -> int { return QDSE_OK; };
-    rc = gmres_batched(c, apply, no_prec, false, d_F, d_dx, lin_tol, 400, nullptr);
-    if (rc < 0) return rc;
-    HIPCHK(launch_axpby(st, nI, len, 1.0, d_x, nullptr, d_dx, d_x));  // x += dx
+  std::vector<int> st, stp, ev;
+  std::vector<double> rs;
+  int rc = newton_impl(c, d_x, tol, QDSE_CONV_ABS, max_newton, lin_tol,
+                       std::vector<char>(c->n_inst, 1), st, stp, ev, rs);
+  if (rc) return rc;
+  rc = newton_outcome(c, d_x, st);
+  if (rc < 0 && rc != QDSE_ENAN && rc != QDSE_ESPURIOUS) return rc;
+  c->last_evals = ev;
+  for (int k = 0; k < c->n_inst; ++k) {
+    if (steps) steps[k] = stp[k];
+    if (resid) resid[k] = rs[k];
   }
-  HIPCHK(hipStreamSynchronize(st));
-  for (int k = 0; k < nI; ++k) {
-    if (steps) steps[k] = it;
-    if (resid) resid[k] = rmax[k];
-  }
-  if (bad) return QDSE_ENAN;
-  return done ? QDSE_OK : QDSE_NOT_CONVERGED;
+  return worst_of(c->last_status);
 }
 
 int qdse_kernel_matrices(qdse_ctx* c, int inst, double* d_K) {
@@ -1435,6 +1744,8 @@ const char* qdse_strerror(int code) {
     case QDSE_EDEVICE: return "HIP device error";
     case QDSE_ENAN: return "iterate became NaN or infinite";
     case QDSE_ENOTSUP: return "not supported by this context";
+    case QDSE_EDIVERGED: return "successive approximation diverged (the sweep does not contract)";
+    case QDSE_ESPURIOUS: return "fixed point fails the branch certificate (A <= 0, A < 1 or M rising with p^2)";
     default: return "unknown status code";
   }
 }

@@ -189,6 +189,18 @@ constexpr int kPrecBand = 2;
 hipError_t launch_band_lu(hipStream_t st, int n_inst, int n, const double* Jb, double* F, int* ok);
 hipError_t launch_band_solve(hipStream_t st, int n_inst, int n, const double* F, const int* ok,
                              const int* act, const double* in, double* out);
+// out[inst] = the test statistic (mode QDSE_CONV_ABS or QDSE_CONV_MASS) of the
+// change x_old -> x_new of every instance ([n_inst][2n] each); NaN propagates.
+hipError_t launch_conv_stat(hipStream_t st, int n_inst, int n, int mode, const double* x_old,
+                            const double* x_new, double* out);
+// flags[inst] = branch certificate bits of x ([n_inst][2n]): 1 A <= 0 or not
+// finite somewhere, 2 A increases with p^2 (checked if check_a), 4 M = B/A
+// increases with p^2 (see k_certify).
+hipError_t launch_certify(hipStream_t st, int n_inst, int n, int check_a, const double* x,
+                          int* flags);
+// dst[inst][:] = src[inst][:] (len doubles) where sel[inst] != 0.
+hipError_t launch_select(hipStream_t st, int n_inst, int len, const int* sel, const double* src,
+                         double* dst);
 // out[inst][:] = beta * out[inst][:] + sum_v y[inst * ystride + v] V[v][inst][:]
 hipError_t launch_combine(hipStream_t st, int n_inst, int len, const double* V, size_t ldv,
                           int nvec, const double* y, int ystride, double beta, double* out);

@@ -184,11 +184,12 @@ __device__ inline void mirror_state(const SolveCtl* ctl, const SolveState* st, i
                                     double resid, unsigned long long last,
                                     unsigned long long before) {
   SolveState* m = ctl->mirror + (st - ctl->base);
-  m->status = status;
   m->sweeps = now;
   m->resid = resid;
   m->metric[0][0] = last;
   m->metric[1][0] = before;
+  __threadfence_system();  // a host that sees the status sees the fields above
+  m->status = status;
 }
 
 // Status of an instance at the start of sweep k (1-based within a chunk whose
@@ -1199,7 +1200,10 @@ __global__ void k_combine(int n_inst, int len, const double* __restrict__ V, siz
   if (e >= (long)n_inst * len) return;
   const int inst = (int)(e / len);
   double acc = beta == 0.0 ? 0.0 : beta * out[e];
-  for (int v = 0; v < nvec; ++v) acc += y[(size_t)inst * ystride + v] * V[(size_t)v * ldv + e];
+  for (int v = 0; v < nvec; ++v) {  // a zero coefficient contributes 0 (never 0 * inf)
+    const double yv = y[(size_t)inst * ystride + v];
+    if (yv != 0.0) acc += yv * V[(size_t)v * ldv + e];
+  }
   out[e] = acc;
 }
 
@@ -1209,7 +1213,108 @@ __global__ void k_axpby(int n_inst, int len, double alpha, const double* __restr
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n_inst * len) return;
   const double sc = scale ? scale[e / len] : 1.0;
-  dst[e] = (alpha == 0.0 ? 0.0 : alpha * a[e]) + sc * b[e];
+  dst[e] = (alpha == 0.0 ? 0.0 : alpha * a[e]) + (sc == 0.0 ? 0.0 : sc * b[e]);
+}
+
+// dst[inst][:] = src[inst][:] for the instances with sel[inst] != 0.
+__global__ void k_select(int n_inst, int len, const int* __restrict__ sel,
+                         const double* __restrict__ src, double* __restrict__ dst) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n_inst * len) return;
+  if (sel[e / len]) dst[e] = src[e];
+}
+
+// Max over the 64 lanes, in every lane; a NaN in any lane gives NaN.
+__device__ inline double wave_max_nan(double v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(v, o, WAVE);
+    v = (v != v || w != w) ? __longlong_as_double(0x7ff8000000000000ll) : (w > v ? w : v);
+  }
+  return v;
+}
+
+// Block-wide (256 threads) max with NaN propagation; result in every thread.
+__device__ inline double block_max_nan(double v, double* red) {
+  v = wave_max_nan(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double m = red[0];
+  for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) {
+    const double w = red[k];
+    m = (m != m || w != w) ? __longlong_as_double(0x7ff8000000000000ll) : (w > m ? w : m);
+  }
+  __syncthreads();
+  return m;
+}
+
+// The test statistic of Sec. II eq. jifenab2 between two iterates of every
+// instance (one workgroup each): mode 0 max_i max(|A'-A|, |B'-B|); mode 1
+// max_i max(|M'-M| / max(|M'|, kMassFloor), |A'-A|) with M = B/A.
+__global__ void k_conv_stat(int n, int mode, const double* __restrict__ xo,
+                            const double* __restrict__ xn, double* __restrict__ out) {
+  __shared__ double red[256 / WAVE];
+  const int inst = blockIdx.x;
+  const double* a = xo + (size_t)inst * 2 * n;
+  const double* b = xn + (size_t)inst * 2 * n;
+  double r = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double dA = fabs(b[i] - a[i]);
+    double v;
+    if (mode == 0) {
+      const double dB = fabs(b[n + i] - a[n + i]);
+      v = (dA != dA || dB != dB) ? dA + dB : (dA > dB ? dA : dB);
+    } else {
+      const double Mo = a[n + i] / a[i], Mn = b[n + i] / b[i];
+      const double den = fabs(Mn) > kMassFloor ? fabs(Mn) : kMassFloor;
+      const double dM = fabs(Mn - Mo) / den;
+      v = (dA != dA || dM != dM) ? dA + dM : (dA > dM ? dA : dM);
+    }
+    r = (r != r || v != v) ? __longlong_as_double(0x7ff8000000000000ll) : (v > r ? v : r);
+  }
+  r = block_max_nan(r, red);
+  if (threadIdx.x == 0) out[inst] = r;
+}
+
+// Branch certificate of an iterate (one workgroup per instance): bit 1 if
+// A <= 0 (or A or B not finite) at some node, bit 2 if A < 1 - 1e-9 at some
+// node, bit 4 if the mass function M = B/A rises from one node to the next
+// by more than 1e-6 max|M| where |M| exceeds 1e-3 max|M| (in the chiral
+// limit the far tail of B changes sign at the 1e-6 level of its infrared
+// value, and is not looked at). The physical (Nambu) solution of the
+// unrenormalised equation has A = 1 + Sigma_A >= 1 (with a maximum at
+// intermediate p^2 for the Ball-Chiu vertex) and M falling with p^2 for
+// m >= 0; the other fixed points the drivers can reach (successive
+// approximation's with A < 0 in the infrared, Newton's with A << 1 and M of
+// several GeV, the negative-mass partner, the grid-scale oscillations near
+// the end of the branch) fail one of these.
+// check_a = 0 skips bit 2 (renormalised setting: A = 1 at p^2 = zeta^2,
+// and A may fall below 1 beyond it).
+__global__ void k_certify(int n, int check_a, const double* __restrict__ x,
+                          int* __restrict__ flags) {
+  __shared__ double red[256 / WAVE];
+  __shared__ int bits;
+  const int inst = blockIdx.x;
+  const double* A = x + (size_t)inst * 2 * n;
+  const double* B = A + n;
+  if (threadIdx.x == 0) bits = 0;
+  double mmax = 0.0;
+  int b = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    if (!(A[i] > 0.0) || !(A[i] <= 1.7976931348623157e308) || !(fabs(B[i]) <= 1.7976931348623157e308))
+      b |= 1;
+    if (check_a && !(A[i] >= 1.0 - 1e-9)) b |= 2;
+    const double m = fabs(B[i] / A[i]);
+    mmax = (mmax != mmax || m != m) ? __longlong_as_double(0x7ff8000000000000ll) : (m > mmax ? m : mmax);
+  }
+  mmax = block_max_nan(mmax, red);  // contains a barrier: bits is initialised
+  const double rise = 1e-6 * mmax, floor_m = 1e-3 * mmax;
+  for (int i = threadIdx.x; i + 1 < n; i += blockDim.x) {
+    const double m0 = B[i] / A[i], m1 = B[i + 1] / A[i + 1];
+    if (m1 - m0 > rise && (fabs(m0) > floor_m || fabs(m1) > floor_m)) b |= 4;
+  }
+  if (b) atomicOr(&bits, b);
+  __syncthreads();
+  if (threadIdx.x == 0) flags[inst] = bits;
 }
 
 }  // namespace
@@ -1365,6 +1470,26 @@ hipError_t launch_vjp(hipStream_t st, int n_inst, int n, int nq, int ldk, const 
                      ldk, nchunk, t, nodes, part, gq, act);
   hipLaunchKernelGGL(k_vjp_scatter, dim3((n + 255) / 256, n_inst), dim3(256), 0, st, n_inst, n, nq,
                      ldk, lo, sw, gq, out, act);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_stat(hipStream_t st, int n_inst, int n, int mode, const double* x_old,
+                            const double* x_new, double* out) {
+  hipLaunchKernelGGL(k_conv_stat, dim3(n_inst), dim3(256), 0, st, n, mode, x_old, x_new, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(hipStream_t st, int n_inst, int len, const int* sel, const double* src,
+                         double* dst) {
+  const long tot = (long)n_inst * len;
+  hipLaunchKernelGGL(k_select, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n_inst, len,
+                     sel, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_certify(hipStream_t st, int n_inst, int n, int check_a, const double* x,
+                          int* flags) {
+  hipLaunchKernelGGL(k_certify, dim3(n_inst), dim3(256), 0, st, n, check_a, x, flags);
   return hipGetLastError();
 }
 

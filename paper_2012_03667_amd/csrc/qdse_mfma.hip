@@ -124,11 +124,12 @@ __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool
     for (int l = 0; l < kMetricLanes; ++l) S.metric[(k + 1) % 3][l] = 0ull;
     if (ctl->mirror && k % 6 == 0) {  // host mirror (see SolveCtl)
       SolveState* m = ctl->mirror + (st - ctl->base);
-      m->status = status;
       m->sweeps = now;
       m->resid = S.resid;
       m->metric[0][0] = slot_max(S, (k + 2) % 3);
       m->metric[1][0] = before;
+      __threadfence_system();  // a host that sees the status sees the fields above
+      m->status = status;
     }
   }
   return status;

@@ -40,14 +40,15 @@ def test_setup_rejects_bad_arguments_before_hip(L):
            dict(good, s_min=0.0), dict(good, s_max=1e-5)]
     for b in bad:
         g = Grid(**b)
-        assert L.qdse_setup(ctypes.byref(g), p, 1, 0, None, ctypes.byref(h)) == -1, b
+        assert L.qdse_setup(ctypes.byref(g), p, 1, 0, 0, None, ctypes.byref(h)) == -1, b
     g = Grid(**good)
-    assert L.qdse_setup(ctypes.byref(g), p, 0, 0, None, ctypes.byref(h)) == -1
-    assert L.qdse_setup(ctypes.byref(g), p, 1, 7, None, ctypes.byref(h)) == -1
-    assert L.qdse_setup(ctypes.byref(g), p, 1, 0, None, None) == -1
+    assert L.qdse_setup(ctypes.byref(g), p, 0, 0, 0, None, ctypes.byref(h)) == -1
+    assert L.qdse_setup(ctypes.byref(g), p, 1, 7, 0, None, ctypes.byref(h)) == -1
+    assert L.qdse_setup(ctypes.byref(g), p, 1, 0, 3, None, ctypes.byref(h)) == -1
+    assert L.qdse_setup(ctypes.byref(g), p, 1, 0, 0, None, None) == -1
     for badp in (Params(-1.0, 0.5, 0.0), Params(1.0, 0.0, 0.0), Params(1.0, 0.5, float("nan"))):
         pp = (Params * 1)(badp)
-        assert L.qdse_setup(ctypes.byref(g), pp, 1, 0, None, ctypes.byref(h)) == -1
+        assert L.qdse_setup(ctypes.byref(g), pp, 1, 0, 0, None, ctypes.byref(h)) == -1
 
 
 def test_setup_qc_rejects_bad_arguments_before_hip(L):
@@ -89,10 +90,12 @@ def test_fred_entry_points_reject_bad_arguments_before_hip(L):
 
 
 def test_entry_points_reject_null_context(L):
-    assert L.qdse_iterate(None, None, None) == -1
+    assert L.qdse_iterate(None, None, None, None) == -1
     assert L.qdse_solve(None, None, ctypes.c_double(1e-10), 10, 0, None, None) == -1
     assert L.qdse_jvp(None, None, None, None) == -1
     assert L.qdse_vjp(None, None, None, None) == -1
+    assert L.qdse_vjp_noalloc(None, None, None, None) == -1
+    assert L.qdse_solve_status(None, None) == -1
     assert L.qdse_jacobian_band(None, None, 2, None) == -1
     assert L.qdse_measure_launch_floor(None, 0, 1024, None, None) == -1
     assert L.qdse_measure_launch_floor(None, 4, -1, None, None) == -1
@@ -102,7 +105,7 @@ def test_entry_points_reject_null_context(L):
 
 
 def test_strerror_names_every_code(L):
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert L.qdse_strerror(code) and L.qdse_strerror(code) != b"unknown status code"
     assert L.qdse_strerror(99) == b"unknown status code"
 

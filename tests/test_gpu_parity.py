@@ -165,7 +165,10 @@ def test_adjoint_preconditioner_changes_no_result(Q, n):
     S = Q.Solver(n, na, params)
     x = S.initial(1.0, 1.0)
     rc, _, _ = S.solve(x, tol=1e-12, max_iter=5000)
-    assert rc == Q.QDSE_OK
+    # six nodes resolve no physics: the fixed points need not pass the branch
+    # certificate, but the adjoint is defined at any fixed point
+    assert rc in (Q.QDSE_OK, Q.QDSE_ESPURIOUS)
+    assert all(v in (Q.QDSE_OK, Q.QDSE_ESPURIOUS) for v in S.solve_status())
     g = torch.tensor(np.random.default_rng(15).normal(size=tuple(x.shape)), device="cuda")
     tb1, rc1 = S.grad(x, g, tol=1e-12, max_iter=600)
     tb0, rc0 = _without_band_prec(lambda: S.grad(x, g, tol=1e-12, max_iter=600))
@@ -175,16 +178,19 @@ def test_adjoint_preconditioner_changes_no_result(Q, n):
 
 
 def test_adjoint_at_newton_fixed_point_with_and_without_preconditioner(Q):
-    """At fixed points that successive approximation cannot reach (the
-    kappa = 0.8, omega = 0.5 interaction, solved by Newton-Krylov) the adjoint
-    solve converges with the banded preconditioner and agrees with the
+    """Close to the end of the physical branch (kappa = 0.776, omega = 0.553
+    GeV: the sweep's Jacobian has eigenvalues within 0.01 of 1, successive
+    approximation needs about 1400 sweeps) Newton-Krylov reaches the
+    certified fixed point in a few steps, and there the adjoint solve
+    converges with the banded preconditioner and agrees with the
     unpreconditioned one."""
     n, na = 64, 64
-    params = [(KAPPA ** 3 / OMEGA, OMEGA, 0.005), (KAPPA ** 3 / OMEGA, OMEGA, 0.0)]
+    params = [(0.776 ** 3 / 0.553, 0.553, 0.005), (0.776 ** 3 / 0.553, 0.553, 0.0)]
     S = Q.Solver(n, na, params)
-    x = S.initial(1.0, 1.0)
+    x = S.initial(1.0, 0.3)
     rc, steps, res = S.newton(x, tol=1e-12, max_newton=40)
     assert rc == Q.QDSE_OK, (rc, steps, res)
+    assert list(S.solve_status()) == [Q.QDSE_OK, Q.QDSE_OK]
     g = torch.tensor(np.random.default_rng(16).normal(size=tuple(x.shape)), device="cuda")
     tb1, rc1 = S.grad(x, g, tol=1e-12, max_iter=600)
     tb0, rc0 = _without_band_prec(lambda: S.grad(x, g, tol=1e-12, max_iter=600))

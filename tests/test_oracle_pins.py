@@ -437,23 +437,35 @@ def test_continuation_endpoints():
 
 def test_certificate_flags():
     """certificate(): the residual is max |F(x) - x|; A <= 0 anywhere clears
-    A_pos; a mass function whose node-to-node slope changes sign is counted
-    (slope_flips), a monotone one gives 0."""
+    A_pos, A < 1 clears A_ge_1, a rise of M with p^2 clears M_falls; a mass
+    function whose node-to-node slope changes sign is counted (slope_flips),
+    a monotone one gives 0. The Nambu fixed point at the paper's parameters
+    is certified (its A has a maximum at intermediate p^2, so A is not
+    required to fall)."""
     n = 32
     g = O.vac_grid(n, 24)
     p = O.Params(0.55, 0.678, 0.005)
     x0 = np.concatenate([np.ones(n), np.ones(n)])
     xs, _, _, _ = O.picard(g, p, x0, 1e-14, max_iter=500, mode=0)
     c = O.certificate(g, p, xs)
-    assert c["A_pos"] and c["slope_flips"] == 0 and c["resid"] < 1e-13
+    assert c["certified"] and c["slope_flips"] == 0 and c["resid"] < 1e-13
     y = xs.copy()
     y[3] = -0.5
     c = O.certificate(g, p, y)
-    assert not c["A_pos"]
+    assert not c["A_pos"] and not c["certified"]
     assert abs(c["resid"] - np.max(np.abs(O.F(g, p, y) - y))) == 0.0
+    assert np.any(np.diff(xs[:n]) > 0.01)
+    y = xs.copy()
+    y[n - 3] = 0.99
+    c = O.certificate(g, p, y)
+    assert c["A_pos"] and not c["A_ge_1"] and not c["certified"]
     y = xs.copy()
     y[n + 5] *= 1.2  # a bump in B: the slope of M changes sign twice
-    assert O.certificate(g, p, y)["slope_flips"] == 2
+    c = O.certificate(g, p, y)
+    assert c["slope_flips"] == 2 and not c["M_falls"] and not c["certified"]
+    y = xs.copy()
+    y[n:] = -y[n:]  # the negative-mass partner: M rises towards 0
+    assert not O.certificate(g, p, y)["M_falls"]
     y = xs.copy()
     y[n + 4:n + 12] *= 1 + 0.3 * (-1) ** np.arange(8)
     assert O.certificate(g, p, y)["slope_flips"] >= 6
