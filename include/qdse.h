@@ -255,13 +255,14 @@ int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int m
  * instance, for fixed points where successive approximation does not contract:
  * each step solves (I - J) dx = R by restarted GMRES with Jacobian-vector
  * products (to ||.||_2 relative tolerance lin_tol) and sets x += dx. An
- * instance stops when max_i |R_i| < tol (the norm is reduced on the device)
- * or after max_newton steps; converged instances are checked against the
- * branch certificate. d_x: in initial guess, out last iterate. steps[n_inst],
+ * instance stops when max_i |R_i| < tol (the norm is reduced on the device),
+ * when that norm has grown 1e4-fold above its smallest value from the third
+ * step on (QDSE_EDIVERGED), or after max_newton steps; converged instances
+ * are checked against the branch certificate. d_x: in initial guess, out last iterate. steps[n_inst],
  * resid[n_inst] (host, may be NULL): Newton steps and final max|R|. The
  * Krylov workspace is allocated by the context on its first Newton or
  * adjoint solve and reused afterwards. Returns QDSE_OK, QDSE_NOT_CONVERGED,
- * QDSE_ESPURIOUS or QDSE_ENAN. Synchronises the stream. */
+ * QDSE_ESPURIOUS, QDSE_EDIVERGED or QDSE_ENAN. Synchronises the stream. */
 int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double lin_tol,
                 int* steps, double* resid);
 
@@ -400,7 +401,8 @@ void qdse_mu_destroy(qdse_mu_ctx* ctx);
 int qdse_mu_grid_nodes(const qdse_mu_grid* grid, double* ps, double* p4, double* qs,
                        double* q4, double* wqs, double* wq4, double* z, double* wz);
 
-/* One finite-mu sweep for every instance (complex128 device arrays, distinct).
+/* One finite-mu sweep for every instance (complex128 device arrays, distinct),
+ * all instances in one launch with their own mu, m and interaction.
  * Asynchronous. */
 int qdse_mu_iterate(qdse_mu_ctx* ctx, const double* d_x_in, double* d_x_out);
 
@@ -410,6 +412,17 @@ int qdse_mu_iterate(qdse_mu_ctx* ctx, const double* d_x_in, double* d_x_out);
  * QDSE_NOT_CONVERGED or QDSE_ENAN. Synchronises the stream. */
 int qdse_mu_solve(qdse_mu_ctx* ctx, double* d_x, double tol, int max_iter, int* iters,
                   double* resid);
+
+/* The same successive approximation for several finite-mu contexts at once
+ * (for example the grid classes of a mixed batch, each context holding the
+ * instances of one grid with their own mu, m and interaction): every round
+ * enqueues one sweep of each unfinished context on that context's stream,
+ * then reads their statistics, so the classes' sweeps overlap when their
+ * streams differ. ctxs[n_ctx] distinct; d_x[q], iters[q], resid[q] as for
+ * qdse_mu_solve on context q (the outer arrays may be NULL). Returns the
+ * most severe code of any context. Synchronises every context's stream. */
+int qdse_mu_solve_group(qdse_mu_ctx** ctxs, int n_ctx, double** d_x, double tol, int max_iter,
+                        int** iters, double** resid);
 
 /* The same fixed point found with Anderson mixing of depth `depth` (0..16;
  * 0 is plain successive approximation): with g = F(x) and f = g - x at the

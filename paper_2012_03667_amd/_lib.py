@@ -109,6 +109,9 @@ def load():
     L.qdse_mu_solve.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]
     L.qdse_mu_solve_anderson.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                          _ip, _dp]
+    L.qdse_mu_solve_group.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                      ctypes.c_double, ctypes.c_int, ctypes.POINTER(_ip),
+                                      ctypes.POINTER(_dp)]
     L.qdse_measure_peaks.argtypes = [_vp, _dp, _dp, _dp]
     L.qdse_measure_launch_floor.argtypes = [_vp, ctypes.c_int, ctypes.c_longlong, _dp, _dp]
     L.qdse_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip]
@@ -382,6 +385,24 @@ def solve_group(solvers, xs, tol=1e-10, max_iter=1000, conv_mode=QDSE_CONV_MASS)
     R = (_dp * n)(*[a.ctypes.data_as(_dp) for a in rss])
     rc = load().qdse_solve_group(H, n, X, float(tol), int(max_iter), int(conv_mode), I, R)
     _check(rc, "qdse_solve_group", allow=_OUTCOMES)
+    return rc, its, rss
+
+
+def mu_solve_group(solvers, xs, tol=1e-10, max_iter=500):
+    """qdse_mu_solve_group: successive approximation of several finite-mu
+    contexts together (their sweeps overlap when their streams differ).
+    Returns (status, [iters per context], [resid per context])."""
+    n = len(solvers)
+    if n != len(xs) or n == 0:
+        raise ValueError("one unknown tensor per solver is required")
+    H = (_vp * n)(*[S._h for S in solvers])
+    X = (_vp * n)(*[S._cdev(x, "x") for S, x in zip(solvers, xs)])
+    its = [np.zeros(S.n_inst, dtype=np.int32) for S in solvers]
+    rss = [np.zeros(S.n_inst) for S in solvers]
+    I = (_ip * n)(*[a.ctypes.data_as(_ip) for a in its])
+    R = (_dp * n)(*[a.ctypes.data_as(_dp) for a in rss])
+    rc = load().qdse_mu_solve_group(H, n, X, float(tol), int(max_iter), I, R)
+    _check(rc, "qdse_mu_solve_group", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
     return rc, its, rss
 
 

@@ -1477,12 +1477,17 @@ bool band_prec_enabled() {
   return !(e && e[0] == '0');
 }
 
+// A Newton iterate whose test statistic has grown above this factor times
+// its smallest value (from the third step on) is abandoned as diverged.
+constexpr double kNewtonDivergeFactor = 1e4;
+
 // Newton's method on R(x) = F(x) - x for the instances with want[k] != 0
 // (the others are left unchanged): each step solves (I - J) dx = R by the
 // batched restarted GMRES with Jacobian-vector products and sets x += dx. An
 // instance stops when the test statistic (mode) of the sweep x -> F(x) is
-// below tol (status QDSE_OK), when it is not finite (QDSE_ENAN), or after
-// max_newton steps (QDSE_NOT_CONVERGED). The statistic is reduced on the
+// below tol (status QDSE_OK), when it is not finite (QDSE_ENAN), when it
+// has grown kNewtonDivergeFactor-fold above its smallest value
+// (QDSE_EDIVERGED), or after max_newton steps (QDSE_NOT_CONVERGED). The statistic is reduced on the
 // device; only one number per instance reaches the host per step. Per
 // instance: status, steps, evaluations (sweeps and Jacobian-vector products,
 // each about one sweep of work) and the last statistic. The workspace is the
@@ -1502,6 +1507,7 @@ int newton_impl(qdse_ctx* c, double* d_x, double tol, int mode, int max_newton, 
   resid.assign(nI, HUGE_VAL);
   std::vector<char> active(want.begin(), want.end());
   active.resize(nI, 0);
+  std::vector<double> rmin(nI, HUGE_VAL);
   for (int k = 0; k < nI; ++k)
     if (!active[k]) status[k] = QDSE_OK;  // not handed over: untouched
   auto apply = [&](const double* in, double* out_, const int* d_act, int) -> int {  // (I - J(x)) v
@@ -1530,11 +1536,15 @@ int newton_impl(qdse_ctx* c, double* d_x, double tol, int mode, int max_newton, 
       } else if (r < tol) {
         status[k] = QDSE_OK;
         active[k] = 0;
+      } else if (it >= 3 && r > kNewtonDivergeFactor * rmin[k]) {
+        status[k] = QDSE_EDIVERGED;  // the steps lead away from every fixed point nearby
+        active[k] = 0;
       } else if (it >= max_newton) {
         active[k] = 0;  // stays QDSE_NOT_CONVERGED
       } else {
         ++n_act;
       }
+      if (r < rmin[k]) rmin[k] = r;
     }
     if (n_act == 0) break;
     // R = F(x) - x on the active instances, 0 on the others (their GMRES

@@ -230,11 +230,18 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Finite-mu sweep (qdse_mu.hip); x, L complex interleaved.
+// Per-instance constants of a finite-mu sweep: mu, the interaction's
+// prefactor 8 pi^2 D / omega^4 and 1 / omega^2, the current mass.
+struct MuInst {
+  double mu, gnorm, inv_om2, m;
+};
+// One finite-mu sweep of n_inst instances in one launch (act: nullptr, or
+// per instance 0 = copy the iterate forward).
 hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, int nq4, int na,
                            const double* ps, const double* p4, const double* qs, const double* q4,
                            const double* wqs, const double* wq4, const double* z, const double* wz,
                            const int* lo_s, const double* sw_s, const int* lo_4,
-                           const double* sw_4, double mu, double D, double omega, double m,
+                           const double* sw_4, const MuInst* inst, const int* act,
                            const double* x_in, double* x_out, double* L);
 hipError_t launch_mu_stat(hipStream_t st, int n_inst, int ne, const double* x_old,
                           const double* x_new, unsigned long long* stat);

@@ -96,7 +96,9 @@ __global__ void k_mu_interp(int ns, int n4, int nqs, int nq4, const int* __restr
 
 struct MuArgs {
   int n_inst, ns, n4, nqs, nq4, na;
-  double mu, gnorm, inv_om2, m, cw;  // cw = C_F / (8 pi^3)
+  double cw;                 // C_F / (8 pi^3)
+  const MuInst* inst;        // per-instance mu, interaction, mass [n_inst]
+  const int* act;            // nullptr, or 0: the instance is copied forward
   const double* ps;
   const double* p4;
   const double* qs;
@@ -195,13 +197,18 @@ __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
   const long row = (long)blockIdx.x * (blockDim.x / MU_WAVE) + threadIdx.x / MU_WAVE;
   if (row >= (long)a.n_inst * ne) return;
   const int inst = (int)(row / ne), e = (int)(row % ne);
+  const double2* xi = a.x + (size_t)inst * 3 * ne;
+  if (a.act && !a.act[inst]) {  // frozen: the row carries its iterate (uniform per wavefront)
+    if (lane < 3) a.out[(size_t)inst * 3 * ne + (size_t)lane * ne + e] = xi[(size_t)lane * ne + e];
+    return;
+  }
+  const MuInst I = a.inst[inst];
   const int ia = e / a.n4, ib = e % a.n4;
   const double pabs = a.ps[ia], p4r = a.p4[ib];
-  const double2* xi = a.x + (size_t)inst * 3 * ne;
   const double2* Li = a.L + (size_t)inst * 3 * nl;
   MuPoint P;
   P.p = pabs;
-  P.pt4 = mk(p4r, a.mu);
+  P.pt4 = mk(p4r, I.mu);
   P.Ap = mk(xi[e].x, xi[e].y);
   P.Bp = mk(xi[ne + e].x, xi[ne + e].y);
   P.Cp = mk(xi[2 * ne + e].x, xi[2 * ne + e].y);
@@ -209,20 +216,20 @@ __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
   for (int l = lane; l < nl; l += MU_WAVE) {
     const int c = l / a.nq4, d = l % a.nq4;
     const double qa = a.qs[c], q4a = a.q4[d];
-    const double wl = a.cw * a.gnorm * a.wqs[c] * a.wq4[d];
+    const double wl = a.cw * I.gnorm * a.wqs[c] * a.wq4[d];
     const cd A0 = mk(Li[l].x, Li[l].y), B0 = mk(Li[nl + l].x, Li[nl + l].y),
              C0 = mk(Li[2 * nl + l].x, Li[2 * nl + l].y);
     // angular moments for q4 = +|q4| (k4 = p4 - |q4|) and q4 = -|q4|; the
     // geometry in the plane of p_vec and q_vec is common to both
     const double k4p = p4r - q4a, k4m = p4r + q4a;
     const double k4p2 = k4p * k4p, k4m2 = k4m * k4m;
-    const double ep = exp(-k4p2 * a.inv_om2), em = exp(-k4m2 * a.inv_om2);
+    const double ep = exp(-k4p2 * I.inv_om2), em = exp(-k4m2 * I.inv_om2);
     double Sp[3] = {0, 0, 0}, Tp[3] = {0, 0, 0}, Sm[3] = {0, 0, 0}, Tm[3] = {0, 0, 0};
     for (int t = 0; t < a.na; ++t) {
       const double qx = qa * sns[t];
       const double v = pabs - qa * zs[t];
       const double base = qx * qx + v * v;
-      const double g = wzs[t] * exp(-base * a.inv_om2);
+      const double g = wzs[t] * exp(-base * I.inv_om2);
       const double gp = g * ep, gm = g * em;
       const double yp = 1.0 / (base + k4p2), ym = 1.0 / (base + k4m2);
       const double gpv = gp * v, gmv = gm * v;
@@ -243,7 +250,7 @@ __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
     cd IA, IB, IC;
     // q4 > 0: the interpolated values; q4 < 0: their conjugates
     P.k4 = k4p;
-    P.qt4 = mk(q4a, a.mu);
+    P.qt4 = mk(q4a, I.mu);
     P.Aq = A0;
     P.Bq = B0;
     P.Cq = C0;
@@ -255,7 +262,7 @@ __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
     sCr = fma(wl, IC.r, sCr);
     sCi = fma(wl, IC.i, sCi);
     P.k4 = k4m;
-    P.qt4 = mk(-q4a, a.mu);
+    P.qt4 = mk(-q4a, I.mu);
     P.Aq = conj(A0);
     P.Bq = conj(B0);
     P.Cq = conj(C0);
@@ -276,7 +283,7 @@ __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
   if (lane == 0) {
     double2* o = a.out + (size_t)inst * 3 * ne;
     o[e] = make_double2(1.0 + sAr, sAi);
-    o[ne + e] = make_double2(a.m + sBr, sBi);
+    o[ne + e] = make_double2(I.m + sBr, sBi);
     o[2 * ne + e] = make_double2(1.0 + sCr, sCi);
   }
 }
@@ -302,16 +309,16 @@ hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, 
                            const double* ps, const double* p4, const double* qs, const double* q4,
                            const double* wqs, const double* wq4, const double* z, const double* wz,
                            const int* lo_s, const double* sw_s, const int* lo_4,
-                           const double* sw_4, double mu, double D, double omega, double m,
+                           const double* sw_4, const MuInst* inst, const int* act,
                            const double* x_in, double* x_out, double* L) {
   if (na > 256) return hipErrorInvalidValue;
   const int nl = nqs * nq4, ne = ns * n4;
   hipLaunchKernelGGL(k_mu_interp, dim3((nl + 255) / 256, n_inst), dim3(256), 0, st, ns, n4, nqs,
                      nq4, lo_s, sw_s, lo_4, sw_4, (const double2*)x_in, (double2*)L);
   const double pi = 3.14159265358979323846;
-  MuArgs a{n_inst, ns, n4, nqs, nq4, na, mu, 8.0 * pi * pi * D / (omega * omega * omega * omega),
-           1.0 / (omega * omega), m, (4.0 / 3.0) / (8.0 * pi * pi * pi), ps, p4, qs, q4, wqs, wq4,
-           z, wz, (const double2*)x_in, (const double2*)L, (double2*)x_out};
+  MuArgs a{n_inst, ns, n4, nqs, nq4, na, (4.0 / 3.0) / (8.0 * pi * pi * pi), inst, act,
+           ps, p4, qs, q4, wqs, wq4, z, wz, (const double2*)x_in, (const double2*)L,
+           (double2*)x_out};
   const long rows = (long)n_inst * ne;
   hipLaunchKernelGGL(k_mu_sweep, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, a);
   return hipGetLastError();

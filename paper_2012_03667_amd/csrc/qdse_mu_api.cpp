@@ -24,6 +24,11 @@ struct qdse_mu_ctx {
   double* d_L = nullptr;      // interpolated loop values [inst][3][nl] complex
   double* d_xb[2] = {nullptr, nullptr};
   unsigned long long* d_stat = nullptr;
+  MuInst* d_inst = nullptr;        // per-instance constants of the sweep
+  int* d_act = nullptr;            // per-instance activity of masked sweeps
+  std::vector<int> act_h;          // the mask last uploaded
+  unsigned long long* h_stat = nullptr;  // page-locked copy of the statistics
+  hipEvent_t ev = nullptr;
 };
 
 namespace {
@@ -83,9 +88,11 @@ void qdse_mu_destroy(qdse_mu_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->d_ps,   c->d_p4,   c->d_qs, c->d_q4,    c->d_wqs,   c->d_wq4, c->d_z,
                   c->d_wz,   c->d_sw_s, c->d_sw_4, c->d_lo_s, c->d_lo_4, c->d_L,   c->d_xb[0],
-                  c->d_xb[1], c->d_stat};
+                  c->d_xb[1], c->d_stat, c->d_inst, c->d_act};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->h_stat) (void)hipHostFree(c->h_stat);
+  if (c->ev) (void)hipEventDestroy(c->ev);
   delete c;
 }
 
@@ -131,6 +138,27 @@ int qdse_mu_setup(const qdse_mu_grid* grid, const qdse_mu_params* params, int n_
     if (hipMalloc((void**)&c->d_xb[b], mu_xlen(c) * sizeof(double)) != hipSuccess) rc = QDSE_ENOMEM;
   if (!rc && hipMalloc((void**)&c->d_stat, (size_t)n_inst * sizeof(unsigned long long)) != hipSuccess)
     rc = QDSE_ENOMEM;
+  if (!rc) {
+    const double pi = 3.14159265358979323846;
+    std::vector<MuInst> ih(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+      const qdse_mu_params& p = params[k];
+      const double o2 = p.omega * p.omega;
+      ih[k] = MuInst{p.mu, 8.0 * pi * pi * p.D / (o2 * o2), 1.0 / o2, p.m};
+    }
+    rc = up(&c->d_inst, ih, st);
+  }
+  c->act_h.assign(n_inst, 1);
+  if (!rc) rc = up(&c->d_act, c->act_h, st);
+  if (!rc && hipHostMalloc((void**)&c->h_stat, (size_t)n_inst * sizeof(unsigned long long),
+                           hipHostMallocDefault) != hipSuccess) {
+    c->h_stat = nullptr;
+    rc = QDSE_ENOMEM;
+  }
+  if (!rc && hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess) {
+    c->ev = nullptr;
+    rc = QDSE_EDEVICE;
+  }
   if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = QDSE_EDEVICE;
   if (rc) {
     qdse_mu_destroy(c);
@@ -140,29 +168,112 @@ int qdse_mu_setup(const qdse_mu_grid* grid, const qdse_mu_params* params, int n_
   return QDSE_OK;
 }
 
-// One sweep of every instance whose flag in `frozen` is 0 (nullptr: all);
-// frozen instances are copied forward. Instances share the grid; their
-// parameters enter as kernel arguments, one launch per instance.
+// One sweep of every instance whose flag in `frozen` is 0 (nullptr: all),
+// all instances in one launch with their own mu, interaction and mass;
+// frozen instances are copied forward.
 static int mu_sweep(qdse_mu_ctx* c, const double* in, double* out, const std::vector<int>* frozen) {
   const HostMuGrid& h = c->hg;
-  const size_t per = (size_t)3 * h.ns * h.n4 * 2;
-  const size_t nl2 = (size_t)3 * h.nqs * h.nq4 * 2;
-  for (int k = 0; k < c->n_inst; ++k) {
-    if (frozen && (*frozen)[k]) {
-      if (hipMemcpyAsync(out + k * per, in + k * per, per * sizeof(double),
-                         hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        return QDSE_EDEVICE;
-      continue;
+  const int* act = nullptr;
+  if (frozen) {
+    bool changed = false;
+    for (int k = 0; k < c->n_inst; ++k) {
+      const int a = (*frozen)[k] ? 0 : 1;
+      if (a != c->act_h[k]) changed = true;
+      c->act_h[k] = a;
     }
-    const qdse_mu_params& p = c->params[k];
-    hipError_t e = launch_mu_sweep(c->stream, 1, h.ns, h.n4, h.nqs, h.nq4, h.na, c->d_ps, c->d_p4,
-                                   c->d_qs, c->d_q4, c->d_wqs, c->d_wq4, c->d_z, c->d_wz,
-                                   c->d_lo_s, c->d_sw_s, c->d_lo_4, c->d_sw_4, p.mu, p.D, p.omega,
-                                   p.m, in + k * per, out + k * per, c->d_L + k * nl2);
-    if (e != hipSuccess) return QDSE_EDEVICE;
+    if (changed && hipMemcpyAsync(c->d_act, c->act_h.data(), c->n_inst * sizeof(int),
+                                  hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return QDSE_EDEVICE;
+    act = c->d_act;
   }
-  return QDSE_OK;
+  hipError_t e = launch_mu_sweep(c->stream, c->n_inst, h.ns, h.n4, h.nqs, h.nq4, h.na, c->d_ps,
+                                 c->d_p4, c->d_qs, c->d_q4, c->d_wqs, c->d_wq4, c->d_z, c->d_wz,
+                                 c->d_lo_s, c->d_sw_s, c->d_lo_4, c->d_sw_4, c->d_inst, act, in,
+                                 out, c->d_L);
+  return e == hipSuccess ? QDSE_OK : QDSE_EDEVICE;
 }
+
+// Successive approximation of one context as a sequence of steps, so that
+// several contexts (grid classes) can run on their own streams together:
+// enqueue() puts one sweep of the running instances and its statistic on the
+// stream, collect() waits for it and freezes the instances that passed.
+struct MuRun {
+  qdse_mu_ctx* c = nullptr;
+  double* d_x = nullptr;
+  double tol = 0.0;
+  int max_iter = 0, k = 0, cur = 0, rc = QDSE_OK;
+  bool finished = false;
+  std::vector<int> done, it;
+  std::vector<double> res;
+
+  int begin(qdse_mu_ctx* c_, double* d_x_, double tol_, int max_iter_) {
+    c = c_;
+    d_x = d_x_;
+    tol = tol_;
+    max_iter = max_iter_;
+    k = 0;
+    cur = 0;
+    rc = QDSE_OK;
+    finished = false;
+    done.assign(c->n_inst, 0);
+    it.assign(c->n_inst, 0);
+    res.assign(c->n_inst, INFINITY);
+    if (hipMemcpyAsync(c->d_xb[0], d_x, mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return QDSE_EDEVICE;
+    return QDSE_OK;
+  }
+  int enqueue() {
+    hipStream_t st = c->stream;
+    const int ne = c->hg.ns * c->hg.n4;
+    ++k;
+    if (hipMemsetAsync(c->d_stat, 0, c->n_inst * sizeof(unsigned long long), st) != hipSuccess)
+      return QDSE_EDEVICE;
+    int r = mu_sweep(c, c->d_xb[cur], c->d_xb[cur ^ 1], &done);
+    if (r) return r;
+    if (launch_mu_stat(st, c->n_inst, ne, c->d_xb[cur], c->d_xb[cur ^ 1], c->d_stat) != hipSuccess ||
+        hipMemcpyAsync(c->h_stat, c->d_stat, c->n_inst * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipEventRecord(c->ev, st) != hipSuccess)
+      return QDSE_EDEVICE;
+    return QDSE_OK;
+  }
+  int collect() {
+    if (hipEventSynchronize(c->ev) != hipSuccess) return QDSE_EDEVICE;
+    cur ^= 1;
+    bool all = true, bad = false;
+    for (int q = 0; q < c->n_inst; ++q) {
+      double r;
+      std::memcpy(&r, &c->h_stat[q], sizeof(double));
+      if (!done[q]) {
+        it[q] = k;
+        res[q] = r;
+        if (!(r <= 1.7976931348623157e308)) bad = true;
+        else if (r < tol) done[q] = 1;  // frozen (copied forward) from the next sweep on
+      }
+      if (!done[q]) all = false;
+    }
+    if (all || bad) {
+      rc = bad ? QDSE_ENAN : QDSE_OK;
+      finished = true;
+    } else if (k == max_iter) {
+      rc = QDSE_NOT_CONVERGED;
+      finished = true;
+    }
+    return QDSE_OK;
+  }
+  int end(int* iters, double* resid) {
+    if (hipMemcpyAsync(d_x, c->d_xb[cur], mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return QDSE_EDEVICE;
+    for (int q = 0; q < c->n_inst; ++q) {
+      if (iters) iters[q] = it[q];
+      if (resid) resid[q] = res[q];
+    }
+    return rc;
+  }
+};
 
 int qdse_mu_iterate(qdse_mu_ctx* c, const double* d_x_in, double* d_x_out) {
   if (!c || !d_x_in || !d_x_out || d_x_in == d_x_out) return QDSE_EINVAL;
@@ -172,56 +283,46 @@ int qdse_mu_iterate(qdse_mu_ctx* c, const double* d_x_in, double* d_x_out) {
 int qdse_mu_solve(qdse_mu_ctx* c, double* d_x, double tol, int max_iter, int* iters,
                   double* resid) {
   if (!c || !d_x || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
-  hipStream_t st = c->stream;
-  const int ne = c->hg.ns * c->hg.n4;
-  if (hipMemcpyAsync(c->d_xb[0], d_x, mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st) !=
-      hipSuccess)
-    return QDSE_EDEVICE;
-  std::vector<unsigned long long> bits(c->n_inst);
-  std::vector<int> done(c->n_inst, 0), it(c->n_inst, 0);
-  std::vector<double> res(c->n_inst, INFINITY);
-  int cur = 0, rc = QDSE_OK;
-  for (int k = 1; k <= max_iter; ++k) {
-    std::vector<unsigned long long> zero(c->n_inst, 0ull);
-    if (hipMemcpyAsync(c->d_stat, zero.data(), zero.size() * sizeof(unsigned long long),
-                       hipMemcpyHostToDevice, st) != hipSuccess)
-      return QDSE_EDEVICE;
-    if ((rc = mu_sweep(c, c->d_xb[cur], c->d_xb[cur ^ 1], &done))) return rc;
-    if (launch_mu_stat(st, c->n_inst, ne, c->d_xb[cur], c->d_xb[cur ^ 1], c->d_stat) != hipSuccess)
-      return QDSE_EDEVICE;
-    if (hipMemcpyAsync(bits.data(), c->d_stat, bits.size() * sizeof(unsigned long long),
-                       hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return QDSE_EDEVICE;
-    cur ^= 1;
-    bool all = true, bad = false;
-    for (int q = 0; q < c->n_inst; ++q) {
-      double r;
-      std::memcpy(&r, &bits[q], sizeof(double));
-      if (!done[q]) {
-        it[q] = k;
-        res[q] = r;
-        if (!(r <= 1.7976931348623157e308)) bad = true;
-        else if (r < tol) done[q] = 1;
+  MuRun r;
+  int rc = r.begin(c, d_x, tol, max_iter);
+  while (!rc && !r.finished) {
+    if ((rc = r.enqueue())) break;
+    rc = r.collect();
+  }
+  if (rc) return rc;
+  return r.end(iters, resid);
+}
+
+int qdse_mu_solve_group(qdse_mu_ctx** ctxs, int n_ctx, double** d_x, double tol, int max_iter,
+                        int** iters, double** resid) {
+  if (!ctxs || !d_x || n_ctx < 1 || !(tol > 0.0) || max_iter < 1) return QDSE_EINVAL;
+  for (int q = 0; q < n_ctx; ++q) {
+    if (!ctxs[q] || !d_x[q]) return QDSE_EINVAL;
+    for (int p = 0; p < q; ++p)
+      if (ctxs[p] == ctxs[q]) return QDSE_EINVAL;
+  }
+  std::vector<MuRun> R(n_ctx);
+  for (int q = 0; q < n_ctx; ++q)
+    if (int rc = R[q].begin(ctxs[q], d_x[q], tol, max_iter)) return rc;
+  for (;;) {
+    bool any = false;
+    for (MuRun& r : R)  // one sweep of every unfinished context, each on its stream
+      if (!r.finished) {
+        any = true;
+        if (int rc = r.enqueue()) return rc;
       }
-      if (!done[q]) all = false;
-    }
-    // converged instances are frozen (copied forward) from the next sweep on
-    if (all || bad) {
-      rc = bad ? QDSE_ENAN : QDSE_OK;
-      break;
-    }
-    if (k == max_iter) rc = QDSE_NOT_CONVERGED;
+    if (!any) break;
+    for (MuRun& r : R)
+      if (!r.finished && r.k > 0)
+        if (int rc = r.collect()) return rc;
   }
-  if (hipMemcpyAsync(d_x, c->d_xb[cur], mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice, st) !=
-          hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return QDSE_EDEVICE;
-  for (int q = 0; q < c->n_inst; ++q) {
-    if (iters) iters[q] = it[q];
-    if (resid) resid[q] = res[q];
+  int worst = QDSE_OK;
+  for (int q = 0; q < n_ctx; ++q) {
+    const int rc = R[q].end(iters ? iters[q] : nullptr, resid ? resid[q] : nullptr);
+    if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
+    else if (rc > 0 && worst == QDSE_OK) worst = rc;
   }
-  return rc;
+  return worst;
 }
 
 int qdse_mu_solve_anderson(qdse_mu_ctx* c, double* d_x, double tol, int max_iter, int depth,

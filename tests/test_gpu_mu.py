@@ -147,3 +147,69 @@ def test_mu_anderson_solve_reaches_oracle_fixed_point(Q, depth):
         if depth:
             assert it[k] < 0.6 * n_sw, (it[k], n_sw)
 
+
+
+def test_mu_batch_with_own_parameters_matches_single_instances(Q):
+    """One launch sweeps instances with their own mu, m and interaction: the
+    result equals, bit for bit, single-instance contexts of the same grid."""
+    print("case mu batch vs single instances 8x8x6", flush=True)
+    rng = np.random.default_rng(41)
+    kw = dict(r_min=1e-2, r_max=8.0, p4_max=8.0, lam4=0.5)
+    params = [(0.55, 0.678, 0.005, 0.1), (0.55, 0.678, 0.15, 0.37), (1.024, 0.5, 0.0, 0.25)]
+    g = O.mu_grid(8, 8, 6, **kw)
+    xs = np.stack([smooth_mu(g, rng) for _ in params])
+    S = Q.MuSolver(8, 8, 6, params, **kw)
+    y = S.iterate(torch.tensor(xs, device="cuda"))
+    for k, p in enumerate(params):
+        S1 = Q.MuSolver(8, 8, 6, [p], **kw)
+        y1 = S1.iterate(torch.tensor(xs[k:k + 1], device="cuda"))
+        assert torch.equal(y[k:k + 1], y1), k
+        ref = O.F_mu(g, *p, xs[k])
+        for f in range(3):
+            assert rel(y[k, f].cpu().numpy(), ref[f]) < RTOL
+
+
+def test_mu_group_solve_of_ragged_classes_matches_oracle(Q):
+    """A ragged batch in the manner of the mixed configuration: three grid
+    classes (external grids 6x6, 8x8, 6x8 with 12, 16, 16 angles), each
+    context holding instances with their own mu in (0.05, 0.4) and m in
+    (0.03, 0.2), solved together by qdse_mu_solve_group on three streams;
+    each instance's fixed point matches the oracle's successive approximation
+    (same sweep count +-1, values to 1e-11). (Coarser angular rules, and the
+    chiral limit at larger mu, make successive approximation cycle or
+    diverge on grids this small, on both sides.)"""
+    print("case mu group solve of 3 classes", flush=True)
+    rng = np.random.default_rng(4)
+    kw = dict(r_min=1e-2, r_max=1e2, p4_max=1e2, lam4=0.5)
+    classes = [(6, 6, 12), (8, 8, 16), (6, 8, 16)]
+    solvers, xs, plist = [], [], []
+    for q, (ns, n4, na) in enumerate(classes):
+        params = [(0.55, 0.678, float(rng.uniform(0.03, 0.2)), float(rng.uniform(0.05, 0.4)))
+                  for _ in range(2 + q % 2)]
+        st = torch.cuda.Stream()
+        S = Q.MuSolver(ns, n4, na, params, stream=st, **kw)
+        x = torch.zeros(S.shape, dtype=torch.complex128, device="cuda")
+        x[:, 0] = 1.0
+        x[:, 1] = 0.3
+        x[:, 2] = 1.0
+        solvers.append(S)
+        xs.append(x)
+        plist.append(params)
+    torch.cuda.synchronize()
+    rc, its, rss = Q.mu_solve_group(solvers, xs, tol=1e-10, max_iter=300)
+    assert rc == Q.QDSE_OK, (rc, its)
+    for q, (ns, n4, na) in enumerate(classes):
+        g = O.mu_grid(ns, n4, na, **kw)
+        got = xs[q].cpu().numpy()
+        for k, (D, om, m, mu) in enumerate(plist[q]):
+            x = np.zeros((3, g.ne), complex)
+            x[0], x[1], x[2] = 1.0, 0.3, 1.0
+            for it in range(1, 301):
+                xn = O.F_mu(g, D, om, m, mu, x)
+                r = np.max(np.abs(xn - x))
+                x = xn
+                if r < 1e-10:
+                    break
+            assert abs(int(its[q][k]) - it) <= 1, (q, k, its[q][k], it)
+            for f in range(3):
+                assert rel(got[k, f], x[f]) < 1e-11, (q, k, f, rel(got[k, f], x[f]))
