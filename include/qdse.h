@@ -507,13 +507,15 @@ int qdse_measure_launch_floor(void* hip_stream, int workgroups, long long read_b
 
 /* The ceilings quoted by the rooflines, measured on the current device:
  * copy_gbs: read + write bandwidth of a 1 GiB streaming copy (larger than
- * the Infinity Cache); mfma32_tflops / mfma64_tflops: dense rate of
- * back-to-back v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 with
- * independent accumulators on every compute unit. Each output may be NULL
- * (skipped). Allocates and frees its own buffers; synchronises hip_stream.
+ * the Infinity Cache); read_gbs: bandwidth of a read-only streaming pass over
+ * 4 GiB (sixteen times the Infinity Cache; the ceiling of read-dominated
+ * kernels); mfma32_tflops / mfma64_tflops: dense rate of back-to-back
+ * v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 with independent
+ * accumulators on every compute unit. Each output may be NULL (skipped).
+ * Allocates and frees its own buffers; synchronises hip_stream.
  * Errors: QDSE_ENOMEM, QDSE_EDEVICE. */
 int qdse_measure_peaks(void* hip_stream, double* copy_gbs, double* mfma32_tflops,
-                       double* mfma64_tflops);
+                       double* mfma64_tflops, double* read_gbs);
 
 /* Human-readable name of a status code. */
 const char* qdse_strerror(int code);

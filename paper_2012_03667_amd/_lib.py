@@ -112,7 +112,7 @@ def load():
     L.qdse_mu_solve_group.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
                                       ctypes.c_double, ctypes.c_int, ctypes.POINTER(_ip),
                                       ctypes.POINTER(_dp)]
-    L.qdse_measure_peaks.argtypes = [_vp, _dp, _dp, _dp]
+    L.qdse_measure_peaks.argtypes = [_vp, _dp, _dp, _dp, _dp]
     L.qdse_measure_launch_floor.argtypes = [_vp, ctypes.c_int, ctypes.c_longlong, _dp, _dp]
     L.qdse_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, _ip, _ip, _ip]
     L.qdse_fred_nodes.argtypes = [ctypes.POINTER(FredGrid), _dp, _dp, _dp]
@@ -543,14 +543,15 @@ class FredSolver:
 
 
 def measure_peaks(stream=None):
-    """qdse_measure_peaks on the current device: dict of copy GB/s and the
-    FP32 / FP64 matrix-core TFLOP/s."""
+    """qdse_measure_peaks on the current device: dict of copy GB/s, read-only
+    stream GB/s and the FP32 / FP64 matrix-core TFLOP/s."""
     import torch
     st = stream if stream is not None else torch.cuda.current_stream()
-    c, m32, m64 = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    c, m32, m64, rd = (ctypes.c_double(0) for _ in range(4))
     _check(load().qdse_measure_peaks(_vp(st.cuda_stream), ctypes.byref(c), ctypes.byref(m32),
-                                     ctypes.byref(m64)), "qdse_measure_peaks")
-    return {"copy_GBs": c.value, "mfma_fp32_TFLOPs": m32.value, "mfma_fp64_TFLOPs": m64.value}
+                                     ctypes.byref(m64), ctypes.byref(rd)), "qdse_measure_peaks")
+    return {"copy_GBs": c.value, "read_GBs": rd.value, "mfma_fp32_TFLOPs": m32.value,
+            "mfma_fp64_TFLOPs": m64.value}
 
 
 def measure_launch_floor(workgroups, read_bytes, stream=None):

@@ -183,6 +183,7 @@ struct qdse_ctx {
   SolveCtl* d_tctl = nullptr;
   // driver of qdse_solve and the outcome of the last solve per instance
   int solver = QDSE_PICARD;
+  int fp32_state_pending = 0;  // h_state[n_inst..] holds the FP32 phase's final state
   std::vector<int> last_status, last_evals;
   KrylovWork kw;
 };
@@ -842,12 +843,16 @@ static int certify(qdse_ctx* c, const double* d_x, std::vector<int>& cert) {
 // iterate is d_x: the solve state read back from the device after the
 // stream has drained (not the mirror), the host's divergence flags, and the
 // branch certificate of the iterate. Fills c->last_status / last_evals.
-static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diverged,
-                        const std::vector<int>& sweeps_before, int* iters, double* resid) {
+static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diverged, int* iters,
+                        double* resid) {
   const int nI = c->n_inst;
   std::vector<SolveState> hs(nI);
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(hs.data(), c->d_state, nI * sizeof(SolveState), hipMemcpyDeviceToHost));
+  if (c->fp32_state_pending) {  // sweeps of the FP32 phase (its state copy has landed)
+    for (int k = 0; k < nI; ++k) c->last_sweeps32[k] = c->h_state[nI + k].sweeps;
+    c->fp32_state_pending = 0;
+  }
   std::vector<int> cert;
   int rc = certify(c, d_x, cert);
   if (rc) return rc;
@@ -862,7 +867,7 @@ static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diver
     else code = (k < (int)diverged.size() && diverged[k]) ? QDSE_EDIVERGED : QDSE_NOT_CONVERGED;
     c->last_status[k] = code;
     c->last_sweeps64[k] = h.sweeps;
-    c->last_evals[k] = h.sweeps + (k < (int)sweeps_before.size() ? sweeps_before[k] : 0);
+    c->last_evals[k] = h.sweeps + (k < (int)c->last_sweeps32.size() ? c->last_sweeps32[k] : 0);
     if (iters) iters[k] = c->last_evals[k];
     if (resid) resid[k] = h.resid;
   }
@@ -887,7 +892,7 @@ static int solve_persistent(qdse_ctx* c, double* d_x, int* iters, double* resid)
   }
   HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[flags[1] & 1], xlen(c) * sizeof(double),
                         hipMemcpyDeviceToDevice, st));
-  return finish_solve(c, d_x, std::vector<char>(), std::vector<int>(), iters, resid);
+  return finish_solve(c, d_x, std::vector<char>(), iters, resid);
 }
 
 }  // extern "C"
@@ -929,6 +934,7 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
     qdse_ctx* c = g.c;
     c->last_sweeps32.assign(c->n_inst, 0);
     c->last_sweeps64.assign(c->n_inst, 0);
+    c->fp32_state_pending = 0;
     int rc = group_phase_begin(g, tol, max_iter, conv_mode);
     if (rc) return rc;
   }
@@ -946,7 +952,12 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
       if (g.diverged.empty()) g.diverged.assign(c->n_inst, 0);
       for (int k = 0; k < c->n_inst; ++k) g.diverged[k] |= g.run.diverged[k];
       if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
-        for (int k = 0; k < c->n_inst; ++k) c->last_sweeps32[k] = g.hs[k].sweeps;
+        // the FP32 phase's final state, copied behind its last chunk (the
+        // mirror is only a prediction aid: its fields are not written
+        // atomically together); read after the stream drains
+        HIPCHK(hipMemcpyAsync(c->h_state + c->n_inst, c->d_state, c->n_inst * sizeof(SolveState),
+                              hipMemcpyDeviceToHost, c->stream));
+        c->fp32_state_pending = 1;
         g.phase = 1;
         rc = group_phase_begin(g, tol, max_iter, conv_mode);
         if (rc) return rc;
@@ -961,7 +972,7 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
   }
   int worst = QDSE_OK;
   for (GroupEntry& g : G) {
-    g.rc = finish_solve(g.c, g.d_x, g.diverged, g.c->last_sweeps32, g.iters, g.resid);
+    g.rc = finish_solve(g.c, g.d_x, g.diverged, g.iters, g.resid);
     if (severity(g.rc) > severity(worst)) worst = g.rc;
   }
   return worst;

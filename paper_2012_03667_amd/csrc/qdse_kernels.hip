@@ -188,7 +188,6 @@ __device__ inline void mirror_state(const SolveCtl* ctl, const SolveState* st, i
   m->resid = resid;
   m->metric[0][0] = last;
   m->metric[1][0] = before;
-  __threadfence_system();  // a host that sees the status sees the fields above
   m->status = status;
 }
 

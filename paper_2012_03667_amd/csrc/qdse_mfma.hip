@@ -128,7 +128,6 @@ __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool
       m->resid = S.resid;
       m->metric[0][0] = slot_max(S, (k + 2) % 3);
       m->metric[1][0] = before;
-      __threadfence_system();  // a host that sees the status sees the fields above
       m->status = status;
     }
   }

@@ -21,6 +21,32 @@ __global__ void __launch_bounds__(256) k_copy(const double4* __restrict__ a,
     b[i] = a[i];
 }
 
+// Read-only streaming pass: four independent 32-byte loads per thread in
+// flight, one sum per workgroup written.
+__global__ void __launch_bounds__(256) k_read(const double4* __restrict__ a, long n,
+                                              double* __restrict__ out) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const double4 v0 = a[i], v1 = a[i + stride], v2 = a[i + 2 * stride], v3 = a[i + 3 * stride];
+    s += ((v0.x + v0.y) + (v0.z + v0.w)) + ((v1.x + v1.y) + (v1.z + v1.w)) +
+         ((v2.x + v2.y) + (v2.z + v2.w)) + ((v3.x + v3.y) + (v3.z + v3.w));
+  }
+  for (; i < n; i += stride) {
+    const double4 v = a[i];
+    s += (v.x + v.y) + (v.z + v.w);
+  }
+  __shared__ double r[256];
+  r[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 256; ++k) t += r[k];
+    out[blockIdx.x] = t;
+  }
+}
+
 constexpr int kChains = 8;  // independent accumulators per wavefront
 
 __global__ void __launch_bounds__(256) k_mfma32(int iters, float seed, float* out) {
@@ -119,12 +145,34 @@ int time_ms(hipStream_t st, int reps, F&& launch, double* ms_out) {
 }  // namespace
 
 extern "C" int qdse_measure_peaks(void* hip_stream, double* copy_gbs, double* mfma32_tflops,
-                                  double* mfma64_tflops) {
+                                  double* mfma64_tflops, double* read_gbs) {
   hipStream_t st = (hipStream_t)hip_stream;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) != hipSuccess) return QDSE_EDEVICE;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   int rc = QDSE_OK;
+  if (read_gbs) {
+    // 4 GiB read once per pass: sixteen times the 256 MB Infinity Cache
+    const long n4 = (4l << 30) / (long)sizeof(double4);
+    const int blocks = ncu * 16;
+    double4* a = nullptr;
+    double* o = nullptr;
+    if (hipMalloc((void**)&a, n4 * sizeof(double4)) != hipSuccess ||
+        hipMalloc((void**)&o, (size_t)blocks * sizeof(double)) != hipSuccess) {
+      rc = QDSE_ENOMEM;
+    } else if (hipMemsetAsync(a, 0, n4 * sizeof(double4), st) != hipSuccess) {
+      rc = QDSE_EDEVICE;
+    } else {
+      double ms = 0.0;
+      rc = time_ms(st, 5, [&] {
+        hipLaunchKernelGGL(k_read, dim3(blocks), dim3(256), 0, st, (const double4*)a, n4, o);
+      }, &ms);
+      if (!rc) *read_gbs = (double)n4 * sizeof(double4) / (ms * 1e-3) / 1e9;
+    }
+    if (a) (void)hipFree(a);
+    if (o) (void)hipFree(o);
+    if (rc) return rc;
+  }
   if (copy_gbs) {
     // 1 GiB each way, larger than the 256 MB Infinity Cache
     const long n4 = (1l << 30) / (long)sizeof(double4);

@@ -32,5 +32,6 @@ def test_measured_peaks_are_positive_and_below_the_datasheet(Q):
     print("case measured peaks", flush=True)
     p = Q.measure_peaks()
     assert 0.0 < p["copy_GBs"] < 8000.0 * 1.05
+    assert 0.0 < p["read_GBs"] < 8000.0 * 1.05
     assert 0.0 < p["mfma_fp32_TFLOPs"] < 157.3 * 1.05
     assert 0.0 < p["mfma_fp64_TFLOPs"] < 78.6 * 1.05
