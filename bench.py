@@ -11,7 +11,7 @@ One step = reset both instances to the initial functions and solve them.
 Also reported on the same grid and interaction:
 * `batched`: 1024 instances with m ~ U[0, 0.2] GeV solved at equal accuracy
   (1e-7 relative to the oracle's fixed point: test tolerance 1e-8) by
-  (a) FP32 matrix-core sweeps to 1e-6 followed by FP64 matrix-core sweeps,
+  (a) FP32 matrix-core sweeps to 1e-5 followed by FP64 matrix-core sweeps,
   (b) FP64 matrix-core sweeps only and (c) FP64 direct-difference sweeps only;
   plus the plain two-instance solver at the same tolerance, for the
   equal-accuracy comparison.

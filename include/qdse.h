@@ -268,7 +268,7 @@ int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double l
 
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may
  * be NULL): FP32 matrix-core sweeps (QDSE_FP32_REFINE contexts) and FP64
- * sweeps. The FP32 phase stops at max(tol, 1e-6) on the same test; the FP64
+ * sweeps. The FP32 phase stops at max(tol, 1e-5) on the same test; the FP64
  * phase (matrix-core split form) then runs to tol. */
 int qdse_solve_stats(const qdse_ctx* ctx, int* sweeps_fp32, int* sweeps_fp64);
 

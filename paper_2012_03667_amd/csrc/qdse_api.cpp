@@ -917,7 +917,11 @@ struct GroupEntry {
 int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
   qdse_ctx* c = g.c;
   if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
-    double tol32 = 1e-6;  // switch to FP64 sweeps below this change
+    // switch to FP64 sweeps below this change: the refinement needs about
+    // twenty FP64 sweeps from anywhere below ~1e-5, because the FP32 fixed
+    // point itself is ~1e-5 away (broadband rounding error of the FP32
+    // contraction, which a few extra FP32 sweeps cannot remove)
+    double tol32 = 1e-5;
     if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
     if (tol32 < tol) tol32 = tol;
     return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32, g.d_x, nullptr);

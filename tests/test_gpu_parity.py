@@ -492,7 +492,7 @@ def test_fp64_matrix_batched_solve_matches_direct(Q):
 
 @pytest.mark.parametrize("n,na,nb,tol", [(64, 32, 40, 1e-9), (512, 128, 64, 1e-8)])
 def test_fp32_refined_solve_meets_1e7(Q, n, na, nb, tol):
-    """Batched FP32 sweeps to 1e-6, FP64 sweeps to tol on max|dM/M|, |dA| (at
+    """Batched FP32 sweeps to 1e-5, FP64 sweeps to tol on max|dM/M|, |dA| (at
     512 x 128 the benchmark's tolerance): the result is within 1e-7
     (relative, A, B, M) of the oracle's fixed point converged to 1e-13, on
     eight instances spread over the current masses."""
