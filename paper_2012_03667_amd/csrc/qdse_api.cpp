@@ -169,11 +169,15 @@ struct qdse_ctx {
   SolveState* h_state = nullptr;  // [2][n_inst], hipHostMalloc; [0] is the sweeps' mirror
   SolveState* d_mirror = nullptr;  // device address of h_state
   hipEvent_t ev[2] = {nullptr, nullptr};
-  // persistent solve: per-sweep statistics, grid-barrier counter, flags
-  unsigned long long* d_slots = nullptr;
-  unsigned int* d_barrier = nullptr;
-  int* d_flags = nullptr;
-  int persist_G = 0, persist_rpw = 0, persist_gsz = 1;  // G = 0: not usable
+  // single-launch solve (qdse_persistent.hip): tagged exchange words, the
+  // error word, the outcome block (pinned host memory and its device
+  // address) and the next unused tag
+  unsigned long long* d_xw = nullptr;
+  unsigned* d_perr = nullptr;
+  PersistOut* h_pout = nullptr;
+  PersistOut* d_pout = nullptr;
+  unsigned persist_tag = 1;
+  bool persist_ok = false;
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
   double* d_jdiag = nullptr;  // [n_inst][n][4] for qdse_jacobian_band
@@ -343,9 +347,6 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
   TRY(dalloc(&c->d_xbuf[1], xlen(c)));
   TRY(dalloc(&c->d_state, (size_t)n_inst));
   TRY(dalloc(&c->d_ctl, 1));
-  TRY(dalloc(&c->d_slots, (size_t)3 * n_inst));
-  TRY(dalloc(&c->d_barrier, persistent_barrier_words()));
-  TRY(dalloc(&c->d_flags, 2));
   if (hipHostMalloc((void**)&c->h_state, 2 * (size_t)n_inst * sizeof(SolveState),
                     hipHostMallocDefault) != hipSuccess) {
     c->h_state = nullptr;
@@ -424,32 +425,21 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
     }
   }
 #undef TRY
-  // Persistent single-launch solve: every instance must share kernel block 0
-  // and all workgroups must be co-resident. Rows per workgroup: the smallest
-  // count (from one row set per compute unit) whose grid fits, or
-  // QDSE_PERSIST_RPW.
-  if (c->n_blocks == 1 && n_inst <= 64 && !c->qc) {
-    int ncu = 256;
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-    int rpw0 = std::max(1, (g.n + ncu - 1) / ncu), rpw1 = 8;
-    if (const char* e = std::getenv("QDSE_PERSIST_RPW")) rpw0 = rpw1 = std::atoi(e);
-    int dev_lds = 65536;
-    (void)hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
-    for (int rpw = rpw0; rpw <= rpw1 && c->persist_G == 0; ++rpw) {
-      if (rpw < 1) break;
-      // iterate and node functions of as many instances as fit next to the
-      // matrix rows
-      const long left = (long)dev_lds - 4096 - (long)rpw * 3 * g.nq * 8;
-      int gsz = (int)(left / ((long)(2 * g.n + 4 * g.nq) * 8));
-      if (gsz < 1) continue;
-      if (gsz > n_inst) gsz = n_inst;
-      int maxb = 0;
-      if (persistent_max_blocks(rpw, g.n, g.nq, gsz, &maxb) != hipSuccess) break;
-      const int G = (g.n + rpw - 1) / rpw;
-      if (G <= maxb) {
-        c->persist_G = G;
-        c->persist_rpw = rpw;
-        c->persist_gsz = gsz;
+  // Single-launch solve: every instance shares kernel block 0, the LDS fits
+  // and ceil(n / 4) workgroups are co-resident. Its exchange words start at
+  // tag 0, below every tag a solve uses.
+  if (c->n_blocks == 1 && !c->qc) {
+    bool fits = false;
+    if (persistent_fits(n_inst, g.n, g.ldk, &fits) == hipSuccess && fits) {
+      const size_t words = persistent_words(n_inst, g.n);
+      if (dalloc(&c->d_xw, words) == QDSE_OK && dalloc(&c->d_perr, 1) == QDSE_OK &&
+          hipMemsetAsync(c->d_xw, 0, words * sizeof(unsigned long long), st) == hipSuccess &&
+          hipMemsetAsync(c->d_perr, 0, sizeof(unsigned), st) == hipSuccess &&
+          hipHostMalloc((void**)&c->h_pout, sizeof(PersistOut), hipHostMallocDefault) ==
+              hipSuccess &&
+          hipHostGetDevicePointer((void**)&c->d_pout, c->h_pout, 0) == hipSuccess) {
+        c->h_pout->tag = 0;
+        c->persist_ok = true;
       }
     }
     (void)hipGetLastError();
@@ -485,11 +475,12 @@ void qdse_destroy(qdse_ctx* c) {
   for (hipEvent_t e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->h_state) (void)hipHostFree(c->h_state);
+  if (c->h_pout) (void)hipHostFree(c->h_pout);
   void* ptrs[] = {c->d_s,       c->d_t,       c->d_W,       c->d_z,     c->d_wz,
                   c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_M32,
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
-                  c->d_ctl,     c->d_part,    c->d_gq,      c->d_slots, c->d_barrier,
-                  c->d_flags,   c->d_C32,     c->d_M64,     c->d_C64,     c->d_tstate,
+                  c->d_ctl,     c->d_part,    c->d_gq,      c->d_xw,      c->d_perr,
+                  c->d_C32,     c->d_M64,     c->d_C64,     c->d_tstate,
                   c->d_tctl,    c->d_sK,      c->d_sig,     c->d_jdiag};
   for (void* p : ptrs) dfree(p);
   c->kw.release();
@@ -843,19 +834,10 @@ static int certify(qdse_ctx* c, const double* d_x, std::vector<int>& cert) {
 // iterate is d_x: the solve state read back from the device after the
 // stream has drained (not the mirror), the host's divergence flags, and the
 // branch certificate of the iterate. Fills c->last_status / last_evals.
-static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diverged, int* iters,
-                        double* resid) {
+static int finish_outcome(qdse_ctx* c, const std::vector<SolveState>& hs,
+                          const std::vector<int>& cert, const std::vector<char>& diverged,
+                          int* iters, double* resid) {
   const int nI = c->n_inst;
-  std::vector<SolveState> hs(nI);
-  HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(hs.data(), c->d_state, nI * sizeof(SolveState), hipMemcpyDeviceToHost));
-  if (c->fp32_state_pending) {  // sweeps of the FP32 phase (its state copy has landed)
-    for (int k = 0; k < nI; ++k) c->last_sweeps32[k] = c->h_state[nI + k].sweeps;
-    c->fp32_state_pending = 0;
-  }
-  std::vector<int> cert;
-  int rc = certify(c, d_x, cert);
-  if (rc) return rc;
   c->last_status.assign(nI, QDSE_OK);
   c->last_evals.assign(nI, 0);
   c->last_sweeps64.assign(nI, 0);
@@ -874,25 +856,75 @@ static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diver
   return worst_of(c->last_status);
 }
 
-// One cooperative launch runs the whole solve (qdse_persistent.hip); the
-// iterate ends in xbuf[flags[1]].
-static int solve_persistent(qdse_ctx* c, double* d_x, int* iters, double* resid) {
+static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diverged, int* iters,
+                        double* resid) {
+  const int nI = c->n_inst;
+  std::vector<SolveState> hs(nI);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(hs.data(), c->d_state, nI * sizeof(SolveState), hipMemcpyDeviceToHost));
+  if (c->fp32_state_pending) {  // sweeps of the FP32 phase (its state copy has landed)
+    for (int k = 0; k < nI; ++k) c->last_sweeps32[k] = c->h_state[nI + k].sweeps;
+    c->fp32_state_pending = 0;
+  }
+  std::vector<int> cert;
+  int rc = certify(c, d_x, cert);
+  if (rc) return rc;
+  return finish_outcome(c, hs, cert, diverged, iters, resid);
+}
+
+// One cooperative launch runs the whole solve (qdse_persistent.hip), in
+// place on d_x. Its tags are persist_tag + 1 ... persist_tag + max_iter + 1;
+// persist_tag then moves past them. Before the 32-bit tags would wrap, the
+// exchange words and the error word are cleared and the count restarts.
+// QDSE_PERSISTENT=0 selects the kernel-per-sweep driver instead; =1 makes
+// the single-launch solve a requirement (QDSE_ENOTSUP where it cannot run).
+static bool persistent_usable(const qdse_ctx* c, int max_iter) {
+  if (!c->persist_ok || c->solver != QDSE_PICARD || c->precision != QDSE_FP64) return false;
+  if (max_iter > (1 << 30)) return false;
+  const char* e = std::getenv("QDSE_PERSISTENT");
+  return !(e && e[0] == '0');
+}
+
+static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode,
+                            int* iters, double* resid) {
   const HostGrid& g = c->hg;
   hipStream_t st = c->stream;
-  HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_lo, c->d_sw,
-                           c->d_t, c->d_s, c->d_xbuf[0], c->d_xbuf[1], c->d_state, c->d_ctl,
-                           c->d_slots, c->d_barrier, c->d_flags, c->persist_G, c->persist_rpw,
-                           c->persist_gsz, std::getenv("QDSE_PERSIST_PLAIN") ? 0 : 1));
-  int flags[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(flags, c->d_flags, sizeof(flags), hipMemcpyDeviceToHost, st));
+  c->last_sweeps32.assign(c->n_inst, 0);
+  c->last_sweeps64.assign(c->n_inst, 0);
+  const unsigned long long span = (unsigned long long)max_iter + 2;
+  if ((unsigned long long)c->persist_tag + span > 0xffffffffull) {
+    HIPCHK(hipMemsetAsync(c->d_xw, 0,
+                          persistent_words(c->n_inst, g.n) * sizeof(unsigned long long), st));
+    HIPCHK(hipMemsetAsync(c->d_perr, 0, sizeof(unsigned), st));
+    c->persist_tag = 1;
+  }
+  const unsigned tag0 = c->persist_tag;
+  c->persist_tag += (unsigned)span;
+  HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_sw, c->d_t,
+                           c->d_s, d_x, c->d_xw, c->d_pout, tol, max_iter, conv_mode, tag0,
+                           c->d_perr));
   HIPCHK(hipStreamSynchronize(st));
-  if (flags[0] != 0) {
-    g_last_error = "persistent solve: grid barrier timed out";
+  const PersistOut& o = *c->h_pout;
+  if (o.tag != tag0) {
+    unsigned err = 0;
+    HIPCHK(hipMemcpy(&err, c->d_perr, sizeof(unsigned), hipMemcpyDeviceToHost));
+    g_last_error = err == tag0
+                       ? "single-launch solve: a workgroup waited too long for the exchange"
+                       : "single-launch solve: no outcome written";
     return QDSE_EDEVICE;
   }
-  HIPCHK(hipMemcpyAsync(d_x, c->d_xbuf[flags[1] & 1], xlen(c) * sizeof(double),
-                        hipMemcpyDeviceToDevice, st));
-  return finish_solve(c, d_x, std::vector<char>(), iters, resid);
+  const int nI = c->n_inst;
+  std::vector<SolveState> hs(nI);
+  std::vector<int> cert(nI);
+  std::vector<char> diverged(nI);
+  for (int k = 0; k < nI; ++k) {
+    hs[k].status = o.status[k];
+    hs[k].sweeps = o.sweeps[k];
+    hs[k].resid = o.resid[k];
+    cert[k] = o.cert[k];
+    diverged[k] = (char)(o.diverged[k] != 0);
+  }
+  return finish_outcome(c, hs, cert, diverged, iters, resid);
 }
 
 }  // extern "C"
@@ -1079,17 +1111,11 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
     int rc = save_start(c, d_x);
     if (rc) return rc;
   }
-  if (c->solver == QDSE_PICARD && c->precision == QDSE_FP64 && c->persist_G > 0 &&
-      std::getenv("QDSE_PERSISTENT") != nullptr) {
-    hipStream_t st = c->stream;
-    c->last_sweeps32.assign(c->n_inst, 0);
-    c->last_sweeps64.assign(c->n_inst, 0);
-    HIPCHK(hipMemcpyAsync(c->d_xbuf[0], d_x, xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
-                          st));
-    SolveCtl ctl{tol, conv_mode, max_iter};
-    HIPCHK(hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_solve_init(st, c->n_inst, c->d_state));
-    return solve_persistent(c, d_x, iters, resid);
+  if (persistent_usable(c, max_iter))
+    return solve_persistent(c, d_x, tol, max_iter, conv_mode, iters, resid);
+  if (const char* e = std::getenv("QDSE_PERSISTENT"); e && e[0] == '1') {
+    g_last_error = "QDSE_PERSISTENT=1: the single-launch solve does not apply to this context";
+    return QDSE_ENOTSUP;
   }
   std::vector<GroupEntry> G(1);
   G[0].c = c;

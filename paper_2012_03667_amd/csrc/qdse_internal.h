@@ -257,15 +257,29 @@ hipError_t launch_fred_sweep(hipStream_t st, int n, double alpha, const double* 
                              hipEvent_t ev1 = nullptr);
 void gl_nodes_on(int n, double a, double b, double* x, double* w);
 
-// Persistent (cooperative) solve of a few instances sharing kernel block 0.
-size_t persistent_lds_bytes(int rpw, int n, int nq, int gsz);
-size_t persistent_barrier_words();
-hipError_t persistent_max_blocks(int rpw, int n, int nq, int gsz, int* max_blocks);
+// Outcome of a single-launch solve, written by its workgroup 0 into pinned
+// host memory at the end: per instance the status (0 running, 1 converged,
+// 2 sweep cap, 3 not finite), sweeps, deciding statistic, branch
+// certificate bits and divergence mark; tag last (the solve's tag0).
+struct PersistOut {
+  unsigned tag;
+  int pad;
+  int status[4], sweeps[4];
+  double resid[4];
+  int cert[4], diverged[4];
+};
+
+// Single-launch (cooperative) solve of up to persistent_max_inst() instances
+// sharing kernel block 0 (qdse_persistent.hip).
+size_t persistent_lds_bytes(int n_inst, int n, int ldk);
+size_t persistent_words(int n_inst, int n);
+int persistent_blocks(int n);
+int persistent_max_inst();
+hipError_t persistent_fits(int n_inst, int n, int ldk, bool* fits);
 hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
-                             const InstDev* inst, const double* K, const int* lo,
-                             const double* sw, const double* t, const double* s, double* xbuf0,
-                             double* xbuf1, SolveState* state, const SolveCtl* ctl,
-                             unsigned long long* slots, unsigned int* barrier, int* flags, int G,
-                             int rpw, int gsz, int coherent);
+                             const InstDev* inst, const double* K, const double* sw,
+                             const double* t, const double* s, double* x,
+                             unsigned long long* xw, PersistOut* out, double tol, int max_iter,
+                             int mode, unsigned tag0, unsigned* err);
 
 }  // namespace qdse

@@ -32,67 +32,13 @@
 // in FP64 before they multiply the singular kernel.
 
 #include "qdse_internal.h"
+#include "qdse_sweep_row.h"
 
 namespace qdse {
 
 namespace {
 
-constexpr int WAVE = 64;
-// Floor (GeV) of the relative mass-function test, where M = B/A vanishes.
-constexpr double kMassFloor = 1e-8;
-
-// A 64-bit value moved across lanes by a DPP control (two 32-bit halves);
-// lanes of rows outside ROWS receive 0.
-template <int CTRL, int ROWS>
-__device__ inline double dpp_move(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Sum over the 64 lanes (all active), returned in every lane: butterflies
-// inside each row of 16 lanes (two quad permutations, the half-row and row
-// mirrors), then the broadcasts of lanes 15 and 31 gather the four row sums
-// in lane 63, which is read back as a scalar. Register-to-register moves
-// only, no LDS round trips.
-__device__ inline double wave_sum(double v) {
-  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
-  v += dpp_move<0x140, 0xF>(v);  // row_mirror: the row sum in every lane of the row
-  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3: the total in row 3
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Forward-mode dual number: value and directional derivative.
-struct Dual {
-  double v, d;
-  __device__ Dual() = default;
-  __device__ constexpr Dual(double a, double b) : v(a), d(b) {}
-};
-__device__ inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
-__device__ inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
-__device__ inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-__device__ inline Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
-__device__ inline Dual operator/(Dual a, Dual b) {
-  const double q = a.v / b.v;
-  return {q, (a.d - q * b.d) / b.v};
-}
-__device__ inline Dual dual_fma(Dual a, Dual b, Dual c) { return a * b + c; }
-__device__ inline double dual_fma(double a, double b, double c) { return fma(a, b, c); }
-__device__ inline Dual wave_sum(Dual x) { return {wave_sum(x.v), wave_sum(x.d)}; }
-
-template <class T> __device__ inline T make(double v, double d);
-template <> __device__ inline double make<double>(double v, double) { return v; }
-template <> __device__ inline Dual make<Dual>(double v, double d) { return {v, d}; }
-__device__ inline double val(double x) { return x; }
-__device__ inline double val(Dual x) { return x.v; }
-__device__ inline double tan_(Dual x) { return x.d; }
+using namespace sweep;
 
 // Ultraviolet term of the Qin-Chang interaction, the part Sec. II leaves out:
 // 8 pi^2 gamma_m F(k^2) / ln[tau + (1 + k^2/L^2)^2] with F(k^2) =
@@ -271,30 +217,6 @@ __global__ void k_solve_init(int n_inst, SolveState* st, SolveCtl* ctl, SolveCtl
   }
 }
 
-// ---------------------------------------------------------------- node functions
-// Interpolated A, B at the loop nodes (4-point stencil with a base index known
-// from the interleaving, eq. chazhiresult and its cubic analogue) and the
-// functions the contraction needs: nodes[inst][5][ldk] =
-// {A(t), B(t), sigma_V, sigma_S, t sigma_V}, plus their tangents for Dual.
-template <class T>
-__device__ inline void node_core(const double w[4], const T xa[4], const T xb[4], double tj,
-                                 T* out) {
-  T Aq = make<T>(0.0, 0.0), Bq = make<T>(0.0, 0.0);
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const T wl = make<T>(w[l], 0.0);
-    Aq = Aq + wl * xa[l];
-    Bq = Bq + wl * xb[l];
-  }
-  const T tt = make<T>(tj, 0.0);
-  const T Dl = tt * Aq * Aq + Bq * Bq;
-  const T sV = Aq / Dl, sS = Bq / Dl;
-  out[0] = Aq;
-  out[1] = Bq;
-  out[2] = sV;
-  out[3] = sS;
-  out[4] = tt * sV;
-}
 
 template <class T>
 __device__ inline void node_values(int n, int j, const int* lo, const double* sw, double tj,
@@ -375,53 +297,6 @@ __device__ inline void row_accumulate(int nq, int ldk, size_t mat, const double*
   for (int c = 0; c < 4; ++c) acc[c] = wave_sum(acc[c]);
 }
 
-// One loop node's contribution to the four row sums (explicit FMAs).
-__device__ inline void row_term(double kT, double k3, double k0, double Aq, double Bq, double sV,
-                                double sS, double tsV, double s, double Ai, double Bi, double& a0,
-                                double& a1, double& a2, double& a3) {
-  const double dA = Aq - Ai, dB = Bq - Bi, sA = Aq + Ai;
-  const double e = fma(2.0 * sS, dB, fma(s, sV, tsV) * dA);
-  a0 = fma(kT, e, a0);
-  a1 = fma(k3, sV * sA, a1);
-  a2 = fma(kT, fma(sS, dA, -(sV * dB)), a2);
-  a3 = fma(k0, sS * sA, a3);
-}
-
-// Lane sums of the FP64 hot sweep over j = j0, j0 + 64, ... < nq.
-template <int U = 6>
-__device__ inline void row_stream_f64(int j0, int nq, int ldk, size_t mat,
-                                      const double* __restrict__ Ki, const double* __restrict__ nd,
-                                      double s, double Ai, double Bi, double& a0, double& a1,
-                                      double& a2, double& a3) {
-  // Loads of U consecutive lane strides are issued before any arithmetic so
-  // that a wavefront has ~8 U loads in flight; the accumulation order per lane
-  // is still j = j0, j0 + 64, ... whatever U. U = 6 (two load rounds per row
-  // at 513 loop nodes) measured fastest among 4, 5, 6, 8 for small batches;
-  // the many-workgroup large-batch sweep prefers U = 2 (more resident
-  // wavefronts).
-  for (int jb = j0; jb < nq; jb += U * WAVE) {
-    double kT[U], k3[U], k0[U], Aq[U], Bq[U], sV[U], sS[U], tsV[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = jb + u * WAVE;
-      if (j < nq) {
-        kT[u] = Ki[j];
-        k3[u] = Ki[mat + j];
-        k0[u] = Ki[2 * mat + j];
-        Aq[u] = nd[j];
-        Bq[u] = nd[ldk + j];
-        sV[u] = nd[2 * ldk + j];
-        sS[u] = nd[3 * ldk + j];
-        tsV[u] = nd[4 * ldk + j];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (jb + u * WAVE < nq)
-        row_term(kT[u], k3[u], k0[u], Aq[u], Bq[u], sV[u], sS[u], tsV[u], s, Ai, Bi, a0, a1, a2,
-                 a3);
-  }
-}
 
 // Specialised FP64 body for the hot sweep: lane sums, then wave sums.
 template <int U = 6>
@@ -430,18 +305,13 @@ __device__ inline void row_accumulate_f64(int nq, int ldk, size_t mat, const dou
                                           double Bi, int lane, double acc[4]) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   row_stream_f64<U>(lane, nq, ldk, mat, Ki, nd, s, Ai, Bi, a0, a1, a2, a3);
-  acc[0] = wave_sum(a0);
-  acc[1] = wave_sum(a1);
-  acc[2] = wave_sum(a2);
-  acc[3] = wave_sum(a3);
+  wave_sum4(a0, a1, a2, a3);
+  acc[0] = a0;
+  acc[1] = a1;
+  acc[2] = a2;
+  acc[3] = a3;
 }
 
-__device__ inline double test_stat(int mode, double An, double Bn, double Ao, double Bo) {
-  const double dA = fabs(An - Ao);
-  if (mode == QDSE_CONV_ABS) return fmax(dA, fabs(Bn - Bo));
-  const double Mn = Bn / An, Mo = Bo / Ao;
-  return fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloor));
-}
 
 __global__ void __launch_bounds__(256) k_sweep(int n_inst, int n, int nq, int ldk,
                                                const InstDev* __restrict__ inst_,
@@ -677,16 +547,10 @@ __global__ void __launch_bounds__(256) k_sweep_row(
     return;
   }
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll
-  for (int u = 0; u < ROW_PF; ++u) {
-    const int j = lane + u * WAVE;
-    if (j < nq)
-      row_term(kT[u], k3[u], k0[u], nd[j], nd[ldk + j], nd[2 * ldk + j], nd[3 * ldk + j],
-               nd[4 * ldk + j], s, Ai, Bi, a0, a1, a2, a3);
-  }
+  row_regs<ROW_PF>(lane, nq, ldk, nd, kT, k3, k0, s, Ai, Bi, a0, a1, a2, a3);
   row_stream_f64(lane + ROW_PF * WAVE, nq, ldk, mat, Ki, nd, s, Ai, Bi, a0, a1, a2, a3);
-  const double acc0 = wave_sum(a0), acc1 = wave_sum(a1), acc2 = wave_sum(a2),
-               acc3 = wave_sum(a3);
+  wave_sum4(a0, a1, a2, a3);
+  const double acc0 = a0, acc1 = a1, acc2 = a2, acc3 = a3;
   if (QC) {
     if (lane == 0 && i < rows) {
       double* sg = sig + (size_t)inst * 2 * rows;
@@ -1223,29 +1087,6 @@ __global__ void k_select(int n_inst, int len, const int* __restrict__ sel,
   if (sel[e / len]) dst[e] = src[e];
 }
 
-// Max over the 64 lanes, in every lane; a NaN in any lane gives NaN.
-__device__ inline double wave_max_nan(double v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    const double w = __shfl_xor(v, o, WAVE);
-    v = (v != v || w != w) ? __longlong_as_double(0x7ff8000000000000ll) : (w > v ? w : v);
-  }
-  return v;
-}
-
-// Block-wide (256 threads) max with NaN propagation; result in every thread.
-__device__ inline double block_max_nan(double v, double* red) {
-  v = wave_max_nan(v);
-  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
-  __syncthreads();
-  double m = red[0];
-  for (int k = 1; k < (int)(blockDim.x / WAVE); ++k) {
-    const double w = red[k];
-    m = (m != m || w != w) ? __longlong_as_double(0x7ff8000000000000ll) : (w > m ? w : m);
-  }
-  __syncthreads();
-  return m;
-}
-
 // The test statistic of Sec. II eq. jifenab2 between two iterates of every
 // instance (one workgroup each): mode 0 max_i max(|A'-A|, |B'-B|); mode 1
 // max_i max(|M'-M| / max(|M'|, kMassFloor), |A'-A|) with M = B/A.
@@ -1274,46 +1115,15 @@ __global__ void k_conv_stat(int n, int mode, const double* __restrict__ xo,
   if (threadIdx.x == 0) out[inst] = r;
 }
 
-// Branch certificate of an iterate (one workgroup per instance): bit 1 if
-// A <= 0 (or A or B not finite) at some node, bit 2 if A < 1 - 1e-9 at some
-// node, bit 4 if the mass function M = B/A rises from one node to the next
-// by more than 1e-6 max|M| where |M| exceeds 1e-3 max|M| (in the chiral
-// limit the far tail of B changes sign at the 1e-6 level of its infrared
-// value, and is not looked at). The physical (Nambu) solution of the
-// unrenormalised equation has A = 1 + Sigma_A >= 1 (with a maximum at
-// intermediate p^2 for the Ball-Chiu vertex) and M falling with p^2 for
-// m >= 0; the other fixed points the drivers can reach (successive
-// approximation's with A < 0 in the infrared, Newton's with A << 1 and M of
-// several GeV, the negative-mass partner, the grid-scale oscillations near
-// the end of the branch) fail one of these.
-// check_a = 0 skips bit 2 (renormalised setting: A = 1 at p^2 = zeta^2,
-// and A may fall below 1 beyond it).
+// Branch certificate of an iterate, one workgroup per instance
+// (certify_block).
 __global__ void k_certify(int n, int check_a, const double* __restrict__ x,
                           int* __restrict__ flags) {
-  __shared__ double red[256 / WAVE];
+  __shared__ double red[1024 / WAVE];
   __shared__ int bits;
-  const int inst = blockIdx.x;
-  const double* A = x + (size_t)inst * 2 * n;
-  const double* B = A + n;
-  if (threadIdx.x == 0) bits = 0;
-  double mmax = 0.0;
-  int b = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    if (!(A[i] > 0.0) || !(A[i] <= 1.7976931348623157e308) || !(fabs(B[i]) <= 1.7976931348623157e308))
-      b |= 1;
-    if (check_a && !(A[i] >= 1.0 - 1e-9)) b |= 2;
-    const double m = fabs(B[i] / A[i]);
-    mmax = (mmax != mmax || m != m) ? __longlong_as_double(0x7ff8000000000000ll) : (m > mmax ? m : mmax);
-  }
-  mmax = block_max_nan(mmax, red);  // contains a barrier: bits is initialised
-  const double rise = 1e-6 * mmax, floor_m = 1e-3 * mmax;
-  for (int i = threadIdx.x; i + 1 < n; i += blockDim.x) {
-    const double m0 = B[i] / A[i], m1 = B[i + 1] / A[i + 1];
-    if (m1 - m0 > rise && (fabs(m0) > floor_m || fabs(m1) > floor_m)) b |= 4;
-  }
-  if (b) atomicOr(&bits, b);
-  __syncthreads();
-  if (threadIdx.x == 0) flags[inst] = bits;
+  const double* A = x + (size_t)blockIdx.x * 2 * n;
+  const int b = certify_block(n, check_a, A, A + n, red, &bits);
+  if (threadIdx.x == 0) flags[blockIdx.x] = b;
 }
 
 }  // namespace

@@ -1,401 +1,427 @@
 // qdse_persistent.hip -- the whole successive-approximation solve of a few
-// instances in one cooperative launch (Sec. I eq. jifen12 with the per-point
-// test of Sec. II eq. jifenab2 or its mass-function form).
+// instances in one cooperative launch (Sec. I eq. jifen12, stopped by the
+// per-point test of Sec. II eq. jifenab2 or its mass-function form).
 //
-// A few-instance solve at N = 512 does ~7 MFLOP per sweep: launch latency,
-// not arithmetic or bandwidth, bounds a kernel-per-sweep driver. Here each of
-// G workgroups (all co-resident: cooperative launch) owns the external rows
-// i = g, g + G, ... for every instance, keeps the three kernel-matrix rows of
-// those i in LDS for the whole solve, and per sweep
-//   1. decides from the previous sweep's global test statistics which
-//      instances are frozen (all workgroups decide identically),
-//   2. copies the current iterate of a group of instances into LDS (coalesced
-//      coherent loads) and rebuilds their loop-node functions there
-//      (redundantly per workgroup: O(N) work),
-//   3. contracts its rows against them (FP64 direct-difference form, the same
-//      arithmetic as k_sweep) and writes the new iterate rows,
-//   4. folds its rows' test statistics into a per-instance global maximum,
-//   5. meets the other workgroups at a grid barrier.
-// Iterate and statistics travel through coherent (agent-scope) atomic loads,
-// stores and read-modify-writes, which reach the level shared by all L2
-// caches; a workgroup arrives at the barrier only after every one of its
-// memory operations has been acknowledged (s_waitcnt 0), so no cache
-// write-back or invalidation is needed. Arrivals are spread over NCTR
-// counters on separate cache lines (workgroup g adds to counter g % NCTR),
-// and wavefront 0 polls all of them at once. A plain variant (ordinary
-// accesses, release on arrival, acquire after the wait) is kept for checks.
-// The barrier wait is bounded: a workgroup that waits too long raises an error
-// flag and every workgroup leaves the loop, so the grid always drains.
+// A few-instance sweep at N = 512 is ~7 MFLOP and ~6 MB of kernel matrices:
+// with one launch per sweep, launch latency costs more than the sweep's work.
+// Here one launch runs every sweep. Each wavefront owns one external row i
+// (ceil(n / 8) workgroups of eight wavefronts, all co-resident) and keeps the
+// row's three kernel-matrix entries per lane stride in registers for the
+// whole solve. The instances take turns, one sweep per turn, in the same
+// order in every workgroup; a turn of instance q
+//   1. gathers the full iterate x_k of q that its previous turn published
+//      (it travelled while the other instances took their turns),
+//   2. evaluates the test statistic of sweep k over all rows (from x_{k-1}
+//      and x_k in LDS; every workgroup holds the same statistic, so every
+//      workgroup takes the same decision) and the loop-node functions of x_k,
+//   3. decides whether q stops, and if not
+//   4. contracts its rows (the arithmetic and summation order of the
+//      kernel-per-sweep row kernel, so both drivers produce the same bits)
+//      and publishes x_{k+1}.
+// Exchange without a separate barrier: every value travels as two 64-bit
+// words, each holding half of the value's bits and the sweep's 32-bit tag,
+// written and read with agent-scope atomic stores and loads (single-copy
+// atomic, coherent across the caches of the eight XCDs). A reader takes a
+// value once both of its words carry the tag of the sweep it waits for, so
+// the data is its own arrival flag: one store and one load per value and
+// sweep, no counters and no cache write-back or invalidation. Words are
+// double-buffered per instance by the parity of k; a workgroup can publish
+// sweep k + 2 of q only after every workgroup has published sweep k + 1 of
+// q, which each does only after it has finished reading sweep k of q. Tags
+// are tag0 + k; the host raises tag0 above every tag of the previous solve,
+// so words left from earlier solves never match.
+// At the end every workgroup writes its rows of the final iterates, and
+// workgroup 0 the outcome and the branch certificate of every instance into
+// pinned host memory (one synchronisation and no copies for the host).
+// Every wait is bounded: a workgroup that polls too long stores the solve's
+// tag0 into the error word and every workgroup leaves the loop at its next
+// poll, so the grid always drains (an older value in the error word belongs
+// to an earlier solve and is ignored).
 #include "qdse_internal.h"
+#include "qdse_sweep_row.h"
 
 namespace qdse {
 
 namespace {
 
-constexpr int PBLOCK = 256;
-constexpr int PWAVES = PBLOCK / 64;
-constexpr int MAX_RPW = 8;           // rows per workgroup held in LDS
-constexpr long SPIN_LIMIT = 1l << 24;  // ~0.5 s of polling before giving up
-constexpr double kMassFloorP = 1e-8;   // GeV, as in the kernel-per-sweep path
-constexpr int NCTR = 8;                // arrival counters
-constexpr int CTR_STRIDE = 32;         // unsigned ints between counters (128 bytes)
+using namespace sweep;
 
-__device__ inline double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+constexpr int PBLOCK = 512;                 // eight wavefronts, one row each
+constexpr int PROWS = PBLOCK / WAVE;
+constexpr int PMAX_INST = 4;                // instances of one solve
+constexpr int ROW_REG = 9;                  // lane strides of the row held in registers
+constexpr int GATHER_PT = 2;                // values per thread per gather round
+constexpr long SPIN_LIMIT = 1l << 20;       // polls (each ~1-2 us) before giving up
+constexpr int ERR_CHECK_EVERY = 16;         // polls between reads of the error word
+// Divergence of successive approximation: from sweep DIVERGE_AFTER on, a
+// statistic above DIVERGE_FACTOR times the smallest one seen so far marks
+// the instance (reported as diverged if it ends without passing the test).
+constexpr double DIVERGE_FACTOR = 100.0;
+constexpr int DIVERGE_AFTER = 30;
 
-__device__ inline double stat_p(int mode, double An, double Bn, double Ao, double Bo) {
-  const double dA = fabs(An - Ao);
-  if (mode == QDSE_CONV_ABS) return fmax(dA, fabs(Bn - Bo));
-  const double Mn = Bn / An, Mo = Bo / Ao;
-  return fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloorP));
+struct PArgs {
+  int n_inst, n, nq, ldk;
+  const InstDev* inst;
+  const double* K;   // kernel block shared by every instance: [3][n][ldk]
+  const double* sw;  // stencil weights [nq][4]; base clamp(j - 2, 0, n - 4)
+  const double* t;   // loop nodes
+  const double* s;   // external nodes
+  double* x;         // [n_inst][2n]: starting iterate in, solution out
+  unsigned long long* xw;  // [2][n_inst][2n][2] tagged words
+  PersistOut* out;   // per-instance outcome and branch certificate (host-mapped)
+  double tol;
+  int max_iter, mode;
+  unsigned tag0;
+  unsigned* err;
+};
+
+__device__ inline unsigned long long tagged(unsigned half, unsigned tag) {
+  return ((unsigned long long)tag << 32) | half;
 }
 
 __device__ inline unsigned long long stat_bits(double r) {
-  if (isnan(r)) return 0x7ff8000000000000ull;
-  return (unsigned long long)__double_as_longlong(r);
+  return (unsigned long long)__double_as_longlong(
+      isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
 }
 
-// Grid-wide barrier number k (1-based) on NCTR monotonically increasing
-// counters. Returns false if the wait timed out or another workgroup raised
-// the error flag.
-__device__ bool grid_sync(unsigned int* ctr, int G, unsigned int k, int* err,
-                          bool coherent_data) {
-  __shared__ int ok;
-  if (coherent_data) __builtin_amdgcn_s_waitcnt(0);  // this thread's accesses acknowledged
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    if (lane == 0) {
-      ok = 1;
-      unsigned int* mine = ctr + (blockIdx.x % NCTR) * CTR_STRIDE;
-      if (coherent_data)
-        __hip_atomic_fetch_add(mine, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      else  // release: this workgroup's plain stores before the arrival
-        __hip_atomic_fetch_add(mine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    // arrivals expected on counter `lane`: k times the workgroups g < G with
-    // g % NCTR == lane
-    const unsigned int target =
-        lane < NCTR ? k * (unsigned int)((G - lane + NCTR - 1) / NCTR) : 0u;
-    long spins = 0;
-    bool good = true;
-    for (;;) {
-      bool reached = true;
-      if (lane < NCTR)
-        reached = __hip_atomic_load(ctr + lane * CTR_STRIDE, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT) >= target;
-      if (__all(reached)) break;
-      int bad = 0;
-      if (lane == 0) {
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) bad = 1;
-        if (++spins > SPIN_LIMIT) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          bad = 1;
-        }
-      }
-      if (__shfl(bad, 0, 64)) {
-        good = false;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    if (lane == 0) {
-      if (!good) ok = 0;
-      if (!coherent_data)  // agent-wide acquire: other workgroups' plain stores
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
+// Max over the 64 lanes of a wavefront of the bit patterns of non-negative
+// doubles (their integer order is the order of the values, NaN above inf):
+// the butterflies and row broadcasts of wave_sum with max for +, the result
+// read from lane 63. Lanes that a row broadcast leaves out receive 0, which
+// is neutral.
+__device__ inline unsigned long long umax(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+__device__ inline unsigned long long bits_of(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+__device__ inline double from_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ inline unsigned long long wave_max_bits(unsigned long long v) {
+  v = umax(v, bits_of(dpp_move<0xB1, 0xF>(from_bits(v))));
+  v = umax(v, bits_of(dpp_move<0x4E, 0xF>(from_bits(v))));
+  v = umax(v, bits_of(dpp_move<0x141, 0xF>(from_bits(v))));
+  v = umax(v, bits_of(dpp_move<0x140, 0xF>(from_bits(v))));
+  v = umax(v, bits_of(dpp_move<0x142, 0xA>(from_bits(v))));
+  v = umax(v, bits_of(dpp_move<0x143, 0xC>(from_bits(v))));
+  const int lo = __builtin_amdgcn_readlane((int)v, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// The test statistic of one row (test_stat) with M_old = Bo/Ao supplied (the
+// value the previous sweep's statistic computed for the row); M_new = Bn/An
+// is returned for the next sweep. Same operations, same bits.
+__device__ inline double test_stat_m(int mode, double An, double Bn, double Ao, double Bo,
+                                     double Mo, double& Mn) {
+  const double dA = fabs(An - Ao);
+  if (mode == QDSE_CONV_ABS) {
+    Mn = 0.0;
+    return fmax(dA, fabs(Bn - Bo));
   }
-  __syncthreads();
-  return ok != 0;
+  Mn = Bn / An;
+  return fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloor));
 }
-
-// Iterate exchange between workgroups. With coherent = 1 every load and store
-// of the iterate is an agent-scope relaxed atomic (coherent across the XCDs'
-// L2 caches without invalidating them); ordering comes from the release on
-// barrier arrival. With coherent = 0 plain accesses plus an agent-scope
-// acquire after the barrier are used.
-__device__ inline double ld_x(const double* p, int coherent) {
-  return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
-}
-__device__ inline void st_x(double* p, double v, int coherent) {
-  if (coherent)
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else
-    *p = v;
-}
-
-struct PArgs {
-  int n_inst, n, nq, rpw, G, gsz;  // gsz: instances whose node functions share LDS
-  int coherent;  // 1: iterate exchanged with agent-scope atomic loads/stores
-  const InstDev* inst;
-  const double* K;  // kernel block shared by every instance
-  int ldk;
-  const int* lo;
-  const double* sw;
-  const double* t;
-  const double* s;
-  double* xbuf0;
-  double* xbuf1;
-  SolveState* state;
-  const SolveCtl* ctl;
-  unsigned long long* slots;  // [3][n_inst] bits of the per-sweep maxima
-  unsigned int* barrier;
-  int* flags;  // [0] error, [1] buffer index of the final iterate
-};
 
 __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   extern __shared__ double lds[];
-  const int n = a.n, nq = a.nq, rpw = a.rpw, G = a.G, g = blockIdx.x;
-  double* Kl = lds;                            // [rpw][3][nq]
-  double* xs = Kl + (size_t)rpw * 3 * nq;      // [gsz][2n] iterate of a group
-  double* nd = xs + (size_t)a.gsz * 2 * n;     // [gsz][4][nq] node functions
-  __shared__ int st_status[64];
-  __shared__ int st_sweeps[64];
-  __shared__ double st_resid[64];
-  __shared__ double red[PWAVES][MAX_RPW][4];
-  __shared__ unsigned long long wgmax;
-  __shared__ int all_frozen;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const SolveCtl ctl = *a.ctl;
+  const int n = a.n, nq = a.nq, ldk = a.ldk, nI = a.n_inst;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const int i = blockIdx.x * PROWS + wave;
+  const bool row_ok = i < n;
+  const int ic = row_ok ? i : n - 1;  // rows past the last compute and publish nothing
+  const int xl = 2 * n;
+  const size_t ndl = (size_t)5 * ldk;
+  double* xs = lds;                          // [2][nI][2n]: x_k of instance q at parity k & 1
+  double* ms = xs + (size_t)2 * nI * xl;     // [2][nI][n]: M = B/A of the same iterates
+  double* nd = ms + (size_t)2 * nI * n;      // [nI][5][ldk] node functions
+  double* wsl = nd + (size_t)nI * ndl;       // [nq][4] stencil weights
+  double* tl = wsl + (size_t)4 * nq;         // [nq] loop nodes
+  __shared__ unsigned long long st_max[PMAX_INST][2];
+  __shared__ double s_pref[PMAX_INST], s_m[PMAX_INST];
+  __shared__ double red[PBLOCK / WAVE];
+  __shared__ int ok, cbits;
 
-  // rows of this workgroup: i = g + r * G
-  int nrows = 0;
-  for (int r = 0; r < rpw; ++r)
-    if (g + r * G < n) nrows = r + 1;
-  for (int r = 0; r < nrows; ++r) {
-    const int i = g + r * G;
-    for (int c = 0; c < 3; ++c)
-      for (int j = tid; j < nq; j += PBLOCK)
-        Kl[((size_t)r * 3 + c) * nq + j] = a.K[(size_t)c * n * a.ldk + (size_t)i * a.ldk + j];
+  // the row's kernel entries, for the whole solve
+  const size_t mat = (size_t)n * ldk;
+  const double* Ki = a.K + (size_t)ic * ldk;
+  double kT[ROW_REG], k3[ROW_REG], k0[ROW_REG];
+#pragma unroll
+  for (int u = 0; u < ROW_REG; ++u) {
+    const int j = min(lane + u * WAVE, nq - 1);
+    kT[u] = Ki[j];
+    k3[u] = Ki[mat + j];
+    k0[u] = Ki[2 * mat + j];
   }
-  for (int q = tid; q < a.n_inst; q += PBLOCK) {
-    st_status[q] = 0;
-    st_sweeps[q] = 0;
-    st_resid[q] = __longlong_as_double(0x7ff0000000000000ll);
+  const double s = a.s[ic];
+  for (int e = tid; e < 4 * nq; e += PBLOCK) wsl[e] = a.sw[e];
+  for (int e = tid; e < nq; e += PBLOCK) tl[e] = a.t[e];
+  for (int e = tid; e < nI * xl; e += PBLOCK) xs[e] = a.x[e];  // x_0 at parity 0
+  if (tid < nI) {
+    s_pref[tid] = a.inst[tid].pref;
+    s_m[tid] = a.inst[tid].m;
+  }
+  if (tid < 2 * PMAX_INST) st_max[tid / 2][tid % 2] = 0ull;
+  if (tid == 0) ok = 1;
+  __syncthreads();
+
+  // Node functions of loop node j of instance q's iterate x at parity p.
+  auto node = [&](int q, int p, int j) {
+    const double* xq = xs + ((size_t)p * nI + q) * xl;
+    const int b = min(max(j - 2, 0), n - 4);
+    double w[4], xa[4], xb[4], v[5];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      w[l] = wsl[4 * j + l];
+      xa[l] = xq[b + l];
+      xb[l] = xq[n + b + l];
+    }
+    node_core<double>(w, xa, xb, tl[j], v);
+    double* ndq = nd + (size_t)q * ndl;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) ndq[c * ldk + j] = v[c];
+  };
+  for (int q = 0; q < nI; ++q) {
+    const double* x0 = xs + (size_t)q * xl;
+    for (int j = tid; j < nq; j += PBLOCK) node(q, 0, j);
+    for (int ii = tid; ii < n; ii += PBLOCK) ms[(size_t)q * n + ii] = x0[n + ii] / x0[ii];
   }
   __syncthreads();
 
-  int k = 1;
-  bool fine = true;
-  for (;; ++k) {
-    const double* xc = (k & 1) ? a.xbuf0 : a.xbuf1;  // sweep k reads buf[(k-1)%2]
-    double* xn = (k & 1) ? a.xbuf1 : a.xbuf0;
-    // 1. decisions from the statistics of sweep k-1
-    if (tid == 0) all_frozen = 1;
-    __syncthreads();
-    for (int q = tid; q < a.n_inst; q += PBLOCK) {
-      int stq = st_status[q];
-      if (stq == 0) {
-        if (st_sweeps[q] > 0) {
-          const double prev = __longlong_as_double((long long)__hip_atomic_load(
-              &a.slots[(size_t)((k - 1) % 3) * a.n_inst + q], __ATOMIC_RELAXED,
-              __HIP_MEMORY_SCOPE_AGENT));
-          if (!(prev <= 1.7976931348623157e308)) stq = 3;
-          else if (prev < ctl.tol) stq = 1;
-          if (stq) st_resid[q] = prev;
-        }
-        if (stq == 0 && st_sweeps[q] >= ctl.max_iter) {
-          stq = 2;
-          st_resid[q] = __longlong_as_double((long long)__hip_atomic_load(
-              &a.slots[(size_t)((k - 1) % 3) * a.n_inst + q], __ATOMIC_RELAXED,
-              __HIP_MEMORY_SCOPE_AGENT));
-        }
-        st_status[q] = stq;
+  // Solve state of instance q in lane q of every wavefront (the same in every
+  // workgroup): status (0 running, 1 converged, 2 sweep cap, 3 not finite),
+  // the sweeps whose iterate the workgroup holds, the deciding statistic.
+  int st_v = lane < nI ? (a.max_iter <= 0 ? 2 : 0) : 4;
+  int done_v = 0, div_v = 0;
+  double resid_v = __longlong_as_double(0x7ff0000000000000ll);  // +inf: no sweep yet
+  double rmin_v = resid_v;
+  unsigned run = (unsigned)__ballot(st_v == 0);
+
+  // Instances take turns, one sweep per turn, in the same order in every
+  // workgroup: a turn of instance q gathers the iterate its previous turn
+  // published (in flight meanwhile, behind the other instances' turns),
+  // evaluates the test statistic and the node functions, decides, and, if q
+  // still runs, contracts and publishes the next iterate.
+  unsigned pend = 0;  // instances with a published sweep not yet gathered
+  int q = 0;
+  // one round of loads of the tagged words of the values still pending
+  auto load_round = [&](const unsigned long long* wk, int v0, unsigned long long(&lo)[GATHER_PT],
+                        unsigned long long(&hi)[GATHER_PT], unsigned mask) {
+#pragma unroll
+    for (int g = 0; g < GATHER_PT; ++g) {
+      if (mask & (1u << g)) {
+        const int e = v0 + g * PBLOCK + tid;
+        lo[g] = __hip_atomic_load(wk + 2 * e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        hi[g] = __hip_atomic_load(wk + 2 * e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (stq == 0) all_frozen = 0;
-      if (g == 0)
-        __hip_atomic_store(&a.slots[(size_t)((k + 1) % 3) * a.n_inst + q], 0ull, __ATOMIC_RELAXED,
+    }
+  };
+  while (run) {
+    while (!((run >> q) & 1u)) q = (q + 1) % PMAX_INST;
+    int k = __builtin_amdgcn_readlane(done_v, q);  // sweeps of q held before this turn
+    if ((pend >> q) & 1u) {
+      // gather x_{k+1} of q
+      const unsigned tag = a.tag0 + (unsigned)(k + 1);
+      const unsigned long long* wk = a.xw + ((size_t)((k + 1) & 1) * nI + q) * xl * 2;
+      double* xn = xs + ((size_t)((k + 1) & 1) * nI + q) * xl;
+      bool good = true;
+      long spins = 0;
+      for (int v0 = 0; v0 < xl && good; v0 += GATHER_PT * PBLOCK) {
+        unsigned long long lo[GATHER_PT], hi[GATHER_PT];
+        unsigned pending = 0;
+#pragma unroll
+        for (int g = 0; g < GATHER_PT; ++g)
+          if (v0 + g * PBLOCK + tid < xl) pending |= 1u << g;
+        while (pending) {
+          load_round(wk, v0, lo, hi, pending);
+#pragma unroll
+          for (int g = 0; g < GATHER_PT; ++g) {
+            if ((pending & (1u << g)) && (unsigned)(lo[g] >> 32) == tag &&
+                (unsigned)(hi[g] >> 32) == tag) {
+              xn[v0 + g * PBLOCK + tid] =
+                  from_bits(((hi[g] & 0xffffffffull) << 32) | (lo[g] & 0xffffffffull));
+              pending &= ~(1u << g);
+            }
+          }
+          if (!pending) break;
+          ++spins;
+          if (spins % ERR_CHECK_EVERY == 0 &&
+              __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.tag0) {
+            good = false;
+            break;
+          }
+          if (spins > SPIN_LIMIT) {
+            __hip_atomic_store(a.err, a.tag0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            good = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      if (!good) ok = 0;
+      __syncthreads();
+      if (!ok) break;
+      k += 1;
+      pend &= ~(1u << q);
+      // statistic of sweep k over all rows (M of x_k kept for the next one)
+      // and the node functions of x_k (built before the decision: for an
+      // instance that stops here they are not used)
+      const double* xo = xs + ((size_t)((k - 1) & 1) * nI + q) * xl;
+      const double* xq = xs + ((size_t)(k & 1) * nI + q) * xl;
+      const double* mo = ms + ((size_t)((k - 1) & 1) * nI + q) * n;
+      double* mn = ms + ((size_t)(k & 1) * nI + q) * n;
+      if (tid == 0) st_max[q][(k + 1) & 1] = 0ull;  // last read at sweep k - 1
+      unsigned long long m = 0ull;
+      for (int t = tid; t < nq; t += PBLOCK) {
+        if (t < n) {
+          double Mn;
+          m = umax(m, stat_bits(test_stat_m(a.mode, xq[t], xq[n + t], xo[t], xo[n + t], mo[t], Mn)));
+          mn[t] = Mn;
+        }
+        node(q, k & 1, t);
+      }
+      m = wave_max_bits(m);
+      if (lane == 0) atomicMax(&st_max[q][k & 1], m);
+      __syncthreads();
+      // decision (every thread alike)
+      const double st = from_bits(st_max[q][k & 1]);
+      int sq = 0;
+      if (!(st <= 1.7976931348623157e308)) sq = 3;  // NaN or inf
+      else if (st < a.tol) sq = 1;
+      if (sq == 0 && k >= a.max_iter) sq = 2;
+      if (lane == q) {
+        done_v = k;
+        if (st < rmin_v) rmin_v = st;
+        if (k >= DIVERGE_AFTER && st > DIVERGE_FACTOR * rmin_v) div_v = 1;
+        if (sq != 0) {
+          st_v = sq;
+          resid_v = st;
+        }
+      }
+      if (sq != 0) {
+        run &= ~(1u << q);
+        q = (q + 1) % PMAX_INST;
+        continue;
+      }
+    }
+    // contraction of this wavefront's row of q from x_k: x_{k+1}, published
+    // tagged (lanes 0-3: the halves of A_i and B_i)
+    {
+      const double* xq = xs + ((size_t)(k & 1) * nI + q) * xl;
+      const double* ndq = nd + (size_t)q * ndl;
+      const double Ai = xq[ic], Bi = xq[n + ic];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      row_regs<ROW_REG>(lane, nq, ldk, ndq, kT, k3, k0, s, Ai, Bi, a0, a1, a2, a3);
+      if (nq > ROW_REG * WAVE)
+        row_stream_f64(lane + ROW_REG * WAVE, nq, ldk, mat, Ki, ndq, s, Ai, Bi, a0, a1, a2, a3);
+      wave_sum4(a0, a1, a2, a3);
+      const double An = 1.0 + s_pref[q] * (a1 - a0);
+      const double Bn = s_m[q] + s_pref[q] * fma(2.0 * s, a2, a3);
+      if (row_ok && lane < 4) {
+        const unsigned tag = a.tag0 + (unsigned)(k + 1);
+        unsigned long long* wk = a.xw + ((size_t)((k + 1) & 1) * nI + q) * xl * 2;
+        const unsigned long long bits = bits_of(lane < 2 ? An : Bn);
+        const unsigned half = (lane & 1) ? (unsigned)(bits >> 32) : (unsigned)bits;
+        const int e = lane < 2 ? i : n + i;
+        __hip_atomic_store(wk + 2 * e + (lane & 1), tagged(half, tag), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+      }
+      pend |= 1u << q;
     }
-    __syncthreads();
-    if (all_frozen) break;
+    q = (q + 1) % PMAX_INST;
+  }
 
-    for (int q0 = 0; q0 < a.n_inst; q0 += a.gsz) {
-      const int q1 = min(a.n_inst, q0 + a.gsz);
-      // 2. iterate of the group into LDS, then the node functions of its
-      //    running instances
-      for (int e = tid; e < (q1 - q0) * 2 * n; e += PBLOCK) {
-        const int q = q0 + e / (2 * n);
-        if (st_status[q] == 0) xs[e] = ld_x(xc + (size_t)q0 * 2 * n + e, a.coherent);
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int e = tid; e < (q1 - q0) * nq; e += PBLOCK) {
-        const int q = q0 + e / nq, j = e % nq;
-        if (st_status[q] != 0) continue;
-        const double* xq = xs + (size_t)(q - q0) * 2 * n;
-        const int b = a.lo[j];
-        const double* w = a.sw + 4 * j;
-        double Aq = 0.0, Bq = 0.0;
+  if (!ok) return;  // the host reports the error; x is left as it was
+  // the final iterate of every instance: this workgroup's rows
+  for (int e = tid; e < nI * PROWS * 2; e += PBLOCK) {
+    const int qq = e / (PROWS * 2), r = e % (PROWS * 2);
+    const int ii = blockIdx.x * PROWS + (r >> 1);
+    int kq = 0;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          Aq = fma(w[l], xq[b + l], Aq);
-          Bq = fma(w[l], xq[n + b + l], Bq);
-        }
-        const double tj = a.t[j];
-        const double Dl = tj * Aq * Aq + Bq * Bq;
-        double* ndq = nd + (size_t)(q - q0) * 4 * nq;
-        ndq[j] = Aq;
-        ndq[nq + j] = Bq;
-        ndq[2 * nq + j] = Aq / Dl;
-        ndq[3 * nq + j] = Bq / Dl;
-      }
-      __syncthreads();
-      for (int q = q0; q < q1; ++q) {
-        const double* xq = xc + (size_t)q * 2 * n;
-        double* xo = xn + (size_t)q * 2 * n;
-        if (st_status[q] != 0) {  // frozen: carry the iterate forward
-          for (int r = tid; r < nrows; r += PBLOCK) {
-            const int i = g + r * G;
-            st_x(xo + i, ld_x(xq + i, a.coherent), a.coherent);
-            st_x(xo + n + i, ld_x(xq + n + i, a.coherent), a.coherent);
-          }
-          continue;
-        }
-        const double* ndq = nd + (size_t)(q - q0) * 4 * nq;
-        const double* xsq = xs + (size_t)(q - q0) * 2 * n;
-        if (tid == 0) wgmax = 0ull;
-        // 3. contraction of this workgroup's rows
-        const InstDev P = a.inst[q];
-        double acc[MAX_RPW][4];
-        double Ai[MAX_RPW], Bi[MAX_RPW], si[MAX_RPW];
-#pragma unroll
-        for (int r = 0; r < MAX_RPW; ++r) {
-          acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
-          if (r < nrows) {
-            const int i = g + r * G;
-            Ai[r] = xsq[i];
-            Bi[r] = xsq[n + i];
-            si[r] = a.s[i];
-          }
-        }
-        for (int j = tid; j < nq; j += PBLOCK) {
-          const double Aq = ndq[j], Bq = ndq[nq + j], sV = ndq[2 * nq + j], sS = ndq[3 * nq + j];
-          const double tsV = a.t[j] * sV;
-#pragma unroll
-          for (int r = 0; r < MAX_RPW; ++r) {
-            if (r < nrows) {
-              const double* Kr = Kl + (size_t)r * 3 * nq;
-              const double kT = Kr[j], k3 = Kr[nq + j], k0 = Kr[2 * nq + j];
-              const double dA = Aq - Ai[r], dB = Bq - Bi[r], sA = Aq + Ai[r];
-              const double e = fma(2.0 * sS, dB, fma(si[r], sV, tsV) * dA);
-              acc[r][0] = fma(kT, e, acc[r][0]);
-              acc[r][1] = fma(k3, sV * sA, acc[r][1]);
-              acc[r][2] = fma(kT, fma(sS, dA, -(sV * dB)), acc[r][2]);
-              acc[r][3] = fma(k0, sS * sA, acc[r][3]);
-            }
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < MAX_RPW; ++r) {
-          if (r < nrows) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const double v = wsum(acc[r][c]);
-              if (lane == 0) red[wave][r][c] = v;
-            }
-          }
-        }
-        __syncthreads();
-        if (tid < nrows) {
-          const int r = tid, i = g + r * G;
-          double c4[4];
-          for (int c = 0; c < 4; ++c) {
-            double v = 0.0;
-            for (int w = 0; w < PWAVES; ++w) v += red[w][r][c];
-            c4[c] = v;
-          }
-          const double An = 1.0 + P.pref * (c4[1] - c4[0]);
-          const double Bn = P.m + P.pref * fma(2.0 * si[r], c4[2], c4[3]);
-          st_x(xo + i, An, a.coherent);
-          st_x(xo + n + i, Bn, a.coherent);
-          atomicMax(&wgmax, stat_bits(stat_p(ctl.mode, An, Bn, Ai[r], Bi[r])));
-        }
-        __syncthreads();
-        // 4. this workgroup's contribution to the instance's test statistic
-        if (tid == 0) {
-          atomicMax(&a.slots[(size_t)(k % 3) * a.n_inst + q], wgmax);
-          st_sweeps[q] += 1;
-        }
-      }
-      __syncthreads();
+    for (int b = 0; b < PMAX_INST; ++b) {
+      const int db = __builtin_amdgcn_readlane(done_v, b);
+      if (b == qq) kq = db;
     }
-    // 5. grid barrier k
-    if (!grid_sync(a.barrier, G, (unsigned int)k, a.flags, a.coherent != 0)) {
-      fine = false;
-      break;
+    if (ii < n) {
+      const int col = (r & 1) ? n + ii : ii;
+      a.x[(size_t)qq * xl + col] = xs[((size_t)(kq & 1) * nI + qq) * xl + col];
     }
   }
-  if (g == 0) {
-    for (int q = tid; q < a.n_inst; q += PBLOCK) {
-      a.state[q].status = fine ? st_status[q] : 3;
-      a.state[q].sweeps = st_sweeps[q];
-      a.state[q].resid = st_resid[q];
-    }
-    if (tid == 0) a.flags[1] = (k - 1) & 1;  // the last completed sweep wrote buf[(k-1)%2]
+  if (blockIdx.x != 0) return;
+  // outcome and branch certificate of every instance (workgroup 0)
+  for (int qq = 0; qq < nI; ++qq) {
+    const int kq = __builtin_amdgcn_readlane(done_v, qq);
+    const double* xf = xs + ((size_t)(kq & 1) * nI + qq) * xl;
+    const int cb = certify_block(n, 1, xf, xf + n, red, &cbits);
+    if (tid == 0) a.out->cert[qq] = cb;
   }
-}
-
-__global__ void k_persistent_reset(unsigned long long* slots, int nslots, unsigned int* barrier,
-                                   int* flags) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < nslots) slots[t] = 0ull;
-  if (t < NCTR) barrier[t * CTR_STRIDE] = 0u;
-  if (t == 0) {
-    flags[0] = 0;
-    flags[1] = 0;
+  if (tid < nI) {
+    a.out->status[tid] = st_v;
+    a.out->sweeps[tid] = done_v;
+    a.out->resid[tid] = resid_v;
+    a.out->diverged[tid] = div_v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    a.out->tag = a.tag0;
   }
 }
 
 }  // namespace
 
-size_t persistent_lds_bytes(int rpw, int n, int nq, int gsz) {
-  return ((size_t)rpw * 3 * nq + (size_t)gsz * (2 * n + 4 * nq)) * sizeof(double);
+size_t persistent_lds_bytes(int n_inst, int n, int ldk) {
+  const size_t nq = (size_t)n + 1;
+  return ((size_t)2 * n_inst * 3 * n + (size_t)n_inst * 5 * ldk + 5 * nq) * sizeof(double);
 }
 
-size_t persistent_barrier_words() { return (size_t)NCTR * CTR_STRIDE; }
+size_t persistent_words(int n_inst, int n) { return (size_t)2 * n_inst * 2 * n * 2; }
 
-// Launches the persistent solve; G workgroups, each holding rpw rows. The
-// caller has checked that every instance uses kernel block 0, that G
-// workgroups of this size are co-resident, and that n_inst <= 64.
-hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
-                             const InstDev* inst, const double* K, const int* lo,
-                             const double* sw, const double* t, const double* s, double* xbuf0,
-                             double* xbuf1, SolveState* state, const SolveCtl* ctl,
-                             unsigned long long* slots, unsigned int* barrier, int* flags, int G,
-                             int rpw, int gsz, int coherent) {
-  if (rpw > MAX_RPW || n_inst > 64 || (long)G * rpw < n || gsz < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_persistent_reset, dim3((3 * n_inst + 255) / 256), dim3(256), 0, st, slots,
-                     3 * n_inst, barrier, flags);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  PArgs a{n_inst, n, nq, rpw, G, gsz, coherent, inst, K, ldk, lo, sw, t, s, xbuf0, xbuf1, state,
-          ctl, slots, barrier, flags};
-  const size_t lds = persistent_lds_bytes(rpw, n, nq, gsz);
-  e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds);
-  if (e != hipSuccess) return e;
-  void* args[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(G), dim3(PBLOCK), args, lds, st);
-}
+int persistent_blocks(int n) { return (n + PROWS - 1) / PROWS; }
 
-hipError_t persistent_max_blocks(int rpw, int n, int nq, int gsz, int* max_blocks) {
-  int dev = 0, ncu = 0, occ = 0;
+int persistent_max_inst() { return PMAX_INST; }
+
+// Whether the cooperative solve of n_inst instances on an n-row grid fits:
+// LDS within the device's limit and ceil(n / 4) workgroups co-resident.
+hipError_t persistent_fits(int n_inst, int n, int ldk, bool* fits) {
+  *fits = false;
+  if (n_inst < 1 || n_inst > PMAX_INST || n < 4) return hipSuccess;
+  int dev = 0, ncu = 0, occ = 0, lds_max = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = persistent_lds_bytes(rpw, n, nq, gsz);
+  e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  const size_t lds = persistent_lds_bytes(n_inst, n, ldk);
+  if (lds + 1024 > (size_t)lds_max) return hipSuccess;
   e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds);
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_persistent, PBLOCK, lds);
   if (e != hipSuccess) return e;
-  *max_blocks = occ * ncu;
+  *fits = (long)occ * ncu >= persistent_blocks(n);
   return hipSuccess;
+}
+
+// Launches the cooperative solve. The caller has checked persistent_fits,
+// that every instance uses kernel block 0, that xw holds persistent_words
+// zero-initialised or older-tagged words, and that no tag in
+// (tag0, tag0 + max_iter + 1] was used before on xw or err.
+hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
+                             const InstDev* inst, const double* K, const double* sw,
+                             const double* t, const double* s, double* x,
+                             unsigned long long* xw, PersistOut* out, double tol, int max_iter,
+                             int mode, unsigned tag0, unsigned* err) {
+  if (n_inst < 1 || n_inst > PMAX_INST || n < 4 || nq != n + 1 || max_iter < 0)
+    return hipErrorInvalidValue;
+  PArgs a{n_inst, n, nq, ldk, inst, K, sw, t, s, x, xw, out, tol, max_iter, mode, tag0, err};
+  const size_t lds = persistent_lds_bytes(n_inst, n, ldk);
+  hipError_t e = hipFuncSetAttribute((const void*)k_persistent,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(persistent_blocks(n)),
+                                    dim3(PBLOCK), args, lds, st);
 }
 
 }  // namespace qdse

@@ -303,6 +303,7 @@ def test_graph_replay_equals_eager(Q):
     params = [(0.55, 0.678, 0.005), (0.55, 0.678, 0.0), (0.55, 0.678, 0.1)]
     S = Q.Solver(n, 32, params)
     outs = []
+    os.environ["QDSE_PERSISTENT"] = "0"
     try:
         for flag in (None, "1", None, None):
             if flag:
@@ -315,36 +316,44 @@ def test_graph_replay_equals_eager(Q):
             outs.append((x.cpu().numpy(), it.copy()))
     finally:
         os.environ.pop("QDSE_NO_GRAPH", None)
+        os.environ.pop("QDSE_PERSISTENT", None)
     for xo, it in outs[1:]:
         assert np.array_equal(xo, outs[0][0]) and np.array_equal(it, outs[0][1])
 
 
-@pytest.mark.parametrize("n,na,order", [(512, 128, 3), (64, 32, 3), (150, 100, 1), (37, 9, 3)])
-def test_persistent_solve_matches_graph_driver(Q, n, na, order):
-    """The single-launch cooperative solve (opt-in) and the kernel-per-sweep
-    driver stop at the same sweep with the same iterate (summation order
-    differs, so agreement is to rounding)."""
-    print(f"case persistent n={n} na={na}", flush=True)
-    params = [(0.55, 0.678, 0.0), (0.55, 0.678, 0.005)]
+def _solve_with_driver(S, flag, tol, max_iter, x0=None):
+    """One solve with QDSE_PERSISTENT = flag ("1": the single-launch solve is
+    required, "0": the kernel-per-sweep driver)."""
+    os.environ["QDSE_PERSISTENT"] = flag
+    try:
+        x = S.initial(1.0, 1.0) if x0 is None else x0.clone()
+        rc, it, rs = S.solve(x, tol=tol, max_iter=max_iter)
+    finally:
+        os.environ.pop("QDSE_PERSISTENT", None)
+    return rc, x.cpu().numpy(), it.copy(), rs.copy()
+
+
+@pytest.mark.parametrize("n,na,order,masses", [(512, 128, 3, (0.0, 0.005)), (64, 32, 3, (0.0, 0.005)),
+                                                (150, 100, 1, (0.0, 0.005)), (37, 9, 3, (0.0, 0.005)),
+                                                (512, 128, 3, (0.005,)),
+                                                (128, 32, 3, (0.0, 0.005, 0.05))])
+def test_single_launch_solve_matches_graph_driver(Q, n, na, order, masses):
+    """The single-launch cooperative solve (the default for up to a few FP64
+    instances) and the kernel-per-sweep driver compute every row, test
+    statistic and decision with the same arithmetic in the same order: the
+    same sweep counts, statistics and iterates, bit for bit; and the result
+    is the oracle's successive approximation."""
+    print(f"case single-launch n={n} na={na} order={order} masses={masses}", flush=True)
+    params = [(0.55, 0.678, m) for m in masses]
     S = Q.Solver(n, na, params, interp_order=order)
-    res = []
-    for flag in ("1", None):
-        if flag:
-            os.environ["QDSE_PERSISTENT"] = flag
-        else:
-            os.environ.pop("QDSE_PERSISTENT", None)
-        try:
-            x = S.initial(1.0, 1.0)
-            rc, it, rs = S.solve(x, tol=1e-10, max_iter=400)
-        finally:
-            os.environ.pop("QDSE_PERSISTENT", None)
-        assert rc == Q.QDSE_OK, (flag, rc, it, rs)
-        res.append((x.cpu().numpy(), it.copy(), rs.copy()))
-    (xp, ip, rp), (xg, ig, rg) = res
-    assert np.all(np.abs(ip - ig) <= 1), (ip, ig)
-    if np.array_equal(ip, ig):
-        for k in range(len(params)):
-            assert max(errs(xp[k], xg[k], n)) < 1e-13
+    rcp, xp, ip, rp = _solve_with_driver(S, "1", 1e-10, 400)
+    rcg, xg, ig, rg = _solve_with_driver(S, "0", 1e-10, 400)
+    assert rcp == rcg == Q.QDSE_OK, (rcp, rcg, ip, ig)
+    assert np.array_equal(ip, ig) and np.array_equal(rp, rg), (ip, ig, rp, rg)
+    assert np.array_equal(xp, xg)
+    # a second solve on the same context (fresh exchange tags) gives the same bits
+    rc2, x2, i2, r2 = _solve_with_driver(S, "1", 1e-10, 400)
+    assert rc2 == Q.QDSE_OK and np.array_equal(x2, xp) and np.array_equal(i2, ip)
     g = oracle_grid(n, na, order)
     if n <= 150:
         for k, (D, om, m) in enumerate(params):
@@ -352,6 +361,34 @@ def test_persistent_solve_matches_graph_driver(Q, n, na, order):
             assert abs(int(ip[k]) - itr) <= 1
             if ip[k] == itr:
                 assert max(errs(xp[k], xr, n)) < RTOL
+
+
+def test_single_launch_solve_stops_at_the_sweep_cap(Q):
+    """A cap below the sweeps needed: QDSE_NOT_CONVERGED with the cap as the
+    sweep count and the last statistic, as the kernel-per-sweep driver
+    reports, and the same iterate."""
+    print("case single-launch sweep cap", flush=True)
+    S = Q.Solver(64, 32, [(0.55, 0.678, 0.0), (0.55, 0.678, 0.005)], interp_order=3)
+    rcp, xp, ip, rp = _solve_with_driver(S, "1", 1e-10, 7)
+    rcg, xg, ig, rg = _solve_with_driver(S, "0", 1e-10, 7)
+    assert rcp == rcg == Q.QDSE_NOT_CONVERGED
+    assert list(ip) == [7, 7] and np.array_equal(ip, ig)
+    assert np.array_equal(rp, rg) and np.all(rp > 1e-10)
+    assert np.array_equal(xp, xg)
+
+
+def test_single_launch_solve_is_refused_where_it_does_not_apply(Q):
+    """QDSE_PERSISTENT=1 makes the single-launch solve a requirement: a
+    five-instance context (above its instance limit) is refused with
+    QDSE_ENOTSUP instead of silently taking the other driver."""
+    print("case single-launch refused", flush=True)
+    S = Q.Solver(64, 32, [(0.55, 0.678, 0.001 * k) for k in range(5)], interp_order=3)
+    os.environ["QDSE_PERSISTENT"] = "1"
+    try:
+        with pytest.raises(Q.QdseError):
+            S.solve(S.initial(1.0, 1.0), tol=1e-10, max_iter=50)
+    finally:
+        os.environ.pop("QDSE_PERSISTENT", None)
 
 
 def test_full_size_sampled_rows(Q):
