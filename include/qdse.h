@@ -228,7 +228,15 @@ int qdse_iterate_fp64_matrix(qdse_ctx* ctx, const double* d_x_in, double* d_x_ou
  * each about one sweep of work); resid[n_inst] (host, may be NULL): the last
  * test statistic. Returns the most severe per-instance outcome: QDSE_OK,
  * QDSE_NOT_CONVERGED (max_iter reached), QDSE_ESPURIOUS, QDSE_EDIVERGED or
- * QDSE_ENAN (qdse_solve_status lists them). Synchronises the stream. */
+ * QDSE_ENAN (qdse_solve_status lists them). Synchronises the stream.
+ * Drivers of QDSE_PICARD: with FP64 precision, one kernel block, up to four
+ * instances and the iterates, node functions and stencils of all instances
+ * within one workgroup's LDS (N = 512: up to three instances), the whole
+ * solve runs as one cooperative launch (same arithmetic, same results bit
+ * for bit as the kernel-per-sweep driver, which serves every other case);
+ * the environment variable QDSE_PERSISTENT=0 selects the kernel-per-sweep
+ * driver, QDSE_PERSISTENT=1 makes the single launch a requirement
+ * (QDSE_ENOTSUP where it does not apply). */
 int qdse_solve(qdse_ctx* ctx, double* d_x, double tol, int max_iter, int conv_mode,
                int* iters, double* resid);
 
@@ -265,6 +273,12 @@ int qdse_solve_group(qdse_ctx** ctxs, int n_ctx, double** d_x, double tol, int m
  * QDSE_ESPURIOUS, QDSE_EDIVERGED or QDSE_ENAN. Synchronises the stream. */
 int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double lin_tol,
                 int* steps, double* resid);
+
+/* Duration in microseconds of the single-launch kernel of the last
+ * qdse_solve on this context (HIP events recorded on the context's stream
+ * around the launch, so the launch's own latency is included); QDSE_ENOTSUP
+ * if the last solve used another driver. us must not be NULL. */
+int qdse_solve_kernel_us(const qdse_ctx* ctx, double* us);
 
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may
  * be NULL): FP32 matrix-core sweeps (QDSE_FP32_REFINE contexts) and FP64

@@ -91,6 +91,7 @@ def load():
                                    ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(_ip), ctypes.POINTER(_dp)]
     L.qdse_solve_stats.argtypes = [_vp, _ip, _ip]
+    L.qdse_solve_kernel_us.argtypes = [_vp, _dp]
     L.qdse_solve_status.argtypes = [_vp, _ip]
     L.qdse_newton.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]
     L.qdse_jvp.argtypes = [_vp, _vp, _vp, _vp]
@@ -260,6 +261,16 @@ class Solver:
                                int(conv_mode), it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
         _check(rc, "qdse_solve", allow=_OUTCOMES)
         return rc, it, rs
+
+    def solve_kernel_us(self):
+        """Duration (us) of the last solve's single-launch kernel, or None if
+        the last solve used the kernel-per-sweep driver."""
+        v = ctypes.c_double(0.0)
+        rc = load().qdse_solve_kernel_us(self._h, ctypes.byref(v))
+        if rc == QDSE_ENOTSUP:
+            return None
+        _check(rc, "qdse_solve_kernel_us")
+        return v.value
 
     def solve_status(self):
         """Per-instance outcome codes of the last solve."""

@@ -178,6 +178,8 @@ struct qdse_ctx {
   PersistOut* d_pout = nullptr;
   unsigned persist_tag = 1;
   bool persist_ok = false;
+  hipEvent_t pev[2] = {nullptr, nullptr};  // around the launch
+  double last_kernel_us = -1.0;            // of the last solve's single launch
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
   double* d_jdiag = nullptr;  // [n_inst][n][4] for qdse_jacobian_band
@@ -439,7 +441,8 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
               hipSuccess &&
           hipHostGetDevicePointer((void**)&c->d_pout, c->h_pout, 0) == hipSuccess) {
         c->h_pout->tag = 0;
-        c->persist_ok = true;
+        c->persist_ok = hipEventCreate(&c->pev[0]) == hipSuccess &&
+                        hipEventCreate(&c->pev[1]) == hipSuccess;
       }
     }
     (void)hipGetLastError();
@@ -476,6 +479,8 @@ void qdse_destroy(qdse_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   if (c->h_state) (void)hipHostFree(c->h_state);
   if (c->h_pout) (void)hipHostFree(c->h_pout);
+  for (hipEvent_t e : c->pev)
+    if (e) (void)hipEventDestroy(e);
   void* ptrs[] = {c->d_s,       c->d_t,       c->d_W,       c->d_z,     c->d_wz,
                   c->d_sw,      c->d_lo,      c->d_K,       c->d_dK,    c->d_M32,
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
@@ -900,10 +905,15 @@ static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, 
   }
   const unsigned tag0 = c->persist_tag;
   c->persist_tag += (unsigned)span;
+  HIPCHK(hipEventRecord(c->pev[0], st));
   HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_sw, c->d_t,
                            c->d_s, d_x, c->d_xw, c->d_pout, tol, max_iter, conv_mode, tag0,
                            c->d_perr));
+  HIPCHK(hipEventRecord(c->pev[1], st));
   HIPCHK(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, c->pev[0], c->pev[1]));
+  c->last_kernel_us = 1e3 * ms;
   const PersistOut& o = *c->h_pout;
   if (o.tag != tag0) {
     unsigned err = 0;
@@ -1111,6 +1121,7 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
     int rc = save_start(c, d_x);
     if (rc) return rc;
   }
+  c->last_kernel_us = -1.0;
   if (persistent_usable(c, max_iter))
     return solve_persistent(c, d_x, tol, max_iter, conv_mode, iters, resid);
   if (const char* e = std::getenv("QDSE_PERSISTENT"); e && e[0] == '1') {
@@ -1126,6 +1137,13 @@ int qdse_solve(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode
   if (c->solver == QDSE_AUTO && (rc == QDSE_OK || severity(rc) <= severity(QDSE_ENAN)))
     rc = auto_fallback(c, d_x, tol, max_iter, conv_mode, iters, resid);
   return rc;
+}
+
+int qdse_solve_kernel_us(const qdse_ctx* c, double* us) {
+  if (!c || !us) return QDSE_EINVAL;
+  if (c->last_kernel_us < 0.0) return QDSE_ENOTSUP;
+  *us = c->last_kernel_us;
+  return QDSE_OK;
 }
 
 int qdse_solve_status(const qdse_ctx* c, int* status) {

@@ -96,6 +96,7 @@ def test_entry_points_reject_null_context(L):
     assert L.qdse_vjp(None, None, None, None) == -1
     assert L.qdse_vjp_noalloc(None, None, None, None) == -1
     assert L.qdse_solve_status(None, None) == -1
+    assert L.qdse_solve_kernel_us(None, None) == -1
     assert L.qdse_jacobian_band(None, None, 2, None) == -1
     assert L.qdse_measure_launch_floor(None, 0, 1024, None, None) == -1
     assert L.qdse_measure_launch_floor(None, 4, -1, None, None) == -1
