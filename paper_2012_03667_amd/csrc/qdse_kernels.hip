@@ -494,13 +494,7 @@ __global__ void __launch_bounds__(256) k_sweep_row(
   const size_t mat = (size_t)rows * ldk;
   const double* Ki = K + (size_t)P.kblock * kstride + (size_t)ic * ldk;
   double kT[ROW_PF], k3[ROW_PF], k0[ROW_PF];
-#pragma unroll
-  for (int u = 0; u < ROW_PF; ++u) {
-    const int j = min(lane + u * WAVE, nq - 1);
-    kT[u] = Ki[j];
-    k3[u] = Ki[mat + j];
-    k0[u] = Ki[2 * mat + j];
-  }
+  load_row_regs<ROW_PF>(lane, nq, mat, Ki, kT, k3, k0);
   double s, Ai, Bi;
   if (QC && ic == n) {  // the renormalisation point
     s = zp.s;

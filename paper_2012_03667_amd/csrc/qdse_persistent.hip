@@ -122,6 +122,13 @@ __device__ inline double test_stat_m(int mode, double An, double Bn, double Ao, 
   return fmax(dA, fabs(Mn - Mo) / fmax(fabs(Mn), kMassFloor));
 }
 
+// Doubles per instance of the node-function block: five columns of ldk, and
+// room for the unclamped reads of row_regs (up to 4 ldk + 64 ROW_REG).
+__host__ __device__ inline size_t node_block(int ldk) {
+  const size_t need = (size_t)4 * ldk + (size_t)ROW_REG * WAVE;
+  return need > (size_t)5 * ldk ? need : (size_t)5 * ldk;
+}
+
 __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   extern __shared__ double lds[];
   const int n = a.n, nq = a.nq, ldk = a.ldk, nI = a.n_inst;
@@ -130,7 +137,9 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   const bool row_ok = i < n;
   const int ic = row_ok ? i : n - 1;  // rows past the last compute and publish nothing
   const int xl = 2 * n;
-  const size_t ndl = (size_t)5 * ldk;
+  // node functions of one instance: five columns, then zeros up to the last
+  // index the register-held strides read (row_regs without clamping)
+  const size_t ndl = node_block(ldk);
   double* xs = lds;                          // [2][nI][2n]: x_k of instance q at parity k & 1
   double* ms = xs + (size_t)2 * nI * xl;     // [2][nI][n]: M = B/A of the same iterates
   double* nd = ms + (size_t)2 * nI * n;      // [nI][5][ldk] node functions
@@ -145,17 +154,14 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   const size_t mat = (size_t)n * ldk;
   const double* Ki = a.K + (size_t)ic * ldk;
   double kT[ROW_REG], k3[ROW_REG], k0[ROW_REG];
-#pragma unroll
-  for (int u = 0; u < ROW_REG; ++u) {
-    const int j = min(lane + u * WAVE, nq - 1);
-    kT[u] = Ki[j];
-    k3[u] = Ki[mat + j];
-    k0[u] = Ki[2 * mat + j];
-  }
+  load_row_regs<ROW_REG>(lane, nq, mat, Ki, kT, k3, k0);
   const double s = a.s[ic];
   for (int e = tid; e < 4 * nq; e += PBLOCK) wsl[e] = a.sw[e];
   for (int e = tid; e < nq; e += PBLOCK) tl[e] = a.t[e];
   for (int e = tid; e < nI * xl; e += PBLOCK) xs[e] = a.x[e];  // x_0 at parity 0
+  // node blocks zeroed: the padding between and after the columns is read by
+  // the unclamped strides of row_regs (with zero kernel entries)
+  for (size_t e = tid; e < (size_t)nI * ndl; e += PBLOCK) nd[e] = 0.0;
   if (tid < nI) {
     s_pref[tid] = a.inst[tid].pref;
     s_m[tid] = a.inst[tid].m;
@@ -203,6 +209,12 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   // still runs, contracts and publishes the next iterate.
   unsigned pend = 0;  // instances with a published sweep not yet gathered
   int q = 0;
+  // The next turn's instance pf_q: its words are loaded during this turn's
+  // contraction and taken into LDS before this turn publishes (so that the
+  // wait for them does not queue behind this turn's stores); pf_pend marks
+  // this thread's values that did not yet carry the tag.
+  int pf_q = -1;
+  unsigned pf_pend = 0;
   // one round of loads of the tagged words of the values still pending
   auto load_round = [&](const unsigned long long* wk, int v0, unsigned long long(&lo)[GATHER_PT],
                         unsigned long long(&hi)[GATHER_PT], unsigned mask) {
@@ -215,9 +227,31 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       }
     }
   };
+  // the next running instance with a sweep in flight: its first gather round
+  // goes out during this turn
+  int y = -1, ky = 0;
+  unsigned long long pf_lo[GATHER_PT], pf_hi[GATHER_PT];
+  unsigned pf_mask = 0;
+  auto issue_prefetch = [&]() {
+    y = -1;
+    pf_mask = 0;
+#pragma unroll
+    for (int d = 1; d < PMAX_INST; ++d) {
+      const int c = (q + d) % PMAX_INST;
+      if (y < 0 && ((run >> c) & 1u) && ((pend >> c) & 1u)) y = c;
+    }
+    if (y >= 0) {
+      ky = __builtin_amdgcn_readlane(done_v, y);
+#pragma unroll
+      for (int g = 0; g < GATHER_PT; ++g)
+        if (g * PBLOCK + tid < xl) pf_mask |= 1u << g;
+      load_round(a.xw + ((size_t)((ky + 1) & 1) * nI + y) * xl * 2, 0, pf_lo, pf_hi, pf_mask);
+    }
+  };
   while (run) {
     while (!((run >> q) & 1u)) q = (q + 1) % PMAX_INST;
     int k = __builtin_amdgcn_readlane(done_v, q);  // sweeps of q held before this turn
+    bool issued = false;
     if ((pend >> q) & 1u) {
       // gather x_{k+1} of q
       const unsigned tag = a.tag0 + (unsigned)(k + 1);
@@ -231,6 +265,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
 #pragma unroll
         for (int g = 0; g < GATHER_PT; ++g)
           if (v0 + g * PBLOCK + tid < xl) pending |= 1u << g;
+        if (v0 == 0 && pf_q == q) pending &= pf_pend;  // the rest is in LDS already
         while (pending) {
           load_round(wk, v0, lo, hi, pending);
 #pragma unroll
@@ -258,6 +293,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
         }
       }
       if (!good) ok = 0;
+      pf_q = -1;
       __syncthreads();
       if (!ok) break;
       k += 1;
@@ -282,6 +318,8 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       m = wave_max_bits(m);
       if (lane == 0) atomicMax(&st_max[q][k & 1], m);
       __syncthreads();
+      issue_prefetch();
+      issued = true;
       // decision (every thread alike)
       const double st = from_bits(st_max[q][k & 1]);
       int sq = 0;
@@ -303,6 +341,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
         continue;
       }
     }
+    if (!issued) issue_prefetch();
     // contraction of this wavefront's row of q from x_k: x_{k+1}, published
     // tagged (lanes 0-3: the halves of A_i and B_i)
     {
@@ -310,12 +349,27 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       const double* ndq = nd + (size_t)q * ndl;
       const double Ai = xq[ic], Bi = xq[n + ic];
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      row_regs<ROW_REG>(lane, nq, ldk, ndq, kT, k3, k0, s, Ai, Bi, a0, a1, a2, a3);
+      row_regs<ROW_REG, false>(lane, nq, ldk, ndq, kT, k3, k0, s, Ai, Bi, a0, a1, a2, a3);
       if (nq > ROW_REG * WAVE)
         row_stream_f64(lane + ROW_REG * WAVE, nq, ldk, mat, Ki, ndq, s, Ai, Bi, a0, a1, a2, a3);
       wave_sum4(a0, a1, a2, a3);
       const double An = 1.0 + s_pref[q] * (a1 - a0);
       const double Bn = s_m[q] + s_pref[q] * fma(2.0 * s, a2, a3);
+      if (y >= 0) {  // take the next instance's words that have arrived
+        const unsigned tag = a.tag0 + (unsigned)(ky + 1);
+        double* xy = xs + ((size_t)((ky + 1) & 1) * nI + y) * xl;
+        pf_pend = pf_mask;
+#pragma unroll
+        for (int g = 0; g < GATHER_PT; ++g) {
+          if ((pf_mask & (1u << g)) && (unsigned)(pf_lo[g] >> 32) == tag &&
+              (unsigned)(pf_hi[g] >> 32) == tag) {
+            xy[g * PBLOCK + tid] =
+                from_bits(((pf_hi[g] & 0xffffffffull) << 32) | (pf_lo[g] & 0xffffffffull));
+            pf_pend &= ~(1u << g);
+          }
+        }
+        pf_q = y;
+      }
       if (row_ok && lane < 4) {
         const unsigned tag = a.tag0 + (unsigned)(k + 1);
         unsigned long long* wk = a.xw + ((size_t)((k + 1) & 1) * nI + q) * xl * 2;
@@ -371,7 +425,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
 
 size_t persistent_lds_bytes(int n_inst, int n, int ldk) {
   const size_t nq = (size_t)n + 1;
-  return ((size_t)2 * n_inst * 3 * n + (size_t)n_inst * 5 * ldk + 5 * nq) * sizeof(double);
+  return ((size_t)2 * n_inst * 3 * n + (size_t)n_inst * node_block(ldk) + 5 * nq) * sizeof(double);
 }
 
 size_t persistent_words(int n_inst, int n) { return (size_t)2 * n_inst * 2 * n * 2; }

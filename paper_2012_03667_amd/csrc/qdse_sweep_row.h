@@ -156,35 +156,24 @@ __device__ inline void row_term(double kT, double k3, double k0, double Aq, doub
   a3 = fma(k0, sS * sA, a3);
 }
 
-// row_term for a lane stride that may lie past the last loop node: the
-// caller reads that node at a clamped index, and the sums keep their values
-// when !valid (a select, not a branch, so that the reads of consecutive
-// strides can be issued together).
-__device__ inline void row_term_masked(bool valid, double kT, double k3, double k0, double Aq,
-                                       double Bq, double sV, double sS, double tsV, double s,
-                                       double Ai, double Bi, double& a0, double& a1, double& a2,
-                                       double& a3) {
-  double b0 = a0, b1 = a1, b2 = a2, b3 = a3;
-  row_term(kT, k3, k0, Aq, Bq, sV, sS, tsV, s, Ai, Bi, b0, b1, b2, b3);
-  a0 = valid ? b0 : a0;
-  a1 = valid ? b1 : a1;
-  a2 = valid ? b2 : a2;
-  a3 = valid ? b3 : a3;
-}
-
 // Lane sums over the lane strides u < U whose kernel entries the wavefront
 // holds in registers (loop node j = lane + 64 u): the five node values of
-// stride u + 1 are read before the arithmetic of stride u, at an index
-// clamped to the last loop node, and a stride past it leaves the sums as they
-// are. Accumulation order per lane: u = 0, 1, ...
-template <int U>
+// stride u + 1 are read before the arithmetic of stride u. A stride past the
+// last loop node carries zero kernel entries (load_row_regs), so its terms
+// add zero without a branch or a select; its node values are read at an
+// index clamped to the last loop node (CLAMP), or, where the caller's node
+// array holds finite values (its own nodes, or zeros) up to 4 ldk + 64 U,
+// at the stride's own index, which saves the per-stride address arithmetic.
+// (A loop node with a non-finite value makes the row's sum non-finite either
+// way.) Accumulation order per lane: u = 0, 1, ...
+template <int U, bool CLAMP = true>
 __device__ inline void row_regs(int lane, int nq, int ldk, const double* nd,
                                 const double (&kT)[U], const double (&k3)[U],
                                 const double (&k0)[U], double s, double Ai, double Bi,
                                 double& a0, double& a1, double& a2, double& a3) {
   double c[5], x[5];
   auto rd = [&](int u, double(&v)[5]) {
-    const int jc = min(lane + u * WAVE, nq - 1);
+    const int jc = CLAMP ? min(lane + u * WAVE, nq - 1) : lane + u * WAVE;
 #pragma unroll
     for (int f = 0; f < 5; ++f) v[f] = nd[f * ldk + jc];
   };
@@ -192,12 +181,26 @@ __device__ inline void row_regs(int lane, int nq, int ldk, const double* nd,
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (u + 1 < U) rd(u + 1, x);
-    row_term_masked(lane + u * WAVE < nq, kT[u], k3[u], k0[u], c[0], c[1], c[2], c[3], c[4], s,
-                    Ai, Bi, a0, a1, a2, a3);
+    row_term(kT[u], k3[u], k0[u], c[0], c[1], c[2], c[3], c[4], s, Ai, Bi, a0, a1, a2, a3);
     if (u + 1 < U) {
 #pragma unroll
       for (int f = 0; f < 5; ++f) c[f] = x[f];
     }
+  }
+}
+
+// The kernel entries of row Ki (three matrices `mat` apart) for the lane
+// strides u < U of row_regs, zero past the last loop node.
+template <int U>
+__device__ inline void load_row_regs(int lane, int nq, size_t mat, const double* Ki, double (&kT)[U],
+                                     double (&k3)[U], double (&k0)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = lane + u * WAVE, jc = min(j, nq - 1);
+    const double t = Ki[jc], t3 = Ki[mat + jc], t0 = Ki[2 * mat + jc];
+    kT[u] = j < nq ? t : 0.0;
+    k3[u] = j < nq ? t3 : 0.0;
+    k0[u] = j < nq ? t0 : 0.0;
   }
 }
 
