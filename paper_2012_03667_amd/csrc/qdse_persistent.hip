@@ -79,33 +79,25 @@ __device__ inline unsigned long long tagged(unsigned half, unsigned tag) {
   return ((unsigned long long)tag << 32) | half;
 }
 
-__device__ inline unsigned long long stat_bits(double r) {
-  return (unsigned long long)__double_as_longlong(
-      isnan(r) ? __longlong_as_double(0x7ff8000000000000ll) : r);
-}
-
-// Max over the 64 lanes of a wavefront of the bit patterns of non-negative
-// doubles (their integer order is the order of the values, NaN above inf):
-// the butterflies and row broadcasts of wave_sum with max for +, the result
-// read from lane 63. Lanes that a row broadcast leaves out receive 0, which
-// is neutral.
-__device__ inline unsigned long long umax(unsigned long long a, unsigned long long b) {
-  return a > b ? a : b;
-}
 __device__ inline unsigned long long bits_of(double v) {
   return (unsigned long long)__double_as_longlong(v);
 }
 __device__ inline double from_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
-__device__ inline unsigned long long wave_max_bits(unsigned long long v) {
-  v = umax(v, bits_of(dpp_move<0xB1, 0xF>(from_bits(v))));
-  v = umax(v, bits_of(dpp_move<0x4E, 0xF>(from_bits(v))));
-  v = umax(v, bits_of(dpp_move<0x141, 0xF>(from_bits(v))));
-  v = umax(v, bits_of(dpp_move<0x140, 0xF>(from_bits(v))));
-  v = umax(v, bits_of(dpp_move<0x142, 0xA>(from_bits(v))));
-  v = umax(v, bits_of(dpp_move<0x143, 0xC>(from_bits(v))));
-  const int lo = __builtin_amdgcn_readlane((int)v, 63);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
-  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+
+// Max over the 64 lanes of non-negative values, in every lane (v_max_f64
+// through the butterflies and row broadcasts of wave_sum; lanes a row
+// broadcast leaves out receive 0, which is neutral). NaN is the caller's.
+__device__ inline double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_move<0xB1, 0xF>(v));
+  v = fmax(v, dpp_move<0x4E, 0xF>(v));
+  v = fmax(v, dpp_move<0x141, 0xF>(v));
+  v = fmax(v, dpp_move<0x140, 0xF>(v));
+  v = fmax(v, dpp_move<0x142, 0xA>(v));
+  v = fmax(v, dpp_move<0x143, 0xC>(v));
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 // The test statistic of one row (test_stat) with M_old = Bo/Ao supplied (the
@@ -306,17 +298,24 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       const double* mo = ms + ((size_t)((k - 1) & 1) * nI + q) * n;
       double* mn = ms + ((size_t)(k & 1) * nI + q) * n;
       if (tid == 0) st_max[q][(k + 1) & 1] = 0ull;  // last read at sweep k - 1
-      unsigned long long m = 0ull;
+      // (the maximum by value with a separate NaN flag: the same result as
+      // the maximum of the statistics' bit patterns with NaN above inf)
+      double m = 0.0;
+      bool bad = false;
       for (int t = tid; t < nq; t += PBLOCK) {
         if (t < n) {
           double Mn;
-          m = umax(m, stat_bits(test_stat_m(a.mode, xq[t], xq[n + t], xo[t], xo[n + t], mo[t], Mn)));
+          const double r = test_stat_m(a.mode, xq[t], xq[n + t], xo[t], xo[n + t], mo[t], Mn);
+          bad = bad || !(r == r);
+          m = fmax(m, r);
           mn[t] = Mn;
         }
         node(q, k & 1, t);
       }
-      m = wave_max_bits(m);
-      if (lane == 0) atomicMax(&st_max[q][k & 1], m);
+      const bool wave_bad = __ballot(bad) != 0;
+      m = wave_max_nonneg(m);
+      if (lane == 0)
+        atomicMax(&st_max[q][k & 1], wave_bad ? 0x7ff8000000000000ull : bits_of(m));
       __syncthreads();
       issue_prefetch();
       issued = true;

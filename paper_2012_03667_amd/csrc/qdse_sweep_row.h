@@ -136,7 +136,8 @@ __device__ inline void node_core(const double w[4], const T xa[4], const T xb[4]
   }
   const T tt = make<T>(tj, 0.0);
   const T Dl = tt * Aq * Aq + Bq * Bq;
-  const T sV = Aq / Dl, sS = Bq / Dl;
+  const T rD = make<T>(1.0, 0.0) / Dl;  // one division for both
+  const T sV = Aq * rD, sS = Bq * rD;
   out[0] = Aq;
   out[1] = Bq;
   out[2] = sV;
