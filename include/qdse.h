@@ -232,7 +232,7 @@ int qdse_iterate_fp64_matrix(qdse_ctx* ctx, const double* d_x_in, double* d_x_ou
  * Drivers of QDSE_PICARD: with FP64 precision, one kernel block, up to four
  * instances and the iterates, node functions and stencils of all instances
  * within one workgroup's LDS (N = 512: up to three instances), the whole
- * solve runs as one cooperative launch (same arithmetic, same results bit
+ * solve runs as one launch (same arithmetic, same results bit
  * for bit as the kernel-per-sweep driver, which serves every other case);
  * the environment variable QDSE_PERSISTENT=0 selects the kernel-per-sweep
  * driver, QDSE_PERSISTENT=1 makes the single launch a requirement
@@ -275,9 +275,9 @@ int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double l
                 int* steps, double* resid);
 
 /* Duration in microseconds of the single-launch kernel of the last
- * qdse_solve on this context (HIP events recorded on the context's stream
- * around the launch, so the launch's own latency is included); QDSE_ENOTSUP
- * if the last solve used another driver. us must not be NULL. */
+ * qdse_solve on this context (HIP events carried on the launch's dispatch
+ * packet); QDSE_ENOTSUP if the last solve used another driver. us must not
+ * be NULL. */
 int qdse_solve_kernel_us(const qdse_ctx* ctx, double* us);
 
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may

@@ -178,7 +178,7 @@ struct qdse_ctx {
   PersistOut* d_pout = nullptr;
   unsigned persist_tag = 1;
   bool persist_ok = false;
-  hipEvent_t pev[2] = {nullptr, nullptr};  // around the launch
+  hipEvent_t pev[2] = {nullptr, nullptr};  // on the launch's dispatch packet
   double last_kernel_us = -1.0;            // of the last solve's single launch
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
@@ -877,7 +877,7 @@ static int finish_solve(qdse_ctx* c, double* d_x, const std::vector<char>& diver
   return finish_outcome(c, hs, cert, diverged, iters, resid);
 }
 
-// One cooperative launch runs the whole solve (qdse_persistent.hip), in
+// One launch runs the whole solve (qdse_persistent.hip), in
 // place on d_x. Its tags are persist_tag + 1 ... persist_tag + max_iter + 1;
 // persist_tag then moves past them. Before the 32-bit tags would wrap, the
 // exchange words and the error word are cleared and the count restarts.
@@ -905,11 +905,9 @@ static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, 
   }
   const unsigned tag0 = c->persist_tag;
   c->persist_tag += (unsigned)span;
-  HIPCHK(hipEventRecord(c->pev[0], st));
   HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_sw, c->d_t,
                            c->d_s, d_x, c->d_xw, c->d_pout, tol, max_iter, conv_mode, tag0,
-                           c->d_perr));
-  HIPCHK(hipEventRecord(c->pev[1], st));
+                           c->d_perr, c->pev[0], c->pev[1]));
   HIPCHK(hipStreamSynchronize(st));
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, c->pev[0], c->pev[1]));

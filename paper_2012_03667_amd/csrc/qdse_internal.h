@@ -269,7 +269,7 @@ struct PersistOut {
   int cert[4], diverged[4];
 };
 
-// Single-launch (cooperative) solve of up to persistent_max_inst() instances
+// Single-launch solve of up to persistent_max_inst() instances
 // sharing kernel block 0 (qdse_persistent.hip).
 size_t persistent_lds_bytes(int n_inst, int n, int ldk);
 size_t persistent_words(int n_inst, int n);
@@ -280,6 +280,7 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const InstDev* inst, const double* K, const double* sw,
                              const double* t, const double* s, double* x,
                              unsigned long long* xw, PersistOut* out, double tol, int max_iter,
-                             int mode, unsigned tag0, unsigned* err);
+                             int mode, unsigned tag0, unsigned* err, hipEvent_t ev0,
+                             hipEvent_t ev1);
 
 }  // namespace qdse

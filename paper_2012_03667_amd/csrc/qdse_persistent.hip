@@ -1,6 +1,6 @@
 // qdse_persistent.hip -- the whole successive-approximation solve of a few
-// instances in one cooperative launch (Sec. I eq. jifen12, stopped by the
-// per-point test of Sec. II eq. jifenab2 or its mass-function form).
+// instances in one launch (Sec. I eq. jifen12, stopped by the per-point test
+// of Sec. II eq. jifenab2 or its mass-function form).
 //
 // A few-instance sweep at N = 512 is ~7 MFLOP and ~6 MB of kernel matrices:
 // with one launch per sweep, launch latency costs more than the sweep's work.
@@ -37,6 +37,14 @@
 // tag0 into the error word and every workgroup leaves the loop at its next
 // poll, so the grid always drains (an older value in the error word belongs
 // to an earlier solve and is ignored).
+// Co-residency: the host launches only grids that fit the device at once
+// (persistent_fits: ceil(n / 8) workgroups against occupancy x compute
+// units). The launch is an ordinary one: work of
+// other streams can delay the dispatch of some workgroups but not prevent it,
+// since nothing it waits for depends on this kernel. (A cooperative launch
+// gives the same guarantee, but after one the HIP runtime ran the later
+// multi-stream work of the process markedly slower: 8.4 against 5.1 ms for a
+// batch of eight grid classes on their own streams.)
 #include "qdse_internal.h"
 #include "qdse_sweep_row.h"
 
@@ -433,7 +441,7 @@ int persistent_blocks(int n) { return (n + PROWS - 1) / PROWS; }
 
 int persistent_max_inst() { return PMAX_INST; }
 
-// Whether the cooperative solve of n_inst instances on an n-row grid fits:
+// Whether the single-launch solve of n_inst instances on an n-row grid fits:
 // LDS within the device's limit and ceil(n / 4) workgroups co-resident.
 hipError_t persistent_fits(int n_inst, int n, int ldk, bool* fits) {
   *fits = false;
@@ -456,7 +464,7 @@ hipError_t persistent_fits(int n_inst, int n, int ldk, bool* fits) {
   return hipSuccess;
 }
 
-// Launches the cooperative solve. The caller has checked persistent_fits,
+// Launches the solve. The caller has checked persistent_fits,
 // that every instance uses kernel block 0, that xw holds persistent_words
 // zero-initialised or older-tagged words, and that no tag in
 // (tag0, tag0 + max_iter + 1] was used before on xw or err.
@@ -464,7 +472,8 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const InstDev* inst, const double* K, const double* sw,
                              const double* t, const double* s, double* x,
                              unsigned long long* xw, PersistOut* out, double tol, int max_iter,
-                             int mode, unsigned tag0, unsigned* err) {
+                             int mode, unsigned tag0, unsigned* err, hipEvent_t ev0,
+                             hipEvent_t ev1) {
   if (n_inst < 1 || n_inst > PMAX_INST || n < 4 || nq != n + 1 || max_iter < 0)
     return hipErrorInvalidValue;
   PArgs a{n_inst, n, nq, ldk, inst, K, sw, t, s, x, xw, out, tol, max_iter, mode, tag0, err};
@@ -473,8 +482,9 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(persistent_blocks(n)),
-                                    dim3(PBLOCK), args, lds, st);
+  // events (may be null) carried on the dispatch packet: the kernel's own span
+  return hipExtLaunchKernel((const void*)k_persistent, dim3(persistent_blocks(n)), dim3(PBLOCK),
+                            args, lds, st, ev0, ev1, 0);
 }
 
 }  // namespace qdse
