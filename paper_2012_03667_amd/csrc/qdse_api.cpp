@@ -905,9 +905,13 @@ static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, 
   }
   const unsigned tag0 = c->persist_tag;
   c->persist_tag += (unsigned)span;
+  // QDSE_PERSIST_SPIN: failed polls per gather round before the solve is
+  // abandoned (tests force the error path with 0; default about a second)
+  long spin_limit = -1;
+  if (const char* e = std::getenv("QDSE_PERSIST_SPIN")) spin_limit = std::atol(e);
   HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_sw, c->d_t,
                            c->d_s, d_x, c->d_xw, c->d_pout, tol, max_iter, conv_mode, tag0,
-                           c->d_perr, c->pev[0], c->pev[1]));
+                           c->d_perr, c->pev[0], c->pev[1], spin_limit));
   HIPCHK(hipStreamSynchronize(st));
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, c->pev[0], c->pev[1]));

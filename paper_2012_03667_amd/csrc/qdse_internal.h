@@ -281,6 +281,6 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const double* t, const double* s, double* x,
                              unsigned long long* xw, PersistOut* out, double tol, int max_iter,
                              int mode, unsigned tag0, unsigned* err, hipEvent_t ev0,
-                             hipEvent_t ev1);
+                             hipEvent_t ev1, long spin_limit);  // < 0: the default
 
 }  // namespace qdse

@@ -59,7 +59,7 @@ constexpr int PROWS = PBLOCK / WAVE;
 constexpr int PMAX_INST = 4;                // instances of one solve
 constexpr int ROW_REG = 9;                  // lane strides of the row held in registers
 constexpr int GATHER_PT = 2;                // values per thread per gather round
-constexpr long SPIN_LIMIT = 1l << 20;       // polls (each ~1-2 us) before giving up
+constexpr long SPIN_LIMIT = 1l << 20;       // default: polls (each ~1-2 us) before giving up
 constexpr int ERR_CHECK_EVERY = 16;         // polls between reads of the error word
 // Divergence of successive approximation: from sweep DIVERGE_AFTER on, a
 // statistic above DIVERGE_FACTOR times the smallest one seen so far marks
@@ -81,6 +81,7 @@ struct PArgs {
   int max_iter, mode;
   unsigned tag0;
   unsigned* err;
+  long spin_limit;  // failed polls of one gather round before the solve is abandoned
 };
 
 __device__ inline unsigned long long tagged(unsigned half, unsigned tag) {
@@ -284,7 +285,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
             good = false;
             break;
           }
-          if (spins > SPIN_LIMIT) {
+          if (spins > a.spin_limit) {
             __hip_atomic_store(a.err, a.tag0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             good = false;
             break;
@@ -473,10 +474,11 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const double* t, const double* s, double* x,
                              unsigned long long* xw, PersistOut* out, double tol, int max_iter,
                              int mode, unsigned tag0, unsigned* err, hipEvent_t ev0,
-                             hipEvent_t ev1) {
+                             hipEvent_t ev1, long spin_limit) {
   if (n_inst < 1 || n_inst > PMAX_INST || n < 4 || nq != n + 1 || max_iter < 0)
     return hipErrorInvalidValue;
-  PArgs a{n_inst, n, nq, ldk, inst, K, sw, t, s, x, xw, out, tol, max_iter, mode, tag0, err};
+  PArgs a{n_inst, n, nq, ldk, inst, K, sw, t, s, x, xw, out, tol, max_iter, mode, tag0, err,
+          spin_limit < 0 ? SPIN_LIMIT : spin_limit};
   const size_t lds = persistent_lds_bytes(n_inst, n, ldk);
   hipError_t e = hipFuncSetAttribute((const void*)k_persistent,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -172,21 +172,18 @@ __device__ inline void row_regs(int lane, int nq, int ldk, const double* nd,
                                 const double (&kT)[U], const double (&k3)[U],
                                 const double (&k0)[U], double s, double Ai, double Bi,
                                 double& a0, double& a1, double& a2, double& a3) {
-  double c[5], x[5];
+  double c[2][5];  // strides alternate between the two sets (no copies once unrolled)
   auto rd = [&](int u, double(&v)[5]) {
     const int jc = CLAMP ? min(lane + u * WAVE, nq - 1) : lane + u * WAVE;
 #pragma unroll
     for (int f = 0; f < 5; ++f) v[f] = nd[f * ldk + jc];
   };
-  rd(0, c);
+  rd(0, c[0]);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    if (u + 1 < U) rd(u + 1, x);
-    row_term(kT[u], k3[u], k0[u], c[0], c[1], c[2], c[3], c[4], s, Ai, Bi, a0, a1, a2, a3);
-    if (u + 1 < U) {
-#pragma unroll
-      for (int f = 0; f < 5; ++f) c[f] = x[f];
-    }
+    if (u + 1 < U) rd(u + 1, c[(u + 1) & 1]);
+    const double(&v)[5] = c[u & 1];
+    row_term(kT[u], k3[u], k0[u], v[0], v[1], v[2], v[3], v[4], s, Ai, Bi, a0, a1, a2, a3);
   }
 }
 

@@ -377,6 +377,27 @@ def test_single_launch_solve_stops_at_the_sweep_cap(Q):
     assert np.array_equal(xp, xg)
 
 
+def test_single_launch_solve_abandons_a_wait_that_runs_out(Q):
+    """Failure path forced from the host: with no failed poll allowed
+    (QDSE_PERSIST_SPIN=0) the one-instance solve's first gather, issued right
+    after its own publication, runs out; every workgroup leaves its loop, the
+    launch ends and the solve reports QDSE_EDEVICE. The context then solves
+    normally (the next solve's tags and error word are fresh)."""
+    print("case single-launch forced wait failure", flush=True)
+    S = Q.Solver(64, 32, [(0.55, 0.678, 0.005)], interp_order=3)
+    rc0, x0, i0, r0 = _solve_with_driver(S, "0", 1e-10, 400)
+    os.environ["QDSE_PERSIST_SPIN"] = "0"
+    try:
+        with pytest.raises(Q.QdseError) as ei:
+            _solve_with_driver(S, "1", 1e-10, 400)
+        assert ei.value.code == -3  # QDSE_EDEVICE
+    finally:
+        os.environ.pop("QDSE_PERSIST_SPIN", None)
+    rc1, x1, i1, r1 = _solve_with_driver(S, "1", 1e-10, 400)
+    assert rc0 == rc1 == Q.QDSE_OK
+    assert np.array_equal(x1, x0) and np.array_equal(i1, i0)
+
+
 def test_single_launch_solve_is_refused_where_it_does_not_apply(Q):
     """QDSE_PERSISTENT=1 makes the single-launch solve a requirement: a
     five-instance context (above its instance limit) is refused with
