@@ -231,7 +231,10 @@ __global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
       const double base = qx * qx + v * v;
       const double g = wzs[t] * exp(-base * I.inv_om2);
       const double gp = g * ep, gm = g * em;
-      const double yp = 1.0 / (base + k4p2), ym = 1.0 / (base + k4m2);
+      // 1/k^2 for both signs of q4 from one division
+      const double dp = base + k4p2, dm = base + k4m2;
+      const double rpm = 1.0 / (dp * dm);
+      const double yp = dm * rpm, ym = dp * rpm;
       const double gpv = gp * v, gmv = gm * v;
       Sp[0] += gp;
       Sp[1] += gpv;
