@@ -236,7 +236,11 @@ int qdse_iterate_fp64_matrix(qdse_ctx* ctx, const double* d_x_in, double* d_x_ou
  * for bit as the kernel-per-sweep driver, which serves every other case);
  * the environment variable QDSE_PERSISTENT=0 selects the kernel-per-sweep
  * driver, QDSE_PERSISTENT=1 makes the single launch a requirement
- * (QDSE_ENOTSUP where it does not apply). */
+ * (QDSE_ENOTSUP where it does not apply). The single launch's waits for the
+ * other workgroups are bounded (about a second of polling; QDSE_PERSIST_SPIN
+ * sets the number of failed polls, 0 forces the error path in tests): a wait
+ * that runs out ends every workgroup and the solve returns QDSE_EDEVICE with
+ * d_x unchanged. */
 int qdse_solve(qdse_ctx* ctx, double* d_x, double tol, int max_iter, int conv_mode,
                int* iters, double* resid);
 
