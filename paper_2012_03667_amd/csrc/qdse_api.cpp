@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -890,6 +891,19 @@ static bool persistent_usable(const qdse_ctx* c, int max_iter) {
   return !(e && e[0] == '0');
 }
 
+// Waits for the stream's work by polling its state for up to 50 ms, then
+// blocks: a solve of a few hundred microseconds then returns when its kernel
+// ends instead of after a blocked thread's wake-up.
+static hipError_t wait_polling(hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t q = hipStreamQuery(st);
+    if (q != hipErrorNotReady) return q;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) break;
+  }
+  return hipStreamSynchronize(st);
+}
+
 static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, int conv_mode,
                             int* iters, double* resid) {
   const HostGrid& g = c->hg;
@@ -912,7 +926,7 @@ static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, 
   HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_sw, c->d_t,
                            c->d_s, d_x, c->d_xw, c->d_pout, tol, max_iter, conv_mode, tag0,
                            c->d_perr, c->pev[0], c->pev[1], spin_limit));
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(wait_polling(st));
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, c->pev[0], c->pev[1]));
   c->last_kernel_us = 1e3 * ms;
