@@ -619,8 +619,8 @@ def main():
                         "cubic interpolation, m in {0, 5 MeV}, paper interaction D=0.55 GeV^2, "
                         "omega=0.678 GeV, A0=B0=1, tol 1e-10 on max|dM/M| and max|dA|",
             "n_radial": n, "n_angle": na, "instances_per_step": len(masses),
-            "solver": "plain FP64 successive approximation, the whole solve in one cooperative "
-                      "launch (one row per wavefront, the two instances taking turns)",
+            "solver": "plain FP64 successive approximation, the whole solve in one kernel launch "
+                      "(one row per wavefront, the two instances taking turns)",
             "sweeps_per_solve": [int(v) for v in iters],
             "branch_certified": certified,
             "note": "the configurations' interaction (kappa=0.8, omega=0.5) lies beyond the end of "

@@ -338,7 +338,7 @@ def _solve_with_driver(S, flag, tol, max_iter, x0=None):
                                                 (512, 128, 3, (0.005,)),
                                                 (128, 32, 3, (0.0, 0.005, 0.05))])
 def test_single_launch_solve_matches_graph_driver(Q, n, na, order, masses):
-    """The single-launch cooperative solve (the default for up to a few FP64
+    """The single-launch solve (the default for up to a few FP64
     instances) and the kernel-per-sweep driver compute every row, test
     statistic and decision with the same arithmetic in the same order: the
     same sweep counts, statistics and iterates, bit for bit; and the result
