@@ -27,7 +27,8 @@
 // measure d^4q/(2pi)^4 = dq4 |q|^2 d|q| dz / (8 pi^3), weights precomputed.
 // A, B, C at loop points by a tensor-product 4x4 stencil with brackets known
 // from the interleaving. No angular kernel is precomputed: one wavefront per
-// external point, lanes over loop points, angles in registers (FP64 VALU).
+// external point, lanes over loop points, the angle factors of one |p_vec|
+// tabulated in LDS (FP64 VALU).
 #include "qdse_internal.h"
 
 namespace qdse {
@@ -184,99 +185,145 @@ __device__ inline void mu_projections(const MuPoint& P, const double S[3], const
   IC = (iD * inv(pt4 * pt4)) * (S[0] * c00 + S[1] * c01 + T[0] * c10 + T[1] * c11);
 }
 
-__global__ void __launch_bounds__(256) k_mu_sweep(MuArgs a) {
+// A workgroup serves MU_WPB external points of one instance that share |p_vec|
+// (one wavefront each, lanes over loop points). The angular weight with the
+// interaction's angle-dependent factor, g_t = w_t exp(-(q_perp^2 + v_t^2)/omega^2),
+// together with v_t and k_vec^2 = q_perp^2 + v_t^2, depends on |p_vec|, |q_vec|
+// and the angle only: it is tabulated in LDS once per |q_vec| (a block of
+// loop radii at a time) with its moments S_n = sum_t g_t v_t^n, and the q4
+// dependence enters through the factor exp(-k4^2/omega^2) of S and T and
+// through 1/k^2 = 1/(k_vec^2 + k4^2) in T.
+constexpr int MU_WPB = 4;
+constexpr int MU_TAB = 4608;  // table entries (loop radius x angle) per block of radii
+constexpr int MU_TC = 256;    // loop radii per block at most
+
+__global__ void __launch_bounds__(64 * MU_WPB) k_mu_sweep(MuArgs a) {
   __shared__ double zs[256], sns[256], wzs[256];
-  const int lane = threadIdx.x & (MU_WAVE - 1);
-  for (int t = threadIdx.x; t < a.na && t < 256; t += blockDim.x) {
+  __shared__ double tg[MU_TAB], tv[MU_TAB], tb[MU_TAB];  // g_t, v_t, k_vec^2 per (radius, angle)
+  __shared__ double tS[3][MU_TC];                        // S_0, S_1, S_2 per radius
+  const int tid = threadIdx.x, lane = tid & (MU_WAVE - 1), wave = tid / MU_WAVE;
+  const int na = a.na, ne = a.ns * a.n4, nl = a.nqs * a.nq4;
+  const int chunks = (a.n4 + MU_WPB - 1) / MU_WPB;
+  const int inst = blockIdx.x / (a.ns * chunks);
+  const int ia = (blockIdx.x / chunks) % a.ns;
+  const int ib = (blockIdx.x % chunks) * MU_WPB + wave;
+  const bool row = ib < a.n4;  // wavefronts past the last p4 build tables only
+  const int e = ia * a.n4 + ib;
+  const double2* xi = a.x + (size_t)inst * 3 * ne;
+  if (a.act && !a.act[inst]) {  // frozen: the rows carry their iterate (the whole workgroup)
+    if (row && lane < 3) a.out[(size_t)inst * 3 * ne + (size_t)lane * ne + e] = xi[(size_t)lane * ne + e];
+    return;
+  }
+  for (int t = tid; t < na; t += blockDim.x) {
     zs[t] = a.z[t];
     sns[t] = sqrt((1.0 - a.z[t]) * (1.0 + a.z[t]));
     wzs[t] = a.wz[t];
   }
-  __syncthreads();
-  const int ne = a.ns * a.n4, nl = a.nqs * a.nq4;
-  const long row = (long)blockIdx.x * (blockDim.x / MU_WAVE) + threadIdx.x / MU_WAVE;
-  if (row >= (long)a.n_inst * ne) return;
-  const int inst = (int)(row / ne), e = (int)(row % ne);
-  const double2* xi = a.x + (size_t)inst * 3 * ne;
-  if (a.act && !a.act[inst]) {  // frozen: the row carries its iterate (uniform per wavefront)
-    if (lane < 3) a.out[(size_t)inst * 3 * ne + (size_t)lane * ne + e] = xi[(size_t)lane * ne + e];
-    return;
-  }
   const MuInst I = a.inst[inst];
-  const int ia = e / a.n4, ib = e % a.n4;
-  const double pabs = a.ps[ia], p4r = a.p4[ib];
+  const double pabs = a.ps[ia];
+  const double p4r = row ? a.p4[ib] : 0.0;
   const double2* Li = a.L + (size_t)inst * 3 * nl;
   MuPoint P;
   P.p = pabs;
   P.pt4 = mk(p4r, I.mu);
-  P.Ap = mk(xi[e].x, xi[e].y);
-  P.Bp = mk(xi[ne + e].x, xi[ne + e].y);
-  P.Cp = mk(xi[2 * ne + e].x, xi[2 * ne + e].y);
+  if (row) {
+    P.Ap = mk(xi[e].x, xi[e].y);
+    P.Bp = mk(xi[ne + e].x, xi[ne + e].y);
+    P.Cp = mk(xi[2 * ne + e].x, xi[2 * ne + e].y);
+  }
   double sAr = 0, sAi = 0, sBr = 0, sBi = 0, sCr = 0, sCi = 0;
-  for (int l = lane; l < nl; l += MU_WAVE) {
-    const int c = l / a.nq4, d = l % a.nq4;
-    const double qa = a.qs[c], q4a = a.q4[d];
-    const double wl = a.cw * I.gnorm * a.wqs[c] * a.wq4[d];
-    const cd A0 = mk(Li[l].x, Li[l].y), B0 = mk(Li[nl + l].x, Li[nl + l].y),
-             C0 = mk(Li[2 * nl + l].x, Li[2 * nl + l].y);
-    // angular moments for q4 = +|q4| (k4 = p4 - |q4|) and q4 = -|q4|; the
-    // geometry in the plane of p_vec and q_vec is common to both
-    const double k4p = p4r - q4a, k4m = p4r + q4a;
-    const double k4p2 = k4p * k4p, k4m2 = k4m * k4m;
-    const double ep = exp(-k4p2 * I.inv_om2), em = exp(-k4m2 * I.inv_om2);
-    double Sp[3] = {0, 0, 0}, Tp[3] = {0, 0, 0}, Sm[3] = {0, 0, 0}, Tm[3] = {0, 0, 0};
-    for (int t = 0; t < a.na; ++t) {
+  const int tc = min(MU_TC, MU_TAB / na);  // radii per block
+  for (int c0 = 0; c0 < a.nqs; c0 += tc) {
+    const int nc = min(tc, a.nqs - c0);
+    __syncthreads();  // zs, sns, wzs written; the previous block's tables read
+    for (int k = tid; k < nc * na; k += blockDim.x) {
+      const int t = k % na;
+      const double qa = a.qs[c0 + k / na];
       const double qx = qa * sns[t];
       const double v = pabs - qa * zs[t];
       const double base = qx * qx + v * v;
-      const double g = wzs[t] * exp(-base * I.inv_om2);
-      const double gp = g * ep, gm = g * em;
-      // 1/k^2 for both signs of q4 from one division
-      const double dp = base + k4p2, dm = base + k4m2;
-      const double rpm = 1.0 / (dp * dm);
-      const double yp = dm * rpm, ym = dp * rpm;
-      const double gpv = gp * v, gmv = gm * v;
-      Sp[0] += gp;
-      Sp[1] += gpv;
-      Sp[2] = fma(gpv, v, Sp[2]);
-      Tp[0] = fma(gp, yp, Tp[0]);
-      Tp[1] = fma(gpv, yp, Tp[1]);
-      Tp[2] = fma(gpv * v, yp, Tp[2]);
-      Sm[0] += gm;
-      Sm[1] += gmv;
-      Sm[2] = fma(gmv, v, Sm[2]);
-      Tm[0] = fma(gm, ym, Tm[0]);
-      Tm[1] = fma(gmv, ym, Tm[1]);
-      Tm[2] = fma(gmv * v, ym, Tm[2]);
+      tg[k] = wzs[t] * exp(-base * I.inv_om2);
+      tv[k] = v;
+      tb[k] = base;
     }
-    P.q = qa;
-    cd IA, IB, IC;
-    // q4 > 0: the interpolated values; q4 < 0: their conjugates
-    P.k4 = k4p;
-    P.qt4 = mk(q4a, I.mu);
-    P.Aq = A0;
-    P.Bq = B0;
-    P.Cq = C0;
-    mu_projections(P, Sp, Tp, IA, IB, IC);
-    sAr = fma(wl, IA.r, sAr);
-    sAi = fma(wl, IA.i, sAi);
-    sBr = fma(wl, IB.r, sBr);
-    sBi = fma(wl, IB.i, sBi);
-    sCr = fma(wl, IC.r, sCr);
-    sCi = fma(wl, IC.i, sCi);
-    P.k4 = k4m;
-    P.qt4 = mk(-q4a, I.mu);
-    P.Aq = conj(A0);
-    P.Bq = conj(B0);
-    P.Cq = conj(C0);
-    mu_projections(P, Sm, Tm, IA, IB, IC);
-    sAr = fma(wl, IA.r, sAr);
-    sAi = fma(wl, IA.i, sAi);
-    sBr = fma(wl, IB.r, sBr);
-    sBi = fma(wl, IB.i, sBi);
-    sCr = fma(wl, IC.r, sCr);
-    sCi = fma(wl, IC.i, sCi);
+    __syncthreads();
+    for (int cc = tid; cc < nc; cc += blockDim.x) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int t = 0; t < na; ++t) {
+        const double g = tg[cc * na + t], gv = g * tv[cc * na + t];
+        s0 += g;
+        s1 += gv;
+        s2 = fma(gv, tv[cc * na + t], s2);
+      }
+      tS[0][cc] = s0;
+      tS[1][cc] = s1;
+      tS[2][cc] = s2;
+    }
+    __syncthreads();
+    if (!row) continue;
+    for (int l = c0 * a.nq4 + lane; l < (c0 + nc) * a.nq4; l += MU_WAVE) {
+      const int c = l / a.nq4, d = l % a.nq4, cc = c - c0;
+      const double qa = a.qs[c], q4a = a.q4[d];
+      const double wl = a.cw * I.gnorm * a.wqs[c] * a.wq4[d];
+      const cd A0 = mk(Li[l].x, Li[l].y), B0 = mk(Li[nl + l].x, Li[nl + l].y),
+               C0 = mk(Li[2 * nl + l].x, Li[2 * nl + l].y);
+      // q4 = +|q4| (k4 = p4 - |q4|) and q4 = -|q4| (k4 = p4 + |q4|)
+      const double k4p = p4r - q4a, k4m = p4r + q4a;
+      const double k4p2 = k4p * k4p, k4m2 = k4m * k4m;
+      const double ep = exp(-k4p2 * I.inv_om2), em = exp(-k4m2 * I.inv_om2);
+      const double* g_ = tg + cc * na;
+      const double* v_ = tv + cc * na;
+      const double* b_ = tb + cc * na;
+      double up0 = 0, up1 = 0, up2 = 0, um0 = 0, um1 = 0, um2 = 0;
+#pragma unroll 2
+      for (int t = 0; t < na; ++t) {
+        const double g = g_[t], v = v_[t], base = b_[t];
+        // 1/k^2 for both signs of q4 from one division
+        const double dp = base + k4p2, dm = base + k4m2;
+        const double rpm = 1.0 / (dp * dm);
+        const double yp = dm * rpm, ym = dp * rpm;
+        const double gv = g * v, gvv = gv * v;
+        up0 = fma(g, yp, up0);
+        up1 = fma(gv, yp, up1);
+        up2 = fma(gvv, yp, up2);
+        um0 = fma(g, ym, um0);
+        um1 = fma(gv, ym, um1);
+        um2 = fma(gvv, ym, um2);
+      }
+      const double Sp[3] = {ep * tS[0][cc], ep * tS[1][cc], ep * tS[2][cc]};
+      const double Tp[3] = {ep * up0, ep * up1, ep * up2};
+      const double Sm[3] = {em * tS[0][cc], em * tS[1][cc], em * tS[2][cc]};
+      const double Tm[3] = {em * um0, em * um1, em * um2};
+      P.q = qa;
+      cd IA, IB, IC;
+      // q4 > 0: the interpolated values; q4 < 0: their conjugates
+      P.k4 = k4p;
+      P.qt4 = mk(q4a, I.mu);
+      P.Aq = A0;
+      P.Bq = B0;
+      P.Cq = C0;
+      mu_projections(P, Sp, Tp, IA, IB, IC);
+      sAr = fma(wl, IA.r, sAr);
+      sAi = fma(wl, IA.i, sAi);
+      sBr = fma(wl, IB.r, sBr);
+      sBi = fma(wl, IB.i, sBi);
+      sCr = fma(wl, IC.r, sCr);
+      sCi = fma(wl, IC.i, sCi);
+      P.k4 = k4m;
+      P.qt4 = mk(-q4a, I.mu);
+      P.Aq = conj(A0);
+      P.Bq = conj(B0);
+      P.Cq = conj(C0);
+      mu_projections(P, Sm, Tm, IA, IB, IC);
+      sAr = fma(wl, IA.r, sAr);
+      sAi = fma(wl, IA.i, sAi);
+      sBr = fma(wl, IB.r, sBr);
+      sBi = fma(wl, IB.i, sBi);
+      sCr = fma(wl, IC.r, sCr);
+      sCi = fma(wl, IC.i, sCi);
+    }
   }
+  if (!row) return;
   sAr = wsum_mu(sAr);
   sAi = wsum_mu(sAi);
   sBr = wsum_mu(sBr);
@@ -314,7 +361,7 @@ hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, 
                            const int* lo_s, const double* sw_s, const int* lo_4,
                            const double* sw_4, const MuInst* inst, const int* act,
                            const double* x_in, double* x_out, double* L) {
-  if (na > 256) return hipErrorInvalidValue;
+  if (na < 1 || na > 256 || n_inst < 1 || ns < 1 || n4 < 1) return hipErrorInvalidValue;
   const int nl = nqs * nq4, ne = ns * n4;
   hipLaunchKernelGGL(k_mu_interp, dim3((nl + 255) / 256, n_inst), dim3(256), 0, st, ns, n4, nqs,
                      nq4, lo_s, sw_s, lo_4, sw_4, (const double2*)x_in, (double2*)L);
@@ -322,8 +369,8 @@ hipError_t launch_mu_sweep(hipStream_t st, int n_inst, int ns, int n4, int nqs, 
   MuArgs a{n_inst, ns, n4, nqs, nq4, na, (4.0 / 3.0) / (8.0 * pi * pi * pi), inst, act,
            ps, p4, qs, q4, wqs, wq4, z, wz, (const double2*)x_in, (const double2*)L,
            (double2*)x_out};
-  const long rows = (long)n_inst * ne;
-  hipLaunchKernelGGL(k_mu_sweep, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, a);
+  const long blocks = (long)n_inst * ns * ((n4 + MU_WPB - 1) / MU_WPB);
+  hipLaunchKernelGGL(k_mu_sweep, dim3((unsigned)blocks), dim3(64 * MU_WPB), 0, st, a);
   return hipGetLastError();
 }
 
