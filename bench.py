@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP64_VALU_PEAK_TFLOPS = 78.6
-MU_FLOPS_PER_PAIR = 1733
+MU_FLOPS_PER_PAIR = 1617
 MU_FLOPS_PER_ANGLE = 36
 COPY_BYTES = 1 << 30
 

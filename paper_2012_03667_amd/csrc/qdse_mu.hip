@@ -46,8 +46,8 @@ __device__ inline cd operator*(cd a, cd b) { return {a.r * b.r - a.i * b.i, a.r 
 __device__ inline cd operator*(double a, cd b) { return {a * b.r, a * b.i}; }
 __device__ inline cd operator*(cd b, double a) { return {a * b.r, a * b.i}; }
 __device__ inline cd inv(cd a) {
-  const double d = a.r * a.r + a.i * a.i;
-  return {a.r / d, -a.i / d};
+  const double rd = 1.0 / (a.r * a.r + a.i * a.i);
+  return {a.r * rd, -a.i * rd};
 }
 __device__ inline cd conj(cd a) { return {a.r, -a.i}; }
 
@@ -196,11 +196,13 @@ __device__ inline void mu_projections(const MuPoint& P, const double S[3], const
 constexpr int MU_WPB = 4;
 constexpr int MU_TAB = 4608;  // table entries (loop radius x angle) per block of radii
 constexpr int MU_TC = 256;    // loop radii per block at most
+constexpr int MU_NQ4 = 320;   // loop |q4| nodes whose q4 factors are tabulated
 
 __global__ void __launch_bounds__(64 * MU_WPB) k_mu_sweep(MuArgs a) {
   __shared__ double zs[256], sns[256], wzs[256];
   __shared__ double tg[MU_TAB], tv[MU_TAB], tb[MU_TAB];  // g_t, v_t, k_vec^2 per (radius, angle)
   __shared__ double tS[3][MU_TC];                        // S_0, S_1, S_2 per radius
+  __shared__ double te[MU_WPB][2][MU_NQ4];               // exp(-(p4 -+ |q4|)^2 / omega^2) per wavefront
   const int tid = threadIdx.x, lane = tid & (MU_WAVE - 1), wave = tid / MU_WAVE;
   const int na = a.na, ne = a.ns * a.n4, nl = a.nqs * a.nq4;
   const int chunks = (a.n4 + MU_WPB - 1) / MU_WPB;
@@ -230,6 +232,16 @@ __global__ void __launch_bounds__(64 * MU_WPB) k_mu_sweep(MuArgs a) {
     P.Ap = mk(xi[e].x, xi[e].y);
     P.Bp = mk(xi[ne + e].x, xi[ne + e].y);
     P.Cp = mk(xi[2 * ne + e].x, xi[2 * ne + e].y);
+  }
+  // the q4 factor of the interaction for both signs of q4, per loop |q4|
+  // (written and read by this wavefront only; on longer q4 grids evaluated
+  // where it is used, with the same value)
+  const bool tab4 = a.nq4 <= MU_NQ4;
+  for (int d = lane; tab4 && d < a.nq4; d += MU_WAVE) {
+    const double q4a = a.q4[d];
+    const double k4p = p4r - q4a, k4m = p4r + q4a;
+    te[wave][0][d] = exp(-(k4p * k4p) * I.inv_om2);
+    te[wave][1][d] = exp(-(k4m * k4m) * I.inv_om2);
   }
   double sAr = 0, sAi = 0, sBr = 0, sBi = 0, sCr = 0, sCi = 0;
   const int tc = min(MU_TC, MU_TAB / na);  // radii per block
@@ -261,8 +273,10 @@ __global__ void __launch_bounds__(64 * MU_WPB) k_mu_sweep(MuArgs a) {
     }
     __syncthreads();
     if (!row) continue;
+    // loop point l = c nq4 + d, stepped without a division
+    int c = c0 + lane / a.nq4, d = lane % a.nq4;
     for (int l = c0 * a.nq4 + lane; l < (c0 + nc) * a.nq4; l += MU_WAVE) {
-      const int c = l / a.nq4, d = l % a.nq4, cc = c - c0;
+      const int cc = c - c0;
       const double qa = a.qs[c], q4a = a.q4[d];
       const double wl = a.cw * I.gnorm * a.wqs[c] * a.wq4[d];
       const cd A0 = mk(Li[l].x, Li[l].y), B0 = mk(Li[nl + l].x, Li[nl + l].y),
@@ -270,7 +284,8 @@ __global__ void __launch_bounds__(64 * MU_WPB) k_mu_sweep(MuArgs a) {
       // q4 = +|q4| (k4 = p4 - |q4|) and q4 = -|q4| (k4 = p4 + |q4|)
       const double k4p = p4r - q4a, k4m = p4r + q4a;
       const double k4p2 = k4p * k4p, k4m2 = k4m * k4m;
-      const double ep = exp(-k4p2 * I.inv_om2), em = exp(-k4m2 * I.inv_om2);
+      const double ep = tab4 ? te[wave][0][d] : exp(-k4p2 * I.inv_om2);
+      const double em = tab4 ? te[wave][1][d] : exp(-k4m2 * I.inv_om2);
       const double* g_ = tg + cc * na;
       const double* v_ = tv + cc * na;
       const double* b_ = tb + cc * na;
@@ -321,6 +336,11 @@ __global__ void __launch_bounds__(64 * MU_WPB) k_mu_sweep(MuArgs a) {
       sBi = fma(wl, IB.i, sBi);
       sCr = fma(wl, IC.r, sCr);
       sCi = fma(wl, IC.i, sCi);
+      d += MU_WAVE;
+      while (d >= a.nq4) {
+        d -= a.nq4;
+        ++c;
+      }
     }
   }
   if (!row) return;
