@@ -72,6 +72,29 @@ def test_mu_full_size_sampled_rows(Q):
         assert rel(y[f, rows], ref[f]) < RTOL, (f, rel(y[f, rows], ref[f]))
 
 
+@pytest.mark.parametrize("ns,n4,na,T", [(6, 330, 4, 0.0), (80, 4, 64, 0.0), (5, 340, 3, 0.002)])
+def test_mu_sweep_long_grids_sampled_rows(Q, ns, n4, na, T):
+    """Grids past the kernel's per-workgroup tables: a loop q4 grid longer than
+    the tabulated q4 factors (n4 = 330, 340: the factors evaluated in the
+    loop; the last case on Matsubara frequencies) and more loop radii x
+    angles than one LDS table holds (81 x 64: the radii in two blocks). One
+    sweep against the oracle on sampled external points."""
+    print(f"case mu long grid {ns}x{n4}x{na} T {T}", flush=True)
+    mu = 0.25
+    rng = np.random.default_rng(ns * 1000 + n4)
+    kw = dict(r_min=1e-2, r_max=8.0, p4_max=8.0, lam4=0.5)
+    if T > 0:
+        kw["T"] = T
+    S = Q.MuSolver(ns, n4, na, [(0.55, 0.678, 0.005, mu)], **kw)
+    g = O.mu_grid(ns, n4, na, **kw)
+    x0 = smooth_mu(g, rng)
+    y = S.iterate(torch.tensor(x0[None], device="cuda")).cpu().numpy()[0]
+    rows = np.sort(rng.choice(g.ne, 5, replace=False))
+    ref = O.F_mu(g, 0.55, 0.678, 0.005, mu, x0, rows=rows)
+    for f in range(3):
+        assert rel(y[f, rows], ref[f]) < RTOL, (f, rel(y[f, rows], ref[f]))
+
+
 def test_mu_solve_matches_oracle_picard(Q):
     ns, n4, na, mu = 8, 8, 6, 0.25
     kw = dict(r_min=1e-2, r_max=8.0, p4_max=8.0)
