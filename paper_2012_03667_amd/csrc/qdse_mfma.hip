@@ -30,12 +30,16 @@
 // whose partial products are added through LDS before the FP64 epilogue; a
 // wavefront accumulates 16 rows x 32 instances in blocks of 16 x 16, eight
 // products each (one 16-row block per wavefront measured fastest for both
-// element types; four row groups per workgroup measured no faster). Operands are read straight from L2/L1 in layouts where a
-// 16-lane group reads contiguous memory, with the next k-step prefetched.
+// element types; four row groups per workgroup measured no faster). Operands
+// are read straight from L2/L1 in layouts where a 16-lane group reads one
+// contiguous run, with the following k-steps prefetched.
 //
-// Layouts (zero padded): MT[x][j][ldi] (x = 0..4, rows contiguous),
-// C[y][j][ldb] (y = 0..5, instances contiguous); ldi and ldb multiples of 32,
-// the loop-node extent nq_pad a multiple of 8.
+// Layouts (zero padded), VW loop nodes per lane and load (FP32 1, FP64 2):
+// MT[x][j / VW][ldi][j % VW] (x = 0..4), C[y][j / VW][ldb][j % VW]
+// (y = 0..5); ldi and ldb multiples of 32, the loop-node extent nq_pad a
+// multiple of 16. For FP64 a lane's two loop nodes come with one 16-byte
+// load (83-85 against 88 us per 1024-instance contraction); FP32 with two
+// nodes per load measured slower (59.5 against 56 us) and keeps one.
 #include "qdse_internal.h"
 
 namespace qdse {
@@ -56,10 +60,16 @@ template <class T> struct Mfma;
 // copied after the step (measured faster for FP32 at three wavefronts per
 // SIMD: 56 against 70-75 us at 1024 instances; FP64, one wavefront per SIMD,
 // gains from two steps in flight: 88 against 92 us).
+// VW: consecutive loop nodes a lane reads with one load (its k values of VW
+// successive MFMA steps).
+typedef float floatx1 __attribute__((ext_vector_type(1)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
 template <> struct Mfma<float> {
   typedef floatx4 acc_t;
+  typedef floatx1 vec_t;
   static constexpr int RB = 1;  // 16-row blocks per wavefront
   static constexpr int PD = 0;
+  static constexpr int VW = 1;
   __device__ static int row(int g, int e) { return 4 * g + e; }
   __device__ static acc_t zero() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
   __device__ static acc_t mac(float a, float b, acc_t c) {
@@ -68,8 +78,10 @@ template <> struct Mfma<float> {
 };
 template <> struct Mfma<double> {
   typedef doublex4 acc_t;
+  typedef doublex2 vec_t;
   static constexpr int RB = 1;
   static constexpr int PD = 2;
+  static constexpr int VW = 2;
   __device__ static int row(int g, int e) { return g + 4 * e; }
   __device__ static acc_t zero() { return doublex4{0.0, 0.0, 0.0, 0.0}; }
   __device__ static acc_t mac(double a, double b, acc_t c) {
@@ -81,15 +93,19 @@ template <class T>
 __global__ void k_build_m(int n, int nq, int ldk, int ldi, const double* __restrict__ K,
                           const double* __restrict__ s_, const double* __restrict__ t_,
                           T* __restrict__ MT, size_t mstride) {
+  constexpr int VW = Mfma<T>::VW;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)n * nq) return;
-  const int j = (int)(idx / n), i = (int)(idx % n);  // i fastest: coalesced writes
+  const long nqv = (long)(nq + VW - 1) / VW * VW;
+  if (idx >= (long)n * nqv) return;
+  // stored order: loop-node block, row, node within the block (coalesced writes)
+  const int jv = (int)(idx % VW), i = (int)((idx / VW) % n), j = (int)(idx / ((long)VW * n)) * VW + jv;
+  if (j >= nq) return;
   const size_t mat = (size_t)n * ldk;
   const double kT = K[(size_t)i * ldk + j], k3 = K[mat + (size_t)i * ldk + j],
                k0 = K[2 * mat + (size_t)i * ldk + j];
   const double s = s_[i], t = t_[j];
   const double k2 = (s + t) * kT;
-  const size_t o = (size_t)j * ldi + i;
+  const size_t o = ((size_t)(j / VW) * ldi + i) * VW + jv;
   MT[o] = (T)(k3 - k2);
   MT[mstride + o] = (T)(k3 + k2);
   MT[2 * mstride + o] = (T)kT;
@@ -145,7 +161,7 @@ __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool
 // masked-run decision of the previous sweep. A block covers 32 loop nodes x
 // 32 instances: threads compute with j fastest (the interpolation stencils
 // read the iterate contiguously), the six columns pass through LDS, and the
-// stores run with the instance index fastest (contiguous in C).
+// stores run in C's order (contiguous runs of 32 VW values).
 template <class T>
 __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int ldb,
                                                   const int* __restrict__ lo,
@@ -189,11 +205,14 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
     tile[5][bb][jj] = (T)(sS * Aq);
   }
   __syncthreads();
+  // stored order C[y][j / VW][inst][j % VW]: node within the block fastest,
+  // then instance (contiguous runs of 32 VW values)
+  constexpr int VW = Mfma<T>::VW;
   for (int e = tid; e < 32 * 32; e += 256) {
-    const int bb = e % 32, jj = e / 32;
+    const int jv = e % VW, bb = (e / VW) % 32, jj = (e / (VW * 32)) * VW + jv;
     const int j = j0 + jj, inst = b0 + bb;
     if (j >= nq || inst >= n_inst || frozen[bb]) continue;
-    const size_t o = (size_t)j * ldb + inst;
+    const size_t o = ((size_t)(j / VW) * ldb + inst) * VW + jv;
 #pragma unroll
     for (int y = 0; y < 6; ++y) C[(size_t)y * cstride + o] = tile[y][bb][jj];
   }
@@ -248,7 +267,9 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
     }
   }
   const int lr = lane & 15, lk = lane >> 4;
-  const int half = nq_pad / KSPLIT;  // a multiple of KSTEP
+  constexpr int VW = Mfma<T>::VW, KG = KSTEP * VW;  // loop nodes per load group
+  typedef typename Mfma<T>::vec_t vec_t;
+  const int half = nq_pad / KSPLIT;  // a multiple of KG
   const int kb = kh * half, ke = kb + half;
   acc_t acc[8][RB][2];
 #pragma unroll
@@ -263,45 +284,53 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
   constexpr int PD = Mfma<T>::PD;
   // operand sets of PD + 1 consecutive k-steps (two for PD = 0), used in
   // rotation (indices known at compile time, so the sets stay in registers)
-  T a[PD + 1 + (PD == 0)][5][RB], c[PD + 1 + (PD == 0)][6][2];
-  auto load = [&](int k0, T (&A)[5][RB], T (&B)[6][2]) {
-    const size_t ra = (size_t)(k0 + lk) * ldi + i0 + lr;  // A[m][k] = MT[k][m]
-    const size_t rc = (size_t)(k0 + lk) * ldb + b0 + lr;  // B[k][n] = C[k][n]
+  vec_t a[PD + 1 + (PD == 0)][5][RB], c[PD + 1 + (PD == 0)][6][2];
+  // One load group: lane (lk, lr) reads loop nodes k0 + VW lk .. + VW - 1 of
+  // row i0 + lr (A = MT[x][k / VW][row][k % VW]) and of instance b0 + lr
+  // (B = C[y][k / VW][inst][k % VW]): 16 lanes read one contiguous run; MFMA
+  // step v of the group then takes k = k0 + VW lk + v in both operands.
+  auto load = [&](int k0, vec_t (&A)[5][RB], vec_t (&B)[6][2]) {
+    const size_t ra = ((size_t)(k0 / VW + lk) * ldi + i0 + lr) * VW;
+    const size_t rc = ((size_t)(k0 / VW + lk) * ldb + b0 + lr) * VW;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      A[0][r] = M1[ra + 16 * r];
-      A[1][r] = M2[ra + 16 * r];
-      A[2][r] = M3[ra + 16 * r];
-      A[3][r] = M4[ra + 16 * r];
-      A[4][r] = M5[ra + 16 * r];
+      const size_t o = ra + (size_t)16 * r * VW;
+      A[0][r] = *(const vec_t*)(M1 + o);
+      A[1][r] = *(const vec_t*)(M2 + o);
+      A[2][r] = *(const vec_t*)(M3 + o);
+      A[3][r] = *(const vec_t*)(M4 + o);
+      A[4][r] = *(const vec_t*)(M5 + o);
     }
 #pragma unroll
     for (int y = 0; y < 6; ++y)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) B[y][cb] = C[(size_t)y * cstride + rc + 16 * cb];
+      for (int cb = 0; cb < 2; ++cb)
+        B[y][cb] = *(const vec_t*)(C + (size_t)y * cstride + rc + (size_t)16 * cb * VW);
   };
-  auto mma = [&](const T (&A)[5][RB], const T (&B)[6][2]) {
+  auto mma = [&](const vec_t (&A)[5][RB], const vec_t (&B)[6][2]) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int v = 0; v < VW; ++v)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        acc[0][r][cb] = Mfma<T>::mac(A[0][r], B[0][cb], acc[0][r][cb]);
-        acc[1][r][cb] = Mfma<T>::mac(A[1][r], B[1][cb], acc[1][r][cb]);
-        acc[2][r][cb] = Mfma<T>::mac(A[2][r], B[2][cb], acc[2][r][cb]);
-        acc[3][r][cb] = Mfma<T>::mac(A[2][r], B[3][cb], acc[3][r][cb]);
-        acc[4][r][cb] = Mfma<T>::mac(A[2][r], B[4][cb], acc[4][r][cb]);
-        acc[5][r][cb] = Mfma<T>::mac(A[2][r], B[1][cb], acc[5][r][cb]);
-        acc[6][r][cb] = Mfma<T>::mac(A[3][r], B[5][cb], acc[6][r][cb]);
-        acc[7][r][cb] = Mfma<T>::mac(A[4][r], B[3][cb], acc[7][r][cb]);
-      }
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          acc[0][r][cb] = Mfma<T>::mac(A[0][r][v], B[0][cb][v], acc[0][r][cb]);
+          acc[1][r][cb] = Mfma<T>::mac(A[1][r][v], B[1][cb][v], acc[1][r][cb]);
+          acc[2][r][cb] = Mfma<T>::mac(A[2][r][v], B[2][cb][v], acc[2][r][cb]);
+          acc[3][r][cb] = Mfma<T>::mac(A[2][r][v], B[3][cb][v], acc[3][r][cb]);
+          acc[4][r][cb] = Mfma<T>::mac(A[2][r][v], B[4][cb][v], acc[4][r][cb]);
+          acc[5][r][cb] = Mfma<T>::mac(A[2][r][v], B[1][cb][v], acc[5][r][cb]);
+          acc[6][r][cb] = Mfma<T>::mac(A[3][r][v], B[5][cb][v], acc[6][r][cb]);
+          acc[7][r][cb] = Mfma<T>::mac(A[4][r][v], B[3][cb][v], acc[7][r][cb]);
+        }
   };
   // software pipeline
   if constexpr (PD == 0) {
     // one step ahead through the staging set a[1], c[1], copied after each
     // step; the last step is peeled so the loop body has no branch
     load(kb, a[0], c[0]);
-    for (int k0 = kb; k0 + KSTEP < ke; k0 += KSTEP) {
-      load(k0 + KSTEP, a[1], c[1]);
+    for (int k0 = kb; k0 + KG < ke; k0 += KG) {
+      load(k0 + KG, a[1], c[1]);
       mma(a[0], c[0]);
 #pragma unroll
       for (int q = 0; q < 5; ++q)
@@ -316,15 +345,15 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
     // step j uses set j mod (PD + 1) and the load of step j + PD goes to the
     // set step j - 1 used, so no register is copied (a copy would wait for
     // the load it copies)
-    const int nst = (ke - kb) / KSTEP;
+    const int nst = (ke - kb) / KG;
 #pragma unroll
     for (int p = 0; p < PD; ++p)
-      if (p < nst) load(kb + p * KSTEP, a[p], c[p]);
+      if (p < nst) load(kb + p * KG, a[p], c[p]);
     int j0 = 0;
     for (; j0 + 2 * PD < nst; j0 += PD + 1) {
 #pragma unroll
       for (int p = 0; p <= PD; ++p) {
-        load(kb + (j0 + p + PD) * KSTEP, a[(p + PD) % (PD + 1)], c[(p + PD) % (PD + 1)]);
+        load(kb + (j0 + p + PD) * KG, a[(p + PD) % (PD + 1)], c[(p + PD) % (PD + 1)]);
         mma(a[p], c[p]);
       }
     }
@@ -333,7 +362,7 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
       const int j = j0 + p;
       if (j < nst) {
         if (j + PD < nst)
-          load(kb + (j + PD) * KSTEP, a[(p + PD) % (PD + 1)], c[(p + PD) % (PD + 1)]);
+          load(kb + (j + PD) * KG, a[(p + PD) % (PD + 1)], c[(p + PD) % (PD + 1)]);
         mma(a[p % (PD + 1)], c[p % (PD + 1)]);
       }
     }
@@ -421,7 +450,10 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
 
 MmLayout mm_layout(int n, int nq, int n_inst) {
   MmLayout L;
-  L.nq_pad = (nq + KSPLIT * KSTEP - 1) / (KSPLIT * KSTEP) * (KSPLIT * KSTEP);
+  // each K half a whole number of load groups of either element type
+  constexpr int Q = KSPLIT * KSTEP * (Mfma<float>::VW > Mfma<double>::VW ? Mfma<float>::VW
+                                                                          : Mfma<double>::VW);
+  L.nq_pad = (nq + Q - 1) / Q * Q;
   L.ldi = (n + TM_MAX - 1) / TM_MAX * TM_MAX;
   L.ldb = (n_inst + TN - 1) / TN * TN;
   L.mstride = (size_t)L.nq_pad * L.ldi;
@@ -432,7 +464,7 @@ MmLayout mm_layout(int n, int nq, int n_inst) {
 template <class T>
 hipError_t launch_build_mm(hipStream_t st, int n, int nq, int ldk, const MmLayout& L,
                            const double* K, const double* s, const double* t, T* MT) {
-  const long tot = (long)n * nq;
+  const long tot = (long)n * ((nq + Mfma<T>::VW - 1) / Mfma<T>::VW * Mfma<T>::VW);
   hipLaunchKernelGGL(k_build_m<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nq,
                      ldk, L.ldi, K, s, t, MT, L.mstride);
   return hipGetLastError();
