@@ -279,9 +279,9 @@ int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double l
                 int* steps, double* resid);
 
 /* Duration in microseconds of the single-launch kernel of the last
- * qdse_solve on this context (HIP events carried on the launch's dispatch
- * packet); QDSE_ENOTSUP if the last solve used another driver. us must not
- * be NULL. */
+ * qdse_solve on this context (HIP events recorded on the context's stream
+ * just before and after the launch); QDSE_ENOTSUP if the last solve used
+ * another driver. us must not be NULL. */
 int qdse_solve_kernel_us(const qdse_ctx* ctx, double* us);
 
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may

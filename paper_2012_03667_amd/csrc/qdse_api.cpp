@@ -179,7 +179,7 @@ struct qdse_ctx {
   PersistOut* d_pout = nullptr;
   unsigned persist_tag = 1;
   bool persist_ok = false;
-  hipEvent_t pev[2] = {nullptr, nullptr};  // on the launch's dispatch packet
+  hipEvent_t pev[2] = {nullptr, nullptr};  // recorded around the launch
   double last_kernel_us = -1.0;            // of the last solve's single launch
   // vjp / Krylov workspace (lazy)
   double *d_part = nullptr, *d_gq = nullptr;
