@@ -232,8 +232,9 @@ int qdse_iterate_fp64_matrix(qdse_ctx* ctx, const double* d_x_in, double* d_x_ou
  * Drivers of QDSE_PICARD: with FP64 precision, one kernel block, up to four
  * instances and the iterates, node functions and stencils of all instances
  * within one workgroup's LDS (N = 512: up to three instances), the whole
- * solve runs as one launch (same arithmetic, same results bit
- * for bit as the kernel-per-sweep driver, which serves every other case);
+ * solve runs as one launch, also in the renormalised mode of qdse_setup_qc
+ * (same arithmetic, same results bit for bit as the kernel-per-sweep driver,
+ * which serves every other case);
  * the environment variable QDSE_PERSISTENT=0 selects the kernel-per-sweep
  * driver, QDSE_PERSISTENT=1 makes the single launch a requirement
  * (QDSE_ENOTSUP where it does not apply). The single launch's waits for the

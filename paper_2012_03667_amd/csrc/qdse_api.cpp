@@ -428,13 +428,14 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
     }
   }
 #undef TRY
-  // Single-launch solve: every instance shares kernel block 0, the LDS fits
-  // and ceil(n / 4) workgroups are co-resident. Its exchange words start at
-  // tag 0, below every tag a solve uses.
-  if (c->n_blocks == 1 && !c->qc) {
+  // Single-launch solve (also in the renormalised mode): every instance
+  // shares kernel block 0, the LDS fits and ceil(rows / 8) workgroups are
+  // co-resident. Its exchange words start at tag 0, below every tag a solve
+  // uses.
+  if (c->n_blocks == 1) {
     bool fits = false;
-    if (persistent_fits(n_inst, g.n, g.ldk, &fits) == hipSuccess && fits) {
-      const size_t words = persistent_words(n_inst, g.n);
+    if (persistent_fits(n_inst, g.n, g.ldk, c->qc != 0, &fits) == hipSuccess && fits) {
+      const size_t words = persistent_words(n_inst, g.n, c->qc != 0);
       if (dalloc(&c->d_xw, words) == QDSE_OK && dalloc(&c->d_perr, 1) == QDSE_OK &&
           hipMemsetAsync(c->d_xw, 0, words * sizeof(unsigned long long), st) == hipSuccess &&
           hipMemsetAsync(c->d_perr, 0, sizeof(unsigned), st) == hipSuccess &&
@@ -913,7 +914,9 @@ static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, 
   const unsigned long long span = (unsigned long long)max_iter + 2;
   if ((unsigned long long)c->persist_tag + span > 0xffffffffull) {
     HIPCHK(hipMemsetAsync(c->d_xw, 0,
-                          persistent_words(c->n_inst, g.n) * sizeof(unsigned long long), st));
+                          persistent_words(c->n_inst, g.n, c->qc != 0) *
+                              sizeof(unsigned long long),
+                          st));
     HIPCHK(hipMemsetAsync(c->d_perr, 0, sizeof(unsigned), st));
     c->persist_tag = 1;
   }
@@ -925,7 +928,8 @@ static int solve_persistent(qdse_ctx* c, double* d_x, double tol, int max_iter, 
   if (const char* e = std::getenv("QDSE_PERSIST_SPIN")) spin_limit = std::atol(e);
   HIPCHK(launch_persistent(st, c->n_inst, g.n, g.nq, g.ldk, c->d_inst, c->d_K, c->d_sw, c->d_t,
                            c->d_s, d_x, c->d_xw, c->d_pout, tol, max_iter, conv_mode, tag0,
-                           c->d_perr, c->pev[0], c->pev[1], spin_limit));
+                           c->d_perr, c->pev[0], c->pev[1], spin_limit,
+                           c->qc ? &c->zp : nullptr));
   HIPCHK(wait_polling(st));
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, c->pev[0], c->pev[1]));

@@ -271,16 +271,18 @@ struct PersistOut {
 
 // Single-launch solve of up to persistent_max_inst() instances
 // sharing kernel block 0 (qdse_persistent.hip).
-size_t persistent_lds_bytes(int n_inst, int n, int ldk);
-size_t persistent_words(int n_inst, int n);
-int persistent_blocks(int n);
+// qc: the renormalised mode (n + 1 kernel-matrix rows, launch with zp).
+size_t persistent_lds_bytes(int n_inst, int n, int ldk, bool qc);
+size_t persistent_words(int n_inst, int n, bool qc);
+int persistent_blocks(int n, bool qc);
 int persistent_max_inst();
-hipError_t persistent_fits(int n_inst, int n, int ldk, bool* fits);
+hipError_t persistent_fits(int n_inst, int n, int ldk, bool qc, bool* fits);
 hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const InstDev* inst, const double* K, const double* sw,
                              const double* t, const double* s, double* x,
                              unsigned long long* xw, PersistOut* out, double tol, int max_iter,
                              int mode, unsigned tag0, unsigned* err, hipEvent_t ev0,
-                             hipEvent_t ev1, long spin_limit);  // < 0: the default
+                             hipEvent_t ev1, long spin_limit,  // < 0: the default
+                             const QcPoint* zp = nullptr);     // renormalised mode
 
 }  // namespace qdse

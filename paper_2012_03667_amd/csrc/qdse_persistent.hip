@@ -33,6 +33,8 @@
 // At the end every workgroup writes its rows of the final iterates, and
 // workgroup 0 the outcome and the branch certificate of every instance into
 // pinned host memory (one synchronisation and no copies for the host).
+// The renormalised mode (template argument QC, below) exchanges the rows'
+// loop sums instead and renormalises after the gather.
 // Every wait is bounded: a workgroup that polls too long stores the solve's
 // tag0 into the error word and every workgroup leaves the loop at its next
 // poll, so the grid always drains (an older value in the error word belongs
@@ -82,6 +84,7 @@ struct PArgs {
   unsigned tag0;
   unsigned* err;
   long spin_limit;  // failed polls of one gather round before the solve is abandoned
+  QcPoint zp;       // renormalised mode: the renormalisation point's node and stencil
 };
 
 __device__ inline unsigned long long tagged(unsigned half, unsigned tag) {
@@ -130,19 +133,31 @@ __host__ __device__ inline size_t node_block(int ldk) {
   return need > (size_t)5 * ldk ? need : (size_t)5 * ldk;
 }
 
+// QC: the renormalised mode (Qin-Chang interaction with its ultraviolet term,
+// renormalisation at zeta). The kernel matrices have n + 1 rows, row n at
+// p^2 = zeta^2 with A and B interpolated there (the stencil of zp); a
+// wavefront publishes its row's loop sums times pref, sigma_A and sigma_B
+// (row n's two after the 2n of the others), and a workgroup that has gathered
+// them forms Z_2 = 1 / (1 + sigma_A(zeta)), Z_4 m = m - Z_2 sigma_B(zeta) (0 at
+// m = 0), A = Z_2 (1 + sigma_A), B = Z_4 m + Z_2 sigma_B: the arithmetic of the
+// kernel-per-sweep renormalised sweep, so both drivers give the same bits.
+template <bool QC>
 __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   extern __shared__ double lds[];
   const int n = a.n, nq = a.nq, ldk = a.ldk, nI = a.n_inst;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
   const int i = blockIdx.x * PROWS + wave;
-  const bool row_ok = i < n;
-  const int ic = row_ok ? i : n - 1;  // rows past the last compute and publish nothing
+  const int rows = QC ? n + 1 : n;
+  const bool row_ok = i < rows;
+  const int ic = row_ok ? i : rows - 1;  // rows past the last compute and publish nothing
+  const bool zrow = QC && ic == n;       // the renormalisation point's row
   const int xl = 2 * n;
+  const int xlw = xl + (QC ? 2 : 0);  // exchanged values per instance (QC: + sigma(zeta))
   // node functions of one instance: five columns, then zeros up to the last
   // index the register-held strides read (row_regs without clamping)
   const size_t ndl = node_block(ldk);
   double* xs = lds;                          // [2][nI][2n]: x_k of instance q at parity k & 1
-  double* ms = xs + (size_t)2 * nI * xl;     // [2][nI][n]: M = B/A of the same iterates
+  double* ms = xs + (size_t)2 * nI * xlw;    // [2][nI][n]: M = B/A of the same iterates
   double* nd = ms + (size_t)2 * nI * n;      // [nI][5][ldk] node functions
   double* wsl = nd + (size_t)nI * ndl;       // [nq][4] stencil weights
   double* tl = wsl + (size_t)4 * nq;         // [nq] loop nodes
@@ -152,14 +167,18 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
   __shared__ int ok, cbits;
 
   // the row's kernel entries, for the whole solve
-  const size_t mat = (size_t)n * ldk;
+  const size_t mat = (size_t)rows * ldk;
   const double* Ki = a.K + (size_t)ic * ldk;
   double kT[ROW_REG], k3[ROW_REG], k0[ROW_REG];
   load_row_regs<ROW_REG>(lane, nq, mat, Ki, kT, k3, k0);
-  const double s = a.s[ic];
+  const double s = zrow ? a.zp.s : a.s[ic];
   for (int e = tid; e < 4 * nq; e += PBLOCK) wsl[e] = a.sw[e];
   for (int e = tid; e < nq; e += PBLOCK) tl[e] = a.t[e];
-  for (int e = tid; e < nI * xl; e += PBLOCK) xs[e] = a.x[e];  // x_0 at parity 0
+  if constexpr (QC) {
+    for (int e = tid; e < nI * xl; e += PBLOCK) xs[(e / xl) * xlw + e % xl] = a.x[e];
+  } else {
+    for (int e = tid; e < nI * xl; e += PBLOCK) xs[e] = a.x[e];  // x_0 at parity 0
+  }
   // node blocks zeroed: the padding between and after the columns is read by
   // the unclamped strides of row_regs (with zero kernel entries)
   for (size_t e = tid; e < (size_t)nI * ndl; e += PBLOCK) nd[e] = 0.0;
@@ -173,7 +192,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
 
   // Node functions of loop node j of instance q's iterate x at parity p.
   auto node = [&](int q, int p, int j) {
-    const double* xq = xs + ((size_t)p * nI + q) * xl;
+    const double* xq = xs + ((size_t)p * nI + q) * xlw;
     const int b = min(max(j - 2, 0), n - 4);
     double w[4], xa[4], xb[4], v[5];
 #pragma unroll
@@ -188,7 +207,7 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
     for (int c = 0; c < 5; ++c) ndq[c * ldk + j] = v[c];
   };
   for (int q = 0; q < nI; ++q) {
-    const double* x0 = xs + (size_t)q * xl;
+    const double* x0 = xs + (size_t)q * xlw;
     for (int j = tid; j < nq; j += PBLOCK) node(q, 0, j);
     for (int ii = tid; ii < n; ii += PBLOCK) ms[(size_t)q * n + ii] = x0[n + ii] / x0[ii];
   }
@@ -245,8 +264,8 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       ky = __builtin_amdgcn_readlane(done_v, y);
 #pragma unroll
       for (int g = 0; g < GATHER_PT; ++g)
-        if (g * PBLOCK + tid < xl) pf_mask |= 1u << g;
-      load_round(a.xw + ((size_t)((ky + 1) & 1) * nI + y) * xl * 2, 0, pf_lo, pf_hi, pf_mask);
+        if (g * PBLOCK + tid < xlw) pf_mask |= 1u << g;
+      load_round(a.xw + ((size_t)((ky + 1) & 1) * nI + y) * xlw * 2, 0, pf_lo, pf_hi, pf_mask);
     }
   };
   while (run) {
@@ -256,16 +275,16 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
     if ((pend >> q) & 1u) {
       // gather x_{k+1} of q
       const unsigned tag = a.tag0 + (unsigned)(k + 1);
-      const unsigned long long* wk = a.xw + ((size_t)((k + 1) & 1) * nI + q) * xl * 2;
-      double* xn = xs + ((size_t)((k + 1) & 1) * nI + q) * xl;
+      const unsigned long long* wk = a.xw + ((size_t)((k + 1) & 1) * nI + q) * xlw * 2;
+      double* xn = xs + ((size_t)((k + 1) & 1) * nI + q) * xlw;
       bool good = true;
       long spins = 0;
-      for (int v0 = 0; v0 < xl && good; v0 += GATHER_PT * PBLOCK) {
+      for (int v0 = 0; v0 < xlw && good; v0 += GATHER_PT * PBLOCK) {
         unsigned long long lo[GATHER_PT], hi[GATHER_PT];
         unsigned pending = 0;
 #pragma unroll
         for (int g = 0; g < GATHER_PT; ++g)
-          if (v0 + g * PBLOCK + tid < xl) pending |= 1u << g;
+          if (v0 + g * PBLOCK + tid < xlw) pending |= 1u << g;
         if (v0 == 0 && pf_q == q) pending &= pf_pend;  // the rest is in LDS already
         while (pending) {
           load_round(wk, v0, lo, hi, pending);
@@ -297,13 +316,22 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       pf_q = -1;
       __syncthreads();
       if (!ok) break;
+      if constexpr (QC) {
+        // the gathered sums of sweep k + 1 into A and B (every thread the
+        // values it gathered, Z_2 and Z_4 m from the two at the end)
+        const double Z2 = 1.0 / (1.0 + xn[xl]);
+        const double mq = s_m[q];
+        const double Z4m = mq == 0.0 ? 0.0 : mq - Z2 * xn[xl + 1];
+        for (int e = tid; e < xl; e += PBLOCK) xn[e] = e < n ? Z2 * (1.0 + xn[e]) : Z4m + Z2 * xn[e];
+        __syncthreads();
+      }
       k += 1;
       pend &= ~(1u << q);
       // statistic of sweep k over all rows (M of x_k kept for the next one)
       // and the node functions of x_k (built before the decision: for an
       // instance that stops here they are not used)
-      const double* xo = xs + ((size_t)((k - 1) & 1) * nI + q) * xl;
-      const double* xq = xs + ((size_t)(k & 1) * nI + q) * xl;
+      const double* xo = xs + ((size_t)((k - 1) & 1) * nI + q) * xlw;
+      const double* xq = xs + ((size_t)(k & 1) * nI + q) * xlw;
       const double* mo = ms + ((size_t)((k - 1) & 1) * nI + q) * n;
       double* mn = ms + ((size_t)(k & 1) * nI + q) * n;
       if (tid == 0) st_max[q][(k + 1) & 1] = 0ull;  // last read at sweep k - 1
@@ -353,19 +381,32 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
     // contraction of this wavefront's row of q from x_k: x_{k+1}, published
     // tagged (lanes 0-3: the halves of A_i and B_i)
     {
-      const double* xq = xs + ((size_t)(k & 1) * nI + q) * xl;
+      const double* xq = xs + ((size_t)(k & 1) * nI + q) * xlw;
       const double* ndq = nd + (size_t)q * ndl;
-      const double Ai = xq[ic], Bi = xq[n + ic];
+      double Ai, Bi;
+      if (zrow) {  // A and B interpolated at the renormalisation point
+        Ai = 0.0;
+        Bi = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          Ai = fma(a.zp.w[l], xq[a.zp.base + l], Ai);
+          Bi = fma(a.zp.w[l], xq[n + a.zp.base + l], Bi);
+        }
+      } else {
+        Ai = xq[ic];
+        Bi = xq[n + ic];
+      }
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       row_regs<ROW_REG, false>(lane, nq, ldk, ndq, kT, k3, k0, s, Ai, Bi, a0, a1, a2, a3);
       if (nq > ROW_REG * WAVE)
         row_stream_f64(lane + ROW_REG * WAVE, nq, ldk, mat, Ki, ndq, s, Ai, Bi, a0, a1, a2, a3);
       wave_sum4(a0, a1, a2, a3);
-      const double An = 1.0 + s_pref[q] * (a1 - a0);
-      const double Bn = s_m[q] + s_pref[q] * fma(2.0 * s, a2, a3);
+      // published: A and B, or (QC) the sums times pref
+      const double An = (QC ? 0.0 : 1.0) + s_pref[q] * (a1 - a0);
+      const double Bn = (QC ? 0.0 : s_m[q]) + s_pref[q] * fma(2.0 * s, a2, a3);
       if (y >= 0) {  // take the next instance's words that have arrived
         const unsigned tag = a.tag0 + (unsigned)(ky + 1);
-        double* xy = xs + ((size_t)((ky + 1) & 1) * nI + y) * xl;
+        double* xy = xs + ((size_t)((ky + 1) & 1) * nI + y) * xlw;
         pf_pend = pf_mask;
 #pragma unroll
         for (int g = 0; g < GATHER_PT; ++g) {
@@ -380,10 +421,10 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
       }
       if (row_ok && lane < 4) {
         const unsigned tag = a.tag0 + (unsigned)(k + 1);
-        unsigned long long* wk = a.xw + ((size_t)((k + 1) & 1) * nI + q) * xl * 2;
+        unsigned long long* wk = a.xw + ((size_t)((k + 1) & 1) * nI + q) * xlw * 2;
         const unsigned long long bits = bits_of(lane < 2 ? An : Bn);
         const unsigned half = (lane & 1) ? (unsigned)(bits >> 32) : (unsigned)bits;
-        const int e = lane < 2 ? i : n + i;
+        const int e = zrow ? (lane < 2 ? xl : xl + 1) : (lane < 2 ? i : n + i);
         __hip_atomic_store(wk + 2 * e + (lane & 1), tagged(half, tag), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -405,15 +446,15 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
     }
     if (ii < n) {
       const int col = (r & 1) ? n + ii : ii;
-      a.x[(size_t)qq * xl + col] = xs[((size_t)(kq & 1) * nI + qq) * xl + col];
+      a.x[(size_t)qq * xl + col] = xs[((size_t)(kq & 1) * nI + qq) * xlw + col];
     }
   }
   if (blockIdx.x != 0) return;
   // outcome and branch certificate of every instance (workgroup 0)
   for (int qq = 0; qq < nI; ++qq) {
     const int kq = __builtin_amdgcn_readlane(done_v, qq);
-    const double* xf = xs + ((size_t)(kq & 1) * nI + qq) * xl;
-    const int cb = certify_block(n, 1, xf, xf + n, red, &cbits);
+    const double* xf = xs + ((size_t)(kq & 1) * nI + qq) * xlw;
+    const int cb = certify_block(n, QC ? 0 : 1, xf, xf + n, red, &cbits);
     if (tid == 0) a.out->cert[qq] = cb;
   }
   if (tid < nI) {
@@ -431,20 +472,23 @@ __global__ void __launch_bounds__(PBLOCK) k_persistent(PArgs a) {
 
 }  // namespace
 
-size_t persistent_lds_bytes(int n_inst, int n, int ldk) {
+size_t persistent_lds_bytes(int n_inst, int n, int ldk, bool qc) {
   const size_t nq = (size_t)n + 1;
-  return ((size_t)2 * n_inst * 3 * n + (size_t)n_inst * node_block(ldk) + 5 * nq) * sizeof(double);
+  return ((size_t)2 * n_inst * (3 * n + (qc ? 2 : 0)) + (size_t)n_inst * node_block(ldk) + 5 * nq) *
+         sizeof(double);
 }
 
-size_t persistent_words(int n_inst, int n) { return (size_t)2 * n_inst * 2 * n * 2; }
+size_t persistent_words(int n_inst, int n, bool qc) {
+  return (size_t)2 * n_inst * (2 * n + (qc ? 2 : 0)) * 2;
+}
 
-int persistent_blocks(int n) { return (n + PROWS - 1) / PROWS; }
+int persistent_blocks(int n, bool qc) { return (n + (qc ? 1 : 0) + PROWS - 1) / PROWS; }
 
 int persistent_max_inst() { return PMAX_INST; }
 
 // Whether the single-launch solve of n_inst instances on an n-row grid fits:
 // LDS within the device's limit and ceil(n / 4) workgroups co-resident.
-hipError_t persistent_fits(int n_inst, int n, int ldk, bool* fits) {
+hipError_t persistent_fits(int n_inst, int n, int ldk, bool qc, bool* fits) {
   *fits = false;
   if (n_inst < 1 || n_inst > PMAX_INST || n < 4) return hipSuccess;
   int dev = 0, ncu = 0, occ = 0, lds_max = 0;
@@ -454,14 +498,14 @@ hipError_t persistent_fits(int n_inst, int n, int ldk, bool* fits) {
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = persistent_lds_bytes(n_inst, n, ldk);
+  const size_t lds = persistent_lds_bytes(n_inst, n, ldk, qc);
   if (lds + 1024 > (size_t)lds_max) return hipSuccess;
-  e = hipFuncSetAttribute((const void*)k_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds);
+  const void* kern = qc ? (const void*)k_persistent<true> : (const void*)k_persistent<false>;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_persistent, PBLOCK, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, PBLOCK, lds);
   if (e != hipSuccess) return e;
-  *fits = (long)occ * ncu >= persistent_blocks(n);
+  *fits = (long)occ * ncu >= persistent_blocks(n, qc);
   return hipSuccess;
 }
 
@@ -474,14 +518,16 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
                              const double* t, const double* s, double* x,
                              unsigned long long* xw, PersistOut* out, double tol, int max_iter,
                              int mode, unsigned tag0, unsigned* err, hipEvent_t ev0,
-                             hipEvent_t ev1, long spin_limit) {
+                             hipEvent_t ev1, long spin_limit, const QcPoint* zp) {
   if (n_inst < 1 || n_inst > PMAX_INST || n < 4 || nq != n + 1 || max_iter < 0)
     return hipErrorInvalidValue;
+  const bool qc = zp != nullptr;
+  if (qc && (zp->base < 0 || zp->base > n - 4)) return hipErrorInvalidValue;
   PArgs a{n_inst, n, nq, ldk, inst, K, sw, t, s, x, xw, out, tol, max_iter, mode, tag0, err,
-          spin_limit < 0 ? SPIN_LIMIT : spin_limit};
-  const size_t lds = persistent_lds_bytes(n_inst, n, ldk);
-  hipError_t e = hipFuncSetAttribute((const void*)k_persistent,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          spin_limit < 0 ? SPIN_LIMIT : spin_limit, qc ? *zp : QcPoint{}};
+  const size_t lds = persistent_lds_bytes(n_inst, n, ldk, qc);
+  const void* kern = qc ? (const void*)k_persistent<true> : (const void*)k_persistent<false>;
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   void* args[] = {&a};
   // events (may be null) recorded on the stream just before and after the
@@ -493,8 +539,7 @@ hipError_t launch_persistent(hipStream_t st, int n_inst, int n, int nq, int ldk,
     e = hipEventRecord(ev0, st);
     if (e != hipSuccess) return e;
   }
-  e = hipLaunchKernel((const void*)k_persistent, dim3(persistent_blocks(n)), dim3(PBLOCK), args,
-                      lds, st);
+  e = hipLaunchKernel(kern, dim3(persistent_blocks(n, qc)), dim3(PBLOCK), args, lds, st);
   if (e != hipSuccess || !ev1) return e;
   return hipEventRecord(ev1, st);
 }
