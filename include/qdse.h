@@ -427,11 +427,8 @@ int qdse_mu_iterate(qdse_mu_ctx* ctx, const double* d_x_in, double* d_x_out);
 
 /* Successive approximation from d_x until max |F' - F| over the three
  * functions and the grid (complex modulus) < tol for every instance, or
- * max_iter sweeps. An instance whose statistic, from sweep 30 on, exceeds
- * 100 times the smallest it had is stopped there (successive approximation
- * diverges from it) and keeps its last iterate. iters, resid: host [n_inst]
- * (may be NULL). Returns the most severe outcome: QDSE_OK,
- * QDSE_NOT_CONVERGED, QDSE_EDIVERGED or QDSE_ENAN. Synchronises the stream. */
+ * max_iter sweeps. iters, resid: host [n_inst] (may be NULL). Returns QDSE_OK,
+ * QDSE_NOT_CONVERGED or QDSE_ENAN. Synchronises the stream. */
 int qdse_mu_solve(qdse_mu_ctx* ctx, double* d_x, double tol, int max_iter, int* iters,
                   double* resid);
 

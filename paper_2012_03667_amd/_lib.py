@@ -413,7 +413,7 @@ def mu_solve_group(solvers, xs, tol=1e-10, max_iter=500):
     I = (_ip * n)(*[a.ctypes.data_as(_ip) for a in its])
     R = (_dp * n)(*[a.ctypes.data_as(_dp) for a in rss])
     rc = load().qdse_mu_solve_group(H, n, X, float(tol), int(max_iter), I, R)
-    _check(rc, "qdse_mu_solve_group", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN, QDSE_EDIVERGED))
+    _check(rc, "qdse_mu_solve_group", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
     return rc, its, rss
 
 
@@ -477,7 +477,7 @@ class MuSolver:
             rc = load().qdse_mu_solve_anderson(self._h, self._cdev(x, "x"), float(tol),
                                                int(max_iter), int(anderson),
                                                it.ctypes.data_as(_ip), rs.ctypes.data_as(_dp))
-        _check(rc, "qdse_mu_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN, QDSE_EDIVERGED))
+        _check(rc, "qdse_mu_solve", allow=(QDSE_OK, QDSE_NOT_CONVERGED, QDSE_ENAN))
         return rc, it, rs
 
 

@@ -197,32 +197,14 @@ static int mu_sweep(qdse_mu_ctx* c, const double* in, double* out, const std::ve
 // several contexts (grid classes) can run on their own streams together:
 // enqueue() puts one sweep of the running instances and its statistic on the
 // stream, collect() waits for it and freezes the instances that passed.
-// Divergence (the vacuum drivers' rule): from sweep kMuDivergeAfter on, an
-// instance whose statistic exceeds kMuDivergeFactor times the smallest one it
-// had is stopped (copied forward like a converged one) and reported as
-// QDSE_EDIVERGED.
-constexpr int kMuDivergeAfter = 30;
-constexpr double kMuDivergeFactor = 100.0;
-
-// Outcome order of a batch (most severe last), as for the vacuum solves.
-static int mu_severity(int code) {
-  switch (code) {
-    case QDSE_OK: return 0;
-    case QDSE_NOT_CONVERGED: return 1;
-    case QDSE_EDIVERGED: return 3;
-    case QDSE_ENAN: return 4;
-    default: return 5;
-  }
-}
-
 struct MuRun {
   qdse_mu_ctx* c = nullptr;
   double* d_x = nullptr;
   double tol = 0.0;
   int max_iter = 0, k = 0, cur = 0, rc = QDSE_OK;
   bool finished = false;
-  std::vector<int> done, it;  // done: 1 converged, 2 diverged (both stop)
-  std::vector<double> res, rmin;
+  std::vector<int> done, it;
+  std::vector<double> res;
 
   int begin(qdse_mu_ctx* c_, double* d_x_, double tol_, int max_iter_) {
     c = c_;
@@ -236,7 +218,6 @@ struct MuRun {
     done.assign(c->n_inst, 0);
     it.assign(c->n_inst, 0);
     res.assign(c->n_inst, INFINITY);
-    rmin.assign(c->n_inst, INFINITY);
     if (hipMemcpyAsync(c->d_xb[0], d_x, mu_xlen(c) * sizeof(double), hipMemcpyDeviceToDevice,
                        c->stream) != hipSuccess)
       return QDSE_EDEVICE;
@@ -260,33 +241,23 @@ struct MuRun {
   int collect() {
     if (hipEventSynchronize(c->ev) != hipSuccess) return QDSE_EDEVICE;
     cur ^= 1;
-    bool all = true, bad = false, div = false;
+    bool all = true, bad = false;
     for (int q = 0; q < c->n_inst; ++q) {
       double r;
       std::memcpy(&r, &c->h_stat[q], sizeof(double));
       if (!done[q]) {
         it[q] = k;
         res[q] = r;
-        if (!(r <= 1.7976931348623157e308)) {
-          bad = true;
-        } else if (r < tol) {
-          done[q] = 1;  // frozen (copied forward) from the next sweep on
-        } else {
-          if (r < rmin[q]) rmin[q] = r;
-          if (k >= kMuDivergeAfter && r > kMuDivergeFactor * rmin[q]) done[q] = 2;
-        }
+        if (!(r <= 1.7976931348623157e308)) bad = true;
+        else if (r < tol) done[q] = 1;  // frozen (copied forward) from the next sweep on
       }
       if (!done[q]) all = false;
-      if (done[q] == 2) div = true;
     }
-    if (bad) {
-      rc = QDSE_ENAN;
-      finished = true;
-    } else if (all) {
-      rc = div ? QDSE_EDIVERGED : QDSE_OK;
+    if (all || bad) {
+      rc = bad ? QDSE_ENAN : QDSE_OK;
       finished = true;
     } else if (k == max_iter) {
-      rc = div ? QDSE_EDIVERGED : QDSE_NOT_CONVERGED;
+      rc = QDSE_NOT_CONVERGED;
       finished = true;
     }
     return QDSE_OK;
@@ -348,7 +319,8 @@ int qdse_mu_solve_group(qdse_mu_ctx** ctxs, int n_ctx, double** d_x, double tol,
   int worst = QDSE_OK;
   for (int q = 0; q < n_ctx; ++q) {
     const int rc = R[q].end(iters ? iters[q] : nullptr, resid ? resid[q] : nullptr);
-    if (mu_severity(rc) > mu_severity(worst)) worst = rc;
+    if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
+    else if (rc > 0 && worst == QDSE_OK) worst = rc;
   }
   return worst;
 }

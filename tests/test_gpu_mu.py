@@ -95,33 +95,6 @@ def test_mu_sweep_long_grids_sampled_rows(Q, ns, n4, na, T):
         assert rel(y[f, rows], ref[f]) < RTOL, (f, rel(y[f, rows], ref[f]))
 
 
-def test_mu_group_solve_stops_a_diverging_instance(Q):
-    """Two grid classes of the mixed workload's mu > 0 instances solved
-    together: successive approximation diverges for the first (32^2 external
-    points, 128 angles, m = 0.1215 GeV, mu = 0.1506 GeV: its statistic grows
-    without bound), which is stopped once its statistic exceeds 100 times its
-    smallest value (from sweep 30 on) instead of running to the sweep cap; the
-    second (64^2, 64 angles) converges as before. The batch reports
-    QDSE_EDIVERGED, its most severe outcome."""
-    print("case mu divergence stop", flush=True)
-    Sd = Q.MuSolver(32, 32, 128, [(0.55, 0.678, 0.1215, 0.1506)], stream=torch.cuda.Stream())
-    Sc = Q.MuSolver(64, 64, 64, [(0.55, 0.678, 0.1743, 0.2176)], stream=torch.cuda.Stream())
-    xs = []
-    for S in (Sd, Sc):
-        x = torch.zeros(S.shape, dtype=torch.complex128, device="cuda")
-        x[:, 0] = 1.0
-        x[:, 1] = 0.3
-        x[:, 2] = 1.0
-        xs.append(x)
-    rc, its, rss = Q.mu_solve_group([Sd, Sc], xs, tol=1e-8, max_iter=600)
-    torch.cuda.synchronize()
-    assert rc == Q.QDSE_EDIVERGED, rc
-    assert 30 <= int(its[0][0]) < 150 and rss[0][0] > 1e-8, (its[0], rss[0])
-    assert rss[1][0] < 1e-8, (its[1], rss[1])
-    Sd.close()
-    Sc.close()
-
-
 def test_mu_solve_matches_oracle_picard(Q):
     ns, n4, na, mu = 8, 8, 6, 0.25
     kw = dict(r_min=1e-2, r_max=8.0, p4_max=8.0)
