@@ -72,7 +72,7 @@ constexpr int DIVERGE_AFTER = 30;
 struct PArgs {
   int n_inst, n, nq, ldk;
   const InstDev* inst;
-  const double* K;   // kernel block shared by every instance: [3][n][ldk]
+  const double* K;   // kernel block shared by every instance: [3][rows][ldk]
   const double* sw;  // stencil weights [nq][4]; base clamp(j - 2, 0, n - 4)
   const double* t;   // loop nodes
   const double* s;   // external nodes
@@ -487,7 +487,8 @@ int persistent_blocks(int n, bool qc) { return (n + (qc ? 1 : 0) + PROWS - 1) / 
 int persistent_max_inst() { return PMAX_INST; }
 
 // Whether the single-launch solve of n_inst instances on an n-row grid fits:
-// LDS within the device's limit and ceil(n / 4) workgroups co-resident.
+// LDS within the device's limit and ceil(rows / 8) workgroups co-resident
+// (rows = n, or n + 1 in the renormalised mode).
 hipError_t persistent_fits(int n_inst, int n, int ldk, bool qc, bool* fits) {
   *fits = false;
   if (n_inst < 1 || n_inst > PMAX_INST || n < 4) return hipSuccess;
