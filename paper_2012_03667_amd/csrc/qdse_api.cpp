@@ -761,6 +761,13 @@ static long predict_total(MaskedRun& r) {
 }
 
 // *over: the phase has ended (every instance frozen, or the sweep limit).
+// Whether masked_wait would return without blocking (the oldest chunk in
+// flight has completed, or there is none and it reports the error).
+static bool masked_ready(const MaskedRun& r) {
+  if (r.nq == 0) return true;
+  return hipEventQuery(r.c->ev[r.q_ev[0]]) != hipErrorNotReady;
+}
+
 static int masked_wait(MaskedRun& r, bool* over) {
   qdse_ctx* c = r.c;
   if (r.nq == 0) return QDSE_EINVAL;
@@ -1004,11 +1011,19 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
     int rc = group_phase_begin(g, tol, max_iter, conv_mode);
     if (rc) return rc;
   }
+  // The host serves whichever context's oldest chunk has completed (a
+  // blocking wait on one context in turn left the others' queues to drain);
+  // after 50 ms without a completed chunk it blocks on the first pending one.
+  auto idle_since = std::chrono::steady_clock::now();
   for (;;) {
     bool any = false;
+    const bool block =
+        std::chrono::steady_clock::now() - idle_since > std::chrono::milliseconds(50);
     for (GroupEntry& g : G) {
       if (g.phase == 2) continue;
       any = true;
+      if (!block && !masked_ready(g.run)) continue;
+      idle_since = std::chrono::steady_clock::now();
       bool over = false;
       int rc = masked_wait(g.run, &over);
       if (rc) return rc;
