@@ -12,9 +12,9 @@
 //     A'(p^2) = 1 + C_F/(8 pi^3) sum_q sum_angle  W g(k^2) I_A / Delta_q
 //     B'(p^2) = m + C_F/(8 pi^3) sum_q sum_angle  W g(k^2) I_B / Delta_q
 // evaluated for every external momentum by a direct double sum over the loop
-// radial nodes and the angular nodes, as the paper's functionA / functionB do
-// (Sec. III, Listing 1), with an OpenMP parallel-for over external momenta
-// (Sec. III, Listing 2). No angular kernel is precomputed.
+// radial nodes and the angular nodes, one projection at a time (Sec. III), with
+// an OpenMP parallel-for over external momenta for the parallel programs that
+// Table 1 times. No angular kernel is precomputed.
 //
 // Readings of the paper taken here (each is also listed in the design notes):
 //  * g(k^2) = G(k^2)/k^2 = (8 pi^2/omega^4) D exp(-k^2/omega^2): the Gaussian
@@ -258,7 +258,7 @@ void vac_map(const qo_vac_grid* g, const qo_vac_par* par, const T* x, T* out,
   }
 }
 
-// The map as the paper organises it (Sec. III, Listing 1 / Listing 2): for
+// The map as the paper organises it (Sec. III, Table 1's programs): for
 // every external momentum, functionA and functionB each run the whole radial x
 // angular sum, and A(q^2), B(q^2) are interpolated where the integrand needs
 // them, inside the angular loop. Traditional interpolation (Sec. III A) finds
@@ -317,8 +317,8 @@ int qo_vac_map(const qo_vac_grid* g, const qo_vac_par* par, const double* x_in,
 
 // Rows rows[0..nrows-1] of F(x_in): out[r] = A'(rows[r]), out[nrows+r] = B'.
 // One sweep in the paper's organisation (see paper_function): modified = 0
-// traditional interpolation, 1 modified; nthreads = 1 sequential (Listing 1),
-// more: OpenMP over external momenta (Listing 2).
+// traditional interpolation, 1 modified; nthreads = 1 sequential, more: OpenMP
+// over external momenta (Table 1's algorithms 1-2 and 3-4).
 int qo_vac_map_paper(const qo_vac_grid* g, const qo_vac_par* par, const double* x_in,
                      double* x_out, int modified, int nthreads) {
   if (check_grid(g) || !par || !x_in || !x_out || nthreads < 1) return -1;

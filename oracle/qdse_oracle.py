@@ -7,7 +7,7 @@ code with the HIP library.
 
 The map itself (one successive-approximation sweep, Sec. II eqs. dsesys and
 dsesys2, evaluated by direct radial x angular Gauss-Legendre sums as in Sec. III
-Listing 1/2) lives in ``qdse_oracle.cpp``; this module builds the grids, loads
+and Table 1) lives in ``qdse_oracle.cpp``; this module builds the grids, loads
 that library through ctypes and drives it:
 
 * ``picard``: successive approximation (Sec. I eq. jifen12) with the paper's
@@ -267,8 +267,8 @@ def F_paper(g: VacGrid, p: Params, x: np.ndarray, modified: bool, nthreads: int 
     """One sweep organised as the paper's code (Sec. III): functionA and
     functionB per external momentum, interpolation inside the loops, with the
     traditional bracket search (modified = False) or the bracket from eq.
-    pqrelationship (modified = True); nthreads = 1 is Listing 1, more is
-    Listing 2. Table 1's algorithms 1-4 are (False, 1), (True, 1), (False, P),
+    pqrelationship (modified = True); nthreads = 1 is sequential, more runs
+    OpenMP over external momenta. Table 1's algorithms 1-4 are (False, 1), (True, 1), (False, P),
     (True, P). Same values as F."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     assert x.shape == (2 * g.n,)

@@ -286,7 +286,7 @@ def test_constant_inputs_kill_difference_terms():
 
 
 def test_openmp_rows_bitwise_equal_sequential():
-    """Rows are independent (Sec. III, Listings 1 and 2): any thread count gives
+    """Rows are independent (Sec. III, Table 1's sequential and OpenMP programs): any thread count gives
     the same bits."""
     g = O.vac_grid(64, 32)
     x = rand_x(64)
