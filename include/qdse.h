@@ -106,8 +106,13 @@ enum {
 enum {
   QDSE_FP64 = 0,         /* FP64 throughout (direct difference form)          */
   QDSE_FP32_REFINE = 1,  /* FP32 MFMA contraction with FP32 accumulation for
-                            the sweeps, then FP64 matrix-core sweeps until
-                            the test holds                                   */
+                            the sweeps, then the refinement until the test
+                            holds: one FP64 matrix-core sweep stores the
+                            products at the FP32 result (the reference),
+                            and further sweeps contract the node-column
+                            differences from it in FP32, added to those
+                            FP64 products (environment QDSE_REFINE_FP64=1:
+                            FP64 matrix-core sweeps instead)              */
   QDSE_FP64_MATRIX = 2   /* FP64 MFMA contraction (split form) for batches    */
 };
 
@@ -286,9 +291,10 @@ int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double l
 int qdse_solve_kernel_us(const qdse_ctx* ctx, double* us);
 
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may
- * be NULL): FP32 matrix-core sweeps (QDSE_FP32_REFINE contexts) and FP64
- * sweeps. The FP32 phase stops at max(tol, 1e-5) on the same test; the FP64
- * phase (matrix-core split form) then runs to tol. */
+ * be NULL): sweeps of the FP32 phase (QDSE_FP32_REFINE contexts) and of the
+ * final phase (QDSE_FP32_REFINE: the refinement, its FP64 reference sweep
+ * included; otherwise every sweep). The FP32 phase stops at max(tol, 1e-5)
+ * on the same test; the refinement then runs to tol. */
 int qdse_solve_stats(const qdse_ctx* ctx, int* sweeps_fp32, int* sweeps_fp64);
 
 /* Jacobian-vector product d_jv = (dF/dx)(d_x) d_v for every instance (FP64,

@@ -148,6 +148,11 @@ struct qdse_ctx {
   float* d_C32 = nullptr;
   double* d_M64 = nullptr;
   double* d_C64 = nullptr;
+  // refinement of FP32 by differences: the reference iterate [n_inst][2n] and
+  // the FP64 products there, [6][ldi][ldb] (MmDelta)
+  double* d_xref = nullptr;
+  double* d_rq = nullptr;
+  int ref_sweeps = 0;  // FP64 reference sweeps of the last solve (0 or 1)
   std::vector<int> last_sweeps32, last_sweeps64;
   InstDev* d_inst = nullptr;
   double* d_nodes = nullptr;  // [n_inst][10][ldk]
@@ -162,7 +167,7 @@ struct qdse_ctx {
   double* d_sig = nullptr;  // [n_inst][2 (n + 1)]
   // graph of a chunk of masked sweeps; pinned copies of the solve state of
   // the last two chunks, with their completion events
-  std::vector<std::pair<int, hipGraphExec_t>> graphs[4];  // per sweep kind: (length, graph)
+  std::vector<std::pair<int, hipGraphExec_t>> graphs[5];  // per sweep kind: (length, graph)
   int chunk = 24;       // sweeps per graph launch, FP64 direct sweeps (multiple of 6)
   int chunk_mm = 12;    // the same for matrix-core sweeps (masked sweeps cost more)
   int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
@@ -412,7 +417,8 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
     if (e == hipSuccess)
       e = launch_build_mm<double>(st, g.n, g.nq, g.ldk, L, c->d_K, c->d_s, c->d_t, c->d_M64);
     if (e == hipSuccess && precision == QDSE_FP32_REFINE) {
-      if (dalloc(&c->d_M32, 5 * L.mstride) || dalloc(&c->d_C32, 6 * L.cstride)) {
+      if (dalloc(&c->d_M32, 5 * L.mstride) || dalloc(&c->d_C32, 6 * L.cstride) ||
+          dalloc(&c->d_xref, xlen(c)) || dalloc(&c->d_rq, 6 * (size_t)L.ldi * L.ldb)) {
         qdse_destroy(c);
         return QDSE_ENOMEM;
       }
@@ -488,7 +494,8 @@ void qdse_destroy(qdse_ctx* c) {
                   c->d_inst,    c->d_nodes,   c->d_xbuf[0], c->d_xbuf[1], c->d_state,
                   c->d_ctl,     c->d_part,    c->d_gq,      c->d_xw,      c->d_perr,
                   c->d_C32,     c->d_M64,     c->d_C64,     c->d_tstate,
-                  c->d_tctl,    c->d_sK,      c->d_sig,     c->d_jdiag};
+                  c->d_tctl,    c->d_sK,      c->d_sig,     c->d_jdiag,   c->d_xref,
+                  c->d_rq};
   for (void* p : ptrs) dfree(p);
   c->kw.release();
   delete c;
@@ -579,8 +586,9 @@ int qdse_iterate_fp64_matrix(qdse_ctx* c, const double* d_x_in, double* d_x_out)
   return QDSE_OK;
 }
 
-// Sweep kinds of a masked run.
-enum { SWEEP_DIRECT = 0, SWEEP_MM32 = 1, SWEEP_MM64 = 2, SWEEP_QC = 3 };
+// Sweep kinds of a masked run (SWEEP_MM32D: FP32 matrix-core sweeps of the
+// node-column differences from the context's reference iterate).
+enum { SWEEP_DIRECT = 0, SWEEP_MM32 = 1, SWEEP_MM64 = 2, SWEEP_QC = 3, SWEEP_MM32D = 4 };
 
 static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
   const HostGrid& g = c->hg;
@@ -588,10 +596,15 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
     const int p = k & 1;  // sweep k reads xbuf[(k-1)%2] and writes xbuf[k%2]
     const double* xi = c->d_xbuf[p ^ 1];
     double* xo = c->d_xbuf[p];
-    if (kind == SWEEP_MM32) {
+    if (kind == SWEEP_MM32 || kind == SWEEP_MM32D) {
+      MmDelta d;
+      if (kind == SWEEP_MM32D) {
+        d.x_ref = c->d_xref;
+        d.rq = c->d_rq;
+      }
       HIPCHK(launch_sweep_mm<float>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M32, c->d_C32, c->d_inst,
                                     c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo, c->d_state, c->d_ctl,
-                                    k, true));
+                                    k, true, nullptr, nullptr, &d));
     } else if (kind == SWEEP_MM64) {
       HIPCHK(launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64, c->d_C64,
                                      c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo,
@@ -862,8 +875,9 @@ static int finish_outcome(qdse_ctx* c, const std::vector<SolveState>& hs,
     else if (h.status == 1) code = cert[k] ? QDSE_ESPURIOUS : QDSE_OK;
     else code = (k < (int)diverged.size() && diverged[k]) ? QDSE_EDIVERGED : QDSE_NOT_CONVERGED;
     c->last_status[k] = code;
-    c->last_sweeps64[k] = h.sweeps;
-    c->last_evals[k] = h.sweeps + (k < (int)c->last_sweeps32.size() ? c->last_sweeps32[k] : 0);
+    c->last_sweeps64[k] = h.sweeps + c->ref_sweeps;
+    c->last_evals[k] = c->last_sweeps64[k] +
+                       (k < (int)c->last_sweeps32.size() ? c->last_sweeps32[k] : 0);
     if (iters) iters[k] = c->last_evals[k];
     if (resid) resid[k] = h.resid;
   }
@@ -986,14 +1000,38 @@ struct GroupEntry {
 int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
   qdse_ctx* c = g.c;
   if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
-    // switch to FP64 sweeps below this change: the refinement needs about
-    // twenty FP64 sweeps from anywhere below ~1e-5, because the FP32 fixed
-    // point itself is ~1e-5 away (broadband rounding error of the FP32
-    // contraction, which a few extra FP32 sweeps cannot remove)
+    // switch to the refinement below this change: it needs about twenty
+    // sweeps from anywhere below ~1e-5, because the FP32 fixed point itself
+    // is ~1e-5 away (broadband rounding error of the FP32 contraction, which
+    // a few extra FP32 sweeps cannot remove)
     double tol32 = 1e-5;
     if (const char* e = std::getenv("QDSE_FP32_TOL")) tol32 = std::atof(e);
     if (tol32 < tol) tol32 = tol;
     return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32, g.d_x, nullptr);
+  }
+  if (g.phase == 1 && c->precision == QDSE_FP32_REFINE) {
+    const char* e = std::getenv("QDSE_REFINE_FP64");
+    if (!(e && e[0] == '1')) {
+      // Refinement by differences: the FP32 phase's result becomes the
+      // reference; one FP64 sweep from it stores the products there (and is
+      // the phase's first sweep), then FP32 sweeps contract only the
+      // node-column differences from the reference. Their rounding error
+      // scales with the differences (~1e-5 of the columns), so the phase
+      // converges to the FP64 fixed point within ~1e-10 while every sweep
+      // but the first runs at the FP32 rate.
+      const HostGrid& hg = c->hg;
+      HIPCHK(hipMemcpyAsync(c->d_xref, c->d_xbuf[0], xlen(c) * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream));
+      MmDelta d;
+      d.rq_out = c->d_rq;
+      HIPCHK(launch_sweep_mm<double>(c->stream, c->n_inst, hg.n, hg.nq, c->mm, c->d_M64,
+                                     c->d_C64, c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s,
+                                     c->d_xref, c->d_xbuf[0], nullptr, nullptr, 1, true, nullptr,
+                                     nullptr, &d));
+      c->ref_sweeps = 1;
+      return masked_begin(g.run, c, tol, std::max(max_iter - 1, 1), conv_mode, SWEEP_MM32D,
+                          nullptr, g.d_x);
+    }
   }
   const int kind = c->qc                         ? SWEEP_QC
                    : c->precision == QDSE_FP64 ? SWEEP_DIRECT
@@ -1008,6 +1046,7 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
     c->last_sweeps32.assign(c->n_inst, 0);
     c->last_sweeps64.assign(c->n_inst, 0);
     c->fp32_state_pending = 0;
+    c->ref_sweeps = 0;
     int rc = group_phase_begin(g, tol, max_iter, conv_mode);
     if (rc) return rc;
   }
@@ -1963,6 +2002,7 @@ int qdse_autotune(qdse_ctx* c, int reps, const char* cache_path, int* fused_rows
   if (mm) {
     c->mm.rh = best == 1 ? 1 : 2;
     drop_graphs(c, SWEEP_MM32);
+    drop_graphs(c, SWEEP_MM32D);
     drop_graphs(c, SWEEP_MM64);
   } else if (!c->qc) {
     c->fused_rows = (best == 8 || best == 16) ? best : 4;

@@ -220,14 +220,27 @@ MmLayout mm_layout(int n, int nq, int n_inst);
 template <class T>
 hipError_t launch_build_mm(hipStream_t st, int n, int nq, int ldk, const MmLayout& L,
                            const double* K, const double* s, const double* t, T* MT);
+// Refinement by differences from a reference iterate x_ref ([n_inst][2n]):
+// rq ([6][ldi][ldb] doubles) holds the FP64 products at x_ref in the form that
+// makes a row's update affine in its own A_i, B_i. A sweep with rq_out set
+// (x_ref, rq null) writes them; a sweep with x_ref and rq set contracts only
+// the node-column differences c(x) - c(x_ref) and adds them.
+struct MmDelta {
+  const double* x_ref = nullptr;
+  const double* rq = nullptr;
+  double* rq_out = nullptr;
+};
 // nodes = false skips the node-column kernel (columns already built); ev0/ev1
-// time the contraction kernel's dispatch as in launch_sweep_fused.
+// time the contraction kernel's dispatch as in launch_sweep_fused; delta as
+// above (nullptr: the plain sweep). hipErrorInvalidValue for an inconsistent
+// delta (x_ref without rq or the reverse, or rq with rq_out).
 template <class T>
 hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLayout& L,
                            const T* MT, T* C, const InstDev* inst, const int* lo, const double* sw,
                            const double* t, const double* s, const double* x_in, double* x_out,
                            SolveState* state, const SolveCtl* ctl, int k, bool nodes,
-                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                           const MmDelta* delta = nullptr);
 
 // Finite-mu sweep (qdse_mu.hip); x, L complex interleaved.
 // Per-instance constants of a finite-mu sweep: mu, the interaction's

@@ -161,13 +161,16 @@ __device__ inline int decide_mm(SolveState* st, const SolveCtl* ctl, int k, bool
 // masked-run decision of the previous sweep. A block covers 32 loop nodes x
 // 32 instances: threads compute with j fastest (the interpolation stencils
 // read the iterate contiguously), the six columns pass through LDS, and the
-// stores run in C's order (contiguous runs of 32 VW values).
+// stores run in C's order (contiguous runs of 32 VW values). With x_ref, the
+// columns are the differences c(x) - c(x_ref), formed in FP64 before the
+// conversion to T.
 template <class T>
 __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int ldb,
                                                   const int* __restrict__ lo,
                                                   const double* __restrict__ sw,
                                                   const double* __restrict__ t,
                                                   const double* __restrict__ x,
+                                                  const double* __restrict__ x_ref,
                                                   T* __restrict__ C, size_t cstride,
                                                   SolveState* state, const SolveCtl* ctl, int k) {
   __shared__ T tile[6][32][33];
@@ -197,12 +200,23 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
     }
     const double Dl = t[j] * Aq * Aq + Bq * Bq;
     const double sV = Aq / Dl, sS = Bq / Dl;
-    tile[0][bb][jj] = (T)(sV * Aq);
-    tile[1][bb][jj] = (T)sV;
-    tile[2][bb][jj] = (T)(sS * Bq);
-    tile[3][bb][jj] = (T)sS;
-    tile[4][bb][jj] = (T)(sV * Bq);
-    tile[5][bb][jj] = (T)(sS * Aq);
+    double cy[6] = {sV * Aq, sV, sS * Bq, sS, sV * Bq, sS * Aq};
+    if (x_ref) {
+      const double* xR = x_ref + (size_t)inst * 2 * n;
+      double Ar = 0.0, Br = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        Ar = fma(w[l], xR[b + l], Ar);
+        Br = fma(w[l], xR[n + b + l], Br);
+      }
+      const double Dr = t[j] * Ar * Ar + Br * Br;
+      const double rV = Ar / Dr, rS = Br / Dr;
+      const double cr[6] = {rV * Ar, rV, rS * Br, rS, rV * Br, rS * Ar};
+#pragma unroll
+      for (int y = 0; y < 6; ++y) cy[y] -= cr[y];
+    }
+#pragma unroll
+    for (int y = 0; y < 6; ++y) tile[y][bb][jj] = (T)cy[y];
   }
   __syncthreads();
   // stored order C[y][j / VW][inst][j % VW]: node within the block fastest,
@@ -220,12 +234,24 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
 
 // RH: row groups of 16 rows per workgroup (they share the node-column panel);
 // 1 or 2, chosen per context (MmLayout::rh, qdse_autotune).
+// Refinement by differences: rq_out (FP64 sweep at the reference iterate)
+// receives, per row and instance, the six coefficients that make the update
+// affine in the row's own A_i, B_i at the reference products P:
+//   A' = a0 + A_i a1 + B_i a2,  a0 = 1 + pref (P0 - 2 P2), a1 = pref P1,
+//   a2 = 2 pref P3;  B' = b0 + A_i b1 + B_i b2,  b0 = m + pref (P6 - 2 s_i P4),
+//   b1 = pref P7, b2 = 2 s_i pref P5,
+// stored rq[v][i][ldb] (v = a0 a1 a2 b0 b1 b2). With rq (node columns of
+// differences from the reference), the products p of the differences are
+// added: A' = a0 + A_i a1 + B_i a2 + pref (p0 + A_i p1 - 2 p2 + 2 B_i p3), and
+// likewise B'. This is the same map, with T's rounding error now scaled by
+// the size of the differences instead of the columns themselves.
 template <class T, int RH>
 __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
     int n_inst, int n, int nq_pad, int ldi, int ldb, const T* __restrict__ MT, size_t mstride,
     const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
     const double* __restrict__ s_, const double* __restrict__ x_in, double* __restrict__ x_out,
-    SolveState* state, const SolveCtl* ctl, int k) {
+    SolveState* state, const SolveCtl* ctl, int k, const double* __restrict__ rq,
+    double* __restrict__ rq_out) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int RB = Mfma<T>::RB, TM = 16 * RB;
   __shared__ acc_t part[RH][8][RB][2][64];  // partial products of the second K half
@@ -414,8 +440,26 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
         const double p0 = acc[0][r][cb][e], p1 = acc[1][r][cb][e], p2 = acc[2][r][cb][e],
                      p3 = acc[3][r][cb][e], p4 = acc[4][r][cb][e], p5 = acc[5][r][cb][e],
                      p6 = acc[6][r][cb][e], p7 = acc[7][r][cb][e];
-        const double An = 1.0 + P.pref * (p0 + Ai * p1 - 2.0 * p2 + 2.0 * Bi * p3);
-        const double Bn = P.m + P.pref * (p6 + Ai * p7 - 2.0 * s * p4 + 2.0 * s * Bi * p5);
+        double An, Bn;
+        if (rq) {
+          const size_t vs = (size_t)ldi * ldb, o = (size_t)i * ldb + inst;
+          An = rq[o] + Ai * rq[vs + o] + Bi * rq[2 * vs + o] +
+               P.pref * (p0 + Ai * p1 - 2.0 * p2 + 2.0 * Bi * p3);
+          Bn = rq[3 * vs + o] + Ai * rq[4 * vs + o] + Bi * rq[5 * vs + o] +
+               P.pref * (p6 + Ai * p7 - 2.0 * s * p4 + 2.0 * s * Bi * p5);
+        } else {
+          An = 1.0 + P.pref * (p0 + Ai * p1 - 2.0 * p2 + 2.0 * Bi * p3);
+          Bn = P.m + P.pref * (p6 + Ai * p7 - 2.0 * s * p4 + 2.0 * s * Bi * p5);
+          if (rq_out) {
+            const size_t vs = (size_t)ldi * ldb, o = (size_t)i * ldb + inst;
+            rq_out[o] = 1.0 + P.pref * (p0 - 2.0 * p2);
+            rq_out[vs + o] = P.pref * p1;
+            rq_out[2 * vs + o] = 2.0 * P.pref * p3;
+            rq_out[3 * vs + o] = P.m + P.pref * (p6 - 2.0 * s * p4);
+            rq_out[4 * vs + o] = P.pref * p7;
+            rq_out[5 * vs + o] = 2.0 * s * P.pref * p5;
+          }
+        }
         xo[i] = An;
         xo[n + i] = Bn;
         if (state) {
@@ -475,20 +519,24 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
                            const T* MT, T* C, const InstDev* inst, const int* lo, const double* sw,
                            const double* t, const double* s, const double* x_in, double* x_out,
                            SolveState* state, const SolveCtl* ctl, int k, bool nodes,
-                           hipEvent_t ev0, hipEvent_t ev1) {
+                           hipEvent_t ev0, hipEvent_t ev1, const MmDelta* delta) {
+  const double* x_ref = delta ? delta->x_ref : nullptr;
+  const double* rq = delta ? delta->rq : nullptr;
+  double* rq_out = delta ? delta->rq_out : nullptr;
+  if ((x_ref == nullptr) != (rq == nullptr) || (rq && rq_out)) return hipErrorInvalidValue;
   if (nodes)
     hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
-                       n, nq, L.ldb, lo, sw, t, x_in, C, L.cstride, state, ctl, k);
+                       n, nq, L.ldb, lo, sw, t, x_in, x_ref, C, L.cstride, state, ctl, k);
   auto launch = [&](auto kern, int RH) {
     const dim3 grid((L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN));
     if (ev0)
       hipExtLaunchKernelGGL(kern, grid, dim3(64 * KSPLIT * RH), 0, st, ev0, ev1, 0, n_inst, n,
                             L.nq_pad, L.ldi, L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s,
-                            x_in, x_out, state, ctl, k);
+                            x_in, x_out, state, ctl, k, rq, rq_out);
     else
       hipLaunchKernelGGL(kern, grid, dim3(64 * KSPLIT * RH), 0, st, n_inst, n, L.nq_pad, L.ldi,
                          L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s, x_in, x_out, state,
-                         ctl, k);
+                         ctl, k, rq, rq_out);
   };
   if (L.rh == 1)
     launch(k_mm_sweep<T, 1>, 1);
@@ -505,11 +553,11 @@ template hipError_t launch_sweep_mm<float>(hipStream_t, int, int, int, const MmL
                                            const float*, float*, const InstDev*, const int*,
                                            const double*, const double*, const double*,
                                            const double*, double*, SolveState*, const SolveCtl*,
-                                           int, bool, hipEvent_t, hipEvent_t);
+                                           int, bool, hipEvent_t, hipEvent_t, const MmDelta*);
 template hipError_t launch_sweep_mm<double>(hipStream_t, int, int, int, const MmLayout&,
                                             const double*, double*, const InstDev*, const int*,
                                             const double*, const double*, const double*,
                                             const double*, double*, SolveState*, const SolveCtl*,
-                                            int, bool, hipEvent_t, hipEvent_t);
+                                            int, bool, hipEvent_t, hipEvent_t, const MmDelta*);
 
 }  // namespace qdse

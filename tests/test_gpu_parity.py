@@ -548,13 +548,17 @@ def test_fp64_matrix_batched_solve_matches_direct(Q):
         assert max(errs(a[k], b[k], n)) < 1e-11
 
 
+@pytest.mark.parametrize("refine", ["differences", "fp64"])
 @pytest.mark.parametrize("n,na,nb,tol", [(64, 32, 40, 1e-9), (512, 128, 64, 1e-8)])
-def test_fp32_refined_solve_meets_1e7(Q, n, na, nb, tol):
-    """Batched FP32 sweeps to 1e-5, FP64 sweeps to tol on max|dM/M|, |dA| (at
-    512 x 128 the benchmark's tolerance): the result is within 1e-7
-    (relative, A, B, M) of the oracle's fixed point converged to 1e-13, on
-    eight instances spread over the current masses."""
-    print(f"case fp32 refined n={n} nb={nb}", flush=True)
+def test_fp32_refined_solve_meets_1e7(Q, n, na, nb, tol, refine, monkeypatch):
+    """Batched FP32 sweeps to 1e-5, then the refinement to tol on max|dM/M|,
+    |dA| (at 512 x 128 the benchmark's tolerance): by differences (one FP64
+    sweep stores the products at the FP32 result, FP32 sweeps contract the
+    node-column differences from it) or by FP64 matrix-core sweeps. The
+    result is within 1e-7 (relative, A, B, M) of the oracle's fixed point
+    converged to 1e-13, on eight instances spread over the current masses."""
+    monkeypatch.setenv("QDSE_REFINE_FP64", "1" if refine == "fp64" else "0")
+    print(f"case fp32 refined ({refine}) n={n} nb={nb}", flush=True)
     rng = np.random.default_rng(41 + n)
     ms = rng.uniform(0, 0.2, nb)
     params = [(0.55, 0.678, float(m)) for m in ms]
