@@ -404,6 +404,13 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
       return QDSE_ENOTSUP;
     }
     c->mm = mm_layout(g.n, g.nq, n_inst);
+    {
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          cus > 0)
+        c->mm.cus = cus;
+    }
     if (const char* e = std::getenv("QDSE_MM_RH")) {
       const int r = std::atoi(e);
       if (r == 1 || r == 2) c->mm.rh = r;

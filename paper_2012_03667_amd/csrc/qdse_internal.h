@@ -215,6 +215,7 @@ struct MmLayout {
   int nq_pad = 0, ldi = 0, ldb = 0;
   size_t mstride = 0, cstride = 0;
   int rh = 2;  // row groups of 16 rows per workgroup of the contraction (1 or 2)
+  int cus = 256;  // compute units of the device (a smaller grid takes deeper prefetch)
 };
 MmLayout mm_layout(int n, int nq, int n_inst);
 template <class T>

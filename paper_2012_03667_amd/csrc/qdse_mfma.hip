@@ -51,6 +51,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr double kMassFloorM = 1e-8;  // GeV, as in the FP64 sweep
 constexpr int TM_MAX = 32, TN = 32, KSPLIT = 2, KSTEP = 4;
+constexpr int kDeepPD = 2;  // k-steps in flight when the grid underfills the device
 
 template <class T> struct Mfma;
 // Output layout of one 16x16 block: register e of lane l holds row
@@ -59,7 +60,11 @@ template <class T> struct Mfma;
 // register sets; 0: the next step's operands load into a staging set that is
 // copied after the step (measured faster for FP32 at three wavefronts per
 // SIMD: 56 against 70-75 us at 1024 instances; FP64, one wavefront per SIMD,
-// gains from two steps in flight: 88 against 92 us).
+// gains from two steps in flight: 88 against 92 us). This is the depth for a
+// grid that fills the device; with fewer workgroups than compute units (small
+// batches) a wavefront's load latency is exposed and FP32 also takes two
+// steps in flight (kDeepPD; 8 grid classes of 117-142 instances: batch
+// 7.36 -> 6.43 ms).
 // VW: consecutive loop nodes a lane reads with one load (its k values of VW
 // successive MFMA steps).
 typedef float floatx1 __attribute__((ext_vector_type(1)));
@@ -233,7 +238,9 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
 }
 
 // RH: row groups of 16 rows per workgroup (they share the node-column panel);
-// 1 or 2, chosen per context (MmLayout::rh, qdse_autotune).
+// 1 or 2, chosen per context (MmLayout::rh, qdse_autotune). PD: k-steps of
+// operands in flight (Mfma<T>::PD, or kDeepPD for a grid smaller than the
+// device).
 // Refinement by differences: rq_out (FP64 sweep at the reference iterate)
 // receives, per row and instance, the six coefficients that make the update
 // affine in the row's own A_i, B_i at the reference products P:
@@ -245,7 +252,7 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
 // added: A' = a0 + A_i a1 + B_i a2 + pref (p0 + A_i p1 - 2 p2 + 2 B_i p3), and
 // likewise B'. This is the same map, with T's rounding error now scaled by
 // the size of the differences instead of the columns themselves.
-template <class T, int RH>
+template <class T, int RH, int PD>
 __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
     int n_inst, int n, int nq_pad, int ldi, int ldb, const T* __restrict__ MT, size_t mstride,
     const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
@@ -307,7 +314,6 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
   const T* M3 = MT + 2 * mstride;
   const T* M4 = MT + 3 * mstride;
   const T* M5 = MT + 4 * mstride;
-  constexpr int PD = Mfma<T>::PD;
   // operand sets of PD + 1 consecutive k-steps (two for PD = 0), used in
   // rotation (indices known at compile time, so the sets stay in registers)
   vec_t a[PD + 1 + (PD == 0)][5][RB], c[PD + 1 + (PD == 0)][6][2];
@@ -538,10 +544,19 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
                          L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s, x_in, x_out, state,
                          ctl, k, rq, rq_out);
   };
-  if (L.rh == 1)
-    launch(k_mm_sweep<T, 1>, 1);
-  else
-    launch(k_mm_sweep<T, 2>, 2);
+  const int RH = L.rh == 1 ? 1 : 2;
+  const bool deep = (L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN) < L.cus;
+  if (RH == 1) {
+    if (deep)
+      launch(k_mm_sweep<T, 1, kDeepPD>, 1);
+    else
+      launch(k_mm_sweep<T, 1, Mfma<T>::PD>, 1);
+  } else {
+    if (deep)
+      launch(k_mm_sweep<T, 2, kDeepPD>, 2);
+    else
+      launch(k_mm_sweep<T, 2, Mfma<T>::PD>, 2);
+  }
   return hipGetLastError();
 }
 

@@ -495,8 +495,10 @@ def test_fp32_sweep_close_to_oracle(Q):
     """One FP32 sweep (split form on the matrix cores, FP32 accumulation) against
     the FP64 oracle. FP32 rounding (6e-8) of O(N) accumulated terms, amplified by
     the cancellation of the split differences near the singular diagonal, bounds
-    the error; the FP64 refinement removes it."""
-    for n, na, nb in ((64, 32, 3), (512, 128, 70)):
+    the error; the refinement removes it. The batches cover both operand
+    pipelines: grids smaller than the device (3 and 70 instances: two k-steps
+    in flight) and one that fills it (1024 instances: one step)."""
+    for n, na, nb in ((64, 32, 3), (512, 128, 70), (512, 128, 1024)):
         print(f"case fp32 sweep n={n} nb={nb}", flush=True)
         rng = np.random.default_rng(7 + n)
         ms = rng.uniform(0, 0.2, nb)
@@ -577,6 +579,33 @@ def test_fp32_refined_solve_meets_1e7(Q, n, na, nb, tol, refine, monkeypatch):
         worst = max(worst, max(errs(xg[k], xr, n)))
     print("fp32+refine worst rel err vs oracle fixed point", worst, "sweeps", n32[:4], n64[:4], flush=True)
     assert worst < 1e-7, worst
+
+
+def test_refinement_by_differences_reaches_fp64_fixed_point(Q, monkeypatch):
+    """The refinement by differences is the FP64 sweep with the FP32 rounding
+    error scaled by the size of the differences from its reference (~1e-5 of
+    the node columns after the FP32 phase), so its fixed point lies within
+    ~1e-10 of the FP64 one, far inside the 1e-7 the FP32 map alone misses by
+    two orders: solved to a tight tolerance, it agrees with the FP64
+    matrix-core solve to 1e-9 (relative, A, B, M), the same instances and
+    grid (256 x 64, 96 instances over the current masses)."""
+    monkeypatch.setenv("QDSE_REFINE_FP64", "0")
+    n, na, nb = 256, 64, 96
+    print(f"case refinement fixed point n={n} nb={nb}", flush=True)
+    rng = np.random.default_rng(59)
+    params = [(0.55, 0.678, float(m)) for m in rng.uniform(0, 0.2, nb)]
+    S32 = Q.Solver(n, na, params, precision=Q.QDSE_FP32_REFINE)
+    S64 = Q.Solver(n, na, params, precision=Q.QDSE_FP64_MATRIX)
+    x32, x64 = S32.initial(1.0, 1.0), S64.initial(1.0, 1.0)
+    rc32, it32, rs32 = S32.solve(x32, tol=1e-11, max_iter=800)
+    rc64, it64, rs64 = S64.solve(x64, tol=1e-12, max_iter=800)
+    n32, nref = S32.solve_stats()
+    print("sweeps fp32 phase", n32.max(), "refinement", nref.max(), "resid", rs32.max(), flush=True)
+    assert rc32 == Q.QDSE_OK and rc64 == Q.QDSE_OK, (rc32, rc64)
+    a, b = x32.cpu().numpy(), x64.cpu().numpy()
+    worst = max(max(errs(a[k], b[k], n)) for k in range(nb))
+    print("refined vs fp64 matrix-core worst rel", worst, flush=True)
+    assert worst < 1e-9, worst
 
 
 # ---------------------------------------------------------------- Newton-Krylov and the adjoint
