@@ -27,6 +27,7 @@
 // Tiling: a workgroup of four wavefronts owns 32 rows x 32 instances: two row
 // groups of 16 rows (they read the same node-column panel, the second read
 // served from the CU's L1), each split over the loop nodes in two halves
+// (four quarters, with eight wavefronts, when the grid underfills the device)
 // whose partial products are added through LDS before the FP64 epilogue; a
 // wavefront accumulates 16 rows x 32 instances in blocks of 16 x 16, eight
 // products each (one 16-row block per wavefront measured fastest for both
@@ -51,7 +52,13 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr double kMassFloorM = 1e-8;  // GeV, as in the FP64 sweep
 constexpr int TM_MAX = 32, TN = 32, KSPLIT = 2, KSTEP = 4;
-constexpr int kDeepPD = 2;  // k-steps in flight when the grid underfills the device
+// When the grid underfills the device: k-steps in flight, and the loop nodes
+// split four ways between the wavefronts of a row group instead of two (8
+// grid classes of 117-142 instances: FP32 + refinement 6.37 -> 5.72 ms, FP64
+// 6.24 -> 5.00 ms; at 1024 instances four ways measured slower, FP32 61
+// against 56 us and FP64 109 against 83 us). kMinGroupsDeep: load groups a
+// quarter of the loop nodes must hold for the four-way split.
+constexpr int kDeepPD = 2, kDeepKS = 4, kMinGroupsDeep = 4;
 
 template <class T> struct Mfma;
 // Output layout of one 16x16 block: register e of lane l holds row
@@ -240,7 +247,9 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
 // RH: row groups of 16 rows per workgroup (they share the node-column panel);
 // 1 or 2, chosen per context (MmLayout::rh, qdse_autotune). PD: k-steps of
 // operands in flight (Mfma<T>::PD, or kDeepPD for a grid smaller than the
-// device).
+// device). KS: wavefronts per row group, each taking a contiguous range of
+// whole load groups of the loop nodes (KSPLIT, or kDeepKS for a small grid);
+// their partial products are added in the fixed order 0 + 1 + ... + KS-1.
 // Refinement by differences: rq_out (FP64 sweep at the reference iterate)
 // receives, per row and instance, the six coefficients that make the update
 // affine in the row's own A_i, B_i at the reference products P:
@@ -252,8 +261,8 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
 // added: A' = a0 + A_i a1 + B_i a2 + pref (p0 + A_i p1 - 2 p2 + 2 B_i p3), and
 // likewise B'. This is the same map, with T's rounding error now scaled by
 // the size of the differences instead of the columns themselves.
-template <class T, int RH, int PD>
-__global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
+template <class T, int RH, int PD, int KS>
+__global__ void __launch_bounds__(64 * KS * RH) k_mm_sweep(
     int n_inst, int n, int nq_pad, int ldi, int ldb, const T* __restrict__ MT, size_t mstride,
     const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
     const double* __restrict__ s_, const double* __restrict__ x_in, double* __restrict__ x_out,
@@ -264,7 +273,7 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
   __shared__ acc_t part[RH][8][RB][2][64];  // partial products of the second K half
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop
-  const int kh = wave % KSPLIT, rh = wave / KSPLIT;
+  const int kh = wave % KS, rh = wave / KS;
   // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs
   // (workgroup w to XCD w % 8). When the instance blocks divide evenly, XCD x
   // owns the instance blocks ib = x (mod 8) and walks their row blocks, so a
@@ -288,7 +297,7 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
     bool frozen = true;
     if (lane < TN) frozen = b0 + lane >= n_inst || state[b0 + lane].status != 0;
     if (__all(frozen)) {
-      for (int e = threadIdx.x; e < TM * RH * TN; e += 64 * KSPLIT * RH) {
+      for (int e = threadIdx.x; e < TM * RH * TN; e += 64 * KS * RH) {
         const int inst = b0 + e / (TM * RH), i = ib0 + e % (TM * RH);
         if (inst < n_inst && i < n) {
           const size_t o = (size_t)inst * 2 * n;
@@ -302,8 +311,16 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
   const int lr = lane & 15, lk = lane >> 4;
   constexpr int VW = Mfma<T>::VW, KG = KSTEP * VW;  // loop nodes per load group
   typedef typename Mfma<T>::vec_t vec_t;
-  const int half = nq_pad / KSPLIT;  // a multiple of KG
-  const int kb = kh * half, ke = kb + half;
+  int kb, ke;
+  if constexpr (KS == 2) {
+    const int half = nq_pad / 2;  // a multiple of KG
+    kb = kh * half;
+    ke = kb + half;
+  } else {
+    const int ng = nq_pad / KG;  // load groups
+    kb = (kh * ng / KS) * KG;
+    ke = ((kh + 1) * ng / KS) * KG;
+  }
   acc_t acc[8][RB][2];
 #pragma unroll
   for (int p = 0; p < 8; ++p)
@@ -399,23 +416,48 @@ __global__ void __launch_bounds__(64 * KSPLIT * RH) k_mm_sweep(
       }
     }
   }
-  // add the second half's partial products (fixed order: half 0 + half 1)
-  if (kh == 1) {
+  // add the other ranges' partial products, one range at a time through the
+  // same LDS buffer (fixed order: range 0 + 1 + ... + KS-1)
+  if constexpr (KS == 2) {
+    if (kh == 1) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) part[rh][p][r][cb][lane] = acc[p][r][cb];
+    }
+    __syncthreads();
+    if (kh == 1) return;
 #pragma unroll
     for (int p = 0; p < 8; ++p)
 #pragma unroll
       for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) part[rh][p][r][cb][lane] = acc[p][r][cb];
+        for (int cb = 0; cb < 2; ++cb) acc[p][r][cb] += part[rh][p][r][cb][lane];
+  } else {
+  for (int h = 1; h < KS; ++h) {
+    if (kh == h) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) part[rh][p][r][cb][lane] = acc[p][r][cb];
+    }
+    __syncthreads();
+    if (kh == 0) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) acc[p][r][cb] += part[rh][p][r][cb][lane];
+    }
+    if (h + 1 < KS) __syncthreads();  // before range h + 1 overwrites the buffer
   }
-  __syncthreads();
-  if (kh == 1) return;
-#pragma unroll
-  for (int p = 0; p < 8; ++p)
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[p][r][cb] += part[rh][p][r][cb][lane];
+  if (kh != 0) return;
+  }
   // Epilogue (FP64)
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) {
@@ -533,29 +575,35 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
   if (nodes)
     hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
                        n, nq, L.ldb, lo, sw, t, x_in, x_ref, C, L.cstride, state, ctl, k);
-  auto launch = [&](auto kern, int RH) {
+  auto launch = [&](auto kern, int RH, int KS) {
     const dim3 grid((L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN));
     if (ev0)
-      hipExtLaunchKernelGGL(kern, grid, dim3(64 * KSPLIT * RH), 0, st, ev0, ev1, 0, n_inst, n,
+      hipExtLaunchKernelGGL(kern, grid, dim3(64 * KS * RH), 0, st, ev0, ev1, 0, n_inst, n,
                             L.nq_pad, L.ldi, L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s,
                             x_in, x_out, state, ctl, k, rq, rq_out);
     else
-      hipLaunchKernelGGL(kern, grid, dim3(64 * KSPLIT * RH), 0, st, n_inst, n, L.nq_pad, L.ldi,
+      hipLaunchKernelGGL(kern, grid, dim3(64 * KS * RH), 0, st, n_inst, n, L.nq_pad, L.ldi,
                          L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s, x_in, x_out, state,
                          ctl, k, rq, rq_out);
   };
   const int RH = L.rh == 1 ? 1 : 2;
   const bool deep = (L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN) < L.cus;
+  const bool split4 =
+      deep && L.nq_pad / (KSTEP * Mfma<T>::VW) >= kDeepKS * kMinGroupsDeep;
   if (RH == 1) {
-    if (deep)
-      launch(k_mm_sweep<T, 1, kDeepPD>, 1);
+    if (split4)
+      launch(k_mm_sweep<T, 1, kDeepPD, kDeepKS>, 1, kDeepKS);
+    else if (deep)
+      launch(k_mm_sweep<T, 1, kDeepPD, KSPLIT>, 1, KSPLIT);
     else
-      launch(k_mm_sweep<T, 1, Mfma<T>::PD>, 1);
+      launch(k_mm_sweep<T, 1, Mfma<T>::PD, KSPLIT>, 1, KSPLIT);
   } else {
-    if (deep)
-      launch(k_mm_sweep<T, 2, kDeepPD>, 2);
+    if (split4)
+      launch(k_mm_sweep<T, 2, kDeepPD, kDeepKS>, 2, kDeepKS);
+    else if (deep)
+      launch(k_mm_sweep<T, 2, kDeepPD, KSPLIT>, 2, KSPLIT);
     else
-      launch(k_mm_sweep<T, 2, Mfma<T>::PD>, 2);
+      launch(k_mm_sweep<T, 2, Mfma<T>::PD, KSPLIT>, 2, KSPLIT);
   }
   return hipGetLastError();
 }

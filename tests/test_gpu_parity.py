@@ -519,8 +519,10 @@ def test_fp32_sweep_close_to_oracle(Q):
 def test_fp64_matrix_sweep_matches_oracle(Q):
     """The FP64 matrix-core sweep (split form, FP64 MFMA): the cancellation of
     the split differences costs ~50x FP64 rounding, so it meets the FP64
-    parity bar too."""
-    for n, na, nb in ((64, 32, 5), (150, 100, 33), (512, 128, 70)):
+    parity bar too. The batches cover the launch shapes: grids smaller than
+    the device (loop nodes split two or four ways) and one that fills it
+    (1024 instances)."""
+    for n, na, nb in ((64, 32, 5), (150, 100, 33), (512, 128, 70), (512, 128, 1024)):
         print(f"case fp64 matrix sweep n={n} nb={nb}", flush=True)
         rng = np.random.default_rng(17 + n)
         params = [(0.55, 0.678, float(m)) for m in rng.uniform(0, 0.2, nb)]
