@@ -691,10 +691,10 @@ def main():
         n32, n64 = S32.solve_stats()
         res["fp32_mfma_refined"] = {
             "solves_per_s": B * args.batch_steps / dt32, "ms_per_batch": 1e3 * dt32 / args.batch_steps,
-            "fp32_sweeps_max": int(n32.max()), "refine_sweeps_max": int(n64.max()),
-            "fp32_sweeps_mean": float(n32.mean()), "refine_sweeps_mean": float(n64.mean()),
-            "refinement": ("one FP64 sweep at the FP32 result, then FP32 sweeps of the node-column "
-                           "differences from it")}
+            "fp32_sweeps_max": int(n32.max()), "fp64_sweeps_max": int(n64.max()),
+            "fp32_sweeps_mean": float(n32.mean()), "fp64_sweeps_mean": float(n64.mean()),
+            "refinement": ("one phase: FP32 sweeps of the node-column differences from a reference "
+                           "iterate, renewed by an FP64 sweep (the fp64 sweeps) every sixth sweep")}
         del S32
         S64 = Q.Solver(n, na, pb, interp_order=3)
         tuned["fp64_direct_rows_per_workgroup"] = S64.autotune(reps=5)["fused_rows"]

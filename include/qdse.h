@@ -105,14 +105,15 @@ enum {
 /* Arithmetic of the contraction over loop nodes, the only O(N^2) step. */
 enum {
   QDSE_FP64 = 0,         /* FP64 throughout (direct difference form)          */
-  QDSE_FP32_REFINE = 1,  /* FP32 MFMA contraction with FP32 accumulation for
-                            the sweeps, then the refinement until the test
-                            holds: one FP64 matrix-core sweep stores the
-                            products at the FP32 result (the reference),
-                            and further sweeps contract the node-column
-                            differences from it in FP32, added to those
-                            FP64 products (environment QDSE_REFINE_FP64=1:
-                            FP64 matrix-core sweeps instead)              */
+  QDSE_FP32_REFINE = 1,  /* FP32 MFMA contraction with FP32 accumulation of
+                            the node-column differences from a reference
+                            iterate, added to the FP64 products there; an
+                            FP64 matrix-core sweep renews the reference
+                            every sixth sweep, one phase until the test
+                            holds. Environment QDSE_REFINE=phased: FP32
+                            sweeps to 1e-5, one FP64 reference sweep, then
+                            sweeps of differences from it; =fp64: FP32
+                            sweeps to 1e-5, then FP64 matrix-core sweeps    */
   QDSE_FP64_MATRIX = 2   /* FP64 MFMA contraction (split form) for batches    */
 };
 
@@ -291,10 +292,11 @@ int qdse_newton(qdse_ctx* ctx, double* d_x, double tol, int max_newton, double l
 int qdse_solve_kernel_us(const qdse_ctx* ctx, double* us);
 
 /* Sweep counts of the last qdse_solve per instance (host arrays [n_inst], may
- * be NULL): sweeps of the FP32 phase (QDSE_FP32_REFINE contexts) and of the
- * final phase (QDSE_FP32_REFINE: the refinement, its FP64 reference sweep
- * included; otherwise every sweep). The FP32 phase stops at max(tol, 1e-5)
- * on the same test; the refinement then runs to tol. */
+ * be NULL). QDSE_FP32_REFINE in its default form: FP32 sweeps of differences
+ * and FP64 reference sweeps; in the phased and fp64 forms: sweeps of the
+ * FP32 phase, which stops at max(tol, 1e-5) on the same test, and of the
+ * refinement that then runs to tol (its FP64 reference sweep included).
+ * Other contexts: 0 and every sweep. */
 int qdse_solve_stats(const qdse_ctx* ctx, int* sweeps_fp32, int* sweeps_fp64);
 
 /* Jacobian-vector product d_jv = (dF/dx)(d_x) d_v for every instance (FP64,

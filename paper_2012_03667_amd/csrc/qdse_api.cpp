@@ -152,7 +152,8 @@ struct qdse_ctx {
   // the FP64 products there, [6][ldi][ldb] (MmDelta)
   double* d_xref = nullptr;
   double* d_rq = nullptr;
-  int ref_sweeps = 0;  // FP64 reference sweeps of the last solve (0 or 1)
+  int ref_sweeps = 0;    // FP64 reference sweeps of the last solve's refinement phase (0 or 1)
+  int periodic_ref = 0;  // the last solve ran FP32 + FP64 reference sweeps as one phase
   std::vector<int> last_sweeps32, last_sweeps64;
   InstDev* d_inst = nullptr;
   double* d_nodes = nullptr;  // [n_inst][10][ldk]
@@ -167,7 +168,7 @@ struct qdse_ctx {
   double* d_sig = nullptr;  // [n_inst][2 (n + 1)]
   // graph of a chunk of masked sweeps; pinned copies of the solve state of
   // the last two chunks, with their completion events
-  std::vector<std::pair<int, hipGraphExec_t>> graphs[5];  // per sweep kind: (length, graph)
+  std::vector<std::pair<int, hipGraphExec_t>> graphs[6];  // per sweep kind: (length, graph)
   int chunk = 24;       // sweeps per graph launch, FP64 direct sweeps (multiple of 6)
   int chunk_mm = 12;    // the same for matrix-core sweeps (masked sweeps cost more)
   int fused_rows = 8;   // rows per workgroup of the fused FP64 sweep
@@ -594,8 +595,33 @@ int qdse_iterate_fp64_matrix(qdse_ctx* c, const double* d_x_in, double* d_x_out)
 }
 
 // Sweep kinds of a masked run (SWEEP_MM32D: FP32 matrix-core sweeps of the
-// node-column differences from the context's reference iterate).
-enum { SWEEP_DIRECT = 0, SWEEP_MM32 = 1, SWEEP_MM64 = 2, SWEEP_QC = 3, SWEEP_MM32D = 4 };
+// node-column differences from the context's reference iterate; SWEEP_MM32R:
+// the same with the reference renewed by an FP64 matrix-core sweep every
+// kRefEvery sweeps).
+enum {
+  SWEEP_DIRECT = 0,
+  SWEEP_MM32 = 1,
+  SWEEP_MM64 = 2,
+  SWEEP_QC = 3,
+  SWEEP_MM32D = 4,
+  SWEEP_MM32R = 5
+};
+// Sweeps 1, 1 + kRefEvery, ... of every chunk (chunks are multiples of 6 long,
+// so the pattern does not depend on the chunking) are the reference sweeps.
+constexpr int kRefEvery = 6;
+
+// Refinement of QDSE_FP32_REFINE (environment QDSE_REFINE): 0 "periodic"
+// (default: one phase, FP32 sweeps of differences from a reference renewed by
+// an FP64 sweep every kRefEvery sweeps), 1 "phased" (FP32 sweeps to 1e-5,
+// then one FP64 reference sweep and FP32 sweeps of differences from it), 2
+// "fp64" (FP32 sweeps to 1e-5, then FP64 matrix-core sweeps).
+static int refine_mode() {
+  const char* e = std::getenv("QDSE_REFINE");
+  if (!e) return 0;
+  if (std::strcmp(e, "phased") == 0) return 1;
+  if (std::strcmp(e, "fp64") == 0) return 2;
+  return 0;
+}
 
 static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
   const HostGrid& g = c->hg;
@@ -603,9 +629,18 @@ static int record_chunk(qdse_ctx* c, hipStream_t st, int chunk, int kind) {
     const int p = k & 1;  // sweep k reads xbuf[(k-1)%2] and writes xbuf[k%2]
     const double* xi = c->d_xbuf[p ^ 1];
     double* xo = c->d_xbuf[p];
-    if (kind == SWEEP_MM32 || kind == SWEEP_MM32D) {
+    if (kind == SWEEP_MM32R && k % kRefEvery == 1) {
+      // reference sweep: the FP64 products at this sweep's input, which it
+      // also copies to x_ref (running instances; the others do not use it)
       MmDelta d;
-      if (kind == SWEEP_MM32D) {
+      d.rq_out = c->d_rq;
+      d.x_ref_out = c->d_xref;
+      HIPCHK(launch_sweep_mm<double>(st, c->n_inst, g.n, g.nq, c->mm, c->d_M64, c->d_C64,
+                                     c->d_inst, c->d_lo, c->d_sw, c->d_t, c->d_s, xi, xo,
+                                     c->d_state, c->d_ctl, k, true, nullptr, nullptr, &d));
+    } else if (kind == SWEEP_MM32 || kind == SWEEP_MM32D || kind == SWEEP_MM32R) {
+      MmDelta d;
+      if (kind != SWEEP_MM32) {
         d.x_ref = c->d_xref;
         d.rq = c->d_rq;
       }
@@ -882,9 +917,16 @@ static int finish_outcome(qdse_ctx* c, const std::vector<SolveState>& hs,
     else if (h.status == 1) code = cert[k] ? QDSE_ESPURIOUS : QDSE_OK;
     else code = (k < (int)diverged.size() && diverged[k]) ? QDSE_EDIVERGED : QDSE_NOT_CONVERGED;
     c->last_status[k] = code;
-    c->last_sweeps64[k] = h.sweeps + c->ref_sweeps;
-    c->last_evals[k] = c->last_sweeps64[k] +
-                       (k < (int)c->last_sweeps32.size() ? c->last_sweeps32[k] : 0);
+    if (c->periodic_ref) {  // one phase: its reference sweeps and FP32 sweeps
+      const int refs = (h.sweeps + kRefEvery - 1) / kRefEvery;
+      c->last_sweeps64[k] = refs;
+      if (k < (int)c->last_sweeps32.size()) c->last_sweeps32[k] = h.sweeps - refs;
+      c->last_evals[k] = h.sweeps;
+    } else {
+      c->last_sweeps64[k] = h.sweeps + c->ref_sweeps;
+      c->last_evals[k] = c->last_sweeps64[k] +
+                         (k < (int)c->last_sweeps32.size() ? c->last_sweeps32[k] : 0);
+    }
     if (iters) iters[k] = c->last_evals[k];
     if (resid) resid[k] = h.resid;
   }
@@ -1006,6 +1048,16 @@ struct GroupEntry {
 
 int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
   qdse_ctx* c = g.c;
+  if (g.phase == 0 && c->precision == QDSE_FP32_REFINE && refine_mode() == 0) {
+    // One phase: FP32 matrix-core sweeps of the node-column differences from
+    // a reference iterate, renewed by an FP64 matrix-core sweep (which stores
+    // the products there) every kRefEvery sweeps. The FP32 rounding error
+    // scales with the distance from the reference, so the iterates follow the
+    // FP64 sweeps' own path (to ~1e-5 of that distance) and the solve takes
+    // about as many sweeps as FP64 alone, one in kRefEvery of them FP64.
+    c->periodic_ref = 1;
+    return masked_begin(g.run, c, tol, max_iter, conv_mode, SWEEP_MM32R, g.d_x, g.d_x);
+  }
   if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
     // switch to the refinement below this change: it needs about twenty
     // sweeps from anywhere below ~1e-5, because the FP32 fixed point itself
@@ -1017,8 +1069,7 @@ int group_phase_begin(GroupEntry& g, double tol, int max_iter, int conv_mode) {
     return masked_begin(g.run, c, tol32, max_iter, conv_mode, SWEEP_MM32, g.d_x, nullptr);
   }
   if (g.phase == 1 && c->precision == QDSE_FP32_REFINE) {
-    const char* e = std::getenv("QDSE_REFINE_FP64");
-    if (!(e && e[0] == '1')) {
+    if (refine_mode() == 1) {
       // Refinement by differences: the FP32 phase's result becomes the
       // reference; one FP64 sweep from it stores the products there (and is
       // the phase's first sweep), then FP32 sweeps contract only the
@@ -1054,6 +1105,7 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
     c->last_sweeps64.assign(c->n_inst, 0);
     c->fp32_state_pending = 0;
     c->ref_sweeps = 0;
+    c->periodic_ref = 0;
     int rc = group_phase_begin(g, tol, max_iter, conv_mode);
     if (rc) return rc;
   }
@@ -1078,7 +1130,7 @@ int solve_group(std::vector<GroupEntry>& G, double tol, int max_iter, int conv_m
       masked_state(g.run, g.hs);
       if (g.diverged.empty()) g.diverged.assign(c->n_inst, 0);
       for (int k = 0; k < c->n_inst; ++k) g.diverged[k] |= g.run.diverged[k];
-      if (g.phase == 0 && c->precision == QDSE_FP32_REFINE) {
+      if (g.phase == 0 && c->precision == QDSE_FP32_REFINE && !c->periodic_ref) {
         // the FP32 phase's final state, copied behind its last chunk (the
         // mirror is only a prediction aid: its fields are not written
         // atomically together); read after the stream drains
@@ -2010,6 +2062,7 @@ int qdse_autotune(qdse_ctx* c, int reps, const char* cache_path, int* fused_rows
     c->mm.rh = best == 1 ? 1 : 2;
     drop_graphs(c, SWEEP_MM32);
     drop_graphs(c, SWEEP_MM32D);
+    drop_graphs(c, SWEEP_MM32R);
     drop_graphs(c, SWEEP_MM64);
   } else if (!c->qc) {
     c->fused_rows = (best == 8 || best == 16) ? best : 4;

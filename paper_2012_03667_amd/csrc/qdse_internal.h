@@ -224,17 +224,21 @@ hipError_t launch_build_mm(hipStream_t st, int n, int nq, int ldk, const MmLayou
 // Refinement by differences from a reference iterate x_ref ([n_inst][2n]):
 // rq ([6][ldi][ldb] doubles) holds the FP64 products at x_ref in the form that
 // makes a row's update affine in its own A_i, B_i. A sweep with rq_out set
-// (x_ref, rq null) writes them; a sweep with x_ref and rq set contracts only
-// the node-column differences c(x) - c(x_ref) and adds them.
+// (x_ref, rq null) writes them, and with x_ref_out also copies its input
+// iterate there (every running instance; a buffer apart from x_in and x_out);
+// a sweep with x_ref and rq set contracts only the node-column differences
+// c(x) - c(x_ref) and adds them.
 struct MmDelta {
   const double* x_ref = nullptr;
   const double* rq = nullptr;
   double* rq_out = nullptr;
+  double* x_ref_out = nullptr;
 };
 // nodes = false skips the node-column kernel (columns already built); ev0/ev1
 // time the contraction kernel's dispatch as in launch_sweep_fused; delta as
 // above (nullptr: the plain sweep). hipErrorInvalidValue for an inconsistent
-// delta (x_ref without rq or the reverse, or rq with rq_out).
+// delta (x_ref without rq or the reverse, rq with rq_out, x_ref_out without
+// rq_out or equal to x_in or x_out).
 template <class T>
 hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLayout& L,
                            const T* MT, T* C, const InstDev* inst, const int* lo, const double* sw,

@@ -256,7 +256,8 @@ __global__ void __launch_bounds__(256) k_nodes_mm(int n_inst, int n, int nq, int
 //   A' = a0 + A_i a1 + B_i a2,  a0 = 1 + pref (P0 - 2 P2), a1 = pref P1,
 //   a2 = 2 pref P3;  B' = b0 + A_i b1 + B_i b2,  b0 = m + pref (P6 - 2 s_i P4),
 //   b1 = pref P7, b2 = 2 s_i pref P5,
-// stored rq[v][i][ldb] (v = a0 a1 a2 b0 b1 b2). With rq (node columns of
+// stored rq[v][i][ldb] (v = a0 a1 a2 b0 b1 b2), and with xr_out the row's
+// input A_i, B_i into xr_out (the new reference iterate). With rq (node columns of
 // differences from the reference), the products p of the differences are
 // added: A' = a0 + A_i a1 + B_i a2 + pref (p0 + A_i p1 - 2 p2 + 2 B_i p3), and
 // likewise B'. This is the same map, with T's rounding error now scaled by
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(64 * KS * RH) k_mm_sweep(
     const T* __restrict__ C, size_t cstride, const InstDev* __restrict__ inst_,
     const double* __restrict__ s_, const double* __restrict__ x_in, double* __restrict__ x_out,
     SolveState* state, const SolveCtl* ctl, int k, const double* __restrict__ rq,
-    double* __restrict__ rq_out) {
+    double* __restrict__ rq_out, double* __restrict__ xr_out) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int RB = Mfma<T>::RB, TM = 16 * RB;
   __shared__ acc_t part[RH][8][RB][2][64];  // partial products of the second K half
@@ -506,6 +507,10 @@ __global__ void __launch_bounds__(64 * KS * RH) k_mm_sweep(
             rq_out[3 * vs + o] = P.m + P.pref * (p6 - 2.0 * s * p4);
             rq_out[4 * vs + o] = P.pref * p7;
             rq_out[5 * vs + o] = 2.0 * s * P.pref * p5;
+            if (xr_out) {
+              xr_out[(size_t)inst * 2 * n + i] = Ai;
+              xr_out[(size_t)inst * 2 * n + n + i] = Bi;
+            }
           }
         }
         xo[i] = An;
@@ -571,7 +576,10 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
   const double* x_ref = delta ? delta->x_ref : nullptr;
   const double* rq = delta ? delta->rq : nullptr;
   double* rq_out = delta ? delta->rq_out : nullptr;
-  if ((x_ref == nullptr) != (rq == nullptr) || (rq && rq_out)) return hipErrorInvalidValue;
+  double* xr_out = delta ? delta->x_ref_out : nullptr;
+  if ((x_ref == nullptr) != (rq == nullptr) || (rq && rq_out) || (xr_out && !rq_out) ||
+      (xr_out && (xr_out == x_in || xr_out == x_out)))
+    return hipErrorInvalidValue;
   if (nodes)
     hipLaunchKernelGGL(k_nodes_mm<T>, dim3((nq + 31) / 32, L.ldb / 32), dim3(256), 0, st, n_inst,
                        n, nq, L.ldb, lo, sw, t, x_in, x_ref, C, L.cstride, state, ctl, k);
@@ -580,11 +588,11 @@ hipError_t launch_sweep_mm(hipStream_t st, int n_inst, int n, int nq, const MmLa
     if (ev0)
       hipExtLaunchKernelGGL(kern, grid, dim3(64 * KS * RH), 0, st, ev0, ev1, 0, n_inst, n,
                             L.nq_pad, L.ldi, L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s,
-                            x_in, x_out, state, ctl, k, rq, rq_out);
+                            x_in, x_out, state, ctl, k, rq, rq_out, xr_out);
     else
       hipLaunchKernelGGL(kern, grid, dim3(64 * KS * RH), 0, st, n_inst, n, L.nq_pad, L.ldi,
                          L.ldb, MT, L.mstride, (const T*)C, L.cstride, inst, s, x_in, x_out, state,
-                         ctl, k, rq, rq_out);
+                         ctl, k, rq, rq_out, xr_out);
   };
   const int RH = L.rh == 1 ? 1 : 2;
   const bool deep = (L.ldi / (16 * Mfma<T>::RB * RH)) * (L.ldb / TN) < L.cus;

@@ -552,16 +552,18 @@ def test_fp64_matrix_batched_solve_matches_direct(Q):
         assert max(errs(a[k], b[k], n)) < 1e-11
 
 
-@pytest.mark.parametrize("refine", ["differences", "fp64"])
+@pytest.mark.parametrize("refine", ["periodic", "phased", "fp64"])
 @pytest.mark.parametrize("n,na,nb,tol", [(64, 32, 40, 1e-9), (512, 128, 64, 1e-8)])
 def test_fp32_refined_solve_meets_1e7(Q, n, na, nb, tol, refine, monkeypatch):
-    """Batched FP32 sweeps to 1e-5, then the refinement to tol on max|dM/M|,
-    |dA| (at 512 x 128 the benchmark's tolerance): by differences (one FP64
-    sweep stores the products at the FP32 result, FP32 sweeps contract the
-    node-column differences from it) or by FP64 matrix-core sweeps. The
-    result is within 1e-7 (relative, A, B, M) of the oracle's fixed point
-    converged to 1e-13, on eight instances spread over the current masses."""
-    monkeypatch.setenv("QDSE_REFINE_FP64", "1" if refine == "fp64" else "0")
+    """The FP32 matrix-core solve to tol on max|dM/M|, |dA| (at 512 x 128 the
+    benchmark's tolerance) in its three forms: periodic (one phase of FP32
+    sweeps of the node-column differences from a reference that an FP64
+    sweep renews every sixth sweep), phased (FP32 sweeps to 1e-5, one FP64
+    reference sweep, FP32 sweeps of differences from it) and fp64 (FP32
+    sweeps to 1e-5, then FP64 matrix-core sweeps). The result is within 1e-7
+    (relative, A, B, M) of the oracle's fixed point converged to 1e-13, on
+    eight instances spread over the current masses."""
+    monkeypatch.setenv("QDSE_REFINE", refine)
     print(f"case fp32 refined ({refine}) n={n} nb={nb}", flush=True)
     rng = np.random.default_rng(41 + n)
     ms = rng.uniform(0, 0.2, nb)
@@ -583,17 +585,18 @@ def test_fp32_refined_solve_meets_1e7(Q, n, na, nb, tol, refine, monkeypatch):
     assert worst < 1e-7, worst
 
 
-def test_refinement_by_differences_reaches_fp64_fixed_point(Q, monkeypatch):
-    """The refinement by differences is the FP64 sweep with the FP32 rounding
-    error scaled by the size of the differences from its reference (~1e-5 of
-    the node columns after the FP32 phase), so its fixed point lies within
-    ~1e-10 of the FP64 one, far inside the 1e-7 the FP32 map alone misses by
-    two orders: solved to a tight tolerance, it agrees with the FP64
-    matrix-core solve to 1e-9 (relative, A, B, M), the same instances and
-    grid (256 x 64, 96 instances over the current masses)."""
-    monkeypatch.setenv("QDSE_REFINE_FP64", "0")
+@pytest.mark.parametrize("refine", ["periodic", "phased"])
+def test_refinement_by_differences_reaches_fp64_fixed_point(Q, refine, monkeypatch):
+    """A sweep of differences is the FP64 sweep with the FP32 rounding error
+    scaled by the distance from its reference (near the end ~1e-5 of the node
+    columns or less), so its fixed point lies within ~1e-10 of the FP64 one,
+    far inside the 1e-7 the FP32 map alone misses by two orders: solved to a
+    tight tolerance, it agrees with the FP64 matrix-core solve to 1e-9
+    (relative, A, B, M), the same instances and grid (256 x 64, 96 instances
+    over the current masses)."""
+    monkeypatch.setenv("QDSE_REFINE", refine)
     n, na, nb = 256, 64, 96
-    print(f"case refinement fixed point n={n} nb={nb}", flush=True)
+    print(f"case refinement fixed point ({refine}) n={n} nb={nb}", flush=True)
     rng = np.random.default_rng(59)
     params = [(0.55, 0.678, float(m)) for m in rng.uniform(0, 0.2, nb)]
     S32 = Q.Solver(n, na, params, precision=Q.QDSE_FP32_REFINE)
