@@ -417,7 +417,7 @@ static int setup_impl(const qdse_grid* grid, const qdse_params* params, int n_in
       if (r == 1 || r == 2) c->mm.rh = r;
     }
     const MmLayout& L = c->mm;
-    // FP64 matrix-core sweeps serve both precisions (the refinement of FP32)
+    // FP64 matrix-core sweeps serve both precisions (the reference sweeps of FP32)
     TRY(dalloc(&c->d_M64, 5 * L.mstride));
     TRY(dalloc(&c->d_C64, 6 * L.cstride));
     hipError_t e = hipMemsetAsync(c->d_M64, 0, 5 * L.mstride * sizeof(double), st);

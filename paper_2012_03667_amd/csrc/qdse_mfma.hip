@@ -17,8 +17,10 @@
 //
 // Two element types share one kernel template:
 //  * FP32 (v_mfma_f32_16x16x4_f32, FP32 accumulation): the split form cancels
-//    where A_j ~ A_i near the singular diagonal of K_T, so FP32 sweeps are
-//    followed by FP64 sweeps (the refinement) until the FP64 test passes;
+//    where A_j ~ A_i near the singular diagonal of K_T (~1e-5 relative), so
+//    a solve contracts in FP32 only the node-column differences from a
+//    reference iterate, whose products an FP64 sweep stores (the rounding
+//    error then scales with the differences; see k_mm_sweep);
 //  * FP64 (v_mfma_f64_16x16x4_f64): the same products in FP64, whose
 //    cancellation error (~1e-15 relative) is far below the FP64 targets.
 // Node functions (with the denominator t A^2 + B^2), the combination above,
