@@ -613,6 +613,30 @@ def test_refinement_by_differences_reaches_fp64_fixed_point(Q, refine, monkeypat
     assert worst < 1e-9, worst
 
 
+def test_periodic_reference_follows_fp64_sweep_count(Q, monkeypatch):
+    """With the reference renewed every sixth sweep, the FP32 sweeps of
+    differences stay within ~1e-5 of a few sweeps' change of the FP64 path,
+    so each instance converges in the FP64 matrix-core solve's sweep count
+    (within one), one sweep in six of them FP64 (512 x 128, 64 instances over
+    the current masses, tol 1e-8)."""
+    monkeypatch.setenv("QDSE_REFINE", "periodic")
+    n, na, nb = 512, 128, 64
+    print(f"case periodic sweep count n={n} nb={nb}", flush=True)
+    rng = np.random.default_rng(61)
+    params = [(0.55, 0.678, float(m)) for m in rng.uniform(0, 0.2, nb)]
+    S32 = Q.Solver(n, na, params, precision=Q.QDSE_FP32_REFINE)
+    S64 = Q.Solver(n, na, params, precision=Q.QDSE_FP64_MATRIX)
+    x32, x64 = S32.initial(1.0, 1.0), S64.initial(1.0, 1.0)
+    rc32, it32, _ = S32.solve(x32, tol=1e-8, max_iter=600)
+    rc64, it64, _ = S64.solve(x64, tol=1e-8, max_iter=600)
+    assert rc32 == Q.QDSE_OK and rc64 == Q.QDSE_OK, (rc32, rc64)
+    n32, n64 = S32.solve_stats()
+    assert np.array_equal(n32 + n64, it32)
+    assert np.array_equal(n64, (it32 + 5) // 6)
+    print("sweeps periodic", it32.max(), "fp64", it64.max(), "max diff", np.abs(it32 - it64).max(), flush=True)
+    assert np.abs(it32 - it64).max() <= 1
+
+
 # ---------------------------------------------------------------- Newton-Krylov and the adjoint
 def test_newton_krylov_matches_oracle_fixed_point(Q):
     n, na = 64, 32
