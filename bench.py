@@ -729,7 +729,7 @@ def main():
         issued = 16.0 * n * nq * B
         tf = flops / (ms32 * 1e-3) / 1e12
         line["roofline_fp32"] = {
-            "bound": "mfma", "kernel": f"k_mm_sweep<float, {rh32}, 0> (FP32 contraction, batch)",
+            "bound": "mfma", "kernel": f"k_mm_sweep<float, {rh32}, 0, 2> (FP32 contraction, batch)",
             "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tf / FP32_MFMA_PEAK_TFLOPS,
             "traffic": counter_traffic("k_mm_sweep_fp32_512x128_1024inst.md", "qdse_mfma.hip"),
@@ -742,7 +742,7 @@ def main():
         line["batched"]["fp64_mfma_contraction_kernel_us"] = ms_mm64 * 1e3
         line["roofline_fp64_mfma"] = {
             "bound": "mfma",
-            "kernel": f"k_mm_sweep<double, {tuned['fp64_mfma_row_groups']}, 2> (FP64 contraction, batch)",
+            "kernel": f"k_mm_sweep<double, {tuned['fp64_mfma_row_groups']}, 2, 2> (FP64 contraction, batch)",
             "achieved": flops / (ms_mm64 * 1e-3) / 1e12, "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": flops / (ms_mm64 * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
             "traffic": counter_traffic("k_mm_sweep_fp64_512x128_1024inst.md", "qdse_mfma.hip"),
